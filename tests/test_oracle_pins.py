@@ -1,0 +1,607 @@
+"""Pins of the CPU oracle against mathematics outside the oracle itself.
+
+Each test checks a closed form, an invariant, a special case that reduces to
+a textbook or library routine, or brute force on tiny inputs, chosen so that
+a dropped term, a wrong sign or index, or a transposed operand in the oracle
+fails at least one of them.  The paper prints no worked example or per-apply
+value, so no stored paper numbers are compared here.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import oracle as O
+from synth import jacobian as J
+
+
+# ----------------------------------------------------------------- helpers
+def lap1d(n):
+    return sp.diags([-np.ones(n - 1), 2 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1]).tocsr()
+
+
+def lap3d(nx, ny, nz, coef=None, neumann=False, rng=None):
+    """7-point Laplacian; optional random positive face weights; Dirichlet rows
+    keep 6 on the diagonal unless neumann=True (then row sums are zero)."""
+    n = nx * ny * nz
+    idx = np.arange(n).reshape(nz, ny, nx)
+    rows, cols, vals = [], [], []
+    diag = np.zeros(n)
+    for a, b in ((idx[:, :, :-1], idx[:, :, 1:]), (idx[:, :-1, :], idx[:, 1:, :]),
+                 (idx[:-1, :, :], idx[1:, :, :])):
+        a, b = a.ravel(), b.ravel()
+        w = np.ones(a.size) if rng is None else rng.uniform(0.5, 2.0, a.size)
+        rows += [a, b]
+        cols += [b, a]
+        vals += [-w, -w]
+        np.add.at(diag, a, w)
+        np.add.at(diag, b, w)
+    if not neumann:
+        nb = np.zeros(n)
+        nb += 2 * 3  # every cell has 6 faces in an infinite grid
+        deg = np.zeros(n)
+        for r in rows[::2]:
+            np.add.at(deg, r, 1)
+        for r in rows[1::2]:
+            np.add.at(deg, r, 1)
+        diag = diag + (6 - deg) * (1.0 if rng is None else 1.0)
+    rows.append(np.arange(n))
+    cols.append(np.arange(n))
+    vals.append(diag)
+    A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(n, n))
+    A.sum_duplicates()
+    A.sort_indices()
+    return A
+
+
+def interleave2(A0, A1, cross=None):
+    """Two-function system: unknown 2i is function 0, 2i+1 function 1."""
+    n = A0.shape[0]
+    P0 = sp.csr_matrix((np.ones(n), (2 * np.arange(n), np.arange(n))), shape=(2 * n, n))
+    P1 = sp.csr_matrix((np.ones(n), (2 * np.arange(n) + 1, np.arange(n))), shape=(2 * n, n))
+    A = P0 @ A0 @ P0.T + P1 @ A1 @ P1.T
+    if cross is not None:
+        A = A + P0 @ cross @ P1.T + P1 @ cross.T @ P0.T
+    A = sp.csr_matrix(A)
+    A.sort_indices()
+    func = np.tile([0, 1], n).astype(np.int32)
+    return A, func
+
+
+def dense(case):
+    return case.to_scipy().toarray()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+# ----------------------------------------------------------------- SpMV
+def test_bsr_spmv_matches_dense_and_scipy():
+    c = J.small(4, 3, 2)
+    x = np.random.default_rng(1).standard_normal(c.n_dof)
+    y = O.bsr_spmv(c.row_ptr, c.col_idx, c.values, x)
+    assert rel(y, dense(c) @ x) < 1e-14
+    assert rel(y, c.to_scipy() @ x) < 1e-14
+
+
+# ----------------------------------------------------------------- strength
+def test_strength_hand_example():
+    # row 0: diag 4, off -1 (strong), -0.2 (weak: < 0.25 * 1), -0.3 (strong),
+    # +0.5 (positive: never strong for a positive diagonal), and one entry of
+    # the other function that must be ignored however large it is.
+    A = sp.csr_matrix(np.array([
+        [4.0, -1.0, -0.2, -0.3, 0.5, -9.0],
+        [-1.0, 4.0, 0.0, 0.0, 0.0, 0.0],
+        [-0.2, 0.0, 4.0, 0.0, 0.0, 0.0],
+        [-0.3, 0.0, 0.0, 4.0, 0.0, 0.0],
+        [0.5, 0.0, 0.0, 0.0, 4.0, 0.0],
+        [-9.0, 0.0, 0.0, 0.0, 0.0, 4.0]]))
+    func = np.array([0, 0, 0, 0, 0, 1], dtype=np.int32)
+    S = O.strength(A, func, theta=0.25, max_row_sum=1.0)
+    assert sorted(S[0].indices.tolist()) == [1, 3]
+    assert S[1].indices.tolist() == [0]
+    assert S[4].nnz == 0          # only a positive off-diagonal
+    assert S[5].nnz == 0          # its only neighbour is of the other function
+    # negative diagonal: the sign flips the test
+    S2 = O.strength(-A, func, theta=0.25, max_row_sum=1.0)
+    assert sorted(S2[0].indices.tolist()) == [1, 3]
+    # exactly at the threshold counts as strong (-a_ij >= theta * max)
+    B = sp.csr_matrix(np.array([[4.0, -1.0, -0.25], [-1.0, 4.0, 0.0], [-0.25, 0.0, 4.0]]))
+    S3 = O.strength(B, np.zeros(3, dtype=np.int32), theta=0.25, max_row_sum=1.0)
+    assert sorted(S3[0].indices.tolist()) == [1, 2]
+
+
+def test_strength_max_row_sum():
+    # row 0: row sum 9.5 > 0.9 * 10 -> diagonally dominant, all connections weak
+    A = sp.csr_matrix(np.array([[10.0, -0.5, 0.0], [-0.5, 1.0, -0.5], [0.0, -0.5, 1.0]]))
+    f = np.zeros(3, dtype=np.int32)
+    assert O.strength(A, f, 0.25, 0.9)[0].nnz == 0
+    assert O.strength(A, f, 0.25, 1.0)[0].nnz == 1
+    # row 1 has row sum 0: never dominant
+    assert O.strength(A, f, 0.25, 0.9)[1].nnz == 2
+
+
+# ----------------------------------------------------------------- coarsening
+def test_rs_first_pass_1d_alternates():
+    A = lap1d(9)
+    S = O.strength(A, np.zeros(9, dtype=np.int32))
+    cf = O.rs_first_pass(S)
+    # interior measure 2, ends 1: first C is point 1 (largest measure, smallest
+    # index), then every other point
+    assert cf.tolist() == [-1, 1, -1, 1, -1, 1, -1, 1, -1]
+
+
+def _rs_brute(S):
+    """Selection by full scan each step (no heap), same rule."""
+    S = sp.csr_matrix(S)
+    n = S.shape[0]
+    ST = sp.csr_matrix(S.T)
+    lam = np.diff(ST.indptr).astype(int)
+    cf = np.zeros(n, dtype=int)
+    for i in range(n):
+        if S.indptr[i + 1] == S.indptr[i] and lam[i] == 0:
+            cf[i] = -1
+    while True:
+        cand = [i for i in range(n) if cf[i] == 0 and lam[i] >= 1]
+        if not cand:
+            break
+        i = max(cand, key=lambda t: (lam[t], -t))
+        cf[i] = 1
+        for j in ST.indices[ST.indptr[i]:ST.indptr[i + 1]]:
+            if cf[j] == 0:
+                cf[j] = -1
+                for k in S.indices[S.indptr[j]:S.indptr[j + 1]]:
+                    if cf[k] == 0:
+                        lam[k] += 1
+        for k in S.indices[S.indptr[i]:S.indptr[i + 1]]:
+            if cf[k] == 0:
+                lam[k] -= 1
+    cf[cf == 0] = -1
+    return cf
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_rs_first_pass_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    n = 40
+    M = sp.random(n, n, density=0.08, random_state=rng, format="csr")
+    M.setdiag(0)
+    M.eliminate_zeros()
+    S = sp.csr_matrix((np.ones(M.nnz), M.indices, M.indptr), shape=(n, n))
+    assert O.rs_first_pass(S).tolist() == _rs_brute(S).tolist()
+
+
+def test_rs_first_pass_3d_brute_force():
+    A = lap3d(5, 4, 3, rng=np.random.default_rng(3))
+    S = O.strength(A, np.zeros(A.shape[0], dtype=np.int32))
+    assert O.rs_first_pass(S).tolist() == _rs_brute(S).tolist()
+
+
+# ----------------------------------------------------------------- interpolation
+def test_extpi_reproduces_linear_interpolation_1d():
+    """On the 1D Laplacian the A-harmonic (ideal) interpolation is linear; with
+    two F points between C points the distance-two terms of extended+i must
+    give the weights 2/3, 1/3 exactly."""
+    n = 10
+    A = lap1d(n)
+    f = np.zeros(n, dtype=np.int32)
+    S = O.strength(A, f)
+    cf = np.array([1 if i % 3 == 0 else -1 for i in range(n)], dtype=np.int32)
+    P = O.extpi(A, S, cf, f, pmax=0).toarray()
+    cols = np.cumsum(cf == 1) - 1
+    for i in range(n):
+        if cf[i] == 1:
+            assert P[i, cols[i]] == 1.0 and P[i].sum() == 1.0
+            continue
+        left = (i // 3) * 3
+        right = left + 3
+        t = (i - left) / 3.0
+        expect = np.zeros(P.shape[1])
+        expect[cols[left]] = 1 - t
+        if right < n:
+            expect[cols[right]] = t
+        else:
+            # no C point on the right: Dirichlet end, still linear to zero
+            pass
+        if right < n:
+            np.testing.assert_allclose(P[i], expect, atol=1e-15)
+
+
+def test_extpi_direct_case_red_black():
+    """Red-black split of the 7-point Laplacian: every F point has only strong
+    C neighbours, so extended+i reduces to direct interpolation
+    w = -a_ij / a_ii = 1/6 on interior rows; truncation to 4 keeps the four
+    smallest coarse columns (ties) and rescales them to 1/4."""
+    nx = ny = nz = 4
+    A = lap3d(nx, ny, nz)
+    n = A.shape[0]
+    f = np.zeros(n, dtype=np.int32)
+    S = O.strength(A, f)
+    k, j, i = np.unravel_index(np.arange(n), (nz, ny, nx))
+    cf = np.where((i + j + k) % 2 == 0, 1, -1).astype(np.int32)
+    P = O.extpi(A, S, cf, f, pmax=0)
+    Pt = O.extpi(A, S, cf, f, pmax=4)
+    interior = (i > 0) & (i < nx - 1) & (j > 0) & (j < ny - 1) & (k > 0) & (k < nz - 1)
+    for r in np.where(interior & (cf == -1))[0]:
+        row = P[r]
+        assert row.nnz == 6
+        np.testing.assert_allclose(row.data, 1.0 / 6.0, rtol=0, atol=1e-15)
+        trow = Pt[r]
+        assert trow.nnz == 4
+        np.testing.assert_allclose(trow.data, 0.25, rtol=0, atol=1e-15)
+        assert trow.indices.tolist() == sorted(row.indices.tolist())[:4]
+
+
+@pytest.mark.parametrize("pmax", [0, 4])
+def test_extpi_preserves_constants_zero_rowsum(pmax):
+    """Zero same-function row sums => extended+i interpolates constants
+    exactly (every weight term and the lumped diagonal must be right for the
+    row sums to come out as 1); truncation with rescaling keeps it.  Cross-
+    function couplings are present and must be ignored."""
+    rng = np.random.default_rng(5)
+    A0 = lap3d(6, 5, 4, rng=rng, neumann=True)
+    A1 = lap3d(6, 5, 4, rng=rng, neumann=True) * 3.0
+    n = A0.shape[0]
+    cross = sp.diags(rng.uniform(-0.3, 0.3, n)).tocsr()
+    A, func = interleave2(A0, A1, cross)
+    S = O.strength(A, func)
+    cf = O.rs_first_pass(S)
+    P = O.extpi(A, S, cf, func, pmax=pmax)
+    sums = np.asarray(P.sum(axis=1)).ravel()
+    nonempty = np.diff(P.indptr) > 0
+    assert nonempty.mean() > 0.95
+    np.testing.assert_allclose(sums[nonempty], 1.0, rtol=0, atol=1e-13)
+    if pmax:
+        assert np.diff(P.indptr).max() <= pmax
+    # interpolation never mixes functions
+    cfun = func[cf == 1]
+    for r in range(P.shape[0]):
+        cols = P.indices[P.indptr[r]:P.indptr[r + 1]]
+        assert np.all(cfun[cols] == func[r])
+
+
+# ----------------------------------------------------------------- hierarchy
+def test_galerkin_and_invariants():
+    c = J.small(6, 6, 3)
+    h = O.Cptr(c.row_ptr, c.col_idx, c.values)
+    a = h.amg
+    assert a.nlevels >= 3
+    for l in range(a.nlevels - 1):
+        A, P, R = a.A(l), a.P(l), a.R(l)
+        Ac = a.A(l + 1)
+        ref = (P.T @ (A @ P)).toarray()
+        assert rel(Ac.toarray(), ref) < 1e-13
+        assert (R != P.T).nnz == 0
+        cf = a.cf(l)
+        # C rows of P are identity on the matching coarse column
+        cols = np.cumsum(cf == 1) - 1
+        for i in np.where(cf == 1)[0]:
+            assert P[i].nnz == 1 and P[i, cols[i]] == 1.0
+        assert np.diff(P.indptr).max() <= 4
+        # coarse function labels are inherited from C points
+        assert np.array_equal(a.func(l + 1), a.func(l)[cf == 1])
+
+
+def test_galerkin_symmetry_and_laplacian_1d():
+    n = 33
+    A = lap1d(n)
+    amg = O.Amg(A, np.zeros(n, dtype=np.int32), max_levels=2)
+    Ac = amg.A(1).toarray()
+    # linear interpolation, P^T A P = tridiag(-1/2, 1, -1/2) on the coarse grid
+    nc = Ac.shape[0]
+    expect = np.diag(np.ones(nc)) - 0.5 * np.diag(np.ones(nc - 1), 1) - 0.5 * np.diag(np.ones(nc - 1), -1)
+    np.testing.assert_allclose(Ac, expect, atol=1e-15)
+    # l1-Jacobi diagonal: |a_ii| + sum |a_ij| = 4 inside, 3 at the ends
+    d = 1.0 / amg.dinv(0)
+    assert d[0] == 3.0 and d[-1] == 3.0 and np.all(d[1:-1] == 4.0)
+
+
+def test_galerkin_preserves_symmetry_3d():
+    A = lap3d(6, 6, 6, rng=np.random.default_rng(2))
+    amg = O.Amg(A, np.zeros(A.shape[0], dtype=np.int32))
+    for l in range(amg.nlevels):
+        Al = amg.A(l)
+        assert abs(Al - Al.T).max() <= 1e-13 * abs(Al).max()
+
+
+# ----------------------------------------------------------------- V-cycle
+def test_vcycle_one_level_is_exact_solve():
+    c = J.small(3, 3, 2)
+    A, f = O.Cptr(c.row_ptr, c.col_idx, c.values).ahat(), None
+    n = A.shape[0]
+    func = np.tile([0, 1], n // 2).astype(np.int32)
+    amg = O.Amg(A, func, max_levels=1)
+    b = np.random.default_rng(0).standard_normal(n)
+    x = amg.vcycle(b)
+    assert rel(x, np.linalg.solve(A.toarray(), b)) < 1e-12
+
+
+def test_vcycle_symmetric_for_spd():
+    A = lap3d(5, 5, 5, rng=np.random.default_rng(4))
+    n = A.shape[0]
+    amg = O.Amg(A, np.zeros(n, dtype=np.int32))
+    assert amg.nlevels >= 2
+    B = np.column_stack([amg.vcycle(e) for e in np.eye(n)])
+    assert np.abs(B - B.T).max() <= 1e-12 * np.abs(B).max()
+    # and positive definite (V(1,1) with a convergent smoother)
+    assert np.linalg.eigvalsh(0.5 * (B + B.T)).min() > 0
+
+
+def test_two_grid_matrix_form():
+    A = lap3d(4, 4, 3, rng=np.random.default_rng(8))
+    n = A.shape[0]
+    amg = O.Amg(A, np.zeros(n, dtype=np.int32), max_levels=2)
+    P = amg.P(0).toarray()
+    Ad = A.toarray()
+    D = np.diag(amg.dinv(0))
+    I = np.eye(n)
+    Ac = P.T @ Ad @ P
+    E = (I - D @ Ad) @ (I - P @ np.linalg.solve(Ac, P.T @ Ad)) @ (I - D @ Ad)
+    Bref = (I - E) @ np.linalg.inv(Ad)
+    B = np.column_stack([amg.vcycle(e) for e in np.eye(n)])
+    assert np.abs(B - Bref).max() <= 1e-12 * np.abs(Bref).max()
+
+
+def _vcycle_factor(m):
+    rng = np.random.default_rng(10)
+    A0 = lap3d(m, m, m)
+    A1 = lap3d(m, m, m, rng=rng) * 5.0
+    A, func = interleave2(A0, A1)
+    amg = O.Amg(A, func)
+    x_true = rng.standard_normal(A.shape[0])
+    b = A @ x_true
+    x = np.zeros_like(b)
+    res = [np.linalg.norm(b)]
+    for _ in range(12):
+        x = x + amg.vcycle(b - A @ x)
+        res.append(np.linalg.norm(b - A @ x))
+    return (res[-1] / res[-5]) ** 0.25, amg.nlevels
+
+
+def test_amg_decoupled_two_equation_poisson_h_independent():
+    """Stationary V-cycle iteration on two decoupled 3D Poisson problems
+    (functions interleaved): the asymptotic convergence factor stays bounded
+    and does not grow with refinement (h-independence)."""
+    f16, L16 = _vcycle_factor(16)
+    f24, L24 = _vcycle_factor(24)
+    assert f16 < 0.5 and f24 < 0.5, (f16, f24)
+    assert f24 < f16 + 0.08
+    assert L24 >= L16
+
+
+# ----------------------------------------------------------------- ILU(0)
+def test_ilu0_reproduces_a_on_pattern():
+    c = J.small(4, 4, 3)
+    h = O.Cptr(c.row_ptr, c.col_idx, c.values)
+    F = h.ilu().toarray()
+    L = np.tril(F, -1) + np.eye(F.shape[0])
+    U = np.triu(F)
+    A = dense(c)
+    pattern = c.to_scipy().tocsr()
+    pattern.data[:] = 1
+    mask = sp.csr_matrix(c.to_scipy(), copy=True)
+    mask.data = np.ones_like(mask.data)
+    mask = mask.toarray() > 0
+    LU = L @ U
+    assert np.abs((LU - A)[mask]).max() <= 1e-13 * np.abs(A).max()
+    # factors live on the pattern
+    assert np.all(F[~mask] == 0)
+
+
+def test_ilu0_sweeps_match_triangular_solves():
+    c = J.small(4, 3, 3)
+    h = O.Cptr(c.row_ptr, c.col_idx, c.values)
+    F = h.ilu()
+    L = sp.tril(F, -1) + sp.eye(F.shape[0])
+    U = sp.triu(F)
+    r = np.random.default_rng(3).standard_normal(c.n_dof)
+    y = spla.spsolve_triangular(sp.csr_matrix(L), r, lower=True)
+    x = spla.spsolve_triangular(sp.csr_matrix(U), y, lower=False)
+    assert rel(h.ilu_solve(r), x) < 1e-12
+
+
+def test_ilu0_exact_on_block_tridiagonal():
+    """A 1D grid gives a block-tridiagonal matrix; ILU(0) then has no dropped
+    fill and equals the exact LU, so M2^{-1} r = A^{-1} r."""
+    c = J.small(12, 1, 1)
+    h = O.Cptr(c.row_ptr, c.col_idx, c.values)
+    r = np.random.default_rng(4).standard_normal(c.n_dof)
+    assert rel(h.ilu_solve(r), np.linalg.solve(dense(c), r)) < 1e-10
+
+
+def test_ilu0_zero_pivot_is_an_error():
+    c = J.small(3, 2, 1)
+    v = c.values.copy()
+    # zero the diagonal block of row 1
+    for k in range(c.row_ptr[1], c.row_ptr[2]):
+        if c.col_idx[k] == 1:
+            v[k] = 0.0
+    v[:, 2, 2] = np.where(np.all(v == 0, axis=(1, 2)), 0.0, v[:, 2, 2])
+    with pytest.raises(O.OracleError):
+        O.Cptr(c.row_ptr, c.col_idx, v, qi=False)
+
+
+# ----------------------------------------------------------------- quasi-IMPES
+def test_quasi_impes_decouples_diagonal_block():
+    c = J.small(4, 3, 2)
+    h = O.Cptr(c.row_ptr, c.col_idx, c.values)
+    W = h.W()
+    E, H = [0, 1], [2]
+    nb = c.n_cells
+    for i in range(nb):
+        k = [q for q in range(c.row_ptr[i], c.row_ptr[i + 1]) if c.col_idx[q] == i][0]
+        D = c.values[k]
+        Ri = np.hstack([np.eye(2), -W[i]])
+        # the restricted diagonal block has no hyperbolic column left
+        assert np.abs(Ri @ D[np.ix_(E + H, H)]).max() <= 1e-12 * np.abs(D).max()
+    # Ahat = R_QI A P_E as dense products
+    R = np.zeros((2 * nb, 3 * nb))
+    Pe = np.zeros((3 * nb, 2 * nb))
+    for i in range(nb):
+        R[2 * i:2 * i + 2, 3 * i:3 * i + 2] = np.eye(2)
+        R[2 * i:2 * i + 2, 3 * i + 2] = -W[i][:, 0]
+        Pe[3 * i:3 * i + 2, 2 * i:2 * i + 2] = np.eye(2)
+    A = dense(c)
+    assert rel(h.ahat().toarray(), R @ A @ Pe) < 1e-13
+    r = np.random.default_rng(0).standard_normal(c.n_dof)
+    assert rel(h.restrict(r), R @ r) < 1e-14
+    e = np.random.default_rng(1).standard_normal(2 * nb)
+    assert np.array_equal(h.prolong(e), Pe @ e)
+
+
+def test_quasi_impes_two_hyperbolic_unknowns():
+    """One elliptic unknown (the CPR split of Sec. 3.1) leaves a 2x2
+    hyperbolic block: W_i must still cancel the whole hyperbolic column block
+    of the diagonal block."""
+    c = J.small(4, 3, 2)
+    h = O.Cptr(c.row_ptr, c.col_idx, c.values, elliptic=(0,))
+    W = h.W()
+    assert W.shape == (c.n_cells, 1, 2)
+    for i in range(c.n_cells):
+        k = [q for q in range(c.row_ptr[i], c.row_ptr[i + 1]) if c.col_idx[q] == i][0]
+        D = c.values[k]
+        Ri = np.hstack([np.eye(1), -W[i]])
+        assert np.abs(Ri @ D[np.ix_([0, 1, 2], [1, 2])]).max() <= 1e-12 * np.abs(D).max()
+
+
+def test_quasi_impes_zero_coupling_is_injection():
+    c = J.small(4, 3, 2)
+    v = c.values.copy()
+    for i in range(c.n_cells):
+        for k in range(c.row_ptr[i], c.row_ptr[i + 1]):
+            if c.col_idx[k] == i:
+                v[k, 0:2, 2] = 0.0
+    h = O.Cptr(c.row_ptr, c.col_idx, v)
+    assert np.all(h.W() == 0.0)
+    Aee = np.zeros((2 * c.n_cells, 2 * c.n_cells))
+    Ad = sp.bsr_matrix((v, c.col_idx, c.row_ptr), shape=(c.n_dof, c.n_dof)).toarray()
+    sel = np.array([3 * i + e for i in range(c.n_cells) for e in (0, 1)])
+    Aee = Ad[np.ix_(sel, sel)]
+    assert np.array_equal(h.ahat().toarray(), Aee)
+
+
+# ----------------------------------------------------------------- CPTR apply
+def test_apply_is_linear():
+    c = J.small(5, 4, 3)
+    h = O.Cptr(c.row_ptr, c.col_idx, c.values)
+    rng = np.random.default_rng(6)
+    r1, r2 = rng.standard_normal((2, c.n_dof))
+    lhs = h.apply(2.5 * r1 - 0.75 * r2)
+    rhs = 2.5 * h.apply(r1) - 0.75 * h.apply(r2)
+    # rounding is amplified by the cancellation in r - A M1^-1 r (cond(A) ~ 1e7)
+    assert rel(lhs, rhs) < 1e-10
+
+
+def test_apply_is_two_stage_composition():
+    """Eq. (3): M^-1 = M1^-1 + M2^-1 (I - A M1^-1), checked as explicit matrices
+    built column by column from the stage operators; equivalently the error
+    propagation factorises as (I - M2^-1 A)(I - M1^-1 A)."""
+    c = J.small(3, 3, 2)
+    h = O.Cptr(c.row_ptr, c.col_idx, c.values)
+    n = c.n_dof
+    I = np.eye(n)
+    M = np.column_stack([h.apply(e) for e in I])
+    M1 = np.column_stack([h.stage1(e) for e in I])
+    M2 = np.column_stack([h.ilu_solve(e) for e in I])
+    A = dense(c)
+    # componentwise rounding bound: eps-sized relative to |M1| + |M2| + |M2||A||M1|
+    bound = np.abs(M1) + np.abs(M2) + np.abs(M2) @ np.abs(A) @ np.abs(M1)
+    assert np.all(np.abs(M - (M1 + M2 - M2 @ A @ M1)) <= 1e-13 * bound)
+    Ep = I - M @ A
+    bound_e = I + np.abs(M) @ np.abs(A) + (I + np.abs(M2) @ np.abs(A)) @ (I + np.abs(M1) @ np.abs(A))
+    assert np.all(np.abs(Ep - (I - M2 @ A) @ (I - M1 @ A)) <= 1e-13 * bound_e)
+    # M1 is zero on the hyperbolic rows (Sec. 3: first block row of M1 is zero)
+    assert np.all(M1[2::3] == 0.0)
+
+
+def test_apply_exact_on_1d_grid():
+    """With exact ILU(0) (1D grid) Eq. (3) collapses to A^{-1}."""
+    c = J.small(10, 1, 1)
+    h = O.Cptr(c.row_ptr, c.col_idx, c.values)
+    r = np.random.default_rng(7).standard_normal(c.n_dof)
+    assert rel(h.apply(r), np.linalg.solve(dense(c), r)) < 1e-9
+
+
+# ----------------------------------------------------------------- GMRES
+@pytest.mark.parametrize("flexible", [False, True])
+def test_gmres_matches_dense_solve(flexible):
+    c = J.small(4, 4, 2)
+    h = O.Cptr(c.row_ptr, c.col_idx, c.values)
+    x, info = h.gmres(c.b, rtol=1e-12, restart=30, flexible=flexible)
+    assert info["converged"]
+    xd = np.linalg.solve(dense(c), c.b)
+    cond = np.linalg.cond(dense(c))
+    assert rel(x, xd) <= cond * 1e-12 * 10
+    assert info["rel_res_true"] <= 1e-12
+
+
+def test_gmres_residual_monotone_within_cycles():
+    c = J.config0()
+    h = O.Cptr(c.row_ptr, c.col_idx, c.values)
+    _, info = h.gmres(c.b, rtol=1e-10, restart=5, history=True, max_iter=60)
+    hist = info["history"]
+    # inside each restart cycle of 5 steps the estimate never increases
+    for s in range(0, len(hist) - 1, 5):
+        seg = hist[s:s + 6]
+        assert np.all(np.diff(seg) <= 1e-12 * seg[0])
+
+
+def test_gmres_unrestarted_finishes_within_n():
+    c = J.small(4, 2, 2)
+    n = c.n_dof
+    _, info = O.gmres(c.row_ptr, c.col_idx, c.values, c.b, restart=n, max_iter=n,
+                      precond=O.PC_NONE, rtol=1e-9)
+    assert info["iterations"] <= n
+    assert info["rel_res_true"] < 1e-7
+
+
+def test_gmres_exact_preconditioner_one_iteration():
+    c = J.small(10, 1, 1)
+    h = O.Cptr(c.row_ptr, c.col_idx, c.values)
+    _, info = h.gmres(c.b, rtol=1e-8)
+    assert info["iterations"] == 1 and info["converged"]
+
+
+def test_gmres_history_matches_scipy():
+    c = J.small(4, 3, 2)
+    A = c.to_scipy().tocsr()
+    n = c.n_dof
+    ours = O.gmres(c.row_ptr, c.col_idx, c.values, c.b, restart=n, max_iter=20,
+                   precond=O.PC_NONE, rtol=1e-14, history=True)[1]["history"]
+    ref = []
+    spla.gmres(A, c.b, restart=n, maxiter=1, rtol=1e-14, atol=0,
+               callback=lambda pr: ref.append(pr), callback_type="pr_norm")
+    k = min(len(ref), 20)
+    np.testing.assert_allclose(ours[1:k + 1], ref[:k], rtol=1e-6)
+
+
+def test_gmres_estimate_matches_true_residual():
+    c = J.config0()
+    h = O.Cptr(c.row_ptr, c.col_idx, c.values)
+    _, info = h.gmres(c.b, rtol=1e-8, restart=30)
+    assert info["converged"]
+    assert abs(info["rel_res_est"] - info["rel_res_true"]) <= 1e-10 + 1e-3 * info["rel_res_true"]
+
+
+def test_gmres_not_converged_status():
+    c = J.config0()
+    h = O.Cptr(c.row_ptr, c.col_idx, c.values)
+    _, info = h.gmres(c.b, rtol=1e-300, max_iter=3)
+    assert info["status"] == O.NOT_CONVERGED and info["iterations"] == 3
+
+
+# ----------------------------------------------------------------- generator
+def test_generator_properties():
+    c = J.config1(10.0)
+    assert abs(c.meta["peclet"] - 10.0) <= 0.01 * 10.0
+    A = c.to_scipy().tocsr()
+    App = A[0::3, :][:, 0::3]
+    assert abs(App - App.T).max() <= 1e-12 * abs(App).max()
+    diag = [c.values[k] for i in range(0, c.n_cells, 997)
+            for k in range(c.row_ptr[i], c.row_ptr[i + 1]) if c.col_idx[k] == i]
+    assert all(abs(np.linalg.det(D)) > 0 for D in diag)
+    assert np.all(np.diff(c.row_ptr) >= 4)
+    x = O.bsr_spmv(c.row_ptr, c.col_idx, c.values, c.x_star)
+    assert rel(x, c.b) < 1e-12
