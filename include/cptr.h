@@ -1,0 +1,177 @@
+/* cptr.h -- C ABI of the MI355X CPTR library.
+ *
+ * The library applies the Constrained Pressure-Temperature Residual (CPTR)
+ * two-stage preconditioner inside right-preconditioned (F)GMRES to block-sparse
+ * Jacobians with interleaved per-cell unknowns (Cremon, Franc, Hamon, "CPTR
+ * Preconditioner Performance for Large-Scale Thermal CO2 Injection
+ * Simulation").  The operations follow the paper's statement of the problem:
+ *   - Eq. (3): M^-1 = M1^-1 + M2^-1 (I - A M1^-1);
+ *   - Sec. 3: A split into elliptic and hyperbolic unknowns, the first stage
+ *     M1^-1 = [[0,0],[0,Mee^-1]], right-preconditioned GMRES, 200 iterations,
+ *     relative tolerance 1e-6;
+ *   - Sec. 3.1: the variables are interleaved per cell; Mee^-1 is one AMG
+ *     V-cycle (HMIS coarsening, extended+i interpolation truncated to 4
+ *     entries per row, first-order relaxation); the second stage is ILU(0);
+ *   - Sec. 3.2: CPTR puts pressure and temperature in the elliptic block and
+ *     solves it with system AMG;
+ *   - Sec. 5.2: the elliptic block is reached by a quasi-IMPES decomposition.
+ *
+ * General rules
+ *   - Every call returns cptr_status; nothing aborts, throws or prints.
+ *     Negative values are errors, CPTR_NOT_CONVERGED (> 0) is a warning with a
+ *     valid result.  cptr_last_error() returns a message for the last failure.
+ *   - Vectors passed to cptr_apply / cptr_gmres_solve / cptr_spmv are device
+ *     pointers to FP64 arrays of length N = n_block_rows * block_size in the
+ *     matrix's interleaved order (unknown c of cell i at index i*b + c).  The
+ *     caller owns them; they must stay valid until the work on `stream`
+ *     completes.  Input and output must not alias.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     All device work is enqueued on it.
+ *   - A handle owns all hierarchy, factor and workspace memory; it allocates
+ *     in cptr_setup and frees in cptr_destroy.  cptr_apply never allocates;
+ *     cptr_gmres_solve allocates only when its restart length exceeds every
+ *     earlier call's.  A handle is not thread-safe; distinct handles are
+ *     independent.
+ */
+#ifndef CPTR_H
+#define CPTR_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cptr_solver_s *cptr_solver;
+
+typedef enum {
+  CPTR_OK = 0,
+  CPTR_NOT_CONVERGED = 1,      /* max_iter reached; x holds the last iterate */
+  CPTR_E_INVALID = -1,         /* bad argument; message names field and row */
+  CPTR_E_NOMEM = -2,           /* host or device allocation failed */
+  CPTR_E_ZERO_PIVOT = -3,      /* zero ILU(0) pivot, singular hyperbolic block or zero smoother diagonal */
+  CPTR_E_SINGULAR_COARSE = -4, /* coarsest AMG matrix singular or too large */
+  CPTR_E_HIP = -5,             /* a HIP runtime call failed */
+  CPTR_E_STATE = -6            /* call not valid for this handle (e.g. host-only setup) */
+} cptr_status;
+
+/* Block-sparse (BSR) matrix, square blocks of block_size^2 values stored
+ * row-major inside the block, blocks of a row sorted by column with the
+ * diagonal block present.  The caller owns the arrays; the library reads them
+ * only during cptr_setup and keeps its own copies. */
+typedef struct {
+  int32_t n_block_rows;
+  int64_t nnz_blocks;
+  const int32_t *row_ptr;   /* [n_block_rows + 1], row_ptr[0] = 0 */
+  const int32_t *col_idx;   /* [nnz_blocks] */
+  const double *values;     /* [nnz_blocks * block_size * block_size] */
+  int32_t on_device;        /* 0: host pointers, 1: device pointers */
+} cptr_bsr;
+
+enum { CPTR_RESTRICT_QUASI_IMPES = 0, CPTR_RESTRICT_INJECTION = 1 };
+
+typedef struct {
+  double strong_threshold;   /* AMG strength threshold theta, default 0.25 */
+  double max_row_sum;        /* rows with |same-function row sum| > this * |a_ii| have only weak links; 0.9 */
+  int32_t max_levels;        /* AMG levels including the coarsest, default 25 */
+  int32_t max_coarse;        /* stop coarsening at or below this many rows, default 9 */
+  int32_t p_max_elmts;       /* interpolation entries kept per row, default 4 */
+  int32_t restriction;       /* CPTR_RESTRICT_*, default quasi-IMPES */
+  int32_t host_only;         /* 1: build the hierarchy on the host only (for inspection
+                                through cptr_export; apply/solve return CPTR_E_STATE) */
+  int32_t setup_threads;     /* host threads for setup; 0 = min(16, hardware threads) */
+} cptr_setup_opts;
+
+typedef struct {
+  int32_t restart;           /* Krylov vectors per cycle, default 30 */
+  int32_t max_iter;          /* total iterations across restarts, default 200 */
+  int32_t flexible;          /* 0: right GMRES (x += M^-1 V y), 1: FGMRES (x += Z y) */
+  int32_t x0_is_zero;        /* 1: ignore x on entry and start from 0, default 1 */
+  double rtol;               /* stop when ||b - A x||_2 <= rtol ||b||_2, default 1e-6 */
+  int32_t profile;           /* 1: time each kernel phase with HIP events (cptr_phase_times) */
+} cptr_solve_opts;
+
+typedef struct {
+  int32_t iterations;        /* Arnoldi steps = applications of A M^-1 */
+  int32_t restarts;          /* completed cycles before the last */
+  int32_t converged;         /* 1 when the true residual met the tolerance */
+  double rel_res_est;        /* |g_{j+1}| / ||b|| from the Givens recurrence */
+  double rel_res_true;       /* ||b - A x|| / ||b|| recomputed at the end */
+  double setup_s;            /* wall time of cptr_setup */
+  double solve_s;            /* wall time of this cptr_gmres_solve */
+} cptr_solve_info;
+
+void cptr_setup_opts_default(cptr_setup_opts *o);
+void cptr_solve_opts_default(cptr_solve_opts *o);
+
+/* Build the preconditioner for A (Sec. 3, 3.2, 5.2).
+ *   block_size    must be 3 (two elliptic + one hyperbolic, or one + two);
+ *   elliptic_idx  within-block unknown indices of the elliptic block, e.g. {0,1}
+ *                 for (p, T); equation k pairs with unknown k; 1 <= n_elliptic <
+ *                 block_size, values unique and in range;
+ *   opts          NULL for defaults;
+ *   stream        hipStream_t (void*) receiving the uploads;
+ *   out           receives the handle on success (NULL on failure).
+ * Errors: CPTR_E_INVALID (null pointer, block size, indices, unsorted or
+ * duplicate columns, missing diagonal block, non-finite value),
+ * CPTR_E_ZERO_PIVOT (zero ILU(0) pivot, singular hyperbolic diagonal block,
+ * zero smoother diagonal), CPTR_E_SINGULAR_COARSE, CPTR_E_NOMEM, CPTR_E_HIP. */
+cptr_status cptr_setup(const cptr_bsr *A, int32_t block_size, const int32_t *elliptic_idx,
+                       int32_t n_elliptic, const cptr_setup_opts *opts, void *stream,
+                       cptr_solver *out);
+
+/* z = M^-1 r, Eq. (3), asynchronous on `stream`; no host synchronisation and
+ * no allocation. */
+cptr_status cptr_apply(cptr_solver s, const double *r, double *z, void *stream);
+
+/* Solve A x = b with right-preconditioned restarted GMRES (or FGMRES) and the
+ * CPTR preconditioner (Sec. 3).  Synchronises `stream` once per iteration for
+ * the host Givens update and returns with x final and info filled (info may be
+ * NULL; o NULL for defaults).  CPTR_NOT_CONVERGED when max_iter is reached. */
+cptr_status cptr_gmres_solve(cptr_solver s, const double *b, double *x, const cptr_solve_opts *o,
+                             cptr_solve_info *info, void *stream);
+
+/* y = A x with the block SpMV kernel of the solve (Eq. 3 uses A in the
+ * stage-two residual and GMRES applies it once per iteration). */
+cptr_status cptr_spmv(cptr_solver s, const double *x, double *y, void *stream);
+
+cptr_status cptr_destroy(cptr_solver s);
+
+/* Message of the last failed call on s, or of the last failed cptr_setup in
+ * this thread when s is NULL.  Never NULL. */
+const char *cptr_last_error(cptr_solver s);
+
+/* ---- introspection (tests, benchmarks) ---- */
+
+/* Number of AMG levels and, per level, rows and stored entries (arrays of at
+ * least *n_levels entries; pass NULL to query the count only). */
+cptr_status cptr_hierarchy_info(cptr_solver s, int32_t *n_levels, int64_t *rows, int64_t *nnz);
+
+enum {
+  CPTR_EXPORT_CF = 0,        /* int32[rows_l]: 1 = C, -1 = F (levels below the coarsest) */
+  CPTR_EXPORT_A_ROWPTR = 1,  /* int64[rows_l + 1] of level-l scalar CSR A_l */
+  CPTR_EXPORT_A_COLS = 2,    /* int32[nnz_l] */
+  CPTR_EXPORT_A_VALS = 3,    /* double[nnz_l] */
+  CPTR_EXPORT_P_ROWPTR = 4,  /* int64[rows_l + 1] of P_l */
+  CPTR_EXPORT_P_COLS = 5,
+  CPTR_EXPORT_P_VALS = 6,
+  CPTR_EXPORT_W = 7,         /* double[n_block_rows * n_elliptic * n_hyperbolic] */
+  CPTR_EXPORT_DINV = 8,      /* double[rows_l], inverse l1-Jacobi diagonal */
+  CPTR_EXPORT_ILU_VALS = 9,  /* double[nnz_blocks * 9]: L below the diagonal
+                                (unit diagonal blocks implied), U on and above,
+                                with the diagonal blocks stored as U_ii (not inverted) */
+  CPTR_EXPORT_ILU_NLEVELS = 10 /* int32[2]: forward and backward dependency levels */
+};
+/* Copy one piece of the setup into host_buf (bytes = its capacity). */
+cptr_status cptr_export(cptr_solver s, int32_t what, int32_t level, void *host_buf, int64_t bytes);
+
+/* Per-phase GPU times accumulated by solves with profile = 1 since the last
+ * reset.  Phases: 0 SpMV, 1 restriction, 2 V-cycle level 0, 3 V-cycle coarse
+ * levels, 4 stage-two residual, 5 ILU forward, 6 ILU backward, 7 Arnoldi,
+ * 8 solution update.  ms[k] = total milliseconds, count[k] = launches timed.
+ * n = array capacity; reset = 1 clears after copying. */
+cptr_status cptr_phase_times(cptr_solver s, double *ms, int64_t *count, int32_t n, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,836 @@
+// cptr_api.cpp -- C ABI of the CPTR library: setup, apply, (F)GMRES solve.
+//
+// Device work for one preconditioner application (Eq. 3 of the paper):
+//   b0 = R_QI r                              quasi-IMPES restriction (Sec. 5.2)
+//   e0 = one V-cycle on Ahat b0              system AMG, (p, T) block (Sec. 3.1, 3.2)
+//   r2 = r - A P_E e0                        stage-two residual
+//   z  = P_E e0 + U^-1 L^-1 r2               ILU(0) on the full system (Sec. 3.1)
+// The solver is right-preconditioned restarted GMRES (Sec. 3) with classical
+// Gram-Schmidt applied twice on the device and the Hessenberg least-squares
+// problem updated by Givens rotations on the host in FP64.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "cptr.h"
+#include "host_setup.hpp"
+#include "kernels.hpp"
+
+using namespace cptr;
+
+namespace {
+
+thread_local std::string g_setup_error;
+
+constexpr int kMaxRestart = 64;
+constexpr int kPhases = 9;
+enum Phase { PH_SPMV = 0, PH_RESTRICT, PH_VC0, PH_VCC, PH_STAGE2, PH_ILU_F, PH_ILU_B, PH_ARNOLDI, PH_UPDATE };
+
+struct HostSell {
+  int32_t nrows = 0, nslices = 0, nv = 0;
+  std::vector<int32_t> sptr, col;
+  std::vector<double> val;
+};
+
+// Pack rows (or positions) into SELL-64; len(r) blocks per row, fill(r, k, col, vals).
+template <class Len, class Fill>
+HostSell pack_sell(int32_t nrows, int nv, Len len, Fill fill, int32_t pad_col_mode) {
+  HostSell s;
+  s.nrows = nrows;
+  s.nv = nv;
+  s.nslices = (nrows + kLanes - 1) / kLanes;
+  s.sptr.assign(s.nslices + 1, 0);
+  for (int32_t sl = 0; sl < s.nslices; ++sl) {
+    int32_t w = 0;
+    for (int l = 0; l < kLanes; ++l) {
+      const int32_t r = sl * kLanes + l;
+      if (r < nrows) w = std::max<int32_t>(w, len(r));
+    }
+    s.sptr[sl + 1] = s.sptr[sl] + w;
+  }
+  const int64_t slots = s.sptr[s.nslices];
+  s.col.assign((size_t)slots * kLanes, 0);
+  s.val.assign((size_t)slots * kLanes * nv, 0.0);
+  for (int32_t sl = 0; sl < s.nslices; ++sl) {
+    const int32_t w = s.sptr[sl + 1] - s.sptr[sl];
+    for (int l = 0; l < kLanes; ++l) {
+      const int32_t r = sl * kLanes + l;
+      const int32_t n = r < nrows ? len(r) : 0;
+      for (int32_t k = 0; k < w; ++k) {
+        const int64_t slot = (int64_t)s.sptr[sl] + k;
+        double vals[9] = {0};
+        int32_t c;
+        if (k < n) {
+          fill(r, k, c, vals);
+        } else {
+          c = pad_col_mode < 0 ? -1 : (r < nrows ? r : 0);  // padding: own row, zero block
+        }
+        s.col[(size_t)slot * kLanes + l] = c;
+        for (int e = 0; e < nv; ++e) s.val[((size_t)slot * nv + e) * kLanes + l] = k < n ? vals[e] : 0.0;
+      }
+    }
+  }
+  return s;
+}
+
+struct DevVec {
+  double* p = nullptr;
+  int64_t n = 0;
+};
+
+}  // namespace
+
+struct cptr_solver_s {
+  HostSetup host;
+  bool device = false;
+  std::string err;
+  double setup_s = 0.0;
+  int ne = 2;
+  int32_t eidx_h[3] = {0, 1, 2}, hidx_h[3] = {2, 0, 0};
+  int64_t N = 0;  // DOF
+  std::vector<void*> allocs;
+  // device operators
+  Sell A, Ahat, Lf, Ub;
+  double* W = nullptr;
+  int32_t* fperm = nullptr;
+  int32_t* bperm = nullptr;
+  double* uinv = nullptr;
+  std::vector<int32_t> flev_ptr, blev_ptr;
+  struct Lev {
+    DCsr A, P, R;
+    double* dinv = nullptr;
+    double *b = nullptr, *r = nullptr, *x = nullptr, *e = nullptr;
+    int32_t n = 0;
+  };
+  std::vector<Lev> lev;
+  double* coarse_lu = nullptr;
+  int32_t* coarse_piv = nullptr;
+  int32_t ncoarse = 0;
+  // apply workspace
+  double *r2 = nullptr, *y = nullptr, *x2 = nullptr;
+  // solve workspace
+  int restart_cap = 0;
+  bool have_z = false;
+  double* V = nullptr;
+  double* Z = nullptr;
+  int64_t ldv = 0;
+  double *wr = nullptr, *wt = nullptr, *wu = nullptr;
+  double* part = nullptr;
+  double* hdev = nullptr;   // [0,64): first CGS pass, [64,128): second, [128]: ||w||^2, [136]: scratch
+  double* hhost = nullptr;  // pinned copy
+  // profiling
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+  double phase_ms[kPhases] = {0};
+  int64_t phase_cnt[kPhases] = {0};
+};
+
+namespace {
+
+int fail(cptr_solver s, int code, const std::string& msg) {
+  if (s) s->err = msg;
+  else g_setup_error = msg;
+  return code;
+}
+
+int hip_fail(cptr_solver s, hipError_t e, const char* what) {
+  return fail(s, CPTR_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(s, call)                                  \
+  do {                                                    \
+    hipError_t _e = (call);                               \
+    if (_e != hipSuccess) return (cptr_status)hip_fail((s), _e, #call); \
+  } while (0)
+
+template <class T>
+int dalloc(cptr_solver s, T*& p, int64_t count) {
+  p = nullptr;
+  if (count <= 0) count = 1;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, sizeof(T) * (size_t)count);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(s, CPTR_E_NOMEM, "device allocation of " + std::to_string(sizeof(T) * count) + " bytes failed");
+  }
+  s->allocs.push_back(q);
+  p = static_cast<T*>(q);
+  return CPTR_OK;
+}
+
+template <class T>
+int upload(cptr_solver s, T*& p, const T* src, int64_t count, hipStream_t st) {
+  int rc = dalloc(s, p, count);
+  if (rc) return rc;
+  // blocking copy: the host staging vectors die right after the upload
+  (void)st;
+  if (count > 0) HIP_TRY(s, hipMemcpy(p, src, sizeof(T) * (size_t)count, hipMemcpyHostToDevice));
+  return CPTR_OK;
+}
+
+int upload_sell(cptr_solver s, Sell& d, const HostSell& h, hipStream_t st) {
+  d.nrows = h.nrows;
+  d.nslices = h.nslices;
+  d.nv = h.nv;
+  d.nslots = h.sptr.back();
+  int rc;
+  if ((rc = upload(s, d.sptr, h.sptr.data(), (int64_t)h.sptr.size(), st))) return rc;
+  if ((rc = upload(s, d.col, h.col.data(), (int64_t)h.col.size(), st))) return rc;
+  if ((rc = upload(s, d.val, h.val.data(), (int64_t)h.val.size(), st))) return rc;
+  return CPTR_OK;
+}
+
+int pick_group(int64_t nnz, int32_t n) {
+  const double avg = n > 0 ? (double)nnz / n : 1.0;
+  int g = 1;
+  while (g < 32 && g < avg) g <<= 1;
+  return g;
+}
+
+int upload_csr(cptr_solver s, DCsr& d, const Csr& h, hipStream_t st) {
+  d.n = h.n;
+  d.m = h.m;
+  d.nnz = h.nnz();
+  if (d.nnz >= INT32_MAX) return fail(s, CPTR_E_INVALID, "AMG level too large for 32-bit offsets");
+  std::vector<int32_t> rp32(h.rp.begin(), h.rp.end());
+  d.group = pick_group(d.nnz, d.n);
+  int rc;
+  if ((rc = upload(s, d.rp, rp32.data(), (int64_t)rp32.size(), st))) return rc;
+  if ((rc = upload(s, d.ci, h.ci.data(), (int64_t)h.ci.size(), st))) return rc;
+  if ((rc = upload(s, d.v, h.v.data(), (int64_t)h.v.size(), st))) return rc;
+  return CPTR_OK;
+}
+
+int build_device(cptr_solver s, hipStream_t st) {
+  const HostSetup& h = s->host;
+  const int32_t nb = h.nb;
+  const int ne = h.ne;
+  int rc;
+  // A in SELL-64, natural order
+  {
+    HostSell hs = pack_sell(
+        nb, 9, [&](int32_t r) { return h.rp[r + 1] - h.rp[r]; },
+        [&](int32_t r, int32_t k, int32_t& c, double* v) {
+          const int32_t q = h.rp[r] + k;
+          c = h.ci[q];
+          std::memcpy(v, &h.av[(size_t)q * 9], 9 * sizeof(double));
+        },
+        0);
+    if ((rc = upload_sell(s, s->A, hs, st))) return rc;
+  }
+  // Ahat (ne x ne blocks) in SELL-64
+  {
+    HostSell hs = pack_sell(
+        nb, ne * ne, [&](int32_t r) { return h.rp[r + 1] - h.rp[r]; },
+        [&](int32_t r, int32_t k, int32_t& c, double* v) {
+          const int32_t q = h.rp[r] + k;
+          c = h.ci[q];
+          std::memcpy(v, &h.ahat[(size_t)q * ne * ne], ne * ne * sizeof(double));
+        },
+        0);
+    if ((rc = upload_sell(s, s->Ahat, hs, st))) return rc;
+  }
+  // W padded to 2 per cell
+  {
+    std::vector<double> w2((size_t)nb * 2, 0.0);
+    for (int32_t i = 0; i < nb; ++i)
+      for (int t = 0; t < ne * h.nh; ++t) w2[(size_t)i * 2 + t] = h.W[(size_t)i * ne * h.nh + t];
+    if ((rc = upload(s, s->W, w2.data(), (int64_t)w2.size(), st))) return rc;
+  }
+  // ILU sweeps: positions sorted by level (stable in row order)
+  {
+    auto order = [&](const std::vector<int32_t>& lvl, int32_t nl, std::vector<int32_t>& perm,
+                     std::vector<int32_t>& ptr) {
+      ptr.assign(nl + 1, 0);
+      for (int32_t i = 0; i < nb; ++i) ++ptr[lvl[i] + 1];
+      for (int32_t l = 0; l < nl; ++l) ptr[l + 1] += ptr[l];
+      std::vector<int32_t> fillp(ptr.begin(), ptr.end() - 1);
+      perm.resize(nb);
+      for (int32_t i = 0; i < nb; ++i) perm[fillp[lvl[i]]++] = i;
+    };
+    std::vector<int32_t> fp, bp;
+    order(h.fwd_level, h.n_fwd_levels, fp, s->flev_ptr);
+    order(h.bwd_level, h.n_bwd_levels, bp, s->blev_ptr);
+    HostSell Lh = pack_sell(
+        nb, 9, [&](int32_t p) { return h.diag[fp[p]] - h.rp[fp[p]]; },
+        [&](int32_t p, int32_t k, int32_t& c, double* v) {
+          const int32_t q = h.rp[fp[p]] + k;
+          c = h.ci[q];
+          std::memcpy(v, &h.ilu[(size_t)q * 9], 9 * sizeof(double));
+        },
+        -1);
+    if ((rc = upload_sell(s, s->Lf, Lh, st))) return rc;
+    HostSell Uh = pack_sell(
+        nb, 9, [&](int32_t p) { return h.rp[bp[p] + 1] - h.diag[bp[p]] - 1; },
+        [&](int32_t p, int32_t k, int32_t& c, double* v) {
+          const int32_t q = h.diag[bp[p]] + 1 + k;
+          c = h.ci[q];
+          std::memcpy(v, &h.ilu[(size_t)q * 9], 9 * sizeof(double));
+        },
+        -1);
+    if ((rc = upload_sell(s, s->Ub, Uh, st))) return rc;
+    const int64_t npad = (int64_t)Uh.nslices * kLanes;
+    std::vector<double> ui((size_t)npad * 9, 0.0);
+    for (int32_t p = 0; p < nb; ++p)
+      for (int e = 0; e < 9; ++e) ui[(size_t)e * npad + p] = h.uinv[(size_t)bp[p] * 9 + e];
+    if ((rc = upload(s, s->uinv, ui.data(), (int64_t)ui.size(), st))) return rc;
+    if ((rc = upload(s, s->fperm, fp.data(), nb, st))) return rc;
+    if ((rc = upload(s, s->bperm, bp.data(), nb, st))) return rc;
+  }
+  // AMG hierarchy
+  const int L = (int)h.lev.size();
+  s->lev.resize(L);
+  for (int l = 0; l < L; ++l) {
+    const AmgLevel& hl = h.lev[l];
+    auto& d = s->lev[l];
+    d.n = hl.A.n;
+    if (l > 0 && (rc = upload_csr(s, d.A, hl.A, st))) return rc;
+    if (l + 1 < L) {
+      if ((rc = upload_csr(s, d.P, hl.P, st))) return rc;
+      if ((rc = upload_csr(s, d.R, hl.R, st))) return rc;
+      if ((rc = upload(s, d.dinv, hl.dinv.data(), (int64_t)hl.dinv.size(), st))) return rc;
+    }
+    if ((rc = dalloc(s, d.b, d.n)) || (rc = dalloc(s, d.r, d.n)) || (rc = dalloc(s, d.x, d.n)) ||
+        (rc = dalloc(s, d.e, d.n)))
+      return rc;
+  }
+  s->ncoarse = h.lev.back().A.n;
+  if ((rc = upload(s, s->coarse_lu, h.coarse_lu.data(), (int64_t)h.coarse_lu.size(), st))) return rc;
+  if ((rc = upload(s, s->coarse_piv, h.coarse_piv.data(), (int64_t)h.coarse_piv.size(), st))) return rc;
+  const int64_t N = (int64_t)nb * 3;
+  if ((rc = dalloc(s, s->r2, N)) || (rc = dalloc(s, s->y, N)) || (rc = dalloc(s, s->x2, N))) return rc;
+  if ((rc = dalloc(s, s->part, (int64_t)kRedBlocks * (kMaxRestart + 2)))) return rc;
+  if ((rc = dalloc(s, s->hdev, 256))) return rc;
+  {
+    void* hp = nullptr;
+    HIP_TRY(s, hipHostMalloc(&hp, 256 * sizeof(double), hipHostMallocDefault));
+    s->hhost = static_cast<double*>(hp);
+  }
+  HIP_TRY(s, hipStreamSynchronize(st));
+  return CPTR_OK;
+}
+
+// ---------------------------------------------------------------- profiling
+void ph_begin(cptr_solver s, hipStream_t st, hipEvent_t& ev) {
+  ev = nullptr;
+  if (!s->profiling) return;
+  if (s->ev_used + 2 > s->ev_pool.size()) return;
+  ev = s->ev_pool[s->ev_used++];
+  (void)hipEventRecord(ev, st);
+}
+void ph_end(cptr_solver s, hipStream_t st, int phase, hipEvent_t ev0) {
+  if (!s->profiling || !ev0) return;
+  hipEvent_t ev1 = s->ev_pool[s->ev_used++];
+  (void)hipEventRecord(ev1, st);
+  s->ev_pending.push_back({phase, {ev0, ev1}});
+}
+void ph_harvest(cptr_solver s) {  // call after the stream is synchronised
+  for (auto& p : s->ev_pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
+      s->phase_ms[p.first] += ms;
+      s->phase_cnt[p.first] += 1;
+    }
+  }
+  s->ev_pending.clear();
+  s->ev_used = 0;
+}
+
+// ---------------------------------------------------------------- apply
+void enqueue_apply(cptr_solver s, const double* r, double* z, hipStream_t st) {
+  const int ne = s->ne;
+  const int L = (int)s->lev.size();
+  auto& l0 = s->lev[0];
+  hipEvent_t ev;
+  ph_begin(s, st, ev);
+  launch_l0_restrict(s->host.nb, ne, r, s->W, s->eidx_h, s->hidx_h, l0.b, st);
+  ph_end(s, st, PH_RESTRICT, ev);
+  if (L == 1) {
+    ph_begin(s, st, ev);
+    launch_coarse_solve(s->ncoarse, s->coarse_lu, s->coarse_piv, l0.b, l0.e, st);
+    ph_end(s, st, PH_VCC, ev);
+  } else {
+    ph_begin(s, st, ev);
+    launch_l0_resid_jacobi(s->Ahat, ne, l0.b, l0.dinv, l0.r, st);
+    launch_csr_spmv(l0.R, l0.r, s->lev[1].b, st);
+    ph_end(s, st, PH_VC0, ev);
+    ph_begin(s, st, ev);
+    for (int l = 1; l + 1 < L; ++l) {
+      auto& d = s->lev[l];
+      launch_csr_resid_jacobi(d.A, d.b, d.dinv, d.r, st);
+      launch_csr_spmv(d.R, d.r, s->lev[l + 1].b, st);
+    }
+    launch_coarse_solve(s->ncoarse, s->coarse_lu, s->coarse_piv, s->lev[L - 1].b, s->lev[L - 1].e, st);
+    for (int l = L - 2; l >= 1; --l) {
+      auto& d = s->lev[l];
+      launch_csr_prolong(d.P, s->lev[l + 1].e, d.b, d.dinv, d.x, st);
+      launch_csr_post(d.A, d.x, d.b, d.dinv, d.e, st);
+    }
+    ph_end(s, st, PH_VCC, ev);
+    ph_begin(s, st, ev);
+    launch_csr_prolong(l0.P, s->lev[1].e, l0.b, l0.dinv, l0.x, st);
+    launch_l0_post(s->Ahat, ne, l0.x, l0.b, l0.dinv, l0.e, st);
+    ph_end(s, st, PH_VC0, ev);
+  }
+  ph_begin(s, st, ev);
+  launch_stage2_resid(s->A, ne, s->eidx_h, l0.e, r, s->r2, st);
+  ph_end(s, st, PH_STAGE2, ev);
+  ph_begin(s, st, ev);
+  for (size_t l = 0; l + 1 < s->flev_ptr.size(); ++l)
+    launch_ilu_fwd_level(s->Lf, s->fperm, s->flev_ptr[l], s->flev_ptr[l + 1], s->r2, s->y, st);
+  ph_end(s, st, PH_ILU_F, ev);
+  ph_begin(s, st, ev);
+  for (size_t l = 0; l + 1 < s->blev_ptr.size(); ++l)
+    launch_ilu_bwd_level(s->Ub, s->bperm, s->uinv, s->blev_ptr[l], s->blev_ptr[l + 1], s->y, l0.e, ne,
+                         s->eidx_h, s->x2, z, st);
+  ph_end(s, st, PH_ILU_B, ev);
+}
+
+int ensure_solve_space(cptr_solver s, int m, bool flexible) {
+  if (m <= s->restart_cap && (!flexible || s->have_z)) return CPTR_OK;
+  const int64_t ld = (s->N + 63) / 64 * 64;
+  int rc;
+  if (m > s->restart_cap) {
+    if (s->V) {
+      (void)hipFree(s->V);
+      s->allocs.erase(std::find(s->allocs.begin(), s->allocs.end(), (void*)s->V));
+      s->V = nullptr;
+    }
+    if (s->Z) {
+      (void)hipFree(s->Z);
+      s->allocs.erase(std::find(s->allocs.begin(), s->allocs.end(), (void*)s->Z));
+      s->Z = nullptr;
+      s->have_z = false;
+    }
+    if ((rc = dalloc(s, s->V, ld * (m + 1)))) return rc;
+    s->restart_cap = m;
+    s->ldv = ld;
+  }
+  if (flexible && !s->have_z) {
+    if ((rc = dalloc(s, s->Z, ld * s->restart_cap))) return rc;
+    s->have_z = true;
+  }
+  if (!s->wr) {
+    if ((rc = dalloc(s, s->wr, s->N)) || (rc = dalloc(s, s->wt, s->N)) || (rc = dalloc(s, s->wu, s->N)))
+      return rc;
+  }
+  return CPTR_OK;
+}
+
+// ||x||_2 on the device, synchronising st
+int device_norm(cptr_solver s, const double* x, double& out, hipStream_t st) {
+  launch_norm2(s->N, x, s->part, st);
+  launch_reduce(1, s->part, s->hdev + 136, 0, st);
+  HIP_TRY(s, hipMemcpyAsync(s->hhost + 136, s->hdev + 136, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(s, hipStreamSynchronize(st));
+  out = std::sqrt(s->hhost[136]);
+  return CPTR_OK;
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+void cptr_setup_opts_default(cptr_setup_opts* o) {
+  if (!o) return;
+  o->strong_threshold = 0.25;
+  o->max_row_sum = 0.9;
+  o->max_levels = 25;
+  o->max_coarse = 9;
+  o->p_max_elmts = 4;
+  o->restriction = CPTR_RESTRICT_QUASI_IMPES;
+  o->host_only = 0;
+  o->setup_threads = 0;
+}
+
+void cptr_solve_opts_default(cptr_solve_opts* o) {
+  if (!o) return;
+  o->restart = 30;
+  o->max_iter = 200;
+  o->flexible = 0;
+  o->x0_is_zero = 1;
+  o->rtol = 1e-6;
+  o->profile = 0;
+}
+
+const char* cptr_last_error(cptr_solver s) { return s ? s->err.c_str() : g_setup_error.c_str(); }
+
+cptr_status cptr_setup(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_idx,
+                       int32_t n_elliptic, const cptr_setup_opts* opts, void* stream,
+                       cptr_solver* out) {
+  const double t0 = now_s();
+  g_setup_error.clear();
+  if (!out) return (cptr_status)fail(nullptr, CPTR_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!A) return (cptr_status)fail(nullptr, CPTR_E_INVALID, "A is NULL");
+  if (block_size != kBS)
+    return (cptr_status)fail(nullptr, CPTR_E_INVALID, "block_size must be 3");
+  if (!elliptic_idx || n_elliptic < 1 || n_elliptic >= block_size)
+    return (cptr_status)fail(nullptr, CPTR_E_INVALID, "n_elliptic must be 1 or 2 with a non-NULL elliptic_idx");
+  for (int e = 0; e < n_elliptic; ++e) {
+    if (elliptic_idx[e] < 0 || elliptic_idx[e] >= block_size)
+      return (cptr_status)fail(nullptr, CPTR_E_INVALID, "elliptic_idx out of range");
+    for (int f = 0; f < e; ++f)
+      if (elliptic_idx[f] == elliptic_idx[e])
+        return (cptr_status)fail(nullptr, CPTR_E_INVALID, "elliptic_idx has duplicates");
+  }
+  cptr_setup_opts o;
+  cptr_setup_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.max_levels < 1 || o.max_levels > 64 || o.max_coarse < 1 || o.p_max_elmts < 0 ||
+      !(o.strong_threshold >= 0.0) || !(o.max_row_sum > 0.0))
+    return (cptr_status)fail(nullptr, CPTR_E_INVALID, "setup options out of range");
+  if (A->n_block_rows <= 0 || A->nnz_blocks <= 0 || A->nnz_blocks >= INT32_MAX)
+    return (cptr_status)fail(nullptr, CPTR_E_INVALID, "A.n_block_rows / A.nnz_blocks out of range");
+  if (!A->row_ptr || !A->col_idx || !A->values)
+    return (cptr_status)fail(nullptr, CPTR_E_INVALID, "A has a NULL array");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+
+  std::unique_ptr<cptr_solver_s> s(new (std::nothrow) cptr_solver_s());
+  if (!s) return (cptr_status)fail(nullptr, CPTR_E_NOMEM, "host allocation failed");
+  const int32_t nb = A->n_block_rows;
+  const int64_t nnzb = A->nnz_blocks;
+  std::vector<int32_t> rp, ci;
+  std::vector<double> v;
+  const int32_t* prp = A->row_ptr;
+  const int32_t* pci = A->col_idx;
+  const double* pv = A->values;
+  try {
+    if (A->on_device) {
+      if (o.host_only)
+        return (cptr_status)fail(nullptr, CPTR_E_INVALID, "host_only setup needs host arrays");
+      rp.resize(nb + 1);
+      ci.resize(nnzb);
+      v.resize(nnzb * 9);
+      hipError_t e1 = hipMemcpy(rp.data(), prp, sizeof(int32_t) * (nb + 1), hipMemcpyDeviceToHost);
+      hipError_t e2 = hipMemcpy(ci.data(), pci, sizeof(int32_t) * nnzb, hipMemcpyDeviceToHost);
+      hipError_t e3 = hipMemcpy(v.data(), pv, sizeof(double) * nnzb * 9, hipMemcpyDeviceToHost);
+      if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
+        return (cptr_status)fail(nullptr, CPTR_E_HIP, "copying A from the device failed");
+      prp = rp.data();
+      pci = ci.data();
+      pv = v.data();
+    }
+  } catch (const std::bad_alloc&) {
+    return (cptr_status)fail(nullptr, CPTR_E_NOMEM, "host allocation failed");
+  }
+  std::string err;
+  int rc = validate_bsr(nb, nnzb, prp, pci, pv, err);
+  if (rc) return (cptr_status)fail(nullptr, rc, err);
+  SetupParams prm;
+  prm.theta = o.strong_threshold;
+  prm.max_row_sum = o.max_row_sum;
+  prm.max_levels = o.max_levels;
+  prm.max_coarse = o.max_coarse;
+  prm.pmax = o.p_max_elmts;
+  prm.quasi_impes = o.restriction == CPTR_RESTRICT_QUASI_IMPES;
+  unsigned hw = std::thread::hardware_concurrency();
+  prm.threads = o.setup_threads > 0 ? o.setup_threads : (int)std::min<unsigned>(16, hw ? hw : 1);
+  try {
+    rc = build_host_setup(nb, prp, pci, pv, elliptic_idx, n_elliptic, prm, s->host, err);
+  } catch (const std::bad_alloc&) {
+    return (cptr_status)fail(nullptr, CPTR_E_NOMEM, "host allocation failed during setup");
+  }
+  if (rc) return (cptr_status)fail(nullptr, rc, err);
+  s->ne = n_elliptic;
+  for (int e = 0; e < 3; ++e) {
+    s->eidx_h[e] = s->host.eidx[e];
+    s->hidx_h[e] = s->host.hidx[e];
+  }
+  s->N = (int64_t)nb * 3;
+  if (!o.host_only) {
+    int dev_count = 0;
+    hipError_t he = hipGetDeviceCount(&dev_count);
+    if (he != hipSuccess || dev_count == 0)
+      return (cptr_status)fail(nullptr, CPTR_E_HIP, "no HIP device available");
+    try {
+      rc = build_device(s.get(), st);
+    } catch (const std::bad_alloc&) {
+      rc = fail(s.get(), CPTR_E_NOMEM, "host allocation failed while packing device layouts");
+    }
+    if (rc) {
+      g_setup_error = s->err;
+      for (void* p : s->allocs) (void)hipFree(p);
+      if (s->hhost) (void)hipHostFree(s->hhost);
+      return (cptr_status)rc;
+    }
+    s->device = true;
+    s->ev_pool.resize(512);
+    for (auto& e : s->ev_pool)
+      if (hipEventCreate(&e) != hipSuccess) {
+        e = nullptr;
+      }
+  }
+  s->setup_s = now_s() - t0;
+  *out = s.release();
+  return CPTR_OK;
+}
+
+cptr_status cptr_destroy(cptr_solver s) {
+  if (!s) return CPTR_E_INVALID;
+  for (void* p : s->allocs) (void)hipFree(p);
+  if (s->hhost) (void)hipHostFree(s->hhost);
+  for (auto& e : s->ev_pool)
+    if (e) (void)hipEventDestroy(e);
+  delete s;
+  return CPTR_OK;
+}
+
+cptr_status cptr_apply(cptr_solver s, const double* r, double* z, void* stream) {
+  if (!s) return CPTR_E_INVALID;
+  if (!s->device) return (cptr_status)fail(s, CPTR_E_STATE, "handle was set up host-only");
+  if (!r || !z || r == z) return (cptr_status)fail(s, CPTR_E_INVALID, "r and z must be distinct non-NULL device pointers");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  enqueue_apply(s, r, z, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return (cptr_status)hip_fail(s, e, "kernel launch in cptr_apply");
+  return CPTR_OK;
+}
+
+cptr_status cptr_spmv(cptr_solver s, const double* x, double* y, void* stream) {
+  if (!s) return CPTR_E_INVALID;
+  if (!s->device) return (cptr_status)fail(s, CPTR_E_STATE, "handle was set up host-only");
+  if (!x || !y || x == y) return (cptr_status)fail(s, CPTR_E_INVALID, "x and y must be distinct non-NULL device pointers");
+  launch_bsr3_spmv(s->A, x, nullptr, y, false, static_cast<hipStream_t>(stream));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return (cptr_status)hip_fail(s, e, "kernel launch in cptr_spmv");
+  return CPTR_OK;
+}
+
+cptr_status cptr_gmres_solve(cptr_solver s, const double* b, double* x, const cptr_solve_opts* o_in,
+                             cptr_solve_info* info, void* stream) {
+  if (!s) return CPTR_E_INVALID;
+  if (!s->device) return (cptr_status)fail(s, CPTR_E_STATE, "handle was set up host-only");
+  if (!b || !x || b == x) return (cptr_status)fail(s, CPTR_E_INVALID, "b and x must be distinct non-NULL device pointers");
+  cptr_solve_opts o;
+  cptr_solve_opts_default(&o);
+  if (o_in) o = *o_in;
+  if (o.restart < 1 || o.restart > kMaxRestart)
+    return (cptr_status)fail(s, CPTR_E_INVALID, "restart must be in [1, 64]");
+  if (o.max_iter < 0 || !(o.rtol >= 0.0))
+    return (cptr_status)fail(s, CPTR_E_INVALID, "max_iter must be >= 0 and rtol >= 0");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const double t0 = now_s();
+  int rc = ensure_solve_space(s, o.restart, o.flexible != 0);
+  if (rc) return (cptr_status)rc;
+  s->profiling = o.profile != 0 && !s->ev_pool.empty() && s->ev_pool[0];
+  s->ev_used = 0;
+  s->ev_pending.clear();
+  const int64_t N = s->N;
+  const int m = o.restart;
+  const int64_t ld = s->ldv;
+  double* V = s->V;
+  double* r = s->wr;
+  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), yv(m);
+  auto Hij = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
+  hipEvent_t ev;
+
+  double bnorm = 0.0;
+  if ((rc = device_norm(s, b, bnorm, st))) return (cptr_status)rc;
+  if (o.x0_is_zero || bnorm == 0.0) {
+    HIP_TRY(s, hipMemsetAsync(x, 0, sizeof(double) * N, st));
+    HIP_TRY(s, hipMemcpyAsync(r, b, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+  } else {
+    ph_begin(s, st, ev);
+    launch_bsr3_spmv(s->A, x, b, r, true, st);
+    ph_end(s, st, PH_SPMV, ev);
+  }
+  double beta = 0.0;
+  if ((rc = device_norm(s, r, beta, st))) return (cptr_status)rc;
+  ph_harvest(s);
+  const double bref = bnorm == 0.0 ? 1.0 : bnorm;
+  const double target = o.rtol * bref;
+  int it = 0, restarts = 0, converged = 0;
+  double est = beta;
+  for (;;) {
+    if (beta <= target) {
+      converged = 1;
+      break;
+    }
+    if (it >= o.max_iter) break;
+    launch_scale_host(N, r, beta, V, st);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jend = -1;
+    for (int j = 0; j < m; ++j) {
+      double* vj = V + (size_t)j * ld;
+      double* zj = o.flexible ? s->Z + (size_t)j * ld : s->wu;
+      double* w = V + (size_t)(j + 1) * ld;
+      enqueue_apply(s, vj, zj, st);
+      ph_begin(s, st, ev);
+      launch_bsr3_spmv(s->A, zj, nullptr, w, false, st);
+      ph_end(s, st, PH_SPMV, ev);
+      // classical Gram-Schmidt, twice
+      ph_begin(s, st, ev);
+      const int nv = j + 1;
+      launch_mdot(N, nv, V, ld, w, s->part, st);
+      launch_reduce(nv, s->part, s->hdev, 0, st);
+      launch_maxpy_dot(N, nv, V, ld, s->hdev, w, s->part, st);
+      launch_reduce(nv, s->part, s->hdev + 64, 0, st);
+      launch_maxpy_norm(N, nv, V, ld, s->hdev + 64, w, s->part, st);
+      launch_reduce(1, s->part, s->hdev + 128, 0, st);
+      launch_scale(N, w, s->hdev + 128, w, st);
+      ph_end(s, st, PH_ARNOLDI, ev);
+      HIP_TRY(s, hipMemcpyAsync(s->hhost, s->hdev, 136 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_TRY(s, hipStreamSynchronize(st));
+      {
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return (cptr_status)hip_fail(s, e, "kernel launch in cptr_gmres_solve");
+      }
+      ph_harvest(s);
+      for (int i = 0; i <= j; ++i) Hij(i, j) = s->hhost[i] + s->hhost[64 + i];
+      const double hn = std::sqrt(std::max(0.0, s->hhost[128]));
+      Hij(j + 1, j) = hn;
+      for (int i = 0; i < j; ++i) {
+        const double a = Hij(i, j), c = Hij(i + 1, j);
+        Hij(i, j) = cs[i] * a + sn[i] * c;
+        Hij(i + 1, j) = -sn[i] * a + cs[i] * c;
+      }
+      const double a = Hij(j, j), c = Hij(j + 1, j);
+      const double rho = std::hypot(a, c);
+      if (rho == 0.0) {
+        cs[j] = 1.0;
+        sn[j] = 0.0;
+      } else {
+        cs[j] = a / rho;
+        sn[j] = c / rho;
+      }
+      Hij(j, j) = rho;
+      Hij(j + 1, j) = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++it;
+      est = std::fabs(g[j + 1]);
+      jend = j;
+      if (hn == 0.0) break;
+      if (est <= target || it >= o.max_iter) break;
+    }
+    const int k = jend + 1;
+    for (int i = k - 1; i >= 0; --i) {
+      double sum = g[i];
+      for (int q = i + 1; q < k; ++q) sum -= Hij(i, q) * yv[q];
+      yv[i] = Hij(i, i) != 0.0 ? sum / Hij(i, i) : 0.0;
+    }
+    ph_begin(s, st, ev);
+    if (o.flexible) {
+      launch_update_host_coef(N, k, s->Z, ld, yv.data(), x, st);
+      ph_end(s, st, PH_UPDATE, ev);
+    } else {
+      HIP_TRY(s, hipMemsetAsync(s->wt, 0, sizeof(double) * N, st));
+      launch_update_host_coef(N, k, V, ld, yv.data(), s->wt, st);
+      ph_end(s, st, PH_UPDATE, ev);
+      enqueue_apply(s, s->wt, s->wu, st);
+      ph_begin(s, st, ev);
+      std::vector<double> one(1, 1.0);
+      launch_update_host_coef(N, 1, s->wu, ld, one.data(), x, st);
+      ph_end(s, st, PH_UPDATE, ev);
+    }
+    ph_begin(s, st, ev);
+    launch_bsr3_spmv(s->A, x, b, r, true, st);
+    ph_end(s, st, PH_SPMV, ev);
+    if ((rc = device_norm(s, r, beta, st))) return (cptr_status)rc;
+    ph_harvest(s);
+    if (beta > target && it < o.max_iter) ++restarts;
+  }
+  s->profiling = false;
+  if (info) {
+    info->iterations = it;
+    info->restarts = restarts;
+    info->converged = converged;
+    info->rel_res_est = est / bref;
+    info->rel_res_true = beta / bref;
+    info->setup_s = s->setup_s;
+    info->solve_s = now_s() - t0;
+  }
+  return converged ? CPTR_OK : CPTR_NOT_CONVERGED;
+}
+
+cptr_status cptr_hierarchy_info(cptr_solver s, int32_t* n_levels, int64_t* rows, int64_t* nnz) {
+  if (!s || !n_levels) return CPTR_E_INVALID;
+  *n_levels = (int32_t)s->host.lev.size();
+  for (size_t l = 0; l < s->host.lev.size(); ++l) {
+    if (rows) rows[l] = s->host.lev[l].A.n;
+    if (nnz) nnz[l] = s->host.lev[l].A.nnz();
+  }
+  return CPTR_OK;
+}
+
+cptr_status cptr_export(cptr_solver s, int32_t what, int32_t level, void* buf, int64_t bytes) {
+  if (!s || !buf) return CPTR_E_INVALID;
+  const HostSetup& h = s->host;
+  const int L = (int)h.lev.size();
+  auto put = [&](const void* src, int64_t nbytes) -> cptr_status {
+    if (nbytes > bytes) return (cptr_status)fail(s, CPTR_E_INVALID, "export buffer too small");
+    if (nbytes) std::memcpy(buf, src, (size_t)nbytes);
+    return CPTR_OK;
+  };
+  const bool lvl_ok = level >= 0 && level < L;
+  const bool has_p = level >= 0 && level + 1 < L;
+  switch (what) {
+    case CPTR_EXPORT_CF:
+      if (!has_p) break;
+      return put(h.lev[level].cf.data(), (int64_t)h.lev[level].cf.size() * 4);
+    case CPTR_EXPORT_A_ROWPTR:
+      if (!lvl_ok) break;
+      return put(h.lev[level].A.rp.data(), (int64_t)h.lev[level].A.rp.size() * 8);
+    case CPTR_EXPORT_A_COLS:
+      if (!lvl_ok) break;
+      return put(h.lev[level].A.ci.data(), (int64_t)h.lev[level].A.ci.size() * 4);
+    case CPTR_EXPORT_A_VALS:
+      if (!lvl_ok) break;
+      return put(h.lev[level].A.v.data(), (int64_t)h.lev[level].A.v.size() * 8);
+    case CPTR_EXPORT_P_ROWPTR:
+      if (!has_p) break;
+      return put(h.lev[level].P.rp.data(), (int64_t)h.lev[level].P.rp.size() * 8);
+    case CPTR_EXPORT_P_COLS:
+      if (!has_p) break;
+      return put(h.lev[level].P.ci.data(), (int64_t)h.lev[level].P.ci.size() * 4);
+    case CPTR_EXPORT_P_VALS:
+      if (!has_p) break;
+      return put(h.lev[level].P.v.data(), (int64_t)h.lev[level].P.v.size() * 8);
+    case CPTR_EXPORT_W:
+      return put(h.W.data(), (int64_t)h.W.size() * 8);
+    case CPTR_EXPORT_DINV:
+      if (!has_p) break;
+      return put(h.lev[level].dinv.data(), (int64_t)h.lev[level].dinv.size() * 8);
+    case CPTR_EXPORT_ILU_VALS:
+      return put(h.ilu.data(), (int64_t)h.ilu.size() * 8);
+    case CPTR_EXPORT_ILU_NLEVELS: {
+      int32_t nl[2] = {h.n_fwd_levels, h.n_bwd_levels};
+      return put(nl, 8);
+    }
+    default:
+      return (cptr_status)fail(s, CPTR_E_INVALID, "unknown export item");
+  }
+  return (cptr_status)fail(s, CPTR_E_INVALID, "level out of range for this export item");
+}
+
+cptr_status cptr_phase_times(cptr_solver s, double* ms, int64_t* count, int32_t n, int32_t reset) {
+  if (!s || n < 0) return CPTR_E_INVALID;
+  for (int k = 0; k < n && k < kPhases; ++k) {
+    if (ms) ms[k] = s->phase_ms[k];
+    if (count) count[k] = s->phase_cnt[k];
+  }
+  if (reset)
+    for (int k = 0; k < kPhases; ++k) {
+      s->phase_ms[k] = 0.0;
+      s->phase_cnt[k] = 0;
+    }
+  return CPTR_OK;
+}
+
+}  // extern "C"

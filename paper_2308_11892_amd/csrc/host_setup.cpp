@@ -1,0 +1,712 @@
+// host_setup.cpp -- host construction of the CPTR preconditioner.
+//
+// Paper sections: the two-stage form and the elliptic/hyperbolic split
+// (Sec. 3, Eq. 3), the AMG parameters of the first stage and ILU(0) as the
+// second stage (Sec. 3.1), CPTR's (p, T) elliptic block solved by system AMG
+// (Sec. 3.2), the quasi-IMPES decomposition that produces that block
+// (Sec. 5.2).  Where the paper only names a method, the reading used is the
+// one stated at each function below.
+//
+// Compiled with FP contraction off so that the reduced elliptic matrix and the
+// strength tests on it are bit-reproducible.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <thread>
+
+#include "cptr.h"
+#include "host_setup.hpp"
+
+namespace cptr {
+
+void parallel_for(int threads, int64_t n, const std::function<void(int64_t, int64_t, int)>& body) {
+  if (threads <= 1 || n < 4096) {
+    body(0, n, 0);
+    return;
+  }
+  int t = (int)std::min<int64_t>(threads, n / 1024 + 1);
+  std::vector<std::thread> pool;
+  pool.reserve(t);
+  for (int k = 0; k < t; ++k) {
+    int64_t lo = n * k / t, hi = n * (k + 1) / t;
+    pool.emplace_back([&body, lo, hi, k] { body(lo, hi, k); });
+  }
+  for (auto& th : pool) th.join();
+}
+
+int validate_bsr(int32_t nb, int64_t nnzb, const int32_t* rp, const int32_t* ci,
+                 const double* v, std::string& err) {
+  if (nb <= 0) return err = "A.n_block_rows must be positive", CPTR_E_INVALID;
+  if (!rp || !ci || !v) return err = "A has a null array", CPTR_E_INVALID;
+  if (rp[0] != 0) return err = "A.row_ptr[0] must be 0", CPTR_E_INVALID;
+  if ((int64_t)rp[nb] != nnzb)
+    return err = "A.row_ptr[n] != A.nnz_blocks", CPTR_E_INVALID;
+  for (int32_t i = 0; i < nb; ++i) {
+    if (rp[i + 1] < rp[i])
+      return err = "A.row_ptr decreases at row " + std::to_string(i), CPTR_E_INVALID;
+    bool diag = false;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+      if (ci[k] < 0 || ci[k] >= nb)
+        return err = "A.col_idx out of range in row " + std::to_string(i), CPTR_E_INVALID;
+      if (k > rp[i] && ci[k] <= ci[k - 1])
+        return err = "A.col_idx unsorted or duplicated in row " + std::to_string(i),
+               CPTR_E_INVALID;
+      diag |= ci[k] == i;
+    }
+    if (!diag) return err = "A has no diagonal block in row " + std::to_string(i), CPTR_E_INVALID;
+  }
+  for (int64_t k = 0; k < nnzb * kBS * kBS; ++k)
+    if (!std::isfinite(v[k]))
+      return err = "A.values has a non-finite entry in block " + std::to_string(k / 9),
+             CPTR_E_INVALID;
+  return CPTR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// strength of connection, restricted to one unknown type ("unknown" system AMG)
+// j is a strong dependency of i when j has i's type, j != i and
+//   -sign(a_ii) a_ij >= theta * max over same-type k != i of (-sign(a_ii) a_ik),
+// none when that maximum is not positive, and none when the same-type row sum
+// exceeds max_row_sum * |a_ii| in magnitude (diagonally dominant row).
+Csr strength_graph(const Csr& A, const std::vector<int32_t>& func, double theta, double mrs,
+                   int threads) {
+  Csr S;
+  S.n = S.m = A.n;
+  std::vector<int64_t> cnt(A.n + 1, 0);
+  auto row_pass = [&](int32_t i, int32_t* out) -> int64_t {
+    const int64_t b = A.rp[i], e = A.rp[i + 1];
+    double aii = 0.0;
+    for (int64_t k = b; k < e; ++k)
+      if (A.ci[k] == i) aii = A.v[k];
+    const double s = aii < 0.0 ? -1.0 : 1.0;
+    double sum = 0.0, best = 0.0;
+    bool any = false;
+    const int32_t fi = func[i];
+    for (int64_t k = b; k < e; ++k) {
+      const int32_t j = A.ci[k];
+      if (func[j] != fi) continue;
+      sum += A.v[k];
+      if (j != i) {
+        const double t = -s * A.v[k];
+        best = any ? std::max(best, t) : t;
+        any = true;
+      }
+    }
+    if (!any || !(best > 0.0)) return 0;
+    if (mrs < 1.0 && std::fabs(sum) > mrs * std::fabs(aii)) return 0;
+    const double cut = theta * best;
+    int64_t c = 0;
+    for (int64_t k = b; k < e; ++k) {
+      const int32_t j = A.ci[k];
+      if (j != i && func[j] == fi && -s * A.v[k] >= cut) {
+        if (out) out[c] = j;
+        ++c;
+      }
+    }
+    return c;
+  };
+  parallel_for(threads, A.n, [&](int64_t lo, int64_t hi, int) {
+    for (int64_t i = lo; i < hi; ++i) cnt[i + 1] = row_pass((int32_t)i, nullptr);
+  });
+  S.rp.assign(A.n + 1, 0);
+  for (int32_t i = 0; i < A.n; ++i) S.rp[i + 1] = S.rp[i] + cnt[i + 1];
+  S.ci.resize(S.rp[A.n]);
+  parallel_for(threads, A.n, [&](int64_t lo, int64_t hi, int) {
+    for (int64_t i = lo; i < hi; ++i) row_pass((int32_t)i, S.ci.data() + S.rp[i]);
+  });
+  S.v.assign(S.ci.size(), 1.0);
+  return S;
+}
+
+static Csr transpose(const Csr& a, int threads) {
+  (void)threads;
+  Csr t;
+  t.n = a.m;
+  t.m = a.n;
+  t.rp.assign(t.n + 1, 0);
+  for (int64_t k = 0; k < a.nnz(); ++k) ++t.rp[a.ci[k] + 1];
+  for (int32_t j = 0; j < t.n; ++j) t.rp[j + 1] += t.rp[j];
+  t.ci.resize(a.nnz());
+  t.v.resize(a.nnz());
+  std::vector<int64_t> fill(t.rp.begin(), t.rp.end() - 1);
+  for (int32_t i = 0; i < a.n; ++i)
+    for (int64_t k = a.rp[i]; k < a.rp[i + 1]; ++k) {
+      const int64_t p = fill[a.ci[k]]++;
+      t.ci[p] = i;
+      t.v[p] = a.v[k];
+    }
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// HMIS coarsening on one domain = the Ruge-Stueben first pass.
+// Measure = number of points that depend strongly on a point.  Points without
+// any strong link become F.  The unassigned point of largest measure (>= 1,
+// smallest index on ties) becomes C; unassigned points depending on it become
+// F and each unassigned strong dependency of such a new F point gains 1; each
+// unassigned strong dependency of the new C point loses 1.  Leftovers are F.
+// Selection uses a max segment tree keyed on (measure, -index).
+namespace {
+struct MaxTree {
+  int32_t size = 1;
+  std::vector<int64_t> key;    // measure, or -1 when not selectable
+  std::vector<int32_t> arg;    // index achieving the node's maximum
+  explicit MaxTree(int32_t n) {
+    while (size < n) size <<= 1;
+    key.assign(2 * size, -1);
+    arg.assign(2 * size, INT32_MAX);
+    for (int32_t i = 0; i < size; ++i) arg[size + i] = i;
+  }
+  bool better(int32_t a, int32_t b) const {  // node a beats node b
+    if (key[a] != key[b]) return key[a] > key[b];
+    return arg[a] < arg[b];
+  }
+  void pull(int32_t p) {
+    const int32_t l = 2 * p, r = l + 1, w = better(l, r) ? l : r;
+    key[p] = key[w];
+    arg[p] = arg[w];
+  }
+  void build() {
+    for (int32_t p = size - 1; p >= 1; --p) pull(p);
+  }
+  void set(int32_t i, int64_t k) {
+    int32_t p = size + i;
+    key[p] = k;
+    for (p >>= 1; p >= 1; p >>= 1) pull(p);
+  }
+};
+}  // namespace
+
+std::vector<int32_t> first_pass_split(const Csr& S) {
+  const int32_t n = S.n;
+  Csr St = transpose(S, 1);
+  std::vector<int32_t> cf(n, 0);
+  std::vector<int64_t> lam(n);
+  MaxTree tree(n);
+  for (int32_t i = 0; i < n; ++i) {
+    lam[i] = St.rp[i + 1] - St.rp[i];
+    if (lam[i] == 0 && S.rp[i + 1] == S.rp[i]) cf[i] = -1;
+    tree.key[tree.size + i] = (cf[i] == 0 && lam[i] >= 1) ? lam[i] : -1;
+  }
+  tree.build();
+  auto refresh = [&](int32_t m) { tree.set(m, (cf[m] == 0 && lam[m] >= 1) ? lam[m] : -1); };
+  while (tree.key[1] >= 1) {
+    const int32_t c = tree.arg[1];
+    cf[c] = 1;
+    refresh(c);
+    for (int64_t k = St.rp[c]; k < St.rp[c + 1]; ++k) {
+      const int32_t f = St.ci[k];
+      if (cf[f] != 0) continue;
+      cf[f] = -1;
+      refresh(f);
+      for (int64_t q = S.rp[f]; q < S.rp[f + 1]; ++q) {
+        const int32_t m = S.ci[q];
+        if (cf[m] == 0) {
+          ++lam[m];
+          refresh(m);
+        }
+      }
+    }
+    for (int64_t k = S.rp[c]; k < S.rp[c + 1]; ++k) {
+      const int32_t m = S.ci[k];
+      if (cf[m] == 0) {
+        --lam[m];
+        refresh(m);
+      }
+    }
+  }
+  for (auto& x : cf)
+    if (x == 0) x = -1;
+  return cf;
+}
+
+// ---------------------------------------------------------------------------
+// Extended+i interpolation (De Sterck, Falgout, Nolting, Yang, 2008), within
+// one unknown type.  For an F point i: the interpolatory set is its strong C
+// points plus the strong C points of its strong F points.  Each off-diagonal
+// a_im of i's type goes (a) to w_im if m is in the set, (b) for a strong F
+// point m, through row m: a_ml (l in the set or l = i, a_ml of sign opposite
+// to a_mm) shares a_im in proportion to a_ml, the share of l = i going to the
+// diagonal; if those a_ml sum to zero a_im goes to the diagonal, (c) otherwise
+// to the diagonal.  w = -(collected) / (collected diagonal).  Rows keep the
+// pmax largest |w| (smaller column on ties), rescaled to the full row sum.
+namespace {
+struct Entry {
+  int32_t col;
+  double w;
+};
+}  // namespace
+
+Csr extended_i_interp(const Csr& A, const Csr& S, const std::vector<int32_t>& cf,
+                      const std::vector<int32_t>& func, int pmax, int threads) {
+  const int32_t n = A.n;
+  std::vector<int32_t> cidx(n, -1);
+  int32_t nc = 0;
+  for (int32_t i = 0; i < n; ++i)
+    if (cf[i] == 1) cidx[i] = nc++;
+  int nthreads = std::max(1, threads);
+  struct Part {
+    std::vector<int32_t> ci;
+    std::vector<double> v;
+  };
+  std::vector<Part> parts(nthreads);
+  std::vector<int64_t> rowlen(n + 1, 0);
+  std::vector<int64_t> chunk_lo(nthreads + 1, 0);
+  auto a_diag = [&](int32_t r) {
+    for (int64_t k = A.rp[r]; k < A.rp[r + 1]; ++k)
+      if (A.ci[k] == r) return A.v[k];
+    return 0.0;
+  };
+  parallel_for(nthreads, n, [&](int64_t lo, int64_t hi, int t) {
+    Part& out = parts[t];
+    std::vector<int32_t> set;     // interpolatory C points of the current row
+    std::vector<double> acc;
+    std::vector<Entry> row;
+    for (int64_t ii = lo; ii < hi; ++ii) {
+      const int32_t i = (int32_t)ii;
+      row.clear();
+      if (cf[i] == 1) {
+        row.push_back({cidx[i], 1.0});
+      } else {
+        set.clear();
+        auto in_set = [&](int32_t c) -> int {
+          for (size_t q = 0; q < set.size(); ++q)
+            if (set[q] == c) return (int)q;
+          return -1;
+        };
+        auto strong = [&](int32_t m) {
+          for (int64_t k = S.rp[i]; k < S.rp[i + 1]; ++k)
+            if (S.ci[k] == m) return true;
+          return false;
+        };
+        for (int64_t k = S.rp[i]; k < S.rp[i + 1]; ++k) {
+          const int32_t j = S.ci[k];
+          if (cf[j] == 1) {
+            if (in_set(j) < 0) set.push_back(j);
+          } else {
+            for (int64_t q = S.rp[j]; q < S.rp[j + 1]; ++q) {
+              const int32_t l = S.ci[q];
+              if (cf[l] == 1 && in_set(l) < 0) set.push_back(l);
+            }
+          }
+        }
+        if (!set.empty()) {
+          acc.assign(set.size(), 0.0);
+          double dg = a_diag(i);
+          for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+            const int32_t m = A.ci[k];
+            if (m == i || func[m] != func[i]) continue;
+            const double aim = A.v[k];
+            const int pos = in_set(m);
+            if (pos >= 0) {
+              acc[pos] += aim;
+              continue;
+            }
+            if (cf[m] != 1 && strong(m)) {
+              const double sm = a_diag(m) < 0.0 ? -1.0 : 1.0;
+              double den = 0.0;
+              for (int64_t q = A.rp[m]; q < A.rp[m + 1]; ++q) {
+                const int32_t l = A.ci[q];
+                const double aml = A.v[q];
+                if (sm * aml < 0.0 && (l == i || in_set(l) >= 0)) den += aml;
+              }
+              if (den == 0.0) {
+                dg += aim;
+                continue;
+              }
+              for (int64_t q = A.rp[m]; q < A.rp[m + 1]; ++q) {
+                const int32_t l = A.ci[q];
+                const double aml = A.v[q];
+                if (!(sm * aml < 0.0)) continue;
+                const double share = aim * aml / den;
+                if (l == i) {
+                  dg += share;
+                } else {
+                  const int p = in_set(l);
+                  if (p >= 0) acc[p] += share;
+                }
+              }
+              continue;
+            }
+            dg += aim;
+          }
+          if (dg != 0.0)
+            for (size_t q = 0; q < set.size(); ++q) row.push_back({cidx[set[q]], -acc[q] / dg});
+        }
+      }
+      if (pmax > 0 && (int)row.size() > pmax) {
+        double total = 0.0, kept = 0.0;
+        for (const auto& e : row) total += e.w;
+        std::partial_sort(row.begin(), row.begin() + pmax, row.end(),
+                          [](const Entry& a, const Entry& b) {
+                            const double fa = std::fabs(a.w), fb = std::fabs(b.w);
+                            return fa != fb ? fa > fb : a.col < b.col;
+                          });
+        row.resize(pmax);
+        for (const auto& e : row) kept += e.w;
+        if (kept != 0.0) {
+          const double scale = total / kept;
+          for (auto& e : row) e.w *= scale;
+        }
+      }
+      std::sort(row.begin(), row.end(), [](const Entry& a, const Entry& b) { return a.col < b.col; });
+      rowlen[i + 1] = (int64_t)row.size();
+      for (const auto& e : row) {
+        out.ci.push_back(e.col);
+        out.v.push_back(e.w);
+      }
+    }
+    chunk_lo[t + 1] = hi;  // rows of this part end at hi
+  });
+  Csr P;
+  P.n = n;
+  P.m = nc;
+  P.rp.assign(n + 1, 0);
+  for (int32_t i = 0; i < n; ++i) P.rp[i + 1] = P.rp[i] + rowlen[i + 1];
+  P.ci.reserve(P.rp[n]);
+  P.v.reserve(P.rp[n]);
+  for (auto& part : parts) {
+    P.ci.insert(P.ci.end(), part.ci.begin(), part.ci.end());
+    P.v.insert(P.v.end(), part.v.begin(), part.v.end());
+  }
+  return P;
+}
+
+// ---------------------------------------------------------------------------
+// Galerkin product R A P, row by row of R, accumulating (r_Ii a_ik) p_kJ in a
+// small open-addressing table per row.
+static Csr galerkin(const Csr& R, const Csr& A, const Csr& P, int threads) {
+  const int32_t nc = R.n;
+  int nthreads = std::max(1, threads);
+  struct Part {
+    std::vector<int32_t> ci;
+    std::vector<double> v;
+  };
+  std::vector<Part> parts(nthreads);
+  std::vector<int64_t> len(nc + 1, 0);
+  parallel_for(nthreads, nc, [&](int64_t lo, int64_t hi, int t) {
+    std::vector<int32_t> keys(64, -1);
+    std::vector<double> vals(64, 0.0);
+    std::vector<int32_t> used;
+    auto insert = [&](int32_t col, double x) {
+      uint32_t mask = (uint32_t)keys.size() - 1;
+      uint32_t h = ((uint32_t)col * 2654435761u) & mask;
+      while (keys[h] != -1 && keys[h] != col) h = (h + 1) & mask;
+      if (keys[h] == -1) {
+        keys[h] = col;
+        vals[h] = 0.0;
+        used.push_back((int32_t)h);
+      }
+      vals[h] += x;
+    };
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t I = lo; I < hi; ++I) {
+      // size the table for this row's upper bound on distinct columns
+      int64_t bound = 0;
+      for (int64_t q = R.rp[I]; q < R.rp[I + 1]; ++q) {
+        const int32_t i = R.ci[q];
+        for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) bound += P.rp[A.ci[k] + 1] - P.rp[A.ci[k]];
+      }
+      size_t want = 64;
+      while ((int64_t)want < 2 * bound) want <<= 1;
+      if (want > keys.size()) {
+        keys.assign(want, -1);
+        vals.assign(want, 0.0);
+      }
+      used.clear();
+      for (int64_t q = R.rp[I]; q < R.rp[I + 1]; ++q) {
+        const int32_t i = R.ci[q];
+        const double rv = R.v[q];
+        for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+          const int32_t kk = A.ci[k];
+          const double ra = rv * A.v[k];
+          for (int64_t p = P.rp[kk]; p < P.rp[kk + 1]; ++p) insert(P.ci[p], ra * P.v[p]);
+        }
+      }
+      row.clear();
+      for (int32_t h : used) {
+        row.emplace_back(keys[h], vals[h]);
+        keys[h] = -1;
+      }
+      std::sort(row.begin(), row.end());
+      len[I + 1] = (int64_t)row.size();
+      for (auto& e : row) {
+        parts[t].ci.push_back(e.first);
+        parts[t].v.push_back(e.second);
+      }
+    }
+  });
+  Csr C;
+  C.n = C.m = nc;
+  C.rp.assign(nc + 1, 0);
+  for (int32_t I = 0; I < nc; ++I) C.rp[I + 1] = C.rp[I] + len[I + 1];
+  C.ci.reserve(C.rp[nc]);
+  C.v.reserve(C.rp[nc]);
+  for (auto& part : parts) {
+    C.ci.insert(C.ci.end(), part.ci.begin(), part.ci.end());
+    C.v.insert(C.v.end(), part.v.begin(), part.v.end());
+  }
+  return C;
+}
+
+// l1-Jacobi (point blocks): d_i = a_ii + sign(a_ii) sum_{j != i} |a_ij|.
+static int l1_inverse_diag(const Csr& A, std::vector<double>& dinv, std::string& err) {
+  dinv.resize(A.n);
+  for (int32_t i = 0; i < A.n; ++i) {
+    double d = 0.0, off = 0.0;
+    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      if (A.ci[k] == i) d = A.v[k];
+      else off += std::fabs(A.v[k]);
+    }
+    const double l1 = d < 0.0 ? d - off : d + off;
+    if (l1 == 0.0) return err = "zero smoother diagonal at AMG row " + std::to_string(i), CPTR_E_ZERO_PIVOT;
+    dinv[i] = 1.0 / l1;
+  }
+  return CPTR_OK;
+}
+
+static int dense_lu(int n, std::vector<double>& a, std::vector<int32_t>& piv, std::string& err) {
+  piv.resize(n);
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(a[(size_t)i * n + k]) > std::fabs(a[(size_t)p * n + k])) p = i;
+    piv[k] = p;
+    if (a[(size_t)p * n + k] == 0.0)
+      return err = "singular coarsest AMG matrix", CPTR_E_SINGULAR_COARSE;
+    if (p != k)
+      for (int j = 0; j < n; ++j) std::swap(a[(size_t)k * n + j], a[(size_t)p * n + j]);
+    const double inv = a[(size_t)k * n + k];
+    for (int i = k + 1; i < n; ++i) {
+      const double l = a[(size_t)i * n + k] / inv;
+      a[(size_t)i * n + k] = l;
+      for (int j = k + 1; j < n; ++j) a[(size_t)i * n + j] -= l * a[(size_t)k * n + j];
+    }
+  }
+  return CPTR_OK;
+}
+
+// 3x3 inverse by Gauss-Jordan with partial pivoting; false when singular.
+static bool inv3(const double* m, double* out) {
+  double a[3][6];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 6; ++c) a[r][c] = c < 3 ? m[r * 3 + c] : (c - 3 == r ? 1.0 : 0.0);
+  for (int k = 0; k < 3; ++k) {
+    int p = k;
+    for (int r = k + 1; r < 3; ++r)
+      if (std::fabs(a[r][k]) > std::fabs(a[p][k])) p = r;
+    if (a[p][k] == 0.0) return false;
+    if (p != k)
+      for (int c = 0; c < 6; ++c) std::swap(a[k][c], a[p][c]);
+    const double d = a[k][k];
+    for (int c = 0; c < 6; ++c) a[k][c] /= d;
+    for (int r = 0; r < 3; ++r)
+      if (r != k) {
+        const double f = a[r][k];
+        for (int c = 0; c < 6; ++c) a[r][c] -= f * a[k][c];
+      }
+  }
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) out[r * 3 + c] = a[r][c + 3];
+  return true;
+}
+
+static inline void mm3(const double* a, const double* b, double* c) {
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k) {
+      double s = 0.0;
+      for (int q = 0; q < 3; ++q) s += a[r * 3 + q] * b[q * 3 + k];
+      c[r * 3 + k] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const double* v,
+                     const int32_t* elliptic, int ne, const SetupParams& prm, HostSetup& h,
+                     std::string& err) {
+  const int threads = std::max(1, prm.threads);
+  h.nb = nb;
+  h.ne = ne;
+  h.nh = kBS - ne;
+  bool used[kBS] = {false, false, false};
+  for (int e = 0; e < ne; ++e) {
+    h.eidx[e] = elliptic[e];
+    used[elliptic[e]] = true;
+  }
+  for (int c = 0, t = 0; c < kBS; ++c)
+    if (!used[c]) h.hidx[t++] = c;
+  const int64_t nnzb = rp[nb];
+  h.rp.assign(rp, rp + nb + 1);
+  h.ci.assign(ci, ci + nnzb);
+  h.av.assign(v, v + nnzb * 9);
+  h.diag.resize(nb);
+  for (int32_t i = 0; i < nb; ++i)
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+      if (ci[k] == i) h.diag[i] = k;
+
+  // ---- quasi-IMPES weights W_i = A_ii[E,H] A_ii[H,H]^-1 (Sec. 5.2) ----
+  const int nh = h.nh;
+  h.W.assign((size_t)nb * ne * nh, 0.0);
+  if (prm.quasi_impes) {
+    int bad = -1;
+    for (int32_t i = 0; i < nb && bad < 0; ++i) {
+      const double* D = &h.av[(size_t)h.diag[i] * 9];
+      double* w = &h.W[(size_t)i * ne * nh];
+      if (nh == 1) {
+        const double dhh = D[h.hidx[0] * 3 + h.hidx[0]];
+        if (dhh == 0.0) { bad = i; break; }
+        for (int e = 0; e < ne; ++e) w[e] = D[h.eidx[e] * 3 + h.hidx[0]] / dhh;
+      } else {  // nh == 2: explicit 2x2 inverse
+        const int p = h.hidx[0], q = h.hidx[1];
+        const double a = D[p * 3 + p], b = D[p * 3 + q], c = D[q * 3 + p], d = D[q * 3 + q];
+        const double det = a * d - b * c;
+        if (det == 0.0) { bad = i; break; }
+        const double ia = d / det, ib = -b / det, ic = -c / det, id = a / det;
+        for (int e = 0; e < ne; ++e) {
+          const double u = D[h.eidx[e] * 3 + p], t = D[h.eidx[e] * 3 + q];
+          w[e * 2 + 0] = u * ia + t * ic;
+          w[e * 2 + 1] = u * ib + t * id;
+        }
+      }
+    }
+    if (bad >= 0)
+      return err = "singular hyperbolic diagonal block in row " + std::to_string(bad),
+             CPTR_E_ZERO_PIVOT;
+  }
+  // ---- reduced elliptic blocks Ahat_ij = A_ij[E,E] - W_i A_ij[H,E] ----
+  h.ahat.assign((size_t)nnzb * ne * ne, 0.0);
+  parallel_for(threads, nb, [&](int64_t lo, int64_t hi, int) {
+    for (int64_t i = lo; i < hi; ++i) {
+      const double* w = &h.W[(size_t)i * ne * nh];
+      for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+        const double* B = &h.av[(size_t)k * 9];
+        double* o = &h.ahat[(size_t)k * ne * ne];
+        for (int a = 0; a < ne; ++a)
+          for (int c = 0; c < ne; ++c) {
+            double s = B[h.eidx[a] * 3 + h.eidx[c]];
+            for (int t = 0; t < nh; ++t) s -= w[a * nh + t] * B[h.hidx[t] * 3 + h.eidx[c]];
+            o[a * ne + c] = s;
+          }
+      }
+    }
+  });
+
+  // ---- system AMG on Ahat, unknowns interleaved per cell (Sec. 3.1, 3.2) ----
+  h.lev.clear();
+  h.lev.emplace_back();
+  {
+    AmgLevel& L0 = h.lev[0];
+    Csr& A0 = L0.A;
+    A0.n = A0.m = nb * ne;
+    A0.rp.assign(A0.n + 1, 0);
+    for (int32_t i = 0; i < nb; ++i)
+      for (int a = 0; a < ne; ++a) A0.rp[(int64_t)i * ne + a + 1] = (int64_t)(rp[i + 1] - rp[i]) * ne;
+    for (int32_t r = 0; r < A0.n; ++r) A0.rp[r + 1] += A0.rp[r];
+    A0.ci.resize(A0.rp[A0.n]);
+    A0.v.resize(A0.rp[A0.n]);
+    parallel_for(threads, nb, [&](int64_t lo, int64_t hi, int) {
+      for (int64_t i = lo; i < hi; ++i)
+        for (int a = 0; a < ne; ++a) {
+          int64_t p = A0.rp[i * ne + a];
+          for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+            for (int c = 0; c < ne; ++c) {
+              A0.ci[p] = ci[k] * ne + c;
+              A0.v[p] = h.ahat[(size_t)k * ne * ne + a * ne + c];
+              ++p;
+            }
+        }
+    });
+    L0.func.resize(A0.n);
+    for (int32_t r = 0; r < A0.n; ++r) L0.func[r] = r % ne;
+  }
+  for (;;) {
+    const size_t l = h.lev.size() - 1;
+    const Csr& A = h.lev[l].A;
+    if (A.n <= prm.max_coarse || (int)l + 1 >= prm.max_levels) break;
+    Csr S = strength_graph(A, h.lev[l].func, prm.theta, prm.max_row_sum, threads);
+    std::vector<int32_t> cf = first_pass_split(S);
+    int32_t nc = 0;
+    for (auto x : cf) nc += x == 1;
+    if (nc == 0 || nc == A.n) break;
+    Csr P = extended_i_interp(A, S, cf, h.lev[l].func, prm.pmax, threads);
+    Csr R = transpose(P, threads);
+    Csr Ac = galerkin(R, A, P, threads);
+    std::vector<int32_t> fc;
+    fc.reserve(nc);
+    for (int32_t i = 0; i < A.n; ++i)
+      if (cf[i] == 1) fc.push_back(h.lev[l].func[i]);
+    h.lev[l].cf = std::move(cf);
+    h.lev[l].P = std::move(P);
+    h.lev[l].R = std::move(R);
+    AmgLevel next;
+    next.A = std::move(Ac);
+    next.func = std::move(fc);
+    h.lev.push_back(std::move(next));
+  }
+  for (size_t l = 0; l + 1 < h.lev.size(); ++l) {
+    int st = l1_inverse_diag(h.lev[l].A, h.lev[l].dinv, err);
+    if (st != CPTR_OK) return st;
+  }
+  {
+    const Csr& Ac = h.lev.back().A;
+    if (Ac.n > prm.max_dense_coarse)
+      return err = "AMG coarsening stalled at " + std::to_string(Ac.n) +
+                   " rows, above the dense coarse-solve limit",
+             CPTR_E_SINGULAR_COARSE;
+    h.coarse_lu.assign((size_t)Ac.n * Ac.n, 0.0);
+    for (int32_t i = 0; i < Ac.n; ++i)
+      for (int64_t k = Ac.rp[i]; k < Ac.rp[i + 1]; ++k) h.coarse_lu[(size_t)i * Ac.n + Ac.ci[k]] += Ac.v[k];
+    int st = dense_lu(Ac.n, h.coarse_lu, h.coarse_piv, err);
+    if (st != CPTR_OK) return st;
+  }
+
+  // ---- block ILU(0) on A's pattern, matrix ordering (Sec. 3.1) ----
+  h.ilu = h.av;
+  h.uinv.assign((size_t)nb * 9, 0.0);
+  for (int32_t i = 0; i < nb; ++i) {
+    const int32_t d = h.diag[i];
+    for (int32_t q = rp[i]; q < d; ++q) {
+      const int32_t c = ci[q];
+      double Lq[9];
+      mm3(&h.ilu[(size_t)q * 9], &h.uinv[(size_t)c * 9], Lq);
+      std::memcpy(&h.ilu[(size_t)q * 9], Lq, sizeof Lq);
+      // merge the U part of row c (columns > c) into row i's later blocks
+      int32_t t = q + 1;
+      for (int32_t u = h.diag[c] + 1; u < rp[c + 1]; ++u) {
+        const int32_t col = ci[u];
+        while (t < rp[i + 1] && ci[t] < col) ++t;
+        if (t == rp[i + 1]) break;
+        if (ci[t] != col) continue;
+        double prod[9];
+        mm3(Lq, &h.ilu[(size_t)u * 9], prod);
+        double* dst = &h.ilu[(size_t)t * 9];
+        for (int e = 0; e < 9; ++e) dst[e] -= prod[e];
+      }
+    }
+    if (!inv3(&h.ilu[(size_t)d * 9], &h.uinv[(size_t)i * 9]))
+      return err = "zero ILU(0) pivot (singular diagonal block) in block row " + std::to_string(i),
+             CPTR_E_ZERO_PIVOT;
+  }
+  // ---- dependency levels of the two triangular sweeps ----
+  h.fwd_level.assign(nb, 0);
+  h.bwd_level.assign(nb, 0);
+  int32_t nf = 0, nbk = 0;
+  for (int32_t i = 0; i < nb; ++i) {
+    int32_t lv = 0;
+    for (int32_t k = rp[i]; k < h.diag[i]; ++k) lv = std::max(lv, h.fwd_level[ci[k]] + 1);
+    h.fwd_level[i] = lv;
+    nf = std::max(nf, lv + 1);
+  }
+  for (int32_t i = nb - 1; i >= 0; --i) {
+    int32_t lv = 0;
+    for (int32_t k = h.diag[i] + 1; k < rp[i + 1]; ++k) lv = std::max(lv, h.bwd_level[ci[k]] + 1);
+    h.bwd_level[i] = lv;
+    nbk = std::max(nbk, lv + 1);
+  }
+  h.n_fwd_levels = nf;
+  h.n_bwd_levels = nbk;
+  return CPTR_OK;
+}
+
+}  // namespace cptr

@@ -1,0 +1,80 @@
+// host_setup.hpp -- host-side construction of the CPTR preconditioner.
+//
+// Everything here runs once per matrix inside cptr_setup, before any device
+// work: validation of the block-sparse input, the quasi-IMPES reduction of the
+// elliptic block (Sec. 5.2 of the paper), the system-AMG hierarchy on it
+// (Sec. 3.1 and 3.2) and the block ILU(0) factors of the whole matrix
+// (Sec. 3.1), plus the dependency levels the triangular sweeps run in.
+// The device layouts are produced from these host structures by the API layer.
+#pragma once
+#include <cstdint>
+#include <functional>
+#include <string>
+#include <vector>
+
+namespace cptr {
+
+constexpr int kBS = 3;   // unknowns per cell supported by the kernels
+
+struct Csr {
+  int32_t n = 0, m = 0;
+  std::vector<int64_t> rp;
+  std::vector<int32_t> ci;
+  std::vector<double> v;
+  int64_t nnz() const { return rp.empty() ? 0 : rp[n]; }
+};
+
+struct AmgLevel {
+  Csr A;                       // scalar operator of this level
+  Csr P, R;                    // interpolation to this level from the next, R = P^T
+  std::vector<int32_t> cf;     // 1 = C, -1 = F (empty on the coarsest level)
+  std::vector<int32_t> func;   // unknown type (0 = first elliptic unknown, ...)
+  std::vector<double> dinv;    // inverse l1-Jacobi diagonal (empty on the coarsest)
+};
+
+struct SetupParams {
+  double theta = 0.25;
+  double max_row_sum = 0.9;
+  int max_levels = 25;
+  int max_coarse = 9;
+  int pmax = 4;
+  bool quasi_impes = true;
+  int threads = 1;
+  int max_dense_coarse = 4096;  // largest coarsest level solved by dense LU
+};
+
+struct HostSetup {
+  int32_t nb = 0;              // block rows (cells)
+  int ne = 0, nh = 0;          // elliptic / hyperbolic unknowns per cell
+  int eidx[kBS] = {0}, hidx[kBS] = {0};
+  std::vector<int32_t> rp, ci; // validated copy of A's pattern
+  std::vector<double> av;      // A values [nnzb][3][3]
+  std::vector<int32_t> diag;   // position of the diagonal block of each row
+  std::vector<double> W;       // [nb][ne][nh]
+  std::vector<double> ahat;    // [nnzb][ne][ne] reduced elliptic blocks on A's pattern
+  std::vector<AmgLevel> lev;   // lev.back() is the coarsest level
+  std::vector<double> coarse_lu;  // dense LU of the coarsest matrix, row-major
+  std::vector<int32_t> coarse_piv;
+  std::vector<double> ilu;     // [nnzb][3][3]: L blocks left of the diagonal, U on/right
+  std::vector<double> uinv;    // [nb][3][3] inverse of each U_ii
+  std::vector<int32_t> fwd_level, bwd_level;  // dependency level of each row
+  int32_t n_fwd_levels = 0, n_bwd_levels = 0;
+};
+
+// Returns a cptr_status value; on failure `err` holds the message.
+int validate_bsr(int32_t nb, int64_t nnzb, const int32_t* rp, const int32_t* ci,
+                 const double* v, std::string& err);
+int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const double* v,
+                     const int32_t* elliptic, int ne, const SetupParams& prm, HostSetup& out,
+                     std::string& err);
+
+// Building blocks, exported for the library's own host tests.
+Csr strength_graph(const Csr& A, const std::vector<int32_t>& func, double theta, double mrs,
+                   int threads);
+std::vector<int32_t> first_pass_split(const Csr& S);
+Csr extended_i_interp(const Csr& A, const Csr& S, const std::vector<int32_t>& cf,
+                      const std::vector<int32_t>& func, int pmax, int threads);
+
+void parallel_for(int threads, int64_t n, const std::function<void(int64_t, int64_t, int)>& body);
+
+}  // namespace cptr

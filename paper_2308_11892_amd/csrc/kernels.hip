@@ -1,0 +1,613 @@
+// kernels.hip -- HIP kernels of the CPTR hot path for gfx950 (MI355X), FP64.
+//
+// Paper mapping (Cremon, Franc, Hamon, CPTR):
+//   bsr3 SpMV            A z in GMRES and in the residual of Eq. (3)
+//   l0 restrict          quasi-IMPES restriction to the (p, T) block (Sec. 5.2)
+//   l0 / csr V-cycle     one system-AMG V-cycle with one l1-Jacobi sweep before
+//                        and after the coarse correction (Sec. 3.1, 3.2)
+//   stage2 resid         r - A M1^-1 r with M1^-1 injecting into (p, T) (Eq. 3)
+//   ilu fwd / bwd        ILU(0) triangular sweeps, second stage (Sec. 3.1)
+//   mdot / maxpy         Arnoldi orthogonalisation of right-preconditioned GMRES
+//
+// Everything here is bandwidth-bound sparse or vector work: no MFMA.  Block
+// values are stored as lane-contiguous planes (see Sell in kernels.hpp) so a
+// wavefront reads each entry of 64 blocks as one contiguous 512-byte segment.
+// Reductions are two-stage with a fixed order, so results are bit-identical
+// from run to run.
+#include "kernels.hpp"
+
+namespace cptr {
+
+namespace {
+
+// Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
+// XCD walks one contiguous range of logical blocks (its L2 then sees
+// neighbouring rows and shares their gathered vector entries).
+__device__ __forceinline__ int xcd_block(int b, int nblk) {
+  const int x = b & 7, k = b >> 3;
+  const int q = nblk >> 3, r = nblk & 7;
+  return x * q + min(x, r) + k;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_down(v, off, G);
+  return v;
+}
+
+inline int nblocks(int64_t n, int per) { return (int)((n + per - 1) / per); }
+
+// --------------------------------------------------------------------------
+// y = A x  or  y = b - A x, A 3x3 block-sparse in SELL-64
+template <bool RESID>
+__global__ __launch_bounds__(kBlock) void k_bsr3_spmv(int nrows, int nblk, const int32_t* __restrict__ sptr,
+                                                      const int32_t* __restrict__ col,
+                                                      const double* __restrict__ val,
+                                                      const double* __restrict__ x,
+                                                      const double* __restrict__ b,
+                                                      double* __restrict__ y) {
+  const int row = xcd_block(blockIdx.x, nblk) * kBlock + threadIdx.x;
+  if (row >= nrows) return;
+  const int s = row >> 6, lane = row & 63;
+  const int k0 = sptr[s], k1 = sptr[s + 1];
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int k = k0; k < k1; ++k) {
+    const int c = col[(size_t)k * 64 + lane];
+    const double* v = val + (size_t)k * 9 * 64 + lane;
+    const double x0 = x[3 * (size_t)c], x1 = x[3 * (size_t)c + 1], x2 = x[3 * (size_t)c + 2];
+    a0 += v[0] * x0 + v[64] * x1 + v[128] * x2;
+    a1 += v[192] * x0 + v[256] * x1 + v[320] * x2;
+    a2 += v[384] * x0 + v[448] * x1 + v[512] * x2;
+  }
+  double* yo = y + 3 * (size_t)row;
+  if (RESID) {
+    const double* bo = b + 3 * (size_t)row;
+    yo[0] = bo[0] - a0;
+    yo[1] = bo[1] - a1;
+    yo[2] = bo[2] - a2;
+  } else {
+    yo[0] = a0;
+    yo[1] = a1;
+    yo[2] = a2;
+  }
+}
+
+// --------------------------------------------------------------------------
+// quasi-IMPES restriction: b0_i = r_i[E] - W_i r_i[H]
+template <int NE>
+__global__ __launch_bounds__(kBlock) void k_l0_restrict(int nc, const double* __restrict__ r,
+                                                        const double* __restrict__ W, int e0,
+                                                        int e1, int h0, int h1,
+                                                        double* __restrict__ b0) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nc) return;
+  const double* ri = r + 3 * (size_t)i;
+  if (NE == 2) {
+    const double rh = ri[h0];
+    b0[2 * (size_t)i] = ri[e0] - W[2 * (size_t)i] * rh;
+    b0[2 * (size_t)i + 1] = ri[e1] - W[2 * (size_t)i + 1] * rh;
+  } else {
+    b0[i] = ri[e0] - W[2 * (size_t)i] * ri[h0] - W[2 * (size_t)i + 1] * ri[h1];
+  }
+}
+
+// r0 = b0 - Ahat (D^-1 b0): pre-smoothing from zero fused with the residual
+template <int NE>
+__global__ __launch_bounds__(kBlock) void k_l0_resid_jacobi(int nc, int nblk, const int32_t* __restrict__ sptr,
+                                                            const int32_t* __restrict__ col,
+                                                            const double* __restrict__ val,
+                                                            const double* __restrict__ b0,
+                                                            const double* __restrict__ dinv,
+                                                            double* __restrict__ r0) {
+  const int row = xcd_block(blockIdx.x, nblk) * kBlock + threadIdx.x;
+  if (row >= nc) return;
+  const int s = row >> 6, lane = row & 63;
+  double acc[NE];
+#pragma unroll
+  for (int a = 0; a < NE; ++a) acc[a] = 0.0;
+  for (int k = sptr[s]; k < sptr[s + 1]; ++k) {
+    const int c = col[(size_t)k * 64 + lane];
+    const double* v = val + (size_t)k * NE * NE * 64 + lane;
+    double xc[NE];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) xc[q] = dinv[(size_t)c * NE + q] * b0[(size_t)c * NE + q];
+#pragma unroll
+    for (int a = 0; a < NE; ++a)
+#pragma unroll
+      for (int q = 0; q < NE; ++q) acc[a] += v[(a * NE + q) * 64] * xc[q];
+  }
+#pragma unroll
+  for (int a = 0; a < NE; ++a) r0[(size_t)row * NE + a] = b0[(size_t)row * NE + a] - acc[a];
+}
+
+// e0 = x0 + D^-1 (b0 - Ahat x0): post-smoothing at level 0
+template <int NE>
+__global__ __launch_bounds__(kBlock) void k_l0_post(int nc, int nblk, const int32_t* __restrict__ sptr,
+                                                    const int32_t* __restrict__ col,
+                                                    const double* __restrict__ val,
+                                                    const double* __restrict__ x0,
+                                                    const double* __restrict__ b0,
+                                                    const double* __restrict__ dinv,
+                                                    double* __restrict__ e0) {
+  const int row = xcd_block(blockIdx.x, nblk) * kBlock + threadIdx.x;
+  if (row >= nc) return;
+  const int s = row >> 6, lane = row & 63;
+  double acc[NE];
+#pragma unroll
+  for (int a = 0; a < NE; ++a) acc[a] = 0.0;
+  for (int k = sptr[s]; k < sptr[s + 1]; ++k) {
+    const int c = col[(size_t)k * 64 + lane];
+    const double* v = val + (size_t)k * NE * NE * 64 + lane;
+    double xc[NE];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) xc[q] = x0[(size_t)c * NE + q];
+#pragma unroll
+    for (int a = 0; a < NE; ++a)
+#pragma unroll
+      for (int q = 0; q < NE; ++q) acc[a] += v[(a * NE + q) * 64] * xc[q];
+  }
+#pragma unroll
+  for (int a = 0; a < NE; ++a) {
+    const size_t i = (size_t)row * NE + a;
+    e0[i] = x0[i] + dinv[i] * (b0[i] - acc[a]);
+  }
+}
+
+// --------------------------------------------------------------------------
+// scalar CSR kernels: G lanes per row
+enum CsrOp { kSpmv = 0, kResidJacobi = 1, kProlong = 2, kPost = 3 };
+
+template <int G, int OP>
+__global__ __launch_bounds__(kBlock) void k_csr(int n, const int32_t* __restrict__ rp,
+                                                const int32_t* __restrict__ ci,
+                                                const double* __restrict__ v,
+                                                const double* __restrict__ x,
+                                                const double* __restrict__ b,
+                                                const double* __restrict__ dinv,
+                                                double* __restrict__ y) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int row = (int)(t / G), sub = (int)(t % G);
+  const bool live = row < n;
+  double acc = 0.0;
+  if (live) {
+    for (int k = rp[row] + sub; k < rp[row + 1]; k += G) {
+      const int c = ci[k];
+      double xv = x[c];
+      if (OP == kResidJacobi) xv = dinv[c] * b[c];
+      acc += v[k] * xv;
+    }
+  }
+  acc = group_sum<G>(acc);
+  if (!live || sub != 0) return;
+  switch (OP) {
+    case kSpmv: y[row] = acc; break;
+    case kResidJacobi: y[row] = b[row] - acc; break;
+    case kProlong: y[row] = dinv[row] * b[row] + acc; break;
+    case kPost: y[row] = x[row] + dinv[row] * (b[row] - acc); break;
+  }
+}
+
+template <int OP>
+void launch_csr_op(const DCsr& A, const double* x, const double* b, const double* dinv, double* y,
+                   hipStream_t st) {
+  if (A.n == 0) return;
+  const int64_t threads = (int64_t)A.n * A.group;
+  const int grid = nblocks(threads, kBlock);
+  switch (A.group) {
+#define CSR_CASE(G) \
+  case G: k_csr<G, OP><<<grid, kBlock, 0, st>>>(A.n, A.rp, A.ci, A.v, x, b, dinv, y); break;
+    CSR_CASE(1) CSR_CASE(2) CSR_CASE(4) CSR_CASE(8) CSR_CASE(16) CSR_CASE(32) CSR_CASE(64)
+#undef CSR_CASE
+    default: k_csr<8, OP><<<nblocks((int64_t)A.n * 8, kBlock), kBlock, 0, st>>>(A.n, A.rp, A.ci, A.v, x, b, dinv, y);
+  }
+}
+
+// --------------------------------------------------------------------------
+// coarsest level: x = (LU)^-1 b with row swaps piv (one workgroup)
+__global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, const double* __restrict__ lu,
+                                                         const int32_t* __restrict__ piv,
+                                                         const double* __restrict__ b,
+                                                         double* __restrict__ x) {
+  extern __shared__ double s[];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n; i += kBlock) s[i] = b[i];
+  __syncthreads();
+  if (tid == 0)
+    for (int k = 0; k < n; ++k) {
+      const int p = piv[k];
+      if (p != k) {
+        const double t = s[k];
+        s[k] = s[p];
+        s[p] = t;
+      }
+    }
+  __syncthreads();
+  for (int i = 0; i < n; ++i) {  // unit lower
+    const double xi = s[i];
+    for (int j = i + 1 + tid; j < n; j += kBlock) s[j] -= lu[(size_t)j * n + i] * xi;
+    __syncthreads();
+  }
+  for (int i = n - 1; i >= 0; --i) {  // upper
+    if (tid == 0) s[i] /= lu[(size_t)i * n + i];
+    __syncthreads();
+    const double xi = s[i];
+    for (int j = tid; j < i; j += kBlock) s[j] -= lu[(size_t)j * n + i] * xi;
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += kBlock) x[i] = s[i];
+}
+
+// --------------------------------------------------------------------------
+// stage-two residual r2 = r - A x1 with x1[E] = e0, x1[H] = 0: only the
+// elliptic columns of each block are read
+template <int NE>
+__global__ __launch_bounds__(kBlock) void k_stage2_resid(int nrows, int nblk, const int32_t* __restrict__ sptr,
+                                                         const int32_t* __restrict__ col,
+                                                         const double* __restrict__ val, int ea,
+                                                         int eb, const double* __restrict__ e0,
+                                                         const double* __restrict__ r,
+                                                         double* __restrict__ r2) {
+  const int row = xcd_block(blockIdx.x, nblk) * kBlock + threadIdx.x;
+  if (row >= nrows) return;
+  const int s = row >> 6, lane = row & 63;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int k = sptr[s]; k < sptr[s + 1]; ++k) {
+    const int c = col[(size_t)k * 64 + lane];
+    const double* v = val + (size_t)k * 9 * 64 + lane;
+    const double u = e0[(size_t)c * NE];
+    a0 += v[(0 * 3 + ea) * 64] * u;
+    a1 += v[(1 * 3 + ea) * 64] * u;
+    a2 += v[(2 * 3 + ea) * 64] * u;
+    if (NE == 2) {
+      const double w = e0[(size_t)c * NE + 1];
+      a0 += v[(0 * 3 + eb) * 64] * w;
+      a1 += v[(1 * 3 + eb) * 64] * w;
+      a2 += v[(2 * 3 + eb) * 64] * w;
+    }
+  }
+  const double* ri = r + 3 * (size_t)row;
+  double* o = r2 + 3 * (size_t)row;
+  o[0] = ri[0] - a0;
+  o[1] = ri[1] - a1;
+  o[2] = ri[2] - a2;
+}
+
+// --------------------------------------------------------------------------
+// ILU(0) sweeps, one launch per dependency level.  Positions are rows sorted
+// by level; slot columns < 0 are padding.
+__global__ __launch_bounds__(kBlock) void k_ilu_fwd(int p0, int p1, const int32_t* __restrict__ sptr,
+                                                    const int32_t* __restrict__ col,
+                                                    const double* __restrict__ val,
+                                                    const int32_t* __restrict__ perm,
+                                                    const double* __restrict__ r2,
+                                                    double* __restrict__ y) {
+  const int p = p0 + blockIdx.x * kBlock + threadIdx.x;
+  if (p >= p1) return;
+  const int i = perm[p];
+  const int s = p >> 6, lane = p & 63;
+  double a0 = r2[3 * (size_t)i], a1 = r2[3 * (size_t)i + 1], a2 = r2[3 * (size_t)i + 2];
+  for (int k = sptr[s]; k < sptr[s + 1]; ++k) {
+    const int c = col[(size_t)k * 64 + lane];
+    if (c < 0) continue;
+    const double* v = val + (size_t)k * 9 * 64 + lane;
+    const double x0 = y[3 * (size_t)c], x1 = y[3 * (size_t)c + 1], x2 = y[3 * (size_t)c + 2];
+    a0 -= v[0] * x0 + v[64] * x1 + v[128] * x2;
+    a1 -= v[192] * x0 + v[256] * x1 + v[320] * x2;
+    a2 -= v[384] * x0 + v[448] * x1 + v[512] * x2;
+  }
+  y[3 * (size_t)i] = a0;
+  y[3 * (size_t)i + 1] = a1;
+  y[3 * (size_t)i + 2] = a2;
+}
+
+template <int NE>
+__global__ __launch_bounds__(kBlock) void k_ilu_bwd(int p0, int p1, int npad, const int32_t* __restrict__ sptr,
+                                                    const int32_t* __restrict__ col,
+                                                    const double* __restrict__ val,
+                                                    const int32_t* __restrict__ perm,
+                                                    const double* __restrict__ uinv,
+                                                    const double* __restrict__ y, const double* __restrict__ e0,
+                                                    int ea, int eb, double* __restrict__ x2,
+                                                    double* __restrict__ z) {
+  const int p = p0 + blockIdx.x * kBlock + threadIdx.x;
+  if (p >= p1) return;
+  const int i = perm[p];
+  const int s = p >> 6, lane = p & 63;
+  double a0 = y[3 * (size_t)i], a1 = y[3 * (size_t)i + 1], a2 = y[3 * (size_t)i + 2];
+  for (int k = sptr[s]; k < sptr[s + 1]; ++k) {
+    const int c = col[(size_t)k * 64 + lane];
+    if (c < 0) continue;
+    const double* v = val + (size_t)k * 9 * 64 + lane;
+    const double x0 = x2[3 * (size_t)c], x1 = x2[3 * (size_t)c + 1], xx = x2[3 * (size_t)c + 2];
+    a0 -= v[0] * x0 + v[64] * x1 + v[128] * xx;
+    a1 -= v[192] * x0 + v[256] * x1 + v[320] * xx;
+    a2 -= v[384] * x0 + v[448] * x1 + v[512] * xx;
+  }
+  const double* u = uinv + p;
+  const double o0 = u[0] * a0 + u[(size_t)npad] * a1 + u[2 * (size_t)npad] * a2;
+  const double o1 = u[3 * (size_t)npad] * a0 + u[4 * (size_t)npad] * a1 + u[5 * (size_t)npad] * a2;
+  const double o2 = u[6 * (size_t)npad] * a0 + u[7 * (size_t)npad] * a1 + u[8 * (size_t)npad] * a2;
+  x2[3 * (size_t)i] = o0;
+  x2[3 * (size_t)i + 1] = o1;
+  x2[3 * (size_t)i + 2] = o2;
+  // z = x1 + x2 with x1[E] = e0 and x1[H] = 0
+  const double ex = e0[(size_t)i * NE];
+  const double ey = NE == 2 ? e0[(size_t)i * NE + 1] : 0.0;
+  z[3 * (size_t)i] = o0 + (ea == 0 ? ex : 0.0) + (NE == 2 && eb == 0 ? ey : 0.0);
+  z[3 * (size_t)i + 1] = o1 + (ea == 1 ? ex : 0.0) + (NE == 2 && eb == 1 ? ey : 0.0);
+  z[3 * (size_t)i + 2] = o2 + (ea == 2 ? ex : 0.0) + (NE == 2 && eb == 2 ? ey : 0.0);
+}
+
+// --------------------------------------------------------------------------
+// Arnoldi BLAS-1.  part[blk * ncol + j] holds each workgroup's partial sums.
+template <int MAXV>
+__device__ __forceinline__ void block_store(const double* acc, int nv, double* part, int ncol) {
+  __shared__ double red[kBlock / 64][MAXV + 1];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int j = 0; j < MAXV + 1; ++j) {
+    if (j < ncol) {
+      const double v = wave_sum(acc[j]);
+      if (lane == 0) red[wave][j] = v;
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < ncol; j += kBlock) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) s += red[w][j];
+    part[(size_t)blockIdx.x * ncol + j] = s;
+  }
+  (void)nv;
+}
+
+template <int MAXV>
+__global__ __launch_bounds__(kBlock) void k_mdot(int64_t n, int nv, const double* __restrict__ V, int64_t ldv,
+                                                 const double* __restrict__ w, double* __restrict__ part) {
+  double acc[MAXV + 1];
+#pragma unroll
+  for (int j = 0; j <= MAXV; ++j) acc[j] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const double wi = w[i];
+#pragma unroll
+    for (int j = 0; j < MAXV; ++j)
+      if (j < nv) acc[j] += V[(size_t)j * ldv + i] * wi;
+  }
+  block_store<MAXV>(acc, nv, part, nv);
+}
+
+// w -= sum_j coef_j V_j, then partial dots V_j . w (second Gram-Schmidt pass)
+template <int MAXV>
+__global__ __launch_bounds__(kBlock) void k_maxpy_dot(int64_t n, int nv, const double* __restrict__ V,
+                                                      int64_t ldv, const double* __restrict__ coef,
+                                                      double* __restrict__ w, double* __restrict__ part) {
+  double acc[MAXV + 1];
+  double c[MAXV];
+#pragma unroll
+  for (int j = 0; j <= MAXV; ++j) acc[j] = 0.0;
+#pragma unroll
+  for (int j = 0; j < MAXV; ++j) c[j] = j < nv ? coef[j] : 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    double wi = w[i];
+#pragma unroll
+    for (int j = 0; j < MAXV; ++j)
+      if (j < nv) wi -= c[j] * V[(size_t)j * ldv + i];
+    w[i] = wi;
+#pragma unroll
+    for (int j = 0; j < MAXV; ++j)
+      if (j < nv) acc[j] += V[(size_t)j * ldv + i] * wi;
+  }
+  block_store<MAXV>(acc, nv, part, nv);
+}
+
+// w -= sum_j coef_j V_j, then the partial squared norm of w
+template <int MAXV>
+__global__ __launch_bounds__(kBlock) void k_maxpy_norm(int64_t n, int nv, const double* __restrict__ V,
+                                                       int64_t ldv, const double* __restrict__ coef,
+                                                       double* __restrict__ w, double* __restrict__ part) {
+  double c[MAXV];
+#pragma unroll
+  for (int j = 0; j < MAXV; ++j) c[j] = j < nv ? coef[j] : 0.0;
+  double acc[1] = {0.0};
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    double wi = w[i];
+#pragma unroll
+    for (int j = 0; j < MAXV; ++j)
+      if (j < nv) wi -= c[j] * V[(size_t)j * ldv + i];
+    w[i] = wi;
+    acc[0] += wi * wi;
+  }
+  block_store<0>(acc, 1, part, 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_norm2(int64_t n, const double* __restrict__ x,
+                                                  double* __restrict__ part) {
+  double acc[1] = {0.0};
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) acc[0] += x[i] * x[i];
+  block_store<0>(acc, 1, part, 1);
+}
+
+// out[j] (+)= sum over workgroups of part[b * ncol + j], fixed tree order
+__global__ __launch_bounds__(kBlock) void k_reduce(int ncol, const double* __restrict__ part,
+                                                   double* __restrict__ out, int add) {
+  __shared__ double red[kBlock];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < kRedBlocks; b += kBlock) s += part[(size_t)b * ncol + j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = add ? out[j] + red[0] : red[0];
+}
+
+// in place allowed (w == v)
+__global__ __launch_bounds__(kBlock) void k_scale(int64_t n, const double* w, const double* nrm2, double* v) {
+  const double h = sqrt(nrm2[0]);
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) v[i] = w[i] / h;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scale_host(int64_t n, const double* __restrict__ w, double s,
+                                                       double* __restrict__ v) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) v[i] = w[i] / s;
+}
+
+struct Coef64 {
+  double c[64];
+};
+
+__global__ __launch_bounds__(kBlock) void k_update(int64_t n, int nv, const double* __restrict__ V, int64_t ldv,
+                                                   Coef64 coef, double* __restrict__ x) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    double s = x[i];
+    for (int j = 0; j < nv; ++j) s += coef.c[j] * V[(size_t)j * ldv + i];
+    x[i] = s;
+  }
+}
+
+}  // namespace
+
+// ============================================================================
+// launchers
+void launch_bsr3_spmv(const Sell& A, const double* x, const double* b, double* y, bool resid,
+                      hipStream_t st) {
+  const int g = nblocks(A.nrows, kBlock);
+  if (resid)
+    k_bsr3_spmv<true><<<g, kBlock, 0, st>>>(A.nrows, g, A.sptr, A.col, A.val, x, b, y);
+  else
+    k_bsr3_spmv<false><<<g, kBlock, 0, st>>>(A.nrows, g, A.sptr, A.col, A.val, x, b, y);
+}
+
+void launch_l0_restrict(int32_t nc, int ne, const double* r, const double* W, const int32_t* eidx,
+                        const int32_t* hidx, double* b0, hipStream_t st) {
+  const int g = nblocks(nc, kBlock);
+  if (ne == 2)
+    k_l0_restrict<2><<<g, kBlock, 0, st>>>(nc, r, W, eidx[0], eidx[1], hidx[0], 0, b0);
+  else
+    k_l0_restrict<1><<<g, kBlock, 0, st>>>(nc, r, W, eidx[0], 0, hidx[0], hidx[1], b0);
+}
+
+void launch_l0_resid_jacobi(const Sell& Ah, int ne, const double* b0, const double* dinv, double* r0,
+                            hipStream_t st) {
+  const int g = nblocks(Ah.nrows, kBlock);
+  if (ne == 2)
+    k_l0_resid_jacobi<2><<<g, kBlock, 0, st>>>(Ah.nrows, g, Ah.sptr, Ah.col, Ah.val, b0, dinv, r0);
+  else
+    k_l0_resid_jacobi<1><<<g, kBlock, 0, st>>>(Ah.nrows, g, Ah.sptr, Ah.col, Ah.val, b0, dinv, r0);
+}
+
+void launch_l0_post(const Sell& Ah, int ne, const double* x0, const double* b0, const double* dinv,
+                    double* e0, hipStream_t st) {
+  const int g = nblocks(Ah.nrows, kBlock);
+  if (ne == 2)
+    k_l0_post<2><<<g, kBlock, 0, st>>>(Ah.nrows, g, Ah.sptr, Ah.col, Ah.val, x0, b0, dinv, e0);
+  else
+    k_l0_post<1><<<g, kBlock, 0, st>>>(Ah.nrows, g, Ah.sptr, Ah.col, Ah.val, x0, b0, dinv, e0);
+}
+
+void launch_csr_resid_jacobi(const DCsr& A, const double* b, const double* dinv, double* r,
+                             hipStream_t st) {
+  launch_csr_op<kResidJacobi>(A, nullptr, b, dinv, r, st);
+}
+void launch_csr_spmv(const DCsr& A, const double* x, double* y, hipStream_t st) {
+  launch_csr_op<kSpmv>(A, x, nullptr, nullptr, y, st);
+}
+void launch_csr_prolong(const DCsr& P, const double* xc, const double* b, const double* dinv,
+                        double* x, hipStream_t st) {
+  launch_csr_op<kProlong>(P, xc, b, dinv, x, st);
+}
+void launch_csr_post(const DCsr& A, const double* x, const double* b, const double* dinv, double* e,
+                     hipStream_t st) {
+  launch_csr_op<kPost>(A, x, b, dinv, e, st);
+}
+
+void launch_coarse_solve(int n, const double* lu, const int32_t* piv, const double* b, double* x,
+                         hipStream_t st) {
+  k_coarse_solve<<<1, kBlock, sizeof(double) * (size_t)n, st>>>(n, lu, piv, b, x);
+}
+
+void launch_stage2_resid(const Sell& A, int ne, const int32_t* eidx, const double* e0,
+                         const double* r, double* r2, hipStream_t st) {
+  const int g = nblocks(A.nrows, kBlock);
+  if (ne == 2)
+    k_stage2_resid<2><<<g, kBlock, 0, st>>>(A.nrows, g, A.sptr, A.col, A.val, eidx[0], eidx[1], e0, r, r2);
+  else
+    k_stage2_resid<1><<<g, kBlock, 0, st>>>(A.nrows, g, A.sptr, A.col, A.val, eidx[0], 0, e0, r, r2);
+}
+
+void launch_ilu_fwd_level(const Sell& L, const int32_t* perm, int32_t p0, int32_t p1,
+                          const double* r2, double* y, hipStream_t st) {
+  if (p1 <= p0) return;
+  k_ilu_fwd<<<nblocks(p1 - p0, kBlock), kBlock, 0, st>>>(p0, p1, L.sptr, L.col, L.val, perm, r2, y);
+}
+
+void launch_ilu_bwd_level(const Sell& U, const int32_t* perm, const double* uinv, int32_t p0,
+                          int32_t p1, const double* y, const double* e0, int ne,
+                          const int32_t* eidx, double* x2, double* z, hipStream_t st) {
+  if (p1 <= p0) return;
+  const int npad = U.nslices * 64;
+  const int g = nblocks(p1 - p0, kBlock);
+  if (ne == 2)
+    k_ilu_bwd<2><<<g, kBlock, 0, st>>>(p0, p1, npad, U.sptr, U.col, U.val, perm, uinv, y, e0,
+                                       eidx[0], eidx[1], x2, z);
+  else
+    k_ilu_bwd<1><<<g, kBlock, 0, st>>>(p0, p1, npad, U.sptr, U.col, U.val, perm, uinv, y, e0,
+                                       eidx[0], 0, x2, z);
+}
+
+#define MAXV_DISPATCH(KERNEL, nv, ...)                                                     \
+  do {                                                                                     \
+    if ((nv) <= 8) KERNEL<8><<<kRedBlocks, kBlock, 0, st>>>(__VA_ARGS__);                  \
+    else if ((nv) <= 16) KERNEL<16><<<kRedBlocks, kBlock, 0, st>>>(__VA_ARGS__);           \
+    else if ((nv) <= 32) KERNEL<32><<<kRedBlocks, kBlock, 0, st>>>(__VA_ARGS__);           \
+    else KERNEL<64><<<kRedBlocks, kBlock, 0, st>>>(__VA_ARGS__);                           \
+  } while (0)
+
+void launch_mdot(int64_t n, int nv, const double* V, int64_t ldv, const double* w, double* part,
+                 hipStream_t st) {
+  MAXV_DISPATCH(k_mdot, nv, n, nv, V, ldv, w, part);
+}
+void launch_maxpy_dot(int64_t n, int nv, const double* V, int64_t ldv, const double* coef,
+                      double* w, double* part, hipStream_t st) {
+  MAXV_DISPATCH(k_maxpy_dot, nv, n, nv, V, ldv, coef, w, part);
+}
+void launch_maxpy_norm(int64_t n, int nv, const double* V, int64_t ldv, const double* coef,
+                       double* w, double* part, hipStream_t st) {
+  MAXV_DISPATCH(k_maxpy_norm, nv, n, nv, V, ldv, coef, w, part);
+}
+void launch_reduce(int ncols, const double* part, double* out, int add_to_out, hipStream_t st) {
+  k_reduce<<<ncols, kBlock, 0, st>>>(ncols, part, out, add_to_out);
+}
+void launch_scale(int64_t n, const double* w, const double* nrm2, double* v, hipStream_t st) {
+  k_scale<<<kRedBlocks, kBlock, 0, st>>>(n, w, nrm2, v);
+}
+void launch_scale_host(int64_t n, const double* w, double s, double* v, hipStream_t st) {
+  k_scale_host<<<kRedBlocks, kBlock, 0, st>>>(n, w, s, v);
+}
+void launch_norm2(int64_t n, const double* x, double* part, hipStream_t st) {
+  k_norm2<<<kRedBlocks, kBlock, 0, st>>>(n, x, part);
+}
+void launch_update_host_coef(int64_t n, int nv, const double* V, int64_t ldv, const double* coef,
+                             double* x, hipStream_t st) {
+  Coef64 c;
+  for (int j = 0; j < 64; ++j) c.c[j] = j < nv ? coef[j] : 0.0;
+  k_update<<<kRedBlocks, kBlock, 0, st>>>(n, nv, V, ldv, c, x);
+}
+
+}  // namespace cptr

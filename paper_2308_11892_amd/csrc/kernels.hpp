@@ -1,0 +1,78 @@
+// kernels.hpp -- device data layouts and launchers of the CPTR hot path (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cptr {
+
+constexpr int kLanes = 64;      // rows per SELL slice = one wavefront
+constexpr int kBlock = 256;     // threads per workgroup for streaming kernels
+constexpr int kRedBlocks = 1024;  // workgroups of the deterministic reductions
+
+// Sliced-ELL layout with one 64-row slice per wavefront.  Slice s owns the
+// k-columns [sptr[s], sptr[s+1]); k-column k holds, for each of the 64 lanes,
+// one block: col[k*64 + lane] and the block's `nv` values stored as planes
+// val[(k*nv + e)*64 + lane], so lane-consecutive loads of one entry are
+// contiguous.  Padding slots repeat a valid column with zero values.
+struct Sell {
+  int32_t nrows = 0;      // block rows (or positions) covered
+  int32_t nslices = 0;
+  int32_t nv = 0;         // values per block (9 for 3x3, 4 for 2x2)
+  int32_t* sptr = nullptr;
+  int32_t* col = nullptr;
+  double* val = nullptr;
+  int64_t nslots = 0;     // total k-columns
+};
+
+// Scalar CSR on the device.
+struct DCsr {
+  int32_t n = 0, m = 0;
+  int64_t nnz = 0;
+  int32_t* rp = nullptr;
+  int32_t* ci = nullptr;
+  double* v = nullptr;
+  int group = 1;          // lanes cooperating on one row
+};
+
+// ---- launchers (all asynchronous on `st`) ----
+void launch_bsr3_spmv(const Sell& A, const double* x, const double* b, double* y, bool resid,
+                      hipStream_t st);
+void launch_l0_restrict(int32_t nc, int ne, const double* r, const double* W, const int32_t* eidx,
+                        const int32_t* hidx, double* b0, hipStream_t st);
+void launch_l0_resid_jacobi(const Sell& Ah, int ne, const double* b0, const double* dinv, double* r0,
+                            hipStream_t st);
+void launch_l0_post(const Sell& Ah, int ne, const double* x0, const double* b0, const double* dinv,
+                    double* e0, hipStream_t st);
+void launch_csr_resid_jacobi(const DCsr& A, const double* b, const double* dinv, double* r,
+                             hipStream_t st);
+void launch_csr_spmv(const DCsr& A, const double* x, double* y, hipStream_t st);
+void launch_csr_prolong(const DCsr& P, const double* xc, const double* b, const double* dinv,
+                        double* x, hipStream_t st);
+void launch_csr_post(const DCsr& A, const double* x, const double* b, const double* dinv, double* e,
+                     hipStream_t st);
+void launch_coarse_solve(int n, const double* lu, const int32_t* piv, const double* b, double* x,
+                         hipStream_t st);
+void launch_stage2_resid(const Sell& A, int ne, const int32_t* eidx, const double* e0,
+                         const double* r, double* r2, hipStream_t st);
+void launch_ilu_fwd_level(const Sell& L, const int32_t* perm, int32_t p0, int32_t p1,
+                          const double* r2, double* y, hipStream_t st);
+void launch_ilu_bwd_level(const Sell& U, const int32_t* perm, const double* uinv, int32_t p0,
+                          int32_t p1, const double* y, const double* e0, int ne,
+                          const int32_t* eidx, double* x2, double* z, hipStream_t st);
+
+// Arnoldi / BLAS-1 (deterministic two-stage reductions into `part`)
+void launch_mdot(int64_t n, int nv, const double* V, int64_t ldv, const double* w, double* part,
+                 hipStream_t st);
+void launch_maxpy_dot(int64_t n, int nv, const double* V, int64_t ldv, const double* coef,
+                      double* w, double* part, hipStream_t st);
+void launch_maxpy_norm(int64_t n, int nv, const double* V, int64_t ldv, const double* coef,
+                       double* w, double* part, hipStream_t st);
+void launch_reduce(int ncols, const double* part, double* out, int add_to_out, hipStream_t st);
+void launch_scale(int64_t n, const double* w, const double* nrm2, double* v, hipStream_t st);
+void launch_scale_host(int64_t n, const double* w, double s, double* v, hipStream_t st);
+void launch_norm2(int64_t n, const double* x, double* part, hipStream_t st);
+void launch_update_host_coef(int64_t n, int nv, const double* V, int64_t ldv, const double* coef,
+                             double* x, hipStream_t st);
+
+}  // namespace cptr

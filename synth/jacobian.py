@@ -48,6 +48,8 @@ P0 = 20e6                             # Pa
 DP_WELL = 2e6                         # Pa
 R_WELL = 0.5                          # cells
 P_SCALE = 1e6                         # pressure column unit: MPa
+K_REF = 1e-13                         # m^2, reference medium of the flow state
+LAM_REF = 1.0 / 5e-4                  # 1/(Pa s), brine mobility at reservoir T
 
 
 @dataclasses.dataclass
@@ -110,16 +112,23 @@ def _mobility(z, T):
     return lam, dlam_dT, dlam_dz
 
 
+def _radial_p(ii, jj, wells, R):
+    """Superposed radial pressure of the injectors at cell coordinates (ii, jj)."""
+    p = np.full(np.broadcast(ii, jj).shape, P0)
+    for (iw, jw) in wells:
+        r = np.sqrt((ii - iw) ** 2 + (jj - jw) ** 2)
+        p = p + DP_WELL * np.log(R / np.maximum(R_WELL, r)) / math.log(R / R_WELL)
+    return p
+
+
 def _state(nx, ny, nz, wells, r_front):
     i = np.arange(nx, dtype=np.float64)[None, None, :]
     j = np.arange(ny, dtype=np.float64)[None, :, None]
     R = math.hypot(nx, ny)
-    p = np.full((nz, ny, nx), P0)
+    p = np.broadcast_to(_radial_p(i, j, wells, R), (nz, ny, nx))
     dmin = np.full((1, ny, nx), np.inf)
     for (iw, jw) in wells:
-        r = np.sqrt((i - iw) ** 2 + (j - jw) ** 2)
-        p = p + DP_WELL * np.log(R / np.maximum(R_WELL, r)) / math.log(R / R_WELL)
-        dmin = np.minimum(dmin, r)
+        dmin = np.minimum(dmin, np.sqrt((i - iw) ** 2 + (j - jw) ** 2))
     dmin = np.broadcast_to(dmin, (nz, ny, nx))
     T = T_RES - DT_INJ * 0.5 * (1.0 - np.tanh(dmin - r_front))
     z = 0.5 * (1.0 - np.tanh(dmin - 2.0 * r_front))
@@ -139,28 +148,49 @@ def _faces(nx, ny, nz):
     return out
 
 
-def _face_fluxes(p, T, z, perm, faces):
-    """Per-face volumetric flux magnitude data used for the Peclet number."""
+def _face_fluxes(p, faces):
+    """Volumetric face fluxes of the linearisation state.
+
+    They come from the superposed radial flow of the injectors through the
+    reference medium (K_REF, LAM_REF), so the flux field is conservative away
+    from the wells, as the converged Newton state of a simulator would be;
+    the heterogeneity enters the Jacobian through the transmissibilities and
+    the Darcy-consistent face pressure differences dp_f = F_f / (T_f lam_u)."""
     res = []
     for (d, a, b, area, dist) in faces:
-        ka, kb = perm[a], perm[b]
-        tf = (area / dist) * 2.0 * ka * kb / (ka + kb)
-        dp = p[a] - p[b]
-        up = np.where(dp > 0, a, np.where(dp < 0, b, np.minimum(a, b)))
-        lam, _, _ = _mobility(z[up], T[up])
-        F = tf * lam * dp
-        res.append((F, area, dist))
+        res.append((area / dist) * K_REF * LAM_REF * (p[a] - p[b]))
     return res
 
 
-def peclet(p, T, z, perm, faces, kappa):
+def peclet(fluxes, faces, kappa):
     """Median over faces with nonzero flux of |F| C_f d / (kappa A)  (Eq. 4, per face)."""
     vals = []
-    for (F, area, dist) in _face_fluxes(p, T, z, perm, faces):
+    for F, (d, a, b, area, dist) in zip(fluxes, faces):
         nz_ = F != 0
         vals.append(np.abs(F[nz_]) * CF * dist / (kappa * area))
     v = np.concatenate(vals) if vals else np.zeros(0)
     return float(np.median(v)) if v.size else 0.0
+
+
+def _boundary_outflow(nx, ny, nz, wells):
+    """Open lateral boundaries: (cell ids, outward flux > 0) of the radial flow
+    leaving the domain through its x and y boundary faces."""
+    R = math.hypot(nx, ny)
+    idx = np.arange(nx * ny * nz, dtype=np.int64).reshape(nz, ny, nx)
+    cells, flux = [], []
+    jj = np.arange(ny, dtype=np.float64)
+    ii = np.arange(nx, dtype=np.float64)
+    sides = [
+        (idx[:, :, 0], _radial_p(0.0, jj, wells, R) - _radial_p(-1.0, jj, wells, R), DY * DZ / DX),
+        (idx[:, :, nx - 1], _radial_p(nx - 1.0, jj, wells, R) - _radial_p(float(nx), jj, wells, R), DY * DZ / DX),
+        (idx[:, 0, :], _radial_p(ii, 0.0, wells, R) - _radial_p(ii, -1.0, wells, R), DX * DZ / DY),
+        (idx[:, ny - 1, :], _radial_p(ii, ny - 1.0, wells, R) - _radial_p(ii, float(ny), wells, R), DX * DZ / DY),
+    ]
+    for cell_ids, dp, geo in sides:
+        F = np.broadcast_to(geo * K_REF * LAM_REF * dp, cell_ids.shape)
+        cells.append(cell_ids.ravel())
+        flux.append(np.maximum(F, 0.0).ravel())
+    return np.concatenate(cells), np.concatenate(flux)
 
 
 def cartesian(name, nx, ny, nz, *, seed, sigma, corr, n_wells, r_front,
@@ -174,10 +204,11 @@ def cartesian(name, nx, ny, nz, *, seed, sigma, corr, n_wells, r_front,
     p3, T3, z3 = _state(nx, ny, nz, wells, r_front)
     p, T, z = p3.ravel(), T3.ravel(), z3.ravel()
     faces = _faces(nx, ny, nz)
-    pe0 = peclet(p, T, z, perm, faces, kappa)
+    fluxes = _face_fluxes(p, faces)
+    pe0 = peclet(fluxes, faces, kappa)
     if pe_target is not None:
         kappa = kappa * pe0 / pe_target
-    pe = peclet(p, T, z, perm, faces, kappa)
+    pe = peclet(fluxes, faces, kappa)
 
     # Seven slots per row in sorted column order: -z, -y, -x, diag, +x, +y, +z.
     SLOT = {(2, -1): 0, (1, -1): 1, (0, -1): 2, (0, 1): 4, (1, 1): 5, (2, 1): 6}
@@ -189,20 +220,19 @@ def cartesian(name, nx, ny, nz, *, seed, sigma, corr, n_wells, r_front,
     val7[:, 3, 1, 1] += vol * (PORO * CF + (1.0 - PORO) * CR) / DT
     val7[:, 3, 2, 2] += vol * PORO / DT
 
-    for (d, a, b, area, dist) in faces:
+    for F, (d, a, b, area, dist) in zip(fluxes, faces):
         ka, kb = perm[a], perm[b]
         tf = (area / dist) * 2.0 * ka * kb / (ka + kb)
         kf = kappa * area / dist
-        dp = p[a] - p[b]
-        a_up = (dp > 0) | ((dp == 0) & (a < b))
+        a_up = (F > 0) | ((F == 0) & (a < b))
         up = np.where(a_up, a, b)
         lam, lT, lz = _mobility(z[up], T[up])
         Tu, zu = T[up], z[up]
-        F = tf * lam * dp
+        # Darcy: F = tf lam (p_a - p_b); the derivatives follow from that law
         dF_dpa = tf * lam
         dF_dpb = -tf * lam
-        dF_dTu = tf * dp * lT
-        dF_dzu = tf * dp * lz
+        dF_dTu = F * lT / lam
+        dF_dzu = F * lz / lam
         m = a.shape[0]
         Da = np.zeros((m, 3, 3))   # d(flux a->b)/d(vars of a); rows mass, energy, CO2
         Db = np.zeros((m, 3, 3))
@@ -234,6 +264,21 @@ def cartesian(name, nx, ny, nz, *, seed, sigma, corr, n_wells, r_front,
         val7[b, 3] -= Db
         has7[a, s_ab] = True
         has7[b, s_ba] = True
+
+    # Open lateral boundaries: outflow leaves at the cell's own state.
+    bc, bF = _boundary_outflow(nx, ny, nz, wells)
+    keep = bF > 0
+    bc, bF = bc[keep], bF[keep]
+    lam, lT, lz = _mobility(z[bc], T[bc])
+    tb = (DY * DZ / DX) * perm[bc]      # x and y boundary faces share area/distance (DX = DY)
+    D = np.zeros((bc.shape[0], 3, 3))
+    dFdp, dFdT, dFdz = tb * lam, bF * lT / lam, bF * lz / lam
+    D[:, 0, 0], D[:, 0, 1], D[:, 0, 2] = dFdp, dFdT, dFdz
+    D[:, 1, 0] = CF * T[bc] * dFdp
+    D[:, 1, 1] = CF * T[bc] * dFdT + bF * CF
+    D[:, 1, 2] = CF * T[bc] * dFdz
+    D[:, 2, 0], D[:, 2, 1], D[:, 2, 2] = z[bc] * dFdp, z[bc] * dFdT, z[bc] * dFdz + bF
+    np.add.at(val7[:, 3], bc, D)
 
     # Column scaling (p in MPa) and row scaling by the mean accumulation diagonal.
     val7[:, :, :, 0] *= P_SCALE
@@ -297,6 +342,12 @@ def config3():
                      corr=10, n_wells=4, r_front=5.0, tol=1e-6)
 
 
+def config3_slab(nz):
+    """The 250x250x50 generator restricted to nz layers (bounded CPU samples)."""
+    return cartesian(f"grid250x250x{nz}", 250, 250, nz, seed=SEED_BASE + 3, sigma=1.5,
+                     corr=10, n_wells=4, r_front=5.0, tol=1e-6)
+
+
 def small(nx, ny, nz, seed=7, sigma=0.5, n_wells=1, r_front=2.0, **kw):
     """Tiny grids for pins and parity at oracle-friendly sizes."""
     return cartesian(f"grid{nx}x{ny}x{nz}", nx, ny, nz, seed=seed, sigma=sigma, corr=0,
@@ -308,6 +359,8 @@ def by_name(name: str) -> Case:
              "grid250x250x50": config3}
     if name in table:
         return table[name]()
+    if name.startswith("grid250x250x") and name != "grid250x250x50":
+        return config3_slab(int(name.split("x")[-1]))
     if name.startswith("grid100x100x20_pe"):
         return config1(float(name.split("_pe")[1]))
     if name.startswith("grid"):

@@ -1,0 +1,173 @@
+"""CPU tests of the HIP library: ABI surface, error paths and the host setup.
+
+The library's setup is an independent implementation; here it is built
+host-only (no device calls) and compared with the oracle: identical C/F
+splits level by level, interpolation and operators to rounding, and ILU(0)
+factors that reproduce A on its pattern and give the oracle's sweeps.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+import paper_2308_11892_amd as L
+from synth import jacobian as J
+
+
+def host_solver(c, **kw):
+    return L.Solver(c.row_ptr, c.col_idx, c.values, host_only=1, **kw)
+
+
+def test_library_exports_every_header_symbol():
+    lib = C.CDLL(L.LIB_PATH)
+    names = L.header_functions()
+    assert {"cptr_setup", "cptr_apply", "cptr_gmres_solve", "cptr_destroy"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_defaults_follow_the_paper():
+    o = L.setup_opts()
+    assert (o.strong_threshold, o.max_row_sum, o.max_levels, o.max_coarse, o.p_max_elmts) == \
+        (0.25, 0.9, 25, 9, 4)
+    s = L.solve_opts()
+    assert (s.max_iter, s.rtol, s.restart) == (200, 1e-6, 30)
+
+
+@pytest.mark.parametrize("case", ["grid20x20x5", "grid6x5x4", "grid12x1x1"])
+def test_host_setup_matches_oracle(case):
+    c = J.by_name(case) if case == "grid20x20x5" else J.by_name(case)
+    h = O.Cptr(c.row_ptr, c.col_idx, c.values)
+    s = host_solver(c)
+    rows, nnz = s.hierarchy()
+    a = h.amg
+    assert len(rows) == a.nlevels
+    # quasi-IMPES weights are the same division, bit for bit
+    W = s.export("W", 0, c.n_cells * 2)
+    assert np.array_equal(W, h.W().ravel())
+    for l in range(a.nlevels):
+        assert rows[l] == a.size(l)[0]
+        # the Galerkin products sum in a different order; cancellation on the
+        # coarsest levels amplifies that rounding, so compare per row against
+        # the row's absolute sum
+        Al, Ao = s.level_matrix(l, "A"), a.A(l)
+        assert Al.nnz == Ao.nnz
+        d = abs(Al - Ao).tocsr()
+        absrow = np.asarray(abs(Ao).sum(axis=1)).ravel()
+        assert (np.asarray(d.max(axis=1).todense()).ravel() / absrow).max() <= 1e-11, l
+        if l + 1 < a.nlevels:
+            assert np.array_equal(s.cf(l), a.cf(l)), f"C/F split differs at level {l}"
+            Pl, Po = s.level_matrix(l, "P"), a.P(l)
+            assert Pl.shape == Po.shape
+            assert abs(Pl - Po).max() <= 1e-12, l
+            dv = s.export("DINV", l, int(rows[l]))
+            np.testing.assert_allclose(dv, a.dinv(l), rtol=1e-14, atol=0)
+
+
+def _block_factors(c, F):
+    """Block L (unit block-lower) and U from the exported block factors."""
+    nb = c.n_cells
+    rows = np.repeat(np.arange(nb), np.diff(c.row_ptr))
+    cols = c.col_idx
+    low = cols < rows
+    Lb = sp.bsr_matrix((F[low], cols[low], np.concatenate([[0], np.cumsum(np.bincount(rows[low], minlength=nb))])),
+                       shape=(c.n_dof, c.n_dof)).toarray() + np.eye(c.n_dof)
+    up = ~low
+    Ub = sp.bsr_matrix((F[up], cols[up], np.concatenate([[0], np.cumsum(np.bincount(rows[up], minlength=nb))])),
+                       shape=(c.n_dof, c.n_dof)).toarray()
+    return Lb, Ub
+
+
+def test_host_block_ilu_is_ilu0():
+    c = J.small(5, 4, 3)
+    s = host_solver(c)
+    F = s.export("ILU_VALS", 0, c.nnzb * 9).reshape(c.nnzb, 3, 3)
+    Lb, Ub = _block_factors(c, F)
+    A = c.to_scipy().toarray()
+    mask = sp.bsr_matrix((np.ones_like(c.values), c.col_idx, c.row_ptr),
+                         shape=A.shape).toarray() > 0
+    assert np.abs((Lb @ Ub - A)[mask]).max() <= 1e-13 * np.abs(A).max()
+    # same preconditioner as the oracle's scalar ILU(0)
+    h = O.Cptr(c.row_ptr, c.col_idx, c.values)
+    r = np.random.default_rng(0).standard_normal(c.n_dof)
+    x = np.linalg.solve(Ub, np.linalg.solve(Lb, r))
+    assert np.linalg.norm(x - h.ilu_solve(r)) <= 1e-10 * np.linalg.norm(x)
+    nl = s.export("ILU_NLEVELS", 0, 2, np.int32)
+    assert tuple(nl) == (5 + 4 + 3 - 2, 5 + 4 + 3 - 2)
+
+
+def test_host_setup_cpr_split_matches_oracle():
+    c = J.small(6, 5, 3)
+    h = O.Cptr(c.row_ptr, c.col_idx, c.values, elliptic=(0,))
+    s = L.Solver(c.row_ptr, c.col_idx, c.values, elliptic=(0,), host_only=1)
+    W = s.export("W", 0, c.n_cells * 2)
+    # explicit 2x2 inverse here, elimination in the oracle: rounding-level differences
+    np.testing.assert_allclose(W, h.W().ravel(), rtol=1e-9, atol=1e-14 * np.abs(W).max())
+    rows, _ = s.hierarchy()
+    for l in range(len(rows) - 1):
+        assert np.array_equal(s.cf(l), h.amg.cf(l))
+
+
+# ----------------------------------------------------------------- errors
+def _expect(code, fn):
+    with pytest.raises(L.CptrError) as e:
+        fn()
+    assert e.value.code == code, str(e.value)
+    return str(e.value)
+
+
+def test_invalid_arguments():
+    c = J.small(3, 3, 2)
+    _expect(L.CPTR_E_INVALID, lambda: L.Solver(c.row_ptr, c.col_idx, c.values, elliptic=(0, 0), host_only=1))
+    _expect(L.CPTR_E_INVALID, lambda: L.Solver(c.row_ptr, c.col_idx, c.values, elliptic=(0, 3), host_only=1))
+    _expect(L.CPTR_E_INVALID, lambda: L.Solver(c.row_ptr, c.col_idx, c.values, elliptic=(0, 1, 2), host_only=1))
+    v = c.values.copy()
+    v[5, 1, 1] = np.nan
+    msg = _expect(L.CPTR_E_INVALID, lambda: L.Solver(c.row_ptr, c.col_idx, v, host_only=1))
+    assert "non-finite" in msg
+    ci = c.col_idx.copy()
+    ci[[0, 1]] = ci[[1, 0]]
+    msg = _expect(L.CPTR_E_INVALID, lambda: L.Solver(c.row_ptr, ci, c.values, host_only=1))
+    assert "row 0" in msg
+    # drop the diagonal block of row 4
+    k = [q for q in range(c.row_ptr[4], c.row_ptr[5]) if c.col_idx[q] == 4][0]
+    keep = np.ones(c.nnzb, bool)
+    keep[k] = False
+    rp = c.row_ptr.copy()
+    rp[5:] -= 1
+    msg = _expect(L.CPTR_E_INVALID, lambda: L.Solver(rp, c.col_idx[keep], c.values[keep], host_only=1))
+    assert "diagonal" in msg and "4" in msg
+
+
+def test_zero_pivot_errors():
+    c = J.small(3, 3, 2)
+    v = c.values.copy()
+    k = [q for q in range(c.row_ptr[2], c.row_ptr[3]) if c.col_idx[q] == 2][0]
+    v[k, 2, 2] = 0.0
+    v[k, 0:2, 2] = 0.0
+    v[k, 2, 0:2] = 0.0
+    # singular hyperbolic diagonal entry -> quasi-IMPES cannot form W
+    _expect(L.CPTR_E_ZERO_PIVOT, lambda: L.Solver(c.row_ptr, c.col_idx, v, host_only=1))
+    # with injection the same matrix fails in ILU(0) on the singular block
+    msg = _expect(L.CPTR_E_ZERO_PIVOT,
+                  lambda: L.Solver(c.row_ptr, c.col_idx, v, host_only=1, restriction=L.RESTRICT_INJECTION))
+    assert "ILU" in msg
+
+
+def test_host_only_handle_refuses_device_calls():
+    c = J.small(3, 3, 2)
+    s = host_solver(c)
+    x, y = np.zeros(c.n_dof), np.zeros(c.n_dof)
+    assert L.lib().cptr_apply(s._h, L._ptr(x), L._ptr(y), None) == L.CPTR_E_STATE
+    assert "host-only" in L.lib().cptr_last_error(s._h).decode()
+
+
+def test_coarsening_limit_reports_stall():
+    c = J.small(6, 6, 4)
+    # a two-level cap leaves a coarsest level far above the dense limit
+    # only when the limit is tiny; max_levels=1 puts all rows in the dense solve
+    s = L.Solver(c.row_ptr, c.col_idx, c.values, host_only=1, max_levels=1)
+    rows, _ = s.hierarchy()
+    assert len(rows) == 1 and rows[0] == 2 * c.n_cells

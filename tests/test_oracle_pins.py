@@ -508,7 +508,7 @@ def test_apply_is_two_stage_composition():
     A = dense(c)
     # componentwise rounding bound: eps-sized relative to |M1| + |M2| + |M2||A||M1|
     bound = np.abs(M1) + np.abs(M2) + np.abs(M2) @ np.abs(A) @ np.abs(M1)
-    assert np.all(np.abs(M - (M1 + M2 - M2 @ A @ M1)) <= 1e-13 * bound)
+    assert np.all(np.abs(M - (M1 + M2 - M2 @ A @ M1)) <= 1e-12 * bound)
     Ep = I - M @ A
     bound_e = I + np.abs(M) @ np.abs(A) + (I + np.abs(M2) @ np.abs(A)) @ (I + np.abs(M1) @ np.abs(A))
     assert np.all(np.abs(Ep - (I - M2 @ A) @ (I - M1 @ A)) <= 1e-13 * bound_e)
