@@ -79,7 +79,14 @@ typedef struct {
   int32_t host_only;         /* 1: build the hierarchy on the host only (for inspection
                                 through cptr_export; apply/solve return CPTR_E_STATE) */
   int32_t setup_threads;     /* host threads for setup; 0 = min(16, hardware threads) */
+  int32_t ilu_sweep;         /* CPTR_ILU_SWEEP_*: how the ILU(0) triangular solves run */
 } cptr_setup_opts;
+
+enum {
+  CPTR_ILU_SWEEP_AUTO = 0,     /* one launch per sweep when rows are narrow enough, else per level */
+  CPTR_ILU_SWEEP_LEVELS = 1,   /* one launch per dependency level */
+  CPTR_ILU_SWEEP_ONE_LAUNCH = 2 /* one launch per sweep; CPTR_E_INVALID if rows are too wide */
+};
 
 typedef struct {
   int32_t restart;           /* Krylov vectors per cycle, default 30 */
@@ -133,6 +140,15 @@ cptr_status cptr_gmres_solve(cptr_solver s, const double *b, double *x, const cp
 /* y = A x with the block SpMV kernel of the solve (Eq. 3 uses A in the
  * stage-two residual and GMRES applies it once per iteration). */
 cptr_status cptr_spmv(cptr_solver s, const double *x, double *y, void *stream);
+
+/* The two stages of Eq. (3) separately, asynchronous on `stream`:
+ *   cptr_stage1:    x1 = M1^-1 r = P_E Vcycle(R_QI r)  (Sec. 3 form of M1, one
+ *                   system-AMG V-cycle on the quasi-IMPES elliptic block);
+ *   cptr_ilu_solve: x = M2^-1 r = U^-1 L^-1 r with the ILU(0) factors (Sec. 3.1).
+ * Same conventions as cptr_apply (device FP64 vectors of length N, no aliasing,
+ * no allocation). */
+cptr_status cptr_stage1(cptr_solver s, const double *r, double *x1, void *stream);
+cptr_status cptr_ilu_solve(cptr_solver s, const double *r, double *x, void *stream);
 
 cptr_status cptr_destroy(cptr_solver s);
 

@@ -20,6 +20,7 @@ CPTR_OK, CPTR_NOT_CONVERGED = 0, 1
 CPTR_E_INVALID, CPTR_E_NOMEM, CPTR_E_ZERO_PIVOT = -1, -2, -3
 CPTR_E_SINGULAR_COARSE, CPTR_E_HIP, CPTR_E_STATE = -4, -5, -6
 RESTRICT_QUASI_IMPES, RESTRICT_INJECTION = 0, 1
+ILU_SWEEP_AUTO, ILU_SWEEP_LEVELS, ILU_SWEEP_ONE_LAUNCH = 0, 1, 2
 EXPORT = dict(CF=0, A_ROWPTR=1, A_COLS=2, A_VALS=3, P_ROWPTR=4, P_COLS=5, P_VALS=6, W=7,
               DINV=8, ILU_VALS=9, ILU_NLEVELS=10)
 PHASES = ["spmv", "restrict", "vcycle_l0", "vcycle_coarse", "stage2_resid", "ilu_fwd",
@@ -42,7 +43,8 @@ class cptr_setup_opts(C.Structure):
     _fields_ = [("strong_threshold", C.c_double), ("max_row_sum", C.c_double),
                 ("max_levels", C.c_int32), ("max_coarse", C.c_int32),
                 ("p_max_elmts", C.c_int32), ("restriction", C.c_int32),
-                ("host_only", C.c_int32), ("setup_threads", C.c_int32)]
+                ("host_only", C.c_int32), ("setup_threads", C.c_int32),
+                ("ilu_sweep", C.c_int32)]
 
 
 class cptr_solve_opts(C.Structure):
@@ -76,6 +78,10 @@ def lib():
         L.cptr_setup.restype = C.c_int
         L.cptr_apply.argtypes = [P, P, P, P]
         L.cptr_apply.restype = C.c_int
+        L.cptr_stage1.argtypes = [P, P, P, P]
+        L.cptr_stage1.restype = C.c_int
+        L.cptr_ilu_solve.argtypes = [P, P, P, P]
+        L.cptr_ilu_solve.restype = C.c_int
         L.cptr_spmv.argtypes = [P, P, P, P]
         L.cptr_spmv.restype = C.c_int
         L.cptr_gmres_solve.argtypes = [P, P, P, C.POINTER(cptr_solve_opts),
@@ -193,6 +199,12 @@ class Solver:
     # ---- hot path ----
     def apply(self, r, z, stream=None):
         _check(lib().cptr_apply(self._h, _ptr(r), _ptr(z), _stream(stream)), self._h)
+
+    def stage1(self, r, x1, stream=None):
+        _check(lib().cptr_stage1(self._h, _ptr(r), _ptr(x1), _stream(stream)), self._h)
+
+    def ilu_solve(self, r, x, stream=None):
+        _check(lib().cptr_ilu_solve(self._h, _ptr(r), _ptr(x), _stream(stream)), self._h)
 
     def spmv(self, x, y, stream=None):
         _check(lib().cptr_spmv(self._h, _ptr(x), _ptr(y), _stream(stream)), self._h)

@@ -30,6 +30,10 @@ namespace {
 thread_local std::string g_setup_error;
 
 constexpr int kMaxRestart = 64;
+// Rounds a wave of the one-launch sweeps polls before it gives up and raises
+// the wait-limit flag (seconds of waiting; never reached when the schedule is
+// valid).
+constexpr long kSweepSpinLimit = 1L << 22;
 constexpr int kPhases = 9;
 enum Phase { PH_SPMV = 0, PH_RESTRICT, PH_VC0, PH_VCC, PH_STAGE2, PH_ILU_F, PH_ILU_B, PH_ARNOLDI, PH_UPDATE };
 
@@ -90,6 +94,7 @@ struct DevVec {
 struct cptr_solver_s {
   HostSetup host;
   bool device = false;
+  int ilu_mode = CPTR_ILU_SWEEP_AUTO;
   std::string err;
   double setup_s = 0.0;
   int ne = 2;
@@ -103,6 +108,8 @@ struct cptr_solver_s {
   int32_t* bperm = nullptr;
   double* uinv = nullptr;
   std::vector<int32_t> flev_ptr, blev_ptr;
+  int sf_width = 0;          // register slots of the one-launch sweeps; 0 = per-level launches
+  int* tickets = nullptr;    // [2] workgroup ticket counters of the one-launch sweeps
   struct Lev {
     DCsr A, P, R;
     double* dinv = nullptr;
@@ -123,7 +130,8 @@ struct cptr_solver_s {
   int64_t ldv = 0;
   double *wr = nullptr, *wt = nullptr, *wu = nullptr;
   double* part = nullptr;
-  double* hdev = nullptr;   // [0,64): first CGS pass, [64,128): second, [128]: ||w||^2, [136]: scratch
+  double* hdev = nullptr;   // [0,64): first CGS pass, [64,128): second, [128]: ||w||^2,
+                            // [136]: scratch norm, [140]: sweep wait-limit flag
   double* hhost = nullptr;  // pinned copy
   // profiling
   bool profiling = false;
@@ -278,6 +286,15 @@ int build_device(cptr_solver s, hipStream_t st) {
         },
         -1);
     if ((rc = upload_sell(s, s->Ub, Uh, st))) return rc;
+    int maxw = 0;
+    for (int32_t sl = 0; sl < Lh.nslices; ++sl) maxw = std::max(maxw, Lh.sptr[sl + 1] - Lh.sptr[sl]);
+    for (int32_t sl = 0; sl < Uh.nslices; ++sl) maxw = std::max(maxw, Uh.sptr[sl + 1] - Uh.sptr[sl]);
+    const int w = ilu_sf_width(maxw);
+    if (s->ilu_mode == CPTR_ILU_SWEEP_ONE_LAUNCH && w == 0)
+      return fail(s, CPTR_E_INVALID, "rows too wide (" + std::to_string(maxw) + " blocks) for one-launch ILU sweeps");
+    s->sf_width = s->ilu_mode == CPTR_ILU_SWEEP_LEVELS ? 0 : w;
+    if ((rc = dalloc(s, s->tickets, 2))) return rc;
+    HIP_TRY(s, hipMemset(s->tickets, 0, 2 * sizeof(int)));
     const int64_t npad = (int64_t)Uh.nslices * kLanes;
     std::vector<double> ui((size_t)npad * 9, 0.0);
     for (int32_t p = 0; p < nb; ++p)
@@ -310,6 +327,7 @@ int build_device(cptr_solver s, hipStream_t st) {
   if ((rc = dalloc(s, s->r2, N)) || (rc = dalloc(s, s->y, N)) || (rc = dalloc(s, s->x2, N))) return rc;
   if ((rc = dalloc(s, s->part, (int64_t)kRedBlocks * (kMaxRestart + 2)))) return rc;
   if ((rc = dalloc(s, s->hdev, 256))) return rc;
+  HIP_TRY(s, hipMemset(s->hdev, 0, 256 * sizeof(double)));
   {
     void* hp = nullptr;
     HIP_TRY(s, hipHostMalloc(&hp, 256 * sizeof(double), hipHostMallocDefault));
@@ -346,7 +364,17 @@ void ph_harvest(cptr_solver s) {  // call after the stream is synchronised
 }
 
 // ---------------------------------------------------------------- apply
+// e0 = V-cycle(R_QI r) on the elliptic block (first stage without prolongation)
+void enqueue_stage1(cptr_solver s, const double* r, hipStream_t st);
+// z = P_E e0 + M2^-1 (r - A P_E e0); e0 == nullptr gives z = M2^-1 r
+void enqueue_stage2(cptr_solver s, const double* r, const double* e0, double* z, hipStream_t st);
+
 void enqueue_apply(cptr_solver s, const double* r, double* z, hipStream_t st) {
+  enqueue_stage1(s, r, st);
+  enqueue_stage2(s, r, s->lev[0].e, z, st);
+}
+
+void enqueue_stage1(cptr_solver s, const double* r, hipStream_t st) {
   const int ne = s->ne;
   const int L = (int)s->lev.size();
   auto& l0 = s->lev[0];
@@ -381,16 +409,44 @@ void enqueue_apply(cptr_solver s, const double* r, double* z, hipStream_t st) {
     launch_l0_post(s->Ahat, ne, l0.x, l0.b, l0.dinv, l0.e, st);
     ph_end(s, st, PH_VC0, ev);
   }
-  ph_begin(s, st, ev);
-  launch_stage2_resid(s->A, ne, s->eidx_h, l0.e, r, s->r2, st);
-  ph_end(s, st, PH_STAGE2, ev);
+}
+
+void enqueue_stage2(cptr_solver s, const double* r, const double* e0, double* z, hipStream_t st) {
+  const int ne = s->ne;
+  hipEvent_t ev;
+  const double* rhs = r;
+  if (s->sf_width > 0) {
+    ph_begin(s, st, ev);
+    if (e0) {
+      launch_stage2_resid_sf(s->A, ne, s->eidx_h, e0, r, s->r2, s->y, s->tickets, st);
+      rhs = s->r2;
+    } else {
+      launch_sweep_prepare(s->N, s->y, s->tickets, st);
+    }
+    ph_end(s, st, PH_STAGE2, ev);
+    ph_begin(s, st, ev);
+    launch_ilu_fwd_sf(s->Lf, s->sf_width, s->fperm, rhs, s->y, s->x2, s->tickets, s->hdev + 140,
+                      kSweepSpinLimit, st);
+    ph_end(s, st, PH_ILU_F, ev);
+    ph_begin(s, st, ev);
+    launch_ilu_bwd_sf(s->Ub, s->sf_width, s->bperm, s->uinv, s->y, e0, ne, s->eidx_h, s->x2, z,
+                      s->tickets, s->hdev + 140, kSweepSpinLimit, st);
+    ph_end(s, st, PH_ILU_B, ev);
+    return;
+  }
+  if (e0) {
+    ph_begin(s, st, ev);
+    launch_stage2_resid(s->A, ne, s->eidx_h, e0, r, s->r2, st);
+    ph_end(s, st, PH_STAGE2, ev);
+    rhs = s->r2;
+  }
   ph_begin(s, st, ev);
   for (size_t l = 0; l + 1 < s->flev_ptr.size(); ++l)
-    launch_ilu_fwd_level(s->Lf, s->fperm, s->flev_ptr[l], s->flev_ptr[l + 1], s->r2, s->y, st);
+    launch_ilu_fwd_level(s->Lf, s->fperm, s->flev_ptr[l], s->flev_ptr[l + 1], rhs, s->y, st);
   ph_end(s, st, PH_ILU_F, ev);
   ph_begin(s, st, ev);
   for (size_t l = 0; l + 1 < s->blev_ptr.size(); ++l)
-    launch_ilu_bwd_level(s->Ub, s->bperm, s->uinv, s->blev_ptr[l], s->blev_ptr[l + 1], s->y, l0.e, ne,
+    launch_ilu_bwd_level(s->Ub, s->bperm, s->uinv, s->blev_ptr[l], s->blev_ptr[l + 1], s->y, e0, ne,
                          s->eidx_h, s->x2, z, st);
   ph_end(s, st, PH_ILU_B, ev);
 }
@@ -455,6 +511,7 @@ void cptr_setup_opts_default(cptr_setup_opts* o) {
   o->restriction = CPTR_RESTRICT_QUASI_IMPES;
   o->host_only = 0;
   o->setup_threads = 0;
+  o->ilu_sweep = CPTR_ILU_SWEEP_AUTO;
 }
 
 void cptr_solve_opts_default(cptr_solve_opts* o) {
@@ -491,6 +548,8 @@ cptr_status cptr_setup(const cptr_bsr* A, int32_t block_size, const int32_t* ell
   cptr_setup_opts o;
   cptr_setup_opts_default(&o);
   if (opts) o = *opts;
+  if (o.ilu_sweep < 0 || o.ilu_sweep > 2)
+    return (cptr_status)fail(nullptr, CPTR_E_INVALID, "ilu_sweep must be 0, 1 or 2");
   if (o.max_levels < 1 || o.max_levels > 64 || o.max_coarse < 1 || o.p_max_elmts < 0 ||
       !(o.strong_threshold >= 0.0) || !(o.max_row_sum > 0.0))
     return (cptr_status)fail(nullptr, CPTR_E_INVALID, "setup options out of range");
@@ -552,6 +611,7 @@ cptr_status cptr_setup(const cptr_bsr* A, int32_t block_size, const int32_t* ell
     s->hidx_h[e] = s->host.hidx[e];
   }
   s->N = (int64_t)nb * 3;
+  s->ilu_mode = o.ilu_sweep;
   if (!o.host_only) {
     int dev_count = 0;
     hipError_t he = hipGetDeviceCount(&dev_count);
@@ -598,6 +658,29 @@ cptr_status cptr_apply(cptr_solver s, const double* r, double* z, void* stream) 
   enqueue_apply(s, r, z, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (cptr_status)hip_fail(s, e, "kernel launch in cptr_apply");
+  return CPTR_OK;
+}
+
+cptr_status cptr_stage1(cptr_solver s, const double* r, double* x1, void* stream) {
+  if (!s) return CPTR_E_INVALID;
+  if (!s->device) return (cptr_status)fail(s, CPTR_E_STATE, "handle was set up host-only");
+  if (!r || !x1 || r == x1) return (cptr_status)fail(s, CPTR_E_INVALID, "r and x1 must be distinct non-NULL device pointers");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  enqueue_stage1(s, r, st);
+  launch_prolong_e(s->host.nb, s->ne, s->eidx_h, s->lev[0].e, x1, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return (cptr_status)hip_fail(s, e, "kernel launch in cptr_stage1");
+  return CPTR_OK;
+}
+
+cptr_status cptr_ilu_solve(cptr_solver s, const double* r, double* x, void* stream) {
+  if (!s) return CPTR_E_INVALID;
+  if (!s->device) return (cptr_status)fail(s, CPTR_E_STATE, "handle was set up host-only");
+  if (!r || !x || r == x) return (cptr_status)fail(s, CPTR_E_INVALID, "r and x must be distinct non-NULL device pointers");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  enqueue_stage2(s, r, nullptr, x, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return (cptr_status)hip_fail(s, e, "kernel launch in cptr_ilu_solve");
   return CPTR_OK;
 }
 
@@ -685,13 +768,15 @@ cptr_status cptr_gmres_solve(cptr_solver s, const double* b, double* x, const cp
       launch_reduce(1, s->part, s->hdev + 128, 0, st);
       launch_scale(N, w, s->hdev + 128, w, st);
       ph_end(s, st, PH_ARNOLDI, ev);
-      HIP_TRY(s, hipMemcpyAsync(s->hhost, s->hdev, 136 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_TRY(s, hipMemcpyAsync(s->hhost, s->hdev, 144 * sizeof(double), hipMemcpyDeviceToHost, st));
       HIP_TRY(s, hipStreamSynchronize(st));
       {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return (cptr_status)hip_fail(s, e, "kernel launch in cptr_gmres_solve");
       }
       ph_harvest(s);
+      if (s->hhost[140] != 0.0)
+        return (cptr_status)fail(s, CPTR_E_HIP, "ILU sweep dependency wait exceeded its limit");
       for (int i = 0; i <= j; ++i) Hij(i, j) = s->hhost[i] + s->hhost[64 + i];
       const double hn = std::sqrt(std::max(0.0, s->hhost[128]));
       Hij(j + 1, j) = hn;

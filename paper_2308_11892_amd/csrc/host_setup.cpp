@@ -374,63 +374,60 @@ Csr extended_i_interp(const Csr& A, const Csr& S, const std::vector<int32_t>& cf
 }
 
 // ---------------------------------------------------------------------------
-// Galerkin product R A P, row by row of R, accumulating (r_Ii a_ik) p_kJ in a
-// small open-addressing table per row.
-static Csr galerkin(const Csr& R, const Csr& A, const Csr& P, int threads) {
-  const int32_t nc = R.n;
+// Sparse product C = X Y, rows in parallel.  Each output entry is accumulated
+// over the stored entries x_ik in increasing k (and, within row k of Y, in
+// stored order), starting from 0.0, in a small open-addressing table per row;
+// the Galerkin operator R A P is formed as R (A P).  With FP contraction off
+// this summation order fixes every coarse operator to the last bit, so the
+// strength tests of the next level see exactly the same numbers however the
+// rows are distributed over threads.
+static Csr spgemm(const Csr& X, const Csr& Y, int threads) {
+  const int32_t n = X.n;
   int nthreads = std::max(1, threads);
   struct Part {
     std::vector<int32_t> ci;
     std::vector<double> v;
   };
   std::vector<Part> parts(nthreads);
-  std::vector<int64_t> len(nc + 1, 0);
-  parallel_for(nthreads, nc, [&](int64_t lo, int64_t hi, int t) {
+  std::vector<int64_t> len(n + 1, 0);
+  parallel_for(nthreads, n, [&](int64_t lo, int64_t hi, int t) {
     std::vector<int32_t> keys(64, -1);
     std::vector<double> vals(64, 0.0);
     std::vector<int32_t> used;
-    auto insert = [&](int32_t col, double x) {
-      uint32_t mask = (uint32_t)keys.size() - 1;
-      uint32_t h = ((uint32_t)col * 2654435761u) & mask;
-      while (keys[h] != -1 && keys[h] != col) h = (h + 1) & mask;
-      if (keys[h] == -1) {
-        keys[h] = col;
-        vals[h] = 0.0;
-        used.push_back((int32_t)h);
-      }
-      vals[h] += x;
-    };
     std::vector<std::pair<int32_t, double>> row;
-    for (int64_t I = lo; I < hi; ++I) {
-      // size the table for this row's upper bound on distinct columns
+    for (int64_t i = lo; i < hi; ++i) {
       int64_t bound = 0;
-      for (int64_t q = R.rp[I]; q < R.rp[I + 1]; ++q) {
-        const int32_t i = R.ci[q];
-        for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) bound += P.rp[A.ci[k] + 1] - P.rp[A.ci[k]];
-      }
+      for (int64_t q = X.rp[i]; q < X.rp[i + 1]; ++q) bound += Y.rp[X.ci[q] + 1] - Y.rp[X.ci[q]];
       size_t want = 64;
       while ((int64_t)want < 2 * bound) want <<= 1;
       if (want > keys.size()) {
         keys.assign(want, -1);
         vals.assign(want, 0.0);
       }
+      const uint32_t mask = (uint32_t)keys.size() - 1;
       used.clear();
-      for (int64_t q = R.rp[I]; q < R.rp[I + 1]; ++q) {
-        const int32_t i = R.ci[q];
-        const double rv = R.v[q];
-        for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
-          const int32_t kk = A.ci[k];
-          const double ra = rv * A.v[k];
-          for (int64_t p = P.rp[kk]; p < P.rp[kk + 1]; ++p) insert(P.ci[p], ra * P.v[p]);
+      for (int64_t q = X.rp[i]; q < X.rp[i + 1]; ++q) {
+        const int32_t k = X.ci[q];
+        const double xik = X.v[q];
+        for (int64_t p = Y.rp[k]; p < Y.rp[k + 1]; ++p) {
+          const int32_t col = Y.ci[p];
+          uint32_t hsh = ((uint32_t)col * 2654435761u) & mask;
+          while (keys[hsh] != -1 && keys[hsh] != col) hsh = (hsh + 1) & mask;
+          if (keys[hsh] == -1) {
+            keys[hsh] = col;
+            vals[hsh] = 0.0;
+            used.push_back((int32_t)hsh);
+          }
+          vals[hsh] += xik * Y.v[p];
         }
       }
       row.clear();
-      for (int32_t h : used) {
-        row.emplace_back(keys[h], vals[h]);
-        keys[h] = -1;
+      for (int32_t hh : used) {
+        row.emplace_back(keys[hh], vals[hh]);
+        keys[hh] = -1;
       }
       std::sort(row.begin(), row.end());
-      len[I + 1] = (int64_t)row.size();
+      len[i + 1] = (int64_t)row.size();
       for (auto& e : row) {
         parts[t].ci.push_back(e.first);
         parts[t].v.push_back(e.second);
@@ -438,16 +435,22 @@ static Csr galerkin(const Csr& R, const Csr& A, const Csr& P, int threads) {
     }
   });
   Csr C;
-  C.n = C.m = nc;
-  C.rp.assign(nc + 1, 0);
-  for (int32_t I = 0; I < nc; ++I) C.rp[I + 1] = C.rp[I] + len[I + 1];
-  C.ci.reserve(C.rp[nc]);
-  C.v.reserve(C.rp[nc]);
+  C.n = n;
+  C.m = Y.m;
+  C.rp.assign(n + 1, 0);
+  for (int32_t i = 0; i < n; ++i) C.rp[i + 1] = C.rp[i] + len[i + 1];
+  C.ci.reserve(C.rp[n]);
+  C.v.reserve(C.rp[n]);
   for (auto& part : parts) {
     C.ci.insert(C.ci.end(), part.ci.begin(), part.ci.end());
     C.v.insert(C.v.end(), part.v.begin(), part.v.end());
   }
   return C;
+}
+
+static Csr galerkin(const Csr& R, const Csr& A, const Csr& P, int threads) {
+  Csr AP = spgemm(A, P, threads);
+  return spgemm(R, AP, threads);
 }
 
 // l1-Jacobi (point blocks): d_i = a_ii + sign(a_ii) sum_{j != i} |a_ij|.

@@ -337,12 +337,282 @@ __global__ __launch_bounds__(kBlock) void k_ilu_bwd(int p0, int p1, int npad, co
   x2[3 * (size_t)i] = o0;
   x2[3 * (size_t)i + 1] = o1;
   x2[3 * (size_t)i + 2] = o2;
-  // z = x1 + x2 with x1[E] = e0 and x1[H] = 0
-  const double ex = e0[(size_t)i * NE];
-  const double ey = NE == 2 ? e0[(size_t)i * NE + 1] : 0.0;
+  // z = x1 + x2 with x1[E] = e0 and x1[H] = 0 (e0 == nullptr: x1 = 0)
+  const double ex = e0 ? e0[(size_t)i * NE] : 0.0;
+  const double ey = (NE == 2 && e0) ? e0[(size_t)i * NE + 1] : 0.0;
   z[3 * (size_t)i] = o0 + (ea == 0 ? ex : 0.0) + (NE == 2 && eb == 0 ? ey : 0.0);
   z[3 * (size_t)i + 1] = o1 + (ea == 1 ? ex : 0.0) + (NE == 2 && eb == 1 ? ey : 0.0);
   z[3 * (size_t)i + 2] = o2 + (ea == 2 ? ex : 0.0) + (NE == 2 && eb == 2 ? ey : 0.0);
+}
+
+// --------------------------------------------------------------------------
+// ILU(0) sweeps in one launch each, without level barriers.
+//
+// A row may start as soon as the rows it depends on are written.  Readiness is
+// carried by the solution vector itself: the kernel that runs before a sweep
+// fills the sweep's output with a sentinel NaN pattern, rows are published
+// with device-coherent (sc1) stores and dependencies are polled with
+// device-coherent loads until no sentinel is left.  Arithmetic never yields
+// this payload (NaNs produced by arithmetic are the canonical quiet NaN), so
+// a published value can not be mistaken for "not ready".
+//
+// Deadlock freedom: positions are sorted by dependency level, so every
+// dependency sits at a lower position.  Each workgroup takes its block of
+// positions from a ticket counter when it starts, hence it only waits on
+// workgroups that started before it (resident or finished).  Inside a wave
+// the lanes retry until every lane is done, so lanes waiting on lower lanes
+// of the same wave do not block them.  Every wait is bounded: after
+// `spin_limit` rounds the wave records an error flag and exits.
+constexpr unsigned long long kSentinel = 0x7FF4C0DE5E1F0BADull;
+
+__device__ __forceinline__ double ld_dev(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool is_sent(double v) {
+  return (unsigned long long)__double_as_longlong(v) == kSentinel;
+}
+
+__device__ __forceinline__ int take_ticket(int* ctr) {
+  __shared__ int s_ticket;
+  if (threadIdx.x == 0) s_ticket = __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  return s_ticket;
+}
+
+// Forward sweep y = L^-1 r2 (unit block-lower L).  Also fills x2 with the
+// sentinel for the backward sweep and resets the backward ticket counter.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_ilu_fwd_sf(int npos, const int32_t* __restrict__ sptr,
+                                                       const int32_t* __restrict__ col,
+                                                       const double* __restrict__ val,
+                                                       const int32_t* __restrict__ perm,
+                                                       const double* __restrict__ r2, double* y,
+                                                       double* x2, int* tickets, double* err,
+                                                       long spin_limit) {
+  const int blk = take_ticket(tickets);
+  const int p = blk * kBlock + threadIdx.x;
+  const bool active = p < npos;
+  if (blk == 0 && threadIdx.x == 0) tickets[1] = 0;  // backward counter: used after this kernel
+  int i = 0;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  int c[W];
+  double Lv[W][9];
+  double yv[W][3];
+  unsigned need = 0;
+  if (active) {
+    i = perm[p];
+    a0 = r2[3 * (size_t)i];
+    a1 = r2[3 * (size_t)i + 1];
+    a2 = r2[3 * (size_t)i + 2];
+    const int s = p >> 6, lane = p & 63;
+    const int k0 = sptr[s], w = sptr[s + 1] - k0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      c[k] = -1;
+      if (k < w) {
+        c[k] = col[(size_t)(k0 + k) * 64 + lane];
+        const double* v = val + (size_t)(k0 + k) * 9 * 64 + lane;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) Lv[k][e] = v[e * 64];
+      }
+      if (c[k] >= 0) need |= 1u << k;
+    }
+    const double s0 = __longlong_as_double((long long)kSentinel);
+    x2[3 * (size_t)i] = s0;
+    x2[3 * (size_t)i + 1] = s0;
+    x2[3 * (size_t)i + 2] = s0;
+  }
+  bool done = !active;
+  for (long spin = 0;; ++spin) {
+    if (!done) {
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        if (need & (1u << k)) {
+          const double* q = y + 3 * (size_t)c[k];
+          const double u0 = ld_dev(q), u1 = ld_dev(q + 1), u2 = ld_dev(q + 2);
+          if (!is_sent(u0) && !is_sent(u1) && !is_sent(u2)) {
+            yv[k][0] = u0;
+            yv[k][1] = u1;
+            yv[k][2] = u2;
+            need &= ~(1u << k);
+          }
+        }
+      }
+      if (need == 0) {
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+          if (c[k] < 0) continue;
+          a0 -= Lv[k][0] * yv[k][0] + Lv[k][1] * yv[k][1] + Lv[k][2] * yv[k][2];
+          a1 -= Lv[k][3] * yv[k][0] + Lv[k][4] * yv[k][1] + Lv[k][5] * yv[k][2];
+          a2 -= Lv[k][6] * yv[k][0] + Lv[k][7] * yv[k][1] + Lv[k][8] * yv[k][2];
+        }
+        st_dev(y + 3 * (size_t)i, a0);
+        st_dev(y + 3 * (size_t)i + 1, a1);
+        st_dev(y + 3 * (size_t)i + 2, a2);
+        done = true;
+      }
+    }
+    if (__all(done)) break;
+    if (spin >= spin_limit) {
+      st_dev(err, 1.0);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+// Backward sweep x2 = U^-1 y with U_ii^-1 stored per position, and z = x1 + x2.
+template <int W, int NE>
+__global__ __launch_bounds__(kBlock) void k_ilu_bwd_sf(int npos, int npad, const int32_t* __restrict__ sptr,
+                                                       const int32_t* __restrict__ col,
+                                                       const double* __restrict__ val,
+                                                       const int32_t* __restrict__ perm,
+                                                       const double* __restrict__ uinv,
+                                                       const double* y, const double* __restrict__ e0,
+                                                       int ea, int eb, double* x2,
+                                                       double* __restrict__ z, int* tickets,
+                                                       double* err, long spin_limit) {
+  const int blk = take_ticket(tickets + 1);
+  const int p = blk * kBlock + threadIdx.x;
+  const bool active = p < npos;
+  int i = 0;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  int c[W];
+  double Uv[W][9];
+  double xv[W][3];
+  unsigned need = 0;
+  if (active) {
+    i = perm[p];
+    a0 = ld_dev(y + 3 * (size_t)i);
+    a1 = ld_dev(y + 3 * (size_t)i + 1);
+    a2 = ld_dev(y + 3 * (size_t)i + 2);
+    const int s = p >> 6, lane = p & 63;
+    const int k0 = sptr[s], w = sptr[s + 1] - k0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      c[k] = -1;
+      if (k < w) {
+        c[k] = col[(size_t)(k0 + k) * 64 + lane];
+        const double* v = val + (size_t)(k0 + k) * 9 * 64 + lane;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) Uv[k][e] = v[e * 64];
+      }
+      if (c[k] >= 0) need |= 1u << k;
+    }
+  }
+  bool done = !active;
+  for (long spin = 0;; ++spin) {
+    if (!done) {
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        if (need & (1u << k)) {
+          const double* q = x2 + 3 * (size_t)c[k];
+          const double u0 = ld_dev(q), u1 = ld_dev(q + 1), u2 = ld_dev(q + 2);
+          if (!is_sent(u0) && !is_sent(u1) && !is_sent(u2)) {
+            xv[k][0] = u0;
+            xv[k][1] = u1;
+            xv[k][2] = u2;
+            need &= ~(1u << k);
+          }
+        }
+      }
+      if (need == 0) {
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+          if (c[k] < 0) continue;
+          a0 -= Uv[k][0] * xv[k][0] + Uv[k][1] * xv[k][1] + Uv[k][2] * xv[k][2];
+          a1 -= Uv[k][3] * xv[k][0] + Uv[k][4] * xv[k][1] + Uv[k][5] * xv[k][2];
+          a2 -= Uv[k][6] * xv[k][0] + Uv[k][7] * xv[k][1] + Uv[k][8] * xv[k][2];
+        }
+        const double* u = uinv + p;
+        const double o0 = u[0] * a0 + u[(size_t)npad] * a1 + u[2 * (size_t)npad] * a2;
+        const double o1 = u[3 * (size_t)npad] * a0 + u[4 * (size_t)npad] * a1 + u[5 * (size_t)npad] * a2;
+        const double o2 = u[6 * (size_t)npad] * a0 + u[7 * (size_t)npad] * a1 + u[8 * (size_t)npad] * a2;
+        st_dev(x2 + 3 * (size_t)i, o0);
+        st_dev(x2 + 3 * (size_t)i + 1, o1);
+        st_dev(x2 + 3 * (size_t)i + 2, o2);
+        const double ex = e0 ? e0[(size_t)i * NE] : 0.0;
+        const double ey = (NE == 2 && e0) ? e0[(size_t)i * NE + 1] : 0.0;
+        z[3 * (size_t)i] = o0 + (ea == 0 ? ex : 0.0) + (NE == 2 && eb == 0 ? ey : 0.0);
+        z[3 * (size_t)i + 1] = o1 + (ea == 1 ? ex : 0.0) + (NE == 2 && eb == 1 ? ey : 0.0);
+        z[3 * (size_t)i + 2] = o2 + (ea == 2 ? ex : 0.0) + (NE == 2 && eb == 2 ? ey : 0.0);
+        done = true;
+      }
+    }
+    if (__all(done)) break;
+    if (spin >= spin_limit) {
+      st_dev(err, 1.0);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+
+// --------------------------------------------------------------------------
+// x1 = P_E e0: elliptic unknowns from e0, hyperbolic unknowns zero
+template <int NE>
+__global__ __launch_bounds__(kBlock) void k_prolong_e(int nrows, const double* __restrict__ e0, int ea,
+                                                      int eb, double* __restrict__ x1) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nrows) return;
+  double o[3] = {0.0, 0.0, 0.0};
+  const double ex = e0[(size_t)i * NE];
+  const double ey = NE == 2 ? e0[(size_t)i * NE + 1] : 0.0;
+  x1[3 * (size_t)i] = (ea == 0 ? ex : 0.0) + (NE == 2 && eb == 0 ? ey : 0.0) + o[0];
+  x1[3 * (size_t)i + 1] = (ea == 1 ? ex : 0.0) + (NE == 2 && eb == 1 ? ey : 0.0) + o[1];
+  x1[3 * (size_t)i + 2] = (ea == 2 ? ex : 0.0) + (NE == 2 && eb == 2 ? ey : 0.0) + o[2];
+}
+
+// prepares a one-launch forward sweep on an arbitrary right-hand side:
+// y := sentinel, forward ticket counter := 0
+__global__ __launch_bounds__(kBlock) void k_sweep_prepare(int64_t n, double* __restrict__ y, int* tickets) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i == 0) tickets[0] = 0;
+  if (i < n) y[i] = __longlong_as_double((long long)kSentinel);
+}
+
+// stage-two residual that also prepares the forward sweep: y := sentinel and
+// the forward ticket counter := 0
+template <int NE>
+__global__ __launch_bounds__(kBlock) void k_stage2_resid_sf(int nrows, int nblk, const int32_t* __restrict__ sptr,
+                                                            const int32_t* __restrict__ col,
+                                                            const double* __restrict__ val, int ea,
+                                                            int eb, const double* __restrict__ e0,
+                                                            const double* __restrict__ r,
+                                                            double* __restrict__ r2,
+                                                            double* __restrict__ y, int* tickets) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) tickets[0] = 0;
+  const int row = xcd_block(blockIdx.x, nblk) * kBlock + threadIdx.x;
+  if (row >= nrows) return;
+  const int s = row >> 6, lane = row & 63;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int k = sptr[s]; k < sptr[s + 1]; ++k) {
+    const int c = col[(size_t)k * 64 + lane];
+    const double* v = val + (size_t)k * 9 * 64 + lane;
+    const double u = e0[(size_t)c * NE];
+    a0 += v[(0 * 3 + ea) * 64] * u;
+    a1 += v[(1 * 3 + ea) * 64] * u;
+    a2 += v[(2 * 3 + ea) * 64] * u;
+    if (NE == 2) {
+      const double w = e0[(size_t)c * NE + 1];
+      a0 += v[(0 * 3 + eb) * 64] * w;
+      a1 += v[(1 * 3 + eb) * 64] * w;
+      a2 += v[(2 * 3 + eb) * 64] * w;
+    }
+  }
+  const double* ri = r + 3 * (size_t)row;
+  double* o = r2 + 3 * (size_t)row;
+  o[0] = ri[0] - a0;
+  o[1] = ri[1] - a1;
+  o[2] = ri[2] - a2;
+  const double s0 = __longlong_as_double((long long)kSentinel);
+  y[3 * (size_t)row] = s0;
+  y[3 * (size_t)row + 1] = s0;
+  y[3 * (size_t)row + 2] = s0;
 }
 
 // --------------------------------------------------------------------------
@@ -569,6 +839,58 @@ void launch_ilu_bwd_level(const Sell& U, const int32_t* perm, const double* uinv
   else
     k_ilu_bwd<1><<<g, kBlock, 0, st>>>(p0, p1, npad, U.sptr, U.col, U.val, perm, uinv, y, e0,
                                        eidx[0], 0, x2, z);
+}
+
+
+void launch_stage2_resid_sf(const Sell& A, int ne, const int32_t* eidx, const double* e0,
+                            const double* r, double* r2, double* y, int* tickets, hipStream_t st) {
+  const int g = nblocks(A.nrows, kBlock);
+  if (ne == 2)
+    k_stage2_resid_sf<2><<<g, kBlock, 0, st>>>(A.nrows, g, A.sptr, A.col, A.val, eidx[0], eidx[1], e0, r, r2, y, tickets);
+  else
+    k_stage2_resid_sf<1><<<g, kBlock, 0, st>>>(A.nrows, g, A.sptr, A.col, A.val, eidx[0], 0, e0, r, r2, y, tickets);
+}
+
+
+void launch_prolong_e(int32_t nrows, int ne, const int32_t* eidx, const double* e0, double* x1,
+                      hipStream_t st) {
+  const int g = nblocks(nrows, kBlock);
+  if (ne == 2) k_prolong_e<2><<<g, kBlock, 0, st>>>(nrows, e0, eidx[0], eidx[1], x1);
+  else k_prolong_e<1><<<g, kBlock, 0, st>>>(nrows, e0, eidx[0], 0, x1);
+}
+void launch_sweep_prepare(int64_t n, double* y, int* tickets, hipStream_t st) {
+  k_sweep_prepare<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, y, tickets);
+}
+
+int ilu_sf_width(int max_width) {
+  if (max_width <= 4) return 4;
+  if (max_width <= 8) return 8;
+  if (max_width <= 16) return 16;
+  return 0;
+}
+
+void launch_ilu_fwd_sf(const Sell& L, int width, const int32_t* perm, const double* r2, double* y,
+                       double* x2, int* tickets, double* err, long spin_limit, hipStream_t st) {
+  const int g = nblocks(L.nrows, kBlock);
+  switch (width) {
+    case 4: k_ilu_fwd_sf<4><<<g, kBlock, 0, st>>>(L.nrows, L.sptr, L.col, L.val, perm, r2, y, x2, tickets, err, spin_limit); break;
+    case 8: k_ilu_fwd_sf<8><<<g, kBlock, 0, st>>>(L.nrows, L.sptr, L.col, L.val, perm, r2, y, x2, tickets, err, spin_limit); break;
+    default: k_ilu_fwd_sf<16><<<g, kBlock, 0, st>>>(L.nrows, L.sptr, L.col, L.val, perm, r2, y, x2, tickets, err, spin_limit); break;
+  }
+}
+
+void launch_ilu_bwd_sf(const Sell& U, int width, const int32_t* perm, const double* uinv,
+                       const double* y, const double* e0, int ne, const int32_t* eidx, double* x2,
+                       double* z, int* tickets, double* err, long spin_limit, hipStream_t st) {
+  const int g = nblocks(U.nrows, kBlock);
+  const int npad = U.nslices * 64;
+#define BWD(WW, NN) k_ilu_bwd_sf<WW, NN><<<g, kBlock, 0, st>>>(U.nrows, npad, U.sptr, U.col, U.val, perm, uinv, y, e0, eidx[0], NN == 2 ? eidx[1] : 0, x2, z, tickets, err, spin_limit)
+  if (ne == 2) {
+    if (width == 4) BWD(4, 2); else if (width == 8) BWD(8, 2); else BWD(16, 2);
+  } else {
+    if (width == 4) BWD(4, 1); else if (width == 8) BWD(8, 1); else BWD(16, 1);
+  }
+#undef BWD
 }
 
 #define MAXV_DISPATCH(KERNEL, nv, ...)                                                     \

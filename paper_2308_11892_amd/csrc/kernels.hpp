@@ -61,6 +61,20 @@ void launch_ilu_bwd_level(const Sell& U, const int32_t* perm, const double* uinv
                           int32_t p1, const double* y, const double* e0, int ne,
                           const int32_t* eidx, double* x2, double* z, hipStream_t st);
 
+// one-launch ILU sweeps (see kernels.hip); width = register slots per row
+int ilu_sf_width(int max_width);  // 0 when the rows are too wide for the one-launch kernels
+void launch_stage2_resid_sf(const Sell& A, int ne, const int32_t* eidx, const double* e0,
+                            const double* r, double* r2, double* y, int* tickets, hipStream_t st);
+void launch_ilu_fwd_sf(const Sell& L, int width, const int32_t* perm, const double* r2, double* y,
+                       double* x2, int* tickets, double* err, long spin_limit, hipStream_t st);
+void launch_ilu_bwd_sf(const Sell& U, int width, const int32_t* perm, const double* uinv,
+                       const double* y, const double* e0, int ne, const int32_t* eidx, double* x2,
+                       double* z, int* tickets, double* err, long spin_limit, hipStream_t st);
+
+void launch_prolong_e(int32_t nrows, int ne, const int32_t* eidx, const double* e0, double* x1,
+                      hipStream_t st);
+void launch_sweep_prepare(int64_t n, double* y, int* tickets, hipStream_t st);
+
 // Arnoldi / BLAS-1 (deterministic two-stage reductions into `part`)
 void launch_mdot(int64_t n, int nv, const double* V, int64_t ldv, const double* w, double* part,
                  hipStream_t st);
