@@ -83,9 +83,13 @@ typedef struct {
 } cptr_setup_opts;
 
 enum {
-  CPTR_ILU_SWEEP_AUTO = 0,     /* one launch per sweep when rows are narrow enough, else per level */
-  CPTR_ILU_SWEEP_LEVELS = 1,   /* one launch per dependency level */
-  CPTR_ILU_SWEEP_ONE_LAUNCH = 2 /* one launch per sweep; CPTR_E_INVALID if rows are too wide */
+  CPTR_ILU_SWEEP_AUTO = 0,      /* GRID when A is a 7-point lexicographic stencil, else
+                                   ONE_LAUNCH when rows are narrow enough, else LEVELS */
+  CPTR_ILU_SWEEP_LEVELS = 1,    /* one launch per dependency level */
+  CPTR_ILU_SWEEP_ONE_LAUNCH = 2, /* one launch per sweep, rows published as they finish;
+                                   CPTR_E_INVALID if rows are too wide */
+  CPTR_ILU_SWEEP_GRID = 3       /* tiled sweeps over x-pencils of an nx*ny*nz grid (7-point
+                                   stencil, x fastest); CPTR_E_INVALID for other patterns */
 };
 
 typedef struct {
@@ -175,7 +179,9 @@ enum {
   CPTR_EXPORT_ILU_VALS = 9,  /* double[nnz_blocks * 9]: L below the diagonal
                                 (unit diagonal blocks implied), U on and above,
                                 with the diagonal blocks stored as U_ii (not inverted) */
-  CPTR_EXPORT_ILU_NLEVELS = 10 /* int32[2]: forward and backward dependency levels */
+  CPTR_EXPORT_ILU_NLEVELS = 10, /* int32[2]: forward and backward dependency levels */
+  CPTR_EXPORT_SWEEP = 11       /* int32[4]: ILU sweep schedule in use (CPTR_ILU_SWEEP_*),
+                                  then nx, ny, nz of the detected grid (0 if none) */
 };
 /* Copy one piece of the setup into host_buf (bytes = its capacity). */
 cptr_status cptr_export(cptr_solver s, int32_t what, int32_t level, void *host_buf, int64_t bytes);

@@ -109,6 +109,10 @@ struct cptr_solver_s {
   double* uinv = nullptr;
   std::vector<int32_t> flev_ptr, blev_ptr;
   int sf_width = 0;          // register slots of the one-launch sweeps; 0 = per-level launches
+  int grid[3] = {0, 0, 0};   // nx, ny, nz when A is a 7-point stencil in lexicographic order
+  bool use_grid = false;     // tiled systolic sweeps on that grid
+  double* Lg = nullptr;      // [cell][27]: L blocks (-x, -y, -z)
+  double* Ug = nullptr;      // [cell][36]: U blocks (+x, +y, +z), U_ii^-1
   int* tickets = nullptr;    // [2] workgroup ticket counters of the one-launch sweeps
   struct Lev {
     DCsr A, P, R;
@@ -218,6 +222,62 @@ int upload_csr(cptr_solver s, DCsr& d, const Csr& h, hipStream_t st) {
   return CPTR_OK;
 }
 
+// Is A's block pattern exactly the 7-point stencil of an nx*ny*nz grid in
+// lexicographic order (x fastest)?  Requires nx, ny, nz >= 2.
+bool detect_grid(const HostSetup& h, int dims[3]) {
+  const int32_t nb = h.nb;
+  if (h.rp[1] - h.rp[0] != 4) return false;  // corner cell: itself, +x, +y, +z
+  const int32_t nx = h.ci[h.rp[0] + 1] == 1 ? h.ci[h.rp[0] + 2] : 0;
+  const int32_t nxy = h.ci[h.rp[0] + 3];
+  if (h.ci[h.rp[0]] != 0 || h.ci[h.rp[0] + 1] != 1 || nx < 2 || nxy % nx != 0 || nxy / nx < 2) return false;
+  if (nb % nxy != 0 || nb / nxy < 2) return false;
+  const int32_t ny = nxy / nx, nz = nb / nxy;
+  for (int32_t c = 0; c < nb; ++c) {
+    const int32_t x = c % nx, yy = (c / nx) % ny, zz = c / nxy;
+    int32_t want[7], m = 0;
+    if (zz > 0) want[m++] = c - nxy;
+    if (yy > 0) want[m++] = c - nx;
+    if (x > 0) want[m++] = c - 1;
+    want[m++] = c;
+    if (x < nx - 1) want[m++] = c + 1;
+    if (yy < ny - 1) want[m++] = c + nx;
+    if (zz < nz - 1) want[m++] = c + nxy;
+    if (h.rp[c + 1] - h.rp[c] != m) return false;
+    for (int q = 0; q < m; ++q)
+      if (h.ci[h.rp[c] + q] != want[q]) return false;
+  }
+  dims[0] = nx;
+  dims[1] = ny;
+  dims[2] = nz;
+  return true;
+}
+
+int build_grid_factors(cptr_solver s, hipStream_t st) {
+  const HostSetup& h = s->host;
+  const int32_t nb = h.nb;
+  const int32_t nx = s->grid[0], nxy = s->grid[0] * s->grid[1];
+  std::vector<double> lg((size_t)nb * 27, 0.0), ug((size_t)nb * 36, 0.0);
+  for (int32_t c = 0; c < nb; ++c) {
+    for (int32_t q = h.rp[c]; q < h.rp[c + 1]; ++q) {
+      const int32_t d = h.ci[q] - c;
+      int slot = -1;
+      double* dst = nullptr;
+      if (d == -1) slot = 0, dst = &lg[(size_t)c * 27];
+      else if (d == -nx) slot = 1, dst = &lg[(size_t)c * 27];
+      else if (d == -nxy) slot = 2, dst = &lg[(size_t)c * 27];
+      else if (d == 1) slot = 0, dst = &ug[(size_t)c * 36];
+      else if (d == nx) slot = 1, dst = &ug[(size_t)c * 36];
+      else if (d == nxy) slot = 2, dst = &ug[(size_t)c * 36];
+      if (dst) std::memcpy(dst + 9 * slot, &h.ilu[(size_t)q * 9], 9 * sizeof(double));
+    }
+    std::memcpy(&ug[(size_t)c * 36 + 27], &h.uinv[(size_t)c * 9], 9 * sizeof(double));
+  }
+  int rc;
+  if ((rc = upload(s, s->Lg, lg.data(), (int64_t)lg.size(), st))) return rc;
+  if ((rc = upload(s, s->Ug, ug.data(), (int64_t)ug.size(), st))) return rc;
+  return CPTR_OK;
+}
+
 int build_device(cptr_solver s, hipStream_t st) {
   const HostSetup& h = s->host;
   const int32_t nb = h.nb;
@@ -295,6 +355,11 @@ int build_device(cptr_solver s, hipStream_t st) {
     s->sf_width = s->ilu_mode == CPTR_ILU_SWEEP_LEVELS ? 0 : w;
     if ((rc = dalloc(s, s->tickets, 2))) return rc;
     HIP_TRY(s, hipMemset(s->tickets, 0, 2 * sizeof(int)));
+    const bool grid = detect_grid(h, s->grid);
+    if (s->ilu_mode == CPTR_ILU_SWEEP_GRID && !grid)
+      return fail(s, CPTR_E_INVALID, "ilu_sweep = GRID needs a 7-point stencil in lexicographic order");
+    s->use_grid = grid && (s->ilu_mode == CPTR_ILU_SWEEP_AUTO || s->ilu_mode == CPTR_ILU_SWEEP_GRID);
+    if (s->use_grid && (rc = build_grid_factors(s, st))) return rc;
     const int64_t npad = (int64_t)Uh.nslices * kLanes;
     std::vector<double> ui((size_t)npad * 9, 0.0);
     for (int32_t p = 0; p < nb; ++p)
@@ -415,15 +480,26 @@ void enqueue_stage2(cptr_solver s, const double* r, const double* e0, double* z,
   const int ne = s->ne;
   hipEvent_t ev;
   const double* rhs = r;
-  if (s->sf_width > 0) {
+  if (s->use_grid || s->sf_width > 0) {
     ph_begin(s, st, ev);
     if (e0) {
-      launch_stage2_resid_sf(s->A, ne, s->eidx_h, e0, r, s->r2, s->y, s->tickets, st);
+      launch_stage2_resid_sf(s->A, ne, s->eidx_h, e0, r, s->r2, s->y, s->x2, s->tickets, st);
       rhs = s->r2;
     } else {
-      launch_sweep_prepare(s->N, s->y, s->tickets, st);
+      launch_sweep_prepare(s->N, s->y, s->x2, s->tickets, st);
     }
     ph_end(s, st, PH_STAGE2, ev);
+    if (s->use_grid) {
+      ph_begin(s, st, ev);
+      launch_ilu_fwd_grid(s->grid[0], s->grid[1], s->grid[2], s->Lg, rhs, s->y, s->tickets,
+                          s->hdev + 140, kSweepSpinLimit, st);
+      ph_end(s, st, PH_ILU_F, ev);
+      ph_begin(s, st, ev);
+      launch_ilu_bwd_grid(s->grid[0], s->grid[1], s->grid[2], s->Ug, s->y, e0, ne, s->eidx_h, s->x2, z,
+                          s->tickets, s->hdev + 140, kSweepSpinLimit, st);
+      ph_end(s, st, PH_ILU_B, ev);
+      return;
+    }
     ph_begin(s, st, ev);
     launch_ilu_fwd_sf(s->Lf, s->sf_width, s->fperm, rhs, s->y, s->x2, s->tickets, s->hdev + 140,
                       kSweepSpinLimit, st);
@@ -548,8 +624,8 @@ cptr_status cptr_setup(const cptr_bsr* A, int32_t block_size, const int32_t* ell
   cptr_setup_opts o;
   cptr_setup_opts_default(&o);
   if (opts) o = *opts;
-  if (o.ilu_sweep < 0 || o.ilu_sweep > 2)
-    return (cptr_status)fail(nullptr, CPTR_E_INVALID, "ilu_sweep must be 0, 1 or 2");
+  if (o.ilu_sweep < 0 || o.ilu_sweep > 3)
+    return (cptr_status)fail(nullptr, CPTR_E_INVALID, "ilu_sweep must be 0, 1, 2 or 3");
   if (o.max_levels < 1 || o.max_levels > 64 || o.max_coarse < 1 || o.p_max_elmts < 0 ||
       !(o.strong_threshold >= 0.0) || !(o.max_row_sum > 0.0))
     return (cptr_status)fail(nullptr, CPTR_E_INVALID, "setup options out of range");
@@ -894,6 +970,15 @@ cptr_status cptr_export(cptr_solver s, int32_t what, int32_t level, void* buf, i
       return put(h.lev[level].dinv.data(), (int64_t)h.lev[level].dinv.size() * 8);
     case CPTR_EXPORT_ILU_VALS:
       return put(h.ilu.data(), (int64_t)h.ilu.size() * 8);
+    case CPTR_EXPORT_SWEEP: {
+      const int32_t mode = !s->device ? -1
+                           : s->use_grid ? CPTR_ILU_SWEEP_GRID
+                           : s->sf_width > 0 ? CPTR_ILU_SWEEP_ONE_LAUNCH
+                                             : CPTR_ILU_SWEEP_LEVELS;
+      int32_t v[4] = {mode, s->use_grid ? s->grid[0] : 0, s->use_grid ? s->grid[1] : 0,
+                      s->use_grid ? s->grid[2] : 0};
+      return put(v, 16);
+    }
     case CPTR_EXPORT_ILU_NLEVELS: {
       int32_t nl[2] = {h.n_fwd_levels, h.n_bwd_levels};
       return put(nl, 8);

@@ -382,8 +382,7 @@ __device__ __forceinline__ int take_ticket(int* ctr) {
   return s_ticket;
 }
 
-// Forward sweep y = L^-1 r2 (unit block-lower L).  Also fills x2 with the
-// sentinel for the backward sweep and resets the backward ticket counter.
+// Forward sweep y = L^-1 r2 (unit block-lower L).
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_ilu_fwd_sf(int npos, const int32_t* __restrict__ sptr,
                                                        const int32_t* __restrict__ col,
@@ -395,7 +394,6 @@ __global__ __launch_bounds__(kBlock) void k_ilu_fwd_sf(int npos, const int32_t* 
   const int blk = take_ticket(tickets);
   const int p = blk * kBlock + threadIdx.x;
   const bool active = p < npos;
-  if (blk == 0 && threadIdx.x == 0) tickets[1] = 0;  // backward counter: used after this kernel
   int i = 0;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   int c[W];
@@ -420,11 +418,8 @@ __global__ __launch_bounds__(kBlock) void k_ilu_fwd_sf(int npos, const int32_t* 
       }
       if (c[k] >= 0) need |= 1u << k;
     }
-    const double s0 = __longlong_as_double((long long)kSentinel);
-    x2[3 * (size_t)i] = s0;
-    x2[3 * (size_t)i + 1] = s0;
-    x2[3 * (size_t)i + 2] = s0;
   }
+  (void)x2;
   bool done = !active;
   for (long spin = 0;; ++spin) {
     if (!done) {
@@ -567,16 +562,250 @@ __global__ __launch_bounds__(kBlock) void k_prolong_e(int nrows, const double* _
   x1[3 * (size_t)i + 2] = (ea == 2 ? ex : 0.0) + (NE == 2 && eb == 2 ? ey : 0.0) + o[2];
 }
 
-// prepares a one-launch forward sweep on an arbitrary right-hand side:
-// y := sentinel, forward ticket counter := 0
-__global__ __launch_bounds__(kBlock) void k_sweep_prepare(int64_t n, double* __restrict__ y, int* tickets) {
+// prepares one-launch sweeps on an arbitrary right-hand side:
+// y, x2 := sentinel, both ticket counters := 0
+__global__ __launch_bounds__(kBlock) void k_sweep_prepare(int64_t n, double* __restrict__ y,
+                                                          double* __restrict__ x2, int* tickets) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i == 0) tickets[0] = 0;
-  if (i < n) y[i] = __longlong_as_double((long long)kSentinel);
+  if (i == 0) {
+    tickets[0] = 0;
+    tickets[1] = 0;
+  }
+  if (i < n) {
+    const double s0 = __longlong_as_double((long long)kSentinel);
+    y[i] = s0;
+    x2[i] = s0;
+  }
 }
 
-// stage-two residual that also prepares the forward sweep: y := sentinel and
-// the forward ticket counter := 0
+
+// --------------------------------------------------------------------------
+// ILU(0) sweeps for a 7-point stencil in lexicographic order (x fastest).
+//
+// One wavefront owns a tile of 16 x 4 x-pencils (lane = jj + 16 kk, pencil
+// (j, k) = (16 J + jj, 4 K + kk)) and walks it as a skewed systolic array: at
+// step s lane (jj, kk) handles cell i = s - jj - kk of its pencil.  The three
+// lower neighbours of that cell were handled one step earlier by the lane
+// itself (i-1), by lane jj-1 (j-1) and by lane kk-1 (k-1), so they arrive in
+// registers or through cross-lane shuffles.  Only lanes on the tile's low
+// faces (jj = 0, kk = 0) read values of another tile; those are polled from
+// the device-coherent, sentinel-filled output as in the one-launch sweeps,
+// prefetched D steps ahead.  Tiles take tickets in (K, J) order, so a tile
+// only waits on tiles that started before it.  The backward sweep is the
+// mirror image (high faces, tiles in reverse order).
+//
+// Matrix data per cell: L = blocks (-x, -y, -z); U = blocks (+x, +y, +z) then
+// U_ii^-1; blocks of absent neighbours are zero.
+constexpr int kTJ = 16, kTK = 4;
+
+struct Vec3 {
+  double v0, v1, v2;
+};
+
+__device__ __forceinline__ Vec3 shfl_up3(Vec3 a, int d) {
+  return {__shfl_up(a.v0, d, 64), __shfl_up(a.v1, d, 64), __shfl_up(a.v2, d, 64)};
+}
+__device__ __forceinline__ Vec3 shfl_down3(Vec3 a, int d) {
+  return {__shfl_down(a.v0, d, 64), __shfl_down(a.v1, d, 64), __shfl_down(a.v2, d, 64)};
+}
+__device__ __forceinline__ Vec3 ld3_dev(const double* p) { return {ld_dev(p), ld_dev(p + 1), ld_dev(p + 2)}; }
+__device__ __forceinline__ bool sent3(const Vec3& a) { return is_sent(a.v0) || is_sent(a.v1) || is_sent(a.v2); }
+__device__ __forceinline__ void mv3_sub(const double* b, const Vec3& x, double& a0, double& a1, double& a2) {
+  a0 -= b[0] * x.v0 + b[1] * x.v1 + b[2] * x.v2;
+  a1 -= b[3] * x.v0 + b[4] * x.v1 + b[5] * x.v2;
+  a2 -= b[6] * x.v0 + b[7] * x.v1 + b[8] * x.v2;
+}
+
+template <int D>
+__global__ __launch_bounds__(64) void k_ilu_fwd_grid(int nx, int ny, int nz, int nJ,
+                                                     const double* __restrict__ Lg,
+                                                     const double* __restrict__ r2, double* y,
+                                                     int* tickets, double* err, long spin_limit) {
+  __shared__ int s_t;
+  if (threadIdx.x == 0) s_t = __hip_atomic_fetch_add(tickets, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const int t = s_t;
+  const int J = t % nJ, K = t / nJ;
+  const int lane = threadIdx.x, jj = lane & (kTJ - 1), kk = lane / kTJ;
+  const int j = J * kTJ + jj, k = K * kTK + kk;
+  const bool valid = j < ny && k < nz;
+  const size_t line = (size_t)nx;
+  const size_t plane = (size_t)nx * ny;
+  const size_t base = valid ? (size_t)nx * ((size_t)j + (size_t)ny * k) : 0;
+  const int lag = jj + kk;
+  const int nsteps = nx + (kTJ - 1) + (kTK - 1);
+  const bool pollJ = valid && jj == 0 && j > 0;
+  const bool pollK = valid && kk == 0 && k > 0;
+  const Vec3 zero3 = {0.0, 0.0, 0.0};
+
+  double rr[D][3], Lr[D][27];
+  Vec3 bj[D], bk[D];
+  auto fetch = [&](int slot, int step) {
+    const int i = step - lag;
+    const bool act = valid && i >= 0 && i < nx;
+    if (act) {
+      const size_t c = base + i;
+      rr[slot][0] = r2[3 * c];
+      rr[slot][1] = r2[3 * c + 1];
+      rr[slot][2] = r2[3 * c + 2];
+      const double* l = Lg + 27 * c;
+#pragma unroll
+      for (int e = 0; e < 27; ++e) Lr[slot][e] = l[e];
+      bj[slot] = pollJ ? ld3_dev(y + 3 * (c - line)) : zero3;
+      bk[slot] = pollK ? ld3_dev(y + 3 * (c - plane)) : zero3;
+    }
+  };
+#pragma unroll
+  for (int d = 0; d < D; ++d) fetch(d, d);
+  Vec3 prev = zero3;   // own result at i-1
+  Vec3 out = zero3;    // own result of the last step (read by lanes jj+1 and kk+1)
+  long spin = 0;
+  bool failed = false;
+  for (int s0 = 0; s0 < nsteps && !failed; s0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int s = s0 + d;
+      const int i = s - lag;
+      const bool act = valid && i >= 0 && i < nx;
+      const Vec3 fj = shfl_up3(out, 1);
+      const Vec3 fk = shfl_up3(out, kTJ);
+      // tile-boundary values must be ready before anyone computes this step
+      bool ready = !(act && ((pollJ && sent3(bj[d])) || (pollK && sent3(bk[d]))));
+      while (!__all(ready)) {
+        if (++spin > spin_limit) {
+          failed = true;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        if (!ready) {
+          const size_t c = base + i;
+          if (pollJ) bj[d] = ld3_dev(y + 3 * (c - line));
+          if (pollK) bk[d] = ld3_dev(y + 3 * (c - plane));
+          ready = !((pollJ && sent3(bj[d])) || (pollK && sent3(bk[d])));
+        }
+      }
+      if (failed) break;
+      if (act) {
+        const Vec3 yj = jj == 0 ? bj[d] : fj;
+        const Vec3 yk = kk == 0 ? bk[d] : fk;
+        double a0 = rr[d][0], a1 = rr[d][1], a2 = rr[d][2];
+        mv3_sub(&Lr[d][0], prev, a0, a1, a2);
+        mv3_sub(&Lr[d][9], yj, a0, a1, a2);
+        mv3_sub(&Lr[d][18], yk, a0, a1, a2);
+        const size_t c = base + i;
+        st_dev(y + 3 * c, a0);
+        st_dev(y + 3 * c + 1, a1);
+        st_dev(y + 3 * c + 2, a2);
+        prev = {a0, a1, a2};
+        out = prev;
+      }
+      fetch(d, s + D);
+    }
+  }
+  if (failed && lane == 0) st_dev(err, 1.0);
+}
+
+template <int D, int NE>
+__global__ __launch_bounds__(64) void k_ilu_bwd_grid(int nx, int ny, int nz, int nJ, int nK,
+                                                     const double* __restrict__ Ug,
+                                                     const double* y, const double* __restrict__ e0,
+                                                     int ea, int eb, double* x2,
+                                                     double* __restrict__ z, int* tickets,
+                                                     double* err, long spin_limit) {
+  __shared__ int s_t;
+  if (threadIdx.x == 0) s_t = __hip_atomic_fetch_add(tickets + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const int t = nJ * nK - 1 - s_t;
+  const int J = t % nJ, K = t / nJ;
+  const int lane = threadIdx.x, jj = lane & (kTJ - 1), kk = lane / kTJ;
+  const int j = J * kTJ + jj, k = K * kTK + kk;
+  const bool valid = j < ny && k < nz;
+  const size_t line = (size_t)nx;
+  const size_t plane = (size_t)nx * ny;
+  const size_t base = valid ? (size_t)nx * ((size_t)j + (size_t)ny * k) : 0;
+  const int lag = (kTJ - 1 - jj) + (kTK - 1 - kk);
+  const int nsteps = nx + (kTJ - 1) + (kTK - 1);
+  const bool pollJ = valid && jj == kTJ - 1 && j + 1 < ny;
+  const bool pollK = valid && kk == kTK - 1 && k + 1 < nz;
+  const Vec3 zero3 = {0.0, 0.0, 0.0};
+
+  double yr[D][3], Ur[D][36];
+  Vec3 bj[D], bk[D];
+  auto fetch = [&](int slot, int step) {
+    const int i = nx - 1 - (step - lag);
+    const bool act = valid && i >= 0 && i < nx;
+    if (act) {
+      const size_t c = base + i;
+      yr[slot][0] = y[3 * c];
+      yr[slot][1] = y[3 * c + 1];
+      yr[slot][2] = y[3 * c + 2];
+      const double* u = Ug + 36 * c;
+#pragma unroll
+      for (int e = 0; e < 36; ++e) Ur[slot][e] = u[e];
+      bj[slot] = pollJ ? ld3_dev(x2 + 3 * (c + line)) : zero3;
+      bk[slot] = pollK ? ld3_dev(x2 + 3 * (c + plane)) : zero3;
+    }
+  };
+#pragma unroll
+  for (int d = 0; d < D; ++d) fetch(d, d);
+  Vec3 prev = zero3;
+  Vec3 out = zero3;
+  long spin = 0;
+  bool failed = false;
+  for (int s0 = 0; s0 < nsteps && !failed; s0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int s = s0 + d;
+      const int i = nx - 1 - (s - lag);
+      const bool act = valid && i >= 0 && i < nx;
+      const Vec3 fj = shfl_down3(out, 1);
+      const Vec3 fk = shfl_down3(out, kTJ);
+      bool ready = !(act && ((pollJ && sent3(bj[d])) || (pollK && sent3(bk[d]))));
+      while (!__all(ready)) {
+        if (++spin > spin_limit) {
+          failed = true;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        if (!ready) {
+          const size_t c = base + i;
+          if (pollJ) bj[d] = ld3_dev(x2 + 3 * (c + line));
+          if (pollK) bk[d] = ld3_dev(x2 + 3 * (c + plane));
+          ready = !((pollJ && sent3(bj[d])) || (pollK && sent3(bk[d])));
+        }
+      }
+      if (failed) break;
+      if (act) {
+        const Vec3 xj = jj == kTJ - 1 ? bj[d] : fj;
+        const Vec3 xk = kk == kTK - 1 ? bk[d] : fk;
+        double a0 = yr[d][0], a1 = yr[d][1], a2 = yr[d][2];
+        mv3_sub(&Ur[d][0], prev, a0, a1, a2);
+        mv3_sub(&Ur[d][9], xj, a0, a1, a2);
+        mv3_sub(&Ur[d][18], xk, a0, a1, a2);
+        const double* ui = &Ur[d][27];
+        const double o0 = ui[0] * a0 + ui[1] * a1 + ui[2] * a2;
+        const double o1 = ui[3] * a0 + ui[4] * a1 + ui[5] * a2;
+        const double o2 = ui[6] * a0 + ui[7] * a1 + ui[8] * a2;
+        const size_t c = base + i;
+        st_dev(x2 + 3 * c, o0);
+        st_dev(x2 + 3 * c + 1, o1);
+        st_dev(x2 + 3 * c + 2, o2);
+        const double ex = e0 ? e0[c * NE] : 0.0;
+        const double ey = (NE == 2 && e0) ? e0[c * NE + 1] : 0.0;
+        z[3 * c] = o0 + (ea == 0 ? ex : 0.0) + (NE == 2 && eb == 0 ? ey : 0.0);
+        z[3 * c + 1] = o1 + (ea == 1 ? ex : 0.0) + (NE == 2 && eb == 1 ? ey : 0.0);
+        z[3 * c + 2] = o2 + (ea == 2 ? ex : 0.0) + (NE == 2 && eb == 2 ? ey : 0.0);
+        prev = {o0, o1, o2};
+        out = prev;
+      }
+      fetch(d, s + D);
+    }
+  }
+  if (failed && lane == 0) st_dev(err, 1.0);
+}
+
+// stage-two residual that also prepares the one-launch sweeps: y, x2 :=
+// sentinel and both ticket counters := 0
 template <int NE>
 __global__ __launch_bounds__(kBlock) void k_stage2_resid_sf(int nrows, int nblk, const int32_t* __restrict__ sptr,
                                                             const int32_t* __restrict__ col,
@@ -584,8 +813,12 @@ __global__ __launch_bounds__(kBlock) void k_stage2_resid_sf(int nrows, int nblk,
                                                             int eb, const double* __restrict__ e0,
                                                             const double* __restrict__ r,
                                                             double* __restrict__ r2,
-                                                            double* __restrict__ y, int* tickets) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) tickets[0] = 0;
+                                                            double* __restrict__ y,
+                                                            double* __restrict__ x2, int* tickets) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    tickets[0] = 0;
+    tickets[1] = 0;
+  }
   const int row = xcd_block(blockIdx.x, nblk) * kBlock + threadIdx.x;
   if (row >= nrows) return;
   const int s = row >> 6, lane = row & 63;
@@ -613,6 +846,9 @@ __global__ __launch_bounds__(kBlock) void k_stage2_resid_sf(int nrows, int nblk,
   y[3 * (size_t)row] = s0;
   y[3 * (size_t)row + 1] = s0;
   y[3 * (size_t)row + 2] = s0;
+  x2[3 * (size_t)row] = s0;
+  x2[3 * (size_t)row + 1] = s0;
+  x2[3 * (size_t)row + 2] = s0;
 }
 
 // --------------------------------------------------------------------------
@@ -843,12 +1079,13 @@ void launch_ilu_bwd_level(const Sell& U, const int32_t* perm, const double* uinv
 
 
 void launch_stage2_resid_sf(const Sell& A, int ne, const int32_t* eidx, const double* e0,
-                            const double* r, double* r2, double* y, int* tickets, hipStream_t st) {
+                            const double* r, double* r2, double* y, double* x2, int* tickets,
+                            hipStream_t st) {
   const int g = nblocks(A.nrows, kBlock);
   if (ne == 2)
-    k_stage2_resid_sf<2><<<g, kBlock, 0, st>>>(A.nrows, g, A.sptr, A.col, A.val, eidx[0], eidx[1], e0, r, r2, y, tickets);
+    k_stage2_resid_sf<2><<<g, kBlock, 0, st>>>(A.nrows, g, A.sptr, A.col, A.val, eidx[0], eidx[1], e0, r, r2, y, x2, tickets);
   else
-    k_stage2_resid_sf<1><<<g, kBlock, 0, st>>>(A.nrows, g, A.sptr, A.col, A.val, eidx[0], 0, e0, r, r2, y, tickets);
+    k_stage2_resid_sf<1><<<g, kBlock, 0, st>>>(A.nrows, g, A.sptr, A.col, A.val, eidx[0], 0, e0, r, r2, y, x2, tickets);
 }
 
 
@@ -858,8 +1095,27 @@ void launch_prolong_e(int32_t nrows, int ne, const int32_t* eidx, const double* 
   if (ne == 2) k_prolong_e<2><<<g, kBlock, 0, st>>>(nrows, e0, eidx[0], eidx[1], x1);
   else k_prolong_e<1><<<g, kBlock, 0, st>>>(nrows, e0, eidx[0], 0, x1);
 }
-void launch_sweep_prepare(int64_t n, double* y, int* tickets, hipStream_t st) {
-  k_sweep_prepare<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, y, tickets);
+void launch_sweep_prepare(int64_t n, double* y, double* x2, int* tickets, hipStream_t st) {
+  k_sweep_prepare<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, y, x2, tickets);
+}
+
+
+constexpr int kGridPrefetch = 4;
+
+void launch_ilu_fwd_grid(int nx, int ny, int nz, const double* Lg, const double* r2, double* y,
+                         int* tickets, double* err, long spin_limit, hipStream_t st) {
+  const int nJ = (ny + kTJ - 1) / kTJ, nK = (nz + kTK - 1) / kTK;
+  k_ilu_fwd_grid<kGridPrefetch><<<nJ * nK, 64, 0, st>>>(nx, ny, nz, nJ, Lg, r2, y, tickets, err, spin_limit);
+}
+
+void launch_ilu_bwd_grid(int nx, int ny, int nz, const double* Ug, const double* y, const double* e0,
+                         int ne, const int32_t* eidx, double* x2, double* z, int* tickets,
+                         double* err, long spin_limit, hipStream_t st) {
+  const int nJ = (ny + kTJ - 1) / kTJ, nK = (nz + kTK - 1) / kTK;
+  if (ne == 2)
+    k_ilu_bwd_grid<kGridPrefetch, 2><<<nJ * nK, 64, 0, st>>>(nx, ny, nz, nJ, nK, Ug, y, e0, eidx[0], eidx[1], x2, z, tickets, err, spin_limit);
+  else
+    k_ilu_bwd_grid<kGridPrefetch, 1><<<nJ * nK, 64, 0, st>>>(nx, ny, nz, nJ, nK, Ug, y, e0, eidx[0], 0, x2, z, tickets, err, spin_limit);
 }
 
 int ilu_sf_width(int max_width) {

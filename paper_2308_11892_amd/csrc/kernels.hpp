@@ -64,7 +64,14 @@ void launch_ilu_bwd_level(const Sell& U, const int32_t* perm, const double* uinv
 // one-launch ILU sweeps (see kernels.hip); width = register slots per row
 int ilu_sf_width(int max_width);  // 0 when the rows are too wide for the one-launch kernels
 void launch_stage2_resid_sf(const Sell& A, int ne, const int32_t* eidx, const double* e0,
-                            const double* r, double* r2, double* y, int* tickets, hipStream_t st);
+                            const double* r, double* r2, double* y, double* x2, int* tickets,
+                            hipStream_t st);
+// 7-point lexicographic grids: tiled systolic sweeps (Lg: [cell][27], Ug: [cell][36])
+void launch_ilu_fwd_grid(int nx, int ny, int nz, const double* Lg, const double* r2, double* y,
+                         int* tickets, double* err, long spin_limit, hipStream_t st);
+void launch_ilu_bwd_grid(int nx, int ny, int nz, const double* Ug, const double* y, const double* e0,
+                         int ne, const int32_t* eidx, double* x2, double* z, int* tickets,
+                         double* err, long spin_limit, hipStream_t st);
 void launch_ilu_fwd_sf(const Sell& L, int width, const int32_t* perm, const double* r2, double* y,
                        double* x2, int* tickets, double* err, long spin_limit, hipStream_t st);
 void launch_ilu_bwd_sf(const Sell& U, int width, const int32_t* perm, const double* uinv,
@@ -73,7 +80,7 @@ void launch_ilu_bwd_sf(const Sell& U, int width, const int32_t* perm, const doub
 
 void launch_prolong_e(int32_t nrows, int ne, const int32_t* eidx, const double* e0, double* x1,
                       hipStream_t st);
-void launch_sweep_prepare(int64_t n, double* y, int* tickets, hipStream_t st);
+void launch_sweep_prepare(int64_t n, double* y, double* x2, int* tickets, hipStream_t st);
 
 // Arnoldi / BLAS-1 (deterministic two-stage reductions into `part`)
 void launch_mdot(int64_t n, int nv, const double* V, int64_t ldv, const double* w, double* part,

@@ -198,25 +198,43 @@ def test_gmres_parity_grid100x100x20(pe):
     assert res <= 1e-6
 
 
-@pytest.mark.parametrize("name", ["grid20x20x5", "grid33x17x2", "grid7x5x3", "grid1x1x1"])
+@pytest.mark.parametrize("name", ["grid20x20x5", "grid33x17x2", "grid7x5x3", "grid2x2x2",
+                                  "grid1x1x1", "grid13x1x1"])
 def test_ilu_sweep_modes_agree(name):
-    """One-launch sweeps (dependency polling) and per-level launches compute the
-    same preconditioner; both match the oracle."""
+    """Per-level launches, one-launch sweeps and (on 3D grids) the tiled grid
+    sweeps compute the same preconditioner; all match the oracle."""
     c = J.by_name(name)
     say(f"[sweep-modes] {name}")
     ref = O.Cptr(c.row_ptr, c.col_idx, c.values)
     r = np.random.default_rng(12).standard_normal(c.n_dof)
     zo = ref.apply(r)
+    is_grid = min(c.nx, c.ny, c.nz) >= 2
+    modes = [L.ILU_SWEEP_LEVELS, L.ILU_SWEEP_ONE_LAUNCH] + ([L.ILU_SWEEP_GRID] if is_grid else [])
     outs = []
-    for mode in (L.ILU_SWEEP_LEVELS, L.ILU_SWEEP_ONE_LAUNCH):
+    for mode in modes:
         with L.Solver(c.row_ptr, c.col_idx, c.values, ilu_sweep=mode) as s:
+            used = s.export("SWEEP", 0, 4, np.int32)
+            assert used[0] == mode, (mode, used)
+            if mode == L.ILU_SWEEP_GRID:
+                assert tuple(used[1:]) == (c.nx, c.ny, c.nz)
             z = torch.empty(c.n_dof, dtype=torch.float64, device=DEV)
             for _ in range(3):  # repeated applies reuse the ticket counters and sentinels
                 s.apply(dev(r), z)
             outs.append(host(z))
     for z in outs:
         assert np.linalg.norm(z - zo) <= 1e-10 * np.linalg.norm(zo)
-    assert np.linalg.norm(outs[0] - outs[1]) <= 1e-14 * np.linalg.norm(outs[0])
+    for z in outs[1:]:
+        # the schedules sum the neighbour blocks in different orders
+        assert np.linalg.norm(z - outs[0]) <= 1e-13 * np.linalg.norm(outs[0])
+    if not is_grid:
+        with pytest.raises(L.CptrError):
+            L.Solver(c.row_ptr, c.col_idx, c.values, ilu_sweep=L.ILU_SWEEP_GRID)
+
+
+def test_auto_sweep_picks_grid_on_cartesian():
+    c = J.config0()
+    with L.Solver(c.row_ptr, c.col_idx, c.values) as s:
+        assert tuple(s.export("SWEEP", 0, 4, np.int32)) == (L.ILU_SWEEP_GRID, 20, 20, 5)
 
 
 def test_one_launch_sweep_gmres_grid100x100x20():

@@ -22,7 +22,7 @@ def say(*a):
 
 @pytest.mark.parametrize("name", ["grid20x20x5", "grid100x100x20", "grid100x100x20_pe0.1",
                                   "grid100x100x20_pe1000"])
-@pytest.mark.parametrize("mode", [L.ILU_SWEEP_LEVELS, L.ILU_SWEEP_ONE_LAUNCH])
+@pytest.mark.parametrize("mode", [L.ILU_SWEEP_LEVELS, L.ILU_SWEEP_ONE_LAUNCH, L.ILU_SWEEP_GRID])
 def test_stage_parity(name, mode):
     c = J.by_name(name)
     say(f"[stages] {name} mode={mode}")
