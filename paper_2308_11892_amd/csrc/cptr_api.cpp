@@ -111,8 +111,11 @@ struct cptr_solver_s {
   int sf_width = 0;          // register slots of the one-launch sweeps; 0 = per-level launches
   int grid[3] = {0, 0, 0};   // nx, ny, nz when A is a 7-point stencil in lexicographic order
   bool use_grid = false;     // tiled systolic sweeps on that grid
-  double* Lg = nullptr;      // [cell][27]: L blocks (-x, -y, -z)
-  double* Ug = nullptr;      // [cell][36]: U blocks (+x, +y, +z), U_ii^-1
+  double* Lg = nullptr;      // L blocks (-x, -y, -z), tile layout of the forward sweep
+  double* Ug = nullptr;      // U blocks (+x, +y, +z) and U_ii^-1, tile layout of the backward sweep
+  double* ytile = nullptr;   // forward-sweep results in the backward tile layout
+  double* r2tile = nullptr;  // stage-two residual in the forward tile layout
+  double* e0tile = nullptr;  // V-cycle result in the backward tile layout
   int* tickets = nullptr;    // [2] workgroup ticket counters of the one-launch sweeps
   struct Lev {
     DCsr A, P, R;
@@ -254,27 +257,49 @@ bool detect_grid(const HostSetup& h, int dims[3]) {
 
 int build_grid_factors(cptr_solver s, hipStream_t st) {
   const HostSetup& h = s->host;
-  const int32_t nb = h.nb;
-  const int32_t nx = s->grid[0], nxy = s->grid[0] * s->grid[1];
-  std::vector<double> lg((size_t)nb * 27, 0.0), ug((size_t)nb * 36, 0.0);
-  for (int32_t c = 0; c < nb; ++c) {
+  const int nx = s->grid[0], ny = s->grid[1], nz = s->grid[2];
+  const int32_t nxy = nx * ny;
+  const int64_t rows = grid_ntiles(ny, nz) * grid_nsteps(nx);   // 64-lane rows of either layout
+  std::vector<double> lt((size_t)rows * 27 * 64, 0.0), ut((size_t)rows * 36 * 64, 0.0);
+  for (int32_t c = 0; c < h.nb; ++c) {
+    const int i = c % nx, j = (c / nx) % ny, k = c / nxy;
+    int64_t fr, br;
+    int lane;
+    grid_tile_slot(nx, ny, i, j, k, fr, br, lane);
     for (int32_t q = h.rp[c]; q < h.rp[c + 1]; ++q) {
       const int32_t d = h.ci[q] - c;
-      int slot = -1;
-      double* dst = nullptr;
-      if (d == -1) slot = 0, dst = &lg[(size_t)c * 27];
-      else if (d == -nx) slot = 1, dst = &lg[(size_t)c * 27];
-      else if (d == -nxy) slot = 2, dst = &lg[(size_t)c * 27];
-      else if (d == 1) slot = 0, dst = &ug[(size_t)c * 36];
-      else if (d == nx) slot = 1, dst = &ug[(size_t)c * 36];
-      else if (d == nxy) slot = 2, dst = &ug[(size_t)c * 36];
-      if (dst) std::memcpy(dst + 9 * slot, &h.ilu[(size_t)q * 9], 9 * sizeof(double));
+      const double* blk = &h.ilu[(size_t)q * 9];
+      int slot;
+      double* dst;
+      int nv;
+      int64_t row;
+      if (d == -1 || d == -nx || d == -nxy) {
+        slot = d == -1 ? 0 : d == -nx ? 1 : 2;
+        dst = lt.data();
+        nv = 27;
+        row = fr;
+      } else if (d == 1 || d == nx || d == nxy) {
+        slot = d == 1 ? 0 : d == nx ? 1 : 2;
+        dst = ut.data();
+        nv = 36;
+        row = br;
+      } else {
+        continue;
+      }
+      for (int e = 0; e < 9; ++e) dst[((size_t)row * nv + 9 * slot + e) * 64 + lane] = blk[e];
     }
-    std::memcpy(&ug[(size_t)c * 36 + 27], &h.uinv[(size_t)c * 9], 9 * sizeof(double));
+    for (int e = 0; e < 9; ++e) ut[((size_t)br * 36 + 27 + e) * 64 + lane] = h.uinv[(size_t)c * 9 + e];
   }
   int rc;
-  if ((rc = upload(s, s->Lg, lg.data(), (int64_t)lg.size(), st))) return rc;
-  if ((rc = upload(s, s->Ug, ug.data(), (int64_t)ug.size(), st))) return rc;
+  if ((rc = upload(s, s->Lg, lt.data(), (int64_t)lt.size(), st))) return rc;
+  if ((rc = upload(s, s->Ug, ut.data(), (int64_t)ut.size(), st))) return rc;
+  // padding slots of the tile vectors stay zero forever (no kernel writes them)
+  if ((rc = dalloc(s, s->ytile, rows * 3 * 64))) return rc;
+  HIP_TRY(s, hipMemset(s->ytile, 0, sizeof(double) * (size_t)rows * 3 * 64));
+  if ((rc = dalloc(s, s->r2tile, rows * 3 * 64))) return rc;
+  HIP_TRY(s, hipMemset(s->r2tile, 0, sizeof(double) * (size_t)rows * 3 * 64));
+  if ((rc = dalloc(s, s->e0tile, rows * 2 * 64))) return rc;
+  HIP_TRY(s, hipMemset(s->e0tile, 0, sizeof(double) * (size_t)rows * 2 * 64));
   return CPTR_OK;
 }
 
@@ -480,7 +505,23 @@ void enqueue_stage2(cptr_solver s, const double* r, const double* e0, double* z,
   const int ne = s->ne;
   hipEvent_t ev;
   const double* rhs = r;
-  if (s->use_grid || s->sf_width > 0) {
+  if (s->use_grid) {
+    const int nx = s->grid[0], ny = s->grid[1], nz = s->grid[2];
+    ph_begin(s, st, ev);
+    launch_stage2_grid(nx, ny, nz, s->A, ne, s->eidx_h, e0, r, s->r2tile, s->e0tile, s->y, s->x2,
+                       s->tickets, st);
+    ph_end(s, st, PH_STAGE2, ev);
+    ph_begin(s, st, ev);
+    launch_ilu_fwd_grid(nx, ny, nz, s->Lg, s->r2tile, s->ytile, s->y, s->tickets, s->hdev + 140,
+                        kSweepSpinLimit, st);
+    ph_end(s, st, PH_ILU_F, ev);
+    ph_begin(s, st, ev);
+    launch_ilu_bwd_grid(nx, ny, nz, s->Ug, s->ytile, e0 ? s->e0tile : nullptr, ne, s->eidx_h, s->x2, z,
+                        s->tickets, s->hdev + 140, kSweepSpinLimit, st);
+    ph_end(s, st, PH_ILU_B, ev);
+    return;
+  }
+  if (s->sf_width > 0) {
     ph_begin(s, st, ev);
     if (e0) {
       launch_stage2_resid_sf(s->A, ne, s->eidx_h, e0, r, s->r2, s->y, s->x2, s->tickets, st);
@@ -489,17 +530,6 @@ void enqueue_stage2(cptr_solver s, const double* r, const double* e0, double* z,
       launch_sweep_prepare(s->N, s->y, s->x2, s->tickets, st);
     }
     ph_end(s, st, PH_STAGE2, ev);
-    if (s->use_grid) {
-      ph_begin(s, st, ev);
-      launch_ilu_fwd_grid(s->grid[0], s->grid[1], s->grid[2], s->Lg, rhs, s->y, s->tickets,
-                          s->hdev + 140, kSweepSpinLimit, st);
-      ph_end(s, st, PH_ILU_F, ev);
-      ph_begin(s, st, ev);
-      launch_ilu_bwd_grid(s->grid[0], s->grid[1], s->grid[2], s->Ug, s->y, e0, ne, s->eidx_h, s->x2, z,
-                          s->tickets, s->hdev + 140, kSweepSpinLimit, st);
-      ph_end(s, st, PH_ILU_B, ev);
-      return;
-    }
     ph_begin(s, st, ev);
     launch_ilu_fwd_sf(s->Lf, s->sf_width, s->fperm, rhs, s->y, s->x2, s->tickets, s->hdev + 140,
                       kSweepSpinLimit, st);

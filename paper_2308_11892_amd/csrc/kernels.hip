@@ -616,192 +616,282 @@ __device__ __forceinline__ void mv3_sub(const double* b, const Vec3& x, double& 
   a2 -= b[6] * x.v0 + b[7] * x.v1 + b[8] * x.v2;
 }
 
-template <int D>
-__global__ __launch_bounds__(64) void k_ilu_fwd_grid(int nx, int ny, int nz, int nJ,
-                                                     const double* __restrict__ Lg,
-                                                     const double* __restrict__ r2, double* y,
-                                                     int* tickets, double* err, long spin_limit) {
+// One kernel for both directions.
+//   FWD: y = L^-1 r2.  M = L blocks (-x, -y, -z), rhs = r2, both in the
+//        forward tile layout.  y goes to `ytile` in the backward tile layout
+//        (all lanes of a forward step land in one backward step: coalesced)
+//        and, for the lanes whose values other tiles read (high faces jj = 15,
+//        kk = 3), to the sentinel-filled natural-order vector `pub` with
+//        device-coherent stores.
+//   BWD: x2 = U^-1 y, z = P_E e0 + x2.  M = U blocks (+x, +y, +z) then
+//        U_ii^-1, rhs = ytile, e0 (NE values), all in the backward tile layout;
+//        only low-face lanes (jj = 0, kk = 0) publish x2.
+// Tile layout of per-cell data with NV values: ((tile * nsteps + step) * NV +
+// e) * 64 + lane, tile = J + nJ K, step = the step that handles the cell in
+// this direction; slots of absent cells hold zeros.  The matrix data of the
+// next two steps is in flight while a step computes (two register sets used in
+// turn); the values polled from neighbouring tiles are prefetched kDB steps
+// ahead.  When one of them is not there yet the wave waits until the value kDB
+// steps ahead is there too, so after a stall the tile trails its neighbour far
+// enough for the later prefetches to find published data.
+constexpr int kDB = 4;
+
+template <bool FWD, int NE>
+struct GridTile {
+  static constexpr int NV = FWD ? 27 : 36;
+  int nx, ny, lag, nsteps;
+  long base, offJ, offK;
+  bool valid, pollJ, pollK, publish;
+  int jj, kk;
+  const double* pub;
+
+  __device__ __forceinline__ int cell_i(int step) const { return FWD ? step - lag : nx - 1 - (step - lag); }
+  __device__ __forceinline__ bool active(int step) const {
+    const int i = cell_i(step);
+    return valid && i >= 0 && i < nx;
+  }
+  __device__ __forceinline__ void poll(int step, Vec3& bj, Vec3& bk) const {
+    if (active(step)) {
+      const long c = base + cell_i(step);
+      if (pollJ) bj = ld3_dev(pub + 3 * (c + offJ));
+      if (pollK) bk = ld3_dev(pub + 3 * (c + offK));
+    }
+  }
+  __device__ __forceinline__ bool ready(int step, const Vec3& bj, const Vec3& bk) const {
+    return !(active(step) && ((pollJ && sent3(bj)) || (pollK && sent3(bk))));
+  }
+};
+
+template <bool FWD, int NE>
+__global__ __launch_bounds__(64) void k_ilu_grid(int nx, int ny, int nz, int nJ, int nK,
+                                                 const double* __restrict__ M,
+                                                 const double* rhs, double* ytile, double* pub,
+                                                 const double* __restrict__ e0t, int ea, int eb,
+                                                 double* __restrict__ z, int* tickets, double* err,
+                                                 long spin_limit) {
+  using G = GridTile<FWD, NE>;
+  constexpr int NV = G::NV;
+  constexpr int NR = FWD ? 3 : 3 + NE;  // rhs values (+ e0 in the backward sweep)
   __shared__ int s_t;
-  if (threadIdx.x == 0) s_t = __hip_atomic_fetch_add(tickets, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0)
+    s_t = __hip_atomic_fetch_add(tickets + (FWD ? 0 : 1), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
-  const int t = s_t;
+  const int t = FWD ? s_t : nJ * nK - 1 - s_t;
   const int J = t % nJ, K = t / nJ;
-  const int lane = threadIdx.x, jj = lane & (kTJ - 1), kk = lane / kTJ;
-  const int j = J * kTJ + jj, k = K * kTK + kk;
-  const bool valid = j < ny && k < nz;
-  const size_t line = (size_t)nx;
-  const size_t plane = (size_t)nx * ny;
-  const size_t base = valid ? (size_t)nx * ((size_t)j + (size_t)ny * k) : 0;
-  const int lag = jj + kk;
-  const int nsteps = nx + (kTJ - 1) + (kTK - 1);
-  const bool pollJ = valid && jj == 0 && j > 0;
-  const bool pollK = valid && kk == 0 && k > 0;
+  const int lane = threadIdx.x;
+  G g;
+  g.nx = nx;
+  g.ny = ny;
+  g.jj = lane & (kTJ - 1);
+  g.kk = lane / kTJ;
+  const int j = J * kTJ + g.jj, k = K * kTK + g.kk;
+  g.valid = j < ny && k < nz;
+  const long line = nx, plane = (long)nx * ny;
+  g.base = g.valid ? (long)nx * ((long)j + (long)ny * k) : 0;
+  g.lag = FWD ? g.jj + g.kk : (kTJ - 1 - g.jj) + (kTK - 1 - g.kk);
+  g.nsteps = nx + (kTJ - 1) + (kTK - 1);
+  g.pollJ = g.valid && (FWD ? (g.jj == 0 && j > 0) : (g.jj == kTJ - 1 && j + 1 < ny));
+  g.pollK = g.valid && (FWD ? (g.kk == 0 && k > 0) : (g.kk == kTK - 1 && k + 1 < nz));
+  g.publish = g.valid && (FWD ? (g.jj == kTJ - 1 || g.kk == kTK - 1) : (g.jj == 0 || g.kk == 0));
+  g.offJ = FWD ? -line : line;
+  g.offK = FWD ? -plane : plane;
+  g.pub = pub;
+  const int nsteps = g.nsteps;
   const Vec3 zero3 = {0.0, 0.0, 0.0};
 
-  double rr[D][3], Lr[D][27];
-  Vec3 bj[D], bk[D];
-  auto fetch = [&](int slot, int step) {
-    const int i = step - lag;
-    const bool act = valid && i >= 0 && i < nx;
-    if (act) {
-      const size_t c = base + i;
-      rr[slot][0] = r2[3 * c];
-      rr[slot][1] = r2[3 * c + 1];
-      rr[slot][2] = r2[3 * c + 2];
-      const double* l = Lg + 27 * c;
+  // running pointers to this tile's rows of the tile layouts
+  const size_t trow = (size_t)t * nsteps;
+  const double* mp = M + trow * NV * 64 + lane;
+  const double* rp = rhs + trow * 3 * 64 + lane;
+  const double* ep = (FWD || !e0t) ? nullptr : e0t + trow * NE * 64 + lane;
+  double* yo = FWD ? ytile + (trow + nsteps - 1) * 3 * 64 + lane : nullptr;
+
+  double ma[NV], mb[NV], ra[NR], rb[NR];
+  auto load = [&](double* m, double* r, int step) {
+    if (step < nsteps) {
+      const double* mm = mp + (size_t)step * NV * 64;
 #pragma unroll
-      for (int e = 0; e < 27; ++e) Lr[slot][e] = l[e];
-      bj[slot] = pollJ ? ld3_dev(y + 3 * (c - line)) : zero3;
-      bk[slot] = pollK ? ld3_dev(y + 3 * (c - plane)) : zero3;
+      for (int e = 0; e < NV; ++e) m[e] = mm[e * 64];
+      const double* rr = rp + (size_t)step * 3 * 64;
+      r[0] = rr[0];
+      r[1] = rr[64];
+      r[2] = rr[128];
+      if (!FWD) {
+        // e0t == nullptr (M2^-1 alone): no P_E e0 term, nothing to read
+        r[3] = 0.0;
+        if (NE == 2) r[4] = 0.0;
+        if (e0t) {
+          const double* ee = ep + (size_t)step * NE * 64;
+          r[3] = ee[0];
+          if (NE == 2) r[4] = ee[64];
+        }
+      }
     }
   };
+  Vec3 bj[kDB], bk[kDB];
 #pragma unroll
-  for (int d = 0; d < D; ++d) fetch(d, d);
-  Vec3 prev = zero3;   // own result at i-1
-  Vec3 out = zero3;    // own result of the last step (read by lanes jj+1 and kk+1)
+  for (int q = 0; q < kDB; ++q) {
+    bj[q] = bk[q] = zero3;
+    g.poll(q, bj[q], bk[q]);
+  }
+  load(ma, ra, 0);
+  load(mb, rb, 1);
+  Vec3 prev = zero3;   // own result one cell earlier along the pencil
+  Vec3 last = zero3;   // own result of the last step, read by the neighbouring lanes
   long spin = 0;
   bool failed = false;
-  for (int s0 = 0; s0 < nsteps && !failed; s0 += D) {
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      const int s = s0 + d;
-      const int i = s - lag;
-      const bool act = valid && i >= 0 && i < nx;
-      const Vec3 fj = shfl_up3(out, 1);
-      const Vec3 fk = shfl_up3(out, kTJ);
-      // tile-boundary values must be ready before anyone computes this step
-      bool ready = !(act && ((pollJ && sent3(bj[d])) || (pollK && sent3(bk[d]))));
-      while (!__all(ready)) {
+
+  auto step_body = [&](int s, double* m, double* r) {
+    const Vec3 fj = FWD ? shfl_up3(last, 1) : shfl_down3(last, 1);
+    const Vec3 fk = FWD ? shfl_up3(last, kTJ) : shfl_down3(last, kTJ);
+    if (!__all(g.ready(s, bj[0], bk[0]))) {
+      // wait for this step's value and for the one kDB steps ahead
+      for (;;) {
+        bool ok = g.ready(s, bj[0], bk[0]);
+        Vec3 aj = zero3, ak = zero3;
+        g.poll(s + kDB, aj, ak);
+        ok = ok && g.ready(s + kDB, aj, ak);
+        if (__all(ok)) break;
         if (++spin > spin_limit) {
           failed = true;
-          break;
+          return;
         }
-        __builtin_amdgcn_s_sleep(1);
-        if (!ready) {
-          const size_t c = base + i;
-          if (pollJ) bj[d] = ld3_dev(y + 3 * (c - line));
-          if (pollK) bk[d] = ld3_dev(y + 3 * (c - plane));
-          ready = !((pollJ && sent3(bj[d])) || (pollK && sent3(bk[d])));
-        }
+        __builtin_amdgcn_s_sleep(2);
+        if (!g.ready(s, bj[0], bk[0])) g.poll(s, bj[0], bk[0]);
       }
-      if (failed) break;
-      if (act) {
-        const Vec3 yj = jj == 0 ? bj[d] : fj;
-        const Vec3 yk = kk == 0 ? bk[d] : fk;
-        double a0 = rr[d][0], a1 = rr[d][1], a2 = rr[d][2];
-        mv3_sub(&Lr[d][0], prev, a0, a1, a2);
-        mv3_sub(&Lr[d][9], yj, a0, a1, a2);
-        mv3_sub(&Lr[d][18], yk, a0, a1, a2);
-        const size_t c = base + i;
-        st_dev(y + 3 * c, a0);
-        st_dev(y + 3 * c + 1, a1);
-        st_dev(y + 3 * c + 2, a2);
+#pragma unroll
+      for (int q = 1; q < kDB; ++q) g.poll(s + q, bj[q], bk[q]);
+    }
+    if (g.active(s)) {
+      // a face lane without a neighbouring tile (domain boundary) has a zero
+      // block there; pass an explicit zero so no stale register enters 0 * x
+      const Vec3 vj = (FWD ? g.jj == 0 : g.jj == kTJ - 1) ? (g.pollJ ? bj[0] : zero3) : fj;
+      const Vec3 vk = (FWD ? g.kk == 0 : g.kk == kTK - 1) ? (g.pollK ? bk[0] : zero3) : fk;
+      double a0 = r[0], a1 = r[1], a2 = r[2];
+      mv3_sub(&m[0], prev, a0, a1, a2);
+      mv3_sub(&m[9], vj, a0, a1, a2);
+      mv3_sub(&m[18], vk, a0, a1, a2);
+      const long c = g.base + g.cell_i(s);
+      if (FWD) {
+        // the backward sweep handles this cell at step nsteps - 1 - s
+        double* yw = yo - (size_t)s * 3 * 64;
+        yw[0] = a0;
+        yw[64] = a1;
+        yw[128] = a2;
+        if (g.publish) {
+          st_dev(pub + 3 * c, a0);
+          st_dev(pub + 3 * c + 1, a1);
+          st_dev(pub + 3 * c + 2, a2);
+        }
         prev = {a0, a1, a2};
-        out = prev;
+      } else {
+        const double* ui = &m[27];
+        const double o0 = ui[0] * a0 + ui[1] * a1 + ui[2] * a2;
+        const double o1 = ui[3] * a0 + ui[4] * a1 + ui[5] * a2;
+        const double o2 = ui[6] * a0 + ui[7] * a1 + ui[8] * a2;
+        if (g.publish) {
+          st_dev(pub + 3 * c, o0);
+          st_dev(pub + 3 * c + 1, o1);
+          st_dev(pub + 3 * c + 2, o2);
+        }
+        const double ex = e0t ? r[3] : 0.0;
+        const double ey = (NE == 2 && e0t) ? r[NR - 1] : 0.0;
+        z[3 * c] = o0 + (ea == 0 ? ex : 0.0) + (NE == 2 && eb == 0 ? ey : 0.0);
+        z[3 * c + 1] = o1 + (ea == 1 ? ex : 0.0) + (NE == 2 && eb == 1 ? ey : 0.0);
+        z[3 * c + 2] = o2 + (ea == 2 ? ex : 0.0) + (NE == 2 && eb == 2 ? ey : 0.0);
+        prev = {o0, o1, o2};
       }
-      fetch(d, s + D);
+      last = prev;
+    }
+    // rotate the polled-value ring and prefetch kDB steps ahead
+#pragma unroll
+    for (int q = 0; q + 1 < kDB; ++q) {
+      bj[q] = bj[q + 1];
+      bk[q] = bk[q + 1];
+    }
+    g.poll(s + kDB, bj[kDB - 1], bk[kDB - 1]);
+  };
+
+  for (int s = 0; s < nsteps; s += 2) {
+    step_body(s, ma, ra);
+    if (failed) break;
+    load(ma, ra, s + 2);
+    if (s + 1 < nsteps) {
+      step_body(s + 1, mb, rb);
+      if (failed) break;
+      load(mb, rb, s + 3);
     }
   }
   if (failed && lane == 0) st_dev(err, 1.0);
 }
 
-template <int D, int NE>
-__global__ __launch_bounds__(64) void k_ilu_bwd_grid(int nx, int ny, int nz, int nJ, int nK,
-                                                     const double* __restrict__ Ug,
-                                                     const double* y, const double* __restrict__ e0,
-                                                     int ea, int eb, double* x2,
-                                                     double* __restrict__ z, int* tickets,
-                                                     double* err, long spin_limit) {
-  __shared__ int s_t;
-  if (threadIdx.x == 0) s_t = __hip_atomic_fetch_add(tickets + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-  const int t = nJ * nK - 1 - s_t;
-  const int J = t % nJ, K = t / nJ;
-  const int lane = threadIdx.x, jj = lane & (kTJ - 1), kk = lane / kTJ;
-  const int j = J * kTJ + jj, k = K * kTK + kk;
-  const bool valid = j < ny && k < nz;
-  const size_t line = (size_t)nx;
-  const size_t plane = (size_t)nx * ny;
-  const size_t base = valid ? (size_t)nx * ((size_t)j + (size_t)ny * k) : 0;
-  const int lag = (kTJ - 1 - jj) + (kTK - 1 - kk);
-  const int nsteps = nx + (kTJ - 1) + (kTK - 1);
-  const bool pollJ = valid && jj == kTJ - 1 && j + 1 < ny;
-  const bool pollK = valid && kk == kTK - 1 && k + 1 < nz;
-  const Vec3 zero3 = {0.0, 0.0, 0.0};
-
-  double yr[D][3], Ur[D][36];
-  Vec3 bj[D], bk[D];
-  auto fetch = [&](int slot, int step) {
-    const int i = nx - 1 - (step - lag);
-    const bool act = valid && i >= 0 && i < nx;
-    if (act) {
-      const size_t c = base + i;
-      yr[slot][0] = y[3 * c];
-      yr[slot][1] = y[3 * c + 1];
-      yr[slot][2] = y[3 * c + 2];
-      const double* u = Ug + 36 * c;
-#pragma unroll
-      for (int e = 0; e < 36; ++e) Ur[slot][e] = u[e];
-      bj[slot] = pollJ ? ld3_dev(x2 + 3 * (c + line)) : zero3;
-      bk[slot] = pollK ? ld3_dev(x2 + 3 * (c + plane)) : zero3;
-    }
-  };
-#pragma unroll
-  for (int d = 0; d < D; ++d) fetch(d, d);
-  Vec3 prev = zero3;
-  Vec3 out = zero3;
-  long spin = 0;
-  bool failed = false;
-  for (int s0 = 0; s0 < nsteps && !failed; s0 += D) {
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      const int s = s0 + d;
-      const int i = nx - 1 - (s - lag);
-      const bool act = valid && i >= 0 && i < nx;
-      const Vec3 fj = shfl_down3(out, 1);
-      const Vec3 fk = shfl_down3(out, kTJ);
-      bool ready = !(act && ((pollJ && sent3(bj[d])) || (pollK && sent3(bk[d]))));
-      while (!__all(ready)) {
-        if (++spin > spin_limit) {
-          failed = true;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-        if (!ready) {
-          const size_t c = base + i;
-          if (pollJ) bj[d] = ld3_dev(x2 + 3 * (c + line));
-          if (pollK) bk[d] = ld3_dev(x2 + 3 * (c + plane));
-          ready = !((pollJ && sent3(bj[d])) || (pollK && sent3(bk[d])));
-        }
+// stage-two residual for the grid sweeps: r2 and e0 are also written in the
+// tile layouts (r2 forward, e0 backward), and the face vectors get the
+// sentinel; both ticket counters := 0
+template <int NE>
+__global__ __launch_bounds__(kBlock) void k_stage2_grid(int nx, int ny, int nz, int nrows, int nblk,
+                                                        const int32_t* __restrict__ sptr,
+                                                        const int32_t* __restrict__ col,
+                                                        const double* __restrict__ val, int ea,
+                                                        int eb, const double* __restrict__ e0,
+                                                        const double* __restrict__ r,
+                                                        double* __restrict__ r2t,
+                                                        double* __restrict__ e0t,
+                                                        double* __restrict__ y,
+                                                        double* __restrict__ x2, int* tickets) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    tickets[0] = 0;
+    tickets[1] = 0;
+  }
+  const int row = xcd_block(blockIdx.x, nblk) * kBlock + threadIdx.x;
+  if (row >= nrows) return;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  if (e0) {
+    const int s = row >> 6, lane = row & 63;
+    for (int kq = sptr[s]; kq < sptr[s + 1]; ++kq) {
+      const int c = col[(size_t)kq * 64 + lane];
+      const double* v = val + (size_t)kq * 9 * 64 + lane;
+      const double u = e0[(size_t)c * NE];
+      a0 += v[(0 * 3 + ea) * 64] * u;
+      a1 += v[(1 * 3 + ea) * 64] * u;
+      a2 += v[(2 * 3 + ea) * 64] * u;
+      if (NE == 2) {
+        const double w = e0[(size_t)c * NE + 1];
+        a0 += v[(0 * 3 + eb) * 64] * w;
+        a1 += v[(1 * 3 + eb) * 64] * w;
+        a2 += v[(2 * 3 + eb) * 64] * w;
       }
-      if (failed) break;
-      if (act) {
-        const Vec3 xj = jj == kTJ - 1 ? bj[d] : fj;
-        const Vec3 xk = kk == kTK - 1 ? bk[d] : fk;
-        double a0 = yr[d][0], a1 = yr[d][1], a2 = yr[d][2];
-        mv3_sub(&Ur[d][0], prev, a0, a1, a2);
-        mv3_sub(&Ur[d][9], xj, a0, a1, a2);
-        mv3_sub(&Ur[d][18], xk, a0, a1, a2);
-        const double* ui = &Ur[d][27];
-        const double o0 = ui[0] * a0 + ui[1] * a1 + ui[2] * a2;
-        const double o1 = ui[3] * a0 + ui[4] * a1 + ui[5] * a2;
-        const double o2 = ui[6] * a0 + ui[7] * a1 + ui[8] * a2;
-        const size_t c = base + i;
-        st_dev(x2 + 3 * c, o0);
-        st_dev(x2 + 3 * c + 1, o1);
-        st_dev(x2 + 3 * c + 2, o2);
-        const double ex = e0 ? e0[c * NE] : 0.0;
-        const double ey = (NE == 2 && e0) ? e0[c * NE + 1] : 0.0;
-        z[3 * c] = o0 + (ea == 0 ? ex : 0.0) + (NE == 2 && eb == 0 ? ey : 0.0);
-        z[3 * c + 1] = o1 + (ea == 1 ? ex : 0.0) + (NE == 2 && eb == 1 ? ey : 0.0);
-        z[3 * c + 2] = o2 + (ea == 2 ? ex : 0.0) + (NE == 2 && eb == 2 ? ey : 0.0);
-        prev = {o0, o1, o2};
-        out = prev;
-      }
-      fetch(d, s + D);
     }
   }
-  if (failed && lane == 0) st_dev(err, 1.0);
+  const int i = row % nx, jg = (row / nx) % ny, kg = row / (nx * ny);
+  const int nJ = (ny + kTJ - 1) / kTJ;
+  const int J = jg / kTJ, jj = jg % kTJ, K = kg / kTK, kk = kg % kTK;
+  const size_t t = (size_t)J + (size_t)nJ * K;
+  const int ns = nx + (kTJ - 1) + (kTK - 1);
+  const int lane = jj + kTJ * kk;
+  const size_t frow = t * ns + (i + jj + kk);
+  const size_t brow = t * ns + ((nx - 1 - i) + (kTJ - 1 - jj) + (kTK - 1 - kk));
+  const double* ri = r + 3 * (size_t)row;
+  double* o = r2t + frow * 3 * 64 + lane;
+  o[0] = ri[0] - a0;
+  o[64] = ri[1] - a1;
+  o[128] = ri[2] - a2;
+  if (e0) {
+    double* eo = e0t + brow * NE * 64 + lane;
+    eo[0] = e0[(size_t)row * NE];
+    if (NE == 2) eo[64] = e0[(size_t)row * NE + 1];
+  }
+  const bool face = jj == 0 || jj == kTJ - 1 || kk == 0 || kk == kTK - 1;
+  if (face) {
+    const double s0 = __longlong_as_double((long long)kSentinel);
+    y[3 * (size_t)row] = s0;
+    y[3 * (size_t)row + 1] = s0;
+    y[3 * (size_t)row + 2] = s0;
+    x2[3 * (size_t)row] = s0;
+    x2[3 * (size_t)row + 1] = s0;
+    x2[3 * (size_t)row + 2] = s0;
+  }
+  (void)nz;
 }
 
 // stage-two residual that also prepares the one-launch sweeps: y, x2 :=
@@ -1100,22 +1190,35 @@ void launch_sweep_prepare(int64_t n, double* y, double* x2, int* tickets, hipStr
 }
 
 
-constexpr int kGridPrefetch = 4;
-
-void launch_ilu_fwd_grid(int nx, int ny, int nz, const double* Lg, const double* r2, double* y,
-                         int* tickets, double* err, long spin_limit, hipStream_t st) {
-  const int nJ = (ny + kTJ - 1) / kTJ, nK = (nz + kTK - 1) / kTK;
-  k_ilu_fwd_grid<kGridPrefetch><<<nJ * nK, 64, 0, st>>>(nx, ny, nz, nJ, Lg, r2, y, tickets, err, spin_limit);
+void launch_stage2_grid(int nx, int ny, int nz, const Sell& A, int ne, const int32_t* eidx,
+                        const double* e0, const double* r, double* r2t, double* e0t, double* y,
+                        double* x2, int* tickets, hipStream_t st) {
+  const int g = nblocks(A.nrows, kBlock);
+  if (ne == 2)
+    k_stage2_grid<2><<<g, kBlock, 0, st>>>(nx, ny, nz, A.nrows, g, A.sptr, A.col, A.val, eidx[0], eidx[1],
+                                           e0, r, r2t, e0t, y, x2, tickets);
+  else
+    k_stage2_grid<1><<<g, kBlock, 0, st>>>(nx, ny, nz, A.nrows, g, A.sptr, A.col, A.val, eidx[0], 0,
+                                           e0, r, r2t, e0t, y, x2, tickets);
 }
 
-void launch_ilu_bwd_grid(int nx, int ny, int nz, const double* Ug, const double* y, const double* e0,
+void launch_ilu_fwd_grid(int nx, int ny, int nz, const double* Lt, const double* r2t, double* ytile,
+                         double* y, int* tickets, double* err, long spin_limit, hipStream_t st) {
+  const int nJ = (ny + kTJ - 1) / kTJ, nK = (nz + kTK - 1) / kTK;
+  k_ilu_grid<true, 2><<<nJ * nK, 64, 0, st>>>(nx, ny, nz, nJ, nK, Lt, r2t, ytile, y, nullptr, 0, 0,
+                                              nullptr, tickets, err, spin_limit);
+}
+
+void launch_ilu_bwd_grid(int nx, int ny, int nz, const double* Ut, double* ytile, const double* e0t,
                          int ne, const int32_t* eidx, double* x2, double* z, int* tickets,
                          double* err, long spin_limit, hipStream_t st) {
   const int nJ = (ny + kTJ - 1) / kTJ, nK = (nz + kTK - 1) / kTK;
   if (ne == 2)
-    k_ilu_bwd_grid<kGridPrefetch, 2><<<nJ * nK, 64, 0, st>>>(nx, ny, nz, nJ, nK, Ug, y, e0, eidx[0], eidx[1], x2, z, tickets, err, spin_limit);
+    k_ilu_grid<false, 2><<<nJ * nK, 64, 0, st>>>(nx, ny, nz, nJ, nK, Ut, ytile, nullptr, x2, e0t,
+                                                 eidx[0], eidx[1], z, tickets, err, spin_limit);
   else
-    k_ilu_bwd_grid<kGridPrefetch, 1><<<nJ * nK, 64, 0, st>>>(nx, ny, nz, nJ, nK, Ug, y, e0, eidx[0], 0, x2, z, tickets, err, spin_limit);
+    k_ilu_grid<false, 1><<<nJ * nK, 64, 0, st>>>(nx, ny, nz, nJ, nK, Ut, ytile, nullptr, x2, e0t,
+                                                 eidx[0], 0, z, tickets, err, spin_limit);
 }
 
 int ilu_sf_width(int max_width) {

@@ -66,10 +66,33 @@ int ilu_sf_width(int max_width);  // 0 when the rows are too wide for the one-la
 void launch_stage2_resid_sf(const Sell& A, int ne, const int32_t* eidx, const double* e0,
                             const double* r, double* r2, double* y, double* x2, int* tickets,
                             hipStream_t st);
-// 7-point lexicographic grids: tiled systolic sweeps (Lg: [cell][27], Ug: [cell][36])
-void launch_ilu_fwd_grid(int nx, int ny, int nz, const double* Lg, const double* r2, double* y,
-                         int* tickets, double* err, long spin_limit, hipStream_t st);
-void launch_ilu_bwd_grid(int nx, int ny, int nz, const double* Ug, const double* y, const double* e0,
+// 7-point lexicographic grids: tiled systolic sweeps.  Lt / Ut: per-cell L
+// (27 values) and U + U_ii^-1 (36 values) in the tile layout of grid_tile_slot;
+// ytile: forward results in the backward sweep's tile layout.
+constexpr int kGridTJ = 16, kGridTK = 4;
+inline int grid_nsteps(int nx) { return nx + kGridTJ - 1 + kGridTK - 1; }
+inline int64_t grid_ntiles(int ny, int nz) {
+  return (int64_t)((ny + kGridTJ - 1) / kGridTJ) * ((nz + kGridTK - 1) / kGridTK);
+}
+// slot (in units of 64-lane rows) of cell (i, j, k) in the forward / backward layout
+inline void grid_tile_slot(int nx, int ny, int i, int j, int k, int64_t& fwd_row, int64_t& bwd_row,
+                           int& lane) {
+  const int nJ = (ny + kGridTJ - 1) / kGridTJ;
+  const int J = j / kGridTJ, jj = j % kGridTJ, K = k / kGridTK, kk = k % kGridTK;
+  const int64_t t = J + (int64_t)nJ * K;
+  const int ns = grid_nsteps(nx);
+  lane = jj + kGridTJ * kk;
+  fwd_row = t * ns + (i + jj + kk);
+  bwd_row = t * ns + ((nx - 1 - i) + (kGridTJ - 1 - jj) + (kGridTK - 1 - kk));
+}
+// r2t: stage-two residual in the forward tile layout (3 per slot); e0t: the
+// V-cycle result in the backward tile layout (ne per slot), or null (x1 = 0)
+void launch_stage2_grid(int nx, int ny, int nz, const Sell& A, int ne, const int32_t* eidx,
+                        const double* e0, const double* r, double* r2t, double* e0t, double* y,
+                        double* x2, int* tickets, hipStream_t st);
+void launch_ilu_fwd_grid(int nx, int ny, int nz, const double* Lt, const double* r2t, double* ytile,
+                         double* y, int* tickets, double* err, long spin_limit, hipStream_t st);
+void launch_ilu_bwd_grid(int nx, int ny, int nz, const double* Ut, double* ytile, const double* e0t,
                          int ne, const int32_t* eidx, double* x2, double* z, int* tickets,
                          double* err, long spin_limit, hipStream_t st);
 void launch_ilu_fwd_sf(const Sell& L, int width, const int32_t* perm, const double* r2, double* y,
@@ -77,7 +100,6 @@ void launch_ilu_fwd_sf(const Sell& L, int width, const int32_t* perm, const doub
 void launch_ilu_bwd_sf(const Sell& U, int width, const int32_t* perm, const double* uinv,
                        const double* y, const double* e0, int ne, const int32_t* eidx, double* x2,
                        double* z, int* tickets, double* err, long spin_limit, hipStream_t st);
-
 void launch_prolong_e(int32_t nrows, int ne, const int32_t* eidx, const double* e0, double* x1,
                       hipStream_t st);
 void launch_sweep_prepare(int64_t n, double* y, double* x2, int* tickets, hipStream_t st);
