@@ -582,17 +582,17 @@ __global__ __launch_bounds__(kBlock) void k_sweep_prepare(int64_t n, double* __r
 // --------------------------------------------------------------------------
 // ILU(0) sweeps for a 7-point stencil in lexicographic order (x fastest).
 //
-// One wavefront owns a tile of 16 x 4 x-pencils (lane = jj + 16 kk, pencil
+// One workgroup owns a tile of 16 x 4 x-pencils (lane = jj + 16 kk, pencil
 // (j, k) = (16 J + jj, 4 K + kk)) and walks it as a skewed systolic array: at
 // step s lane (jj, kk) handles cell i = s - jj - kk of its pencil.  The three
 // lower neighbours of that cell were handled one step earlier by the lane
 // itself (i-1), by lane jj-1 (j-1) and by lane kk-1 (k-1), so they arrive in
-// registers or through cross-lane shuffles.  Only lanes on the tile's low
-// faces (jj = 0, kk = 0) read values of another tile; those are polled from
-// the device-coherent, sentinel-filled output as in the one-launch sweeps,
-// prefetched D steps ahead.  Tiles take tickets in (K, J) order, so a tile
-// only waits on tiles that started before it.  The backward sweep is the
-// mirror image (high faces, tiles in reverse order).
+// registers or through cross-lane moves.  Only lanes on the tile's low faces
+// (jj = 0, kk = 0) need values of another tile; those are polled from the
+// device-coherent, sentinel-filled output as in the one-launch sweeps.  Tiles
+// take tickets in (K, J) order, so a tile only waits on tiles that started
+// before it.  The backward sweep is the mirror image (high faces, tiles in
+// reverse order).
 //
 // Matrix data per cell: L = blocks (-x, -y, -z); U = blocks (+x, +y, +z) then
 // U_ii^-1; blocks of absent neighbours are zero.
@@ -616,7 +616,7 @@ __device__ __forceinline__ void mv3_sub(const double* b, const Vec3& x, double& 
   a2 -= b[6] * x.v0 + b[7] * x.v1 + b[8] * x.v2;
 }
 
-// One kernel for both directions.
+// Both directions share one kernel.
 //   FWD: y = L^-1 r2.  M = L blocks (-x, -y, -z), rhs = r2, both in the
 //        forward tile layout.  y goes to `ytile` in the backward tile layout
 //        (all lanes of a forward step land in one backward step: coalesced)
@@ -628,14 +628,7 @@ __device__ __forceinline__ void mv3_sub(const double* b, const Vec3& x, double& 
 //        only low-face lanes (jj = 0, kk = 0) publish x2.
 // Tile layout of per-cell data with NV values: ((tile * nsteps + step) * NV +
 // e) * 64 + lane, tile = J + nJ K, step = the step that handles the cell in
-// this direction; slots of absent cells hold zeros.  The matrix data of the
-// next two steps is in flight while a step computes (two register sets used in
-// turn); the values polled from neighbouring tiles are prefetched kDB steps
-// ahead.  When one of them is not there yet the wave waits until the value kDB
-// steps ahead is there too, so after a stall the tile trails its neighbour far
-// enough for the later prefetches to find published data.
-constexpr int kDB = 4;
-
+// this direction; slots of absent cells hold zeros.
 template <bool FWD, int NE>
 struct GridTile {
   static constexpr int NV = FWD ? 27 : 36;
@@ -645,6 +638,26 @@ struct GridTile {
   int jj, kk;
   const double* pub;
 
+  // tile t of an nJ-wide tile grid, seen by lane `lane`
+  __device__ __forceinline__ void init(int nx_, int ny_, int nz, int nJ, int t, int lane, const double* pub_) {
+    const int J = t % nJ, K = t / nJ;
+    nx = nx_;
+    ny = ny_;
+    jj = lane & (kTJ - 1);
+    kk = lane / kTJ;
+    const int j = J * kTJ + jj, k = K * kTK + kk;
+    valid = j < ny && k < nz;
+    const long line = nx, plane = (long)nx * ny;
+    base = valid ? (long)nx * ((long)j + (long)ny * k) : 0;
+    lag = FWD ? jj + kk : (kTJ - 1 - jj) + (kTK - 1 - kk);
+    nsteps = nx + (kTJ - 1) + (kTK - 1);
+    pollJ = valid && (FWD ? (jj == 0 && j > 0) : (jj == kTJ - 1 && j + 1 < ny));
+    pollK = valid && (FWD ? (kk == 0 && k > 0) : (kk == kTK - 1 && k + 1 < nz));
+    publish = valid && (FWD ? (jj == kTJ - 1 || kk == kTK - 1) : (jj == 0 || kk == 0));
+    offJ = FWD ? -line : line;
+    offK = FWD ? -plane : plane;
+    pub = pub_;
+  }
   __device__ __forceinline__ int cell_i(int step) const { return FWD ? step - lag : nx - 1 - (step - lag); }
   __device__ __forceinline__ bool active(int step) const {
     const int i = cell_i(step);
@@ -662,167 +675,293 @@ struct GridTile {
   }
 };
 
+// j-shift of the systolic array (lane = jj + 16 kk): the j-neighbour is one
+// lane over inside a 16-lane row, a DPP row shift in which the row's edge lane
+// keeps `old` (the value of the neighbouring tile).
+template <bool FWD>
+__device__ __forceinline__ double dpp_row_shift(double x, double old) {
+  constexpr int ctrl = FWD ? 0x111 : 0x101;  // row_shr:1 / row_shl:1
+  const long long xi = __double_as_longlong(x), oi = __double_as_longlong(old);
+  const int lo = __builtin_amdgcn_update_dpp((int)oi, (int)xi, ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(oi >> 32), (int)(xi >> 32), ctrl, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <bool FWD>
+__device__ __forceinline__ Vec3 grid_shift_j(const Vec3& x, const Vec3& old) {
+  return {dpp_row_shift<FWD>(x.v0, old.v0), dpp_row_shift<FWD>(x.v1, old.v1), dpp_row_shift<FWD>(x.v2, old.v2)};
+}
+
+// One lane's place in the sweep and the cell update of a step: m holds the 27
+// off-diagonal block values, ui the 9 of U_ii^-1 (backward), r the right-hand
+// side (3, then NE values of e0 backward); vj and vk are the values of the two
+// other lower (upper) neighbours.
 template <bool FWD, int NE>
-__global__ __launch_bounds__(64) void k_ilu_grid(int nx, int ny, int nz, int nJ, int nK,
-                                                 const double* __restrict__ M,
-                                                 const double* rhs, double* ytile, double* pub,
-                                                 const double* __restrict__ e0t, int ea, int eb,
-                                                 double* __restrict__ z, int* tickets, double* err,
-                                                 long spin_limit) {
-  using G = GridTile<FWD, NE>;
-  constexpr int NV = G::NV;
-  constexpr int NR = FWD ? 3 : 3 + NE;  // rhs values (+ e0 in the backward sweep)
-  __shared__ int s_t;
-  if (threadIdx.x == 0)
+struct GridCell {
+  GridTile<FWD, NE> g;
+  Vec3 prev, last;  // own result one cell earlier / of the last step
+  double* yo;       // forward: this tile's last backward-layout row of ytile
+  double* z;
+  bool has_e0;
+  int ea, eb;
+
+  __device__ __forceinline__ void init(int nx, int ny, int nz, int nJ, int t, int lane, const double* pub,
+                                       double* ytile, const double* e0t, int ea_, int eb_, double* z_) {
+    g.init(nx, ny, nz, nJ, t, lane, pub);
+    const size_t trow = (size_t)t * g.nsteps;
+    yo = FWD ? ytile + (trow + g.nsteps - 1) * 3 * 64 + lane : nullptr;
+    z = z_;
+    has_e0 = e0t != nullptr;
+    ea = ea_;
+    eb = eb_;
+    prev = last = {0.0, 0.0, 0.0};
+  }
+
+  __device__ __forceinline__ void update(int s, const Vec3& vj, const Vec3& vk, const double* m,
+                                         const double* ui, const double* r, double* pub) {
+    if (!g.active(s)) return;
+    double a0 = r[0], a1 = r[1], a2 = r[2];
+    mv3_sub(&m[0], prev, a0, a1, a2);
+    mv3_sub(&m[9], vj, a0, a1, a2);
+    mv3_sub(&m[18], vk, a0, a1, a2);
+    const long c = g.base + g.cell_i(s);
+    if (FWD) {
+      // the backward sweep handles this cell at step nsteps - 1 - s
+      double* yw = yo - (size_t)s * 3 * 64;
+      yw[0] = a0;
+      yw[64] = a1;
+      yw[128] = a2;
+      if (g.publish) {
+        st_dev(pub + 3 * c, a0);
+        st_dev(pub + 3 * c + 1, a1);
+        st_dev(pub + 3 * c + 2, a2);
+      }
+      prev = {a0, a1, a2};
+    } else {
+      const double o0 = ui[0] * a0 + ui[1] * a1 + ui[2] * a2;
+      const double o1 = ui[3] * a0 + ui[4] * a1 + ui[5] * a2;
+      const double o2 = ui[6] * a0 + ui[7] * a1 + ui[8] * a2;
+      if (g.publish) {
+        st_dev(pub + 3 * c, o0);
+        st_dev(pub + 3 * c + 1, o1);
+        st_dev(pub + 3 * c + 2, o2);
+      }
+      const double ex = has_e0 ? r[3] : 0.0;
+      const double ey = (NE == 2 && has_e0) ? r[3 + NE - 1] : 0.0;
+      z[3 * c] = o0 + (ea == 0 ? ex : 0.0) + (NE == 2 && eb == 0 ? ey : 0.0);
+      z[3 * c + 1] = o1 + (ea == 1 ? ex : 0.0) + (NE == 2 && eb == 1 ? ey : 0.0);
+      z[3 * c + 2] = o2 + (ea == 2 ? ex : 0.0) + (NE == 2 && eb == 2 ? ey : 0.0);
+      prev = {o0, o1, o2};
+    }
+    last = prev;
+  }
+};
+
+// The kernel: one workgroup per tile.  Wave 0 runs the systolic steps and
+// reads no global memory; waves 1..H stage each step into a ring of R step
+// slots in LDS (wave l takes steps l - 1, l - 1 + H, ...): the matrix data,
+// right-hand side and e0 go from HBM to the slot directly, and the values of
+// the neighbouring tiles are polled (until the sentinel is gone) and written
+// next to them.  So up to R - 1 steps are staged ahead of wave 0, and wave 0's
+// own memory traffic is its stores.  Hand-over is through workgroup-scope
+// flags with release / acquire fences restricted to LDS:
+//   ready[slot] = step     the slot holds that step;
+//   consumed = n           wave 0 has read the slots of steps < n.
+// A stager of step s first waits for consumed > s - R, wave 0 only waits for
+// a step whose slot it has freed, and the polled tiles only wait on tiles
+// that started earlier, so nothing waits in a cycle.  Every wait is bounded;
+// on failure a wave raises `abort` so the others stop waiting too.
+__device__ __forceinline__ int lds_ld(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_st(int* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local"); }
+__device__ __forceinline__ void lds_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local"); }
+
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) void glb_void;
+
+// copy of N doubles (N a multiple of 64, 16-byte aligned) from global memory
+// straight into LDS by one wave: each instruction moves 64 x 16 bytes, the
+// lanes of a half-used last instruction stay masked
+template <int N>
+__device__ __forceinline__ void wave_copy_to_lds(const double* src, double* dst, int lane) {
+#pragma unroll
+  for (int q = 0; q < (N + 127) / 128; ++q) {
+    if (N % 128 == 0 || q * 128 + 2 * lane < N)
+      __builtin_amdgcn_global_load_lds((glb_void*)(src + q * 128 + 2 * lane), (lds_void*)(dst + q * 128),
+                                       16, 0, 0);
+  }
+}
+
+template <bool FWD, int NE, int H, int R>
+__global__ __launch_bounds__(64 * (H + 1)) void k_ilu_grid(int nx, int ny, int nz, int nJ, int nK,
+                                                               const double* __restrict__ M,
+                                                               const double* rhs, double* ytile,
+                                                               double* pub,
+                                                               const double* __restrict__ e0t,
+                                                               int ea, int eb, double* __restrict__ z,
+                                                               int* tickets, double* err,
+                                                               long spin_limit) {
+  constexpr int NV = GridTile<FWD, NE>::NV;
+  constexpr int NE0 = FWD ? 0 : NE;
+  constexpr int NR = 3 + NE0;
+  // slot: M (NV), rhs (3), e0 (NE0), polled j and k values (3 + 3); x 64 lanes
+  constexpr int OR = NV * 64, OE = (NV + 3) * 64, OF = (NV + NR) * 64;
+  constexpr int SLOT = (NV + NR + 6) * 64;
+  __shared__ double ring[R * SLOT];
+  __shared__ int s_ready[R];
+  __shared__ int s_t, s_consumed, s_abort;
+  if (threadIdx.x == 0) {
     s_t = __hip_atomic_fetch_add(tickets + (FWD ? 0 : 1), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_consumed = 0;
+    s_abort = 0;
+  }
+  if (threadIdx.x < R) s_ready[threadIdx.x] = -1;
   __syncthreads();
   const int t = FWD ? s_t : nJ * nK - 1 - s_t;
-  const int J = t % nJ, K = t / nJ;
-  const int lane = threadIdx.x;
-  G g;
-  g.nx = nx;
-  g.ny = ny;
-  g.jj = lane & (kTJ - 1);
-  g.kk = lane / kTJ;
-  const int j = J * kTJ + g.jj, k = K * kTK + g.kk;
-  g.valid = j < ny && k < nz;
-  const long line = nx, plane = (long)nx * ny;
-  g.base = g.valid ? (long)nx * ((long)j + (long)ny * k) : 0;
-  g.lag = FWD ? g.jj + g.kk : (kTJ - 1 - g.jj) + (kTK - 1 - g.kk);
-  g.nsteps = nx + (kTJ - 1) + (kTK - 1);
-  g.pollJ = g.valid && (FWD ? (g.jj == 0 && j > 0) : (g.jj == kTJ - 1 && j + 1 < ny));
-  g.pollK = g.valid && (FWD ? (g.kk == 0 && k > 0) : (g.kk == kTK - 1 && k + 1 < nz));
-  g.publish = g.valid && (FWD ? (g.jj == kTJ - 1 || g.kk == kTK - 1) : (g.jj == 0 || g.kk == 0));
-  g.offJ = FWD ? -line : line;
-  g.offK = FWD ? -plane : plane;
-  g.pub = pub;
+  // the wave index is uniform per wave: keep it (and the stagers' loops) scalar
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int wait_limit = (int)min(4 * spin_limit, (long)1 << 30);
+  GridCell<FWD, NE> w;
+  w.init(nx, ny, nz, nJ, t, lane, pub, ytile, e0t, ea, eb, z);
+  const GridTile<FWD, NE>& g = w.g;
   const int nsteps = g.nsteps;
-  const Vec3 zero3 = {0.0, 0.0, 0.0};
-
-  // running pointers to this tile's rows of the tile layouts
   const size_t trow = (size_t)t * nsteps;
-  const double* mp = M + trow * NV * 64 + lane;
-  const double* rp = rhs + trow * 3 * 64 + lane;
-  const double* ep = (FWD || !e0t) ? nullptr : e0t + trow * NE * 64 + lane;
-  double* yo = FWD ? ytile + (trow + nsteps - 1) * 3 * 64 + lane : nullptr;
 
-  double ma[NV], mb[NV], ra[NR], rb[NR];
-  auto load = [&](double* m, double* r, int step) {
-    if (step < nsteps) {
-      const double* mm = mp + (size_t)step * NV * 64;
-#pragma unroll
-      for (int e = 0; e < NV; ++e) m[e] = mm[e * 64];
-      const double* rr = rp + (size_t)step * 3 * 64;
-      r[0] = rr[0];
-      r[1] = rr[64];
-      r[2] = rr[128];
-      if (!FWD) {
-        // e0t == nullptr (M2^-1 alone): no P_E e0 term, nothing to read
-        r[3] = 0.0;
-        if (NE == 2) r[4] = 0.0;
-        if (e0t) {
-          const double* ee = ep + (size_t)step * NE * 64;
-          r[3] = ee[0];
-          if (NE == 2) r[4] = ee[64];
-        }
-      }
-    }
-  };
-  Vec3 bj[kDB], bk[kDB];
-#pragma unroll
-  for (int q = 0; q < kDB; ++q) {
-    bj[q] = bk[q] = zero3;
-    g.poll(q, bj[q], bk[q]);
-  }
-  load(ma, ra, 0);
-  load(mb, rb, 1);
-  Vec3 prev = zero3;   // own result one cell earlier along the pencil
-  Vec3 last = zero3;   // own result of the last step, read by the neighbouring lanes
-  long spin = 0;
-  bool failed = false;
-
-  auto step_body = [&](int s, double* m, double* r) {
-    const Vec3 fj = FWD ? shfl_up3(last, 1) : shfl_down3(last, 1);
-    const Vec3 fk = FWD ? shfl_up3(last, kTJ) : shfl_down3(last, kTJ);
-    if (!__all(g.ready(s, bj[0], bk[0]))) {
-      // wait for this step's value and for the one kDB steps ahead
-      for (;;) {
-        bool ok = g.ready(s, bj[0], bk[0]);
-        Vec3 aj = zero3, ak = zero3;
-        g.poll(s + kDB, aj, ak);
-        ok = ok && g.ready(s + kDB, aj, ak);
-        if (__all(ok)) break;
-        if (++spin > spin_limit) {
-          failed = true;
+  // wave 0 runs an even number of steps and reads two slots past them: the
+  // stagers fill steps up to nst + 1 (beyond nsteps - 1 with copies of the
+  // last step's data, no lane active), so no read is conditional
+  const int nst = (nsteps + 1) & ~1;
+  if (wave > 0) {
+    // stager
+    int spin = 0;
+    for (int s = wave - 1; s <= nst + 1; s += H) {
+      while (lds_ld(&s_consumed) <= s - R) {
+        if (lds_ld(&s_abort)) return;
+        if (++spin > wait_limit) {
+          lds_st(&s_abort, 1);
+          if (lane == 0) st_dev(err, 1.0);
           return;
         }
-        __builtin_amdgcn_s_sleep(2);
-        if (!g.ready(s, bj[0], bk[0])) g.poll(s, bj[0], bk[0]);
+        __builtin_amdgcn_s_sleep(1);
       }
-#pragma unroll
-      for (int q = 1; q < kDB; ++q) g.poll(s + q, bj[q], bk[q]);
-    }
-    if (g.active(s)) {
-      // a face lane without a neighbouring tile (domain boundary) has a zero
-      // block there; pass an explicit zero so no stale register enters 0 * x
-      const Vec3 vj = (FWD ? g.jj == 0 : g.jj == kTJ - 1) ? (g.pollJ ? bj[0] : zero3) : fj;
-      const Vec3 vk = (FWD ? g.kk == 0 : g.kk == kTK - 1) ? (g.pollK ? bk[0] : zero3) : fk;
-      double a0 = r[0], a1 = r[1], a2 = r[2];
-      mv3_sub(&m[0], prev, a0, a1, a2);
-      mv3_sub(&m[9], vj, a0, a1, a2);
-      mv3_sub(&m[18], vk, a0, a1, a2);
-      const long c = g.base + g.cell_i(s);
-      if (FWD) {
-        // the backward sweep handles this cell at step nsteps - 1 - s
-        double* yw = yo - (size_t)s * 3 * 64;
-        yw[0] = a0;
-        yw[64] = a1;
-        yw[128] = a2;
-        if (g.publish) {
-          st_dev(pub + 3 * c, a0);
-          st_dev(pub + 3 * c + 1, a1);
-          st_dev(pub + 3 * c + 2, a2);
+      lds_acquire();
+      double* slot = ring + (s % R) * SLOT;
+      const size_t row = trow + min(s, nsteps - 1);
+      wave_copy_to_lds<NV * 64>(M + row * NV * 64, slot, lane);
+      wave_copy_to_lds<3 * 64>(rhs + row * 3 * 64, slot + OR, lane);
+      // without e0 (M2^-1 alone) the slot's e0 part is left as it is: unused
+      if (!FWD && e0t) wave_copy_to_lds<NE0 * 64>(e0t + row * NE0 * 64, slot + OE, lane);
+      // values of the neighbouring tiles, once published.  All face values a
+      // step needs from one neighbour come from one step of that tile, so
+      // while they are missing a single lane waits on one of them and the
+      // whole face is read again once it is there.
+      Vec3 bj = {0.0, 0.0, 0.0}, bk = bj;
+      bool need = g.active(s) && (g.pollJ || g.pollK);
+      for (;;) {
+        if (need) {
+          g.poll(s, bj, bk);
+          need = !g.ready(s, bj, bk);
         }
-        prev = {a0, a1, a2};
-      } else {
-        const double* ui = &m[27];
-        const double o0 = ui[0] * a0 + ui[1] * a1 + ui[2] * a2;
-        const double o1 = ui[3] * a0 + ui[4] * a1 + ui[5] * a2;
-        const double o2 = ui[6] * a0 + ui[7] * a1 + ui[8] * a2;
-        if (g.publish) {
-          st_dev(pub + 3 * c, o0);
-          st_dev(pub + 3 * c + 1, o1);
-          st_dev(pub + 3 * c + 2, o2);
+        const unsigned long long waiting = __ballot(need);
+        if (!waiting) break;
+        const int leader = __builtin_ctzll(waiting);
+        for (;;) {
+          if (lds_ld(&s_abort)) return;
+          if (++spin > wait_limit) {
+            lds_st(&s_abort, 1);
+            if (lane == 0) st_dev(err, 1.0);
+            return;
+          }
+          __builtin_amdgcn_s_sleep(2);
+          bool there = true;
+          if (lane == leader) {
+            const long c = g.base + g.cell_i(s);
+            const double* q = g.pub + 3 * (c + (g.pollJ && sent3(bj) ? g.offJ : g.offK)) + 2;
+            there = !is_sent(ld_dev(q));
+          }
+          if (__all(there)) break;
         }
-        const double ex = e0t ? r[3] : 0.0;
-        const double ey = (NE == 2 && e0t) ? r[NR - 1] : 0.0;
-        z[3 * c] = o0 + (ea == 0 ? ex : 0.0) + (NE == 2 && eb == 0 ? ey : 0.0);
-        z[3 * c + 1] = o1 + (ea == 1 ? ex : 0.0) + (NE == 2 && eb == 1 ? ey : 0.0);
-        z[3 * c + 2] = o2 + (ea == 2 ? ex : 0.0) + (NE == 2 && eb == 2 ? ey : 0.0);
-        prev = {o0, o1, o2};
       }
-      last = prev;
+      double* f = slot + OF + lane;
+      f[0] = bj.v0;
+      f[64] = bj.v1;
+      f[128] = bj.v2;
+      f[192] = bk.v0;
+      f[256] = bk.v1;
+      f[320] = bk.v2;
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the copies have landed in LDS
+      lds_release();
+      lds_st(&s_ready[s % R], s);
     }
-    // rotate the polled-value ring and prefetch kDB steps ahead
-#pragma unroll
-    for (int q = 0; q + 1 < kDB; ++q) {
-      bj[q] = bj[q + 1];
-      bk[q] = bk[q + 1];
-    }
-    g.poll(s + kDB, bj[kDB - 1], bk[kDB - 1]);
-  };
-
-  for (int s = 0; s < nsteps; s += 2) {
-    step_body(s, ma, ra);
-    if (failed) break;
-    load(ma, ra, s + 2);
-    if (s + 1 < nsteps) {
-      step_body(s + 1, mb, rb);
-      if (failed) break;
-      load(mb, rb, s + 3);
-    }
+    return;
   }
-  if (failed && lane == 0) st_dev(err, 1.0);
+
+  // wave 0: the systolic sweep.  A step first sends its k-shift through the
+  // LDS crossbar, then issues the reads of the next step's slot and the ready
+  // flag of the step after it, and computes while they are in flight; the
+  // j-shift is a DPP move whose edge lanes keep the polled value.
+  double ma[NV], mb[NV], ra[NR], rb[NR];
+  Vec3 ja, ka, jb, kb;
+  const bool kedge = FWD ? g.kk == 0 : g.kk == kTK - 1;
+  auto wait_ready = [&](int s) __attribute__((always_inline)) -> bool {
+    const int slot = s % R;
+    int sp = 0;
+    while (lds_ld(&s_ready[slot]) != s) {
+      if (lds_ld(&s_abort) || ++sp > wait_limit) return false;
+      __builtin_amdgcn_s_sleep(1);
+    }
+    return true;
+  };
+  // (the caller has seen the ready flag of step s and fenced)
+  auto read = [&](double* m, double* r, Vec3& bj, Vec3& bk, int s) __attribute__((always_inline)) {
+    const double* sl = ring + (s % R) * SLOT + lane;
+#pragma unroll
+    for (int e = 0; e < NV; ++e) m[e] = sl[e * 64];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) r[q] = sl[OR + q * 64];
+    bj = {sl[OF], sl[OF + 64], sl[OF + 128]};
+    bk = {sl[OF + 192], sl[OF + 256], sl[OF + 320]};
+  };
+  auto consumed = [&](int n) __attribute__((always_inline)) {
+    lds_release();
+    lds_st(&s_consumed, n);
+  };
+  // step s on (m, r, bj, bk) while the slot of step s + 1 is read into
+  // (mn, rn, bjn, bkn); returns the ready flag of step s + 2
+  auto step = [&](int s, const double* m, const double* r, const Vec3& bj, const Vec3& bk, double* mn,
+                  double* rn, Vec3& bjn, Vec3& bkn) __attribute__((always_inline)) -> int {
+    const Vec3 fk = FWD ? shfl_up3(w.last, kTJ) : shfl_down3(w.last, kTJ);
+    __builtin_amdgcn_sched_barrier(0);
+    read(mn, rn, bjn, bkn, s + 1);
+    const int f = lds_ld(&s_ready[(s + 2) % R]);
+    __builtin_amdgcn_sched_barrier(0);
+    const Vec3 vj = grid_shift_j<FWD>(w.last, bj);
+    w.update(s, vj, kedge ? bk : fk, m, m + 27, r, pub);
+    consumed(s + 1);
+    return f;
+  };
+  bool ok = wait_ready(0);
+  if (ok) {
+    lds_acquire();
+    read(ma, ra, ja, ka, 0);
+    ok = wait_ready(1);
+    lds_acquire();
+  }
+  for (int s = 0; ok && s < nst; s += 2) {
+    int f = step(s, ma, ra, ja, ka, mb, rb, jb, kb);
+    if (f != s + 2 && !(ok = wait_ready(s + 2))) break;
+    lds_acquire();
+    f = step(s + 1, mb, rb, jb, kb, ma, ra, ja, ka);
+    if (f != s + 3 && !(ok = wait_ready(s + 3))) break;
+    lds_acquire();
+  }
+  if (!ok) {
+    lds_st(&s_abort, 1);
+    if (lane == 0) st_dev(err, 1.0);
+  }
 }
 
 // stage-two residual for the grid sweeps: r2 and e0 are also written in the
@@ -1202,11 +1341,15 @@ void launch_stage2_grid(int nx, int ny, int nz, const Sell& A, int ne, const int
                                            e0, r, r2t, e0t, y, x2, tickets);
 }
 
+// workgroup: the sweeping wave and kGridStagers staging waves; ring slots:
+// as many as fit in LDS (18 KB forward, 24 KB backward per slot)
+constexpr int kGridStagers = 3;
+
 void launch_ilu_fwd_grid(int nx, int ny, int nz, const double* Lt, const double* r2t, double* ytile,
                          double* y, int* tickets, double* err, long spin_limit, hipStream_t st) {
   const int nJ = (ny + kTJ - 1) / kTJ, nK = (nz + kTK - 1) / kTK;
-  k_ilu_grid<true, 2><<<nJ * nK, 64, 0, st>>>(nx, ny, nz, nJ, nK, Lt, r2t, ytile, y, nullptr, 0, 0,
-                                              nullptr, tickets, err, spin_limit);
+  k_ilu_grid<true, 2, kGridStagers, 8><<<nJ * nK, 64 * (kGridStagers + 1), 0, st>>>(
+      nx, ny, nz, nJ, nK, Lt, r2t, ytile, y, nullptr, 0, 0, nullptr, tickets, err, spin_limit);
 }
 
 void launch_ilu_bwd_grid(int nx, int ny, int nz, const double* Ut, double* ytile, const double* e0t,
@@ -1214,11 +1357,11 @@ void launch_ilu_bwd_grid(int nx, int ny, int nz, const double* Ut, double* ytile
                          double* err, long spin_limit, hipStream_t st) {
   const int nJ = (ny + kTJ - 1) / kTJ, nK = (nz + kTK - 1) / kTK;
   if (ne == 2)
-    k_ilu_grid<false, 2><<<nJ * nK, 64, 0, st>>>(nx, ny, nz, nJ, nK, Ut, ytile, nullptr, x2, e0t,
-                                                 eidx[0], eidx[1], z, tickets, err, spin_limit);
+    k_ilu_grid<false, 2, kGridStagers, 6><<<nJ * nK, 64 * (kGridStagers + 1), 0, st>>>(
+        nx, ny, nz, nJ, nK, Ut, ytile, nullptr, x2, e0t, eidx[0], eidx[1], z, tickets, err, spin_limit);
   else
-    k_ilu_grid<false, 1><<<nJ * nK, 64, 0, st>>>(nx, ny, nz, nJ, nK, Ut, ytile, nullptr, x2, e0t,
-                                                 eidx[0], 0, z, tickets, err, spin_limit);
+    k_ilu_grid<false, 1, kGridStagers, 6><<<nJ * nK, 64 * (kGridStagers + 1), 0, st>>>(
+        nx, ny, nz, nJ, nK, Ut, ytile, nullptr, x2, e0t, eidx[0], 0, z, tickets, err, spin_limit);
 }
 
 int ilu_sf_width(int max_width) {
