@@ -93,6 +93,9 @@ def main():
     ap.add_argument("--workload", default="grid250x250x50")
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run a plain device copy of MIB MiB (three times), the "
+                         "reference dispatch for scaling HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -117,6 +120,15 @@ def main():
     b = torch.tensor(c.b, device=dev)
     x = torch.zeros_like(b)
     kw = dict(restart=args.restart, flexible=True, rtol=c.tol)
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {args.copy_calibration} MiB")
+        del src, dst
     setup_s = None
     for w in range(args.warmup):
         info = s.gmres_solve(b, x, **kw)

@@ -80,6 +80,10 @@ typedef struct {
                                 through cptr_export; apply/solve return CPTR_E_STATE) */
   int32_t setup_threads;     /* host threads for setup; 0 = min(16, hardware threads) */
   int32_t ilu_sweep;         /* CPTR_ILU_SWEEP_*: how the ILU(0) triangular solves run */
+  int32_t agg_levels;        /* AMG levels coarsened aggressively (the "aggregate level" of
+                                Sec. 3.1): a second first pass over the C points on the
+                                distance-two strength graph, multipass interpolation, no
+                                truncation; default 1, 0 = none */
 } cptr_setup_opts;
 
 enum {

@@ -52,6 +52,11 @@ def lib():
         L.or_rs_first_pass.argtypes = [C.c_int, lp, ip, ip]
         L.or_extpi.restype = P
         L.or_extpi.argtypes = [C.c_int, lp, ip, dp, lp, ip, ip, ip, C.c_int]
+        L.or_strength2.restype = P
+        L.or_strength2.argtypes = [C.c_int, lp, ip, ip]
+        L.or_aggressive_split.argtypes = [C.c_int, lp, ip, ip]
+        L.or_multipass.restype = P
+        L.or_multipass.argtypes = [C.c_int, lp, ip, dp, lp, ip, ip, ip]
         L.or_amg_setup.argtypes = [C.c_int, lp, ip, dp, ip, P, C.POINTER(P)]
         L.or_amg_nlevels.argtypes = [P]
         L.or_amg_get.restype = P
@@ -82,10 +87,12 @@ def lib():
 
 class AmgOpts(C.Structure):
     _fields_ = [("theta", C.c_double), ("max_row_sum", C.c_double),
-                ("max_levels", C.c_int), ("max_coarse", C.c_int), ("pmax", C.c_int)]
+                ("max_levels", C.c_int), ("max_coarse", C.c_int), ("pmax", C.c_int),
+                ("agg_levels", C.c_int)]
 
-    def __init__(self, theta=0.25, max_row_sum=0.9, max_levels=25, max_coarse=9, pmax=4):
-        super().__init__(theta, max_row_sum, max_levels, max_coarse, pmax)
+    def __init__(self, theta=0.25, max_row_sum=0.9, max_levels=25, max_coarse=9, pmax=4,
+                 agg_levels=1):
+        super().__init__(theta, max_row_sum, max_levels, max_coarse, pmax, agg_levels)
 
 
 class GmresOpts(C.Structure):
@@ -182,6 +189,28 @@ def extpi(A, S, cf, func, pmax=0):
     cf, f = _i32(cf), _i32(func)
     return _take_mat(lib().or_extpi(n, _l(rp), _i(ci), _d(v), _l(srp), _i(sci), _i(cf),
                                     _i(f), pmax))
+
+
+def strength2(S, cf):
+    """Distance-two strength among the C points of cf (rows/columns = C points in order)."""
+    n, rp, ci, _ = _csr_parts(S)
+    cf = _i32(cf)
+    return _take_mat(lib().or_strength2(n, _l(rp), _i(ci), _i(cf)))
+
+
+def aggressive_split(S):
+    n, rp, ci, _ = _csr_parts(S)
+    cf = np.zeros(n, dtype=np.int32)
+    lib().or_aggressive_split(n, _l(rp), _i(ci), _i(cf))
+    return cf
+
+
+def multipass(A, S, cf, func):
+    n, rp, ci, v = _csr_parts(A)
+    _, srp, sci, _ = _csr_parts(S)
+    cf, f = _i32(cf), _i32(func)
+    return _take_mat(lib().or_multipass(n, _l(rp), _i(ci), _d(v), _l(srp), _i(sci), _i(cf),
+                                        _i(f)))
 
 
 # ----------------------------------------------------------------- AMG

@@ -523,6 +523,205 @@ or_mat *or_extpi(int n, const long *rp, const int *ci, const double *v,
 }
 
 /* ------------------------------------------------------------------ */
+/* Aggressive coarsening: the "aggregate level" of Sec. 3.1             */
+/* ------------------------------------------------------------------ */
+/* Distance-two strength among the C points of a first pass: for C points
+ * i != j, j is in S2_i when i depends strongly on j directly (j in S_i) or
+ * through one intermediate point of any kind (k in S_i and j in S_k).  One
+ * such path is enough.  Rows and columns are the C points numbered in
+ * ascending order of their original index; each row is sorted. */
+or_mat *or_strength2(int n, const long *srp, const int *sci, const int *cf) {
+  int *cmap = xmalloc(sizeof(int) * (size_t)(n ? n : 1));
+  int nc = 0;
+  for (int i = 0; i < n; i++) cmap[i] = cf[i] == 1 ? nc++ : -1;
+  int *mark = xmalloc(sizeof(int) * (size_t)(n ? n : 1));
+  for (int i = 0; i < n; i++) mark[i] = -1;
+  long cap = 16, nnz = 0;
+  long *rp2 = xcalloc((size_t)nc + 1, sizeof(long));
+  int *ci2 = xmalloc(sizeof(int) * (size_t)cap);
+  int row = 0;
+  for (int i = 0; i < n; i++) {
+    if (cf[i] != 1) continue;
+    long start = nnz;
+    for (long a = srp[i]; a < srp[i + 1]; a++) {
+      int k = sci[a];
+      /* paths of length one (to k) and two (through k) */
+      int nk = (int)(srp[k + 1] - srp[k]);
+      for (int b = -1; b < nk; b++) {
+        int j = b < 0 ? k : sci[srp[k] + b];
+        if (j == i || cf[j] != 1 || mark[j] == i) continue;
+        mark[j] = i;
+        if (nnz == cap) {
+          cap *= 2;
+          ci2 = realloc(ci2, sizeof(int) * (size_t)cap);
+          if (!ci2) abort();
+        }
+        ci2[nnz++] = cmap[j];
+      }
+    }
+    qsort(ci2 + start, (size_t)(nnz - start), sizeof(int), cmp_int);
+    rp2[++row] = nnz;
+  }
+  or_mat *s2 = mat_from(nc, nc, rp2, ci2, NULL);
+  free(rp2);
+  free(ci2);
+  free(mark);
+  free(cmap);
+  return s2;
+}
+
+/* Aggressive C/F split: a first pass on S gives C1; a second first pass over
+ * the C1 points with the distance-two strength S2 gives C2, the final C
+ * points.  Everything else is F.  cf: 1 = C, -1 = F. */
+void or_aggressive_split(int n, const long *srp, const int *sci, int *cf) {
+  int *cf1 = xmalloc(sizeof(int) * (size_t)(n ? n : 1));
+  or_rs_first_pass(n, srp, sci, cf1);
+  or_mat *s2 = or_strength2(n, srp, sci, cf1);
+  int *cf2 = xmalloc(sizeof(int) * (size_t)(s2->n ? s2->n : 1));
+  or_rs_first_pass(s2->n, s2->rp, s2->ci, cf2);
+  for (int i = 0, c = 0; i < n; i++) {
+    if (cf1[i] == 1)
+      cf[i] = cf2[c++] == 1 ? 1 : -1;
+    else
+      cf[i] = -1;
+  }
+  or_mat_free(s2);
+  free(cf2);
+  free(cf1);
+}
+
+/* Multipass interpolation (Stueben, "A review of algebraic multigrid", 2001)
+ * for an aggressive split.  In row i let neg(a) = a when a and a_ii have
+ * opposite signs (else 0) and pos(a) = a - neg(a); N_i are the off-diagonal
+ * entries of i's own function (unknown approach) and P_i a set of strong
+ * neighbours that already have interpolation rows.  Then
+ *   alpha_i = sum_{k in N_i} neg(a_ik) / sum_{k in P_i} neg(a_ik),
+ *   d_i     = a_ii + sum_{k in N_i} pos(a_ik),
+ *   c_ik    = -alpha_i a_ik / d_i                 (k in P_i).
+ * Pass 1 takes every F point with strong C neighbours, P_i = those, and sets
+ * w_ij = c_ij.  Pass m > 1 takes every F point not yet handled that has
+ * strong neighbours handled in earlier passes, P_i = those, and sets
+ * w_ij = sum_{k in P_i} c_ik w_kj.  C rows are identity.  A row with d_i = 0
+ * is empty (the point still counts as handled); F points never reached get
+ * empty rows.  The rows are not truncated.  Sums run over row i in column
+ * order; the terms of w_ij accumulate in increasing k. */
+typedef struct {
+  int *c;
+  double *w;
+  int n;
+} prow;
+or_mat *or_multipass(int n, const long *rp, const int *ci, const double *v,
+                     const long *srp, const int *sci, const int *cf, const int *func) {
+  int *cmap = xmalloc(sizeof(int) * (size_t)(n ? n : 1));
+  int nc = 0;
+  for (int i = 0; i < n; i++) cmap[i] = cf[i] == 1 ? nc++ : -1;
+  int *pass = xmalloc(sizeof(int) * (size_t)(n ? n : 1)); /* 0 = C, m = pass, -1 = none */
+  for (int i = 0; i < n; i++) pass[i] = cf[i] == 1 ? 0 : -1;
+  prow *rows = xcalloc((size_t)(n ? n : 1), sizeof(prow));
+  int *inp = xmalloc(sizeof(int) * (size_t)(n ? n : 1));
+  for (int i = 0; i < n; i++) inp[i] = -1;
+  double *acc = xcalloc((size_t)(nc ? nc : 1), sizeof(double));
+  int *touched = xmalloc(sizeof(int) * (size_t)(nc ? nc : 1));
+  int *seen = xmalloc(sizeof(int) * (size_t)(nc ? nc : 1));
+  for (int j = 0; j < nc; j++) seen[j] = -1;
+  for (int i = 0; i < n; i++)
+    if (cf[i] == 1) {
+      rows[i].c = xmalloc(sizeof(int));
+      rows[i].w = xmalloc(sizeof(double));
+      rows[i].c[0] = cmap[i];
+      rows[i].w[0] = 1.0;
+      rows[i].n = 1;
+    }
+  for (int m = 1;; m++) {
+    /* the points of pass m, chosen from the passes before it */
+    int *now = xmalloc(sizeof(int) * (size_t)(n ? n : 1));
+    int nnow = 0;
+    for (int i = 0; i < n; i++) {
+      if (pass[i] != -1) continue;
+      for (long a = srp[i]; a < srp[i + 1]; a++)
+        if (pass[sci[a]] != -1 && pass[sci[a]] < m) {
+          now[nnow++] = i;
+          break;
+        }
+    }
+    if (nnow == 0) {
+      free(now);
+      break;
+    }
+    for (int t = 0; t < nnow; t++) {
+      int i = now[t];
+      for (long a = srp[i]; a < srp[i + 1]; a++)
+        if (pass[sci[a]] != -1 && pass[sci[a]] < m) inp[sci[a]] = i;
+      double aii = 0.0, negn = 0.0, posn = 0.0, negp = 0.0;
+      for (long k = rp[i]; k < rp[i + 1]; k++)
+        if (ci[k] == i) aii = v[k];
+      for (long k = rp[i]; k < rp[i + 1]; k++) {
+        int j = ci[k];
+        if (j == i || func[j] != func[i]) continue;
+        int opp = (aii < 0.0) ? v[k] > 0.0 : v[k] < 0.0;
+        if (opp)
+          negn += v[k];
+        else
+          posn += v[k];
+        if (inp[j] == i && opp) negp += v[k];
+      }
+      double d = aii + posn;
+      int nt = 0;
+      if (d != 0.0 && negp != 0.0) {
+        double alpha = negn / negp;
+        for (long k = rp[i]; k < rp[i + 1]; k++) {
+          int q = ci[k];
+          if (q == i || func[q] != func[i] || inp[q] != i) continue;
+          double c = -alpha * v[k] / d;
+          const prow *rq = &rows[q];
+          for (int e = 0; e < rq->n; e++) {
+            int j = rq->c[e];
+            if (seen[j] != i) {
+              seen[j] = i;
+              acc[j] = 0.0;
+              touched[nt++] = j;
+            }
+            acc[j] += c * rq->w[e];
+          }
+        }
+      }
+      qsort(touched, (size_t)nt, sizeof(int), cmp_int);
+      rows[i].c = xmalloc(sizeof(int) * (size_t)(nt ? nt : 1));
+      rows[i].w = xmalloc(sizeof(double) * (size_t)(nt ? nt : 1));
+      rows[i].n = nt;
+      for (int e = 0; e < nt; e++) {
+        rows[i].c[e] = touched[e];
+        rows[i].w[e] = acc[touched[e]];
+      }
+    }
+    for (int t = 0; t < nnow; t++) pass[now[t]] = m;
+    free(now);
+  }
+  long nnz = 0;
+  for (int i = 0; i < n; i++) nnz += rows[i].n;
+  or_mat *p = mat_new(n, nc, nnz);
+  long q = 0;
+  for (int i = 0; i < n; i++) {
+    for (int e = 0; e < rows[i].n; e++) {
+      p->ci[q] = rows[i].c[e];
+      p->v[q] = rows[i].w[e];
+      q++;
+    }
+    p->rp[i + 1] = q;
+    free(rows[i].c);
+    free(rows[i].w);
+  }
+  free(rows);
+  free(seen);
+  free(touched);
+  free(acc);
+  free(inp);
+  free(pass);
+  free(cmap);
+  return p;
+}
+
+/* ------------------------------------------------------------------ */
 /* AMG hierarchy and V-cycle                                           */
 /* ------------------------------------------------------------------ */
 #define OR_MAXLEV 64
@@ -542,6 +741,7 @@ void or_amg_opts_default(or_amg_opts *o) {
   o->max_levels = 25;
   o->max_coarse = 9;
   o->pmax = 4;
+  o->agg_levels = 1;
 }
 
 /* l1-Jacobi (Baker, Falgout, Kolev, Yang 2011) with one point per block:
@@ -623,7 +823,8 @@ void or_amg_free(or_amg *a) {
 
 /* Coarsen while the level has more than max_coarse rows and fewer than
  * max_levels levels exist; stop early when a split gives no C point or only
- * C points.  A_{l+1} = R_l A_l P_l with R_l = P_l^T (Galerkin), coarse
+ * C points.  The first agg_levels levels use the aggressive split with
+ * multipass interpolation, the others the first pass with extended+i.  A_{l+1} = R_l A_l P_l with R_l = P_l^T (Galerkin), coarse
  * function labels inherited from the C points. */
 int or_amg_setup(int n, const long *rp, const int *ci, const double *v,
                  const int *func, const or_amg_opts *o_in, or_amg **out) {
@@ -644,7 +845,11 @@ int or_amg_setup(int n, const long *rp, const int *ci, const double *v,
     if (A->n <= o.max_coarse || l + 1 >= o.max_levels) break;
     or_mat *s = or_strength(A->n, A->rp, A->ci, A->v, a->func[l], o.theta, o.max_row_sum);
     int *cf = xmalloc(sizeof(int) * (size_t)A->n);
-    or_rs_first_pass(A->n, s->rp, s->ci, cf);
+    const int agg = l < o.agg_levels;
+    if (agg)
+      or_aggressive_split(A->n, s->rp, s->ci, cf);
+    else
+      or_rs_first_pass(A->n, s->rp, s->ci, cf);
     int nc = 0;
     for (int i = 0; i < A->n; i++) nc += cf[i] == 1;
     if (nc == 0 || nc == A->n) {
@@ -652,7 +857,8 @@ int or_amg_setup(int n, const long *rp, const int *ci, const double *v,
       or_mat_free(s);
       break;
     }
-    or_mat *p = or_extpi(A->n, A->rp, A->ci, A->v, s->rp, s->ci, cf, a->func[l], o.pmax);
+    or_mat *p = agg ? or_multipass(A->n, A->rp, A->ci, A->v, s->rp, s->ci, cf, a->func[l])
+                    : or_extpi(A->n, A->rp, A->ci, A->v, s->rp, s->ci, cf, a->func[l], o.pmax);
     or_mat_free(s);
     or_mat *r = mat_transpose(p);
     or_mat *ap = mat_mul(A, p);

@@ -53,6 +53,13 @@ void or_rs_first_pass(int n, const long *srp, const int *sci, int *cf);
 or_mat *or_extpi(int n, const long *rp, const int *ci, const double *v,
                  const long *srp, const int *sci, const int *cf, const int *func,
                  int pmax);
+/* distance-two strength among the C points of cf (rows = C points in order) */
+or_mat *or_strength2(int n, const long *srp, const int *sci, const int *cf);
+/* aggressive split: first pass, then a first pass over C with or_strength2 */
+void or_aggressive_split(int n, const long *srp, const int *sci, int *cf);
+/* multipass interpolation for a split (no truncation) */
+or_mat *or_multipass(int n, const long *rp, const int *ci, const double *v,
+                     const long *srp, const int *sci, const int *cf, const int *func);
 
 typedef struct {
   double theta;        /* strength threshold, 0.25 */
@@ -60,6 +67,7 @@ typedef struct {
   int max_levels;      /* 25 */
   int max_coarse;      /* 9 */
   int pmax;            /* 4 */
+  int agg_levels;      /* 1: levels coarsened aggressively (multipass interpolation) */
 } or_amg_opts;
 void or_amg_opts_default(or_amg_opts *o);
 

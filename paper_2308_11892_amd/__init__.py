@@ -44,7 +44,7 @@ class cptr_setup_opts(C.Structure):
                 ("max_levels", C.c_int32), ("max_coarse", C.c_int32),
                 ("p_max_elmts", C.c_int32), ("restriction", C.c_int32),
                 ("host_only", C.c_int32), ("setup_threads", C.c_int32),
-                ("ilu_sweep", C.c_int32)]
+                ("ilu_sweep", C.c_int32), ("agg_levels", C.c_int32)]
 
 
 class cptr_solve_opts(C.Structure):

@@ -618,6 +618,7 @@ void cptr_setup_opts_default(cptr_setup_opts* o) {
   o->host_only = 0;
   o->setup_threads = 0;
   o->ilu_sweep = CPTR_ILU_SWEEP_AUTO;
+  o->agg_levels = 1;
 }
 
 void cptr_solve_opts_default(cptr_solve_opts* o) {
@@ -657,6 +658,7 @@ cptr_status cptr_setup(const cptr_bsr* A, int32_t block_size, const int32_t* ell
   if (o.ilu_sweep < 0 || o.ilu_sweep > 3)
     return (cptr_status)fail(nullptr, CPTR_E_INVALID, "ilu_sweep must be 0, 1, 2 or 3");
   if (o.max_levels < 1 || o.max_levels > 64 || o.max_coarse < 1 || o.p_max_elmts < 0 ||
+      o.agg_levels < 0 ||
       !(o.strong_threshold >= 0.0) || !(o.max_row_sum > 0.0))
     return (cptr_status)fail(nullptr, CPTR_E_INVALID, "setup options out of range");
   if (A->n_block_rows <= 0 || A->nnz_blocks <= 0 || A->nnz_blocks >= INT32_MAX)
@@ -702,6 +704,7 @@ cptr_status cptr_setup(const cptr_bsr* A, int32_t block_size, const int32_t* ell
   prm.max_levels = o.max_levels;
   prm.max_coarse = o.max_coarse;
   prm.pmax = o.p_max_elmts;
+  prm.agg_levels = o.agg_levels;
   prm.quasi_impes = o.restriction == CPTR_RESTRICT_QUASI_IMPES;
   unsigned hw = std::thread::hardware_concurrency();
   prm.threads = o.setup_threads > 0 ? o.setup_threads : (int)std::min<unsigned>(16, hw ? hw : 1);

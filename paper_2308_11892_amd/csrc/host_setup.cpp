@@ -127,14 +127,15 @@ static Csr transpose(const Csr& a, int threads) {
   t.rp.assign(t.n + 1, 0);
   for (int64_t k = 0; k < a.nnz(); ++k) ++t.rp[a.ci[k] + 1];
   for (int32_t j = 0; j < t.n; ++j) t.rp[j + 1] += t.rp[j];
+  const bool values = !a.v.empty();  // a pattern-only matrix stays pattern-only
   t.ci.resize(a.nnz());
-  t.v.resize(a.nnz());
+  t.v.resize(values ? a.nnz() : 0);
   std::vector<int64_t> fill(t.rp.begin(), t.rp.end() - 1);
   for (int32_t i = 0; i < a.n; ++i)
     for (int64_t k = a.rp[i]; k < a.rp[i + 1]; ++k) {
       const int64_t p = fill[a.ci[k]]++;
       t.ci[p] = i;
-      t.v[p] = a.v[k];
+      if (values) t.v[p] = a.v[k];
     }
   return t;
 }
@@ -219,6 +220,200 @@ std::vector<int32_t> first_pass_split(const Csr& S) {
   for (auto& x : cf)
     if (x == 0) x = -1;
   return cf;
+}
+
+// ---------------------------------------------------------------------------
+// Aggressive coarsening (the "aggregate level" of Sec. 3.1).  Among the C
+// points of a first pass, C point j is a distance-two strong dependency of C
+// point i when i depends strongly on j directly or through one intermediate
+// point of any kind; a second first pass over the C points on that graph keeps
+// the final C points.  Rows of the distance-two graph are the C points in
+// ascending order, each row sorted.
+Csr distance_two_strength(const Csr& S, const std::vector<int32_t>& cf, int threads) {
+  const int32_t n = S.n;
+  std::vector<int32_t> cidx(n, -1), cpts;
+  for (int32_t i = 0; i < n; ++i)
+    if (cf[i] == 1) {
+      cidx[i] = (int32_t)cpts.size();
+      cpts.push_back(i);
+    }
+  const int32_t nc = (int32_t)cpts.size();
+  const int nthreads = std::max(1, threads);
+  std::vector<std::vector<int32_t>> part(nthreads);
+  std::vector<int64_t> len(nc + 1, 0);
+  parallel_for(nthreads, nc, [&](int64_t lo, int64_t hi, int t) {
+    std::vector<int32_t> seen(n, -1);
+    auto& out = part[t];
+    for (int64_t r = lo; r < hi; ++r) {
+      const int32_t i = cpts[r];
+      const size_t start = out.size();
+      auto take = [&](int32_t j) {
+        if (j != i && cf[j] == 1 && seen[j] != i) {
+          seen[j] = i;
+          out.push_back(cidx[j]);
+        }
+      };
+      for (int64_t a = S.rp[i]; a < S.rp[i + 1]; ++a) {
+        const int32_t k = S.ci[a];
+        take(k);
+        for (int64_t b = S.rp[k]; b < S.rp[k + 1]; ++b) take(S.ci[b]);
+      }
+      std::sort(out.begin() + start, out.end());
+      len[r + 1] = (int64_t)(out.size() - start);
+    }
+  });
+  Csr S2;
+  S2.n = S2.m = nc;
+  S2.rp.assign(nc + 1, 0);
+  for (int32_t r = 0; r < nc; ++r) S2.rp[r + 1] = S2.rp[r] + len[r + 1];
+  S2.ci.reserve(S2.rp[nc]);
+  for (auto& p : part) S2.ci.insert(S2.ci.end(), p.begin(), p.end());
+  return S2;
+}
+
+std::vector<int32_t> aggressive_split(const Csr& S, int threads) {
+  std::vector<int32_t> cf1 = first_pass_split(S);
+  const Csr S2 = distance_two_strength(S, cf1, threads);
+  const std::vector<int32_t> cf2 = first_pass_split(S2);
+  std::vector<int32_t> cf(S.n, -1);
+  for (int32_t i = 0, c = 0; i < S.n; ++i)
+    if (cf1[i] == 1) cf[i] = cf2[c++] == 1 ? 1 : -1;
+  return cf;
+}
+
+// ---------------------------------------------------------------------------
+// Multipass interpolation (Stueben 2001) for the aggressive level, within one
+// unknown type.  F points are handled in passes: pass 1 takes the F points
+// with strong C points, pass m > 1 the remaining F points with strong points
+// handled in earlier passes; P_i = those strong points.  In row i, with
+// "negative" meaning of sign opposite to a_ii:
+//   alpha = (negative same-type off-diagonal sum) / (negative sum over P_i),
+//   d     = a_ii + (the rest of the same-type off-diagonal sum),
+//   c_k   = -alpha a_ik / d  for k in P_i,   w_ij = sum_k c_k w_kj
+// (w_kj = identity for C points).  Sums run over row i in column order and the
+// terms of w_ij in increasing k, which is also the oracle's order.  A row with
+// d = 0 is empty; unreached F points get empty rows; no truncation.
+Csr multipass_interp(const Csr& A, const Csr& S, const std::vector<int32_t>& cf,
+                     const std::vector<int32_t>& func, int threads) {
+  const int32_t n = A.n;
+  std::vector<int32_t> cidx(n, -1);
+  int32_t nc = 0;
+  for (int32_t i = 0; i < n; ++i)
+    if (cf[i] == 1) cidx[i] = nc++;
+  std::vector<int32_t> pass(n, -1);
+  // rows live in one growing store: row i = [start[i], start[i] + len[i])
+  std::vector<int64_t> start(n, 0), len(n, 0);
+  std::vector<int32_t> sc;
+  std::vector<double> sv;
+  for (int32_t i = 0; i < n; ++i)
+    if (cf[i] == 1) {
+      pass[i] = 0;
+      start[i] = (int64_t)sc.size();
+      len[i] = 1;
+      sc.push_back(cidx[i]);
+      sv.push_back(1.0);
+    }
+  const int nthreads = std::max(1, threads);
+  for (int m = 1;; ++m) {
+    std::vector<int32_t> now;
+    for (int32_t i = 0; i < n; ++i) {
+      if (pass[i] != -1) continue;
+      for (int64_t a = S.rp[i]; a < S.rp[i + 1]; ++a)
+        if (pass[S.ci[a]] != -1 && pass[S.ci[a]] < m) {
+          now.push_back(i);
+          break;
+        }
+    }
+    if (now.empty()) break;
+    struct Out {
+      std::vector<int32_t> c;
+      std::vector<double> w;
+      std::vector<int64_t> off;  // per row of this part: offset into c / w
+    };
+    std::vector<Out> parts(nthreads);
+    std::vector<int64_t> chunk_lo(nthreads + 1, 0);
+    parallel_for(nthreads, (int64_t)now.size(), [&](int64_t lo, int64_t hi, int t) {
+      chunk_lo[t] = lo;
+      Out& o = parts[t];
+      std::vector<double> acc(nc, 0.0);
+      std::vector<int32_t> seen(nc, -1), touched;
+      for (int64_t r = lo; r < hi; ++r) {
+        const int32_t i = now[r];
+        o.off.push_back((int64_t)o.c.size());
+        // is column q (of row i) in P_i?  walk S_i alongside the sorted row
+        auto in_p = [&](int64_t& sa, int32_t q) {
+          while (sa < S.rp[i + 1] && S.ci[sa] < q) ++sa;
+          return sa < S.rp[i + 1] && S.ci[sa] == q && pass[q] != -1 && pass[q] < m;
+        };
+        double aii = 0.0, negn = 0.0, posn = 0.0, negp = 0.0;
+        for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+          if (A.ci[k] == i) aii = A.v[k];
+        int64_t sa = S.rp[i];
+        for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+          const int32_t j = A.ci[k];
+          if (j == i || func[j] != func[i]) continue;
+          const bool opp = aii < 0.0 ? A.v[k] > 0.0 : A.v[k] < 0.0;
+          if (opp)
+            negn += A.v[k];
+          else
+            posn += A.v[k];
+          if (opp && in_p(sa, j)) negp += A.v[k];
+        }
+        const double d = aii + posn;
+        touched.clear();
+        if (d != 0.0 && negp != 0.0) {
+          const double alpha = negn / negp;
+          sa = S.rp[i];
+          for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+            const int32_t q = A.ci[k];
+            if (q == i || func[q] != func[i] || !in_p(sa, q)) continue;
+            const double c = -alpha * A.v[k] / d;
+            for (int64_t e = start[q]; e < start[q] + len[q]; ++e) {
+              const int32_t j = sc[e];
+              if (seen[j] != i) {
+                seen[j] = i;
+                acc[j] = 0.0;
+                touched.push_back(j);
+              }
+              acc[j] += c * sv[e];
+            }
+          }
+        }
+        std::sort(touched.begin(), touched.end());
+        for (int32_t j : touched) {
+          o.c.push_back(j);
+          o.w.push_back(acc[j]);
+        }
+      }
+      o.off.push_back((int64_t)o.c.size());
+    });
+    for (int t = 0; t < nthreads; ++t) {
+      const Out& o = parts[t];
+      for (size_t r = 0; r + 1 < o.off.size(); ++r) {
+        const int32_t i = now[chunk_lo[t] + (int64_t)r];
+        start[i] = (int64_t)sc.size();
+        len[i] = o.off[r + 1] - o.off[r];
+        sc.insert(sc.end(), o.c.begin() + o.off[r], o.c.begin() + o.off[r + 1]);
+        sv.insert(sv.end(), o.w.begin() + o.off[r], o.w.begin() + o.off[r + 1]);
+      }
+    }
+    for (int32_t i : now) pass[i] = m;
+  }
+  Csr P;
+  P.n = n;
+  P.m = nc;
+  P.rp.assign(n + 1, 0);
+  for (int32_t i = 0; i < n; ++i) P.rp[i + 1] = P.rp[i] + len[i];
+  P.ci.resize(P.rp[n]);
+  P.v.resize(P.rp[n]);
+  parallel_for(nthreads, n, [&](int64_t lo, int64_t hi, int) {
+    for (int64_t i = lo; i < hi; ++i)
+      for (int64_t e = 0; e < len[i]; ++e) {
+        P.ci[P.rp[i] + e] = sc[start[i] + e];
+        P.v[P.rp[i] + e] = sv[start[i] + e];
+      }
+  });
+  return P;
 }
 
 // ---------------------------------------------------------------------------
@@ -628,11 +823,13 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
     const Csr& A = h.lev[l].A;
     if (A.n <= prm.max_coarse || (int)l + 1 >= prm.max_levels) break;
     Csr S = strength_graph(A, h.lev[l].func, prm.theta, prm.max_row_sum, threads);
-    std::vector<int32_t> cf = first_pass_split(S);
+    const bool agg = (int)l < prm.agg_levels;
+    std::vector<int32_t> cf = agg ? aggressive_split(S, threads) : first_pass_split(S);
     int32_t nc = 0;
     for (auto x : cf) nc += x == 1;
     if (nc == 0 || nc == A.n) break;
-    Csr P = extended_i_interp(A, S, cf, h.lev[l].func, prm.pmax, threads);
+    Csr P = agg ? multipass_interp(A, S, cf, h.lev[l].func, threads)
+                : extended_i_interp(A, S, cf, h.lev[l].func, prm.pmax, threads);
     Csr R = transpose(P, threads);
     Csr Ac = galerkin(R, A, P, threads);
     std::vector<int32_t> fc;

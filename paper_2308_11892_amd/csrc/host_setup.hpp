@@ -38,6 +38,7 @@ struct SetupParams {
   int max_levels = 25;
   int max_coarse = 9;
   int pmax = 4;
+  int agg_levels = 1;           // levels coarsened aggressively (multipass interpolation)
   bool quasi_impes = true;
   int threads = 1;
   int max_dense_coarse = 4096;  // largest coarsest level solved by dense LU
@@ -74,6 +75,10 @@ Csr strength_graph(const Csr& A, const std::vector<int32_t>& func, double theta,
 std::vector<int32_t> first_pass_split(const Csr& S);
 Csr extended_i_interp(const Csr& A, const Csr& S, const std::vector<int32_t>& cf,
                       const std::vector<int32_t>& func, int pmax, int threads);
+Csr distance_two_strength(const Csr& S, const std::vector<int32_t>& cf, int threads);
+std::vector<int32_t> aggressive_split(const Csr& S, int threads);
+Csr multipass_interp(const Csr& A, const Csr& S, const std::vector<int32_t>& cf,
+                     const std::vector<int32_t>& func, int threads);
 
 void parallel_for(int threads, int64_t n, const std::function<void(int64_t, int64_t, int)>& body);
 

@@ -30,17 +30,19 @@ def test_library_exports_every_header_symbol():
 
 def test_defaults_follow_the_paper():
     o = L.setup_opts()
-    assert (o.strong_threshold, o.max_row_sum, o.max_levels, o.max_coarse, o.p_max_elmts) == \
-        (0.25, 0.9, 25, 9, 4)
+    assert (o.strong_threshold, o.max_row_sum, o.max_levels, o.max_coarse, o.p_max_elmts,
+            o.agg_levels) == (0.25, 0.9, 25, 9, 4, 1)
     s = L.solve_opts()
     assert (s.max_iter, s.rtol, s.restart) == (200, 1e-6, 30)
 
 
-@pytest.mark.parametrize("case", ["grid20x20x5", "grid6x5x4", "grid12x1x1", "grid100x100x20_pe0.1"])
-def test_host_setup_matches_oracle(case):
-    c = J.by_name(case) if case == "grid20x20x5" else J.by_name(case)
-    h = O.Cptr(c.row_ptr, c.col_idx, c.values)
-    s = host_solver(c)
+@pytest.mark.parametrize("case,agg", [("grid20x20x5", 1), ("grid6x5x4", 1), ("grid12x1x1", 1),
+                                      ("grid100x100x20_pe0.1", 1), ("grid20x20x5", 0),
+                                      ("grid100x100x20_pe0.1", 0)])
+def test_host_setup_matches_oracle(case, agg):
+    c = J.by_name(case)
+    h = O.Cptr(c.row_ptr, c.col_idx, c.values, agg_levels=agg)
+    s = host_solver(c, agg_levels=agg)
     rows, nnz = s.hierarchy()
     a = h.amg
     assert len(rows) == a.nlevels
