@@ -66,6 +66,24 @@ KERNEL_OF_PHASE = {"spmv": "k_bsr3_spmv", "restrict": "k_l0_restrict",
                    "ilu_bwd": "k_ilu_grid<false>"}
 
 
+def pmc_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_grid250x250x50.md")
+    src = os.path.join(ROOT, "paper_2308_11892_amd", "csrc", "kernels.hip")
+    try:
+        m = re.search(r"```json\s*(\{.*?\})\s*```", open(path).read(), re.S)
+        table = json.loads(m.group(1))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, AttributeError, ValueError):
+        return None
+    if table.get("kernels_sha256") != sha:
+        return None
+    return table["bytes_per_launch"].get(kernel)
+
+
 def run_cpu_baseline(c, restart):
     """The oracle on the same system (single thread): its FGMRES solve is the
     bounded sample, about 10 s of CPU work; setup is timed separately."""
@@ -171,7 +189,7 @@ def main():
         kname = "k_stage2_resid"
     roof = dict(kernel=kname, phase=dom, bound="hbm", achieved=round(dk["GBps"], 1),
                 peak=HBM_PEAK_GBS, unit="GB/s", frac=round(dk["GBps"] / HBM_PEAK_GBS, 4),
-                traffic=None, bytes_per_launch=dk["bytes_per_launch"],
+                traffic=pmc_traffic(kname), bytes_per_launch=dk["bytes_per_launch"],
                 avg_launch_ms=round(dk["avg_ms"], 4))
     out = {
         "metric": "CPTR-FGMRES DOF-iter/s to 1e-6 relative residual",
