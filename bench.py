@@ -92,7 +92,7 @@ def run_cpu_baseline(c, restart):
     h = O.Cptr(c.row_ptr, c.col_idx, c.values)
     t_setup = time.perf_counter() - t0
     t0 = time.perf_counter()
-    _, info = h.gmres(c.b, restart=restart, flexible=True, rtol=c.tol)
+    xo, info = h.gmres(c.b, restart=restart, flexible=True, rtol=c.tol)
     t_solve = time.perf_counter() - t0
     v = c.n_dof * info["iterations"] / t_solve
     return dict(value=v, unit="DOF-iter/s", cores=1, kind="oracle",
@@ -100,7 +100,7 @@ def run_cpu_baseline(c, restart):
                         f"{c.name} system ({c.n_dof} DOF), single thread: "
                         f"{info['iterations']} iterations in {t_solve:.2f} s; oracle setup "
                         f"{t_setup:.2f} s not in value"),
-                iterations=info["iterations"], solve_s=t_solve, setup_s=t_setup)
+                iterations=info["iterations"], solve_s=t_solve, setup_s=t_setup, x=xo)
 
 
 def main():
@@ -111,6 +111,9 @@ def main():
     ap.add_argument("--workload", default="grid250x250x50")
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["fp64", "both"], default="both",
+                    help="fp64: the FP64 solve only; both: also the mixed-precision solve "
+                         "(FP32 preconditioner inside FP64 FGMRES), reported beside it")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (three times), the "
                          "reference dispatch for scaling HBM byte counters")
@@ -215,11 +218,47 @@ def main():
         "roofline": roof,
         "phases": phases,
     }
+    x64 = x.cpu().numpy()
     s.close()
+    x32h = None
+    if args.precision == "both":
+        log("mixed precision: FP32 preconditioner, FP64 FGMRES; setup")
+        s32 = L.Solver(c.row_ptr, c.col_idx, c.values, precond_precision=L.PRECISION_FP32)
+        x32 = torch.zeros_like(b)
+        for w in range(args.warmup):
+            s32.gmres_solve(b, x32, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its32, infos32 = [], []
+        for k in range(args.steps):
+            info = s32.gmres_solve(b, x32, **kw)
+            its32.append(info["iterations"])
+            infos32.append(info)
+        torch.cuda.synchronize()
+        dt32 = time.perf_counter() - t0
+        for k, info in enumerate(infos32):
+            log(f"fp32 step {k}: {info['iterations']} it, {info['solve_s']:.3f} s, rel res {info['rel_res_true']:.2e}")
+        x32h = x32.cpu().numpy()
+        s32.close()
+        nrm = lambda v: float(np.linalg.norm(v))
+        out["mixed_precision"] = {
+            "value": c.n_dof * sum(its32) / dt32, "unit": "DOF-iter/s",
+            "dtype": "f32 preconditioner, f64 Krylov",
+            "ms_per_step": dt32 / args.steps * 1e3, "time_to_tol_s": dt32 / args.steps,
+            "iterations": its32, "true_rel_res": infos32[-1]["rel_res_true"],
+            "speedup_time_to_tol_vs_fp64": dt / dt32,
+            "rel_diff_vs_fp64_solution": nrm(x32h - x64) / nrm(x64),
+            "rel_err_vs_exact": nrm(x32h - c.x_star) / nrm(c.x_star),
+            "fp64_rel_err_vs_exact": nrm(x64 - c.x_star) / nrm(c.x_star)}
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on {c.name}")
         cb = run_cpu_baseline(c, args.restart)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        xo = cb["x"]
+        out["rel_diff_vs_oracle_solution"] = float(np.linalg.norm(x64 - xo) / np.linalg.norm(xo))
+        if x32h is not None:
+            out["mixed_precision"]["rel_diff_vs_oracle_solution"] = float(
+                np.linalg.norm(x32h - xo) / np.linalg.norm(xo))
     print(json.dumps(out), flush=True)
 
 

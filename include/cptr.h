@@ -84,7 +84,17 @@ typedef struct {
                                 Sec. 3.1): a second first pass over the C points on the
                                 distance-two strength graph, multipass interpolation, no
                                 truncation; default 1, 0 = none */
+  int32_t precond_precision; /* CPTR_PRECISION_*: value type of the preconditioner (the V-cycle
+                                operators and vectors, the ILU(0) factors and sweeps); the
+                                Krylov method, A, the restriction weights and the coarsest dense
+                                solve stay FP64; default FP64 */
 } cptr_setup_opts;
+
+enum {
+  CPTR_PRECISION_FP64 = 0,
+  CPTR_PRECISION_FP32 = 1       /* mixed precision: FP32 preconditioner inside FP64 (F)GMRES;
+                                   not with CPTR_ILU_SWEEP_ONE_LAUNCH (CPTR_E_INVALID) */
+};
 
 enum {
   CPTR_ILU_SWEEP_AUTO = 0,      /* GRID when A is a 7-point lexicographic stencil, else

@@ -21,6 +21,7 @@ CPTR_E_INVALID, CPTR_E_NOMEM, CPTR_E_ZERO_PIVOT = -1, -2, -3
 CPTR_E_SINGULAR_COARSE, CPTR_E_HIP, CPTR_E_STATE = -4, -5, -6
 RESTRICT_QUASI_IMPES, RESTRICT_INJECTION = 0, 1
 ILU_SWEEP_AUTO, ILU_SWEEP_LEVELS, ILU_SWEEP_ONE_LAUNCH, ILU_SWEEP_GRID = 0, 1, 2, 3
+PRECISION_FP64, PRECISION_FP32 = 0, 1
 EXPORT = dict(CF=0, A_ROWPTR=1, A_COLS=2, A_VALS=3, P_ROWPTR=4, P_COLS=5, P_VALS=6, W=7,
               DINV=8, ILU_VALS=9, ILU_NLEVELS=10, SWEEP=11)
 PHASES = ["spmv", "restrict", "vcycle_l0", "vcycle_coarse", "stage2_resid", "ilu_fwd",
@@ -44,7 +45,8 @@ class cptr_setup_opts(C.Structure):
                 ("max_levels", C.c_int32), ("max_coarse", C.c_int32),
                 ("p_max_elmts", C.c_int32), ("restriction", C.c_int32),
                 ("host_only", C.c_int32), ("setup_threads", C.c_int32),
-                ("ilu_sweep", C.c_int32), ("agg_levels", C.c_int32)]
+                ("ilu_sweep", C.c_int32), ("agg_levels", C.c_int32),
+                ("precond_precision", C.c_int32)]
 
 
 class cptr_solve_opts(C.Structure):

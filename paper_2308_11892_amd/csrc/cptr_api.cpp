@@ -17,6 +17,7 @@
 #include <memory>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "cptr.h"
@@ -84,9 +85,26 @@ HostSell pack_sell(int32_t nrows, int nv, Len len, Fill fill, int32_t pad_col_mo
   return s;
 }
 
-struct DevVec {
-  double* p = nullptr;
-  int64_t n = 0;
+// Device operators and workspace of the preconditioner in its value type T
+// (double, or float in the mixed-precision mode).
+template <class T>
+struct PrecDev {
+  SellT<T> Ahat, Lf, Ub;     // elliptic blocks; ILU factors by dependency level
+  T* uinv = nullptr;         // U_ii^-1 per level-sorted position
+  T* Lg = nullptr;           // L blocks (-x, -y, -z), tile layout of the forward sweep
+  T* Ug = nullptr;           // U blocks (+x, +y, +z) and U_ii^-1, tile layout of the backward sweep
+  T* ytile = nullptr;        // forward-sweep results in the backward tile layout
+  T* r2tile = nullptr;       // stage-two residual in the forward tile layout
+  T* e0tile = nullptr;       // V-cycle result in the backward tile layout
+  T* faces = nullptr;        // face buffers of the forward then the backward grid sweep
+  struct Lev {
+    DCsrT<T> A, P, R;
+    T* dinv = nullptr;
+    T *b = nullptr, *r = nullptr, *x = nullptr, *e = nullptr;
+    int32_t n = 0;
+  };
+  std::vector<Lev> lev;
+  T *r2 = nullptr, *y = nullptr, *x2 = nullptr;  // apply workspace
 };
 
 }  // namespace
@@ -101,34 +119,23 @@ struct cptr_solver_s {
   int32_t eidx_h[3] = {0, 1, 2}, hidx_h[3] = {2, 0, 0};
   int64_t N = 0;  // DOF
   std::vector<void*> allocs;
-  // device operators
-  Sell A, Ahat, Lf, Ub;
+  // device operators shared by both precisions
+  Sell A;
   double* W = nullptr;
   int32_t* fperm = nullptr;
   int32_t* bperm = nullptr;
-  double* uinv = nullptr;
   std::vector<int32_t> flev_ptr, blev_ptr;
   int sf_width = 0;          // register slots of the one-launch sweeps; 0 = per-level launches
   int grid[3] = {0, 0, 0};   // nx, ny, nz when A is a 7-point stencil in lexicographic order
   bool use_grid = false;     // tiled systolic sweeps on that grid
-  double* Lg = nullptr;      // L blocks (-x, -y, -z), tile layout of the forward sweep
-  double* Ug = nullptr;      // U blocks (+x, +y, +z) and U_ii^-1, tile layout of the backward sweep
-  double* ytile = nullptr;   // forward-sweep results in the backward tile layout
-  double* r2tile = nullptr;  // stage-two residual in the forward tile layout
-  double* e0tile = nullptr;  // V-cycle result in the backward tile layout
   int* tickets = nullptr;    // [2] workgroup ticket counters of the one-launch sweeps
-  struct Lev {
-    DCsr A, P, R;
-    double* dinv = nullptr;
-    double *b = nullptr, *r = nullptr, *x = nullptr, *e = nullptr;
-    int32_t n = 0;
-  };
-  std::vector<Lev> lev;
   double* coarse_lu = nullptr;
   int32_t* coarse_piv = nullptr;
   int32_t ncoarse = 0;
-  // apply workspace
-  double *r2 = nullptr, *y = nullptr, *x2 = nullptr;
+  // the preconditioner in FP64 or FP32 (cptr_setup_opts.precond_precision)
+  int prec = CPTR_PRECISION_FP64;
+  PrecDev<double> p64;
+  PrecDev<float> p32;
   // solve workspace
   int restart_cap = 0;
   bool have_z = false;
@@ -192,7 +199,19 @@ int upload(cptr_solver s, T*& p, const T* src, int64_t count, hipStream_t st) {
   return CPTR_OK;
 }
 
-int upload_sell(cptr_solver s, Sell& d, const HostSell& h, hipStream_t st) {
+// FP64 host values uploaded as T (rounded to nearest when T is float)
+template <class T>
+int upload_as(cptr_solver s, T*& p, const double* src, int64_t count, hipStream_t st) {
+  if constexpr (std::is_same<T, double>::value) {
+    return upload(s, p, src, count, st);
+  } else {
+    std::vector<T> tmp(src, src + count);
+    return upload(s, p, tmp.data(), count, st);
+  }
+}
+
+template <class T>
+int upload_sell(cptr_solver s, SellT<T>& d, const HostSell& h, hipStream_t st) {
   d.nrows = h.nrows;
   d.nslices = h.nslices;
   d.nv = h.nv;
@@ -200,7 +219,7 @@ int upload_sell(cptr_solver s, Sell& d, const HostSell& h, hipStream_t st) {
   int rc;
   if ((rc = upload(s, d.sptr, h.sptr.data(), (int64_t)h.sptr.size(), st))) return rc;
   if ((rc = upload(s, d.col, h.col.data(), (int64_t)h.col.size(), st))) return rc;
-  if ((rc = upload(s, d.val, h.val.data(), (int64_t)h.val.size(), st))) return rc;
+  if ((rc = upload_as(s, d.val, h.val.data(), (int64_t)h.val.size(), st))) return rc;
   return CPTR_OK;
 }
 
@@ -211,7 +230,8 @@ int pick_group(int64_t nnz, int32_t n) {
   return g;
 }
 
-int upload_csr(cptr_solver s, DCsr& d, const Csr& h, hipStream_t st) {
+template <class T>
+int upload_csr(cptr_solver s, DCsrT<T>& d, const Csr& h, hipStream_t st) {
   d.n = h.n;
   d.m = h.m;
   d.nnz = h.nnz();
@@ -221,7 +241,7 @@ int upload_csr(cptr_solver s, DCsr& d, const Csr& h, hipStream_t st) {
   int rc;
   if ((rc = upload(s, d.rp, rp32.data(), (int64_t)rp32.size(), st))) return rc;
   if ((rc = upload(s, d.ci, h.ci.data(), (int64_t)h.ci.size(), st))) return rc;
-  if ((rc = upload(s, d.v, h.v.data(), (int64_t)h.v.size(), st))) return rc;
+  if ((rc = upload_as(s, d.v, h.v.data(), (int64_t)h.v.size(), st))) return rc;
   return CPTR_OK;
 }
 
@@ -255,7 +275,8 @@ bool detect_grid(const HostSetup& h, int dims[3]) {
   return true;
 }
 
-int build_grid_factors(cptr_solver s, hipStream_t st) {
+template <class T>
+int build_grid_factors(cptr_solver s, PrecDev<T>& d, hipStream_t st) {
   const HostSetup& h = s->host;
   const int nx = s->grid[0], ny = s->grid[1], nz = s->grid[2];
   const int32_t nxy = nx * ny;
@@ -291,15 +312,96 @@ int build_grid_factors(cptr_solver s, hipStream_t st) {
     for (int e = 0; e < 9; ++e) ut[((size_t)br * 36 + 27 + e) * 64 + lane] = h.uinv[(size_t)c * 9 + e];
   }
   int rc;
-  if ((rc = upload(s, s->Lg, lt.data(), (int64_t)lt.size(), st))) return rc;
-  if ((rc = upload(s, s->Ug, ut.data(), (int64_t)ut.size(), st))) return rc;
+  if ((rc = upload_as(s, d.Lg, lt.data(), (int64_t)lt.size(), st))) return rc;
+  if ((rc = upload_as(s, d.Ug, ut.data(), (int64_t)ut.size(), st))) return rc;
   // padding slots of the tile vectors stay zero forever (no kernel writes them)
-  if ((rc = dalloc(s, s->ytile, rows * 3 * 64))) return rc;
-  HIP_TRY(s, hipMemset(s->ytile, 0, sizeof(double) * (size_t)rows * 3 * 64));
-  if ((rc = dalloc(s, s->r2tile, rows * 3 * 64))) return rc;
-  HIP_TRY(s, hipMemset(s->r2tile, 0, sizeof(double) * (size_t)rows * 3 * 64));
-  if ((rc = dalloc(s, s->e0tile, rows * 2 * 64))) return rc;
-  HIP_TRY(s, hipMemset(s->e0tile, 0, sizeof(double) * (size_t)rows * 2 * 64));
+  if ((rc = dalloc(s, d.ytile, rows * 3 * 64))) return rc;
+  HIP_TRY(s, hipMemset(d.ytile, 0, sizeof(T) * (size_t)rows * 3 * 64));
+  if ((rc = dalloc(s, d.r2tile, rows * 3 * 64))) return rc;
+  HIP_TRY(s, hipMemset(d.r2tile, 0, sizeof(T) * (size_t)rows * 3 * 64));
+  if ((rc = dalloc(s, d.e0tile, rows * 2 * 64))) return rc;
+  HIP_TRY(s, hipMemset(d.e0tile, 0, sizeof(T) * (size_t)rows * 2 * 64));
+  if ((rc = dalloc(s, d.faces, 2 * grid_face_values(nx, ny, nz)))) return rc;
+  return CPTR_OK;
+}
+
+// The preconditioner's own operators in its value type T.
+template <class T>
+int build_prec(cptr_solver s, PrecDev<T>& d, const std::vector<int32_t>& fp,
+               const std::vector<int32_t>& bp, hipStream_t st) {
+  const HostSetup& h = s->host;
+  const int32_t nb = h.nb;
+  const int ne = h.ne;
+  int rc;
+  // Ahat (ne x ne blocks) in SELL-64
+  {
+    HostSell hs = pack_sell(
+        nb, ne * ne, [&](int32_t r) { return h.rp[r + 1] - h.rp[r]; },
+        [&](int32_t r, int32_t k, int32_t& c, double* v) {
+          const int32_t q = h.rp[r] + k;
+          c = h.ci[q];
+          std::memcpy(v, &h.ahat[(size_t)q * ne * ne], ne * ne * sizeof(double));
+        },
+        0);
+    if ((rc = upload_sell(s, d.Ahat, hs, st))) return rc;
+  }
+  // ILU factors by dependency level
+  {
+    HostSell Lh = pack_sell(
+        nb, 9, [&](int32_t p) { return h.diag[fp[p]] - h.rp[fp[p]]; },
+        [&](int32_t p, int32_t k, int32_t& c, double* v) {
+          const int32_t q = h.rp[fp[p]] + k;
+          c = h.ci[q];
+          std::memcpy(v, &h.ilu[(size_t)q * 9], 9 * sizeof(double));
+        },
+        -1);
+    if ((rc = upload_sell(s, d.Lf, Lh, st))) return rc;
+    HostSell Uh = pack_sell(
+        nb, 9, [&](int32_t p) { return h.rp[bp[p] + 1] - h.diag[bp[p]] - 1; },
+        [&](int32_t p, int32_t k, int32_t& c, double* v) {
+          const int32_t q = h.diag[bp[p]] + 1 + k;
+          c = h.ci[q];
+          std::memcpy(v, &h.ilu[(size_t)q * 9], 9 * sizeof(double));
+        },
+        -1);
+    if ((rc = upload_sell(s, d.Ub, Uh, st))) return rc;
+    if (s->sf_width == 0 && s->ilu_mode != CPTR_ILU_SWEEP_LEVELS) {
+      int maxw = 0;
+      for (int32_t sl = 0; sl < Lh.nslices; ++sl) maxw = std::max(maxw, Lh.sptr[sl + 1] - Lh.sptr[sl]);
+      for (int32_t sl = 0; sl < Uh.nslices; ++sl) maxw = std::max(maxw, Uh.sptr[sl + 1] - Uh.sptr[sl]);
+      const int w = ilu_sf_width(maxw);
+      if (s->ilu_mode == CPTR_ILU_SWEEP_ONE_LAUNCH && w == 0)
+        return fail(s, CPTR_E_INVALID,
+                    "rows too wide (" + std::to_string(maxw) + " blocks) for one-launch ILU sweeps");
+      // the one-launch sweeps run in FP64 only
+      s->sf_width = std::is_same<T, double>::value ? w : 0;
+    }
+    if (s->use_grid && (rc = build_grid_factors(s, d, st))) return rc;
+    const int64_t npad = (int64_t)Uh.nslices * kLanes;
+    std::vector<double> ui((size_t)npad * 9, 0.0);
+    for (int32_t p = 0; p < nb; ++p)
+      for (int e = 0; e < 9; ++e) ui[(size_t)e * npad + p] = h.uinv[(size_t)bp[p] * 9 + e];
+    if ((rc = upload_as(s, d.uinv, ui.data(), (int64_t)ui.size(), st))) return rc;
+  }
+  // AMG hierarchy (the coarsest LU stays FP64 and is shared)
+  const int L = (int)h.lev.size();
+  d.lev.resize(L);
+  for (int l = 0; l < L; ++l) {
+    const AmgLevel& hl = h.lev[l];
+    auto& dl = d.lev[l];
+    dl.n = hl.A.n;
+    if (l > 0 && (rc = upload_csr(s, dl.A, hl.A, st))) return rc;
+    if (l + 1 < L) {
+      if ((rc = upload_csr(s, dl.P, hl.P, st))) return rc;
+      if ((rc = upload_csr(s, dl.R, hl.R, st))) return rc;
+      if ((rc = upload_as(s, dl.dinv, hl.dinv.data(), (int64_t)hl.dinv.size(), st))) return rc;
+    }
+    if ((rc = dalloc(s, dl.b, dl.n)) || (rc = dalloc(s, dl.r, dl.n)) || (rc = dalloc(s, dl.x, dl.n)) ||
+        (rc = dalloc(s, dl.e, dl.n)))
+      return rc;
+  }
+  const int64_t N = (int64_t)nb * 3;
+  if ((rc = dalloc(s, d.r2, N)) || (rc = dalloc(s, d.y, N)) || (rc = dalloc(s, d.x2, N))) return rc;
   return CPTR_OK;
 }
 
@@ -308,7 +410,7 @@ int build_device(cptr_solver s, hipStream_t st) {
   const int32_t nb = h.nb;
   const int ne = h.ne;
   int rc;
-  // A in SELL-64, natural order
+  // A in SELL-64, natural order (FP64 in both precisions)
   {
     HostSell hs = pack_sell(
         nb, 9, [&](int32_t r) { return h.rp[r + 1] - h.rp[r]; },
@@ -320,18 +422,6 @@ int build_device(cptr_solver s, hipStream_t st) {
         0);
     if ((rc = upload_sell(s, s->A, hs, st))) return rc;
   }
-  // Ahat (ne x ne blocks) in SELL-64
-  {
-    HostSell hs = pack_sell(
-        nb, ne * ne, [&](int32_t r) { return h.rp[r + 1] - h.rp[r]; },
-        [&](int32_t r, int32_t k, int32_t& c, double* v) {
-          const int32_t q = h.rp[r] + k;
-          c = h.ci[q];
-          std::memcpy(v, &h.ahat[(size_t)q * ne * ne], ne * ne * sizeof(double));
-        },
-        0);
-    if ((rc = upload_sell(s, s->Ahat, hs, st))) return rc;
-  }
   // W padded to 2 per cell
   {
     std::vector<double> w2((size_t)nb * 2, 0.0);
@@ -340,6 +430,7 @@ int build_device(cptr_solver s, hipStream_t st) {
     if ((rc = upload(s, s->W, w2.data(), (int64_t)w2.size(), st))) return rc;
   }
   // ILU sweeps: positions sorted by level (stable in row order)
+  std::vector<int32_t> fp, bp;
   {
     auto order = [&](const std::vector<int32_t>& lvl, int32_t nl, std::vector<int32_t>& perm,
                      std::vector<int32_t>& ptr) {
@@ -350,71 +441,23 @@ int build_device(cptr_solver s, hipStream_t st) {
       perm.resize(nb);
       for (int32_t i = 0; i < nb; ++i) perm[fillp[lvl[i]]++] = i;
     };
-    std::vector<int32_t> fp, bp;
     order(h.fwd_level, h.n_fwd_levels, fp, s->flev_ptr);
     order(h.bwd_level, h.n_bwd_levels, bp, s->blev_ptr);
-    HostSell Lh = pack_sell(
-        nb, 9, [&](int32_t p) { return h.diag[fp[p]] - h.rp[fp[p]]; },
-        [&](int32_t p, int32_t k, int32_t& c, double* v) {
-          const int32_t q = h.rp[fp[p]] + k;
-          c = h.ci[q];
-          std::memcpy(v, &h.ilu[(size_t)q * 9], 9 * sizeof(double));
-        },
-        -1);
-    if ((rc = upload_sell(s, s->Lf, Lh, st))) return rc;
-    HostSell Uh = pack_sell(
-        nb, 9, [&](int32_t p) { return h.rp[bp[p] + 1] - h.diag[bp[p]] - 1; },
-        [&](int32_t p, int32_t k, int32_t& c, double* v) {
-          const int32_t q = h.diag[bp[p]] + 1 + k;
-          c = h.ci[q];
-          std::memcpy(v, &h.ilu[(size_t)q * 9], 9 * sizeof(double));
-        },
-        -1);
-    if ((rc = upload_sell(s, s->Ub, Uh, st))) return rc;
-    int maxw = 0;
-    for (int32_t sl = 0; sl < Lh.nslices; ++sl) maxw = std::max(maxw, Lh.sptr[sl + 1] - Lh.sptr[sl]);
-    for (int32_t sl = 0; sl < Uh.nslices; ++sl) maxw = std::max(maxw, Uh.sptr[sl + 1] - Uh.sptr[sl]);
-    const int w = ilu_sf_width(maxw);
-    if (s->ilu_mode == CPTR_ILU_SWEEP_ONE_LAUNCH && w == 0)
-      return fail(s, CPTR_E_INVALID, "rows too wide (" + std::to_string(maxw) + " blocks) for one-launch ILU sweeps");
-    s->sf_width = s->ilu_mode == CPTR_ILU_SWEEP_LEVELS ? 0 : w;
     if ((rc = dalloc(s, s->tickets, 2))) return rc;
     HIP_TRY(s, hipMemset(s->tickets, 0, 2 * sizeof(int)));
     const bool grid = detect_grid(h, s->grid);
     if (s->ilu_mode == CPTR_ILU_SWEEP_GRID && !grid)
       return fail(s, CPTR_E_INVALID, "ilu_sweep = GRID needs a 7-point stencil in lexicographic order");
     s->use_grid = grid && (s->ilu_mode == CPTR_ILU_SWEEP_AUTO || s->ilu_mode == CPTR_ILU_SWEEP_GRID);
-    if (s->use_grid && (rc = build_grid_factors(s, st))) return rc;
-    const int64_t npad = (int64_t)Uh.nslices * kLanes;
-    std::vector<double> ui((size_t)npad * 9, 0.0);
-    for (int32_t p = 0; p < nb; ++p)
-      for (int e = 0; e < 9; ++e) ui[(size_t)e * npad + p] = h.uinv[(size_t)bp[p] * 9 + e];
-    if ((rc = upload(s, s->uinv, ui.data(), (int64_t)ui.size(), st))) return rc;
+    s->sf_width = 0;
     if ((rc = upload(s, s->fperm, fp.data(), nb, st))) return rc;
     if ((rc = upload(s, s->bperm, bp.data(), nb, st))) return rc;
   }
-  // AMG hierarchy
-  const int L = (int)h.lev.size();
-  s->lev.resize(L);
-  for (int l = 0; l < L; ++l) {
-    const AmgLevel& hl = h.lev[l];
-    auto& d = s->lev[l];
-    d.n = hl.A.n;
-    if (l > 0 && (rc = upload_csr(s, d.A, hl.A, st))) return rc;
-    if (l + 1 < L) {
-      if ((rc = upload_csr(s, d.P, hl.P, st))) return rc;
-      if ((rc = upload_csr(s, d.R, hl.R, st))) return rc;
-      if ((rc = upload(s, d.dinv, hl.dinv.data(), (int64_t)hl.dinv.size(), st))) return rc;
-    }
-    if ((rc = dalloc(s, d.b, d.n)) || (rc = dalloc(s, d.r, d.n)) || (rc = dalloc(s, d.x, d.n)) ||
-        (rc = dalloc(s, d.e, d.n)))
-      return rc;
-  }
+  rc = s->prec == CPTR_PRECISION_FP32 ? build_prec(s, s->p32, fp, bp, st) : build_prec(s, s->p64, fp, bp, st);
+  if (rc) return rc;
   s->ncoarse = h.lev.back().A.n;
   if ((rc = upload(s, s->coarse_lu, h.coarse_lu.data(), (int64_t)h.coarse_lu.size(), st))) return rc;
   if ((rc = upload(s, s->coarse_piv, h.coarse_piv.data(), (int64_t)h.coarse_piv.size(), st))) return rc;
-  const int64_t N = (int64_t)nb * 3;
-  if ((rc = dalloc(s, s->r2, N)) || (rc = dalloc(s, s->y, N)) || (rc = dalloc(s, s->x2, N))) return rc;
   if ((rc = dalloc(s, s->part, (int64_t)kRedBlocks * (kMaxRestart + 2)))) return rc;
   if ((rc = dalloc(s, s->hdev, 256))) return rc;
   HIP_TRY(s, hipMemset(s->hdev, 0, 256 * sizeof(double)));
@@ -454,20 +497,13 @@ void ph_harvest(cptr_solver s) {  // call after the stream is synchronised
 }
 
 // ---------------------------------------------------------------- apply
-// e0 = V-cycle(R_QI r) on the elliptic block (first stage without prolongation)
-void enqueue_stage1(cptr_solver s, const double* r, hipStream_t st);
-// z = P_E e0 + M2^-1 (r - A P_E e0); e0 == nullptr gives z = M2^-1 r
-void enqueue_stage2(cptr_solver s, const double* r, const double* e0, double* z, hipStream_t st);
-
-void enqueue_apply(cptr_solver s, const double* r, double* z, hipStream_t st) {
-  enqueue_stage1(s, r, st);
-  enqueue_stage2(s, r, s->lev[0].e, z, st);
-}
-
-void enqueue_stage1(cptr_solver s, const double* r, hipStream_t st) {
+// e0 = V-cycle(R_QI r) on the elliptic block (first stage without
+// prolongation), in the preconditioner's type T
+template <class T>
+void enqueue_stage1(cptr_solver s, PrecDev<T>& d, const double* r, hipStream_t st) {
   const int ne = s->ne;
-  const int L = (int)s->lev.size();
-  auto& l0 = s->lev[0];
+  const int L = (int)d.lev.size();
+  auto& l0 = d.lev[0];
   hipEvent_t ev;
   ph_begin(s, st, ev);
   launch_l0_restrict(s->host.nb, ne, r, s->W, s->eidx_h, s->hidx_h, l0.b, st);
@@ -478,83 +514,103 @@ void enqueue_stage1(cptr_solver s, const double* r, hipStream_t st) {
     ph_end(s, st, PH_VCC, ev);
   } else {
     ph_begin(s, st, ev);
-    launch_l0_resid_jacobi(s->Ahat, ne, l0.b, l0.dinv, l0.r, st);
-    launch_csr_spmv(l0.R, l0.r, s->lev[1].b, st);
+    launch_l0_resid_jacobi(d.Ahat, ne, l0.b, l0.dinv, l0.r, st);
+    launch_csr_spmv(l0.R, l0.r, d.lev[1].b, st);
     ph_end(s, st, PH_VC0, ev);
     ph_begin(s, st, ev);
     for (int l = 1; l + 1 < L; ++l) {
-      auto& d = s->lev[l];
-      launch_csr_resid_jacobi(d.A, d.b, d.dinv, d.r, st);
-      launch_csr_spmv(d.R, d.r, s->lev[l + 1].b, st);
+      auto& dl = d.lev[l];
+      launch_csr_resid_jacobi(dl.A, dl.b, dl.dinv, dl.r, st);
+      launch_csr_spmv(dl.R, dl.r, d.lev[l + 1].b, st);
     }
-    launch_coarse_solve(s->ncoarse, s->coarse_lu, s->coarse_piv, s->lev[L - 1].b, s->lev[L - 1].e, st);
+    launch_coarse_solve(s->ncoarse, s->coarse_lu, s->coarse_piv, d.lev[L - 1].b, d.lev[L - 1].e, st);
     for (int l = L - 2; l >= 1; --l) {
-      auto& d = s->lev[l];
-      launch_csr_prolong(d.P, s->lev[l + 1].e, d.b, d.dinv, d.x, st);
-      launch_csr_post(d.A, d.x, d.b, d.dinv, d.e, st);
+      auto& dl = d.lev[l];
+      launch_csr_prolong(dl.P, d.lev[l + 1].e, dl.b, dl.dinv, dl.x, st);
+      launch_csr_post(dl.A, dl.x, dl.b, dl.dinv, dl.e, st);
     }
     ph_end(s, st, PH_VCC, ev);
     ph_begin(s, st, ev);
-    launch_csr_prolong(l0.P, s->lev[1].e, l0.b, l0.dinv, l0.x, st);
-    launch_l0_post(s->Ahat, ne, l0.x, l0.b, l0.dinv, l0.e, st);
+    launch_csr_prolong(l0.P, d.lev[1].e, l0.b, l0.dinv, l0.x, st);
+    launch_l0_post(d.Ahat, ne, l0.x, l0.b, l0.dinv, l0.e, st);
     ph_end(s, st, PH_VC0, ev);
   }
 }
 
-void enqueue_stage2(cptr_solver s, const double* r, const double* e0, double* z, hipStream_t st) {
+// z = P_E e0 + M2^-1 (r - A P_E e0); e0 == nullptr gives z = M2^-1 r
+template <class T>
+void enqueue_stage2(cptr_solver s, PrecDev<T>& d, const double* r, const T* e0, double* z,
+                    hipStream_t st) {
   const int ne = s->ne;
   hipEvent_t ev;
-  const double* rhs = r;
   if (s->use_grid) {
     const int nx = s->grid[0], ny = s->grid[1], nz = s->grid[2];
     ph_begin(s, st, ev);
-    launch_stage2_grid(nx, ny, nz, s->A, ne, s->eidx_h, e0, r, s->r2tile, s->e0tile, s->y, s->x2,
-                       s->tickets, st);
+    launch_stage2_grid(nx, ny, nz, s->A, ne, s->eidx_h, e0, r, d.r2tile, d.e0tile, d.faces, s->tickets,
+                       st);
     ph_end(s, st, PH_STAGE2, ev);
     ph_begin(s, st, ev);
-    launch_ilu_fwd_grid(nx, ny, nz, s->Lg, s->r2tile, s->ytile, s->y, s->tickets, s->hdev + 140,
+    launch_ilu_fwd_grid(nx, ny, nz, d.Lg, d.r2tile, d.ytile, d.faces, s->tickets, s->hdev + 140,
                         kSweepSpinLimit, st);
     ph_end(s, st, PH_ILU_F, ev);
     ph_begin(s, st, ev);
-    launch_ilu_bwd_grid(nx, ny, nz, s->Ug, s->ytile, e0 ? s->e0tile : nullptr, ne, s->eidx_h, s->x2, z,
+    launch_ilu_bwd_grid(nx, ny, nz, d.Ug, d.ytile, e0 ? d.e0tile : nullptr, ne, s->eidx_h,
+                        d.faces + grid_face_values(nx, ny, nz), z, s->tickets, s->hdev + 140,
+                        kSweepSpinLimit, st);
+    ph_end(s, st, PH_ILU_B, ev);
+    return;
+  }
+  const T* rhs = d.r2;
+  if constexpr (std::is_same<T, double>::value) {
+    if (s->sf_width > 0) {  // one-launch sweeps (FP64 only)
+      ph_begin(s, st, ev);
+      if (e0) {
+        launch_stage2_resid_sf(s->A, ne, s->eidx_h, e0, r, d.r2, d.y, d.x2, s->tickets, st);
+      } else {
+        launch_sweep_prepare(s->N, d.y, d.x2, s->tickets, st);
+        rhs = r;
+      }
+      ph_end(s, st, PH_STAGE2, ev);
+      ph_begin(s, st, ev);
+      launch_ilu_fwd_sf(d.Lf, s->sf_width, s->fperm, rhs, d.y, d.x2, s->tickets, s->hdev + 140,
+                        kSweepSpinLimit, st);
+      ph_end(s, st, PH_ILU_F, ev);
+      ph_begin(s, st, ev);
+      launch_ilu_bwd_sf(d.Ub, s->sf_width, s->bperm, d.uinv, d.y, e0, ne, s->eidx_h, d.x2, z,
                         s->tickets, s->hdev + 140, kSweepSpinLimit, st);
-    ph_end(s, st, PH_ILU_B, ev);
-    return;
-  }
-  if (s->sf_width > 0) {
-    ph_begin(s, st, ev);
-    if (e0) {
-      launch_stage2_resid_sf(s->A, ne, s->eidx_h, e0, r, s->r2, s->y, s->x2, s->tickets, st);
-      rhs = s->r2;
-    } else {
-      launch_sweep_prepare(s->N, s->y, s->x2, s->tickets, st);
+      ph_end(s, st, PH_ILU_B, ev);
+      return;
     }
-    ph_end(s, st, PH_STAGE2, ev);
-    ph_begin(s, st, ev);
-    launch_ilu_fwd_sf(s->Lf, s->sf_width, s->fperm, rhs, s->y, s->x2, s->tickets, s->hdev + 140,
-                      kSweepSpinLimit, st);
-    ph_end(s, st, PH_ILU_F, ev);
-    ph_begin(s, st, ev);
-    launch_ilu_bwd_sf(s->Ub, s->sf_width, s->bperm, s->uinv, s->y, e0, ne, s->eidx_h, s->x2, z,
-                      s->tickets, s->hdev + 140, kSweepSpinLimit, st);
-    ph_end(s, st, PH_ILU_B, ev);
-    return;
+    if (!e0) rhs = r;
   }
-  if (e0) {
+  // per-level launches; the stage-two residual also converts r to T
+  if (rhs == d.r2) {
     ph_begin(s, st, ev);
-    launch_stage2_resid(s->A, ne, s->eidx_h, e0, r, s->r2, st);
+    launch_stage2_resid(s->A, ne, s->eidx_h, e0, r, d.r2, st);
     ph_end(s, st, PH_STAGE2, ev);
-    rhs = s->r2;
   }
   ph_begin(s, st, ev);
   for (size_t l = 0; l + 1 < s->flev_ptr.size(); ++l)
-    launch_ilu_fwd_level(s->Lf, s->fperm, s->flev_ptr[l], s->flev_ptr[l + 1], rhs, s->y, st);
+    launch_ilu_fwd_level(d.Lf, s->fperm, s->flev_ptr[l], s->flev_ptr[l + 1], rhs, d.y, st);
   ph_end(s, st, PH_ILU_F, ev);
   ph_begin(s, st, ev);
   for (size_t l = 0; l + 1 < s->blev_ptr.size(); ++l)
-    launch_ilu_bwd_level(s->Ub, s->bperm, s->uinv, s->blev_ptr[l], s->blev_ptr[l + 1], s->y, e0, ne,
-                         s->eidx_h, s->x2, z, st);
+    launch_ilu_bwd_level(d.Ub, s->bperm, d.uinv, s->blev_ptr[l], s->blev_ptr[l + 1], d.y, e0, ne,
+                         s->eidx_h, d.x2, z, st);
   ph_end(s, st, PH_ILU_B, ev);
+}
+
+template <class T>
+void enqueue_apply(cptr_solver s, PrecDev<T>& d, const double* r, double* z, hipStream_t st) {
+  enqueue_stage1(s, d, r, st);
+  enqueue_stage2(s, d, r, (const T*)d.lev[0].e, z, st);
+}
+
+void enqueue_apply(cptr_solver s, const double* r, double* z, hipStream_t st) {
+  if (s->prec == CPTR_PRECISION_FP32)
+    enqueue_apply(s, s->p32, r, z, st);
+  else
+    enqueue_apply(s, s->p64, r, z, st);
 }
 
 int ensure_solve_space(cptr_solver s, int m, bool flexible) {
@@ -619,6 +675,7 @@ void cptr_setup_opts_default(cptr_setup_opts* o) {
   o->setup_threads = 0;
   o->ilu_sweep = CPTR_ILU_SWEEP_AUTO;
   o->agg_levels = 1;
+  o->precond_precision = CPTR_PRECISION_FP64;
 }
 
 void cptr_solve_opts_default(cptr_solve_opts* o) {
@@ -657,6 +714,10 @@ cptr_status cptr_setup(const cptr_bsr* A, int32_t block_size, const int32_t* ell
   if (opts) o = *opts;
   if (o.ilu_sweep < 0 || o.ilu_sweep > 3)
     return (cptr_status)fail(nullptr, CPTR_E_INVALID, "ilu_sweep must be 0, 1, 2 or 3");
+  if (o.precond_precision != CPTR_PRECISION_FP64 && o.precond_precision != CPTR_PRECISION_FP32)
+    return (cptr_status)fail(nullptr, CPTR_E_INVALID, "precond_precision must be FP64 or FP32");
+  if (o.precond_precision == CPTR_PRECISION_FP32 && o.ilu_sweep == CPTR_ILU_SWEEP_ONE_LAUNCH)
+    return (cptr_status)fail(nullptr, CPTR_E_INVALID, "one-launch ILU sweeps run in FP64 only");
   if (o.max_levels < 1 || o.max_levels > 64 || o.max_coarse < 1 || o.p_max_elmts < 0 ||
       o.agg_levels < 0 ||
       !(o.strong_threshold >= 0.0) || !(o.max_row_sum > 0.0))
@@ -721,6 +782,7 @@ cptr_status cptr_setup(const cptr_bsr* A, int32_t block_size, const int32_t* ell
   }
   s->N = (int64_t)nb * 3;
   s->ilu_mode = o.ilu_sweep;
+  s->prec = o.precond_precision;
   if (!o.host_only) {
     int dev_count = 0;
     hipError_t he = hipGetDeviceCount(&dev_count);
@@ -775,8 +837,13 @@ cptr_status cptr_stage1(cptr_solver s, const double* r, double* x1, void* stream
   if (!s->device) return (cptr_status)fail(s, CPTR_E_STATE, "handle was set up host-only");
   if (!r || !x1 || r == x1) return (cptr_status)fail(s, CPTR_E_INVALID, "r and x1 must be distinct non-NULL device pointers");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  enqueue_stage1(s, r, st);
-  launch_prolong_e(s->host.nb, s->ne, s->eidx_h, s->lev[0].e, x1, st);
+  if (s->prec == CPTR_PRECISION_FP32) {
+    enqueue_stage1(s, s->p32, r, st);
+    launch_prolong_e(s->host.nb, s->ne, s->eidx_h, s->p32.lev[0].e, x1, st);
+  } else {
+    enqueue_stage1(s, s->p64, r, st);
+    launch_prolong_e(s->host.nb, s->ne, s->eidx_h, s->p64.lev[0].e, x1, st);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (cptr_status)hip_fail(s, e, "kernel launch in cptr_stage1");
   return CPTR_OK;
@@ -787,7 +854,10 @@ cptr_status cptr_ilu_solve(cptr_solver s, const double* r, double* x, void* stre
   if (!s->device) return (cptr_status)fail(s, CPTR_E_STATE, "handle was set up host-only");
   if (!r || !x || r == x) return (cptr_status)fail(s, CPTR_E_INVALID, "r and x must be distinct non-NULL device pointers");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  enqueue_stage2(s, r, nullptr, x, st);
+  if (s->prec == CPTR_PRECISION_FP32)
+    enqueue_stage2<float>(s, s->p32, r, nullptr, x, st);
+  else
+    enqueue_stage2<double>(s, s->p64, r, nullptr, x, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (cptr_status)hip_fail(s, e, "kernel launch in cptr_ilu_solve");
   return CPTR_OK;

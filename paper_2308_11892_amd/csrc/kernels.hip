@@ -35,8 +35,8 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <int G>
-__device__ __forceinline__ double group_sum(double v) {
+template <int G, class T>
+__device__ __forceinline__ T group_sum(T v) {
 #pragma unroll
   for (int off = G / 2; off > 0; off >>= 1) v += __shfl_down(v, off, G);
   return v;
@@ -81,41 +81,42 @@ __global__ __launch_bounds__(kBlock) void k_bsr3_spmv(int nrows, int nblk, const
 
 // --------------------------------------------------------------------------
 // quasi-IMPES restriction: b0_i = r_i[E] - W_i r_i[H]
-template <int NE>
+// (computed in FP64, stored in the preconditioner's type T)
+template <int NE, class T>
 __global__ __launch_bounds__(kBlock) void k_l0_restrict(int nc, const double* __restrict__ r,
                                                         const double* __restrict__ W, int e0,
                                                         int e1, int h0, int h1,
-                                                        double* __restrict__ b0) {
+                                                        T* __restrict__ b0) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= nc) return;
   const double* ri = r + 3 * (size_t)i;
   if (NE == 2) {
     const double rh = ri[h0];
-    b0[2 * (size_t)i] = ri[e0] - W[2 * (size_t)i] * rh;
-    b0[2 * (size_t)i + 1] = ri[e1] - W[2 * (size_t)i + 1] * rh;
+    b0[2 * (size_t)i] = (T)(ri[e0] - W[2 * (size_t)i] * rh);
+    b0[2 * (size_t)i + 1] = (T)(ri[e1] - W[2 * (size_t)i + 1] * rh);
   } else {
-    b0[i] = ri[e0] - W[2 * (size_t)i] * ri[h0] - W[2 * (size_t)i + 1] * ri[h1];
+    b0[i] = (T)(ri[e0] - W[2 * (size_t)i] * ri[h0] - W[2 * (size_t)i + 1] * ri[h1]);
   }
 }
 
 // r0 = b0 - Ahat (D^-1 b0): pre-smoothing from zero fused with the residual
-template <int NE>
+template <int NE, class T>
 __global__ __launch_bounds__(kBlock) void k_l0_resid_jacobi(int nc, int nblk, const int32_t* __restrict__ sptr,
                                                             const int32_t* __restrict__ col,
-                                                            const double* __restrict__ val,
-                                                            const double* __restrict__ b0,
-                                                            const double* __restrict__ dinv,
-                                                            double* __restrict__ r0) {
+                                                            const T* __restrict__ val,
+                                                            const T* __restrict__ b0,
+                                                            const T* __restrict__ dinv,
+                                                            T* __restrict__ r0) {
   const int row = xcd_block(blockIdx.x, nblk) * kBlock + threadIdx.x;
   if (row >= nc) return;
   const int s = row >> 6, lane = row & 63;
-  double acc[NE];
+  T acc[NE];
 #pragma unroll
-  for (int a = 0; a < NE; ++a) acc[a] = 0.0;
+  for (int a = 0; a < NE; ++a) acc[a] = 0;
   for (int k = sptr[s]; k < sptr[s + 1]; ++k) {
     const int c = col[(size_t)k * 64 + lane];
-    const double* v = val + (size_t)k * NE * NE * 64 + lane;
-    double xc[NE];
+    const T* v = val + (size_t)k * NE * NE * 64 + lane;
+    T xc[NE];
 #pragma unroll
     for (int q = 0; q < NE; ++q) xc[q] = dinv[(size_t)c * NE + q] * b0[(size_t)c * NE + q];
 #pragma unroll
@@ -128,24 +129,24 @@ __global__ __launch_bounds__(kBlock) void k_l0_resid_jacobi(int nc, int nblk, co
 }
 
 // e0 = x0 + D^-1 (b0 - Ahat x0): post-smoothing at level 0
-template <int NE>
+template <int NE, class T>
 __global__ __launch_bounds__(kBlock) void k_l0_post(int nc, int nblk, const int32_t* __restrict__ sptr,
                                                     const int32_t* __restrict__ col,
-                                                    const double* __restrict__ val,
-                                                    const double* __restrict__ x0,
-                                                    const double* __restrict__ b0,
-                                                    const double* __restrict__ dinv,
-                                                    double* __restrict__ e0) {
+                                                    const T* __restrict__ val,
+                                                    const T* __restrict__ x0,
+                                                    const T* __restrict__ b0,
+                                                    const T* __restrict__ dinv,
+                                                    T* __restrict__ e0) {
   const int row = xcd_block(blockIdx.x, nblk) * kBlock + threadIdx.x;
   if (row >= nc) return;
   const int s = row >> 6, lane = row & 63;
-  double acc[NE];
+  T acc[NE];
 #pragma unroll
-  for (int a = 0; a < NE; ++a) acc[a] = 0.0;
+  for (int a = 0; a < NE; ++a) acc[a] = 0;
   for (int k = sptr[s]; k < sptr[s + 1]; ++k) {
     const int c = col[(size_t)k * 64 + lane];
-    const double* v = val + (size_t)k * NE * NE * 64 + lane;
-    double xc[NE];
+    const T* v = val + (size_t)k * NE * NE * 64 + lane;
+    T xc[NE];
 #pragma unroll
     for (int q = 0; q < NE; ++q) xc[q] = x0[(size_t)c * NE + q];
 #pragma unroll
@@ -164,27 +165,27 @@ __global__ __launch_bounds__(kBlock) void k_l0_post(int nc, int nblk, const int3
 // scalar CSR kernels: G lanes per row
 enum CsrOp { kSpmv = 0, kResidJacobi = 1, kProlong = 2, kPost = 3 };
 
-template <int G, int OP>
+template <int G, int OP, class T>
 __global__ __launch_bounds__(kBlock) void k_csr(int n, const int32_t* __restrict__ rp,
                                                 const int32_t* __restrict__ ci,
-                                                const double* __restrict__ v,
-                                                const double* __restrict__ x,
-                                                const double* __restrict__ b,
-                                                const double* __restrict__ dinv,
-                                                double* __restrict__ y) {
+                                                const T* __restrict__ v,
+                                                const T* __restrict__ x,
+                                                const T* __restrict__ b,
+                                                const T* __restrict__ dinv,
+                                                T* __restrict__ y) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int row = (int)(t / G), sub = (int)(t % G);
   const bool live = row < n;
-  double acc = 0.0;
+  T acc = 0;
   if (live) {
     for (int k = rp[row] + sub; k < rp[row + 1]; k += G) {
       const int c = ci[k];
-      double xv = x[c];
+      T xv = OP == kResidJacobi ? (T)0 : x[c];
       if (OP == kResidJacobi) xv = dinv[c] * b[c];
       acc += v[k] * xv;
     }
   }
-  acc = group_sum<G>(acc);
+  acc = group_sum<G, T>(acc);
   if (!live || sub != 0) return;
   switch (OP) {
     case kSpmv: y[row] = acc; break;
@@ -194,27 +195,28 @@ __global__ __launch_bounds__(kBlock) void k_csr(int n, const int32_t* __restrict
   }
 }
 
-template <int OP>
-void launch_csr_op(const DCsr& A, const double* x, const double* b, const double* dinv, double* y,
-                   hipStream_t st) {
+template <int OP, class T>
+void launch_csr_op(const DCsrT<T>& A, const T* x, const T* b, const T* dinv, T* y, hipStream_t st) {
   if (A.n == 0) return;
   const int64_t threads = (int64_t)A.n * A.group;
   const int grid = nblocks(threads, kBlock);
   switch (A.group) {
 #define CSR_CASE(G) \
-  case G: k_csr<G, OP><<<grid, kBlock, 0, st>>>(A.n, A.rp, A.ci, A.v, x, b, dinv, y); break;
+  case G: k_csr<G, OP, T><<<grid, kBlock, 0, st>>>(A.n, A.rp, A.ci, A.v, x, b, dinv, y); break;
     CSR_CASE(1) CSR_CASE(2) CSR_CASE(4) CSR_CASE(8) CSR_CASE(16) CSR_CASE(32) CSR_CASE(64)
 #undef CSR_CASE
-    default: k_csr<8, OP><<<nblocks((int64_t)A.n * 8, kBlock), kBlock, 0, st>>>(A.n, A.rp, A.ci, A.v, x, b, dinv, y);
+    default: k_csr<8, OP, T><<<nblocks((int64_t)A.n * 8, kBlock), kBlock, 0, st>>>(A.n, A.rp, A.ci, A.v, x, b, dinv, y);
   }
 }
 
 // --------------------------------------------------------------------------
 // coarsest level: x = (LU)^-1 b with row swaps piv (one workgroup)
+// (FP64 factors and arithmetic; b and x in the preconditioner's type)
+template <class T>
 __global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, const double* __restrict__ lu,
                                                          const int32_t* __restrict__ piv,
-                                                         const double* __restrict__ b,
-                                                         double* __restrict__ x) {
+                                                         const T* __restrict__ b,
+                                                         T* __restrict__ x) {
   extern __shared__ double s[];
   const int tid = threadIdx.x;
   for (int i = tid; i < n; i += kBlock) s[i] = b[i];
@@ -241,24 +243,27 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, const double* __
     for (int j = tid; j < i; j += kBlock) s[j] -= lu[(size_t)j * n + i] * xi;
     __syncthreads();
   }
-  for (int i = tid; i < n; i += kBlock) x[i] = s[i];
+  for (int i = tid; i < n; i += kBlock) x[i] = (T)s[i];
 }
 
 // --------------------------------------------------------------------------
 // stage-two residual r2 = r - A x1 with x1[E] = e0, x1[H] = 0: only the
 // elliptic columns of each block are read
-template <int NE>
+// (A and the arithmetic in FP64, e0 and r2 in the preconditioner's type T;
+// without e0 this only converts r)
+template <int NE, class T>
 __global__ __launch_bounds__(kBlock) void k_stage2_resid(int nrows, int nblk, const int32_t* __restrict__ sptr,
                                                          const int32_t* __restrict__ col,
                                                          const double* __restrict__ val, int ea,
-                                                         int eb, const double* __restrict__ e0,
+                                                         int eb, const T* __restrict__ e0,
                                                          const double* __restrict__ r,
-                                                         double* __restrict__ r2) {
+                                                         T* __restrict__ r2) {
   const int row = xcd_block(blockIdx.x, nblk) * kBlock + threadIdx.x;
   if (row >= nrows) return;
   const int s = row >> 6, lane = row & 63;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  for (int k = sptr[s]; k < sptr[s + 1]; ++k) {
+  // e0 == nullptr (no first stage): r2 = r, converted to T
+  for (int k = sptr[s]; e0 && k < sptr[s + 1]; ++k) {
     const int c = col[(size_t)k * 64 + lane];
     const double* v = val + (size_t)k * 9 * 64 + lane;
     const double u = e0[(size_t)c * NE];
@@ -273,31 +278,32 @@ __global__ __launch_bounds__(kBlock) void k_stage2_resid(int nrows, int nblk, co
     }
   }
   const double* ri = r + 3 * (size_t)row;
-  double* o = r2 + 3 * (size_t)row;
-  o[0] = ri[0] - a0;
-  o[1] = ri[1] - a1;
-  o[2] = ri[2] - a2;
+  T* o = r2 + 3 * (size_t)row;
+  o[0] = (T)(ri[0] - a0);
+  o[1] = (T)(ri[1] - a1);
+  o[2] = (T)(ri[2] - a2);
 }
 
 // --------------------------------------------------------------------------
 // ILU(0) sweeps, one launch per dependency level.  Positions are rows sorted
 // by level; slot columns < 0 are padding.
+template <class T>
 __global__ __launch_bounds__(kBlock) void k_ilu_fwd(int p0, int p1, const int32_t* __restrict__ sptr,
                                                     const int32_t* __restrict__ col,
-                                                    const double* __restrict__ val,
+                                                    const T* __restrict__ val,
                                                     const int32_t* __restrict__ perm,
-                                                    const double* __restrict__ r2,
-                                                    double* __restrict__ y) {
+                                                    const T* __restrict__ r2,
+                                                    T* __restrict__ y) {
   const int p = p0 + blockIdx.x * kBlock + threadIdx.x;
   if (p >= p1) return;
   const int i = perm[p];
   const int s = p >> 6, lane = p & 63;
-  double a0 = r2[3 * (size_t)i], a1 = r2[3 * (size_t)i + 1], a2 = r2[3 * (size_t)i + 2];
+  T a0 = r2[3 * (size_t)i], a1 = r2[3 * (size_t)i + 1], a2 = r2[3 * (size_t)i + 2];
   for (int k = sptr[s]; k < sptr[s + 1]; ++k) {
     const int c = col[(size_t)k * 64 + lane];
     if (c < 0) continue;
-    const double* v = val + (size_t)k * 9 * 64 + lane;
-    const double x0 = y[3 * (size_t)c], x1 = y[3 * (size_t)c + 1], x2 = y[3 * (size_t)c + 2];
+    const T* v = val + (size_t)k * 9 * 64 + lane;
+    const T x0 = y[3 * (size_t)c], x1 = y[3 * (size_t)c + 1], x2 = y[3 * (size_t)c + 2];
     a0 -= v[0] * x0 + v[64] * x1 + v[128] * x2;
     a1 -= v[192] * x0 + v[256] * x1 + v[320] * x2;
     a2 -= v[384] * x0 + v[448] * x1 + v[512] * x2;
@@ -307,42 +313,42 @@ __global__ __launch_bounds__(kBlock) void k_ilu_fwd(int p0, int p1, const int32_
   y[3 * (size_t)i + 2] = a2;
 }
 
-template <int NE>
+template <int NE, class T>
 __global__ __launch_bounds__(kBlock) void k_ilu_bwd(int p0, int p1, int npad, const int32_t* __restrict__ sptr,
                                                     const int32_t* __restrict__ col,
-                                                    const double* __restrict__ val,
+                                                    const T* __restrict__ val,
                                                     const int32_t* __restrict__ perm,
-                                                    const double* __restrict__ uinv,
-                                                    const double* __restrict__ y, const double* __restrict__ e0,
-                                                    int ea, int eb, double* __restrict__ x2,
+                                                    const T* __restrict__ uinv,
+                                                    const T* __restrict__ y, const T* __restrict__ e0,
+                                                    int ea, int eb, T* __restrict__ x2,
                                                     double* __restrict__ z) {
   const int p = p0 + blockIdx.x * kBlock + threadIdx.x;
   if (p >= p1) return;
   const int i = perm[p];
   const int s = p >> 6, lane = p & 63;
-  double a0 = y[3 * (size_t)i], a1 = y[3 * (size_t)i + 1], a2 = y[3 * (size_t)i + 2];
+  T a0 = y[3 * (size_t)i], a1 = y[3 * (size_t)i + 1], a2 = y[3 * (size_t)i + 2];
   for (int k = sptr[s]; k < sptr[s + 1]; ++k) {
     const int c = col[(size_t)k * 64 + lane];
     if (c < 0) continue;
-    const double* v = val + (size_t)k * 9 * 64 + lane;
-    const double x0 = x2[3 * (size_t)c], x1 = x2[3 * (size_t)c + 1], xx = x2[3 * (size_t)c + 2];
+    const T* v = val + (size_t)k * 9 * 64 + lane;
+    const T x0 = x2[3 * (size_t)c], x1 = x2[3 * (size_t)c + 1], xx = x2[3 * (size_t)c + 2];
     a0 -= v[0] * x0 + v[64] * x1 + v[128] * xx;
     a1 -= v[192] * x0 + v[256] * x1 + v[320] * xx;
     a2 -= v[384] * x0 + v[448] * x1 + v[512] * xx;
   }
-  const double* u = uinv + p;
-  const double o0 = u[0] * a0 + u[(size_t)npad] * a1 + u[2 * (size_t)npad] * a2;
-  const double o1 = u[3 * (size_t)npad] * a0 + u[4 * (size_t)npad] * a1 + u[5 * (size_t)npad] * a2;
-  const double o2 = u[6 * (size_t)npad] * a0 + u[7 * (size_t)npad] * a1 + u[8 * (size_t)npad] * a2;
+  const T* u = uinv + p;
+  const T o0 = u[0] * a0 + u[(size_t)npad] * a1 + u[2 * (size_t)npad] * a2;
+  const T o1 = u[3 * (size_t)npad] * a0 + u[4 * (size_t)npad] * a1 + u[5 * (size_t)npad] * a2;
+  const T o2 = u[6 * (size_t)npad] * a0 + u[7 * (size_t)npad] * a1 + u[8 * (size_t)npad] * a2;
   x2[3 * (size_t)i] = o0;
   x2[3 * (size_t)i + 1] = o1;
   x2[3 * (size_t)i + 2] = o2;
-  // z = x1 + x2 with x1[E] = e0 and x1[H] = 0 (e0 == nullptr: x1 = 0)
-  const double ex = e0 ? e0[(size_t)i * NE] : 0.0;
-  const double ey = (NE == 2 && e0) ? e0[(size_t)i * NE + 1] : 0.0;
-  z[3 * (size_t)i] = o0 + (ea == 0 ? ex : 0.0) + (NE == 2 && eb == 0 ? ey : 0.0);
-  z[3 * (size_t)i + 1] = o1 + (ea == 1 ? ex : 0.0) + (NE == 2 && eb == 1 ? ey : 0.0);
-  z[3 * (size_t)i + 2] = o2 + (ea == 2 ? ex : 0.0) + (NE == 2 && eb == 2 ? ey : 0.0);
+  // z = x1 + x2 with x1[E] = e0 and x1[H] = 0 (e0 == nullptr: x1 = 0), in FP64
+  const double ex = e0 ? (double)e0[(size_t)i * NE] : 0.0;
+  const double ey = (NE == 2 && e0) ? (double)e0[(size_t)i * NE + 1] : 0.0;
+  z[3 * (size_t)i] = (double)o0 + (ea == 0 ? ex : 0.0) + (NE == 2 && eb == 0 ? ey : 0.0);
+  z[3 * (size_t)i + 1] = (double)o1 + (ea == 1 ? ex : 0.0) + (NE == 2 && eb == 1 ? ey : 0.0);
+  z[3 * (size_t)i + 2] = (double)o2 + (ea == 2 ? ex : 0.0) + (NE == 2 && eb == 2 ? ey : 0.0);
 }
 
 // --------------------------------------------------------------------------
@@ -363,16 +369,31 @@ __global__ __launch_bounds__(kBlock) void k_ilu_bwd(int p0, int p1, int npad, co
 // the lanes retry until every lane is done, so lanes waiting on lower lanes
 // of the same wave do not block them.  Every wait is bounded: after
 // `spin_limit` rounds the wave records an error flag and exits.
+// The FP32 sweeps use a signalling-NaN payload of their own.
 constexpr unsigned long long kSentinel = 0x7FF4C0DE5E1F0BADull;
+constexpr unsigned kSentinelF = 0x7FA5C0DEu;
 
-__device__ __forceinline__ double ld_dev(const double* p) {
+template <class T>
+__device__ __forceinline__ T ld_dev(const T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_dev(double* p, double v) {
+template <class T>
+__device__ __forceinline__ void st_dev(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ bool is_sent(double v) {
   return (unsigned long long)__double_as_longlong(v) == kSentinel;
+}
+__device__ __forceinline__ bool is_sent(float v) { return __float_as_uint(v) == kSentinelF; }
+template <class T>
+__device__ __forceinline__ T sentinel_value();
+template <>
+__device__ __forceinline__ double sentinel_value<double>() {
+  return __longlong_as_double((long long)kSentinel);
+}
+template <>
+__device__ __forceinline__ float sentinel_value<float>() {
+  return __uint_as_float(kSentinelF);
 }
 
 __device__ __forceinline__ int take_ticket(int* ctr) {
@@ -549,14 +570,14 @@ __global__ __launch_bounds__(kBlock) void k_ilu_bwd_sf(int npos, int npad, const
 
 // --------------------------------------------------------------------------
 // x1 = P_E e0: elliptic unknowns from e0, hyperbolic unknowns zero
-template <int NE>
-__global__ __launch_bounds__(kBlock) void k_prolong_e(int nrows, const double* __restrict__ e0, int ea,
+template <int NE, class T>
+__global__ __launch_bounds__(kBlock) void k_prolong_e(int nrows, const T* __restrict__ e0, int ea,
                                                       int eb, double* __restrict__ x1) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= nrows) return;
   double o[3] = {0.0, 0.0, 0.0};
   const double ex = e0[(size_t)i * NE];
-  const double ey = NE == 2 ? e0[(size_t)i * NE + 1] : 0.0;
+  const double ey = NE == 2 ? (double)e0[(size_t)i * NE + 1] : 0.0;
   x1[3 * (size_t)i] = (ea == 0 ? ex : 0.0) + (NE == 2 && eb == 0 ? ey : 0.0) + o[0];
   x1[3 * (size_t)i + 1] = (ea == 1 ? ex : 0.0) + (NE == 2 && eb == 1 ? ey : 0.0) + o[1];
   x1[3 * (size_t)i + 2] = (ea == 2 ? ex : 0.0) + (NE == 2 && eb == 2 ? ey : 0.0) + o[2];
@@ -598,19 +619,25 @@ __global__ __launch_bounds__(kBlock) void k_sweep_prepare(int64_t n, double* __r
 // U_ii^-1; blocks of absent neighbours are zero.
 constexpr int kTJ = 16, kTK = 4;
 
+template <class T>
 struct Vec3 {
-  double v0, v1, v2;
+  T v0, v1, v2;
 };
 
-__device__ __forceinline__ Vec3 shfl_up3(Vec3 a, int d) {
+template <class T>
+__device__ __forceinline__ Vec3<T> shfl_up3(Vec3<T> a, int d) {
   return {__shfl_up(a.v0, d, 64), __shfl_up(a.v1, d, 64), __shfl_up(a.v2, d, 64)};
 }
-__device__ __forceinline__ Vec3 shfl_down3(Vec3 a, int d) {
+template <class T>
+__device__ __forceinline__ Vec3<T> shfl_down3(Vec3<T> a, int d) {
   return {__shfl_down(a.v0, d, 64), __shfl_down(a.v1, d, 64), __shfl_down(a.v2, d, 64)};
 }
-__device__ __forceinline__ Vec3 ld3_dev(const double* p) { return {ld_dev(p), ld_dev(p + 1), ld_dev(p + 2)}; }
-__device__ __forceinline__ bool sent3(const Vec3& a) { return is_sent(a.v0) || is_sent(a.v1) || is_sent(a.v2); }
-__device__ __forceinline__ void mv3_sub(const double* b, const Vec3& x, double& a0, double& a1, double& a2) {
+template <class T>
+__device__ __forceinline__ Vec3<T> ld3_dev(const T* p) { return {ld_dev(p), ld_dev(p + 1), ld_dev(p + 2)}; }
+template <class T>
+__device__ __forceinline__ bool sent3(const Vec3<T>& a) { return is_sent(a.v0) || is_sent(a.v1) || is_sent(a.v2); }
+template <class T>
+__device__ __forceinline__ void mv3_sub(const T* b, const Vec3<T>& x, T& a0, T& a1, T& a2) {
   a0 -= b[0] * x.v0 + b[1] * x.v1 + b[2] * x.v2;
   a1 -= b[3] * x.v0 + b[4] * x.v1 + b[5] * x.v2;
   a2 -= b[6] * x.v0 + b[7] * x.v1 + b[8] * x.v2;
@@ -619,27 +646,38 @@ __device__ __forceinline__ void mv3_sub(const double* b, const Vec3& x, double& 
 // Both directions share one kernel.
 //   FWD: y = L^-1 r2.  M = L blocks (-x, -y, -z), rhs = r2, both in the
 //        forward tile layout.  y goes to `ytile` in the backward tile layout
-//        (all lanes of a forward step land in one backward step: coalesced)
-//        and, for the lanes whose values other tiles read (high faces jj = 15,
-//        kk = 3), to the sentinel-filled natural-order vector `pub` with
-//        device-coherent stores.
+//        (all lanes of a forward step land in one backward step: coalesced);
+//        the lanes whose values other tiles read (high faces jj = 15,
+//        kk = 3) also publish them to the tile's face buffer.
 //   BWD: x2 = U^-1 y, z = P_E e0 + x2.  M = U blocks (+x, +y, +z) then
 //        U_ii^-1, rhs = ytile, e0 (NE values), all in the backward tile layout;
-//        only low-face lanes (jj = 0, kk = 0) publish x2.
+//        low-face lanes (jj = 0, kk = 0) publish x2.
+// Face buffer of a sweep: per tile and step 60 values, the J face (3
+// components x 4 lanes kk) then the K face (3 components x 16 lanes jj),
+// ((tile * nsteps + step) * 60 + ...), written with device-coherent stores at
+// the step that computes them and filled with the sentinel before the sweep.
+// A tile needs the J-face values of its upstream J neighbour from that tile's
+// step s + 15 and the K-face values of its K neighbour from step s + 3 (the
+// skew), so both the stores of one step and the loads of one step are
+// contiguous.
 // Tile layout of per-cell data with NV values: ((tile * nsteps + step) * NV +
 // e) * 64 + lane, tile = J + nJ K, step = the step that handles the cell in
 // this direction; slots of absent cells hold zeros.
-template <bool FWD, int NE>
+constexpr int kFaceVals = 3 * (kTK + kTJ);  // face-buffer values per tile and step
+constexpr int kSkewJ = kTJ - 1, kSkewK = kTK - 1;
+
+template <bool FWD, int NE, class T>
 struct GridTile {
   static constexpr int NV = FWD ? 27 : 36;
   int nx, ny, lag, nsteps;
-  long base, offJ, offK;
-  bool valid, pollJ, pollK, publish;
-  int jj, kk;
-  const double* pub;
+  long base;
+  bool valid, pollJ, pollK, pubJ, pubK;
+  int jj, kk, t, tJ, tK;
+  T* faces;
 
-  // tile t of an nJ-wide tile grid, seen by lane `lane`
-  __device__ __forceinline__ void init(int nx_, int ny_, int nz, int nJ, int t, int lane, const double* pub_) {
+  // tile t_ of an nJ-wide tile grid, seen by lane `lane`
+  __device__ __forceinline__ void init(int nx_, int ny_, int nz, int nJ, int t_, int lane, T* faces_) {
+    t = t_;
     const int J = t % nJ, K = t / nJ;
     nx = nx_;
     ny = ny_;
@@ -647,30 +685,54 @@ struct GridTile {
     kk = lane / kTJ;
     const int j = J * kTJ + jj, k = K * kTK + kk;
     valid = j < ny && k < nz;
-    const long line = nx, plane = (long)nx * ny;
     base = valid ? (long)nx * ((long)j + (long)ny * k) : 0;
     lag = FWD ? jj + kk : (kTJ - 1 - jj) + (kTK - 1 - kk);
     nsteps = nx + (kTJ - 1) + (kTK - 1);
     pollJ = valid && (FWD ? (jj == 0 && j > 0) : (jj == kTJ - 1 && j + 1 < ny));
     pollK = valid && (FWD ? (kk == 0 && k > 0) : (kk == kTK - 1 && k + 1 < nz));
-    publish = valid && (FWD ? (jj == kTJ - 1 || kk == kTK - 1) : (jj == 0 || kk == 0));
-    offJ = FWD ? -line : line;
-    offK = FWD ? -plane : plane;
-    pub = pub_;
+    pubJ = valid && (FWD ? jj == kTJ - 1 : jj == 0);
+    pubK = valid && (FWD ? kk == kTK - 1 : kk == 0);
+    tJ = FWD ? t - 1 : t + 1;    // the tiles whose faces this tile reads
+    tK = FWD ? t - nJ : t + nJ;
+    faces = faces_;
   }
   __device__ __forceinline__ int cell_i(int step) const { return FWD ? step - lag : nx - 1 - (step - lag); }
   __device__ __forceinline__ bool active(int step) const {
     const int i = cell_i(step);
     return valid && i >= 0 && i < nx;
   }
-  __device__ __forceinline__ void poll(int step, Vec3& bj, Vec3& bk) const {
+  // component q of the J-face value of lane (., kk) / K-face value of lane (jj, .)
+  __device__ __forceinline__ T* jface(int tile, int step, int q) const {
+    return faces + ((size_t)tile * nsteps + step) * kFaceVals + q * kTK + kk;
+  }
+  __device__ __forceinline__ T* kface(int tile, int step, int q) const {
+    return faces + ((size_t)tile * nsteps + step) * kFaceVals + 3 * kTK + q * kTJ + jj;
+  }
+  __device__ __forceinline__ void poll(int step, Vec3<T>& bj, Vec3<T>& bk) const {
     if (active(step)) {
-      const long c = base + cell_i(step);
-      if (pollJ) bj = ld3_dev(pub + 3 * (c + offJ));
-      if (pollK) bk = ld3_dev(pub + 3 * (c + offK));
+      if (pollJ) bj = {ld_dev(jface(tJ, step + kSkewJ, 0)), ld_dev(jface(tJ, step + kSkewJ, 1)),
+                       ld_dev(jface(tJ, step + kSkewJ, 2))};
+      if (pollK) bk = {ld_dev(kface(tK, step + kSkewK, 0)), ld_dev(kface(tK, step + kSkewK, 1)),
+                       ld_dev(kface(tK, step + kSkewK, 2))};
     }
   }
-  __device__ __forceinline__ bool ready(int step, const Vec3& bj, const Vec3& bk) const {
+  // the value one waiting lane spins on: the last component of a missing face
+  __device__ __forceinline__ const T* spin_addr(int step, const Vec3<T>& bj) const {
+    return pollJ && sent3(bj) ? jface(tJ, step + kSkewJ, 2) : kface(tK, step + kSkewK, 2);
+  }
+  __device__ __forceinline__ void publish(int step, T a0, T a1, T a2) const {
+    if (pubJ) {
+      st_dev(jface(t, step, 0), a0);
+      st_dev(jface(t, step, 1), a1);
+      st_dev(jface(t, step, 2), a2);
+    }
+    if (pubK) {
+      st_dev(kface(t, step, 0), a0);
+      st_dev(kface(t, step, 1), a1);
+      st_dev(kface(t, step, 2), a2);
+    }
+  }
+  __device__ __forceinline__ bool ready(int step, const Vec3<T>& bj, const Vec3<T>& bk) const {
     return !(active(step) && ((pollJ && sent3(bj)) || (pollK && sent3(bk))));
   }
 };
@@ -687,7 +749,12 @@ __device__ __forceinline__ double dpp_row_shift(double x, double old) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 template <bool FWD>
-__device__ __forceinline__ Vec3 grid_shift_j(const Vec3& x, const Vec3& old) {
+__device__ __forceinline__ float dpp_row_shift(float x, float old) {
+  constexpr int ctrl = FWD ? 0x111 : 0x101;
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(x), ctrl, 0xF, 0xF, false));
+}
+template <bool FWD, class T>
+__device__ __forceinline__ Vec3<T> grid_shift_j(const Vec3<T>& x, const Vec3<T>& old) {
   return {dpp_row_shift<FWD>(x.v0, old.v0), dpp_row_shift<FWD>(x.v1, old.v1), dpp_row_shift<FWD>(x.v2, old.v2)};
 }
 
@@ -695,61 +762,54 @@ __device__ __forceinline__ Vec3 grid_shift_j(const Vec3& x, const Vec3& old) {
 // off-diagonal block values, ui the 9 of U_ii^-1 (backward), r the right-hand
 // side (3, then NE values of e0 backward); vj and vk are the values of the two
 // other lower (upper) neighbours.
-template <bool FWD, int NE>
+template <bool FWD, int NE, class T>
 struct GridCell {
-  GridTile<FWD, NE> g;
-  Vec3 prev, last;  // own result one cell earlier / of the last step
-  double* yo;       // forward: this tile's last backward-layout row of ytile
+  GridTile<FWD, NE, T> g;
+  Vec3<T> prev, last;  // own result one cell earlier / of the last step
+  T* yo;            // forward: this tile's last backward-layout row of ytile
   double* z;
   bool has_e0;
   int ea, eb;
 
-  __device__ __forceinline__ void init(int nx, int ny, int nz, int nJ, int t, int lane, const double* pub,
-                                       double* ytile, const double* e0t, int ea_, int eb_, double* z_) {
-    g.init(nx, ny, nz, nJ, t, lane, pub);
+  __device__ __forceinline__ void init(int nx, int ny, int nz, int nJ, int t, int lane, T* faces,
+                                       T* ytile, const T* e0t, int ea_, int eb_, double* z_) {
+    g.init(nx, ny, nz, nJ, t, lane, faces);
     const size_t trow = (size_t)t * g.nsteps;
     yo = FWD ? ytile + (trow + g.nsteps - 1) * 3 * 64 + lane : nullptr;
     z = z_;
     has_e0 = e0t != nullptr;
     ea = ea_;
     eb = eb_;
-    prev = last = {0.0, 0.0, 0.0};
+    prev = last = {T(0), T(0), T(0)};
   }
 
-  __device__ __forceinline__ void update(int s, const Vec3& vj, const Vec3& vk, const double* m,
-                                         const double* ui, const double* r, double* pub) {
+  __device__ __forceinline__ void update(int s, const Vec3<T>& vj, const Vec3<T>& vk, const T* m,
+                                         const T* ui, const T* r) {
     if (!g.active(s)) return;
-    double a0 = r[0], a1 = r[1], a2 = r[2];
+    T a0 = r[0], a1 = r[1], a2 = r[2];
     mv3_sub(&m[0], prev, a0, a1, a2);
     mv3_sub(&m[9], vj, a0, a1, a2);
     mv3_sub(&m[18], vk, a0, a1, a2);
     const long c = g.base + g.cell_i(s);
     if (FWD) {
       // the backward sweep handles this cell at step nsteps - 1 - s
-      double* yw = yo - (size_t)s * 3 * 64;
+      T* yw = yo - (size_t)s * 3 * 64;
       yw[0] = a0;
       yw[64] = a1;
       yw[128] = a2;
-      if (g.publish) {
-        st_dev(pub + 3 * c, a0);
-        st_dev(pub + 3 * c + 1, a1);
-        st_dev(pub + 3 * c + 2, a2);
-      }
+      g.publish(s, a0, a1, a2);
       prev = {a0, a1, a2};
     } else {
-      const double o0 = ui[0] * a0 + ui[1] * a1 + ui[2] * a2;
-      const double o1 = ui[3] * a0 + ui[4] * a1 + ui[5] * a2;
-      const double o2 = ui[6] * a0 + ui[7] * a1 + ui[8] * a2;
-      if (g.publish) {
-        st_dev(pub + 3 * c, o0);
-        st_dev(pub + 3 * c + 1, o1);
-        st_dev(pub + 3 * c + 2, o2);
-      }
-      const double ex = has_e0 ? r[3] : 0.0;
-      const double ey = (NE == 2 && has_e0) ? r[3 + NE - 1] : 0.0;
-      z[3 * c] = o0 + (ea == 0 ? ex : 0.0) + (NE == 2 && eb == 0 ? ey : 0.0);
-      z[3 * c + 1] = o1 + (ea == 1 ? ex : 0.0) + (NE == 2 && eb == 1 ? ey : 0.0);
-      z[3 * c + 2] = o2 + (ea == 2 ? ex : 0.0) + (NE == 2 && eb == 2 ? ey : 0.0);
+      const T o0 = ui[0] * a0 + ui[1] * a1 + ui[2] * a2;
+      const T o1 = ui[3] * a0 + ui[4] * a1 + ui[5] * a2;
+      const T o2 = ui[6] * a0 + ui[7] * a1 + ui[8] * a2;
+      g.publish(s, o0, o1, o2);
+      // z = P_E e0 + x2 in FP64
+      const double ex = has_e0 ? (double)r[3] : 0.0;
+      const double ey = (NE == 2 && has_e0) ? (double)r[3 + NE - 1] : 0.0;
+      z[3 * c] = (double)o0 + (ea == 0 ? ex : 0.0) + (NE == 2 && eb == 0 ? ey : 0.0);
+      z[3 * c + 1] = (double)o1 + (ea == 1 ? ex : 0.0) + (NE == 2 && eb == 1 ? ey : 0.0);
+      z[3 * c + 2] = (double)o2 + (ea == 2 ? ex : 0.0) + (NE == 2 && eb == 2 ? ey : 0.0);
       prev = {o0, o1, o2};
     }
     last = prev;
@@ -782,35 +842,37 @@ __device__ __forceinline__ void lds_release() { __builtin_amdgcn_fence(__ATOMIC_
 typedef __attribute__((address_space(3))) void lds_void;
 typedef __attribute__((address_space(1))) void glb_void;
 
-// copy of N doubles (N a multiple of 64, 16-byte aligned) from global memory
-// straight into LDS by one wave: each instruction moves 64 x 16 bytes, the
-// lanes of a half-used last instruction stay masked
-template <int N>
-__device__ __forceinline__ void wave_copy_to_lds(const double* src, double* dst, int lane) {
+// copy of N values of T (N * sizeof(T) a multiple of 256 bytes, 16-byte
+// aligned) from global memory straight into LDS by one wave: each instruction
+// moves 64 x 16 bytes, the lanes past the end of the last one stay masked
+template <class T, int N>
+__device__ __forceinline__ void wave_copy_to_lds(const T* src, T* dst, int lane) {
+  constexpr int PL = 16 / (int)sizeof(T);  // values per lane and instruction
+  constexpr int PI = 64 * PL;              // values per instruction
 #pragma unroll
-  for (int q = 0; q < (N + 127) / 128; ++q) {
-    if (N % 128 == 0 || q * 128 + 2 * lane < N)
-      __builtin_amdgcn_global_load_lds((glb_void*)(src + q * 128 + 2 * lane), (lds_void*)(dst + q * 128),
+  for (int q = 0; q < (N + PI - 1) / PI; ++q) {
+    if (N % PI == 0 || q * PI + PL * lane < N)
+      __builtin_amdgcn_global_load_lds((glb_void*)(src + q * PI + PL * lane), (lds_void*)(dst + q * PI),
                                        16, 0, 0);
   }
 }
 
-template <bool FWD, int NE, int H, int R>
+template <bool FWD, int NE, int H, int R, class T>
 __global__ __launch_bounds__(64 * (H + 1)) void k_ilu_grid(int nx, int ny, int nz, int nJ, int nK,
-                                                               const double* __restrict__ M,
-                                                               const double* rhs, double* ytile,
-                                                               double* pub,
-                                                               const double* __restrict__ e0t,
+                                                               const T* __restrict__ M,
+                                                               const T* rhs, T* ytile,
+                                                               T* faces,
+                                                               const T* __restrict__ e0t,
                                                                int ea, int eb, double* __restrict__ z,
                                                                int* tickets, double* err,
                                                                long spin_limit) {
-  constexpr int NV = GridTile<FWD, NE>::NV;
+  constexpr int NV = GridTile<FWD, NE, T>::NV;
   constexpr int NE0 = FWD ? 0 : NE;
   constexpr int NR = 3 + NE0;
   // slot: M (NV), rhs (3), e0 (NE0), polled j and k values (3 + 3); x 64 lanes
   constexpr int OR = NV * 64, OE = (NV + 3) * 64, OF = (NV + NR) * 64;
   constexpr int SLOT = (NV + NR + 6) * 64;
-  __shared__ double ring[R * SLOT];
+  __shared__ T ring[R * SLOT];
   __shared__ int s_ready[R];
   __shared__ int s_t, s_consumed, s_abort;
   if (threadIdx.x == 0) {
@@ -824,9 +886,9 @@ __global__ __launch_bounds__(64 * (H + 1)) void k_ilu_grid(int nx, int ny, int n
   // the wave index is uniform per wave: keep it (and the stagers' loops) scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int wait_limit = (int)min(4 * spin_limit, (long)1 << 30);
-  GridCell<FWD, NE> w;
-  w.init(nx, ny, nz, nJ, t, lane, pub, ytile, e0t, ea, eb, z);
-  const GridTile<FWD, NE>& g = w.g;
+  GridCell<FWD, NE, T> w;
+  w.init(nx, ny, nz, nJ, t, lane, faces, ytile, e0t, ea, eb, z);
+  const GridTile<FWD, NE, T>& g = w.g;
   const int nsteps = g.nsteps;
   const size_t trow = (size_t)t * nsteps;
 
@@ -848,17 +910,17 @@ __global__ __launch_bounds__(64 * (H + 1)) void k_ilu_grid(int nx, int ny, int n
         __builtin_amdgcn_s_sleep(1);
       }
       lds_acquire();
-      double* slot = ring + (s % R) * SLOT;
+      T* slot = ring + (s % R) * SLOT;
       const size_t row = trow + min(s, nsteps - 1);
-      wave_copy_to_lds<NV * 64>(M + row * NV * 64, slot, lane);
-      wave_copy_to_lds<3 * 64>(rhs + row * 3 * 64, slot + OR, lane);
+      wave_copy_to_lds<T, NV * 64>(M + row * NV * 64, slot, lane);
+      wave_copy_to_lds<T, 3 * 64>(rhs + row * 3 * 64, slot + OR, lane);
       // without e0 (M2^-1 alone) the slot's e0 part is left as it is: unused
-      if (!FWD && e0t) wave_copy_to_lds<NE0 * 64>(e0t + row * NE0 * 64, slot + OE, lane);
+      if (!FWD && e0t) wave_copy_to_lds<T, NE0 * 64>(e0t + row * NE0 * 64, slot + OE, lane);
       // values of the neighbouring tiles, once published.  All face values a
       // step needs from one neighbour come from one step of that tile, so
       // while they are missing a single lane waits on one of them and the
       // whole face is read again once it is there.
-      Vec3 bj = {0.0, 0.0, 0.0}, bk = bj;
+      Vec3<T> bj = {T(0), T(0), T(0)}, bk = bj;
       bool need = g.active(s) && (g.pollJ || g.pollK);
       for (;;) {
         if (need) {
@@ -878,14 +940,12 @@ __global__ __launch_bounds__(64 * (H + 1)) void k_ilu_grid(int nx, int ny, int n
           __builtin_amdgcn_s_sleep(2);
           bool there = true;
           if (lane == leader) {
-            const long c = g.base + g.cell_i(s);
-            const double* q = g.pub + 3 * (c + (g.pollJ && sent3(bj) ? g.offJ : g.offK)) + 2;
-            there = !is_sent(ld_dev(q));
+            there = !is_sent(ld_dev(g.spin_addr(s, bj)));
           }
           if (__all(there)) break;
         }
       }
-      double* f = slot + OF + lane;
+      T* f = slot + OF + lane;
       f[0] = bj.v0;
       f[64] = bj.v1;
       f[128] = bj.v2;
@@ -903,8 +963,8 @@ __global__ __launch_bounds__(64 * (H + 1)) void k_ilu_grid(int nx, int ny, int n
   // LDS crossbar, then issues the reads of the next step's slot and the ready
   // flag of the step after it, and computes while they are in flight; the
   // j-shift is a DPP move whose edge lanes keep the polled value.
-  double ma[NV], mb[NV], ra[NR], rb[NR];
-  Vec3 ja, ka, jb, kb;
+  T ma[NV], mb[NV], ra[NR], rb[NR];
+  Vec3<T> ja, ka, jb, kb;
   const bool kedge = FWD ? g.kk == 0 : g.kk == kTK - 1;
   auto wait_ready = [&](int s) __attribute__((always_inline)) -> bool {
     const int slot = s % R;
@@ -916,8 +976,8 @@ __global__ __launch_bounds__(64 * (H + 1)) void k_ilu_grid(int nx, int ny, int n
     return true;
   };
   // (the caller has seen the ready flag of step s and fenced)
-  auto read = [&](double* m, double* r, Vec3& bj, Vec3& bk, int s) __attribute__((always_inline)) {
-    const double* sl = ring + (s % R) * SLOT + lane;
+  auto read = [&](T* m, T* r, Vec3<T>& bj, Vec3<T>& bk, int s) __attribute__((always_inline)) {
+    const T* sl = ring + (s % R) * SLOT + lane;
 #pragma unroll
     for (int e = 0; e < NV; ++e) m[e] = sl[e * 64];
 #pragma unroll
@@ -931,15 +991,15 @@ __global__ __launch_bounds__(64 * (H + 1)) void k_ilu_grid(int nx, int ny, int n
   };
   // step s on (m, r, bj, bk) while the slot of step s + 1 is read into
   // (mn, rn, bjn, bkn); returns the ready flag of step s + 2
-  auto step = [&](int s, const double* m, const double* r, const Vec3& bj, const Vec3& bk, double* mn,
-                  double* rn, Vec3& bjn, Vec3& bkn) __attribute__((always_inline)) -> int {
-    const Vec3 fk = FWD ? shfl_up3(w.last, kTJ) : shfl_down3(w.last, kTJ);
+  auto step = [&](int s, const T* m, const T* r, const Vec3<T>& bj, const Vec3<T>& bk, T* mn,
+                  T* rn, Vec3<T>& bjn, Vec3<T>& bkn) __attribute__((always_inline)) -> int {
+    const Vec3<T> fk = FWD ? shfl_up3(w.last, kTJ) : shfl_down3(w.last, kTJ);
     __builtin_amdgcn_sched_barrier(0);
     read(mn, rn, bjn, bkn, s + 1);
     const int f = lds_ld(&s_ready[(s + 2) % R]);
     __builtin_amdgcn_sched_barrier(0);
-    const Vec3 vj = grid_shift_j<FWD>(w.last, bj);
-    w.update(s, vj, kedge ? bk : fk, m, m + 27, r, pub);
+    const Vec3<T> vj = grid_shift_j<FWD>(w.last, bj);
+    w.update(s, vj, kedge ? bk : fk, m, m + 27, r);
     consumed(s + 1);
     return f;
   };
@@ -965,22 +1025,27 @@ __global__ __launch_bounds__(64 * (H + 1)) void k_ilu_grid(int nx, int ny, int n
 }
 
 // stage-two residual for the grid sweeps: r2 and e0 are also written in the
-// tile layouts (r2 forward, e0 backward), and the face vectors get the
-// sentinel; both ticket counters := 0
-template <int NE>
+// tile layouts (r2 forward, e0 backward), the face buffers of both sweeps
+// (nfaces values) get the sentinel, and both ticket counters := 0
+template <int NE, class T>
 __global__ __launch_bounds__(kBlock) void k_stage2_grid(int nx, int ny, int nz, int nrows, int nblk,
                                                         const int32_t* __restrict__ sptr,
                                                         const int32_t* __restrict__ col,
                                                         const double* __restrict__ val, int ea,
-                                                        int eb, const double* __restrict__ e0,
+                                                        int eb, const T* __restrict__ e0,
                                                         const double* __restrict__ r,
-                                                        double* __restrict__ r2t,
-                                                        double* __restrict__ e0t,
-                                                        double* __restrict__ y,
-                                                        double* __restrict__ x2, int* tickets) {
+                                                        T* __restrict__ r2t,
+                                                        T* __restrict__ e0t,
+                                                        T* __restrict__ faces, int64_t nfaces,
+                                                        int* tickets) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     tickets[0] = 0;
     tickets[1] = 0;
+  }
+  {
+    const T s0 = sentinel_value<T>();
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < nfaces; q += stride) faces[q] = s0;
   }
   const int row = xcd_block(blockIdx.x, nblk) * kBlock + threadIdx.x;
   if (row >= nrows) return;
@@ -1011,24 +1076,14 @@ __global__ __launch_bounds__(kBlock) void k_stage2_grid(int nx, int ny, int nz, 
   const size_t frow = t * ns + (i + jj + kk);
   const size_t brow = t * ns + ((nx - 1 - i) + (kTJ - 1 - jj) + (kTK - 1 - kk));
   const double* ri = r + 3 * (size_t)row;
-  double* o = r2t + frow * 3 * 64 + lane;
-  o[0] = ri[0] - a0;
-  o[64] = ri[1] - a1;
-  o[128] = ri[2] - a2;
+  T* o = r2t + frow * 3 * 64 + lane;
+  o[0] = (T)(ri[0] - a0);
+  o[64] = (T)(ri[1] - a1);
+  o[128] = (T)(ri[2] - a2);
   if (e0) {
-    double* eo = e0t + brow * NE * 64 + lane;
+    T* eo = e0t + brow * NE * 64 + lane;
     eo[0] = e0[(size_t)row * NE];
     if (NE == 2) eo[64] = e0[(size_t)row * NE + 1];
-  }
-  const bool face = jj == 0 || jj == kTJ - 1 || kk == 0 || kk == kTK - 1;
-  if (face) {
-    const double s0 = __longlong_as_double((long long)kSentinel);
-    y[3 * (size_t)row] = s0;
-    y[3 * (size_t)row + 1] = s0;
-    y[3 * (size_t)row + 2] = s0;
-    x2[3 * (size_t)row] = s0;
-    x2[3 * (size_t)row + 1] = s0;
-    x2[3 * (size_t)row + 2] = s0;
   }
   (void)nz;
 }
@@ -1229,81 +1284,90 @@ void launch_bsr3_spmv(const Sell& A, const double* x, const double* b, double* y
     k_bsr3_spmv<false><<<g, kBlock, 0, st>>>(A.nrows, g, A.sptr, A.col, A.val, x, b, y);
 }
 
+template <class T>
 void launch_l0_restrict(int32_t nc, int ne, const double* r, const double* W, const int32_t* eidx,
-                        const int32_t* hidx, double* b0, hipStream_t st) {
+                        const int32_t* hidx, T* b0, hipStream_t st) {
   const int g = nblocks(nc, kBlock);
   if (ne == 2)
-    k_l0_restrict<2><<<g, kBlock, 0, st>>>(nc, r, W, eidx[0], eidx[1], hidx[0], 0, b0);
+    k_l0_restrict<2, T><<<g, kBlock, 0, st>>>(nc, r, W, eidx[0], eidx[1], hidx[0], 0, b0);
   else
-    k_l0_restrict<1><<<g, kBlock, 0, st>>>(nc, r, W, eidx[0], 0, hidx[0], hidx[1], b0);
+    k_l0_restrict<1, T><<<g, kBlock, 0, st>>>(nc, r, W, eidx[0], 0, hidx[0], hidx[1], b0);
 }
 
-void launch_l0_resid_jacobi(const Sell& Ah, int ne, const double* b0, const double* dinv, double* r0,
+template <class T>
+void launch_l0_resid_jacobi(const SellT<T>& Ah, int ne, const T* b0, const T* dinv, T* r0,
                             hipStream_t st) {
   const int g = nblocks(Ah.nrows, kBlock);
   if (ne == 2)
-    k_l0_resid_jacobi<2><<<g, kBlock, 0, st>>>(Ah.nrows, g, Ah.sptr, Ah.col, Ah.val, b0, dinv, r0);
+    k_l0_resid_jacobi<2, T><<<g, kBlock, 0, st>>>(Ah.nrows, g, Ah.sptr, Ah.col, Ah.val, b0, dinv, r0);
   else
-    k_l0_resid_jacobi<1><<<g, kBlock, 0, st>>>(Ah.nrows, g, Ah.sptr, Ah.col, Ah.val, b0, dinv, r0);
+    k_l0_resid_jacobi<1, T><<<g, kBlock, 0, st>>>(Ah.nrows, g, Ah.sptr, Ah.col, Ah.val, b0, dinv, r0);
 }
 
-void launch_l0_post(const Sell& Ah, int ne, const double* x0, const double* b0, const double* dinv,
-                    double* e0, hipStream_t st) {
+template <class T>
+void launch_l0_post(const SellT<T>& Ah, int ne, const T* x0, const T* b0, const T* dinv, T* e0,
+                    hipStream_t st) {
   const int g = nblocks(Ah.nrows, kBlock);
   if (ne == 2)
-    k_l0_post<2><<<g, kBlock, 0, st>>>(Ah.nrows, g, Ah.sptr, Ah.col, Ah.val, x0, b0, dinv, e0);
+    k_l0_post<2, T><<<g, kBlock, 0, st>>>(Ah.nrows, g, Ah.sptr, Ah.col, Ah.val, x0, b0, dinv, e0);
   else
-    k_l0_post<1><<<g, kBlock, 0, st>>>(Ah.nrows, g, Ah.sptr, Ah.col, Ah.val, x0, b0, dinv, e0);
+    k_l0_post<1, T><<<g, kBlock, 0, st>>>(Ah.nrows, g, Ah.sptr, Ah.col, Ah.val, x0, b0, dinv, e0);
 }
 
-void launch_csr_resid_jacobi(const DCsr& A, const double* b, const double* dinv, double* r,
-                             hipStream_t st) {
-  launch_csr_op<kResidJacobi>(A, nullptr, b, dinv, r, st);
+template <class T>
+void launch_csr_resid_jacobi(const DCsrT<T>& A, const T* b, const T* dinv, T* r, hipStream_t st) {
+  launch_csr_op<kResidJacobi, T>(A, nullptr, b, dinv, r, st);
 }
-void launch_csr_spmv(const DCsr& A, const double* x, double* y, hipStream_t st) {
-  launch_csr_op<kSpmv>(A, x, nullptr, nullptr, y, st);
+template <class T>
+void launch_csr_spmv(const DCsrT<T>& A, const T* x, T* y, hipStream_t st) {
+  launch_csr_op<kSpmv, T>(A, x, nullptr, nullptr, y, st);
 }
-void launch_csr_prolong(const DCsr& P, const double* xc, const double* b, const double* dinv,
-                        double* x, hipStream_t st) {
-  launch_csr_op<kProlong>(P, xc, b, dinv, x, st);
+template <class T>
+void launch_csr_prolong(const DCsrT<T>& P, const T* xc, const T* b, const T* dinv, T* x,
+                        hipStream_t st) {
+  launch_csr_op<kProlong, T>(P, xc, b, dinv, x, st);
 }
-void launch_csr_post(const DCsr& A, const double* x, const double* b, const double* dinv, double* e,
-                     hipStream_t st) {
-  launch_csr_op<kPost>(A, x, b, dinv, e, st);
+template <class T>
+void launch_csr_post(const DCsrT<T>& A, const T* x, const T* b, const T* dinv, T* e, hipStream_t st) {
+  launch_csr_op<kPost, T>(A, x, b, dinv, e, st);
 }
 
-void launch_coarse_solve(int n, const double* lu, const int32_t* piv, const double* b, double* x,
+template <class T>
+void launch_coarse_solve(int n, const double* lu, const int32_t* piv, const T* b, T* x,
                          hipStream_t st) {
-  k_coarse_solve<<<1, kBlock, sizeof(double) * (size_t)n, st>>>(n, lu, piv, b, x);
+  k_coarse_solve<T><<<1, kBlock, sizeof(double) * (size_t)n, st>>>(n, lu, piv, b, x);
 }
 
-void launch_stage2_resid(const Sell& A, int ne, const int32_t* eidx, const double* e0,
-                         const double* r, double* r2, hipStream_t st) {
+template <class T>
+void launch_stage2_resid(const Sell& A, int ne, const int32_t* eidx, const T* e0, const double* r,
+                         T* r2, hipStream_t st) {
   const int g = nblocks(A.nrows, kBlock);
   if (ne == 2)
-    k_stage2_resid<2><<<g, kBlock, 0, st>>>(A.nrows, g, A.sptr, A.col, A.val, eidx[0], eidx[1], e0, r, r2);
+    k_stage2_resid<2, T><<<g, kBlock, 0, st>>>(A.nrows, g, A.sptr, A.col, A.val, eidx[0], eidx[1], e0, r, r2);
   else
-    k_stage2_resid<1><<<g, kBlock, 0, st>>>(A.nrows, g, A.sptr, A.col, A.val, eidx[0], 0, e0, r, r2);
+    k_stage2_resid<1, T><<<g, kBlock, 0, st>>>(A.nrows, g, A.sptr, A.col, A.val, eidx[0], 0, e0, r, r2);
 }
 
-void launch_ilu_fwd_level(const Sell& L, const int32_t* perm, int32_t p0, int32_t p1,
-                          const double* r2, double* y, hipStream_t st) {
+template <class T>
+void launch_ilu_fwd_level(const SellT<T>& L, const int32_t* perm, int32_t p0, int32_t p1, const T* r2,
+                          T* y, hipStream_t st) {
   if (p1 <= p0) return;
-  k_ilu_fwd<<<nblocks(p1 - p0, kBlock), kBlock, 0, st>>>(p0, p1, L.sptr, L.col, L.val, perm, r2, y);
+  k_ilu_fwd<T><<<nblocks(p1 - p0, kBlock), kBlock, 0, st>>>(p0, p1, L.sptr, L.col, L.val, perm, r2, y);
 }
 
-void launch_ilu_bwd_level(const Sell& U, const int32_t* perm, const double* uinv, int32_t p0,
-                          int32_t p1, const double* y, const double* e0, int ne,
-                          const int32_t* eidx, double* x2, double* z, hipStream_t st) {
+template <class T>
+void launch_ilu_bwd_level(const SellT<T>& U, const int32_t* perm, const T* uinv, int32_t p0,
+                          int32_t p1, const T* y, const T* e0, int ne, const int32_t* eidx, T* x2,
+                          double* z, hipStream_t st) {
   if (p1 <= p0) return;
   const int npad = U.nslices * 64;
   const int g = nblocks(p1 - p0, kBlock);
   if (ne == 2)
-    k_ilu_bwd<2><<<g, kBlock, 0, st>>>(p0, p1, npad, U.sptr, U.col, U.val, perm, uinv, y, e0,
-                                       eidx[0], eidx[1], x2, z);
+    k_ilu_bwd<2, T><<<g, kBlock, 0, st>>>(p0, p1, npad, U.sptr, U.col, U.val, perm, uinv, y, e0,
+                                          eidx[0], eidx[1], x2, z);
   else
-    k_ilu_bwd<1><<<g, kBlock, 0, st>>>(p0, p1, npad, U.sptr, U.col, U.val, perm, uinv, y, e0,
-                                       eidx[0], 0, x2, z);
+    k_ilu_bwd<1, T><<<g, kBlock, 0, st>>>(p0, p1, npad, U.sptr, U.col, U.val, perm, uinv, y, e0,
+                                          eidx[0], 0, x2, z);
 }
 
 
@@ -1318,50 +1382,59 @@ void launch_stage2_resid_sf(const Sell& A, int ne, const int32_t* eidx, const do
 }
 
 
-void launch_prolong_e(int32_t nrows, int ne, const int32_t* eidx, const double* e0, double* x1,
+template <class T>
+void launch_prolong_e(int32_t nrows, int ne, const int32_t* eidx, const T* e0, double* x1,
                       hipStream_t st) {
   const int g = nblocks(nrows, kBlock);
-  if (ne == 2) k_prolong_e<2><<<g, kBlock, 0, st>>>(nrows, e0, eidx[0], eidx[1], x1);
-  else k_prolong_e<1><<<g, kBlock, 0, st>>>(nrows, e0, eidx[0], 0, x1);
+  if (ne == 2) k_prolong_e<2, T><<<g, kBlock, 0, st>>>(nrows, e0, eidx[0], eidx[1], x1);
+  else k_prolong_e<1, T><<<g, kBlock, 0, st>>>(nrows, e0, eidx[0], 0, x1);
 }
 void launch_sweep_prepare(int64_t n, double* y, double* x2, int* tickets, hipStream_t st) {
   k_sweep_prepare<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, y, x2, tickets);
 }
 
 
-void launch_stage2_grid(int nx, int ny, int nz, const Sell& A, int ne, const int32_t* eidx,
-                        const double* e0, const double* r, double* r2t, double* e0t, double* y,
-                        double* x2, int* tickets, hipStream_t st) {
+int64_t grid_face_values(int nx, int ny, int nz) {
+  return grid_ntiles(ny, nz) * grid_nsteps(nx) * kFaceVals;
+}
+
+template <class T>
+void launch_stage2_grid(int nx, int ny, int nz, const Sell& A, int ne, const int32_t* eidx, const T* e0,
+                        const double* r, T* r2t, T* e0t, T* faces, int* tickets, hipStream_t st) {
   const int g = nblocks(A.nrows, kBlock);
+  const int64_t nfaces = 2 * grid_face_values(nx, ny, nz);
   if (ne == 2)
-    k_stage2_grid<2><<<g, kBlock, 0, st>>>(nx, ny, nz, A.nrows, g, A.sptr, A.col, A.val, eidx[0], eidx[1],
-                                           e0, r, r2t, e0t, y, x2, tickets);
+    k_stage2_grid<2, T><<<g, kBlock, 0, st>>>(nx, ny, nz, A.nrows, g, A.sptr, A.col, A.val, eidx[0],
+                                              eidx[1], e0, r, r2t, e0t, faces, nfaces, tickets);
   else
-    k_stage2_grid<1><<<g, kBlock, 0, st>>>(nx, ny, nz, A.nrows, g, A.sptr, A.col, A.val, eidx[0], 0,
-                                           e0, r, r2t, e0t, y, x2, tickets);
+    k_stage2_grid<1, T><<<g, kBlock, 0, st>>>(nx, ny, nz, A.nrows, g, A.sptr, A.col, A.val, eidx[0], 0,
+                                              e0, r, r2t, e0t, faces, nfaces, tickets);
 }
 
 // workgroup: the sweeping wave and kGridStagers staging waves; ring slots:
-// as many as fit in LDS (18 KB forward, 24 KB backward per slot)
+// as many as fit in LDS (18 KB forward, 24 KB backward per slot in FP64; the
+// FP32 slots are half that)
 constexpr int kGridStagers = 3;
 
-void launch_ilu_fwd_grid(int nx, int ny, int nz, const double* Lt, const double* r2t, double* ytile,
-                         double* y, int* tickets, double* err, long spin_limit, hipStream_t st) {
+template <class T>
+void launch_ilu_fwd_grid(int nx, int ny, int nz, const T* Lt, const T* r2t, T* ytile, T* faces,
+                         int* tickets, double* err, long spin_limit, hipStream_t st) {
   const int nJ = (ny + kTJ - 1) / kTJ, nK = (nz + kTK - 1) / kTK;
-  k_ilu_grid<true, 2, kGridStagers, 8><<<nJ * nK, 64 * (kGridStagers + 1), 0, st>>>(
-      nx, ny, nz, nJ, nK, Lt, r2t, ytile, y, nullptr, 0, 0, nullptr, tickets, err, spin_limit);
+  k_ilu_grid<true, 2, kGridStagers, 8, T><<<nJ * nK, 64 * (kGridStagers + 1), 0, st>>>(
+      nx, ny, nz, nJ, nK, Lt, r2t, ytile, faces, nullptr, 0, 0, nullptr, tickets, err, spin_limit);
 }
 
-void launch_ilu_bwd_grid(int nx, int ny, int nz, const double* Ut, double* ytile, const double* e0t,
-                         int ne, const int32_t* eidx, double* x2, double* z, int* tickets,
-                         double* err, long spin_limit, hipStream_t st) {
+template <class T>
+void launch_ilu_bwd_grid(int nx, int ny, int nz, const T* Ut, T* ytile, const T* e0t, int ne,
+                         const int32_t* eidx, T* faces, double* z, int* tickets, double* err,
+                         long spin_limit, hipStream_t st) {
   const int nJ = (ny + kTJ - 1) / kTJ, nK = (nz + kTK - 1) / kTK;
   if (ne == 2)
-    k_ilu_grid<false, 2, kGridStagers, 6><<<nJ * nK, 64 * (kGridStagers + 1), 0, st>>>(
-        nx, ny, nz, nJ, nK, Ut, ytile, nullptr, x2, e0t, eidx[0], eidx[1], z, tickets, err, spin_limit);
+    k_ilu_grid<false, 2, kGridStagers, 6, T><<<nJ * nK, 64 * (kGridStagers + 1), 0, st>>>(
+        nx, ny, nz, nJ, nK, Ut, ytile, nullptr, faces, e0t, eidx[0], eidx[1], z, tickets, err, spin_limit);
   else
-    k_ilu_grid<false, 1, kGridStagers, 6><<<nJ * nK, 64 * (kGridStagers + 1), 0, st>>>(
-        nx, ny, nz, nJ, nK, Ut, ytile, nullptr, x2, e0t, eidx[0], 0, z, tickets, err, spin_limit);
+    k_ilu_grid<false, 1, kGridStagers, 6, T><<<nJ * nK, 64 * (kGridStagers + 1), 0, st>>>(
+        nx, ny, nz, nJ, nK, Ut, ytile, nullptr, faces, e0t, eidx[0], 0, z, tickets, err, spin_limit);
 }
 
 int ilu_sf_width(int max_width) {
@@ -1433,5 +1506,34 @@ void launch_update_host_coef(int64_t n, int nv, const double* V, int64_t ldv, co
   for (int j = 0; j < 64; ++j) c.c[j] = j < nv ? coef[j] : 0.0;
   k_update<<<kRedBlocks, kBlock, 0, st>>>(n, nv, V, ldv, c, x);
 }
+
+// the preconditioner runs in FP64 or, in the mixed-precision mode, in FP32
+#define CPTR_PREC_LAUNCHERS(T)                                                                      \
+  template void launch_l0_restrict<T>(int32_t, int, const double*, const double*, const int32_t*,   \
+                                      const int32_t*, T*, hipStream_t);                               \
+  template void launch_l0_resid_jacobi<T>(const SellT<T>&, int, const T*, const T*, T*, hipStream_t); \
+  template void launch_l0_post<T>(const SellT<T>&, int, const T*, const T*, const T*, T*, hipStream_t); \
+  template void launch_csr_resid_jacobi<T>(const DCsrT<T>&, const T*, const T*, T*, hipStream_t);    \
+  template void launch_csr_spmv<T>(const DCsrT<T>&, const T*, T*, hipStream_t);                      \
+  template void launch_csr_prolong<T>(const DCsrT<T>&, const T*, const T*, const T*, T*, hipStream_t); \
+  template void launch_csr_post<T>(const DCsrT<T>&, const T*, const T*, const T*, T*, hipStream_t);  \
+  template void launch_coarse_solve<T>(int, const double*, const int32_t*, const T*, T*, hipStream_t); \
+  template void launch_stage2_resid<T>(const Sell&, int, const int32_t*, const T*, const double*, T*, \
+                                       hipStream_t);                                                 \
+  template void launch_ilu_fwd_level<T>(const SellT<T>&, const int32_t*, int32_t, int32_t, const T*, \
+                                        T*, hipStream_t);                                            \
+  template void launch_ilu_bwd_level<T>(const SellT<T>&, const int32_t*, const T*, int32_t, int32_t,  \
+                                        const T*, const T*, int, const int32_t*, T*, double*,        \
+                                        hipStream_t);                                                \
+  template void launch_prolong_e<T>(int32_t, int, const int32_t*, const T*, double*, hipStream_t);   \
+  template void launch_stage2_grid<T>(int, int, int, const Sell&, int, const int32_t*, const T*,     \
+                                      const double*, T*, T*, T*, int*, hipStream_t);                 \
+  template void launch_ilu_fwd_grid<T>(int, int, int, const T*, const T*, T*, T*, int*, double*, long, \
+                                       hipStream_t);                                                 \
+  template void launch_ilu_bwd_grid<T>(int, int, int, const T*, T*, const T*, int, const int32_t*, T*, \
+                                       double*, int*, double*, long, hipStream_t);
+CPTR_PREC_LAUNCHERS(double)
+CPTR_PREC_LAUNCHERS(float)
+#undef CPTR_PREC_LAUNCHERS
 
 }  // namespace cptr

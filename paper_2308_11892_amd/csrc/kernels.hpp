@@ -14,52 +14,69 @@ constexpr int kRedBlocks = 1024;  // workgroups of the deterministic reductions
 // k-columns [sptr[s], sptr[s+1]); k-column k holds, for each of the 64 lanes,
 // one block: col[k*64 + lane] and the block's `nv` values stored as planes
 // val[(k*nv + e)*64 + lane], so lane-consecutive loads of one entry are
-// contiguous.  Padding slots repeat a valid column with zero values.
-struct Sell {
+// contiguous.  Padding slots repeat a valid column with zero values.  Values
+// are FP64, or FP32 for the preconditioner's operators in mixed precision.
+template <class T>
+struct SellT {
   int32_t nrows = 0;      // block rows (or positions) covered
   int32_t nslices = 0;
   int32_t nv = 0;         // values per block (9 for 3x3, 4 for 2x2)
   int32_t* sptr = nullptr;
   int32_t* col = nullptr;
-  double* val = nullptr;
+  T* val = nullptr;
   int64_t nslots = 0;     // total k-columns
 };
+using Sell = SellT<double>;
 
 // Scalar CSR on the device.
-struct DCsr {
+template <class T>
+struct DCsrT {
   int32_t n = 0, m = 0;
   int64_t nnz = 0;
   int32_t* rp = nullptr;
   int32_t* ci = nullptr;
-  double* v = nullptr;
+  T* v = nullptr;
   int group = 1;          // lanes cooperating on one row
 };
+using DCsr = DCsrT<double>;
 
 // ---- launchers (all asynchronous on `st`) ----
 void launch_bsr3_spmv(const Sell& A, const double* x, const double* b, double* y, bool resid,
                       hipStream_t st);
+// The preconditioner's launchers take its value type T: double, or float in
+// the mixed-precision mode (A, the restriction weights and the coarsest LU stay
+// FP64 in both).
+template <class T>
 void launch_l0_restrict(int32_t nc, int ne, const double* r, const double* W, const int32_t* eidx,
-                        const int32_t* hidx, double* b0, hipStream_t st);
-void launch_l0_resid_jacobi(const Sell& Ah, int ne, const double* b0, const double* dinv, double* r0,
+                        const int32_t* hidx, T* b0, hipStream_t st);
+template <class T>
+void launch_l0_resid_jacobi(const SellT<T>& Ah, int ne, const T* b0, const T* dinv, T* r0,
                             hipStream_t st);
-void launch_l0_post(const Sell& Ah, int ne, const double* x0, const double* b0, const double* dinv,
-                    double* e0, hipStream_t st);
-void launch_csr_resid_jacobi(const DCsr& A, const double* b, const double* dinv, double* r,
-                             hipStream_t st);
-void launch_csr_spmv(const DCsr& A, const double* x, double* y, hipStream_t st);
-void launch_csr_prolong(const DCsr& P, const double* xc, const double* b, const double* dinv,
-                        double* x, hipStream_t st);
-void launch_csr_post(const DCsr& A, const double* x, const double* b, const double* dinv, double* e,
-                     hipStream_t st);
-void launch_coarse_solve(int n, const double* lu, const int32_t* piv, const double* b, double* x,
+template <class T>
+void launch_l0_post(const SellT<T>& Ah, int ne, const T* x0, const T* b0, const T* dinv, T* e0,
+                    hipStream_t st);
+template <class T>
+void launch_csr_resid_jacobi(const DCsrT<T>& A, const T* b, const T* dinv, T* r, hipStream_t st);
+template <class T>
+void launch_csr_spmv(const DCsrT<T>& A, const T* x, T* y, hipStream_t st);
+template <class T>
+void launch_csr_prolong(const DCsrT<T>& P, const T* xc, const T* b, const T* dinv, T* x,
+                        hipStream_t st);
+template <class T>
+void launch_csr_post(const DCsrT<T>& A, const T* x, const T* b, const T* dinv, T* e, hipStream_t st);
+template <class T>
+void launch_coarse_solve(int n, const double* lu, const int32_t* piv, const T* b, T* x,
                          hipStream_t st);
-void launch_stage2_resid(const Sell& A, int ne, const int32_t* eidx, const double* e0,
-                         const double* r, double* r2, hipStream_t st);
-void launch_ilu_fwd_level(const Sell& L, const int32_t* perm, int32_t p0, int32_t p1,
-                          const double* r2, double* y, hipStream_t st);
-void launch_ilu_bwd_level(const Sell& U, const int32_t* perm, const double* uinv, int32_t p0,
-                          int32_t p1, const double* y, const double* e0, int ne,
-                          const int32_t* eidx, double* x2, double* z, hipStream_t st);
+template <class T>
+void launch_stage2_resid(const Sell& A, int ne, const int32_t* eidx, const T* e0, const double* r,
+                         T* r2, hipStream_t st);
+template <class T>
+void launch_ilu_fwd_level(const SellT<T>& L, const int32_t* perm, int32_t p0, int32_t p1, const T* r2,
+                          T* y, hipStream_t st);
+template <class T>
+void launch_ilu_bwd_level(const SellT<T>& U, const int32_t* perm, const T* uinv, int32_t p0,
+                          int32_t p1, const T* y, const T* e0, int ne, const int32_t* eidx, T* x2,
+                          double* z, hipStream_t st);
 
 // one-launch ILU sweeps (see kernels.hip); width = register slots per row
 int ilu_sf_width(int max_width);  // 0 when the rows are too wide for the one-launch kernels
@@ -86,21 +103,27 @@ inline void grid_tile_slot(int nx, int ny, int i, int j, int k, int64_t& fwd_row
   bwd_row = t * ns + ((nx - 1 - i) + (kGridTJ - 1 - jj) + (kGridTK - 1 - kk));
 }
 // r2t: stage-two residual in the forward tile layout (3 per slot); e0t: the
-// V-cycle result in the backward tile layout (ne per slot), or null (x1 = 0)
-void launch_stage2_grid(int nx, int ny, int nz, const Sell& A, int ne, const int32_t* eidx,
-                        const double* e0, const double* r, double* r2t, double* e0t, double* y,
-                        double* x2, int* tickets, hipStream_t st);
-void launch_ilu_fwd_grid(int nx, int ny, int nz, const double* Lt, const double* r2t, double* ytile,
-                         double* y, int* tickets, double* err, long spin_limit, hipStream_t st);
-void launch_ilu_bwd_grid(int nx, int ny, int nz, const double* Ut, double* ytile, const double* e0t,
-                         int ne, const int32_t* eidx, double* x2, double* z, int* tickets,
-                         double* err, long spin_limit, hipStream_t st);
+// V-cycle result in the backward tile layout (ne per slot), or null (x1 = 0).
+// faces: the face buffers of the two sweeps, grid_face_values() each
+// (forward first); the stage-two kernel fills both with the sentinel.
+int64_t grid_face_values(int nx, int ny, int nz);
+template <class T>
+void launch_stage2_grid(int nx, int ny, int nz, const Sell& A, int ne, const int32_t* eidx, const T* e0,
+                        const double* r, T* r2t, T* e0t, T* faces, int* tickets, hipStream_t st);
+template <class T>
+void launch_ilu_fwd_grid(int nx, int ny, int nz, const T* Lt, const T* r2t, T* ytile, T* faces,
+                         int* tickets, double* err, long spin_limit, hipStream_t st);
+template <class T>
+void launch_ilu_bwd_grid(int nx, int ny, int nz, const T* Ut, T* ytile, const T* e0t, int ne,
+                         const int32_t* eidx, T* faces, double* z, int* tickets, double* err,
+                         long spin_limit, hipStream_t st);
 void launch_ilu_fwd_sf(const Sell& L, int width, const int32_t* perm, const double* r2, double* y,
                        double* x2, int* tickets, double* err, long spin_limit, hipStream_t st);
 void launch_ilu_bwd_sf(const Sell& U, int width, const int32_t* perm, const double* uinv,
                        const double* y, const double* e0, int ne, const int32_t* eidx, double* x2,
                        double* z, int* tickets, double* err, long spin_limit, hipStream_t st);
-void launch_prolong_e(int32_t nrows, int ne, const int32_t* eidx, const double* e0, double* x1,
+template <class T>
+void launch_prolong_e(int32_t nrows, int ne, const int32_t* eidx, const T* e0, double* x1,
                       hipStream_t st);
 void launch_sweep_prepare(int64_t n, double* y, double* x2, int* tickets, hipStream_t st);
 

@@ -170,3 +170,18 @@ def test_coarsening_limit_reports_stall():
     s = L.Solver(c.row_ptr, c.col_idx, c.values, host_only=1, max_levels=1)
     rows, _ = s.hierarchy()
     assert len(rows) == 1 and rows[0] == 2 * c.n_cells
+
+
+def test_fp32_preconditioner_options():
+    """Mixed precision is a setup option; the one-launch sweeps are FP64 only,
+    and an unknown precision is rejected before any work."""
+    c = J.by_name("grid7x5x3")
+    with pytest.raises(L.CptrError):
+        L.Solver(c.row_ptr, c.col_idx, c.values, host_only=1, ilu_sweep=L.ILU_SWEEP_ONE_LAUNCH,
+                 precond_precision=L.PRECISION_FP32)
+    with pytest.raises(L.CptrError):
+        L.Solver(c.row_ptr, c.col_idx, c.values, host_only=1, precond_precision=7)
+    # the host hierarchy does not depend on the precision
+    a = host_solver(c, precond_precision=L.PRECISION_FP32)
+    b = host_solver(c)
+    assert np.array_equal(a.hierarchy()[0], b.hierarchy()[0])
