@@ -167,7 +167,9 @@ def peclet(fluxes, faces, kappa):
     vals = []
     for F, (d, a, b, area, dist) in zip(fluxes, faces):
         nz_ = F != 0
-        vals.append(np.abs(F[nz_]) * CF * dist / (kappa * area))
+        area_ = np.broadcast_to(area, F.shape)[nz_]
+        dist_ = np.broadcast_to(dist, F.shape)[nz_]
+        vals.append(np.abs(F[nz_]) * CF * dist_ / (kappa * area_))
     v = np.concatenate(vals) if vals else np.zeros(0)
     return float(np.median(v)) if v.size else 0.0
 
@@ -191,6 +193,43 @@ def _boundary_outflow(nx, ny, nz, wells):
         cells.append(cell_ids.ravel())
         flux.append(np.maximum(F, 0.0).ravel())
     return np.concatenate(cells), np.concatenate(flux)
+
+
+def _face_blocks(F, a_up, up, tf, kf, z, T):
+    """Derivatives of the a->b face terms (rows: mass, energy, CO2) with respect
+    to the unknowns of cell a (Da) and of cell b (Db).  F is the volumetric flux
+    a->b, a_up marks faces upwinded from a, up the upwind cell, tf the
+    transmissibility and kf the conductive transmissibility."""
+    lam, lT, lz = _mobility(z[up], T[up])
+    Tu, zu = T[up], z[up]
+    # Darcy: F = tf lam (p_a - p_b); the derivatives follow from that law
+    dF_dpa = tf * lam
+    dF_dpb = -tf * lam
+    dF_dTu = F * lT / lam
+    dF_dzu = F * lz / lam
+    m = F.shape[0]
+    Da = np.zeros((m, 3, 3))   # d(flux a->b)/d(vars of a); rows mass, energy, CO2
+    Db = np.zeros((m, 3, 3))
+    ua = a_up.astype(np.float64)
+    ub = 1.0 - ua
+    for (D, dpv, u) in ((Da, dF_dpa, ua), (Db, dF_dpb, ub)):
+        dFdT = dF_dTu * u
+        dFdz = dF_dzu * u
+        # mass
+        D[:, 0, 0] = dpv
+        D[:, 0, 1] = dFdT
+        D[:, 0, 2] = dFdz
+        # energy: F Cf Tu + kf (Ta - Tb)
+        D[:, 1, 0] = CF * Tu * dpv
+        D[:, 1, 1] = CF * Tu * dFdT + F * CF * u
+        D[:, 1, 2] = CF * Tu * dFdz
+        # CO2: F zu
+        D[:, 2, 0] = zu * dpv
+        D[:, 2, 1] = zu * dFdT
+        D[:, 2, 2] = zu * dFdz + F * u
+    Da[:, 1, 1] += kf
+    Db[:, 1, 1] -= kf
+    return Da, Db
 
 
 def cartesian(name, nx, ny, nz, *, seed, sigma, corr, n_wells, r_front,
@@ -226,35 +265,7 @@ def cartesian(name, nx, ny, nz, *, seed, sigma, corr, n_wells, r_front,
         kf = kappa * area / dist
         a_up = (F > 0) | ((F == 0) & (a < b))
         up = np.where(a_up, a, b)
-        lam, lT, lz = _mobility(z[up], T[up])
-        Tu, zu = T[up], z[up]
-        # Darcy: F = tf lam (p_a - p_b); the derivatives follow from that law
-        dF_dpa = tf * lam
-        dF_dpb = -tf * lam
-        dF_dTu = F * lT / lam
-        dF_dzu = F * lz / lam
-        m = a.shape[0]
-        Da = np.zeros((m, 3, 3))   # d(flux a->b)/d(vars of a); rows mass, energy, CO2
-        Db = np.zeros((m, 3, 3))
-        ua = a_up.astype(np.float64)
-        ub = 1.0 - ua
-        for (D, dpv, u) in ((Da, dF_dpa, ua), (Db, dF_dpb, ub)):
-            dFdT = dF_dTu * u
-            dFdz = dF_dzu * u
-            # mass
-            D[:, 0, 0] = dpv
-            D[:, 0, 1] = dFdT
-            D[:, 0, 2] = dFdz
-            # energy: F Cf Tu + kf (Ta - Tb)
-            D[:, 1, 0] = CF * Tu * dpv
-            D[:, 1, 1] = CF * Tu * dFdT + F * CF * u
-            D[:, 1, 2] = CF * Tu * dFdz
-            # CO2: F zu
-            D[:, 2, 0] = zu * dpv
-            D[:, 2, 1] = zu * dFdT
-            D[:, 2, 2] = zu * dFdz + F * u
-        Da[:, 1, 1] += kf
-        Db[:, 1, 1] -= kf
+        Da, Db = _face_blocks(F, a_up, up, tf, kf, z, T)
         s_ab = SLOT[(d, 1)]    # in row a, neighbour b is on the + side
         s_ba = SLOT[(d, -1)]
         # within one direction every cell is a left (right) end at most once
@@ -311,6 +322,212 @@ def cartesian(name, nx, ny, nz, *, seed, sigma, corr, n_wells, r_front,
                 b, xs, tol, meta)
 
 
+def _delaunay_geometry(pts):
+    """Planar Delaunay triangulation of `pts` (cell units) and its Voronoi dual.
+
+    Returns the unique edges (i < j), the Voronoi edge length of each
+    (circumcentre to circumcentre; circumcentre to the edge midpoint on the
+    hull), the dual (barycentric) area of each point, and for every hull edge
+    its outward unit normal, its length, and the triangle count."""
+    from scipy.spatial import Delaunay
+    tri = Delaunay(pts).simplices.astype(np.int64)
+    ntri = tri.shape[0]
+    A, B, C = pts[tri[:, 0]], pts[tri[:, 1]], pts[tri[:, 2]]
+    # circumcentres
+    d = 2.0 * (A[:, 0] * (B[:, 1] - C[:, 1]) + B[:, 0] * (C[:, 1] - A[:, 1]) + C[:, 0] * (A[:, 1] - B[:, 1]))
+    a2, b2, c2 = (A ** 2).sum(1), (B ** 2).sum(1), (C ** 2).sum(1)
+    cc = np.stack([(a2 * (B[:, 1] - C[:, 1]) + b2 * (C[:, 1] - A[:, 1]) + c2 * (A[:, 1] - B[:, 1])) / d,
+                   (a2 * (C[:, 0] - B[:, 0]) + b2 * (A[:, 0] - C[:, 0]) + c2 * (B[:, 0] - A[:, 0])) / d], axis=1)
+    tri_area = 0.5 * np.abs(d) / 2.0
+    dual = np.zeros(pts.shape[0])
+    for k in range(3):
+        np.add.at(dual, tri[:, k], tri_area / 3.0)
+    # edges with the triangles on either side and the vertex opposite
+    e = np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]])
+    opp = np.concatenate([tri[:, 2], tri[:, 0], tri[:, 1]])
+    tid = np.tile(np.arange(ntri), 3)
+    e.sort(axis=1)
+    key = e[:, 0] * pts.shape[0] + e[:, 1]
+    order = np.argsort(key, kind="stable")
+    key, e, opp, tid = key[order], e[order], opp[order], tid[order]
+    first = np.ones(key.shape[0], dtype=bool)
+    first[1:] = key[1:] != key[:-1]
+    start = np.flatnonzero(first)
+    count = np.diff(np.append(start, key.shape[0]))
+    edges = e[start]
+    t0 = tid[start]
+    mid = 0.5 * (pts[edges[:, 0]] + pts[edges[:, 1]])
+    ell = np.empty(edges.shape[0])
+    two = count == 2
+    ell[two] = np.linalg.norm(cc[t0[two]] - cc[tid[start[two] + 1]], axis=1)
+    hull = ~two
+    ell[hull] = np.linalg.norm(cc[t0[hull]] - mid[hull], axis=1)
+    ell = np.maximum(ell, 1e-3)
+    # outward normals of hull edges: away from the opposite vertex
+    he = edges[hull]
+    t = pts[he[:, 1]] - pts[he[:, 0]]
+    nrm = np.stack([t[:, 1], -t[:, 0]], axis=1)
+    nrm /= np.linalg.norm(nrm, axis=1)[:, None]
+    away = mid[hull] - pts[opp[start[hull]]]
+    nrm *= np.where((nrm * away).sum(1) < 0, -1.0, 1.0)[:, None]
+    hull_len = np.linalg.norm(t, axis=1)
+    return edges, ell, dual, he, nrm, hull_len, ntri
+
+
+def prism(name, n_points, n_layers, *, seed, sigma, corr, n_wells, r_front,
+          kappa=KAPPA0, pe_target=None, tol=1e-6, rhs=True, rcm=True):
+    """Assemble the thermal TPFA Jacobian on an unstructured prism mesh.
+
+    `n_points` seeded uniform points in a square of side sqrt(n_points) cells
+    (one cell = DX metres, so the mean point spacing is about DX) are
+    Delaunay-triangulated; each point's Voronoi column, cut into `n_layers`
+    layers of thickness DZ, is a cell.  Lateral neighbours are the Delaunay
+    edges with TPFA transmissibility DZ * l_ij * k_harm / d_ij (l_ij the
+    Voronoi edge length, d_ij the point distance); vertical neighbours share
+    the column's dual area.  The physics, state, permeability statistics and
+    scaling follow `cartesian`.  With `rcm` the cells are renumbered by
+    reverse Cuthill-McKee on the cell graph, and that numbering is the matrix
+    order (and so the ILU(0) order)."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import reverse_cuthill_mckee
+    rng = np.random.default_rng(seed)
+    side = math.sqrt(n_points)
+    pts = rng.uniform(0.0, side, size=(n_points, 2))
+    edges, ell, dual, hedges, hnrm, hlen, ntri = _delaunay_geometry(pts)
+    npnt, nl = n_points, n_layers
+    nc = npnt * nl
+    # permeability: the cartesian correlated field on a covering grid, sampled per cell
+    G = max(1, int(math.ceil(side)))
+    g = _gauss_field(rng, (nl, G, G), corr)
+    gx = np.minimum((pts[:, 0]).astype(np.int64), G - 1)
+    gy = np.minimum((pts[:, 1]).astype(np.int64), G - 1)
+    perm = (10.0 ** (-13.0 + sigma * g[:, gy, gx])).ravel()          # layer-major: c = l*npnt + i
+    # state from the point coordinates (cell units)
+    if n_wells == 1:
+        wells = [(0.0, 0.0)]
+    elif n_wells == 4:
+        q1, q3 = side / 4.0, 3.0 * side / 4.0
+        wells = [(q1, q1), (q3, q1), (q1, q3), (q3, q3)]
+    else:
+        raise ValueError("n_wells must be 1 or 4")
+    R = math.hypot(side, side)
+    px, py = pts[:, 0], pts[:, 1]
+    p2 = _radial_p(px, py, wells, R)
+    dmin = np.full(npnt, np.inf)
+    for (iw, jw) in wells:
+        dmin = np.minimum(dmin, np.sqrt((px - iw) ** 2 + (py - jw) ** 2))
+    T2 = T_RES - DT_INJ * 0.5 * (1.0 - np.tanh(dmin - r_front))
+    z2 = 0.5 * (1.0 - np.tanh(dmin - 2.0 * r_front))
+    p, T, z = np.tile(p2, nl), np.tile(T2, nl), np.tile(z2, nl)
+    vol = np.tile(dual * DX * DY * DZ, nl)
+    # faces: (direction, a, b, area, dist) with per-face area and distance
+    lay = (np.arange(nl, dtype=np.int64) * npnt)[:, None]
+    dlen = np.linalg.norm(pts[edges[:, 0]] - pts[edges[:, 1]], axis=1) * DX
+    faces = [(0, (lay + edges[:, 0]).ravel(), (lay + edges[:, 1]).ravel(),
+              np.tile(DZ * ell * DX, nl), np.tile(dlen, nl))]
+    if nl > 1:
+        lv = (np.arange(nl - 1, dtype=np.int64) * npnt)[:, None]
+        ids = np.arange(npnt, dtype=np.int64)[None, :]
+        faces.append((2, (lv + ids).ravel(), (lv + npnt + ids).ravel(),
+                      np.tile(dual * DX * DY, nl - 1), np.full((nl - 1) * npnt, DZ)))
+    fluxes = [(area / dist) * K_REF * LAM_REF * (p[a] - p[b]) for (d, a, b, area, dist) in faces]
+    pe0 = peclet(fluxes, faces, kappa)
+    if pe_target is not None:
+        kappa = kappa * pe0 / pe_target
+    pe = peclet(fluxes, faces, kappa)
+
+    # matrix order
+    fa = np.concatenate([f[1] for f in faces])
+    fb = np.concatenate([f[2] for f in faces])
+    if rcm:
+        graph = csr_matrix((np.ones(2 * fa.shape[0], dtype=np.int8),
+                            (np.concatenate([fa, fb]), np.concatenate([fb, fa]))), shape=(nc, nc))
+        order = reverse_cuthill_mckee(graph, symmetric_mode=True).astype(np.int64)
+        new = np.empty(nc, dtype=np.int64)
+        new[order] = np.arange(nc, dtype=np.int64)
+        del graph
+    else:
+        order = new = np.arange(nc, dtype=np.int64)
+
+    rows, cols, blks = [], [], []
+    diag = np.zeros((nc, 3, 3))
+    diag[:, 0, 0] = vol * PORO * CT / DT
+    diag[:, 1, 1] = vol * (PORO * CF + (1.0 - PORO) * CR) / DT
+    diag[:, 2, 2] = vol * PORO / DT
+    for F, (d, a, b, area, dist) in zip(fluxes, faces):
+        ka, kb = perm[a], perm[b]
+        tf = (area / dist) * 2.0 * ka * kb / (ka + kb)
+        kf = kappa * area / dist
+        a_up = (F > 0) | ((F == 0) & (new[a] < new[b]))
+        up = np.where(a_up, a, b)
+        Da, Db = _face_blocks(F, a_up, up, tf, kf, z, T)
+        np.add.at(diag, a, Da)
+        np.add.at(diag, b, -Db)
+        rows += [a, b]
+        cols += [b, a]
+        blks += [Db, -Da]
+    # open lateral boundary: outflow through the hull faces at the cell's own state
+    mid = 0.5 * (pts[hedges[:, 0]] + pts[hedges[:, 1]])
+    dp = _radial_p(mid[:, 0], mid[:, 1], wells, R) - _radial_p(mid[:, 0] + hnrm[:, 0], mid[:, 1] + hnrm[:, 1], wells, R)
+    geo = DZ * hlen * DX / DX                                   # area / distance (one cell outward)
+    Fh = np.maximum(geo * K_REF * LAM_REF * dp, 0.0)
+    for end in (0, 1):                                          # half of the face to each end point
+        bc = (lay + hedges[:, end]).ravel()
+        bF = np.tile(0.5 * Fh, nl)
+        keep = bF > 0
+        bc, bF = bc[keep], bF[keep]
+        lam, lT, lz = _mobility(z[bc], T[bc])
+        tb = np.tile(0.5 * geo, nl)[keep] * perm[bc]
+        D = np.zeros((bc.shape[0], 3, 3))
+        dFdp, dFdT, dFdz = tb * lam, bF * lT / lam, bF * lz / lam
+        D[:, 0, 0], D[:, 0, 1], D[:, 0, 2] = dFdp, dFdT, dFdz
+        D[:, 1, 0] = CF * T[bc] * dFdp
+        D[:, 1, 1] = CF * T[bc] * dFdT + bF * CF
+        D[:, 1, 2] = CF * T[bc] * dFdz
+        D[:, 2, 0], D[:, 2, 1], D[:, 2, 2] = z[bc] * dFdp, z[bc] * dFdT, z[bc] * dFdz + bF
+        np.add.at(diag, bc, D)
+
+    # scaling: p in MPa; rows by the accumulation diagonal of the mean cell
+    vbar = float(vol.mean())
+    acc = np.array([vbar * PORO * CT / DT * P_SCALE,
+                    vbar * (PORO * CF + (1.0 - PORO) * CR) / DT,
+                    vbar * PORO / DT])
+    ids = np.arange(nc, dtype=np.int64)
+    r_all = new[np.concatenate([ids] + rows)]
+    c_all = new[np.concatenate([ids] + cols)]
+    v_all = np.concatenate([diag] + blks)
+    del diag, blks
+    v_all[:, :, 0] *= P_SCALE
+    v_all /= acc[None, :, None]
+    key = r_all * nc + c_all
+    srt = np.argsort(key, kind="stable")
+    key, v_all = key[srt], v_all[srt]
+    first = np.ones(key.shape[0], dtype=bool)
+    first[1:] = key[1:] != key[:-1]
+    start = np.flatnonzero(first)
+    values = np.ascontiguousarray(np.add.reduceat(v_all, start, axis=0))
+    ukey = key[start]
+    col_idx = (ukey % nc).astype(np.int32)
+    counts = np.bincount(ukey // nc, minlength=nc)
+    row_ptr = np.zeros(nc + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    deg = np.bincount(np.concatenate([edges[:, 0], edges[:, 1]]), minlength=npnt)
+    meta = dict(name=name, mesh="voronoi-prism", n_points=npnt, n_layers=nl, seed=seed,
+                sigma=sigma, corr=corr, n_wells=n_wells, r_front=r_front, kappa=kappa,
+                peclet=pe, peclet_at_kappa0=pe0, pe_target=pe_target, tol=tol, rcm=bool(rcm),
+                dz=DZ, spacing=DX, porosity=PORO, ct=CT, mu_c=MU_C, cf=CF, cr=CR, dt=DT,
+                row_scale=acc.tolist(), p_scale=P_SCALE, n_cells=nc, nnzb=int(col_idx.shape[0]),
+                lateral_degree=[int(deg.min()), float(deg.mean()), int(deg.max())],
+                n_triangles=int(ntri))
+    if rhs:
+        xs = np.random.default_rng(seed + 1000).standard_normal(BLOCK * nc)
+        b = bsr_matvec_plain(row_ptr, col_idx, values, xs)
+    else:
+        xs = np.zeros(BLOCK * nc)
+        b = np.zeros(BLOCK * nc)
+    return Case(name, npnt, 1, nl, row_ptr.astype(np.int32), col_idx, values, b, xs, tol, meta)
+
+
 def bsr_matvec_plain(row_ptr, col_idx, values, x):
     """b = A x used only to manufacture right-hand sides (b = A x*)."""
     nc = row_ptr.shape[0] - 1
@@ -348,6 +565,19 @@ def config3_slab(nz):
                      corr=10, n_wells=4, r_front=5.0, tol=1e-6)
 
 
+def config2():
+    """Unstructured mesh: 50k points x 20 layers of Voronoi prisms (1M cells,
+    3M DOF), log-k std 1.0, correlation 10 cells, four injectors, RCM order."""
+    return prism("prism50000x20", 50000, 20, seed=SEED_BASE + 2, sigma=1.0, corr=10,
+                 n_wells=4, r_front=5.0, tol=1e-6)
+
+
+def prism_small(n_points, n_layers, seed=17, rcm=True, **kw):
+    """Small prism meshes for pins and parity at oracle-friendly sizes."""
+    return prism(f"prism{n_points}x{n_layers}", n_points, n_layers, seed=seed, sigma=1.0,
+                 corr=2, n_wells=4, r_front=2.0, rcm=rcm, **kw)
+
+
 def small(nx, ny, nz, seed=7, sigma=0.5, n_wells=1, r_front=2.0, **kw):
     """Tiny grids for pins and parity at oracle-friendly sizes."""
     return cartesian(f"grid{nx}x{ny}x{nz}", nx, ny, nz, seed=seed, sigma=sigma, corr=0,
@@ -359,6 +589,11 @@ def by_name(name: str) -> Case:
              "grid250x250x50": config3}
     if name in table:
         return table[name]()
+    if name == "prism50000x20":
+        return config2()
+    if name.startswith("prism"):
+        npnt, nl = (int(v) for v in name[5:].split("x"))
+        return prism_small(npnt, nl)
     if name.startswith("grid250x250x") and name != "grid250x250x50":
         return config3_slab(int(name.split("x")[-1]))
     if name.startswith("grid100x100x20_pe"):

@@ -31,7 +31,9 @@ def host(t):
     return t.cpu().numpy()
 
 
-CASES = ["grid20x20x5", "grid7x5x3", "grid1x1x1", "grid2x1x1", "grid13x1x1", "grid33x17x2"]
+# Voronoi-prism meshes in RCM order (the unstructured workload at small sizes)
+PRISMS = ["prism300x4", "prism2000x5"]
+CASES = ["grid20x20x5", "grid7x5x3", "grid1x1x1", "grid2x1x1", "grid13x1x1", "grid33x17x2"] + PRISMS
 
 
 @pytest.fixture(scope="module")
@@ -76,7 +78,7 @@ def _apply_vectors(c, ref):
     return vecs
 
 
-@pytest.mark.parametrize("name", GRIDS_3D)
+@pytest.mark.parametrize("name", GRIDS_3D + PRISMS)
 def test_apply_parity(solvers, name):
     c, s, ref = solvers(name)
     say(f"[apply] {name}")
@@ -120,6 +122,8 @@ def test_apply_is_deterministic(solvers):
     ("grid20x20x5", 50, True, 1e-8),
     ("grid33x17x2", 30, False, 1e-8),
     ("grid13x1x1", 30, False, 1e-10),
+    ("prism2000x5", 30, False, 1e-8),
+    ("prism2000x5", 50, True, 1e-6),
 ])
 def test_gmres_parity(solvers, name, restart, flexible, tol):
     c, s, ref = solvers(name)
@@ -199,7 +203,7 @@ def test_gmres_parity_grid100x100x20(pe):
 
 
 @pytest.mark.parametrize("name", ["grid20x20x5", "grid33x17x2", "grid7x5x3", "grid2x2x2",
-                                  "grid1x1x1", "grid13x1x1"])
+                                  "grid1x1x1", "grid13x1x1"] + PRISMS)
 def test_ilu_sweep_modes_agree(name):
     """Per-level launches, one-launch sweeps and (on 3D grids) the tiled grid
     sweeps compute the same preconditioner; all match the oracle."""
@@ -247,3 +251,27 @@ def test_one_launch_sweep_gmres_grid100x100x20():
     ref = O.Cptr(c.row_ptr, c.col_idx, c.values)
     _, oinfo = ref.gmres(c.b, restart=50, flexible=True, rtol=1e-6)
     assert info["converged"] and abs(info["iterations"] - oinfo["iterations"]) <= 1
+
+
+def test_gmres_parity_prism10000x10():
+    """A 100k-cell Voronoi-prism mesh in RCM order: one application within
+    1e-10 and FGMRES(50) to 1e-6 within +-1 iteration of the oracle, through
+    the automatic sweep schedule (no grid structure)."""
+    c = J.by_name("prism10000x10")
+    say(f"[gmres] {c.name} FGMRES(50) tol 1e-6")
+    ref = O.Cptr(c.row_ptr, c.col_idx, c.values)
+    with L.Solver(c.row_ptr, c.col_idx, c.values) as s:
+        assert s.export("SWEEP", 0, 4, np.int32)[0] in (L.ILU_SWEEP_ONE_LAUNCH, L.ILU_SWEEP_LEVELS)
+        r = np.random.default_rng(6).standard_normal(c.n_dof)
+        z = torch.empty(c.n_dof, dtype=torch.float64, device=DEV)
+        s.apply(dev(r), z)
+        zo = ref.apply(r)
+        assert np.linalg.norm(host(z) - zo) <= 1e-10 * np.linalg.norm(zo)
+        b = dev(c.b)
+        x = torch.zeros_like(b)
+        info = s.gmres_solve(b, x, restart=50, flexible=True, rtol=1e-6)
+    _, oinfo = ref.gmres(c.b, restart=50, flexible=True, rtol=1e-6)
+    say(f"  gpu {info['iterations']} it, oracle {oinfo['iterations']} it")
+    assert info["converged"] and abs(info["iterations"] - oinfo["iterations"]) <= 1
+    res = np.linalg.norm(c.b - O.bsr_spmv(c.row_ptr, c.col_idx, c.values, host(x))) / np.linalg.norm(c.b)
+    assert res <= 1e-6

@@ -38,7 +38,8 @@ def test_defaults_follow_the_paper():
 
 @pytest.mark.parametrize("case,agg", [("grid20x20x5", 1), ("grid6x5x4", 1), ("grid12x1x1", 1),
                                       ("grid100x100x20_pe0.1", 1), ("grid20x20x5", 0),
-                                      ("grid100x100x20_pe0.1", 0)])
+                                      ("grid100x100x20_pe0.1", 0), ("prism300x4", 1),
+                                      ("prism2000x5", 1), ("prism2000x5", 0)])
 def test_host_setup_matches_oracle(case, agg):
     c = J.by_name(case)
     h = O.Cptr(c.row_ptr, c.col_idx, c.values, agg_levels=agg)
