@@ -92,8 +92,7 @@ typedef struct {
 
 enum {
   CPTR_PRECISION_FP64 = 0,
-  CPTR_PRECISION_FP32 = 1       /* mixed precision: FP32 preconditioner inside FP64 (F)GMRES;
-                                   not with CPTR_ILU_SWEEP_ONE_LAUNCH (CPTR_E_INVALID) */
+  CPTR_PRECISION_FP32 = 1       /* mixed precision: FP32 preconditioner inside FP64 (F)GMRES */
 };
 
 enum {

@@ -373,8 +373,7 @@ int build_prec(cptr_solver s, PrecDev<T>& d, const std::vector<int32_t>& fp,
       if (s->ilu_mode == CPTR_ILU_SWEEP_ONE_LAUNCH && w == 0)
         return fail(s, CPTR_E_INVALID,
                     "rows too wide (" + std::to_string(maxw) + " blocks) for one-launch ILU sweeps");
-      // the one-launch sweeps run in FP64 only
-      s->sf_width = std::is_same<T, double>::value ? w : 0;
+      s->sf_width = w;
     }
     if (s->use_grid && (rc = build_grid_factors(s, d, st))) return rc;
     const int64_t npad = (int64_t)Uh.nslices * kLanes;
@@ -561,26 +560,28 @@ void enqueue_stage2(cptr_solver s, PrecDev<T>& d, const double* r, const T* e0, 
     return;
   }
   const T* rhs = d.r2;
-  if constexpr (std::is_same<T, double>::value) {
-    if (s->sf_width > 0) {  // one-launch sweeps (FP64 only)
-      ph_begin(s, st, ev);
-      if (e0) {
-        launch_stage2_resid_sf(s->A, ne, s->eidx_h, e0, r, d.r2, d.y, d.x2, s->tickets, st);
-      } else {
-        launch_sweep_prepare(s->N, d.y, d.x2, s->tickets, st);
-        rhs = r;
-      }
-      ph_end(s, st, PH_STAGE2, ev);
-      ph_begin(s, st, ev);
-      launch_ilu_fwd_sf(d.Lf, s->sf_width, s->fperm, rhs, d.y, d.x2, s->tickets, s->hdev + 140,
-                        kSweepSpinLimit, st);
-      ph_end(s, st, PH_ILU_F, ev);
-      ph_begin(s, st, ev);
-      launch_ilu_bwd_sf(d.Ub, s->sf_width, s->bperm, d.uinv, d.y, e0, ne, s->eidx_h, d.x2, z,
-                        s->tickets, s->hdev + 140, kSweepSpinLimit, st);
-      ph_end(s, st, PH_ILU_B, ev);
-      return;
+  constexpr bool f64 = std::is_same<T, double>::value;
+  if (s->sf_width > 0) {  // one-launch sweeps
+    ph_begin(s, st, ev);
+    if (e0 || !f64) {
+      // the stage-two residual (or, without e0, r converted to T)
+      launch_stage2_resid_sf(s->A, ne, s->eidx_h, e0, r, d.r2, d.y, d.x2, s->tickets, st);
+    } else if constexpr (f64) {
+      launch_sweep_prepare(s->N, d.y, d.x2, s->tickets, st);
+      rhs = r;
     }
+    ph_end(s, st, PH_STAGE2, ev);
+    ph_begin(s, st, ev);
+    launch_ilu_fwd_sf(d.Lf, s->sf_width, s->fperm, rhs, d.y, s->tickets, s->hdev + 140,
+                      kSweepSpinLimit, st);
+    ph_end(s, st, PH_ILU_F, ev);
+    ph_begin(s, st, ev);
+    launch_ilu_bwd_sf(d.Ub, s->sf_width, s->bperm, d.uinv, d.y, e0, ne, s->eidx_h, d.x2, z,
+                      s->tickets, s->hdev + 140, kSweepSpinLimit, st);
+    ph_end(s, st, PH_ILU_B, ev);
+    return;
+  }
+  if constexpr (f64) {
     if (!e0) rhs = r;
   }
   // per-level launches; the stage-two residual also converts r to T
@@ -716,8 +717,6 @@ cptr_status cptr_setup(const cptr_bsr* A, int32_t block_size, const int32_t* ell
     return (cptr_status)fail(nullptr, CPTR_E_INVALID, "ilu_sweep must be 0, 1, 2 or 3");
   if (o.precond_precision != CPTR_PRECISION_FP64 && o.precond_precision != CPTR_PRECISION_FP32)
     return (cptr_status)fail(nullptr, CPTR_E_INVALID, "precond_precision must be FP64 or FP32");
-  if (o.precond_precision == CPTR_PRECISION_FP32 && o.ilu_sweep == CPTR_ILU_SWEEP_ONE_LAUNCH)
-    return (cptr_status)fail(nullptr, CPTR_E_INVALID, "one-launch ILU sweeps run in FP64 only");
   if (o.max_levels < 1 || o.max_levels > 64 || o.max_coarse < 1 || o.p_max_elmts < 0 ||
       o.agg_levels < 0 ||
       !(o.strong_threshold >= 0.0) || !(o.max_row_sum > 0.0))

@@ -403,23 +403,22 @@ __device__ __forceinline__ int take_ticket(int* ctr) {
   return s_ticket;
 }
 
-// Forward sweep y = L^-1 r2 (unit block-lower L).
-template <int W>
+// Forward sweep y = L^-1 r2 (unit block-lower L), in the factors' type T.
+template <int W, class T>
 __global__ __launch_bounds__(kBlock) void k_ilu_fwd_sf(int npos, const int32_t* __restrict__ sptr,
                                                        const int32_t* __restrict__ col,
-                                                       const double* __restrict__ val,
+                                                       const T* __restrict__ val,
                                                        const int32_t* __restrict__ perm,
-                                                       const double* __restrict__ r2, double* y,
-                                                       double* x2, int* tickets, double* err,
-                                                       long spin_limit) {
+                                                       const T* __restrict__ r2, T* y,
+                                                       int* tickets, double* err, long spin_limit) {
   const int blk = take_ticket(tickets);
   const int p = blk * kBlock + threadIdx.x;
   const bool active = p < npos;
   int i = 0;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  T a0 = T(0), a1 = T(0), a2 = T(0);
   int c[W];
-  double Lv[W][9];
-  double yv[W][3];
+  T Lv[W][9];
+  T yv[W][3];
   unsigned need = 0;
   if (active) {
     i = perm[p];
@@ -433,22 +432,21 @@ __global__ __launch_bounds__(kBlock) void k_ilu_fwd_sf(int npos, const int32_t* 
       c[k] = -1;
       if (k < w) {
         c[k] = col[(size_t)(k0 + k) * 64 + lane];
-        const double* v = val + (size_t)(k0 + k) * 9 * 64 + lane;
+        const T* v = val + (size_t)(k0 + k) * 9 * 64 + lane;
 #pragma unroll
         for (int e = 0; e < 9; ++e) Lv[k][e] = v[e * 64];
       }
       if (c[k] >= 0) need |= 1u << k;
     }
   }
-  (void)x2;
   bool done = !active;
   for (long spin = 0;; ++spin) {
     if (!done) {
 #pragma unroll
       for (int k = 0; k < W; ++k) {
         if (need & (1u << k)) {
-          const double* q = y + 3 * (size_t)c[k];
-          const double u0 = ld_dev(q), u1 = ld_dev(q + 1), u2 = ld_dev(q + 2);
+          const T* q = y + 3 * (size_t)c[k];
+          const T u0 = ld_dev(q), u1 = ld_dev(q + 1), u2 = ld_dev(q + 2);
           if (!is_sent(u0) && !is_sent(u1) && !is_sent(u2)) {
             yv[k][0] = u0;
             yv[k][1] = u1;
@@ -480,25 +478,26 @@ __global__ __launch_bounds__(kBlock) void k_ilu_fwd_sf(int npos, const int32_t* 
   }
 }
 
-// Backward sweep x2 = U^-1 y with U_ii^-1 stored per position, and z = x1 + x2.
-template <int W, int NE>
+// Backward sweep x2 = U^-1 y with U_ii^-1 stored per position, and z = x1 + x2
+// (the sweep in T, z in FP64).
+template <int W, int NE, class T>
 __global__ __launch_bounds__(kBlock) void k_ilu_bwd_sf(int npos, int npad, const int32_t* __restrict__ sptr,
                                                        const int32_t* __restrict__ col,
-                                                       const double* __restrict__ val,
+                                                       const T* __restrict__ val,
                                                        const int32_t* __restrict__ perm,
-                                                       const double* __restrict__ uinv,
-                                                       const double* y, const double* __restrict__ e0,
-                                                       int ea, int eb, double* x2,
+                                                       const T* __restrict__ uinv,
+                                                       const T* y, const T* __restrict__ e0,
+                                                       int ea, int eb, T* x2,
                                                        double* __restrict__ z, int* tickets,
                                                        double* err, long spin_limit) {
   const int blk = take_ticket(tickets + 1);
   const int p = blk * kBlock + threadIdx.x;
   const bool active = p < npos;
   int i = 0;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  T a0 = T(0), a1 = T(0), a2 = T(0);
   int c[W];
-  double Uv[W][9];
-  double xv[W][3];
+  T Uv[W][9];
+  T xv[W][3];
   unsigned need = 0;
   if (active) {
     i = perm[p];
@@ -512,7 +511,7 @@ __global__ __launch_bounds__(kBlock) void k_ilu_bwd_sf(int npos, int npad, const
       c[k] = -1;
       if (k < w) {
         c[k] = col[(size_t)(k0 + k) * 64 + lane];
-        const double* v = val + (size_t)(k0 + k) * 9 * 64 + lane;
+        const T* v = val + (size_t)(k0 + k) * 9 * 64 + lane;
 #pragma unroll
         for (int e = 0; e < 9; ++e) Uv[k][e] = v[e * 64];
       }
@@ -525,8 +524,8 @@ __global__ __launch_bounds__(kBlock) void k_ilu_bwd_sf(int npos, int npad, const
 #pragma unroll
       for (int k = 0; k < W; ++k) {
         if (need & (1u << k)) {
-          const double* q = x2 + 3 * (size_t)c[k];
-          const double u0 = ld_dev(q), u1 = ld_dev(q + 1), u2 = ld_dev(q + 2);
+          const T* q = x2 + 3 * (size_t)c[k];
+          const T u0 = ld_dev(q), u1 = ld_dev(q + 1), u2 = ld_dev(q + 2);
           if (!is_sent(u0) && !is_sent(u1) && !is_sent(u2)) {
             xv[k][0] = u0;
             xv[k][1] = u1;
@@ -543,18 +542,18 @@ __global__ __launch_bounds__(kBlock) void k_ilu_bwd_sf(int npos, int npad, const
           a1 -= Uv[k][3] * xv[k][0] + Uv[k][4] * xv[k][1] + Uv[k][5] * xv[k][2];
           a2 -= Uv[k][6] * xv[k][0] + Uv[k][7] * xv[k][1] + Uv[k][8] * xv[k][2];
         }
-        const double* u = uinv + p;
-        const double o0 = u[0] * a0 + u[(size_t)npad] * a1 + u[2 * (size_t)npad] * a2;
-        const double o1 = u[3 * (size_t)npad] * a0 + u[4 * (size_t)npad] * a1 + u[5 * (size_t)npad] * a2;
-        const double o2 = u[6 * (size_t)npad] * a0 + u[7 * (size_t)npad] * a1 + u[8 * (size_t)npad] * a2;
+        const T* u = uinv + p;
+        const T o0 = u[0] * a0 + u[(size_t)npad] * a1 + u[2 * (size_t)npad] * a2;
+        const T o1 = u[3 * (size_t)npad] * a0 + u[4 * (size_t)npad] * a1 + u[5 * (size_t)npad] * a2;
+        const T o2 = u[6 * (size_t)npad] * a0 + u[7 * (size_t)npad] * a1 + u[8 * (size_t)npad] * a2;
         st_dev(x2 + 3 * (size_t)i, o0);
         st_dev(x2 + 3 * (size_t)i + 1, o1);
         st_dev(x2 + 3 * (size_t)i + 2, o2);
-        const double ex = e0 ? e0[(size_t)i * NE] : 0.0;
-        const double ey = (NE == 2 && e0) ? e0[(size_t)i * NE + 1] : 0.0;
-        z[3 * (size_t)i] = o0 + (ea == 0 ? ex : 0.0) + (NE == 2 && eb == 0 ? ey : 0.0);
-        z[3 * (size_t)i + 1] = o1 + (ea == 1 ? ex : 0.0) + (NE == 2 && eb == 1 ? ey : 0.0);
-        z[3 * (size_t)i + 2] = o2 + (ea == 2 ? ex : 0.0) + (NE == 2 && eb == 2 ? ey : 0.0);
+        const double ex = e0 ? (double)e0[(size_t)i * NE] : 0.0;
+        const double ey = (NE == 2 && e0) ? (double)e0[(size_t)i * NE + 1] : 0.0;
+        z[3 * (size_t)i] = (double)o0 + (ea == 0 ? ex : 0.0) + (NE == 2 && eb == 0 ? ey : 0.0);
+        z[3 * (size_t)i + 1] = (double)o1 + (ea == 1 ? ex : 0.0) + (NE == 2 && eb == 1 ? ey : 0.0);
+        z[3 * (size_t)i + 2] = (double)o2 + (ea == 2 ? ex : 0.0) + (NE == 2 && eb == 2 ? ey : 0.0);
         done = true;
       }
     }
@@ -1090,15 +1089,15 @@ __global__ __launch_bounds__(kBlock) void k_stage2_grid(int nx, int ny, int nz, 
 
 // stage-two residual that also prepares the one-launch sweeps: y, x2 :=
 // sentinel and both ticket counters := 0
-template <int NE>
+template <int NE, class T>
 __global__ __launch_bounds__(kBlock) void k_stage2_resid_sf(int nrows, int nblk, const int32_t* __restrict__ sptr,
                                                             const int32_t* __restrict__ col,
                                                             const double* __restrict__ val, int ea,
-                                                            int eb, const double* __restrict__ e0,
+                                                            int eb, const T* __restrict__ e0,
                                                             const double* __restrict__ r,
-                                                            double* __restrict__ r2,
-                                                            double* __restrict__ y,
-                                                            double* __restrict__ x2, int* tickets) {
+                                                            T* __restrict__ r2,
+                                                            T* __restrict__ y,
+                                                            T* __restrict__ x2, int* tickets) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     tickets[0] = 0;
     tickets[1] = 0;
@@ -1107,7 +1106,8 @@ __global__ __launch_bounds__(kBlock) void k_stage2_resid_sf(int nrows, int nblk,
   if (row >= nrows) return;
   const int s = row >> 6, lane = row & 63;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  for (int k = sptr[s]; k < sptr[s + 1]; ++k) {
+  // without e0 (M2^-1 alone) this only converts r to T
+  for (int k = sptr[s]; e0 && k < sptr[s + 1]; ++k) {
     const int c = col[(size_t)k * 64 + lane];
     const double* v = val + (size_t)k * 9 * 64 + lane;
     const double u = e0[(size_t)c * NE];
@@ -1122,11 +1122,11 @@ __global__ __launch_bounds__(kBlock) void k_stage2_resid_sf(int nrows, int nblk,
     }
   }
   const double* ri = r + 3 * (size_t)row;
-  double* o = r2 + 3 * (size_t)row;
-  o[0] = ri[0] - a0;
-  o[1] = ri[1] - a1;
-  o[2] = ri[2] - a2;
-  const double s0 = __longlong_as_double((long long)kSentinel);
+  T* o = r2 + 3 * (size_t)row;
+  o[0] = (T)(ri[0] - a0);
+  o[1] = (T)(ri[1] - a1);
+  o[2] = (T)(ri[2] - a2);
+  const T s0 = sentinel_value<T>();
   y[3 * (size_t)row] = s0;
   y[3 * (size_t)row + 1] = s0;
   y[3 * (size_t)row + 2] = s0;
@@ -1371,14 +1371,14 @@ void launch_ilu_bwd_level(const SellT<T>& U, const int32_t* perm, const T* uinv,
 }
 
 
-void launch_stage2_resid_sf(const Sell& A, int ne, const int32_t* eidx, const double* e0,
-                            const double* r, double* r2, double* y, double* x2, int* tickets,
-                            hipStream_t st) {
+template <class T>
+void launch_stage2_resid_sf(const Sell& A, int ne, const int32_t* eidx, const T* e0,
+                            const double* r, T* r2, T* y, T* x2, int* tickets, hipStream_t st) {
   const int g = nblocks(A.nrows, kBlock);
   if (ne == 2)
-    k_stage2_resid_sf<2><<<g, kBlock, 0, st>>>(A.nrows, g, A.sptr, A.col, A.val, eidx[0], eidx[1], e0, r, r2, y, x2, tickets);
+    k_stage2_resid_sf<2, T><<<g, kBlock, 0, st>>>(A.nrows, g, A.sptr, A.col, A.val, eidx[0], eidx[1], e0, r, r2, y, x2, tickets);
   else
-    k_stage2_resid_sf<1><<<g, kBlock, 0, st>>>(A.nrows, g, A.sptr, A.col, A.val, eidx[0], 0, e0, r, r2, y, x2, tickets);
+    k_stage2_resid_sf<1, T><<<g, kBlock, 0, st>>>(A.nrows, g, A.sptr, A.col, A.val, eidx[0], 0, e0, r, r2, y, x2, tickets);
 }
 
 
@@ -1444,22 +1444,24 @@ int ilu_sf_width(int max_width) {
   return 0;
 }
 
-void launch_ilu_fwd_sf(const Sell& L, int width, const int32_t* perm, const double* r2, double* y,
-                       double* x2, int* tickets, double* err, long spin_limit, hipStream_t st) {
+template <class T>
+void launch_ilu_fwd_sf(const SellT<T>& L, int width, const int32_t* perm, const T* r2, T* y,
+                       int* tickets, double* err, long spin_limit, hipStream_t st) {
   const int g = nblocks(L.nrows, kBlock);
   switch (width) {
-    case 4: k_ilu_fwd_sf<4><<<g, kBlock, 0, st>>>(L.nrows, L.sptr, L.col, L.val, perm, r2, y, x2, tickets, err, spin_limit); break;
-    case 8: k_ilu_fwd_sf<8><<<g, kBlock, 0, st>>>(L.nrows, L.sptr, L.col, L.val, perm, r2, y, x2, tickets, err, spin_limit); break;
-    default: k_ilu_fwd_sf<16><<<g, kBlock, 0, st>>>(L.nrows, L.sptr, L.col, L.val, perm, r2, y, x2, tickets, err, spin_limit); break;
+    case 4: k_ilu_fwd_sf<4, T><<<g, kBlock, 0, st>>>(L.nrows, L.sptr, L.col, L.val, perm, r2, y, tickets, err, spin_limit); break;
+    case 8: k_ilu_fwd_sf<8, T><<<g, kBlock, 0, st>>>(L.nrows, L.sptr, L.col, L.val, perm, r2, y, tickets, err, spin_limit); break;
+    default: k_ilu_fwd_sf<16, T><<<g, kBlock, 0, st>>>(L.nrows, L.sptr, L.col, L.val, perm, r2, y, tickets, err, spin_limit); break;
   }
 }
 
-void launch_ilu_bwd_sf(const Sell& U, int width, const int32_t* perm, const double* uinv,
-                       const double* y, const double* e0, int ne, const int32_t* eidx, double* x2,
+template <class T>
+void launch_ilu_bwd_sf(const SellT<T>& U, int width, const int32_t* perm, const T* uinv,
+                       const T* y, const T* e0, int ne, const int32_t* eidx, T* x2,
                        double* z, int* tickets, double* err, long spin_limit, hipStream_t st) {
   const int g = nblocks(U.nrows, kBlock);
   const int npad = U.nslices * 64;
-#define BWD(WW, NN) k_ilu_bwd_sf<WW, NN><<<g, kBlock, 0, st>>>(U.nrows, npad, U.sptr, U.col, U.val, perm, uinv, y, e0, eidx[0], NN == 2 ? eidx[1] : 0, x2, z, tickets, err, spin_limit)
+#define BWD(WW, NN) k_ilu_bwd_sf<WW, NN, T><<<g, kBlock, 0, st>>>(U.nrows, npad, U.sptr, U.col, U.val, perm, uinv, y, e0, eidx[0], NN == 2 ? eidx[1] : 0, x2, z, tickets, err, spin_limit)
   if (ne == 2) {
     if (width == 4) BWD(4, 2); else if (width == 8) BWD(8, 2); else BWD(16, 2);
   } else {
@@ -1531,7 +1533,14 @@ void launch_update_host_coef(int64_t n, int nv, const double* V, int64_t ldv, co
   template void launch_ilu_fwd_grid<T>(int, int, int, const T*, const T*, T*, T*, int*, double*, long, \
                                        hipStream_t);                                                 \
   template void launch_ilu_bwd_grid<T>(int, int, int, const T*, T*, const T*, int, const int32_t*, T*, \
-                                       double*, int*, double*, long, hipStream_t);
+                                       double*, int*, double*, long, hipStream_t);                   \
+  template void launch_stage2_resid_sf<T>(const Sell&, int, const int32_t*, const T*, const double*,  \
+                                          T*, T*, T*, int*, hipStream_t);                            \
+  template void launch_ilu_fwd_sf<T>(const SellT<T>&, int, const int32_t*, const T*, T*, int*,       \
+                                     double*, long, hipStream_t);                                    \
+  template void launch_ilu_bwd_sf<T>(const SellT<T>&, int, const int32_t*, const T*, const T*,       \
+                                     const T*, int, const int32_t*, T*, double*, int*, double*, long, \
+                                     hipStream_t);
 CPTR_PREC_LAUNCHERS(double)
 CPTR_PREC_LAUNCHERS(float)
 #undef CPTR_PREC_LAUNCHERS

@@ -80,9 +80,10 @@ void launch_ilu_bwd_level(const SellT<T>& U, const int32_t* perm, const T* uinv,
 
 // one-launch ILU sweeps (see kernels.hip); width = register slots per row
 int ilu_sf_width(int max_width);  // 0 when the rows are too wide for the one-launch kernels
-void launch_stage2_resid_sf(const Sell& A, int ne, const int32_t* eidx, const double* e0,
-                            const double* r, double* r2, double* y, double* x2, int* tickets,
-                            hipStream_t st);
+// r2 = r - A P_E e0 in T (e0 null: r2 = r), y, x2 := sentinel, tickets := 0
+template <class T>
+void launch_stage2_resid_sf(const Sell& A, int ne, const int32_t* eidx, const T* e0,
+                            const double* r, T* r2, T* y, T* x2, int* tickets, hipStream_t st);
 // 7-point lexicographic grids: tiled systolic sweeps.  Lt / Ut: per-cell L
 // (27 values) and U + U_ii^-1 (36 values) in the tile layout of grid_tile_slot;
 // ytile: forward results in the backward sweep's tile layout.
@@ -117,10 +118,12 @@ template <class T>
 void launch_ilu_bwd_grid(int nx, int ny, int nz, const T* Ut, T* ytile, const T* e0t, int ne,
                          const int32_t* eidx, T* faces, double* z, int* tickets, double* err,
                          long spin_limit, hipStream_t st);
-void launch_ilu_fwd_sf(const Sell& L, int width, const int32_t* perm, const double* r2, double* y,
-                       double* x2, int* tickets, double* err, long spin_limit, hipStream_t st);
-void launch_ilu_bwd_sf(const Sell& U, int width, const int32_t* perm, const double* uinv,
-                       const double* y, const double* e0, int ne, const int32_t* eidx, double* x2,
+template <class T>
+void launch_ilu_fwd_sf(const SellT<T>& L, int width, const int32_t* perm, const T* r2, T* y,
+                       int* tickets, double* err, long spin_limit, hipStream_t st);
+template <class T>
+void launch_ilu_bwd_sf(const SellT<T>& U, int width, const int32_t* perm, const T* uinv,
+                       const T* y, const T* e0, int ne, const int32_t* eidx, T* x2,
                        double* z, int* tickets, double* err, long spin_limit, hipStream_t st);
 template <class T>
 void launch_prolong_e(int32_t nrows, int ne, const int32_t* eidx, const T* e0, double* x1,

@@ -42,8 +42,10 @@ def host(t):
 
 
 @pytest.mark.parametrize("name,sweep", [("grid20x20x5", L.ILU_SWEEP_AUTO), ("grid20x20x5", L.ILU_SWEEP_LEVELS),
+                                        ("grid20x20x5", L.ILU_SWEEP_ONE_LAUNCH),
                                         ("grid33x17x2", L.ILU_SWEEP_AUTO), ("grid100x100x20", L.ILU_SWEEP_AUTO),
-                                        ("grid100x100x20", L.ILU_SWEEP_LEVELS)])
+                                        ("grid100x100x20", L.ILU_SWEEP_LEVELS),
+                                        ("prism2000x5", L.ILU_SWEEP_AUTO), ("prism2000x5", L.ILU_SWEEP_LEVELS)])
 def test_fp32_apply_against_oracle(name, sweep):
     c = J.by_name(name)
     say(f"[fp32 apply] {name} sweep={sweep}")
@@ -67,23 +69,24 @@ def test_fp32_apply_against_oracle(name, sweep):
 
 
 def test_fp32_schedules_agree():
-    """Grid and per-level sweeps do the same FP32 arithmetic per row in a
-    different order: they agree to a few FP32 roundings."""
+    """Grid, one-launch and per-level sweeps do the same FP32 arithmetic per
+    row in a different order: they agree to a few FP32 roundings."""
     c = J.by_name("grid20x20x5")
     r = dev(np.random.default_rng(4).standard_normal(c.n_dof))
     out = []
-    for sweep in (L.ILU_SWEEP_GRID, L.ILU_SWEEP_LEVELS):
+    for sweep in (L.ILU_SWEEP_GRID, L.ILU_SWEEP_LEVELS, L.ILU_SWEEP_ONE_LAUNCH):
         with L.Solver(c.row_ptr, c.col_idx, c.values, ilu_sweep=sweep, **FP32) as s:
             z = torch.empty_like(r)
             s.apply(r, z)
             out.append(host(z))
-    d = np.linalg.norm(out[0] - out[1]) / np.linalg.norm(out[1])
-    say(f"[fp32 schedules] {d:.2e}")
-    assert d <= 1e-5
+    for o in out[1:]:
+        d = np.linalg.norm(out[0] - o) / np.linalg.norm(o)
+        say(f"[fp32 schedules] {d:.2e}")
+        assert d <= 1e-5
 
 
 @pytest.mark.parametrize("name,restart", [("grid20x20x5", 30), ("grid100x100x20", 50),
-                                          ("grid100x100x20_pe1000", 50)])
+                                          ("grid100x100x20_pe1000", 50), ("prism10000x10", 50)])
 def test_fp32_fgmres_reaches_tolerance(name, restart):
     c = J.by_name(name)
     say(f"[fp32 fgmres] {name}")

@@ -174,12 +174,11 @@ def test_coarsening_limit_reports_stall():
 
 
 def test_fp32_preconditioner_options():
-    """Mixed precision is a setup option; the one-launch sweeps are FP64 only,
-    and an unknown precision is rejected before any work."""
+    """Mixed precision is a setup option, valid with every sweep schedule; an
+    unknown precision is rejected before any work."""
     c = J.by_name("grid7x5x3")
-    with pytest.raises(L.CptrError):
-        L.Solver(c.row_ptr, c.col_idx, c.values, host_only=1, ilu_sweep=L.ILU_SWEEP_ONE_LAUNCH,
-                 precond_precision=L.PRECISION_FP32)
+    for sweep in (L.ILU_SWEEP_LEVELS, L.ILU_SWEEP_ONE_LAUNCH, L.ILU_SWEEP_GRID):
+        host_solver(c, ilu_sweep=sweep, precond_precision=L.PRECISION_FP32).close()
     with pytest.raises(L.CptrError):
         L.Solver(c.row_ptr, c.col_idx, c.values, host_only=1, precond_precision=7)
     # the host hierarchy does not depend on the precision
