@@ -15,6 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcptr.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "cptr.h")
+HEADERS = [HEADER, os.path.join(os.path.dirname(_HERE), "include", "cptr_serve.h")]
 
 CPTR_OK, CPTR_NOT_CONVERGED = 0, 1
 CPTR_E_INVALID, CPTR_E_NOMEM, CPTR_E_ZERO_PIVOT = -1, -2, -3
@@ -60,6 +61,26 @@ class cptr_solve_info(C.Structure):
                 ("setup_s", C.c_double), ("solve_s", C.c_double)]
 
 
+class cptr_server_opts(C.Structure):
+    _fields_ = [("max_inflight", C.c_int32), ("setup_workers", C.c_int32),
+                ("hbm_budget_bytes", C.c_int64), ("device", C.c_int32),
+                ("setup", cptr_setup_opts)]
+
+
+class cptr_serve_info(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("converged", C.c_int32),
+                ("pad_", C.c_int32), ("rel_res_true", C.c_double), ("queue_s", C.c_double),
+                ("host_setup_s", C.c_double), ("admit_wait_s", C.c_double),
+                ("device_setup_s", C.c_double), ("solve_s", C.c_double),
+                ("latency_s", C.c_double), ("device_bytes", C.c_int64)]
+
+
+class cptr_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("peak_inflight", C.c_int32), ("pad_", C.c_int32),
+                ("peak_reserved_bytes", C.c_int64), ("hbm_budget_bytes", C.c_int64)]
+
+
 _lib = None
 
 
@@ -99,15 +120,32 @@ def lib():
         L.cptr_export.restype = C.c_int
         L.cptr_phase_times.argtypes = [P, P, P, C.c_int32, C.c_int32]
         L.cptr_phase_times.restype = C.c_int
+        L.cptr_server_opts_default.argtypes = [C.POINTER(cptr_server_opts)]
+        L.cptr_server_opts_default.restype = None
+        L.cptr_server_create.argtypes = [C.POINTER(cptr_server_opts), P]
+        L.cptr_server_create.restype = C.c_int
+        L.cptr_server_submit.argtypes = [P, C.POINTER(cptr_bsr), C.POINTER(C.c_int32), C.c_int32, P,
+                                         C.POINTER(cptr_solve_opts), C.POINTER(C.c_int64)]
+        L.cptr_server_submit.restype = C.c_int
+        L.cptr_server_wait.argtypes = [P, C.c_int64, P, C.POINTER(cptr_serve_info), C.c_int32]
+        L.cptr_server_wait.restype = C.c_int
+        L.cptr_server_last_error.argtypes = [P]
+        L.cptr_server_last_error.restype = C.c_char_p
+        L.cptr_server_get_stats.argtypes = [P, C.POINTER(cptr_server_stats)]
+        L.cptr_server_get_stats.restype = C.c_int
+        L.cptr_server_destroy.argtypes = [P]
+        L.cptr_server_destroy.restype = C.c_int
         _lib = L
     return _lib
 
 
 def header_functions():
-    """Names of the functions declared in include/cptr.h."""
-    txt = open(HEADER).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(cptr_[a-z0-9_]+)\s*\(", txt)))
+    """Names of the functions declared in include/*.h."""
+    names = set()
+    for h in HEADERS:
+        txt = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(cptr_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
 
 
 def _ptr(a):
@@ -260,3 +298,78 @@ class Solver:
         cnt = np.zeros(len(PHASES), dtype=np.int64)
         _check(lib().cptr_phase_times(self._h, _ptr(ms), _ptr(cnt), len(PHASES), int(reset)), self._h)
         return {p: (float(ms[k]), int(cnt[k])) for k, p in enumerate(PHASES)}
+
+
+class Server:
+    """Handle around cptr_server_*: queues solve requests, admits them to the
+    GPU by HBM footprint as slots free up, and returns their solutions."""
+
+    def __init__(self, max_inflight=4, setup_workers=2, hbm_budget_bytes=16 << 30, device=0,
+                 **setup):
+        self._h = None
+        o = cptr_server_opts()
+        lib().cptr_server_opts_default(C.byref(o))
+        o.max_inflight, o.setup_workers = max_inflight, setup_workers
+        o.hbm_budget_bytes, o.device = hbm_budget_bytes, device
+        for k, v in setup.items():
+            if not hasattr(o.setup, k):
+                raise TypeError(f"unknown setup option {k}")
+            setattr(o.setup, k, v)
+        h = C.c_void_p()
+        code = lib().cptr_server_create(C.byref(o), C.byref(h))
+        if code < 0:
+            raise CptrError(code, "cptr_server_create failed")
+        self._h = h
+        self._n = {}
+
+    def submit(self, row_ptr, col_idx, values, b, elliptic=(0, 1), **solve):
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        v = np.ascontiguousarray(values, dtype=np.float64)
+        bb = np.ascontiguousarray(b, dtype=np.float64)
+        nb = rp.shape[0] - 1
+        A = cptr_bsr(nb, ci.shape[0], _ptr(rp).value, _ptr(ci).value, _ptr(v).value, 0)
+        ell = (C.c_int32 * len(elliptic))(*elliptic)
+        o = solve_opts(**solve)
+        rid = C.c_int64()
+        code = lib().cptr_server_submit(self._h, C.byref(A), ell, len(elliptic), _ptr(bb), C.byref(o),
+                                        C.byref(rid))
+        if code < 0:
+            raise CptrError(code, "cptr_server_submit failed")
+        self._n[rid.value] = 3 * nb
+        return rid.value
+
+    def wait(self, rid, timeout_ms=-1):
+        """(x, info) of request rid; info["status"] < 0 for a failed request
+        (x is None then)."""
+        n = self._n[rid]
+        x = np.zeros(n)
+        info = cptr_serve_info()
+        code = lib().cptr_server_wait(self._h, rid, _ptr(x), C.byref(info), timeout_ms)
+        if code == CPTR_E_STATE:
+            raise TimeoutError(f"request {rid} not finished")
+        del self._n[rid]
+        d = {k: getattr(info, k) for k, _ in cptr_serve_info._fields_ if k != "pad_"}
+        d["status"] = code
+        if code < 0:
+            d["error"] = lib().cptr_server_last_error(self._h).decode()
+            return None, d
+        return x, d
+
+    def stats(self):
+        st = cptr_server_stats()
+        lib().cptr_server_get_stats(self._h, C.byref(st))
+        return {k: getattr(st, k) for k, _ in cptr_server_stats._fields_ if k != "pad_"}
+
+    def close(self):
+        if self._h:
+            lib().cptr_server_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -37,7 +37,7 @@ def build(verbose: bool = False) -> str:
           "-Wno-unused-parameter", f"-I{INC}", "-c", os.path.join(CSRC, "host_setup.cpp"),
           "-o", host])
     objs.append(host)
-    for src in ("cptr_api.cpp", "kernels.hip"):
+    for src in ("cptr_api.cpp", "cptr_serve.cpp", "kernels.hip"):
         obj = os.path.join(BUILD, src.replace(".", "_") + ".o")
         _run([HIPCC, "-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
               "-ffp-contract=fast", *NO_PK, f"-I{INC}", "-c", os.path.join(CSRC, src), "-o", obj])

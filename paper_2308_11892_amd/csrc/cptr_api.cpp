@@ -21,8 +21,10 @@
 #include <vector>
 
 #include "cptr.h"
+#include "dev_arena.hpp"
 #include "host_setup.hpp"
 #include "kernels.hpp"
+#include "solver_internal.hpp"
 
 using namespace cptr;
 
@@ -119,6 +121,9 @@ struct cptr_solver_s {
   int32_t eidx_h[3] = {0, 1, 2}, hidx_h[3] = {2, 0, 0};
   int64_t N = 0;  // DOF
   std::vector<void*> allocs;
+  DevArena* arena = nullptr;  // device memory comes from here when set (serving)
+  bool measure = false;       // count device bytes only: no allocation, copy or launch
+  int64_t dev_bytes = 0;      // device bytes held (or counted), in DevArena pieces
   // device operators shared by both precisions
   Sell A;
   double* W = nullptr;
@@ -174,19 +179,54 @@ int hip_fail(cptr_solver s, hipError_t e, const char* what) {
     if (_e != hipSuccess) return (cptr_status)hip_fail((s), _e, #call); \
   } while (0)
 
+// In measure mode pointers are this placeholder: never dereferenced, never
+// passed to a kernel or a copy.
+char g_measure_placeholder[DevArena::kAlign];
+
 template <class T>
 int dalloc(cptr_solver s, T*& p, int64_t count) {
   p = nullptr;
   if (count <= 0) count = 1;
+  const size_t bytes = sizeof(T) * (size_t)count;
+  if (s->measure) {
+    s->dev_bytes += (int64_t)DevArena::round(bytes);
+    p = reinterpret_cast<T*>(g_measure_placeholder);
+    return CPTR_OK;
+  }
   void* q = nullptr;
-  hipError_t e = hipMalloc(&q, sizeof(T) * (size_t)count);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(s, CPTR_E_NOMEM, "device allocation of " + std::to_string(sizeof(T) * count) + " bytes failed");
+  if (s->arena) {
+    q = s->arena->alloc(bytes);
+    if (!q)
+      return fail(s, CPTR_E_NOMEM, "HBM arena has no free piece of " + std::to_string(bytes) + " bytes");
+  } else {
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(s, CPTR_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
   }
   s->allocs.push_back(q);
+  s->dev_bytes += (int64_t)DevArena::round(bytes);
   p = static_cast<T*>(q);
   return CPTR_OK;
+}
+
+// returns one allocation of the handle (to the arena when there is one)
+void dfree(cptr_solver s, void* p) {
+  auto it = std::find(s->allocs.begin(), s->allocs.end(), p);
+  if (it == s->allocs.end()) return;
+  s->allocs.erase(it);
+  if (s->arena) (void)s->arena->release(p);
+  else (void)hipFree(p);
+}
+
+void dfree_all(cptr_solver s) {
+  for (void* p : s->allocs) {
+    if (s->arena) (void)s->arena->release(p);
+    else (void)hipFree(p);
+  }
+  s->allocs.clear();
+  s->dev_bytes = 0;
 }
 
 template <class T>
@@ -195,7 +235,8 @@ int upload(cptr_solver s, T*& p, const T* src, int64_t count, hipStream_t st) {
   if (rc) return rc;
   // blocking copy: the host staging vectors die right after the upload
   (void)st;
-  if (count > 0) HIP_TRY(s, hipMemcpy(p, src, sizeof(T) * (size_t)count, hipMemcpyHostToDevice));
+  if (count > 0 && !s->measure)
+    HIP_TRY(s, hipMemcpy(p, src, sizeof(T) * (size_t)count, hipMemcpyHostToDevice));
   return CPTR_OK;
 }
 
@@ -205,6 +246,7 @@ int upload_as(cptr_solver s, T*& p, const double* src, int64_t count, hipStream_
   if constexpr (std::is_same<T, double>::value) {
     return upload(s, p, src, count, st);
   } else {
+    if (s->measure) return dalloc(s, p, count);
     std::vector<T> tmp(src, src + count);
     return upload(s, p, tmp.data(), count, st);
   }
@@ -316,11 +358,13 @@ int build_grid_factors(cptr_solver s, PrecDev<T>& d, hipStream_t st) {
   if ((rc = upload_as(s, d.Ug, ut.data(), (int64_t)ut.size(), st))) return rc;
   // padding slots of the tile vectors stay zero forever (no kernel writes them)
   if ((rc = dalloc(s, d.ytile, rows * 3 * 64))) return rc;
-  HIP_TRY(s, hipMemset(d.ytile, 0, sizeof(T) * (size_t)rows * 3 * 64));
   if ((rc = dalloc(s, d.r2tile, rows * 3 * 64))) return rc;
-  HIP_TRY(s, hipMemset(d.r2tile, 0, sizeof(T) * (size_t)rows * 3 * 64));
   if ((rc = dalloc(s, d.e0tile, rows * 2 * 64))) return rc;
-  HIP_TRY(s, hipMemset(d.e0tile, 0, sizeof(T) * (size_t)rows * 2 * 64));
+  if (!s->measure) {
+    HIP_TRY(s, hipMemset(d.ytile, 0, sizeof(T) * (size_t)rows * 3 * 64));
+    HIP_TRY(s, hipMemset(d.r2tile, 0, sizeof(T) * (size_t)rows * 3 * 64));
+    HIP_TRY(s, hipMemset(d.e0tile, 0, sizeof(T) * (size_t)rows * 2 * 64));
+  }
   if ((rc = dalloc(s, d.faces, 2 * grid_face_values(nx, ny, nz)))) return rc;
   return CPTR_OK;
 }
@@ -404,6 +448,34 @@ int build_prec(cptr_solver s, PrecDev<T>& d, const std::vector<int32_t>& fp,
   return CPTR_OK;
 }
 
+// device-side members back to their initial (host-only) values; no freeing
+void reset_device_state(cptr_solver s) {
+  s->allocs.clear();
+  s->dev_bytes = 0;
+  s->A = Sell();
+  s->W = nullptr;
+  s->fperm = s->bperm = nullptr;
+  s->flev_ptr.clear();
+  s->blev_ptr.clear();
+  s->sf_width = 0;
+  s->grid[0] = s->grid[1] = s->grid[2] = 0;
+  s->use_grid = false;
+  s->tickets = nullptr;
+  s->coarse_lu = nullptr;
+  s->coarse_piv = nullptr;
+  s->ncoarse = 0;
+  s->p64 = PrecDev<double>();
+  s->p32 = PrecDev<float>();
+  s->restart_cap = 0;
+  s->have_z = false;
+  s->V = s->Z = nullptr;
+  s->ldv = 0;
+  s->wr = s->wt = s->wu = nullptr;
+  s->part = nullptr;
+  s->hdev = nullptr;
+  s->hhost = nullptr;
+}
+
 int build_device(cptr_solver s, hipStream_t st) {
   const HostSetup& h = s->host;
   const int32_t nb = h.nb;
@@ -443,7 +515,7 @@ int build_device(cptr_solver s, hipStream_t st) {
     order(h.fwd_level, h.n_fwd_levels, fp, s->flev_ptr);
     order(h.bwd_level, h.n_bwd_levels, bp, s->blev_ptr);
     if ((rc = dalloc(s, s->tickets, 2))) return rc;
-    HIP_TRY(s, hipMemset(s->tickets, 0, 2 * sizeof(int)));
+    if (!s->measure) HIP_TRY(s, hipMemset(s->tickets, 0, 2 * sizeof(int)));
     const bool grid = detect_grid(h, s->grid);
     if (s->ilu_mode == CPTR_ILU_SWEEP_GRID && !grid)
       return fail(s, CPTR_E_INVALID, "ilu_sweep = GRID needs a 7-point stencil in lexicographic order");
@@ -459,6 +531,7 @@ int build_device(cptr_solver s, hipStream_t st) {
   if ((rc = upload(s, s->coarse_piv, h.coarse_piv.data(), (int64_t)h.coarse_piv.size(), st))) return rc;
   if ((rc = dalloc(s, s->part, (int64_t)kRedBlocks * (kMaxRestart + 2)))) return rc;
   if ((rc = dalloc(s, s->hdev, 256))) return rc;
+  if (s->measure) return CPTR_OK;
   HIP_TRY(s, hipMemset(s->hdev, 0, 256 * sizeof(double)));
   {
     void* hp = nullptr;
@@ -620,13 +693,11 @@ int ensure_solve_space(cptr_solver s, int m, bool flexible) {
   int rc;
   if (m > s->restart_cap) {
     if (s->V) {
-      (void)hipFree(s->V);
-      s->allocs.erase(std::find(s->allocs.begin(), s->allocs.end(), (void*)s->V));
+      dfree(s, s->V);
       s->V = nullptr;
     }
     if (s->Z) {
-      (void)hipFree(s->Z);
-      s->allocs.erase(std::find(s->allocs.begin(), s->allocs.end(), (void*)s->Z));
+      dfree(s, s->Z);
       s->Z = nullptr;
       s->have_z = false;
     }
@@ -691,10 +762,12 @@ void cptr_solve_opts_default(cptr_solve_opts* o) {
 
 const char* cptr_last_error(cptr_solver s) { return s ? s->err.c_str() : g_setup_error.c_str(); }
 
-cptr_status cptr_setup(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_idx,
-                       int32_t n_elliptic, const cptr_setup_opts* opts, void* stream,
-                       cptr_solver* out) {
-  const double t0 = now_s();
+}  // extern "C"
+
+namespace cptr {
+
+int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_idx, int32_t n_elliptic,
+               const cptr_setup_opts* opts, cptr_solver* out) {
   g_setup_error.clear();
   if (!out) return (cptr_status)fail(nullptr, CPTR_E_INVALID, "out is NULL");
   *out = nullptr;
@@ -725,7 +798,6 @@ cptr_status cptr_setup(const cptr_bsr* A, int32_t block_size, const int32_t* ell
     return (cptr_status)fail(nullptr, CPTR_E_INVALID, "A.n_block_rows / A.nnz_blocks out of range");
   if (!A->row_ptr || !A->col_idx || !A->values)
     return (cptr_status)fail(nullptr, CPTR_E_INVALID, "A has a NULL array");
-  hipStream_t st = static_cast<hipStream_t>(stream);
 
   std::unique_ptr<cptr_solver_s> s(new (std::nothrow) cptr_solver_s());
   if (!s) return (cptr_status)fail(nullptr, CPTR_E_NOMEM, "host allocation failed");
@@ -782,40 +854,98 @@ cptr_status cptr_setup(const cptr_bsr* A, int32_t block_size, const int32_t* ell
   s->N = (int64_t)nb * 3;
   s->ilu_mode = o.ilu_sweep;
   s->prec = o.precond_precision;
+  *out = s.release();
+  return CPTR_OK;
+}
+
+int measure_device(cptr_solver s, int restart, bool flexible, int64_t* bytes) {
+  if (!s || !bytes) return CPTR_E_INVALID;
+  if (s->device) return fail(s, CPTR_E_STATE, "handle already has its device half");
+  s->measure = true;
+  s->dev_bytes = 0;
+  int rc = CPTR_OK;
+  try {
+    rc = build_device(s, nullptr);
+    if (!rc) rc = ensure_solve_space(s, std::max(1, std::min(restart, kMaxRestart)), flexible);
+  } catch (const std::bad_alloc&) {
+    rc = fail(s, CPTR_E_NOMEM, "host allocation failed while packing device layouts");
+  }
+  *bytes = s->dev_bytes;
+  s->measure = false;
+  reset_device_state(s);
+  return rc;
+}
+
+int setup_device(cptr_solver s, DevArena* arena, int restart, bool flexible, hipStream_t st) {
+  if (!s) return CPTR_E_INVALID;
+  if (s->device) return fail(s, CPTR_E_STATE, "handle already has its device half");
+  int dev_count = 0;
+  hipError_t he = hipGetDeviceCount(&dev_count);
+  if (he != hipSuccess || dev_count == 0) return fail(s, CPTR_E_HIP, "no HIP device available");
+  s->arena = arena;
+  int rc;
+  try {
+    rc = build_device(s, st);
+    if (!rc && restart > 0) rc = ensure_solve_space(s, std::min(restart, kMaxRestart), flexible);
+  } catch (const std::bad_alloc&) {
+    rc = fail(s, CPTR_E_NOMEM, "host allocation failed while packing device layouts");
+  }
+  if (rc) {
+    release_device(s);
+    return rc;
+  }
+  s->device = true;
+  return CPTR_OK;
+}
+
+void release_device(cptr_solver s) {
+  if (!s) return;
+  dfree_all(s);
+  if (s->hhost) (void)hipHostFree(s->hhost);
+  for (auto& e : s->ev_pool)
+    if (e) (void)hipEventDestroy(e);
+  s->ev_pool.clear();
+  s->ev_used = 0;
+  s->ev_pending.clear();
+  reset_device_state(s);
+  s->device = false;
+}
+
+const char* last_error(cptr_solver s) { return s ? s->err.c_str() : g_setup_error.c_str(); }
+
+int64_t device_bytes(cptr_solver s) { return s ? s->dev_bytes : 0; }
+
+}  // namespace cptr
+
+extern "C" {
+
+cptr_status cptr_setup(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_idx,
+                       int32_t n_elliptic, const cptr_setup_opts* opts, void* stream,
+                       cptr_solver* out) {
+  const double t0 = now_s();
+  if (out) *out = nullptr;
+  cptr_solver s = nullptr;
+  int rc = setup_host(A, block_size, elliptic_idx, n_elliptic, opts, &s);
+  if (rc) return (cptr_status)rc;
+  cptr_setup_opts o;
+  cptr_setup_opts_default(&o);
+  if (opts) o = *opts;
   if (!o.host_only) {
-    int dev_count = 0;
-    hipError_t he = hipGetDeviceCount(&dev_count);
-    if (he != hipSuccess || dev_count == 0)
-      return (cptr_status)fail(nullptr, CPTR_E_HIP, "no HIP device available");
-    try {
-      rc = build_device(s.get(), st);
-    } catch (const std::bad_alloc&) {
-      rc = fail(s.get(), CPTR_E_NOMEM, "host allocation failed while packing device layouts");
-    }
+    rc = setup_device(s, nullptr, 0, false, static_cast<hipStream_t>(stream));
     if (rc) {
       g_setup_error = s->err;
-      for (void* p : s->allocs) (void)hipFree(p);
-      if (s->hhost) (void)hipHostFree(s->hhost);
+      delete s;
       return (cptr_status)rc;
     }
-    s->device = true;
-    s->ev_pool.resize(512);
-    for (auto& e : s->ev_pool)
-      if (hipEventCreate(&e) != hipSuccess) {
-        e = nullptr;
-      }
   }
   s->setup_s = now_s() - t0;
-  *out = s.release();
+  *out = s;
   return CPTR_OK;
 }
 
 cptr_status cptr_destroy(cptr_solver s) {
   if (!s) return CPTR_E_INVALID;
-  for (void* p : s->allocs) (void)hipFree(p);
-  if (s->hhost) (void)hipHostFree(s->hhost);
-  for (auto& e : s->ev_pool)
-    if (e) (void)hipEventDestroy(e);
+  release_device(s);
   delete s;
   return CPTR_OK;
 }
@@ -888,6 +1018,11 @@ cptr_status cptr_gmres_solve(cptr_solver s, const double* b, double* x, const cp
   const double t0 = now_s();
   int rc = ensure_solve_space(s, o.restart, o.flexible != 0);
   if (rc) return (cptr_status)rc;
+  if (o.profile != 0 && s->ev_pool.empty()) {
+    s->ev_pool.resize(512);
+    for (auto& e : s->ev_pool)
+      if (hipEventCreate(&e) != hipSuccess) e = nullptr;
+  }
   s->profiling = o.profile != 0 && !s->ev_pool.empty() && s->ev_pool[0];
   s->ev_used = 0;
   s->ev_pending.clear();

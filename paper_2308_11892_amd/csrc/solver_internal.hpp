@@ -1,0 +1,35 @@
+// solver_internal.hpp -- the two halves of cptr_setup, for the serving runtime.
+//
+// cptr_setup = setup_host (validation, host AMG and ILU(0) setup; no device
+// call) + setup_device (device layouts and uploads).  measure_device runs the
+// device half without touching the device and returns the exact bytes it would
+// allocate (in DevArena pieces), so a request can be admitted by its HBM
+// footprint before any of it is allocated.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "cptr.h"
+#include "dev_arena.hpp"
+
+namespace cptr {
+
+// Host half.  On success *out is a handle with no device state.
+int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_idx, int32_t n_elliptic,
+               const cptr_setup_opts* opts, cptr_solver* out);
+// Device bytes setup_device(s, arena, restart, flexible) allocates, counted in
+// DevArena pieces.
+int measure_device(cptr_solver s, int restart, bool flexible, int64_t* bytes);
+// Device half: allocations from `arena` (nullptr: hipMalloc), including the
+// solve workspace of (F)GMRES(restart); synchronises `st`.
+int setup_device(cptr_solver s, DevArena* arena, int restart, bool flexible, hipStream_t st);
+// Frees the device half (back to the arena when there is one); the handle
+// returns to its host-only state.
+void release_device(cptr_solver s);
+// Device bytes the handle holds now, in DevArena pieces.
+int64_t device_bytes(cptr_solver s);
+// Message of the last failure on the handle (or of the calling thread's setup).
+const char* last_error(cptr_solver s);
+
+}  // namespace cptr
