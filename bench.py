@@ -103,6 +103,86 @@ def run_cpu_baseline(c, restart):
                 iterations=info["iterations"], solve_s=t_solve, setup_s=t_setup, x=xo)
 
 
+def _make_request(spec):
+    from synth import jacobian as J
+    _, grid, tol, seed = spec
+    return J.serving_case(grid, tol, seed)
+
+
+def run_serving(args):
+    """Serving: requests arrive as a Poisson stream; each is one FGMRES(50)
+    solve of its own seeded Jacobian.  The Jacobians are generated before the
+    stream starts (the simulator's side); the timed part is submission to
+    completion through the solve server.  Prints one JSON line with solves/s
+    and the p50/p99 latency."""
+    import multiprocessing as mp
+    import threading
+
+    import numpy as np
+    from synth import jacobian as J
+
+    stream = J.serving_stream(args.serve, rate=args.rate)
+    log(f"serving: generating {len(stream)} requests")
+    # worker processes are forked before this process touches the GPU
+    with mp.get_context("fork").Pool(min(8, os.cpu_count() or 1)) as pool:
+        cases = pool.map(_make_request, stream, chunksize=1)
+    import torch
+    import paper_2308_11892_amd as L
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    cells = [c.n_cells for c in cases]
+    log(f"serving: {sum(cells)} cells in total; starting the server")
+    sv = L.Server(max_inflight=4, setup_workers=4, setup_threads=4, hbm_budget_bytes=64 << 30)
+    ids = [None] * len(stream)
+    t0 = time.perf_counter()
+
+    def submitter():
+        for r, (ta, grid, tol, seed) in enumerate(stream):
+            dt = t0 + ta - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            c = cases[r]
+            ids[r] = sv.submit(c.row_ptr, c.col_idx, c.values, c.b, rtol=tol, restart=50, flexible=True,
+                               max_iter=200)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    th.join()
+    res = []
+    for r, rid in enumerate(ids):
+        x, info = sv.wait(rid)
+        c = cases[r]
+        rr = float("nan") if x is None else float(
+            np.linalg.norm(c.b - J.bsr_matvec_plain(c.row_ptr, c.col_idx, c.values, x)) / np.linalg.norm(c.b))
+        res.append((info, rr, stream[r][2]))
+        log(f"request {r} {c.name} tol {stream[r][2]:g}: status {info['status']} {info['iterations']} it "
+            f"rel res {rr:.2e} latency {info['latency_s'] * 1e3:.0f} ms (queue {info['queue_s'] * 1e3:.0f}, "
+            f"host setup {info['host_setup_s'] * 1e3:.0f}, admit {info['admit_wait_s'] * 1e3:.0f}, "
+            f"device setup {info['device_setup_s'] * 1e3:.0f}, solve {info['solve_s'] * 1e3:.0f})")
+    t_end = time.perf_counter()
+    st = sv.stats()
+    sv.close()
+    ok = [i for i, rr, tol in res if i["status"] >= 0 and rr <= tol]
+    lat = np.array([i["latency_s"] for i, _, _ in res])
+    med = lambda k: float(np.median([i[k] for i, _, _ in res]))
+    out = {
+        "metric": "CPTR-FGMRES serving: solves/s and p50/p99 solve latency",
+        "value": len(ok) / (t_end - t0), "unit": "solves/s", "n_gpus": 1,
+        "requests": len(res), "converged_within_tol": len(ok),
+        "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
+        "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
+        "median_ms": {k: med(k) * 1e3 for k in ("queue_s", "host_setup_s", "admit_wait_s",
+                                                  "device_setup_s", "solve_s")},
+        "makespan_s": t_end - t0, "peak_inflight": st["peak_inflight"],
+        "peak_reserved_gib": st["peak_reserved_bytes"] / 2**30, "hbm_budget_gib": st["hbm_budget_bytes"] / 2**30,
+        "higher_is_better": True, "dtype": "f32 preconditioner, f64 Krylov", "data": "synthetic",
+        "config": {"workload": f"serving: {len(res)} Poisson arrivals at {args.rate:g}/s, grids "
+                               "40x40x10/80x80x20/160x160x20/200x200x40, tol 1e-4 or 1e-6, FGMRES(50)",
+                   "slots": 4, "setup_workers": 4, "setup_threads": 4},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,11 +197,20 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (three times), the "
                          "reference dispatch for scaling HBM byte counters")
+    ap.add_argument("--serve", type=int, default=0, metavar="N",
+                    help="instead of the solve benchmark, run the serving workload: N requests "
+                         "of four grid sizes arriving as a Poisson stream, solved by the "
+                         "solve server with the mixed-precision preconditioner")
+    ap.add_argument("--rate", type=float, default=20.0, help="serving: mean arrivals per second")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU design is documented, not built)", file=sys.stderr)
         sys.exit(2)
+
+    if args.serve:
+        run_serving(args)
+        return
 
     import numpy as np
     import torch

@@ -46,9 +46,24 @@ struct HostSell {
   std::vector<double> val;
 };
 
+// run body(lo, hi) over [0, n) split into `threads` contiguous ranges
+template <class Body>
+void parallel_ranges(int64_t n, int threads, Body body) {
+  const int t = (int)std::max<int64_t>(1, std::min<int64_t>(threads, n / 4096));
+  if (t <= 1) {
+    body((int64_t)0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int k = 0; k < t; ++k) th.emplace_back(body, n * k / t, n * (k + 1) / t);
+  for (auto& x : th) x.join();
+}
+
 // Pack rows (or positions) into SELL-64; len(r) blocks per row, fill(r, k, col, vals).
+// With sizes_only only the slice pointers are built (col and val stay empty).
 template <class Len, class Fill>
-HostSell pack_sell(int32_t nrows, int nv, Len len, Fill fill, int32_t pad_col_mode) {
+HostSell pack_sell(int32_t nrows, int nv, Len len, Fill fill, int32_t pad_col_mode, bool sizes_only,
+                   int threads) {
   HostSell s;
   s.nrows = nrows;
   s.nv = nv;
@@ -63,9 +78,11 @@ HostSell pack_sell(int32_t nrows, int nv, Len len, Fill fill, int32_t pad_col_mo
     s.sptr[sl + 1] = s.sptr[sl] + w;
   }
   const int64_t slots = s.sptr[s.nslices];
+  if (sizes_only) return s;
   s.col.assign((size_t)slots * kLanes, 0);
   s.val.assign((size_t)slots * kLanes * nv, 0.0);
-  for (int32_t sl = 0; sl < s.nslices; ++sl) {
+  parallel_ranges(s.nslices, threads, [&](int64_t s0, int64_t s1) {
+  for (int32_t sl = (int32_t)s0; sl < (int32_t)s1; ++sl) {
     const int32_t w = s.sptr[sl + 1] - s.sptr[sl];
     for (int l = 0; l < kLanes; ++l) {
       const int32_t r = sl * kLanes + l;
@@ -84,6 +101,7 @@ HostSell pack_sell(int32_t nrows, int nv, Len len, Fill fill, int32_t pad_col_mo
       }
     }
   }
+  });
   return s;
 }
 
@@ -123,6 +141,7 @@ struct cptr_solver_s {
   std::vector<void*> allocs;
   DevArena* arena = nullptr;  // device memory comes from here when set (serving)
   bool measure = false;       // count device bytes only: no allocation, copy or launch
+  int threads = 1;            // host threads for packing device layouts
   int64_t dev_bytes = 0;      // device bytes held (or counted), in DevArena pieces
   // device operators shared by both precisions
   Sell A;
@@ -260,8 +279,9 @@ int upload_sell(cptr_solver s, SellT<T>& d, const HostSell& h, hipStream_t st) {
   d.nslots = h.sptr.back();
   int rc;
   if ((rc = upload(s, d.sptr, h.sptr.data(), (int64_t)h.sptr.size(), st))) return rc;
-  if ((rc = upload(s, d.col, h.col.data(), (int64_t)h.col.size(), st))) return rc;
-  if ((rc = upload_as(s, d.val, h.val.data(), (int64_t)h.val.size(), st))) return rc;
+  const int64_t slots = h.sptr.back();
+  if ((rc = upload(s, d.col, h.col.data(), slots * kLanes, st))) return rc;
+  if ((rc = upload_as(s, d.val, h.val.data(), slots * kLanes * h.nv, st))) return rc;
   return CPTR_OK;
 }
 
@@ -323,8 +343,18 @@ int build_grid_factors(cptr_solver s, PrecDev<T>& d, hipStream_t st) {
   const int nx = s->grid[0], ny = s->grid[1], nz = s->grid[2];
   const int32_t nxy = nx * ny;
   const int64_t rows = grid_ntiles(ny, nz) * grid_nsteps(nx);   // 64-lane rows of either layout
+  int rc;
+  if (s->measure) {
+    if ((rc = dalloc(s, d.Lg, rows * 27 * 64)) || (rc = dalloc(s, d.Ug, rows * 36 * 64)) ||
+        (rc = dalloc(s, d.ytile, rows * 3 * 64)) || (rc = dalloc(s, d.r2tile, rows * 3 * 64)) ||
+        (rc = dalloc(s, d.e0tile, rows * 2 * 64)) || (rc = dalloc(s, d.faces, 2 * grid_face_values(nx, ny, nz))))
+      return rc;
+    return CPTR_OK;
+  }
   std::vector<double> lt((size_t)rows * 27 * 64, 0.0), ut((size_t)rows * 36 * 64, 0.0);
-  for (int32_t c = 0; c < h.nb; ++c) {
+  // every cell owns its own lane of its own rows: the cells split freely
+  parallel_ranges(h.nb, s->threads, [&](int64_t c0, int64_t c1) {
+  for (int32_t c = (int32_t)c0; c < (int32_t)c1; ++c) {
     const int i = c % nx, j = (c / nx) % ny, k = c / nxy;
     int64_t fr, br;
     int lane;
@@ -353,7 +383,7 @@ int build_grid_factors(cptr_solver s, PrecDev<T>& d, hipStream_t st) {
     }
     for (int e = 0; e < 9; ++e) ut[((size_t)br * 36 + 27 + e) * 64 + lane] = h.uinv[(size_t)c * 9 + e];
   }
-  int rc;
+  });
   if ((rc = upload_as(s, d.Lg, lt.data(), (int64_t)lt.size(), st))) return rc;
   if ((rc = upload_as(s, d.Ug, ut.data(), (int64_t)ut.size(), st))) return rc;
   // padding slots of the tile vectors stay zero forever (no kernel writes them)
@@ -386,11 +416,14 @@ int build_prec(cptr_solver s, PrecDev<T>& d, const std::vector<int32_t>& fp,
           c = h.ci[q];
           std::memcpy(v, &h.ahat[(size_t)q * ne * ne], ne * ne * sizeof(double));
         },
-        0);
+        0, s->measure, s->threads);
     if ((rc = upload_sell(s, d.Ahat, hs, st))) return rc;
   }
-  // ILU factors by dependency level
-  {
+  // ILU factors: in the tile layouts of the grid sweeps, or by dependency
+  // level for the one-launch and per-level sweeps (only one of the two is kept)
+  if (s->use_grid) {
+    if ((rc = build_grid_factors(s, d, st))) return rc;
+  } else {
     HostSell Lh = pack_sell(
         nb, 9, [&](int32_t p) { return h.diag[fp[p]] - h.rp[fp[p]]; },
         [&](int32_t p, int32_t k, int32_t& c, double* v) {
@@ -398,7 +431,7 @@ int build_prec(cptr_solver s, PrecDev<T>& d, const std::vector<int32_t>& fp,
           c = h.ci[q];
           std::memcpy(v, &h.ilu[(size_t)q * 9], 9 * sizeof(double));
         },
-        -1);
+        -1, s->measure, s->threads);
     if ((rc = upload_sell(s, d.Lf, Lh, st))) return rc;
     HostSell Uh = pack_sell(
         nb, 9, [&](int32_t p) { return h.rp[bp[p] + 1] - h.diag[bp[p]] - 1; },
@@ -407,7 +440,7 @@ int build_prec(cptr_solver s, PrecDev<T>& d, const std::vector<int32_t>& fp,
           c = h.ci[q];
           std::memcpy(v, &h.ilu[(size_t)q * 9], 9 * sizeof(double));
         },
-        -1);
+        -1, s->measure, s->threads);
     if ((rc = upload_sell(s, d.Ub, Uh, st))) return rc;
     if (s->sf_width == 0 && s->ilu_mode != CPTR_ILU_SWEEP_LEVELS) {
       int maxw = 0;
@@ -419,12 +452,15 @@ int build_prec(cptr_solver s, PrecDev<T>& d, const std::vector<int32_t>& fp,
                     "rows too wide (" + std::to_string(maxw) + " blocks) for one-launch ILU sweeps");
       s->sf_width = w;
     }
-    if (s->use_grid && (rc = build_grid_factors(s, d, st))) return rc;
     const int64_t npad = (int64_t)Uh.nslices * kLanes;
-    std::vector<double> ui((size_t)npad * 9, 0.0);
-    for (int32_t p = 0; p < nb; ++p)
-      for (int e = 0; e < 9; ++e) ui[(size_t)e * npad + p] = h.uinv[(size_t)bp[p] * 9 + e];
-    if ((rc = upload_as(s, d.uinv, ui.data(), (int64_t)ui.size(), st))) return rc;
+    if (s->measure) {
+      if ((rc = dalloc(s, d.uinv, npad * 9))) return rc;
+    } else {
+      std::vector<double> ui((size_t)npad * 9, 0.0);
+      for (int32_t p = 0; p < nb; ++p)
+        for (int e = 0; e < 9; ++e) ui[(size_t)e * npad + p] = h.uinv[(size_t)bp[p] * 9 + e];
+      if ((rc = upload_as(s, d.uinv, ui.data(), (int64_t)ui.size(), st))) return rc;
+    }
   }
   // AMG hierarchy (the coarsest LU stays FP64 and is shared)
   const int L = (int)h.lev.size();
@@ -444,7 +480,8 @@ int build_prec(cptr_solver s, PrecDev<T>& d, const std::vector<int32_t>& fp,
       return rc;
   }
   const int64_t N = (int64_t)nb * 3;
-  if ((rc = dalloc(s, d.r2, N)) || (rc = dalloc(s, d.y, N)) || (rc = dalloc(s, d.x2, N))) return rc;
+  if (!s->use_grid && ((rc = dalloc(s, d.r2, N)) || (rc = dalloc(s, d.y, N)) || (rc = dalloc(s, d.x2, N))))
+    return rc;
   return CPTR_OK;
 }
 
@@ -490,7 +527,7 @@ int build_device(cptr_solver s, hipStream_t st) {
           c = h.ci[q];
           std::memcpy(v, &h.av[(size_t)q * 9], 9 * sizeof(double));
         },
-        0);
+        0, s->measure, s->threads);
     if ((rc = upload_sell(s, s->A, hs, st))) return rc;
   }
   // W padded to 2 per cell
@@ -853,6 +890,7 @@ int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_id
   }
   s->N = (int64_t)nb * 3;
   s->ilu_mode = o.ilu_sweep;
+  s->threads = prm.threads;
   s->prec = o.precond_precision;
   *out = s.release();
   return CPTR_OK;

@@ -578,6 +578,32 @@ def prism_small(n_points, n_layers, seed=17, rcm=True, **kw):
                  corr=2, n_wells=4, r_front=2.0, rcm=rcm, **kw)
 
 
+SERVING_GRIDS = [(40, 40, 10), (80, 80, 20), (160, 160, 20), (200, 200, 40)]
+SERVING_TOLS = [1e-4, 1e-6]
+
+
+def serving_stream(n_requests, rate=20.0, seed=SEED_BASE * 1000):
+    """A Poisson request stream: (arrival time in s, grid, tolerance, seed) per
+    request.  Inter-arrival times are exponential with mean 1/rate; the grid is
+    drawn uniformly from SERVING_GRIDS and the tolerance from SERVING_TOLS.
+    Request r's Jacobian uses seed + r."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n_requests))
+    t -= t[0]
+    grids = rng.integers(len(SERVING_GRIDS), size=n_requests)
+    tols = rng.integers(len(SERVING_TOLS), size=n_requests)
+    return [(float(t[r]), SERVING_GRIDS[int(grids[r])], SERVING_TOLS[int(tols[r])], seed + r)
+            for r in range(n_requests)]
+
+
+def serving_case(grid, tol, seed):
+    """One serving request: the 100x100x20 generator (log-k std 1.0,
+    correlation 10 cells, four injectors) on `grid` with its own seed."""
+    nx, ny, nz = grid
+    return cartesian(f"grid{nx}x{ny}x{nz}_s{seed}", nx, ny, nz, seed=seed, sigma=1.0, corr=10,
+                     n_wells=4, r_front=5.0, tol=tol)
+
+
 def small(nx, ny, nz, seed=7, sigma=0.5, n_wells=1, r_front=2.0, **kw):
     """Tiny grids for pins and parity at oracle-friendly sizes."""
     return cartesian(f"grid{nx}x{ny}x{nz}", nx, ny, nz, seed=seed, sigma=sigma, corr=0,
