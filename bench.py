@@ -183,6 +183,35 @@ def run_serving(args):
     print(json.dumps(out), flush=True)
 
 
+def run_cpr_comparison():
+    """FGMRES(50) iterations to 1e-6 with CPTR (elliptic set {p, T}) and CPR
+    (elliptic set {p}) on the 100x100x20 generator over the Peclet sweep, at the
+    configured time step (1 day) and at 30 days.  Prints one JSON line."""
+    import numpy as np
+    import torch
+    import paper_2308_11892_amd as L
+    from synth import jacobian as J
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    rows = []
+    for days in (1, 30):
+        for pe in (0.1, 10.0, 1000.0):
+            c = J.cartesian("grid100x100x20", 100, 100, 20, seed=J.SEED_BASE + 1, sigma=1.0, corr=10,
+                            n_wells=4, r_front=5.0, pe_target=pe, dt=86400.0 * days)
+            b = torch.tensor(c.b, device="cuda:0")
+            its = {}
+            for name, ell in (("cptr", (0, 1)), ("cpr", (0,))):
+                with L.Solver(c.row_ptr, c.col_idx, c.values, elliptic=ell) as s:
+                    x = torch.zeros_like(b)
+                    info = s.gmres_solve(b, x, restart=50, flexible=True, rtol=1e-6)
+                    its[name] = info["iterations"] if info["converged"] else None
+            log(f"dt {days} d, Pe {pe:g}: CPTR {its['cptr']} CPR {its['cpr']}")
+            rows.append({"dt_days": days, "peclet": pe, "kappa": c.meta["kappa"], **its})
+    print(json.dumps({"metric": "FGMRES(50) iterations to 1e-6, CPTR vs CPR", "unit": "iterations",
+                      "higher_is_better": False, "data": "synthetic",
+                      "config": {"workload": "grid100x100x20 Peclet sweep"}, "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,6 +231,9 @@ def main():
                          "of four grid sizes arriving as a Poisson stream, solved by the "
                          "solve server with the mixed-precision preconditioner")
     ap.add_argument("--rate", type=float, default=20.0, help="serving: mean arrivals per second")
+    ap.add_argument("--compare-cpr", action="store_true",
+                    help="instead of the solve benchmark, compare CPTR with CPR (elliptic set {p}) "
+                         "on the 100x100x20 Peclet sweep at time steps of 1 and 30 days")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -210,6 +242,9 @@ def main():
 
     if args.serve:
         run_serving(args)
+        return
+    if args.compare_cpr:
+        run_cpr_comparison()
         return
 
     import numpy as np

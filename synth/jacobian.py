@@ -233,8 +233,9 @@ def _face_blocks(F, a_up, up, tf, kf, z, T):
 
 
 def cartesian(name, nx, ny, nz, *, seed, sigma, corr, n_wells, r_front,
-              kappa=KAPPA0, pe_target=None, tol=1e-6, rhs=True):
-    """Assemble the thermal TPFA Jacobian on an nx*ny*nz grid (x fastest)."""
+              kappa=KAPPA0, pe_target=None, tol=1e-6, rhs=True, dt=DT):
+    """Assemble the thermal TPFA Jacobian on an nx*ny*nz grid (x fastest).
+    `dt` is the time step dividing the accumulation terms."""
     rng = np.random.default_rng(seed)
     nc = nx * ny * nz
     g = _gauss_field(rng, (nz, ny, nx), corr)
@@ -255,9 +256,9 @@ def cartesian(name, nx, ny, nz, *, seed, sigma, corr, n_wells, r_front,
     has7 = np.zeros((nc, 7), dtype=bool)
     has7[:, 3] = True
     vol = DX * DY * DZ
-    val7[:, 3, 0, 0] += vol * PORO * CT / DT
-    val7[:, 3, 1, 1] += vol * (PORO * CF + (1.0 - PORO) * CR) / DT
-    val7[:, 3, 2, 2] += vol * PORO / DT
+    val7[:, 3, 0, 0] += vol * PORO * CT / dt
+    val7[:, 3, 1, 1] += vol * (PORO * CF + (1.0 - PORO) * CR) / dt
+    val7[:, 3, 2, 2] += vol * PORO / dt
 
     for F, (d, a, b, area, dist) in zip(fluxes, faces):
         ka, kb = perm[a], perm[b]
@@ -293,9 +294,9 @@ def cartesian(name, nx, ny, nz, *, seed, sigma, corr, n_wells, r_front,
 
     # Column scaling (p in MPa) and row scaling by the mean accumulation diagonal.
     val7[:, :, :, 0] *= P_SCALE
-    acc = np.array([vol * PORO * CT / DT * P_SCALE,
-                    vol * (PORO * CF + (1.0 - PORO) * CR) / DT,
-                    vol * PORO / DT])
+    acc = np.array([vol * PORO * CT / dt * P_SCALE,
+                    vol * (PORO * CF + (1.0 - PORO) * CR) / dt,
+                    vol * PORO / dt])
     val7 /= acc[None, None, :, None]
 
     offs = np.array([-nx * ny, -nx, -1, 0, 1, nx, nx * ny], dtype=np.int64)
@@ -310,7 +311,7 @@ def cartesian(name, nx, ny, nz, *, seed, sigma, corr, n_wells, r_front,
                 n_wells=n_wells, r_front=r_front, kappa=kappa, peclet=pe,
                 peclet_at_kappa0=pe0, pe_target=pe_target, tol=tol,
                 dx=[DX, DY, DZ], porosity=PORO, ct=CT, mu_c=MU_C, cf=CF, cr=CR,
-                dt=DT, row_scale=acc.tolist(), p_scale=P_SCALE,
+                dt=dt, row_scale=acc.tolist(), p_scale=P_SCALE,
                 n_cells=nc, nnzb=int(col_idx.shape[0]))
     if rhs:
         xs = np.random.default_rng(seed + 1000).standard_normal(BLOCK * nc)
