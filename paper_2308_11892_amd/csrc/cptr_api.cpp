@@ -285,8 +285,10 @@ int upload_sell(cptr_solver s, SellT<T>& d, const HostSell& h, hipStream_t st) {
   return CPTR_OK;
 }
 
+// lanes per row of the scalar CSR kernels: about four nonzeros per lane, so
+// each lane keeps several independent index/value/gather loads in flight
 int pick_group(int64_t nnz, int32_t n) {
-  const double avg = n > 0 ? (double)nnz / n : 1.0;
+  const double avg = n > 0 ? (double)nnz / n / 4.0 : 1.0;
   int g = 1;
   while (g < 32 && g < avg) g <<= 1;
   return g;

@@ -178,6 +178,7 @@ __global__ __launch_bounds__(kBlock) void k_csr(int n, const int32_t* __restrict
   const bool live = row < n;
   T acc = 0;
   if (live) {
+#pragma unroll 4
     for (int k = rp[row] + sub; k < rp[row + 1]; k += G) {
       const int c = ci[k];
       T xv = OP == kResidJacobi ? (T)0 : x[c];
