@@ -132,7 +132,8 @@ def run_serving(args):
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     cells = [c.n_cells for c in cases]
     log(f"serving: {sum(cells)} cells in total; starting the server")
-    sv = L.Server(max_inflight=4, setup_workers=4, setup_threads=4, hbm_budget_bytes=64 << 30)
+    sv = L.Server(max_inflight=args.slots, setup_workers=args.setup_workers,
+                  setup_threads=args.setup_threads, hbm_budget_bytes=64 << 30)
     ids = [None] * len(stream)
     t0 = time.perf_counter()
 
@@ -178,7 +179,8 @@ def run_serving(args):
         "higher_is_better": True, "dtype": "f32 preconditioner, f64 Krylov", "data": "synthetic",
         "config": {"workload": f"serving: {len(res)} Poisson arrivals at {args.rate:g}/s, grids "
                                "40x40x10/80x80x20/160x160x20/200x200x40, tol 1e-4 or 1e-6, FGMRES(50)",
-                   "slots": 4, "setup_workers": 4, "setup_threads": 4},
+                   "slots": args.slots, "setup_workers": args.setup_workers,
+                   "setup_threads": args.setup_threads},
     }
     print(json.dumps(out), flush=True)
 
@@ -231,6 +233,10 @@ def main():
                          "of four grid sizes arriving as a Poisson stream, solved by the "
                          "solve server with the mixed-precision preconditioner")
     ap.add_argument("--rate", type=float, default=20.0, help="serving: mean arrivals per second")
+    ap.add_argument("--slots", type=int, default=4, help="serving: requests on the GPU at once")
+    ap.add_argument("--setup-workers", type=int, default=16, help="serving: concurrent host setups")
+    ap.add_argument("--setup-threads", type=int, default=0,
+                    help="serving: threads per host setup (0: sized per request, 1 to 4)")
     ap.add_argument("--compare-cpr", action="store_true",
                     help="instead of the solve benchmark, compare CPTR with CPR (elliptic set {p}) "
                          "on the 100x100x20 Peclet sweep at time steps of 1 and 30 days")

@@ -16,8 +16,9 @@
  * every kernel is deterministic and a request only touches its own memory.
  *
  * Threads: `setup_workers` host threads run host setups (each with
- * `setup.setup_threads` threads of its own); `max_inflight` slot threads each
- * own one non-blocking HIP stream.  The server's functions are thread-safe.
+ * `setup.setup_threads` threads of its own, or a number sized to the request
+ * when that is 0); `max_inflight` slot threads each own one non-blocking HIP
+ * stream.  The server's functions are thread-safe.
  */
 #ifndef CPTR_SERVE_H
 #define CPTR_SERVE_H
@@ -34,11 +35,12 @@ typedef struct cptr_server_s* cptr_server;
 
 typedef struct {
   int32_t max_inflight;      /* slots: requests on the GPU at once (default 4, 1..64) */
-  int32_t setup_workers;     /* concurrent host setups (default 2, 1..64) */
+  int32_t setup_workers;     /* concurrent host setups (default 8, 1..64) */
   int64_t hbm_budget_bytes;  /* device bytes for all admitted requests (default 16 GiB) */
   int32_t device;            /* HIP device ordinal (default 0) */
   cptr_setup_opts setup;     /* setup options of every request (default cptr_setup_opts_default,
-                                with precond_precision = CPTR_PRECISION_FP32) */
+                                with precond_precision = CPTR_PRECISION_FP32 and setup_threads = 0:
+                                per request, one thread per 400k block rows, 1 to 4) */
 } cptr_server_opts;
 
 typedef struct {

@@ -304,7 +304,7 @@ class Server:
     """Handle around cptr_server_*: queues solve requests, admits them to the
     GPU by HBM footprint as slots free up, and returns their solutions."""
 
-    def __init__(self, max_inflight=4, setup_workers=2, hbm_budget_bytes=16 << 30, device=0,
+    def __init__(self, max_inflight=4, setup_workers=8, hbm_budget_bytes=16 << 30, device=0,
                  **setup):
         self._h = None
         o = cptr_server_opts()

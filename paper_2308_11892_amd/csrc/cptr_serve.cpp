@@ -97,8 +97,12 @@ void setup_worker(cptr_server sv) {
       r->t_setup0 = now_s();
     }
     const cptr_bsr A{r->nb, r->nnzb, r->rp.data(), r->ci.data(), r->v.data(), 0};
+    cptr_setup_opts so = sv->o.setup;
+    // automatic: most of a host setup is sequential, so small requests get one
+    // thread and large ones up to four (one per 400k block rows)
+    if (so.setup_threads <= 0) so.setup_threads = std::min(4, 1 + r->nb / 400000);
     cptr_solver h = nullptr;
-    int rc = cptr::setup_host(&A, 3, r->eidx, r->ne, &sv->o.setup, &h);
+    int rc = cptr::setup_host(&A, 3, r->eidx, r->ne, &so, &h);
     std::string err = rc ? cptr::last_error(nullptr) : "";
     int64_t bytes = 0;
     const int m = r->so.restart;
@@ -265,11 +269,12 @@ void cptr_server_opts_default(cptr_server_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));
   o->max_inflight = 4;
-  o->setup_workers = 2;
+  o->setup_workers = 8;
   o->hbm_budget_bytes = (int64_t)16 << 30;
   o->device = 0;
   cptr_setup_opts_default(&o->setup);
   o->setup.precond_precision = CPTR_PRECISION_FP32;
+  o->setup.setup_threads = 0;
 }
 
 cptr_status cptr_server_create(const cptr_server_opts* o_in, cptr_server* out) {

@@ -31,7 +31,8 @@ def test_server_rejects_bad_options(kw):
 def test_server_defaults():
     o = L.cptr_server_opts()
     L.lib().cptr_server_opts_default(o)
-    assert (o.max_inflight, o.setup_workers, o.device) == (4, 2, 0)
+    assert (o.max_inflight, o.setup_workers, o.device) == (4, 8, 0)
+    assert o.setup.setup_threads == 0  # sized per request
     assert o.hbm_budget_bytes == 16 << 30
     # requests run with the mixed-precision preconditioner by default
     assert o.setup.precond_precision == L.PRECISION_FP32 and o.setup.agg_levels == 1
