@@ -266,7 +266,10 @@ int upload_as(cptr_solver s, T*& p, const double* src, int64_t count, hipStream_
     return upload(s, p, src, count, st);
   } else {
     if (s->measure) return dalloc(s, p, count);
-    std::vector<T> tmp(src, src + count);
+    std::vector<T> tmp((size_t)count);
+    parallel_ranges(count, s->threads, [&](int64_t lo, int64_t hi) {
+      for (int64_t q = lo; q < hi; ++q) tmp[(size_t)q] = (T)src[q];
+    });
     return upload(s, p, tmp.data(), count, st);
   }
 }
@@ -353,7 +356,8 @@ int build_grid_factors(cptr_solver s, PrecDev<T>& d, hipStream_t st) {
       return rc;
     return CPTR_OK;
   }
-  std::vector<double> lt((size_t)rows * 27 * 64, 0.0), ut((size_t)rows * 36 * 64, 0.0);
+  // packed straight in T (no FP64 staging copy in the mixed-precision form)
+  std::vector<T> lt((size_t)rows * 27 * 64, T(0)), ut((size_t)rows * 36 * 64, T(0));
   // every cell owns its own lane of its own rows: the cells split freely
   parallel_ranges(h.nb, s->threads, [&](int64_t c0, int64_t c1) {
   for (int32_t c = (int32_t)c0; c < (int32_t)c1; ++c) {
@@ -365,7 +369,7 @@ int build_grid_factors(cptr_solver s, PrecDev<T>& d, hipStream_t st) {
       const int32_t d = h.ci[q] - c;
       const double* blk = &h.ilu[(size_t)q * 9];
       int slot;
-      double* dst;
+      T* dst;
       int nv;
       int64_t row;
       if (d == -1 || d == -nx || d == -nxy) {
@@ -381,13 +385,13 @@ int build_grid_factors(cptr_solver s, PrecDev<T>& d, hipStream_t st) {
       } else {
         continue;
       }
-      for (int e = 0; e < 9; ++e) dst[((size_t)row * nv + 9 * slot + e) * 64 + lane] = blk[e];
+      for (int e = 0; e < 9; ++e) dst[((size_t)row * nv + 9 * slot + e) * 64 + lane] = (T)blk[e];
     }
-    for (int e = 0; e < 9; ++e) ut[((size_t)br * 36 + 27 + e) * 64 + lane] = h.uinv[(size_t)c * 9 + e];
+    for (int e = 0; e < 9; ++e) ut[((size_t)br * 36 + 27 + e) * 64 + lane] = (T)h.uinv[(size_t)c * 9 + e];
   }
   });
-  if ((rc = upload_as(s, d.Lg, lt.data(), (int64_t)lt.size(), st))) return rc;
-  if ((rc = upload_as(s, d.Ug, ut.data(), (int64_t)ut.size(), st))) return rc;
+  if ((rc = upload(s, d.Lg, lt.data(), (int64_t)lt.size(), st))) return rc;
+  if ((rc = upload(s, d.Ug, ut.data(), (int64_t)ut.size(), st))) return rc;
   // padding slots of the tile vectors stay zero forever (no kernel writes them)
   if ((rc = dalloc(s, d.ytile, rows * 3 * 64))) return rc;
   if ((rc = dalloc(s, d.r2tile, rows * 3 * 64))) return rc;

@@ -104,3 +104,25 @@ def test_fp32_fgmres_reaches_tolerance(name, restart):
     # both solutions have residual <= tol; their difference is bounded by the
     # error that residual allows (measured well below 1e-3 on these systems)
     assert dx <= 1e-3
+
+
+@pytest.mark.parametrize("name", ["grid20x20x5", "prism2000x5"])
+def test_fp32_cpr_against_oracle(name):
+    """The FP32 preconditioner with one elliptic unknown (CPR): one application
+    against the FP64 oracle's CPR, and FGMRES to tolerance."""
+    c = J.by_name(name)
+    h = O.Cptr(c.row_ptr, c.col_idx, c.values, elliptic=(0,))
+    r = np.random.default_rng(8).standard_normal(c.n_dof)
+    zo = h.apply(r)
+    with L.Solver(c.row_ptr, c.col_idx, c.values, elliptic=(0,), **FP32) as s:
+        z = torch.empty(c.n_dof, dtype=torch.float64, device=DEV)
+        s.apply(dev(r), z)
+        err = np.linalg.norm(host(z) - zo) / np.linalg.norm(zo)
+        x = torch.zeros(c.n_dof, dtype=torch.float64, device=DEV)
+        info = s.gmres_solve(dev(c.b), x, restart=30, flexible=True, rtol=1e-8)
+        xg = host(x)
+    _, io = h.gmres(c.b, restart=30, flexible=True, rtol=1e-8)
+    rel = np.linalg.norm(c.b - J.bsr_matvec_plain(c.row_ptr, c.col_idx, c.values, xg)) / np.linalg.norm(c.b)
+    say(f"[fp32 cpr] {name}: apply {err:.2e}; {info['iterations']} it (oracle {io['iterations']}), rel res {rel:.2e}")
+    assert err <= 1e-3
+    assert info["converged"] and rel <= 1e-8 and info["iterations"] <= io["iterations"] + 2

@@ -23,6 +23,8 @@ DEV = "cuda:0"
 # (workload, tolerance): the serving mix at oracle-friendly sizes
 MIX = [("grid12x10x4", 1e-6), ("grid20x20x5", 1e-4), ("grid30x20x6", 1e-6), ("prism300x4", 1e-6),
        ("grid16x16x8", 1e-4), ("grid20x20x5", 1e-6)]
+# the elliptic set of each request: CPTR ({p, T}) except one CPR request ({p})
+ELL = [(0, 1), (0, 1), (0, 1), (0, 1), (0,), (0, 1)]
 SOLVE = dict(restart=30, flexible=True, max_iter=200)
 
 
@@ -39,8 +41,8 @@ def _rel_res(c, x):
     return np.linalg.norm(c.b - J.bsr_matvec_plain(c.row_ptr, c.col_idx, c.values, x)) / np.linalg.norm(c.b)
 
 
-def _direct(c, tol):
-    with L.Solver(c.row_ptr, c.col_idx, c.values, precond_precision=L.PRECISION_FP32) as s:
+def _direct(c, tol, ell=(0, 1)):
+    with L.Solver(c.row_ptr, c.col_idx, c.values, elliptic=ell, precond_precision=L.PRECISION_FP32) as s:
         b = torch.tensor(c.b, device=DEV)
         x = torch.zeros_like(b)
         info = s.gmres_solve(b, x, rtol=tol, **SOLVE)
@@ -50,17 +52,19 @@ def _direct(c, tol):
 
 def test_same_result_alone_in_the_mix_and_direct(cases):
     say("[serve] direct solves")
-    direct = [_direct(cases[n], tol) for n, tol in MIX]
+    direct = [_direct(cases[n], tol, ell) for (n, tol), ell in zip(MIX, ELL)]
     say("[serve] one slot, one request at a time")
     alone = []
     with L.Server(max_inflight=1, setup_workers=1, hbm_budget_bytes=2 << 30) as sv:
-        for n, tol in MIX:
+        for (n, tol), ell in zip(MIX, ELL):
             c = cases[n]
-            alone.append(sv.wait(sv.submit(c.row_ptr, c.col_idx, c.values, c.b, rtol=tol, **SOLVE)))
+            alone.append(sv.wait(sv.submit(c.row_ptr, c.col_idx, c.values, c.b, elliptic=ell, rtol=tol,
+                                           **SOLVE)))
     say("[serve] four slots, all submitted at once")
     with L.Server(max_inflight=4, setup_workers=3, hbm_budget_bytes=2 << 30) as sv:
-        ids = [sv.submit(cases[n].row_ptr, cases[n].col_idx, cases[n].values, cases[n].b, rtol=tol, **SOLVE)
-               for n, tol in MIX]
+        ids = [sv.submit(cases[n].row_ptr, cases[n].col_idx, cases[n].values, cases[n].b, elliptic=ell,
+                         rtol=tol, **SOLVE)
+               for (n, tol), ell in zip(MIX, ELL)]
         mix = [sv.wait(i) for i in ids]
         st = sv.stats()
     say(f"[serve] stats {st}")
