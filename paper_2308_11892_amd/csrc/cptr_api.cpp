@@ -152,6 +152,7 @@ struct cptr_solver_s {
   int sf_width = 0;          // register slots of the one-launch sweeps; 0 = per-level launches
   int grid[3] = {0, 0, 0};   // nx, ny, nz when A is a 7-point stencil in lexicographic order
   bool use_grid = false;     // tiled systolic sweeps on that grid
+  bool device_ilu = false;   // ILU(0) factored on the device (grid sweeps; no host factors)
   int* tickets = nullptr;    // [2] workgroup ticket counters of the one-launch sweeps
   double* coarse_lu = nullptr;
   int32_t* coarse_piv = nullptr;
@@ -313,13 +314,13 @@ int upload_csr(cptr_solver s, DCsrT<T>& d, const Csr& h, hipStream_t st) {
 }
 
 // Is A's block pattern exactly the 7-point stencil of an nx*ny*nz grid in
-// lexicographic order (x fastest)?  Requires nx, ny, nz >= 2.
-bool detect_grid(const HostSetup& h, int dims[3]) {
-  const int32_t nb = h.nb;
-  if (h.rp[1] - h.rp[0] != 4) return false;  // corner cell: itself, +x, +y, +z
-  const int32_t nx = h.ci[h.rp[0] + 1] == 1 ? h.ci[h.rp[0] + 2] : 0;
-  const int32_t nxy = h.ci[h.rp[0] + 3];
-  if (h.ci[h.rp[0]] != 0 || h.ci[h.rp[0] + 1] != 1 || nx < 2 || nxy % nx != 0 || nxy / nx < 2) return false;
+// lexicographic order (x fastest)?  Requires nx, ny, nz >= 2.  (rp, ci:
+// a validated pattern with sorted rows.)
+bool detect_grid(int32_t nb, const int32_t* rp, const int32_t* ci, int dims[3]) {
+  if (rp[1] - rp[0] != 4) return false;  // corner cell: itself, +x, +y, +z
+  const int32_t nx = ci[rp[0] + 1] == 1 ? ci[rp[0] + 2] : 0;
+  const int32_t nxy = ci[rp[0] + 3];
+  if (ci[rp[0]] != 0 || ci[rp[0] + 1] != 1 || nx < 2 || nxy % nx != 0 || nxy / nx < 2) return false;
   if (nb % nxy != 0 || nb / nxy < 2) return false;
   const int32_t ny = nxy / nx, nz = nb / nxy;
   for (int32_t c = 0; c < nb; ++c) {
@@ -332,18 +333,59 @@ bool detect_grid(const HostSetup& h, int dims[3]) {
     if (x < nx - 1) want[m++] = c + 1;
     if (yy < ny - 1) want[m++] = c + nx;
     if (zz < nz - 1) want[m++] = c + nxy;
-    if (h.rp[c + 1] - h.rp[c] != m) return false;
+    if (rp[c + 1] - rp[c] != m) return false;
     for (int q = 0; q < m; ++q)
-      if (h.ci[h.rp[c] + q] != want[q]) return false;
+      if (ci[rp[c] + q] != want[q]) return false;
   }
   dims[0] = nx;
   dims[1] = ny;
   dims[2] = nz;
   return true;
 }
+bool detect_grid(const HostSetup& h, int dims[3]) { return detect_grid(h.nb, h.rp.data(), h.ci.data(), dims); }
+
+// The grid factors computed on the device from A (see launch_grid_ilu_diag):
+// U_cc^-1 level by level into a temporary FP64 array, then the tile layouts.
+template <class T>
+int build_grid_factors_device(cptr_solver s, PrecDev<T>& d, hipStream_t st) {
+  const int nx = s->grid[0], ny = s->grid[1], nz = s->grid[2];
+  const int64_t rows = grid_ntiles(ny, nz) * grid_nsteps(nx);
+  const int32_t nb = s->host.nb;
+  double* uinv = nullptr;
+  int* bad = nullptr;
+  int rc;
+  if ((rc = dalloc(s, d.Lg, rows * 27 * 64)) || (rc = dalloc(s, d.Ug, rows * 36 * 64)) ||
+      (rc = dalloc(s, d.ytile, rows * 3 * 64)) || (rc = dalloc(s, d.r2tile, rows * 3 * 64)) ||
+      (rc = dalloc(s, d.e0tile, rows * 2 * 64)) || (rc = dalloc(s, d.faces, 2 * grid_face_values(nx, ny, nz))) ||
+      (rc = dalloc(s, uinv, (int64_t)nb * 9)) || (rc = dalloc(s, bad, 1)))
+    return rc;
+  if (s->measure) return CPTR_OK;
+  HIP_TRY(s, hipMemset(d.Lg, 0, sizeof(T) * (size_t)rows * 27 * 64));
+  HIP_TRY(s, hipMemset(d.Ug, 0, sizeof(T) * (size_t)rows * 36 * 64));
+  HIP_TRY(s, hipMemset(d.ytile, 0, sizeof(T) * (size_t)rows * 3 * 64));
+  HIP_TRY(s, hipMemset(d.r2tile, 0, sizeof(T) * (size_t)rows * 3 * 64));
+  HIP_TRY(s, hipMemset(d.e0tile, 0, sizeof(T) * (size_t)rows * 2 * 64));
+  const int none = INT32_MAX;
+  HIP_TRY(s, hipMemcpy(bad, &none, sizeof(int), hipMemcpyHostToDevice));
+  for (size_t l = 0; l + 1 < s->flev_ptr.size(); ++l)
+    launch_grid_ilu_diag(s->A, s->fperm, s->flev_ptr[l], s->flev_ptr[l + 1], nx, nx * ny, uinv, bad, st);
+  launch_grid_ilu_pack(s->A, nx, ny, uinv, d.Lg, d.Ug, st);
+  HIP_TRY(s, hipGetLastError());
+  int first_bad = none;
+  HIP_TRY(s, hipMemcpyAsync(&first_bad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(s, hipStreamSynchronize(st));
+  // the temporaries go back; the handle's counted footprint keeps them (peak)
+  dfree(s, uinv);
+  dfree(s, bad);
+  if (first_bad != none)
+    return fail(s, CPTR_E_ZERO_PIVOT,
+                "zero ILU(0) pivot (singular diagonal block) in block row " + std::to_string(first_bad));
+  return CPTR_OK;
+}
 
 template <class T>
 int build_grid_factors(cptr_solver s, PrecDev<T>& d, hipStream_t st) {
+  if (s->device_ilu) return build_grid_factors_device(s, d, st);
   const HostSetup& h = s->host;
   const int nx = s->grid[0], ny = s->grid[1], nz = s->grid[2];
   const int32_t nxy = nx * ny;
@@ -874,6 +916,12 @@ int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_id
   int rc = validate_bsr(nb, nnzb, prp, pci, pv, err);
   if (rc) return (cptr_status)fail(nullptr, rc, err);
   SetupParams prm;
+  // a device handle on a 7-point grid (grid sweeps) factors ILU(0) on the device
+  int gdims[3] = {0, 0, 0};
+  const bool dev_ilu = !o.host_only &&
+                       (o.ilu_sweep == CPTR_ILU_SWEEP_AUTO || o.ilu_sweep == CPTR_ILU_SWEEP_GRID) &&
+                       detect_grid(nb, prp, pci, gdims);
+  prm.skip_ilu = dev_ilu;
   prm.theta = o.strong_threshold;
   prm.max_row_sum = o.max_row_sum;
   prm.max_levels = o.max_levels;
@@ -897,6 +945,7 @@ int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_id
   s->N = (int64_t)nb * 3;
   s->ilu_mode = o.ilu_sweep;
   s->threads = prm.threads;
+  s->device_ilu = dev_ilu;
   s->prec = o.precond_precision;
   *out = s.release();
   return CPTR_OK;
@@ -1250,6 +1299,8 @@ cptr_status cptr_export(cptr_solver s, int32_t what, int32_t level, void* buf, i
       if (!has_p) break;
       return put(h.lev[level].dinv.data(), (int64_t)h.lev[level].dinv.size() * 8);
     case CPTR_EXPORT_ILU_VALS:
+      if (s->device_ilu)
+        return (cptr_status)fail(s, CPTR_E_STATE, "this handle factors ILU(0) on the device (grid sweeps)");
       return put(h.ilu.data(), (int64_t)h.ilu.size() * 8);
     case CPTR_EXPORT_SWEEP: {
       const int32_t mode = !s->device ? -1

@@ -862,31 +862,33 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
   }
 
   // ---- block ILU(0) on A's pattern, matrix ordering (Sec. 3.1) ----
-  h.ilu = h.av;
-  h.uinv.assign((size_t)nb * 9, 0.0);
-  for (int32_t i = 0; i < nb; ++i) {
-    const int32_t d = h.diag[i];
-    for (int32_t q = rp[i]; q < d; ++q) {
-      const int32_t c = ci[q];
-      double Lq[9];
-      mm3(&h.ilu[(size_t)q * 9], &h.uinv[(size_t)c * 9], Lq);
-      std::memcpy(&h.ilu[(size_t)q * 9], Lq, sizeof Lq);
-      // merge the U part of row c (columns > c) into row i's later blocks
-      int32_t t = q + 1;
-      for (int32_t u = h.diag[c] + 1; u < rp[c + 1]; ++u) {
-        const int32_t col = ci[u];
-        while (t < rp[i + 1] && ci[t] < col) ++t;
-        if (t == rp[i + 1]) break;
-        if (ci[t] != col) continue;
-        double prod[9];
-        mm3(Lq, &h.ilu[(size_t)u * 9], prod);
-        double* dst = &h.ilu[(size_t)t * 9];
-        for (int e = 0; e < 9; ++e) dst[e] -= prod[e];
+  if (!prm.skip_ilu) {
+    h.ilu = h.av;
+    h.uinv.assign((size_t)nb * 9, 0.0);
+    for (int32_t i = 0; i < nb; ++i) {
+      const int32_t d = h.diag[i];
+      for (int32_t q = rp[i]; q < d; ++q) {
+        const int32_t c = ci[q];
+        double Lq[9];
+        mm3(&h.ilu[(size_t)q * 9], &h.uinv[(size_t)c * 9], Lq);
+        std::memcpy(&h.ilu[(size_t)q * 9], Lq, sizeof Lq);
+        // merge the U part of row c (columns > c) into row i's later blocks
+        int32_t t = q + 1;
+        for (int32_t u = h.diag[c] + 1; u < rp[c + 1]; ++u) {
+          const int32_t col = ci[u];
+          while (t < rp[i + 1] && ci[t] < col) ++t;
+          if (t == rp[i + 1]) break;
+          if (ci[t] != col) continue;
+          double prod[9];
+          mm3(Lq, &h.ilu[(size_t)u * 9], prod);
+          double* dst = &h.ilu[(size_t)t * 9];
+          for (int e = 0; e < 9; ++e) dst[e] -= prod[e];
+        }
       }
+      if (!inv3(&h.ilu[(size_t)d * 9], &h.uinv[(size_t)i * 9]))
+        return err = "zero ILU(0) pivot (singular diagonal block) in block row " + std::to_string(i),
+               CPTR_E_ZERO_PIVOT;
     }
-    if (!inv3(&h.ilu[(size_t)d * 9], &h.uinv[(size_t)i * 9]))
-      return err = "zero ILU(0) pivot (singular diagonal block) in block row " + std::to_string(i),
-             CPTR_E_ZERO_PIVOT;
   }
   // ---- dependency levels of the two triangular sweeps ----
   h.fwd_level.assign(nb, 0);

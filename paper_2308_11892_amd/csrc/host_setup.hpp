@@ -42,6 +42,7 @@ struct SetupParams {
   bool quasi_impes = true;
   int threads = 1;
   int max_dense_coarse = 4096;  // largest coarsest level solved by dense LU
+  bool skip_ilu = false;        // ILU(0) is factored elsewhere (on the device, 7-point grids)
 };
 
 struct HostSetup {
@@ -57,7 +58,7 @@ struct HostSetup {
   std::vector<double> coarse_lu;  // dense LU of the coarsest matrix, row-major
   std::vector<int32_t> coarse_piv;
   std::vector<double> ilu;     // [nnzb][3][3]: L blocks left of the diagonal, U on/right
-  std::vector<double> uinv;    // [nb][3][3] inverse of each U_ii
+  std::vector<double> uinv;    // [nb][3][3] inverse of each U_ii (both empty with skip_ilu)
   std::vector<int32_t> fwd_level, bwd_level;  // dependency level of each row
   int32_t n_fwd_levels = 0, n_bwd_levels = 0;
 };

@@ -1412,6 +1412,153 @@ void launch_stage2_grid(int nx, int ny, int nz, const Sell& A, int ne, const int
                                               e0, r, r2t, e0t, faces, nfaces, tickets);
 }
 
+// --------------------------------------------------------------------------
+// Block ILU(0) of a 7-point stencil in lexicographic order (Sec. 3.1).  On this
+// pattern the elimination has no fill and touches only diagonal blocks: a lower
+// neighbour k of cell c (c - nx*ny, c - nx, c - 1) contributes L_ck = A_ck
+// U_kk^-1 and U_cc = A_cc - sum_k L_ck A_kc (k in increasing column order), the
+// blocks right of the diagonal are A's own.
+__device__ __forceinline__ void mm3_dev(const double* a, const double* b, double* c) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) s += a[r * 3 + q] * b[q * 3 + k];
+      c[r * 3 + k] = s;
+    }
+}
+// 3x3 inverse by Gauss-Jordan with partial pivoting; false for a zero pivot
+__device__ __forceinline__ bool inv3_dev(const double* m, double* out) {
+  double a[3][6];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) a[r][c] = c < 3 ? m[r * 3 + c] : (c - 3 == r ? 1.0 : 0.0);
+  for (int k = 0; k < 3; ++k) {
+    int p = k;
+    for (int r = k + 1; r < 3; ++r)
+      if (fabs(a[r][k]) > fabs(a[p][k])) p = r;
+    if (a[p][k] == 0.0) return false;
+    if (p != k)
+      for (int c = 0; c < 6; ++c) {
+        const double t = a[k][c];
+        a[k][c] = a[p][c];
+        a[p][c] = t;
+      }
+    const double d = a[k][k];
+    for (int c = 0; c < 6; ++c) a[k][c] /= d;
+    for (int r = 0; r < 3; ++r)
+      if (r != k) {
+        const double f = a[r][k];
+        for (int c = 0; c < 6; ++c) a[r][c] -= f * a[k][c];
+      }
+  }
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) out[r * 3 + c] = a[r][c + 3];
+  return true;
+}
+// block (9 values) of A's row r at column c, or zeros when absent
+__device__ __forceinline__ void sell_block(const int32_t* __restrict__ sptr, const int32_t* __restrict__ col,
+                                           const double* __restrict__ val, int r, int c, double* out) {
+  const int s = r >> 6, lane = r & 63;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) out[e] = 0.0;
+  for (int k = sptr[s]; k < sptr[s + 1]; ++k)
+    if (col[(size_t)k * 64 + lane] == c) {
+#pragma unroll
+      for (int e = 0; e < 9; ++e) out[e] = val[((size_t)k * 9 + e) * 64 + lane];
+      return;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_grid_ilu_diag(int p0, int p1, const int32_t* __restrict__ perm,
+                                                          const int32_t* __restrict__ sptr,
+                                                          const int32_t* __restrict__ col,
+                                                          const double* __restrict__ val, int nx, int nxy,
+                                                          double* __restrict__ uinv, int* bad) {
+  const int p = p0 + blockIdx.x * kBlock + threadIdx.x;
+  if (p >= p1) return;
+  const int c = perm[p];
+  double D[9];
+  sell_block(sptr, col, val, c, c, D);
+  const int lower[3] = {c - nxy, c - nx, c - 1};  // increasing column order
+  for (int q = 0; q < 3; ++q) {
+    const int k = lower[q];
+    double Ack[9], Akc[9], Lq[9], prod[9];
+    sell_block(sptr, col, val, c, k, Ack);
+    bool present = false;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) present |= Ack[e] != 0.0;
+    if (k < 0 || !present) continue;
+    mm3_dev(Ack, uinv + (size_t)k * 9, Lq);
+    sell_block(sptr, col, val, k, c, Akc);
+    mm3_dev(Lq, Akc, prod);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) D[e] -= prod[e];
+  }
+  double inv[9];
+  if (!inv3_dev(D, inv)) {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) inv[e] = 0.0;
+    atomicMin(bad, c);
+  }
+#pragma unroll
+  for (int e = 0; e < 9; ++e) uinv[(size_t)c * 9 + e] = inv[e];
+}
+
+// tile layouts of the grid sweeps: L_ck = A_ck U_kk^-1 (forward, slots -x, -y,
+// -z), A_ck (backward, slots +x, +y, +z) and U_cc^-1 (backward, values 27..35)
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_grid_ilu_pack(int nb, int nx, int ny, const int32_t* __restrict__ sptr,
+                                                          const int32_t* __restrict__ col,
+                                                          const double* __restrict__ val,
+                                                          const double* __restrict__ uinv, T* __restrict__ Lt,
+                                                          T* __restrict__ Ut) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= nb) return;
+  const int nxy = nx * ny;
+  const int i = c % nx, j = (c / nx) % ny, k = c / nxy;
+  int64_t fr, br;
+  int lane;
+  grid_tile_slot(nx, ny, i, j, k, fr, br, lane);
+  const int s = c >> 6, sl = c & 63;
+  for (int q = sptr[s]; q < sptr[s + 1]; ++q) {
+    const int cc = col[(size_t)q * 64 + sl];
+    const int d = cc - c;
+    double blk[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) blk[e] = val[((size_t)q * 9 + e) * 64 + sl];
+    if (d == -1 || d == -nx || d == -nxy) {
+      const int slot = d == -1 ? 0 : d == -nx ? 1 : 2;
+      double Lq[9];
+      mm3_dev(blk, uinv + (size_t)cc * 9, Lq);
+#pragma unroll
+      for (int e = 0; e < 9; ++e) Lt[((size_t)fr * 27 + 9 * slot + e) * 64 + lane] = (T)Lq[e];
+    } else if (d == 1 || d == nx || d == nxy) {
+      const int slot = d == 1 ? 0 : d == nx ? 1 : 2;
+#pragma unroll
+      for (int e = 0; e < 9; ++e) Ut[((size_t)br * 36 + 9 * slot + e) * 64 + lane] = (T)blk[e];
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 9; ++e) Ut[((size_t)br * 36 + 27 + e) * 64 + lane] = (T)uinv[(size_t)c * 9 + e];
+}
+
+void launch_grid_ilu_diag(const Sell& A, const int32_t* fperm, int32_t p0, int32_t p1, int nx, int nxy,
+                          double* uinv, int* bad, hipStream_t st) {
+  if (p1 <= p0) return;
+  k_grid_ilu_diag<<<nblocks(p1 - p0, kBlock), kBlock, 0, st>>>(p0, p1, fperm, A.sptr, A.col, A.val, nx, nxy,
+                                                                  uinv, bad);
+}
+
+template <class T>
+void launch_grid_ilu_pack(const Sell& A, int nx, int ny, const double* uinv, T* Lt, T* Ut, hipStream_t st) {
+  k_grid_ilu_pack<T><<<nblocks(A.nrows, kBlock), kBlock, 0, st>>>(A.nrows, nx, ny, A.sptr, A.col, A.val, uinv,
+                                                                  Lt, Ut);
+}
+
 // workgroup: the sweeping wave and the staging waves; ring slots: as many as
 // fit in LDS (18 KB forward, 24 KB backward per slot in FP64; the FP32 slots
 // are half that).  The forward sweep keeps five steps in flight from HBM; the
@@ -1533,6 +1680,7 @@ void launch_update_host_coef(int64_t n, int nv, const double* V, int64_t ldv, co
   template void launch_prolong_e<T>(int32_t, int, const int32_t*, const T*, double*, hipStream_t);   \
   template void launch_stage2_grid<T>(int, int, int, const Sell&, int, const int32_t*, const T*,     \
                                       const double*, T*, T*, T*, int*, hipStream_t);                 \
+  template void launch_grid_ilu_pack<T>(const Sell&, int, int, const double*, T*, T*, hipStream_t);  \
   template void launch_ilu_fwd_grid<T>(int, int, int, const T*, const T*, T*, T*, int*, double*, long, \
                                        hipStream_t);                                                 \
   template void launch_ilu_bwd_grid<T>(int, int, int, const T*, T*, const T*, int, const int32_t*, T*, \

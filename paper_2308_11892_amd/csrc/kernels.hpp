@@ -88,12 +88,12 @@ void launch_stage2_resid_sf(const Sell& A, int ne, const int32_t* eidx, const T*
 // (27 values) and U + U_ii^-1 (36 values) in the tile layout of grid_tile_slot;
 // ytile: forward results in the backward sweep's tile layout.
 constexpr int kGridTJ = 16, kGridTK = 4;
-inline int grid_nsteps(int nx) { return nx + kGridTJ - 1 + kGridTK - 1; }
+__host__ __device__ inline int grid_nsteps(int nx) { return nx + kGridTJ - 1 + kGridTK - 1; }
 inline int64_t grid_ntiles(int ny, int nz) {
   return (int64_t)((ny + kGridTJ - 1) / kGridTJ) * ((nz + kGridTK - 1) / kGridTK);
 }
 // slot (in units of 64-lane rows) of cell (i, j, k) in the forward / backward layout
-inline void grid_tile_slot(int nx, int ny, int i, int j, int k, int64_t& fwd_row, int64_t& bwd_row,
+__host__ __device__ inline void grid_tile_slot(int nx, int ny, int i, int j, int k, int64_t& fwd_row, int64_t& bwd_row,
                            int& lane) {
   const int nJ = (ny + kGridTJ - 1) / kGridTJ;
   const int J = j / kGridTJ, jj = j % kGridTJ, K = k / kGridTK, kk = k % kGridTK;
@@ -108,6 +108,16 @@ inline void grid_tile_slot(int nx, int ny, int i, int j, int k, int64_t& fwd_row
 // faces: the face buffers of the two sweeps, grid_face_values() each
 // (forward first); the stage-two kernel fills both with the sentinel.
 int64_t grid_face_values(int nx, int ny, int nz);
+// Block ILU(0) of A on an nx*ny*nz 7-point grid, on the device.  One call per
+// forward dependency level (positions [p0, p1) of fperm): U_cc^-1 of the
+// level's cells into uinv (FP64, 9 per cell); a singular U_cc leaves zeros and
+// lowers *bad to the smallest such cell.  Then launch_grid_ilu_pack writes the
+// sweeps' tile layouts (Lt forward, Ut backward; cleared beforehand).
+void launch_grid_ilu_diag(const Sell& A, const int32_t* fperm, int32_t p0, int32_t p1, int nx, int nxy,
+                          double* uinv, int* bad, hipStream_t st);
+template <class T>
+void launch_grid_ilu_pack(const Sell& A, int nx, int ny, const double* uinv, T* Lt, T* Ut,
+                          hipStream_t st);
 template <class T>
 void launch_stage2_grid(int nx, int ny, int nz, const Sell& A, int ne, const int32_t* eidx, const T* e0,
                         const double* r, T* r2t, T* e0t, T* faces, int* tickets, hipStream_t st);

@@ -317,3 +317,29 @@ def test_cptr_against_cpr_on_the_peclet_sweep():
     say(f"[cpr] Pe 0.1/10/1000: CPTR {its['cptr']} CPR {its['cpr']}")
     assert all(a <= b for a, b in zip(its["cptr"], its["cpr"]))
     assert max(its["cptr"]) - min(its["cptr"]) <= 1
+
+
+def test_device_ilu_zero_pivot_matches_host():
+    """On 7-point grids a device handle factors ILU(0) on the GPU; a singular
+    diagonal block is reported like the host factorisation does (same row)."""
+    c = J.small(3, 3, 2)
+    v = c.values.copy()
+    k = [q for q in range(c.row_ptr[2], c.row_ptr[3]) if c.col_idx[q] == 2][0]
+    v[k, 2, 2] = 0.0
+    v[k, 0:2, 2] = 0.0
+    v[k, 2, 0:2] = 0.0
+    msgs = []
+    for host_only in (1, 0):
+        with pytest.raises(L.CptrError) as e:
+            L.Solver(c.row_ptr, c.col_idx, v, host_only=host_only, restriction=L.RESTRICT_INJECTION)
+        assert e.value.code == L.CPTR_E_ZERO_PIVOT
+        msgs.append(str(e.value))
+    assert "ILU" in msgs[1] and msgs[0] == msgs[1], msgs
+
+
+def test_device_ilu_export_refused_on_grids():
+    c = J.by_name("grid7x5x3")
+    with L.Solver(c.row_ptr, c.col_idx, c.values) as s:
+        with pytest.raises(L.CptrError) as e:
+            s.export("ILU_VALS", 0, c.nnzb * 9)
+        assert e.value.code == L.CPTR_E_STATE
