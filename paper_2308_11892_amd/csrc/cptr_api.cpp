@@ -937,6 +937,12 @@ int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_id
     return (cptr_status)fail(nullptr, CPTR_E_NOMEM, "host allocation failed during setup");
   }
   if (rc) return (cptr_status)fail(nullptr, rc, err);
+  if (A->on_device) {
+    // the host copy of A's values dies with this call: the handle keeps it
+    // until the device half has been built
+    s->host.av_owned = std::move(v);
+    s->host.av = s->host.av_owned.data();
+  }
   s->ne = n_elliptic;
   for (int e = 0; e < 3; ++e) {
     s->eidx_h[e] = s->host.eidx[e];
@@ -1006,6 +1012,12 @@ void release_device(cptr_solver s) {
 
 const char* last_error(cptr_solver s) { return s ? s->err.c_str() : g_setup_error.c_str(); }
 
+void drop_input(cptr_solver s) {
+  if (!s) return;
+  s->host.av = nullptr;
+  std::vector<double>().swap(s->host.av_owned);
+}
+
 int64_t device_bytes(cptr_solver s) { return s ? s->dev_bytes : 0; }
 
 }  // namespace cptr
@@ -1031,6 +1043,7 @@ cptr_status cptr_setup(const cptr_bsr* A, int32_t block_size, const int32_t* ell
       return (cptr_status)rc;
     }
   }
+  drop_input(s);  // A's values belong to the caller again
   s->setup_s = now_s() - t0;
   *out = s;
   return CPTR_OK;

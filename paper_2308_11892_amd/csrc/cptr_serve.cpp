@@ -117,9 +117,11 @@ void setup_worker(cptr_server sv) {
       err = "request needs " + std::to_string(bytes) + " bytes of HBM; the budget is " +
             std::to_string(sv->arena.size());
     }
+    // A's pattern is copied into the handle; its values are read in place
+    // until the device half is built
     std::vector<int32_t>().swap(r->rp);
     std::vector<int32_t>().swap(r->ci);
-    std::vector<double>().swap(r->v);
+    if (rc) std::vector<double>().swap(r->v);
     if (rc && h) {
       cptr_destroy(h);
       h = nullptr;
@@ -145,7 +147,7 @@ void setup_worker(cptr_server sv) {
 bool run_request(cptr_server sv, Request* r, hipStream_t st, int& rc) {
   const size_t n = 3 * (size_t)r->nb;
   rc = cptr::setup_device(r->h, &sv->arena, r->so.restart, r->so.flexible != 0, st);
-  if (rc == CPTR_E_NOMEM) return false;
+  if (rc == CPTR_E_NOMEM) return false;  // retried later: A's values stay
   double* bd = nullptr;
   double* xd = nullptr;
   const int64_t vec = (int64_t)cptr::DevArena::round(sizeof(double) * n);
@@ -165,6 +167,9 @@ bool run_request(cptr_server sv, Request* r, hipStream_t st, int& rc) {
       return false;
     }
   }
+  // the device half stays: the handle no longer reads A's values
+  cptr::drop_input(r->h);
+  std::vector<double>().swap(r->v);
   r->t_dev = now_s();
   if (!rc) {
     hipError_t e = hipMemcpyAsync(bd, r->b.data(), sizeof(double) * n, hipMemcpyHostToDevice, st);

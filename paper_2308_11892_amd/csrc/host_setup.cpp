@@ -737,7 +737,7 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
   const int64_t nnzb = rp[nb];
   h.rp.assign(rp, rp + nb + 1);
   h.ci.assign(ci, ci + nnzb);
-  h.av.assign(v, v + nnzb * 9);
+  h.av = v;  // read in place: no copy of the largest input
   h.diag.resize(nb);
   for (int32_t i = 0; i < nb; ++i)
     for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
@@ -863,7 +863,7 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
 
   // ---- block ILU(0) on A's pattern, matrix ordering (Sec. 3.1) ----
   if (!prm.skip_ilu) {
-    h.ilu = h.av;
+    h.ilu.assign(h.av, h.av + (size_t)nnzb * 9);
     h.uinv.assign((size_t)nb * 9, 0.0);
     for (int32_t i = 0; i < nb; ++i) {
       const int32_t d = h.diag[i];

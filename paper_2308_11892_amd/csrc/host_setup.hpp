@@ -50,7 +50,9 @@ struct HostSetup {
   int ne = 0, nh = 0;          // elliptic / hyperbolic unknowns per cell
   int eidx[kBS] = {0}, hidx[kBS] = {0};
   std::vector<int32_t> rp, ci; // validated copy of A's pattern
-  std::vector<double> av;      // A values [nnzb][3][3]
+  const double* av = nullptr;  // A values [nnzb][3][3]: the caller's array (or av_owned),
+                               // valid while the setup runs, cleared afterwards
+  std::vector<double> av_owned;  // A values when the caller's array does not outlive the setup
   std::vector<int32_t> diag;   // position of the diagonal block of each row
   std::vector<double> W;       // [nb][ne][nh]
   std::vector<double> ahat;    // [nnzb][ne][ne] reduced elliptic blocks on A's pattern

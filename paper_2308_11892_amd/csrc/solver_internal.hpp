@@ -15,7 +15,9 @@
 
 namespace cptr {
 
-// Host half.  On success *out is a handle with no device state.
+// Host half.  On success *out is a handle with no device state.  The handle
+// reads A's values in place until drop_input is called: the caller keeps them
+// alive until then (setup_device reads them).
 int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_idx, int32_t n_elliptic,
                const cptr_setup_opts* opts, cptr_solver* out);
 // Device bytes setup_device(s, arena, restart, flexible) allocates, counted in
@@ -27,6 +29,8 @@ int setup_device(cptr_solver s, DevArena* arena, int restart, bool flexible, hip
 // Frees the device half (back to the arena when there is one); the handle
 // returns to its host-only state.
 void release_device(cptr_solver s);
+// The handle stops reading A's values (call after the last setup_device).
+void drop_input(cptr_solver s);
 // Device bytes the handle holds now, in DevArena pieces.
 int64_t device_bytes(cptr_solver s);
 // Message of the last failure on the handle (or of the calling thread's setup).

@@ -343,3 +343,23 @@ def test_device_ilu_export_refused_on_grids():
         with pytest.raises(L.CptrError) as e:
             s.export("ILU_VALS", 0, c.nnzb * 9)
         assert e.value.code == L.CPTR_E_STATE
+
+
+@pytest.mark.parametrize("name", ["grid20x20x5", "prism2000x5"])
+def test_setup_from_device_arrays(name):
+    """A handed over in device memory (cptr_bsr.on_device = 1) gives the same
+    preconditioner, bit for bit, as the same matrix from host memory."""
+    c = J.by_name(name)
+    r = dev(np.random.default_rng(13).standard_normal(c.n_dof))
+    outs = []
+    for on_dev in (False, True):
+        if on_dev:
+            args = (torch.tensor(c.row_ptr, device=DEV), torch.tensor(c.col_idx, device=DEV),
+                    torch.tensor(c.values, device=DEV))
+        else:
+            args = (c.row_ptr, c.col_idx, c.values)
+        with L.Solver(*args) as s:
+            z = torch.empty_like(r)
+            s.apply(r, z)
+            outs.append(host(z))
+    assert np.array_equal(outs[0], outs[1])
