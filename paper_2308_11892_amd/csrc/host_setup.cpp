@@ -149,32 +149,67 @@ static Csr transpose(const Csr& a, int threads) {
 // unassigned strong dependency of the new C point loses 1.  Leftovers are F.
 // Selection uses a max segment tree keyed on (measure, -index).
 namespace {
-struct MaxTree {
-  int32_t size = 1;
-  std::vector<int64_t> key;    // measure, or -1 when not selectable
-  std::vector<int32_t> arg;    // index achieving the node's maximum
-  explicit MaxTree(int32_t n) {
-    while (size < n) size <<= 1;
-    key.assign(2 * size, -1);
-    arg.assign(2 * size, INT32_MAX);
-    for (int32_t i = 0; i < size; ++i) arg[size + i] = i;
+// Points keyed by a small non-negative integer measure; pick() returns the
+// largest key, ties to the smallest index.  Each key value holds its points in
+// a three-level bitset (64-way fan-out), so insert, erase and the smallest
+// member of a key are O(1); the largest occupied key only drops when its set
+// empties.  Keys below 1 are not selectable and are not stored.
+struct BucketQueue {
+  struct Bits {
+    std::vector<uint64_t> w0, w1, w2;
+    int64_t count = 0;
+  };
+  int32_t n;
+  std::vector<int64_t> key;  // stored key of each point, -1 = absent
+  std::vector<Bits> bucket;
+  int64_t top = 0;           // an upper bound of the largest occupied key
+  explicit BucketQueue(int32_t n_) : n(n_), key(n_, -1) {}
+  Bits& at(int64_t k) {
+    if ((int64_t)bucket.size() <= k) bucket.resize(k + 1);
+    Bits& b = bucket[k];
+    if (b.w0.empty()) {
+      b.w0.assign(((size_t)n + 63) / 64, 0);
+      b.w1.assign((b.w0.size() + 63) / 64, 0);
+      b.w2.assign((b.w1.size() + 63) / 64, 0);
+    }
+    return b;
   }
-  bool better(int32_t a, int32_t b) const {  // node a beats node b
-    if (key[a] != key[b]) return key[a] > key[b];
-    return arg[a] < arg[b];
+  void insert(int32_t i, int64_t k) {
+    Bits& b = at(k);
+    const size_t a = (size_t)i >> 6, c = a >> 6, d = c >> 6;
+    if (!b.w0[a]) {
+      if (!b.w1[c]) b.w2[d] |= 1ull << (c & 63);
+      b.w1[c] |= 1ull << (a & 63);
+    }
+    b.w0[a] |= 1ull << (i & 63);
+    ++b.count;
+    if (k > top) top = k;
   }
-  void pull(int32_t p) {
-    const int32_t l = 2 * p, r = l + 1, w = better(l, r) ? l : r;
-    key[p] = key[w];
-    arg[p] = arg[w];
-  }
-  void build() {
-    for (int32_t p = size - 1; p >= 1; --p) pull(p);
+  void erase(int32_t i, int64_t k) {
+    Bits& b = bucket[k];
+    const size_t a = (size_t)i >> 6, c = a >> 6, d = c >> 6;
+    b.w0[a] &= ~(1ull << (i & 63));
+    if (!b.w0[a]) {
+      b.w1[c] &= ~(1ull << (a & 63));
+      if (!b.w1[c]) b.w2[d] &= ~(1ull << (c & 63));
+    }
+    --b.count;
   }
   void set(int32_t i, int64_t k) {
-    int32_t p = size + i;
-    key[p] = k;
-    for (p >>= 1; p >= 1; p >>= 1) pull(p);
+    if (key[i] >= 1) erase(i, key[i]);
+    key[i] = k >= 1 ? k : -1;
+    if (k >= 1) insert(i, k);
+  }
+  // the selected point, or -1 when no key >= 1 is left
+  int32_t pick() {
+    while (top >= 1 && ((int64_t)bucket.size() <= top || bucket[top].count == 0)) --top;
+    if (top < 1) return -1;
+    const Bits& b = bucket[top];
+    size_t d = 0;
+    while (!b.w2[d]) ++d;
+    const size_t c = d * 64 + (size_t)__builtin_ctzll(b.w2[d]);
+    const size_t a = c * 64 + (size_t)__builtin_ctzll(b.w1[c]);
+    return (int32_t)(a * 64 + (size_t)__builtin_ctzll(b.w0[a]));
   }
 };
 }  // namespace
@@ -184,16 +219,16 @@ std::vector<int32_t> first_pass_split(const Csr& S) {
   Csr St = transpose(S, 1);
   std::vector<int32_t> cf(n, 0);
   std::vector<int64_t> lam(n);
-  MaxTree tree(n);
+  BucketQueue queue(n);
   for (int32_t i = 0; i < n; ++i) {
     lam[i] = St.rp[i + 1] - St.rp[i];
     if (lam[i] == 0 && S.rp[i + 1] == S.rp[i]) cf[i] = -1;
-    tree.key[tree.size + i] = (cf[i] == 0 && lam[i] >= 1) ? lam[i] : -1;
+    if (cf[i] == 0) queue.set(i, lam[i]);
   }
-  tree.build();
-  auto refresh = [&](int32_t m) { tree.set(m, (cf[m] == 0 && lam[m] >= 1) ? lam[m] : -1); };
-  while (tree.key[1] >= 1) {
-    const int32_t c = tree.arg[1];
+  auto refresh = [&](int32_t m) { queue.set(m, cf[m] == 0 ? lam[m] : -1); };
+  for (;;) {
+    const int32_t c = queue.pick();
+    if (c < 0) break;
     cf[c] = 1;
     refresh(c);
     for (int64_t k = St.rp[c]; k < St.rp[c + 1]; ++k) {
