@@ -455,17 +455,20 @@ int build_prec(cptr_solver s, PrecDev<T>& d, const std::vector<int32_t>& fp,
   const int32_t nb = h.nb;
   const int ne = h.ne;
   int rc;
-  // Ahat (ne x ne blocks) in SELL-64
+  // Ahat (ne x ne blocks) in A's SELL-64 slots, formed on the device from A
+  // and W (slice pointers and columns are A's)
   {
-    HostSell hs = pack_sell(
-        nb, ne * ne, [&](int32_t r) { return h.rp[r + 1] - h.rp[r]; },
-        [&](int32_t r, int32_t k, int32_t& c, double* v) {
-          const int32_t q = h.rp[r] + k;
-          c = h.ci[q];
-          std::memcpy(v, &h.ahat[(size_t)q * ne * ne], ne * ne * sizeof(double));
-        },
-        0, s->measure, s->threads);
-    if ((rc = upload_sell(s, d.Ahat, hs, st))) return rc;
+    d.Ahat.nrows = s->A.nrows;
+    d.Ahat.nslices = s->A.nslices;
+    d.Ahat.nv = ne * ne;
+    d.Ahat.nslots = s->A.nslots;
+    d.Ahat.sptr = s->A.sptr;
+    d.Ahat.col = s->A.col;
+    if ((rc = dalloc(s, d.Ahat.val, s->A.nslots * kLanes * ne * ne))) return rc;
+    if (!s->measure) {
+      launch_sell_ahat(s->A, s->W, ne, s->eidx_h, s->hidx_h, d.Ahat.val, st);
+      HIP_TRY(s, hipGetLastError());
+    }
   }
   // ILU factors: in the tile layouts of the grid sweeps, or by dependency
   // level for the one-launch and per-level sweeps (only one of the two is kept)

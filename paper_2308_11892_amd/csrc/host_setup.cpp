@@ -147,7 +147,7 @@ static Csr transpose(const Csr& a, int threads) {
 // smallest index on ties) becomes C; unassigned points depending on it become
 // F and each unassigned strong dependency of such a new F point gains 1; each
 // unassigned strong dependency of the new C point loses 1.  Leftovers are F.
-// Selection uses a max segment tree keyed on (measure, -index).
+// Selection takes points from a bucket queue keyed on the measure.
 namespace {
 // Points keyed by a small non-negative integer measure; pick() returns the
 // largest key, ties to the smallest index.  Each key value holds its points in
@@ -807,25 +807,10 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
       return err = "singular hyperbolic diagonal block in row " + std::to_string(bad),
              CPTR_E_ZERO_PIVOT;
   }
-  // ---- reduced elliptic blocks Ahat_ij = A_ij[E,E] - W_i A_ij[H,E] ----
-  h.ahat.assign((size_t)nnzb * ne * ne, 0.0);
-  parallel_for(threads, nb, [&](int64_t lo, int64_t hi, int) {
-    for (int64_t i = lo; i < hi; ++i) {
-      const double* w = &h.W[(size_t)i * ne * nh];
-      for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
-        const double* B = &h.av[(size_t)k * 9];
-        double* o = &h.ahat[(size_t)k * ne * ne];
-        for (int a = 0; a < ne; ++a)
-          for (int c = 0; c < ne; ++c) {
-            double s = B[h.eidx[a] * 3 + h.eidx[c]];
-            for (int t = 0; t < nh; ++t) s -= w[a * nh + t] * B[h.hidx[t] * 3 + h.eidx[c]];
-            o[a * ne + c] = s;
-          }
-      }
-    }
-  });
-
   // ---- system AMG on Ahat, unknowns interleaved per cell (Sec. 3.1, 3.2) ----
+  // Level 0 is Ahat as a scalar matrix, formed here from the reduced elliptic
+  // blocks Ahat_ij = A_ij[E,E] - W_i A_ij[H,E]: each product rounded before
+  // its subtraction, t = 0, 1, ... (the device forms the same values).
   h.lev.clear();
   h.lev.emplace_back();
   {
@@ -839,16 +824,22 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
     A0.ci.resize(A0.rp[A0.n]);
     A0.v.resize(A0.rp[A0.n]);
     parallel_for(threads, nb, [&](int64_t lo, int64_t hi, int) {
-      for (int64_t i = lo; i < hi; ++i)
+      for (int64_t i = lo; i < hi; ++i) {
+        const double* w = &h.W[(size_t)i * ne * nh];
         for (int a = 0; a < ne; ++a) {
           int64_t p = A0.rp[i * ne + a];
-          for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+          for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const double* B = &h.av[(size_t)k * 9];
             for (int c = 0; c < ne; ++c) {
+              double x = B[h.eidx[a] * 3 + h.eidx[c]];
+              for (int t = 0; t < nh; ++t) x -= w[a * nh + t] * B[h.hidx[t] * 3 + h.eidx[c]];
               A0.ci[p] = ci[k] * ne + c;
-              A0.v[p] = h.ahat[(size_t)k * ne * ne + a * ne + c];
+              A0.v[p] = x;
               ++p;
             }
+          }
         }
+      }
     });
     L0.func.resize(A0.n);
     for (int32_t r = 0; r < A0.n; ++r) L0.func[r] = r % ne;

@@ -55,7 +55,6 @@ struct HostSetup {
   std::vector<double> av_owned;  // A values when the caller's array does not outlive the setup
   std::vector<int32_t> diag;   // position of the diagonal block of each row
   std::vector<double> W;       // [nb][ne][nh]
-  std::vector<double> ahat;    // [nnzb][ne][ne] reduced elliptic blocks on A's pattern
   std::vector<AmgLevel> lev;   // lev.back() is the coarsest level
   std::vector<double> coarse_lu;  // dense LU of the coarsest matrix, row-major
   std::vector<int32_t> coarse_piv;

@@ -1546,6 +1546,51 @@ __global__ __launch_bounds__(kBlock) void k_grid_ilu_pack(int nb, int nx, int ny
   for (int e = 0; e < 9; ++e) Ut[((size_t)br * 36 + 27 + e) * 64 + lane] = (T)uinv[(size_t)c * 9 + e];
 }
 
+// reduced elliptic blocks Ahat_ij = A_ij[E,E] - W_i A_ij[H,E] (Sec. 5.2) in
+// A's SELL-64 slots: one thread per row, ne*ne values per slot.  Products are
+// rounded before each subtraction, in the order t = 0, 1, ..., so the values
+// are the ones the host computes (and, in FP32, their rounding).  Padding
+// slots hold zero blocks and give zero blocks.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_sell_ahat(int nrows, int nslices, const int32_t* __restrict__ sptr,
+                                                      const double* __restrict__ aval,
+                                                      const double* __restrict__ W, int ne, int e0, int e1,
+                                                      int h0, int h1, T* __restrict__ out) {
+#pragma clang fp contract(off)
+  const int row = blockIdx.x * kBlock + threadIdx.x;
+  const int s = row >> 6, lane = row & 63;
+  if (s >= nslices) return;
+  const int nh = 3 - ne;
+  const int eidx[2] = {e0, e1}, hidx[2] = {h0, h1};
+  double w[2] = {0.0, 0.0};
+  if (row < nrows) {
+    w[0] = W[(size_t)row * 2];
+    w[1] = W[(size_t)row * 2 + 1];
+  }
+  const int nv = ne * ne;
+  for (int q = sptr[s]; q < sptr[s + 1]; ++q) {
+    const double* B = aval + (size_t)q * 9 * 64 + lane;
+    for (int a = 0; a < ne; ++a)
+      for (int c = 0; c < ne; ++c) {
+        double v = B[(eidx[a] * 3 + eidx[c]) * 64];
+        for (int t = 0; t < nh; ++t) {
+          const double prod = w[a * nh + t] * B[(hidx[t] * 3 + eidx[c]) * 64];
+          v = v - prod;
+        }
+        out[((size_t)q * nv + a * ne + c) * 64 + lane] = (T)v;
+      }
+  }
+}
+
+template <class T>
+void launch_sell_ahat(const Sell& A, const double* W, int ne, const int32_t* eidx, const int32_t* hidx,
+                      T* out, hipStream_t st) {
+  if (A.nslices == 0) return;
+  k_sell_ahat<T><<<nblocks((int64_t)A.nslices * 64, kBlock), kBlock, 0, st>>>(
+      A.nrows, A.nslices, A.sptr, A.val, W, ne, eidx[0], ne > 1 ? eidx[1] : 0, hidx[0],
+      ne < 2 ? hidx[1] : 0, out);
+}
+
 void launch_grid_ilu_diag(const Sell& A, const int32_t* fperm, int32_t p0, int32_t p1, int nx, int nxy,
                           double* uinv, int* bad, hipStream_t st) {
   if (p1 <= p0) return;
@@ -1681,6 +1726,8 @@ void launch_update_host_coef(int64_t n, int nv, const double* V, int64_t ldv, co
   template void launch_stage2_grid<T>(int, int, int, const Sell&, int, const int32_t*, const T*,     \
                                       const double*, T*, T*, T*, int*, hipStream_t);                 \
   template void launch_grid_ilu_pack<T>(const Sell&, int, int, const double*, T*, T*, hipStream_t);  \
+  template void launch_sell_ahat<T>(const Sell&, const double*, int, const int32_t*, const int32_t*,  \
+                                    T*, hipStream_t);                                                 \
   template void launch_ilu_fwd_grid<T>(int, int, int, const T*, const T*, T*, T*, int*, double*, long, \
                                        hipStream_t);                                                 \
   template void launch_ilu_bwd_grid<T>(int, int, int, const T*, T*, const T*, int, const int32_t*, T*, \

@@ -118,6 +118,11 @@ void launch_grid_ilu_diag(const Sell& A, const int32_t* fperm, int32_t p0, int32
 template <class T>
 void launch_grid_ilu_pack(const Sell& A, int nx, int ny, const double* uinv, T* Lt, T* Ut,
                           hipStream_t st);
+// Ahat_ij = A_ij[E,E] - W_i A_ij[H,E] in A's SELL-64 slots (ne*ne values per
+// slot, A's sptr and col apply); W: 2 per cell; eidx/hidx: host arrays.
+template <class T>
+void launch_sell_ahat(const Sell& A, const double* W, int ne, const int32_t* eidx, const int32_t* hidx,
+                      T* out, hipStream_t st);
 template <class T>
 void launch_stage2_grid(int nx, int ny, int nz, const Sell& A, int ne, const int32_t* eidx, const T* e0,
                         const double* r, T* r2t, T* e0t, T* faces, int* tickets, hipStream_t st);
