@@ -569,17 +569,57 @@ int build_device(cptr_solver s, hipStream_t st) {
   const int32_t nb = h.nb;
   const int ne = h.ne;
   int rc;
-  // A in SELL-64, natural order (FP64 in both precisions)
+  // A in SELL-64, natural order (FP64 in both precisions).  Slice widths come
+  // from the row pointers on the host; A's columns and blocks go to the device
+  // as they are, in chunks of whole slices through a staging buffer, and a
+  // kernel places them in the slots.
   {
-    HostSell hs = pack_sell(
-        nb, 9, [&](int32_t r) { return h.rp[r + 1] - h.rp[r]; },
-        [&](int32_t r, int32_t k, int32_t& c, double* v) {
-          const int32_t q = h.rp[r] + k;
-          c = h.ci[q];
-          std::memcpy(v, &h.av[(size_t)q * 9], 9 * sizeof(double));
-        },
-        0, s->measure, s->threads);
-    if ((rc = upload_sell(s, s->A, hs, st))) return rc;
+    Sell& d = s->A;
+    d.nrows = nb;
+    d.nslices = (nb + kLanes - 1) / kLanes;
+    d.nv = 9;
+    std::vector<int32_t> sptr((size_t)d.nslices + 1, 0);
+    int64_t max_slice_blocks = 0;
+    for (int32_t sl = 0; sl < d.nslices; ++sl) {
+      const int32_t r0 = sl * kLanes, r1 = std::min(nb, r0 + kLanes);
+      int32_t w = 0;
+      for (int32_t r = r0; r < r1; ++r) w = std::max(w, h.rp[r + 1] - h.rp[r]);
+      sptr[sl + 1] = sptr[sl] + w;
+      max_slice_blocks = std::max<int64_t>(max_slice_blocks, h.rp[r1] - h.rp[r0]);
+    }
+    d.nslots = sptr[d.nslices];
+    if ((rc = upload(s, d.sptr, sptr.data(), (int64_t)sptr.size(), st))) return rc;
+    if ((rc = dalloc(s, d.col, d.nslots * kLanes)) || (rc = dalloc(s, d.val, d.nslots * kLanes * 9)))
+      return rc;
+    // staging: up to 1M blocks, never more than A itself
+    const int64_t cap = std::max<int64_t>(std::min<int64_t>(int64_t(1) << 20, h.rp[nb]), max_slice_blocks);
+    int32_t* rp_d = nullptr;
+    int32_t* ci_st = nullptr;
+    double* v_st = nullptr;
+    if ((rc = upload(s, rp_d, h.rp.data(), (int64_t)nb + 1, st)) || (rc = dalloc(s, ci_st, cap)) ||
+        (rc = dalloc(s, v_st, cap * 9)))
+      return rc;
+    if (!s->measure) {
+      for (int32_t s0 = 0; s0 < d.nslices;) {
+        const int32_t q0 = h.rp[(int64_t)s0 * kLanes];
+        int32_t s1 = s0 + 1;
+        while (s1 < d.nslices && h.rp[std::min<int64_t>(nb, (int64_t)(s1 + 1) * kLanes)] - q0 <= cap) ++s1;
+        const int32_t q1 = h.rp[std::min<int64_t>(nb, (int64_t)s1 * kLanes)];
+        if (q1 > q0) {
+          HIP_TRY(s, hipMemcpyAsync(ci_st, h.ci.data() + q0, sizeof(int32_t) * (size_t)(q1 - q0),
+                                    hipMemcpyHostToDevice, st));
+          HIP_TRY(s, hipMemcpyAsync(v_st, h.av + (size_t)q0 * 9, sizeof(double) * 9 * (size_t)(q1 - q0),
+                                    hipMemcpyHostToDevice, st));
+        }
+        launch_bsr_to_sell(nb, s0 * kLanes, s1 * kLanes, rp_d, q0, ci_st, v_st, d, st);
+        HIP_TRY(s, hipGetLastError());
+        s0 = s1;
+      }
+      HIP_TRY(s, hipStreamSynchronize(st));
+    }
+    dfree(s, rp_d);
+    dfree(s, ci_st);
+    dfree(s, v_st);
   }
   // W padded to 2 per cell
   {

@@ -1546,6 +1546,39 @@ __global__ __launch_bounds__(kBlock) void k_grid_ilu_pack(int nb, int nx, int ny
   for (int e = 0; e < 9; ++e) Ut[((size_t)br * 36 + 27 + e) * 64 + lane] = (T)uinv[(size_t)c * 9 + e];
 }
 
+// A's 3x3 blocks into SELL-64 slots, one thread per row of the whole slices
+// [r0, r_end): the blocks of those rows (from q0 = rp[r0] on) are staged in
+// ci_chunk / v_chunk in CSR order.  Padding slots get the row's own column
+// (column 0 in padding rows) and a zero block, as every SELL-64 operator here.
+__global__ __launch_bounds__(kBlock) void k_bsr_to_sell(int nrows, int r0, int r_end,
+                                                        const int32_t* __restrict__ rp, int32_t q0,
+                                                        const int32_t* __restrict__ ci_chunk,
+                                                        const double* __restrict__ v_chunk,
+                                                        const int32_t* __restrict__ sptr,
+                                                        int32_t* __restrict__ col, double* __restrict__ val) {
+  const int row = r0 + blockIdx.x * kBlock + threadIdx.x;
+  if (row >= r_end) return;
+  const int s = row >> 6, lane = row & 63;
+  const bool live = row < nrows;
+  const int n = live ? rp[row + 1] - rp[row] : 0;
+  const int64_t qb = live ? (int64_t)rp[row] - q0 : 0;
+  const int w = sptr[s + 1] - sptr[s];
+  for (int k = 0; k < w; ++k) {
+    const size_t slot = (size_t)sptr[s] + k;
+    const bool real = k < n;
+    col[slot * 64 + lane] = real ? ci_chunk[qb + k] : (live ? row : 0);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) val[(slot * 9 + e) * 64 + lane] = real ? v_chunk[(qb + k) * 9 + e] : 0.0;
+  }
+}
+
+void launch_bsr_to_sell(int nrows, int r0, int r_end, const int32_t* rp, int32_t q0, const int32_t* ci_chunk,
+                        const double* v_chunk, Sell& A, hipStream_t st) {
+  if (r_end <= r0) return;
+  k_bsr_to_sell<<<nblocks(r_end - r0, kBlock), kBlock, 0, st>>>(nrows, r0, r_end, rp, q0, ci_chunk, v_chunk,
+                                                                A.sptr, A.col, A.val);
+}
+
 // reduced elliptic blocks Ahat_ij = A_ij[E,E] - W_i A_ij[H,E] (Sec. 5.2) in
 // A's SELL-64 slots: one thread per row, ne*ne values per slot.  Products are
 // rounded before each subtraction, in the order t = 0, 1, ..., so the values

@@ -118,6 +118,12 @@ void launch_grid_ilu_diag(const Sell& A, const int32_t* fperm, int32_t p0, int32
 template <class T>
 void launch_grid_ilu_pack(const Sell& A, int nx, int ny, const double* uinv, T* Lt, T* Ut,
                           hipStream_t st);
+// A (3x3 blocks, CSR order) into its SELL-64 layout, for the whole slices of
+// rows [r0, r_end) (r0 a multiple of 64, r_end a multiple of 64 or the padded
+// end); rp on the device; the rows' columns and blocks staged from q0 = rp[r0].
+// A.sptr is filled beforehand.
+void launch_bsr_to_sell(int nrows, int r0, int r_end, const int32_t* rp, int32_t q0, const int32_t* ci_chunk,
+                        const double* v_chunk, Sell& A, hipStream_t st);
 // Ahat_ij = A_ij[E,E] - W_i A_ij[H,E] in A's SELL-64 slots (ne*ne values per
 // slot, A's sptr and col apply); W: 2 per cell; eidx/hidx: host arrays.
 template <class T>
