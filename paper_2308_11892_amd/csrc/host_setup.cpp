@@ -10,6 +10,7 @@
 // Compiled with FP contraction off so that the reduced elliptic matrix and the
 // strength tests on it are bit-reproducible.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -33,6 +34,28 @@ void parallel_for(int threads, int64_t n, const std::function<void(int64_t, int6
     pool.emplace_back([&body, lo, hi, k] { body(lo, hi, k); });
   }
   for (auto& th : pool) th.join();
+}
+
+// Rows [lo, hi) of thread t of parallel_for(threads, n, ...) were written, in
+// row order, to part t; each thread of the same partition copies its part to
+// offset rp[lo] of the result arrays (sized here).
+template <class Part>
+static void place_parts(int threads, int64_t n, const std::vector<int64_t>& rp, const std::vector<Part>& parts,
+                        HVec<int32_t>& ci, HVec<double>& v) {
+  ci.resize(rp[n]);
+  v.resize(rp[n]);
+  parallel_for(threads, n, [&](int64_t lo, int64_t, int t) {
+    std::copy(parts[t].ci.begin(), parts[t].ci.end(), ci.begin() + rp[lo]);
+    std::copy(parts[t].v.begin(), parts[t].v.end(), v.begin() + rp[lo]);
+  });
+}
+
+static void place_parts(int threads, int64_t n, const std::vector<int64_t>& rp,
+                        const std::vector<std::vector<int32_t>>& parts, HVec<int32_t>& ci) {
+  ci.resize(rp[n]);
+  parallel_for(threads, n, [&](int64_t lo, int64_t, int t) {
+    std::copy(parts[t].begin(), parts[t].end(), ci.begin() + rp[lo]);
+  });
 }
 
 int validate_bsr(int32_t nb, int64_t nnzb, const int32_t* rp, const int32_t* ci,
@@ -115,28 +138,62 @@ Csr strength_graph(const Csr& A, const std::vector<int32_t>& func, double theta,
   parallel_for(threads, A.n, [&](int64_t lo, int64_t hi, int) {
     for (int64_t i = lo; i < hi; ++i) row_pass((int32_t)i, S.ci.data() + S.rp[i]);
   });
-  S.v.assign(S.ci.size(), 1.0);
   return S;
 }
 
+// Rows of the transpose hold their columns in increasing order.  Large
+// matrices are placed with atomic counters by several threads and each row is
+// then sorted, which gives the same arrays as the sequential placement.
 static Csr transpose(const Csr& a, int threads) {
-  (void)threads;
   Csr t;
   t.n = a.m;
   t.m = a.n;
-  t.rp.assign(t.n + 1, 0);
-  for (int64_t k = 0; k < a.nnz(); ++k) ++t.rp[a.ci[k] + 1];
-  for (int32_t j = 0; j < t.n; ++j) t.rp[j + 1] += t.rp[j];
   const bool values = !a.v.empty();  // a pattern-only matrix stays pattern-only
-  t.ci.resize(a.nnz());
-  t.v.resize(values ? a.nnz() : 0);
+  const int64_t nnz = a.nnz();
+  t.ci.resize(nnz);
+  t.v.resize(values ? nnz : 0);
+  if (threads <= 1 || nnz < 4096) {
+    t.rp.assign(t.n + 1, 0);
+    for (int64_t k = 0; k < nnz; ++k) ++t.rp[a.ci[k] + 1];
+    for (int32_t j = 0; j < t.n; ++j) t.rp[j + 1] += t.rp[j];
+    std::vector<int64_t> fill(t.rp.begin(), t.rp.end() - 1);
+    for (int32_t i = 0; i < a.n; ++i)
+      for (int64_t k = a.rp[i]; k < a.rp[i + 1]; ++k) {
+        const int64_t p = fill[a.ci[k]]++;
+        t.ci[p] = i;
+        if (values) t.v[p] = a.v[k];
+      }
+    return t;
+  }
+  std::vector<int64_t> cnt(t.n + 1, 0);
+  parallel_for(threads, a.n, [&](int64_t lo, int64_t hi, int) {
+    for (int64_t k = a.rp[lo]; k < a.rp[hi]; ++k) __atomic_fetch_add(&cnt[a.ci[k] + 1], 1, __ATOMIC_RELAXED);
+  });
+  t.rp.assign(t.n + 1, 0);
+  for (int32_t j = 0; j < t.n; ++j) t.rp[j + 1] = t.rp[j] + cnt[j + 1];
   std::vector<int64_t> fill(t.rp.begin(), t.rp.end() - 1);
-  for (int32_t i = 0; i < a.n; ++i)
-    for (int64_t k = a.rp[i]; k < a.rp[i + 1]; ++k) {
-      const int64_t p = fill[a.ci[k]]++;
-      t.ci[p] = i;
-      if (values) t.v[p] = a.v[k];
-    }
+  parallel_for(threads, a.n, [&](int64_t lo, int64_t hi, int) {
+    for (int64_t i = lo; i < hi; ++i)
+      for (int64_t k = a.rp[i]; k < a.rp[i + 1]; ++k) {
+        const int64_t p = __atomic_fetch_add(&fill[a.ci[k]], 1, __ATOMIC_RELAXED);
+        t.ci[p] = (int32_t)i;
+        if (values) t.v[p] = a.v[k];
+      }
+  });
+  parallel_for(threads, t.n, [&](int64_t lo, int64_t hi, int) {
+    for (int64_t j = lo; j < hi; ++j)  // insertion sort: rows are short
+      for (int64_t p = t.rp[j] + 1; p < t.rp[j + 1]; ++p) {
+        const int32_t c = t.ci[p];
+        const double x = values ? t.v[p] : 0.0;
+        int64_t q = p;
+        for (; q > t.rp[j] && t.ci[q - 1] > c; --q) {
+          t.ci[q] = t.ci[q - 1];
+          if (values) t.v[q] = t.v[q - 1];
+        }
+        t.ci[q] = c;
+        if (values) t.v[q] = x;
+      }
+  });
   return t;
 }
 
@@ -214,9 +271,9 @@ struct BucketQueue {
 };
 }  // namespace
 
-std::vector<int32_t> first_pass_split(const Csr& S) {
+std::vector<int32_t> first_pass_split(const Csr& S, int threads) {
   const int32_t n = S.n;
-  Csr St = transpose(S, 1);
+  Csr St = transpose(S, threads);
   std::vector<int32_t> cf(n, 0);
   std::vector<int64_t> lam(n);
   BucketQueue queue(n);
@@ -301,15 +358,14 @@ Csr distance_two_strength(const Csr& S, const std::vector<int32_t>& cf, int thre
   S2.n = S2.m = nc;
   S2.rp.assign(nc + 1, 0);
   for (int32_t r = 0; r < nc; ++r) S2.rp[r + 1] = S2.rp[r] + len[r + 1];
-  S2.ci.reserve(S2.rp[nc]);
-  for (auto& p : part) S2.ci.insert(S2.ci.end(), p.begin(), p.end());
+  place_parts(nthreads, nc, S2.rp, part, S2.ci);
   return S2;
 }
 
 std::vector<int32_t> aggressive_split(const Csr& S, int threads) {
-  std::vector<int32_t> cf1 = first_pass_split(S);
+  std::vector<int32_t> cf1 = first_pass_split(S, threads);
   const Csr S2 = distance_two_strength(S, cf1, threads);
-  const std::vector<int32_t> cf2 = first_pass_split(S2);
+  const std::vector<int32_t> cf2 = first_pass_split(S2, threads);
   std::vector<int32_t> cf(S.n, -1);
   for (int32_t i = 0, c = 0; i < S.n; ++i)
     if (cf1[i] == 1) cf[i] = cf2[c++] == 1 ? 1 : -1;
@@ -594,12 +650,7 @@ Csr extended_i_interp(const Csr& A, const Csr& S, const std::vector<int32_t>& cf
   P.m = nc;
   P.rp.assign(n + 1, 0);
   for (int32_t i = 0; i < n; ++i) P.rp[i + 1] = P.rp[i] + rowlen[i + 1];
-  P.ci.reserve(P.rp[n]);
-  P.v.reserve(P.rp[n]);
-  for (auto& part : parts) {
-    P.ci.insert(P.ci.end(), part.ci.begin(), part.ci.end());
-    P.v.insert(P.v.end(), part.v.begin(), part.v.end());
-  }
+  place_parts(nthreads, n, P.rp, parts, P.ci, P.v);
   return P;
 }
 
@@ -669,12 +720,7 @@ static Csr spgemm(const Csr& X, const Csr& Y, int threads) {
   C.m = Y.m;
   C.rp.assign(n + 1, 0);
   for (int32_t i = 0; i < n; ++i) C.rp[i + 1] = C.rp[i] + len[i + 1];
-  C.ci.reserve(C.rp[n]);
-  C.v.reserve(C.rp[n]);
-  for (auto& part : parts) {
-    C.ci.insert(C.ci.end(), part.ci.begin(), part.ci.end());
-    C.v.insert(C.v.end(), part.v.begin(), part.v.end());
-  }
+  place_parts(nthreads, n, C.rp, parts, C.ci, C.v);
   return C;
 }
 
@@ -684,18 +730,24 @@ static Csr galerkin(const Csr& R, const Csr& A, const Csr& P, int threads) {
 }
 
 // l1-Jacobi (point blocks): d_i = a_ii + sign(a_ii) sum_{j != i} |a_ij|.
-static int l1_inverse_diag(const Csr& A, std::vector<double>& dinv, std::string& err) {
+static int l1_inverse_diag(const Csr& A, std::vector<double>& dinv, int threads, std::string& err) {
   dinv.resize(A.n);
-  for (int32_t i = 0; i < A.n; ++i) {
-    double d = 0.0, off = 0.0;
-    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
-      if (A.ci[k] == i) d = A.v[k];
-      else off += std::fabs(A.v[k]);
+  std::vector<int32_t> first_bad(std::max(1, threads), INT32_MAX);
+  parallel_for(threads, A.n, [&](int64_t lo, int64_t hi, int t) {
+    for (int64_t i = lo; i < hi; ++i) {
+      double d = 0.0, off = 0.0;
+      for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+        if (A.ci[k] == i) d = A.v[k];
+        else off += std::fabs(A.v[k]);
+      }
+      const double l1 = d < 0.0 ? d - off : d + off;
+      if (l1 == 0.0) first_bad[t] = std::min(first_bad[t], (int32_t)i);
+      dinv[i] = l1 == 0.0 ? 0.0 : 1.0 / l1;
     }
-    const double l1 = d < 0.0 ? d - off : d + off;
-    if (l1 == 0.0) return err = "zero smoother diagonal at AMG row " + std::to_string(i), CPTR_E_ZERO_PIVOT;
-    dinv[i] = 1.0 / l1;
-  }
+  });
+  const int32_t bad = *std::min_element(first_bad.begin(), first_bad.end());
+  if (bad != INT32_MAX)
+    return err = "zero smoother diagonal at AMG row " + std::to_string(bad), CPTR_E_ZERO_PIVOT;
   return CPTR_OK;
 }
 
@@ -774,36 +826,47 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
   h.ci.assign(ci, ci + nnzb);
   h.av = v;  // read in place: no copy of the largest input
   h.diag.resize(nb);
-  for (int32_t i = 0; i < nb; ++i)
-    for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
-      if (ci[k] == i) h.diag[i] = k;
+  parallel_for(threads, nb, [&](int64_t lo, int64_t hi, int) {
+    for (int64_t i = lo; i < hi; ++i)
+      for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+        if (ci[k] == i) h.diag[i] = k;
+  });
 
   // ---- quasi-IMPES weights W_i = A_ii[E,H] A_ii[H,H]^-1 (Sec. 5.2) ----
   const int nh = h.nh;
   h.W.assign((size_t)nb * ne * nh, 0.0);
   if (prm.quasi_impes) {
-    int bad = -1;
-    for (int32_t i = 0; i < nb && bad < 0; ++i) {
-      const double* D = &h.av[(size_t)h.diag[i] * 9];
-      double* w = &h.W[(size_t)i * ne * nh];
-      if (nh == 1) {
-        const double dhh = D[h.hidx[0] * 3 + h.hidx[0]];
-        if (dhh == 0.0) { bad = i; break; }
-        for (int e = 0; e < ne; ++e) w[e] = D[h.eidx[e] * 3 + h.hidx[0]] / dhh;
-      } else {  // nh == 2: explicit 2x2 inverse
-        const int p = h.hidx[0], q = h.hidx[1];
-        const double a = D[p * 3 + p], b = D[p * 3 + q], c = D[q * 3 + p], d = D[q * 3 + q];
-        const double det = a * d - b * c;
-        if (det == 0.0) { bad = i; break; }
-        const double ia = d / det, ib = -b / det, ic = -c / det, id = a / det;
-        for (int e = 0; e < ne; ++e) {
-          const double u = D[h.eidx[e] * 3 + p], t = D[h.eidx[e] * 3 + q];
-          w[e * 2 + 0] = u * ia + t * ic;
-          w[e * 2 + 1] = u * ib + t * id;
+    std::vector<int32_t> first_bad(threads, INT32_MAX);
+    parallel_for(threads, nb, [&](int64_t lo, int64_t hi, int th) {
+      for (int64_t i = lo; i < hi; ++i) {
+        const double* D = &h.av[(size_t)h.diag[i] * 9];
+        double* w = &h.W[(size_t)i * ne * nh];
+        if (nh == 1) {
+          const double dhh = D[h.hidx[0] * 3 + h.hidx[0]];
+          if (dhh == 0.0) {
+            first_bad[th] = std::min(first_bad[th], (int32_t)i);
+            continue;
+          }
+          for (int e = 0; e < ne; ++e) w[e] = D[h.eidx[e] * 3 + h.hidx[0]] / dhh;
+        } else {  // nh == 2: explicit 2x2 inverse
+          const int p = h.hidx[0], q = h.hidx[1];
+          const double a = D[p * 3 + p], b = D[p * 3 + q], c = D[q * 3 + p], d = D[q * 3 + q];
+          const double det = a * d - b * c;
+          if (det == 0.0) {
+            first_bad[th] = std::min(first_bad[th], (int32_t)i);
+            continue;
+          }
+          const double ia = d / det, ib = -b / det, ic = -c / det, id = a / det;
+          for (int e = 0; e < ne; ++e) {
+            const double u = D[h.eidx[e] * 3 + p], t = D[h.eidx[e] * 3 + q];
+            w[e * 2 + 0] = u * ia + t * ic;
+            w[e * 2 + 1] = u * ib + t * id;
+          }
         }
       }
-    }
-    if (bad >= 0)
+    });
+    const int32_t bad = *std::min_element(first_bad.begin(), first_bad.end());
+    if (bad != INT32_MAX)
       return err = "singular hyperbolic diagonal block in row " + std::to_string(bad),
              CPTR_E_ZERO_PIVOT;
   }
@@ -850,7 +913,7 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
     if (A.n <= prm.max_coarse || (int)l + 1 >= prm.max_levels) break;
     Csr S = strength_graph(A, h.lev[l].func, prm.theta, prm.max_row_sum, threads);
     const bool agg = (int)l < prm.agg_levels;
-    std::vector<int32_t> cf = agg ? aggressive_split(S, threads) : first_pass_split(S);
+    std::vector<int32_t> cf = agg ? aggressive_split(S, threads) : first_pass_split(S, threads);
     int32_t nc = 0;
     for (auto x : cf) nc += x == 1;
     if (nc == 0 || nc == A.n) break;
@@ -871,7 +934,7 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
     h.lev.push_back(std::move(next));
   }
   for (size_t l = 0; l + 1 < h.lev.size(); ++l) {
-    int st = l1_inverse_diag(h.lev[l].A, h.lev[l].dinv, err);
+    int st = l1_inverse_diag(h.lev[l].A, h.lev[l].dinv, threads, err);
     if (st != CPTR_OK) return st;
   }
   {

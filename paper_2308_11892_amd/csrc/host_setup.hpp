@@ -9,18 +9,45 @@
 #pragma once
 #include <cstdint>
 #include <functional>
+#include <memory>
 #include <string>
+#include <utility>
 #include <vector>
 
 namespace cptr {
 
 constexpr int kBS = 3;   // unknowns per cell supported by the kernels
 
+// std::vector whose resize() leaves new elements of trivial types
+// uninitialised (assign() and value-taking constructors still fill), so that a
+// large array is first written by the threads that fill it instead of being
+// zeroed by one thread beforehand.
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = NoInitAlloc<U>;
+  };
+  NoInitAlloc() = default;
+  template <class U>
+  NoInitAlloc(const NoInitAlloc<U>&) noexcept {}
+  template <class U>
+  void construct(U* p) noexcept {
+    ::new (static_cast<void*>(p)) U;
+  }
+  template <class U, class... Args>
+  void construct(U* p, Args&&... args) {
+    ::new (static_cast<void*>(p)) U(std::forward<Args>(args)...);
+  }
+};
+template <class T>
+using HVec = std::vector<T, NoInitAlloc<T>>;
+
 struct Csr {
   int32_t n = 0, m = 0;
   std::vector<int64_t> rp;
-  std::vector<int32_t> ci;
-  std::vector<double> v;
+  HVec<int32_t> ci;
+  HVec<double> v;  // empty for a pattern-only matrix (strength graphs)
   int64_t nnz() const { return rp.empty() ? 0 : rp[n]; }
 };
 
@@ -74,7 +101,7 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
 // Building blocks, exported for the library's own host tests.
 Csr strength_graph(const Csr& A, const std::vector<int32_t>& func, double theta, double mrs,
                    int threads);
-std::vector<int32_t> first_pass_split(const Csr& S);
+std::vector<int32_t> first_pass_split(const Csr& S, int threads = 1);
 Csr extended_i_interp(const Csr& A, const Csr& S, const std::vector<int32_t>& cf,
                       const std::vector<int32_t>& func, int pmax, int threads);
 Csr distance_two_strength(const Csr& S, const std::vector<int32_t>& cf, int threads);
