@@ -119,6 +119,8 @@ struct PrecDev {
   T* faces = nullptr;        // face buffers of the forward then the backward grid sweep
   struct Lev {
     DCsrT<T> A, P, R;
+    SellT<T> As;             // A in SELL-64 instead (levels of many short rows)
+    bool sell = false;
     T* dinv = nullptr;
     T *b = nullptr, *r = nullptr, *x = nullptr, *e = nullptr;
     int32_t n = 0;
@@ -311,6 +313,35 @@ int upload_csr(cptr_solver s, DCsrT<T>& d, const Csr& h, hipStream_t st) {
   if ((rc = upload(s, d.ci, h.ci.data(), (int64_t)h.ci.size(), st))) return rc;
   if ((rc = upload_as(s, d.v, h.v.data(), (int64_t)h.v.size(), st))) return rc;
   return CPTR_OK;
+}
+
+// A coarse level's operator: SELL-64 (one thread per row, fully coalesced)
+// for many short rows of similar length, where the slices pad by at most
+// 10 %; otherwise CSR with several lanes per row, which keeps enough loads in
+// flight for long rows and small levels.
+template <class Lev>
+int upload_level_op(cptr_solver s, Lev& dl, const Csr& h, hipStream_t st) {
+  const int32_t n = h.n;
+  auto len = [&](int32_t r) { return (int32_t)(h.rp[r + 1] - h.rp[r]); };
+  int64_t padded = 0;
+  int32_t maxlen = 0;
+  for (int32_t a = 0; a < n; a += kLanes) {
+    int32_t w = 0;
+    for (int32_t r = a; r < std::min(n, a + kLanes); ++r) w = std::max(w, len(r));
+    padded += (int64_t)w * kLanes;
+    maxlen = std::max(maxlen, w);
+  }
+  dl.sell = n >= (1 << 18) && maxlen <= 32 && padded <= 1.1 * (double)h.nnz();
+  if (!dl.sell) return upload_csr(s, dl.A, h, st);
+  HostSell hs = pack_sell(
+      n, 1, len,
+      [&](int32_t r, int32_t k, int32_t& c, double* v) {
+        const int64_t q = h.rp[r] + k;
+        c = h.ci[q];
+        v[0] = h.v[q];
+      },
+      0, s->measure, s->threads);
+  return upload_sell(s, dl.As, hs, st);
 }
 
 // Is A's block pattern exactly the 7-point stencil of an nx*ny*nz grid in
@@ -520,7 +551,7 @@ int build_prec(cptr_solver s, PrecDev<T>& d, const std::vector<int32_t>& fp,
     const AmgLevel& hl = h.lev[l];
     auto& dl = d.lev[l];
     dl.n = hl.A.n;
-    if (l > 0 && (rc = upload_csr(s, dl.A, hl.A, st))) return rc;
+    if (l > 0 && l + 1 < L && (rc = upload_level_op(s, dl, hl.A, st))) return rc;
     if (l + 1 < L) {
       if ((rc = upload_csr(s, dl.P, hl.P, st))) return rc;
       if ((rc = upload_csr(s, dl.R, hl.R, st))) return rc;
@@ -714,20 +745,35 @@ void enqueue_stage1(cptr_solver s, PrecDev<T>& d, const double* r, hipStream_t s
     ph_end(s, st, PH_VCC, ev);
   } else {
     ph_begin(s, st, ev);
+    // restrictions to a smoothed level also write its pre-smoothed iterate
+    // x = D^-1 b, which its residual then reads
+    auto restrict_to = [&](int l, const T* r) {
+      auto& nx = d.lev[l + 1];
+      if (l + 2 < L)
+        launch_csr_restrict(d.lev[l].R, r, nx.dinv, nx.b, nx.x, st);
+      else
+        launch_csr_spmv(d.lev[l].R, r, nx.b, st);
+    };
     launch_l0_resid_jacobi(d.Ahat, ne, l0.b, l0.dinv, l0.r, st);
-    launch_csr_spmv(l0.R, l0.r, d.lev[1].b, st);
+    restrict_to(0, l0.r);
     ph_end(s, st, PH_VC0, ev);
     ph_begin(s, st, ev);
     for (int l = 1; l + 1 < L; ++l) {
       auto& dl = d.lev[l];
-      launch_csr_resid_jacobi(dl.A, dl.b, dl.dinv, dl.r, st);
-      launch_csr_spmv(dl.R, dl.r, d.lev[l + 1].b, st);
+      if (dl.sell)
+        launch_sell_resid(dl.As, dl.x, dl.b, dl.r, st);
+      else
+        launch_csr_resid(dl.A, dl.x, dl.b, dl.r, st);
+      restrict_to(l, dl.r);
     }
     launch_coarse_solve(s->ncoarse, s->coarse_lu, s->coarse_piv, d.lev[L - 1].b, d.lev[L - 1].e, st);
     for (int l = L - 2; l >= 1; --l) {
       auto& dl = d.lev[l];
       launch_csr_prolong(dl.P, d.lev[l + 1].e, dl.b, dl.dinv, dl.x, st);
-      launch_csr_post(dl.A, dl.x, dl.b, dl.dinv, dl.e, st);
+      if (dl.sell)
+        launch_sell_post(dl.As, dl.x, dl.b, dl.dinv, dl.e, st);
+      else
+        launch_csr_post(dl.A, dl.x, dl.b, dl.dinv, dl.e, st);
     }
     ph_end(s, st, PH_VCC, ev);
     ph_begin(s, st, ev);

@@ -163,7 +163,11 @@ __global__ __launch_bounds__(kBlock) void k_l0_post(int nc, int nblk, const int3
 
 // --------------------------------------------------------------------------
 // scalar CSR kernels: G lanes per row
-enum CsrOp { kSpmv = 0, kResidJacobi = 1, kProlong = 2, kPost = 3 };
+// kRestrict: y = A x and y2 = D^-1 y (the next level's right-hand side and its
+// pre-smoothed iterate); kResid: y = b - A x with x = D^-1 b, the residual
+// after one l1-Jacobi sweep from zero; kProlong: y = D^-1 b + A x; kPost:
+// y = x + D^-1 (b - A x)
+enum CsrOp { kSpmv = 0, kResid = 1, kProlong = 2, kPost = 3, kRestrict = 4 };
 
 template <int G, int OP, class T>
 __global__ __launch_bounds__(kBlock) void k_csr(int n, const int32_t* __restrict__ rp,
@@ -172,7 +176,7 @@ __global__ __launch_bounds__(kBlock) void k_csr(int n, const int32_t* __restrict
                                                 const T* __restrict__ x,
                                                 const T* __restrict__ b,
                                                 const T* __restrict__ dinv,
-                                                T* __restrict__ y) {
+                                                T* __restrict__ y, T* __restrict__ y2) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int row = (int)(t / G), sub = (int)(t % G);
   const bool live = row < n;
@@ -181,32 +185,55 @@ __global__ __launch_bounds__(kBlock) void k_csr(int n, const int32_t* __restrict
 #pragma unroll 4
     for (int k = rp[row] + sub; k < rp[row + 1]; k += G) {
       const int c = ci[k];
-      T xv = OP == kResidJacobi ? (T)0 : x[c];
-      if (OP == kResidJacobi) xv = dinv[c] * b[c];
-      acc += v[k] * xv;
+      acc += v[k] * x[c];
     }
   }
   acc = group_sum<G, T>(acc);
   if (!live || sub != 0) return;
   switch (OP) {
     case kSpmv: y[row] = acc; break;
-    case kResidJacobi: y[row] = b[row] - acc; break;
+    case kRestrict:
+      y[row] = acc;
+      y2[row] = dinv[row] * acc;
+      break;
+    case kResid: y[row] = b[row] - acc; break;
     case kProlong: y[row] = dinv[row] * b[row] + acc; break;
     case kPost: y[row] = x[row] + dinv[row] * (b[row] - acc); break;
   }
 }
 
+// scalar SELL-64 operator (kResid or kPost), one thread per row, each row
+// summing its entries in stored order
 template <int OP, class T>
-void launch_csr_op(const DCsrT<T>& A, const T* x, const T* b, const T* dinv, T* y, hipStream_t st) {
+__global__ __launch_bounds__(kBlock) void k_sell_scalar(int n, int nblk, const int32_t* __restrict__ sptr,
+                                                        const int32_t* __restrict__ col,
+                                                        const T* __restrict__ val, const T* __restrict__ x,
+                                                        const T* __restrict__ b, const T* __restrict__ dinv,
+                                                        T* __restrict__ y) {
+  const int row = xcd_block(blockIdx.x, nblk) * kBlock + threadIdx.x;
+  if (row >= n) return;
+  const int s = row >> 6, lane = row & 63;
+  T acc = 0;
+  for (int k = sptr[s]; k < sptr[s + 1]; ++k) acc += val[(size_t)k * 64 + lane] * x[col[(size_t)k * 64 + lane]];
+  if (OP == kResid)
+    y[row] = b[row] - acc;
+  else
+    y[row] = x[row] + dinv[row] * (b[row] - acc);
+}
+
+template <int OP, class T>
+void launch_csr_op(const DCsrT<T>& A, const T* x, const T* b, const T* dinv, T* y, hipStream_t st,
+                   T* y2 = nullptr) {
   if (A.n == 0) return;
   const int64_t threads = (int64_t)A.n * A.group;
   const int grid = nblocks(threads, kBlock);
   switch (A.group) {
 #define CSR_CASE(G) \
-  case G: k_csr<G, OP, T><<<grid, kBlock, 0, st>>>(A.n, A.rp, A.ci, A.v, x, b, dinv, y); break;
+  case G: k_csr<G, OP, T><<<grid, kBlock, 0, st>>>(A.n, A.rp, A.ci, A.v, x, b, dinv, y, y2); break;
     CSR_CASE(1) CSR_CASE(2) CSR_CASE(4) CSR_CASE(8) CSR_CASE(16) CSR_CASE(32) CSR_CASE(64)
 #undef CSR_CASE
-    default: k_csr<8, OP, T><<<nblocks((int64_t)A.n * 8, kBlock), kBlock, 0, st>>>(A.n, A.rp, A.ci, A.v, x, b, dinv, y);
+    default:
+      k_csr<8, OP, T><<<nblocks((int64_t)A.n * 8, kBlock), kBlock, 0, st>>>(A.n, A.rp, A.ci, A.v, x, b, dinv, y, y2);
   }
 }
 
@@ -1316,12 +1343,16 @@ void launch_l0_post(const SellT<T>& Ah, int ne, const T* x0, const T* b0, const 
 }
 
 template <class T>
-void launch_csr_resid_jacobi(const DCsrT<T>& A, const T* b, const T* dinv, T* r, hipStream_t st) {
-  launch_csr_op<kResidJacobi, T>(A, nullptr, b, dinv, r, st);
+void launch_csr_resid(const DCsrT<T>& A, const T* x0, const T* b, T* r, hipStream_t st) {
+  launch_csr_op<kResid, T>(A, x0, b, nullptr, r, st);
 }
 template <class T>
 void launch_csr_spmv(const DCsrT<T>& A, const T* x, T* y, hipStream_t st) {
   launch_csr_op<kSpmv, T>(A, x, nullptr, nullptr, y, st);
+}
+template <class T>
+void launch_csr_restrict(const DCsrT<T>& R, const T* r, const T* dinv_c, T* bc, T* xc, hipStream_t st) {
+  launch_csr_op<kRestrict, T>(R, r, nullptr, dinv_c, bc, st, xc);
 }
 template <class T>
 void launch_csr_prolong(const DCsrT<T>& P, const T* xc, const T* b, const T* dinv, T* x,
@@ -1331,6 +1362,18 @@ void launch_csr_prolong(const DCsrT<T>& P, const T* xc, const T* b, const T* din
 template <class T>
 void launch_csr_post(const DCsrT<T>& A, const T* x, const T* b, const T* dinv, T* e, hipStream_t st) {
   launch_csr_op<kPost, T>(A, x, b, dinv, e, st);
+}
+template <class T>
+void launch_sell_resid(const SellT<T>& A, const T* x0, const T* b, T* r, hipStream_t st) {
+  if (A.nrows == 0) return;
+  const int g = nblocks(A.nrows, kBlock);
+  k_sell_scalar<kResid, T><<<g, kBlock, 0, st>>>(A.nrows, g, A.sptr, A.col, A.val, x0, b, nullptr, r);
+}
+template <class T>
+void launch_sell_post(const SellT<T>& A, const T* x, const T* b, const T* dinv, T* e, hipStream_t st) {
+  if (A.nrows == 0) return;
+  const int g = nblocks(A.nrows, kBlock);
+  k_sell_scalar<kPost, T><<<g, kBlock, 0, st>>>(A.nrows, g, A.sptr, A.col, A.val, x, b, dinv, e);
 }
 
 template <class T>
@@ -1743,10 +1786,13 @@ void launch_update_host_coef(int64_t n, int nv, const double* V, int64_t ldv, co
                                       const int32_t*, T*, hipStream_t);                               \
   template void launch_l0_resid_jacobi<T>(const SellT<T>&, int, const T*, const T*, T*, hipStream_t); \
   template void launch_l0_post<T>(const SellT<T>&, int, const T*, const T*, const T*, T*, hipStream_t); \
-  template void launch_csr_resid_jacobi<T>(const DCsrT<T>&, const T*, const T*, T*, hipStream_t);    \
+  template void launch_csr_resid<T>(const DCsrT<T>&, const T*, const T*, T*, hipStream_t);           \
   template void launch_csr_spmv<T>(const DCsrT<T>&, const T*, T*, hipStream_t);                      \
+  template void launch_csr_restrict<T>(const DCsrT<T>&, const T*, const T*, T*, T*, hipStream_t);    \
   template void launch_csr_prolong<T>(const DCsrT<T>&, const T*, const T*, const T*, T*, hipStream_t); \
   template void launch_csr_post<T>(const DCsrT<T>&, const T*, const T*, const T*, T*, hipStream_t);  \
+  template void launch_sell_resid<T>(const SellT<T>&, const T*, const T*, T*, hipStream_t);          \
+  template void launch_sell_post<T>(const SellT<T>&, const T*, const T*, const T*, T*, hipStream_t); \
   template void launch_coarse_solve<T>(int, const double*, const int32_t*, const T*, T*, hipStream_t); \
   template void launch_stage2_resid<T>(const Sell&, int, const int32_t*, const T*, const double*, T*, \
                                        hipStream_t);                                                 \

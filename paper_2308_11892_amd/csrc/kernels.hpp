@@ -55,15 +55,29 @@ void launch_l0_resid_jacobi(const SellT<T>& Ah, int ne, const T* b0, const T* di
 template <class T>
 void launch_l0_post(const SellT<T>& Ah, int ne, const T* x0, const T* b0, const T* dinv, T* e0,
                     hipStream_t st);
+// Coarse-level V-cycle operators (scalar CSR, G lanes per row):
+//   resid:    r = b - A x0, with x0 = D^-1 b the pre-smoothed iterate
+//   spmv:     y = A x
+//   restrict: bc = R r and xc = D_c^-1 bc (the next level's right-hand side
+//             and pre-smoothed iterate)
+//   prolong:  x = D^-1 b + P xc
+//   post:     e = x + D^-1 (b - A x)
 template <class T>
-void launch_csr_resid_jacobi(const DCsrT<T>& A, const T* b, const T* dinv, T* r, hipStream_t st);
+void launch_csr_resid(const DCsrT<T>& A, const T* x0, const T* b, T* r, hipStream_t st);
 template <class T>
 void launch_csr_spmv(const DCsrT<T>& A, const T* x, T* y, hipStream_t st);
+template <class T>
+void launch_csr_restrict(const DCsrT<T>& R, const T* r, const T* dinv_c, T* bc, T* xc, hipStream_t st);
 template <class T>
 void launch_csr_prolong(const DCsrT<T>& P, const T* xc, const T* b, const T* dinv, T* x,
                         hipStream_t st);
 template <class T>
 void launch_csr_post(const DCsrT<T>& A, const T* x, const T* b, const T* dinv, T* e, hipStream_t st);
+// resid and post on a scalar SELL-64 operator (nv = 1, one thread per row)
+template <class T>
+void launch_sell_resid(const SellT<T>& A, const T* x0, const T* b, T* r, hipStream_t st);
+template <class T>
+void launch_sell_post(const SellT<T>& A, const T* x, const T* b, const T* dinv, T* e, hipStream_t st);
 template <class T>
 void launch_coarse_solve(int n, const double* lu, const int32_t* piv, const T* b, T* x,
                          hipStream_t st);
