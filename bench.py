@@ -39,7 +39,8 @@ def phase_bytes(c, rows, nnz, ne, grid):
     n0 = ne * nc
     out = {}
     out["spmv"] = 76 * nnzb + 4 * (nc + 1) + 16 * N
-    out["restrict"] = 8 * N + 8 * 2 * nc + 8 * n0
+    # r and W in; b0, and the pre-smoothed x0 = D^-1 b0 (with D^-1 read), out
+    out["restrict"] = 8 * N + 8 * 2 * nc + 8 * n0 + 16 * n0
     a0 = (8 * ne * ne + 4) * nnzb                     # Ahat blocks + column indices
     p0 = 12 * 4 * n0                                  # P_0 / R_0: at most 4 entries per row
     # level 0: (residual after zero-start smoothing + restriction) and

@@ -737,7 +737,8 @@ void enqueue_stage1(cptr_solver s, PrecDev<T>& d, const double* r, hipStream_t s
   auto& l0 = d.lev[0];
   hipEvent_t ev;
   ph_begin(s, st, ev);
-  launch_l0_restrict(s->host.nb, ne, r, s->W, s->eidx_h, s->hidx_h, l0.b, st);
+  launch_l0_restrict(s->host.nb, ne, r, s->W, s->eidx_h, s->hidx_h, l0.b, L > 1 ? l0.dinv : nullptr,
+                     l0.x, st);
   ph_end(s, st, PH_RESTRICT, ev);
   if (L == 1) {
     ph_begin(s, st, ev);
@@ -754,7 +755,7 @@ void enqueue_stage1(cptr_solver s, PrecDev<T>& d, const double* r, hipStream_t s
       else
         launch_csr_spmv(d.lev[l].R, r, nx.b, st);
     };
-    launch_l0_resid_jacobi(d.Ahat, ne, l0.b, l0.dinv, l0.r, st);
+    launch_l0_resid(d.Ahat, ne, l0.x, l0.b, l0.r, st);
     restrict_to(0, l0.r);
     ph_end(s, st, PH_VC0, ev);
     ph_begin(s, st, ev);

@@ -58,13 +58,19 @@ __global__ __launch_bounds__(kBlock) void k_bsr3_spmv(int nrows, int nblk, const
   const int s = row >> 6, lane = row & 63;
   const int k0 = sptr[s], k1 = sptr[s + 1];
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  // A is read once per product: non-temporal loads keep it from displacing x
+  // in the caches
+#pragma unroll 4
   for (int k = k0; k < k1; ++k) {
-    const int c = col[(size_t)k * 64 + lane];
+    const int c = __builtin_nontemporal_load(col + (size_t)k * 64 + lane);
     const double* v = val + (size_t)k * 9 * 64 + lane;
+    double m[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) m[e] = __builtin_nontemporal_load(v + e * 64);
     const double x0 = x[3 * (size_t)c], x1 = x[3 * (size_t)c + 1], x2 = x[3 * (size_t)c + 2];
-    a0 += v[0] * x0 + v[64] * x1 + v[128] * x2;
-    a1 += v[192] * x0 + v[256] * x1 + v[320] * x2;
-    a2 += v[384] * x0 + v[448] * x1 + v[512] * x2;
+    a0 += m[0] * x0 + m[1] * x1 + m[2] * x2;
+    a1 += m[3] * x0 + m[4] * x1 + m[5] * x2;
+    a2 += m[6] * x0 + m[7] * x1 + m[8] * x2;
   }
   double* yo = y + 3 * (size_t)row;
   if (RESID) {
@@ -82,47 +88,57 @@ __global__ __launch_bounds__(kBlock) void k_bsr3_spmv(int nrows, int nblk, const
 // --------------------------------------------------------------------------
 // quasi-IMPES restriction: b0_i = r_i[E] - W_i r_i[H]
 // (computed in FP64, stored in the preconditioner's type T)
+// (with dinv, also the pre-smoothed iterate x0 = D^-1 b0 of the V-cycle)
 template <int NE, class T>
 __global__ __launch_bounds__(kBlock) void k_l0_restrict(int nc, const double* __restrict__ r,
                                                         const double* __restrict__ W, int e0,
                                                         int e1, int h0, int h1,
-                                                        T* __restrict__ b0) {
+                                                        T* __restrict__ b0, const T* __restrict__ dinv,
+                                                        T* __restrict__ x0) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= nc) return;
   const double* ri = r + 3 * (size_t)i;
+  T bv[NE];
   if (NE == 2) {
     const double rh = ri[h0];
-    b0[2 * (size_t)i] = (T)(ri[e0] - W[2 * (size_t)i] * rh);
-    b0[2 * (size_t)i + 1] = (T)(ri[e1] - W[2 * (size_t)i + 1] * rh);
+    bv[0] = (T)(ri[e0] - W[2 * (size_t)i] * rh);
+    bv[NE - 1] = (T)(ri[e1] - W[2 * (size_t)i + 1] * rh);
   } else {
-    b0[i] = (T)(ri[e0] - W[2 * (size_t)i] * ri[h0] - W[2 * (size_t)i + 1] * ri[h1]);
+    bv[0] = (T)(ri[e0] - W[2 * (size_t)i] * ri[h0] - W[2 * (size_t)i + 1] * ri[h1]);
+  }
+#pragma unroll
+  for (int a = 0; a < NE; ++a) {
+    b0[(size_t)i * NE + a] = bv[a];
+    if (dinv) x0[(size_t)i * NE + a] = dinv[(size_t)i * NE + a] * bv[a];
   }
 }
 
-// r0 = b0 - Ahat (D^-1 b0): pre-smoothing from zero fused with the residual
+// r0 = b0 - Ahat x0 with x0 = D^-1 b0: the residual after pre-smoothing from
+// zero
 template <int NE, class T>
-__global__ __launch_bounds__(kBlock) void k_l0_resid_jacobi(int nc, int nblk, const int32_t* __restrict__ sptr,
-                                                            const int32_t* __restrict__ col,
-                                                            const T* __restrict__ val,
-                                                            const T* __restrict__ b0,
-                                                            const T* __restrict__ dinv,
-                                                            T* __restrict__ r0) {
+__global__ __launch_bounds__(kBlock) void k_l0_resid(int nc, int nblk, const int32_t* __restrict__ sptr,
+                                                     const int32_t* __restrict__ col,
+                                                     const T* __restrict__ val,
+                                                     const T* __restrict__ x0,
+                                                     const T* __restrict__ b0,
+                                                     T* __restrict__ r0) {
   const int row = xcd_block(blockIdx.x, nblk) * kBlock + threadIdx.x;
   if (row >= nc) return;
   const int s = row >> 6, lane = row & 63;
   T acc[NE];
 #pragma unroll
   for (int a = 0; a < NE; ++a) acc[a] = 0;
+#pragma unroll 4
   for (int k = sptr[s]; k < sptr[s + 1]; ++k) {
-    const int c = col[(size_t)k * 64 + lane];
+    const int c = __builtin_nontemporal_load(col + (size_t)k * 64 + lane);
     const T* v = val + (size_t)k * NE * NE * 64 + lane;
     T xc[NE];
 #pragma unroll
-    for (int q = 0; q < NE; ++q) xc[q] = dinv[(size_t)c * NE + q] * b0[(size_t)c * NE + q];
+    for (int q = 0; q < NE; ++q) xc[q] = x0[(size_t)c * NE + q];
 #pragma unroll
     for (int a = 0; a < NE; ++a)
 #pragma unroll
-      for (int q = 0; q < NE; ++q) acc[a] += v[(a * NE + q) * 64] * xc[q];
+      for (int q = 0; q < NE; ++q) acc[a] += __builtin_nontemporal_load(v + (a * NE + q) * 64) * xc[q];
   }
 #pragma unroll
   for (int a = 0; a < NE; ++a) r0[(size_t)row * NE + a] = b0[(size_t)row * NE + a] - acc[a];
@@ -143,8 +159,9 @@ __global__ __launch_bounds__(kBlock) void k_l0_post(int nc, int nblk, const int3
   T acc[NE];
 #pragma unroll
   for (int a = 0; a < NE; ++a) acc[a] = 0;
+#pragma unroll 4
   for (int k = sptr[s]; k < sptr[s + 1]; ++k) {
-    const int c = col[(size_t)k * 64 + lane];
+    const int c = __builtin_nontemporal_load(col + (size_t)k * 64 + lane);
     const T* v = val + (size_t)k * NE * NE * 64 + lane;
     T xc[NE];
 #pragma unroll
@@ -152,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_l0_post(int nc, int nblk, const int3
 #pragma unroll
     for (int a = 0; a < NE; ++a)
 #pragma unroll
-      for (int q = 0; q < NE; ++q) acc[a] += v[(a * NE + q) * 64] * xc[q];
+      for (int q = 0; q < NE; ++q) acc[a] += __builtin_nontemporal_load(v + (a * NE + q) * 64) * xc[q];
   }
 #pragma unroll
   for (int a = 0; a < NE; ++a) {
@@ -1079,18 +1096,19 @@ __global__ __launch_bounds__(kBlock) void k_stage2_grid(int nx, int ny, int nz, 
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   if (e0) {
     const int s = row >> 6, lane = row & 63;
+#pragma unroll 4
     for (int kq = sptr[s]; kq < sptr[s + 1]; ++kq) {
-      const int c = col[(size_t)kq * 64 + lane];
+      const int c = __builtin_nontemporal_load(col + (size_t)kq * 64 + lane);
       const double* v = val + (size_t)kq * 9 * 64 + lane;
       const double u = e0[(size_t)c * NE];
-      a0 += v[(0 * 3 + ea) * 64] * u;
-      a1 += v[(1 * 3 + ea) * 64] * u;
-      a2 += v[(2 * 3 + ea) * 64] * u;
+      a0 += __builtin_nontemporal_load(v + (0 * 3 + ea) * 64) * u;
+      a1 += __builtin_nontemporal_load(v + (1 * 3 + ea) * 64) * u;
+      a2 += __builtin_nontemporal_load(v + (2 * 3 + ea) * 64) * u;
       if (NE == 2) {
         const double w = e0[(size_t)c * NE + 1];
-        a0 += v[(0 * 3 + eb) * 64] * w;
-        a1 += v[(1 * 3 + eb) * 64] * w;
-        a2 += v[(2 * 3 + eb) * 64] * w;
+        a0 += __builtin_nontemporal_load(v + (0 * 3 + eb) * 64) * w;
+        a1 += __builtin_nontemporal_load(v + (1 * 3 + eb) * 64) * w;
+        a2 += __builtin_nontemporal_load(v + (2 * 3 + eb) * 64) * w;
       }
     }
   }
@@ -1314,22 +1332,21 @@ void launch_bsr3_spmv(const Sell& A, const double* x, const double* b, double* y
 
 template <class T>
 void launch_l0_restrict(int32_t nc, int ne, const double* r, const double* W, const int32_t* eidx,
-                        const int32_t* hidx, T* b0, hipStream_t st) {
+                        const int32_t* hidx, T* b0, const T* dinv, T* x0, hipStream_t st) {
   const int g = nblocks(nc, kBlock);
   if (ne == 2)
-    k_l0_restrict<2, T><<<g, kBlock, 0, st>>>(nc, r, W, eidx[0], eidx[1], hidx[0], 0, b0);
+    k_l0_restrict<2, T><<<g, kBlock, 0, st>>>(nc, r, W, eidx[0], eidx[1], hidx[0], 0, b0, dinv, x0);
   else
-    k_l0_restrict<1, T><<<g, kBlock, 0, st>>>(nc, r, W, eidx[0], 0, hidx[0], hidx[1], b0);
+    k_l0_restrict<1, T><<<g, kBlock, 0, st>>>(nc, r, W, eidx[0], 0, hidx[0], hidx[1], b0, dinv, x0);
 }
 
 template <class T>
-void launch_l0_resid_jacobi(const SellT<T>& Ah, int ne, const T* b0, const T* dinv, T* r0,
-                            hipStream_t st) {
+void launch_l0_resid(const SellT<T>& Ah, int ne, const T* x0, const T* b0, T* r0, hipStream_t st) {
   const int g = nblocks(Ah.nrows, kBlock);
   if (ne == 2)
-    k_l0_resid_jacobi<2, T><<<g, kBlock, 0, st>>>(Ah.nrows, g, Ah.sptr, Ah.col, Ah.val, b0, dinv, r0);
+    k_l0_resid<2, T><<<g, kBlock, 0, st>>>(Ah.nrows, g, Ah.sptr, Ah.col, Ah.val, x0, b0, r0);
   else
-    k_l0_resid_jacobi<1, T><<<g, kBlock, 0, st>>>(Ah.nrows, g, Ah.sptr, Ah.col, Ah.val, b0, dinv, r0);
+    k_l0_resid<1, T><<<g, kBlock, 0, st>>>(Ah.nrows, g, Ah.sptr, Ah.col, Ah.val, x0, b0, r0);
 }
 
 template <class T>
@@ -1783,8 +1800,8 @@ void launch_update_host_coef(int64_t n, int nv, const double* V, int64_t ldv, co
 // the preconditioner runs in FP64 or, in the mixed-precision mode, in FP32
 #define CPTR_PREC_LAUNCHERS(T)                                                                      \
   template void launch_l0_restrict<T>(int32_t, int, const double*, const double*, const int32_t*,   \
-                                      const int32_t*, T*, hipStream_t);                               \
-  template void launch_l0_resid_jacobi<T>(const SellT<T>&, int, const T*, const T*, T*, hipStream_t); \
+                                      const int32_t*, T*, const T*, T*, hipStream_t);                 \
+  template void launch_l0_resid<T>(const SellT<T>&, int, const T*, const T*, T*, hipStream_t);        \
   template void launch_l0_post<T>(const SellT<T>&, int, const T*, const T*, const T*, T*, hipStream_t); \
   template void launch_csr_resid<T>(const DCsrT<T>&, const T*, const T*, T*, hipStream_t);           \
   template void launch_csr_spmv<T>(const DCsrT<T>&, const T*, T*, hipStream_t);                      \

@@ -46,12 +46,16 @@ void launch_bsr3_spmv(const Sell& A, const double* x, const double* b, double* y
 // The preconditioner's launchers take its value type T: double, or float in
 // the mixed-precision mode (A, the restriction weights and the coarsest LU stay
 // FP64 in both).
+// Level 0 of the V-cycle on Ahat:
+//   restrict: b0 = quasi-IMPES restriction of r, and with dinv also the
+//             pre-smoothed iterate x0 = D^-1 b0 (dinv null: b0 only)
+//   resid:    r0 = b0 - Ahat x0
+//   post:     e0 = x0 + D^-1 (b0 - Ahat x0)
 template <class T>
 void launch_l0_restrict(int32_t nc, int ne, const double* r, const double* W, const int32_t* eidx,
-                        const int32_t* hidx, T* b0, hipStream_t st);
+                        const int32_t* hidx, T* b0, const T* dinv, T* x0, hipStream_t st);
 template <class T>
-void launch_l0_resid_jacobi(const SellT<T>& Ah, int ne, const T* b0, const T* dinv, T* r0,
-                            hipStream_t st);
+void launch_l0_resid(const SellT<T>& Ah, int ne, const T* x0, const T* b0, T* r0, hipStream_t st);
 template <class T>
 void launch_l0_post(const SellT<T>& Ah, int ne, const T* x0, const T* b0, const T* dinv, T* e0,
                     hipStream_t st);
