@@ -135,10 +135,11 @@ void cptr_solve_opts_default(cptr_solve_opts *o);
  *   opts          NULL for defaults;
  *   stream        hipStream_t (void*) receiving the uploads;
  *   out           receives the handle on success (NULL on failure).
- * The AMG hierarchy is built on the host.  ILU(0) is factored on the host,
- * except for a device handle whose A is a 7-point stencil in lexicographic
- * order with the grid sweeps in use: there the factors are computed on the
- * device from A (the same ILU(0) up to rounding).
+ * The AMG hierarchy is built on the host.  A device handle factors ILU(0) on
+ * the device (rows of one dependency level at a time, each in the host
+ * factorisation's order and rounding, so the factors equal the host's); a
+ * host-only handle factors it on the host.  A's device layout and the reduced
+ * elliptic blocks are also formed on the device.
  * Errors: CPTR_E_INVALID (null pointer, block size, indices, unsorted or
  * duplicate columns, missing diagonal block, non-finite value),
  * CPTR_E_ZERO_PIVOT (zero ILU(0) pivot, singular hyperbolic diagonal block,
@@ -196,8 +197,8 @@ enum {
   CPTR_EXPORT_ILU_VALS = 9,  /* double[nnz_blocks * 9]: L below the diagonal
                                 (unit diagonal blocks implied), U on and above,
                                 with the diagonal blocks stored as U_ii (not inverted);
-                                CPTR_E_STATE for a device handle on a 7-point grid,
-                                whose factors are computed on the device */
+                                CPTR_E_STATE for a device handle, whose
+                                factors are computed on the device */
   CPTR_EXPORT_ILU_NLEVELS = 10, /* int32[2]: forward and backward dependency levels */
   CPTR_EXPORT_SWEEP = 11       /* int32[4]: ILU sweep schedule in use (CPTR_ILU_SWEEP_*),
                                   then nx, ny, nz of the detected grid (0 if none) */

@@ -154,7 +154,7 @@ struct cptr_solver_s {
   int sf_width = 0;          // register slots of the one-launch sweeps; 0 = per-level launches
   int grid[3] = {0, 0, 0};   // nx, ny, nz when A is a 7-point stencil in lexicographic order
   bool use_grid = false;     // tiled systolic sweeps on that grid
-  bool device_ilu = false;   // ILU(0) factored on the device (grid sweeps; no host factors)
+  bool device_ilu = false;   // ILU(0) factored on the device (every device handle; no host factors)
   int* tickets = nullptr;    // [2] workgroup ticket counters of the one-launch sweeps
   double* coarse_lu = nullptr;
   int32_t* coarse_piv = nullptr;
@@ -414,67 +414,75 @@ int build_grid_factors_device(cptr_solver s, PrecDev<T>& d, hipStream_t st) {
   return CPTR_OK;
 }
 
+// ILU(0) factors of any matrix for the level-ordered sweeps, factored on the
+// device: the slice widths of Lf (forward positions) and Ub (backward
+// positions) come from the host's row pointers and diagonals, the values from
+// launch_ilu_rows on a copy of A's SELL values.
 template <class T>
-int build_grid_factors(cptr_solver s, PrecDev<T>& d, hipStream_t st) {
-  if (s->device_ilu) return build_grid_factors_device(s, d, st);
+int build_ilu_factors_device(cptr_solver s, PrecDev<T>& d, const std::vector<int32_t>& fp,
+                             const std::vector<int32_t>& bp, hipStream_t st) {
   const HostSetup& h = s->host;
-  const int nx = s->grid[0], ny = s->grid[1], nz = s->grid[2];
-  const int32_t nxy = nx * ny;
-  const int64_t rows = grid_ntiles(ny, nz) * grid_nsteps(nx);   // 64-lane rows of either layout
+  const int32_t nb = h.nb;
+  auto nolen = [](int32_t, int32_t, int32_t&, double*) {};
+  HostSell Lh = pack_sell(nb, 9, [&](int32_t p) { return h.diag[fp[p]] - h.rp[fp[p]]; }, nolen, -1, true, 1);
+  HostSell Uh = pack_sell(nb, 9, [&](int32_t p) { return h.rp[bp[p] + 1] - h.diag[bp[p]] - 1; }, nolen, -1, true, 1);
+  if (s->sf_width == 0 && s->ilu_mode != CPTR_ILU_SWEEP_LEVELS) {
+    int maxw = 0;
+    for (int32_t sl = 0; sl < Lh.nslices; ++sl) maxw = std::max(maxw, Lh.sptr[sl + 1] - Lh.sptr[sl]);
+    for (int32_t sl = 0; sl < Uh.nslices; ++sl) maxw = std::max(maxw, Uh.sptr[sl + 1] - Uh.sptr[sl]);
+    const int w = ilu_sf_width(maxw);
+    if (s->ilu_mode == CPTR_ILU_SWEEP_ONE_LAUNCH && w == 0)
+      return fail(s, CPTR_E_INVALID,
+                  "rows too wide (" + std::to_string(maxw) + " blocks) for one-launch ILU sweeps");
+    s->sf_width = w;
+  }
   int rc;
-  if (s->measure) {
-    if ((rc = dalloc(s, d.Lg, rows * 27 * 64)) || (rc = dalloc(s, d.Ug, rows * 36 * 64)) ||
-        (rc = dalloc(s, d.ytile, rows * 3 * 64)) || (rc = dalloc(s, d.r2tile, rows * 3 * 64)) ||
-        (rc = dalloc(s, d.e0tile, rows * 2 * 64)) || (rc = dalloc(s, d.faces, 2 * grid_face_values(nx, ny, nz))))
-      return rc;
-    return CPTR_OK;
-  }
-  // packed straight in T (no FP64 staging copy in the mixed-precision form)
-  std::vector<T> lt((size_t)rows * 27 * 64, T(0)), ut((size_t)rows * 36 * 64, T(0));
-  // every cell owns its own lane of its own rows: the cells split freely
-  parallel_ranges(h.nb, s->threads, [&](int64_t c0, int64_t c1) {
-  for (int32_t c = (int32_t)c0; c < (int32_t)c1; ++c) {
-    const int i = c % nx, j = (c / nx) % ny, k = c / nxy;
-    int64_t fr, br;
-    int lane;
-    grid_tile_slot(nx, ny, i, j, k, fr, br, lane);
-    for (int32_t q = h.rp[c]; q < h.rp[c + 1]; ++q) {
-      const int32_t d = h.ci[q] - c;
-      const double* blk = &h.ilu[(size_t)q * 9];
-      int slot;
-      T* dst;
-      int nv;
-      int64_t row;
-      if (d == -1 || d == -nx || d == -nxy) {
-        slot = d == -1 ? 0 : d == -nx ? 1 : 2;
-        dst = lt.data();
-        nv = 27;
-        row = fr;
-      } else if (d == 1 || d == nx || d == nxy) {
-        slot = d == 1 ? 0 : d == nx ? 1 : 2;
-        dst = ut.data();
-        nv = 36;
-        row = br;
-      } else {
-        continue;
-      }
-      for (int e = 0; e < 9; ++e) dst[((size_t)row * nv + 9 * slot + e) * 64 + lane] = (T)blk[e];
-    }
-    for (int e = 0; e < 9; ++e) ut[((size_t)br * 36 + 27 + e) * 64 + lane] = (T)h.uinv[(size_t)c * 9 + e];
-  }
-  });
-  if ((rc = upload(s, d.Lg, lt.data(), (int64_t)lt.size(), st))) return rc;
-  if ((rc = upload(s, d.Ug, ut.data(), (int64_t)ut.size(), st))) return rc;
-  // padding slots of the tile vectors stay zero forever (no kernel writes them)
-  if ((rc = dalloc(s, d.ytile, rows * 3 * 64))) return rc;
-  if ((rc = dalloc(s, d.r2tile, rows * 3 * 64))) return rc;
-  if ((rc = dalloc(s, d.e0tile, rows * 2 * 64))) return rc;
-  if (!s->measure) {
-    HIP_TRY(s, hipMemset(d.ytile, 0, sizeof(T) * (size_t)rows * 3 * 64));
-    HIP_TRY(s, hipMemset(d.r2tile, 0, sizeof(T) * (size_t)rows * 3 * 64));
-    HIP_TRY(s, hipMemset(d.e0tile, 0, sizeof(T) * (size_t)rows * 2 * 64));
-  }
-  if ((rc = dalloc(s, d.faces, 2 * grid_face_values(nx, ny, nz)))) return rc;
+  auto alloc_sell = [&](SellT<T>& o, const HostSell& hs) -> int {
+    o.nrows = hs.nrows;
+    o.nslices = hs.nslices;
+    o.nv = 9;
+    o.nslots = hs.sptr.back();
+    int r = upload(s, o.sptr, hs.sptr.data(), (int64_t)hs.sptr.size(), st);
+    if (!r) r = dalloc(s, o.col, o.nslots * kLanes);
+    if (!r) r = dalloc(s, o.val, o.nslots * kLanes * 9);
+    return r;
+  };
+  if ((rc = alloc_sell(d.Lf, Lh)) || (rc = alloc_sell(d.Ub, Uh))) return rc;
+  const int64_t npad = (int64_t)Uh.nslices * kLanes;
+  if ((rc = dalloc(s, d.uinv, npad * 9))) return rc;
+  // temporaries: the factored copy of A, U_ii^-1 in FP64, rows, diagonal slots
+  std::vector<int32_t> dslot((size_t)nb);
+  for (int32_t i = 0; i < nb; ++i) dslot[i] = h.diag[i] - h.rp[i];
+  double* W = nullptr;
+  double* uinv = nullptr;
+  int32_t* rp_d = nullptr;
+  int32_t* ds_d = nullptr;
+  int* bad = nullptr;
+  if ((rc = dalloc(s, W, s->A.nslots * kLanes * 9)) || (rc = dalloc(s, uinv, (int64_t)nb * 9)) ||
+      (rc = upload(s, rp_d, h.rp.data(), (int64_t)nb + 1, st)) ||
+      (rc = upload(s, ds_d, dslot.data(), (int64_t)nb, st)) || (rc = dalloc(s, bad, 1)))
+    return rc;
+  if (s->measure) return CPTR_OK;
+  const int none = INT32_MAX;
+  HIP_TRY(s, hipMemcpy(bad, &none, sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(s, hipMemcpyAsync(W, s->A.val, sizeof(double) * (size_t)s->A.nslots * kLanes * 9,
+                            hipMemcpyDeviceToDevice, st));
+  for (size_t l = 0; l + 1 < s->flev_ptr.size(); ++l)
+    launch_ilu_rows(s->A, s->fperm, s->flev_ptr[l], s->flev_ptr[l + 1], rp_d, ds_d, W, uinv, bad, st);
+  launch_ilu_pack(s->A, rp_d, ds_d, W, uinv, s->fperm, s->bperm, d.Lf, d.Ub, d.uinv, st);
+  HIP_TRY(s, hipGetLastError());
+  int first_bad = none;
+  HIP_TRY(s, hipMemcpyAsync(&first_bad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(s, hipStreamSynchronize(st));
+  // the temporaries go back; the handle's counted footprint keeps them (peak)
+  dfree(s, W);
+  dfree(s, uinv);
+  dfree(s, rp_d);
+  dfree(s, ds_d);
+  dfree(s, bad);
+  if (first_bad != none)
+    return fail(s, CPTR_E_ZERO_PIVOT,
+                "zero ILU(0) pivot (singular diagonal block) in block row " + std::to_string(first_bad));
   return CPTR_OK;
 }
 
@@ -504,45 +512,9 @@ int build_prec(cptr_solver s, PrecDev<T>& d, const std::vector<int32_t>& fp,
   // ILU factors: in the tile layouts of the grid sweeps, or by dependency
   // level for the one-launch and per-level sweeps (only one of the two is kept)
   if (s->use_grid) {
-    if ((rc = build_grid_factors(s, d, st))) return rc;
+    if ((rc = build_grid_factors_device(s, d, st))) return rc;
   } else {
-    HostSell Lh = pack_sell(
-        nb, 9, [&](int32_t p) { return h.diag[fp[p]] - h.rp[fp[p]]; },
-        [&](int32_t p, int32_t k, int32_t& c, double* v) {
-          const int32_t q = h.rp[fp[p]] + k;
-          c = h.ci[q];
-          std::memcpy(v, &h.ilu[(size_t)q * 9], 9 * sizeof(double));
-        },
-        -1, s->measure, s->threads);
-    if ((rc = upload_sell(s, d.Lf, Lh, st))) return rc;
-    HostSell Uh = pack_sell(
-        nb, 9, [&](int32_t p) { return h.rp[bp[p] + 1] - h.diag[bp[p]] - 1; },
-        [&](int32_t p, int32_t k, int32_t& c, double* v) {
-          const int32_t q = h.diag[bp[p]] + 1 + k;
-          c = h.ci[q];
-          std::memcpy(v, &h.ilu[(size_t)q * 9], 9 * sizeof(double));
-        },
-        -1, s->measure, s->threads);
-    if ((rc = upload_sell(s, d.Ub, Uh, st))) return rc;
-    if (s->sf_width == 0 && s->ilu_mode != CPTR_ILU_SWEEP_LEVELS) {
-      int maxw = 0;
-      for (int32_t sl = 0; sl < Lh.nslices; ++sl) maxw = std::max(maxw, Lh.sptr[sl + 1] - Lh.sptr[sl]);
-      for (int32_t sl = 0; sl < Uh.nslices; ++sl) maxw = std::max(maxw, Uh.sptr[sl + 1] - Uh.sptr[sl]);
-      const int w = ilu_sf_width(maxw);
-      if (s->ilu_mode == CPTR_ILU_SWEEP_ONE_LAUNCH && w == 0)
-        return fail(s, CPTR_E_INVALID,
-                    "rows too wide (" + std::to_string(maxw) + " blocks) for one-launch ILU sweeps");
-      s->sf_width = w;
-    }
-    const int64_t npad = (int64_t)Uh.nslices * kLanes;
-    if (s->measure) {
-      if ((rc = dalloc(s, d.uinv, npad * 9))) return rc;
-    } else {
-      std::vector<double> ui((size_t)npad * 9, 0.0);
-      for (int32_t p = 0; p < nb; ++p)
-        for (int e = 0; e < 9; ++e) ui[(size_t)e * npad + p] = h.uinv[(size_t)bp[p] * 9 + e];
-      if ((rc = upload_as(s, d.uinv, ui.data(), (int64_t)ui.size(), st))) return rc;
-    }
+    if ((rc = build_ilu_factors_device(s, d, fp, bp, st))) return rc;
   }
   // AMG hierarchy (the coarsest LU stays FP64 and is shared)
   const int L = (int)h.lev.size();
@@ -1006,11 +978,8 @@ int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_id
   int rc = validate_bsr(nb, nnzb, prp, pci, pv, err);
   if (rc) return (cptr_status)fail(nullptr, rc, err);
   SetupParams prm;
-  // a device handle on a 7-point grid (grid sweeps) factors ILU(0) on the device
-  int gdims[3] = {0, 0, 0};
-  const bool dev_ilu = !o.host_only &&
-                       (o.ilu_sweep == CPTR_ILU_SWEEP_AUTO || o.ilu_sweep == CPTR_ILU_SWEEP_GRID) &&
-                       detect_grid(nb, prp, pci, gdims);
+  // a device handle factors ILU(0) on the device
+  const bool dev_ilu = !o.host_only;
   prm.skip_ilu = dev_ilu;
   prm.theta = o.strong_threshold;
   prm.max_row_sum = o.max_row_sum;

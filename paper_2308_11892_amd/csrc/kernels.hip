@@ -1478,7 +1478,9 @@ void launch_stage2_grid(int nx, int ny, int nz, const Sell& A, int ne, const int
 // neighbour k of cell c (c - nx*ny, c - nx, c - 1) contributes L_ck = A_ck
 // U_kk^-1 and U_cc = A_cc - sum_k L_ck A_kc (k in increasing column order), the
 // blocks right of the diagonal are A's own.
+// (no FP contraction in these two: they round like the host factorisation's)
 __device__ __forceinline__ void mm3_dev(const double* a, const double* b, double* c) {
+#pragma clang fp contract(off)
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -1491,6 +1493,7 @@ __device__ __forceinline__ void mm3_dev(const double* a, const double* b, double
 }
 // 3x3 inverse by Gauss-Jordan with partial pivoting; false for a zero pivot
 __device__ __forceinline__ bool inv3_dev(const double* m, double* out) {
+#pragma clang fp contract(off)
   double a[3][6];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
@@ -1604,6 +1607,130 @@ __global__ __launch_bounds__(kBlock) void k_grid_ilu_pack(int nb, int nx, int ny
   }
 #pragma unroll
   for (int e = 0; e < 9; ++e) Ut[((size_t)br * 36 + 27 + e) * 64 + lane] = (T)uinv[(size_t)c * 9 + e];
+}
+
+// Block ILU(0) of any block-sparse A (Sec. 3.1) on W, a copy of A's SELL-64
+// values: one launch per forward dependency level, one thread per row, each
+// row in the host factorisation's order: for its lower blocks in column
+// order, L_ic = W_ic U_cc^-1 and W_it -= L_ic U_ct over the U blocks of row c
+// that row i also holds; then U_ii^-1.  Rows of a level depend only on rows
+// of earlier levels.  dslot: the diagonal's slot in each row.  A singular
+// U_ii leaves zeros and lowers *bad to the row.
+__global__ __launch_bounds__(kBlock) void k_ilu_rows(int p0, int p1, const int32_t* __restrict__ fperm,
+                                                     const int32_t* __restrict__ sptr,
+                                                     const int32_t* __restrict__ col,
+                                                     const int32_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ dslot, double* __restrict__ W,
+                                                     double* __restrict__ uinv, int* __restrict__ bad) {
+#pragma clang fp contract(off)
+  const int p = p0 + blockIdx.x * kBlock + threadIdx.x;
+  if (p >= p1) return;
+  const int i = fperm[p];
+  const int lane = i & 63;
+  const size_t k0 = (size_t)sptr[i >> 6];
+  const int n = rp[i + 1] - rp[i], d = dslot[i];
+  for (int q = 0; q < d; ++q) {
+    const int c = col[(k0 + q) * 64 + lane];
+    double a[9], Lq[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) a[e] = W[((k0 + q) * 9 + e) * 64 + lane];
+    mm3_dev(a, uinv + (size_t)c * 9, Lq);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) W[((k0 + q) * 9 + e) * 64 + lane] = Lq[e];
+    const int lc = c & 63;
+    const size_t kc0 = (size_t)sptr[c >> 6];
+    const int nc = rp[c + 1] - rp[c];
+    int t = q + 1;
+    for (int u = dslot[c] + 1; u < nc; ++u) {
+      const int cu = col[(kc0 + u) * 64 + lc];
+      while (t < n && col[(k0 + t) * 64 + lane] < cu) ++t;
+      if (t == n) break;
+      if (col[(k0 + t) * 64 + lane] != cu) continue;
+      double ub[9], prod[9];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) ub[e] = W[((kc0 + u) * 9 + e) * 64 + lc];
+      mm3_dev(Lq, ub, prod);
+#pragma unroll
+      for (int e = 0; e < 9; ++e) {
+        double& x = W[((k0 + t) * 9 + e) * 64 + lane];
+        x = x - prod[e];
+      }
+    }
+  }
+  double dg[9], inv[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) dg[e] = W[((k0 + d) * 9 + e) * 64 + lane];
+  if (!inv3_dev(dg, inv)) {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) inv[e] = 0.0;
+    atomicMin(bad, i);
+  }
+#pragma unroll
+  for (int e = 0; e < 9; ++e) uinv[(size_t)i * 9 + e] = inv[e];
+}
+
+// The factored blocks of the rows perm[p] into a SELL-64 over positions p:
+// the L blocks (lower) or the U blocks right of the diagonal; padding slots
+// get column -1 and zero values.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_ilu_pack_sell(int nb, int npos, const int32_t* __restrict__ perm,
+                                                          int lower, const int32_t* __restrict__ sptrA,
+                                                          const int32_t* __restrict__ colA,
+                                                          const int32_t* __restrict__ rp,
+                                                          const int32_t* __restrict__ dslot,
+                                                          const double* __restrict__ W,
+                                                          const int32_t* __restrict__ sptrF,
+                                                          int32_t* __restrict__ colF, T* __restrict__ valF) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  if (p >= npos) return;
+  const int sl = p >> 6, lp = p & 63;
+  const int w = sptrF[sl + 1] - sptrF[sl];
+  const bool live = p < nb;
+  const int i = live ? perm[p] : 0;
+  const int li = i & 63;
+  const size_t k0 = (size_t)sptrA[i >> 6];
+  const int d = dslot[i];
+  const int first = lower ? 0 : d + 1;
+  const int cnt = live ? (lower ? d : rp[i + 1] - rp[i] - d - 1) : 0;
+  for (int k = 0; k < w; ++k) {
+    const size_t slot = (size_t)sptrF[sl] + k;
+    const bool real = k < cnt;
+    colF[slot * 64 + lp] = real ? colA[(k0 + first + k) * 64 + li] : -1;
+#pragma unroll
+    for (int e = 0; e < 9; ++e)
+      valF[(slot * 9 + e) * 64 + lp] = real ? (T)W[((k0 + first + k) * 9 + e) * 64 + li] : T(0);
+  }
+}
+
+// U_ii^-1 by backward position, planar: out[e * npad + p] (zero past nb)
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_ilu_pack_uinv(int nb, int npad, const int32_t* __restrict__ bperm,
+                                                          const double* __restrict__ uinv,
+                                                          T* __restrict__ out) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  if (p >= npad) return;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) out[(size_t)e * npad + p] = p < nb ? (T)uinv[(size_t)bperm[p] * 9 + e] : T(0);
+}
+
+void launch_ilu_rows(const Sell& A, const int32_t* fperm, int32_t p0, int32_t p1, const int32_t* rp,
+                     const int32_t* dslot, double* W, double* uinv, int* bad, hipStream_t st) {
+  if (p1 <= p0) return;
+  k_ilu_rows<<<nblocks(p1 - p0, kBlock), kBlock, 0, st>>>(p0, p1, fperm, A.sptr, A.col, rp, dslot, W, uinv,
+                                                          bad);
+}
+
+template <class T>
+void launch_ilu_pack(const Sell& A, const int32_t* rp, const int32_t* dslot, const double* W, const double* uinv,
+                     const int32_t* fperm, const int32_t* bperm, SellT<T>& Lf, SellT<T>& Ub, T* uinv_t,
+                     hipStream_t st) {
+  const int nb = A.nrows;
+  const int nl = Lf.nslices * 64, nu = Ub.nslices * 64;
+  k_ilu_pack_sell<T><<<nblocks(nl, kBlock), kBlock, 0, st>>>(nb, nl, fperm, 1, A.sptr, A.col, rp, dslot, W,
+                                                             Lf.sptr, Lf.col, Lf.val);
+  k_ilu_pack_sell<T><<<nblocks(nu, kBlock), kBlock, 0, st>>>(nb, nu, bperm, 0, A.sptr, A.col, rp, dslot, W,
+                                                             Ub.sptr, Ub.col, Ub.val);
+  k_ilu_pack_uinv<T><<<nblocks(nu, kBlock), kBlock, 0, st>>>(nb, nu, bperm, uinv, uinv_t);
 }
 
 // A's 3x3 blocks into SELL-64 slots, one thread per row of the whole slices
@@ -1822,6 +1949,9 @@ void launch_update_host_coef(int64_t n, int nv, const double* V, int64_t ldv, co
   template void launch_stage2_grid<T>(int, int, int, const Sell&, int, const int32_t*, const T*,     \
                                       const double*, T*, T*, T*, int*, hipStream_t);                 \
   template void launch_grid_ilu_pack<T>(const Sell&, int, int, const double*, T*, T*, hipStream_t);  \
+  template void launch_ilu_pack<T>(const Sell&, const int32_t*, const int32_t*, const double*,       \
+                                   const double*, const int32_t*, const int32_t*, SellT<T>&, SellT<T>&, \
+                                   T*, hipStream_t);                                                 \
   template void launch_sell_ahat<T>(const Sell&, const double*, int, const int32_t*, const int32_t*,  \
                                     T*, hipStream_t);                                                 \
   template void launch_ilu_fwd_grid<T>(int, int, int, const T*, const T*, T*, T*, int*, double*, long, \

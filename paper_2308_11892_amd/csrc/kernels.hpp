@@ -136,6 +136,20 @@ void launch_grid_ilu_diag(const Sell& A, const int32_t* fperm, int32_t p0, int32
 template <class T>
 void launch_grid_ilu_pack(const Sell& A, int nx, int ny, const double* uinv, T* Lt, T* Ut,
                           hipStream_t st);
+// Block ILU(0) of any block-sparse A on the device.  W: a copy of A's SELL-64
+// values, factored in place (L left of the diagonal, U on and right of it);
+// one launch_ilu_rows per forward dependency level (positions [p0, p1) of
+// fperm), rows in the host factorisation's order and rounding; uinv (FP64, 9
+// per row) gets U_ii^-1, a singular U_ii leaves zeros and lowers *bad to the
+// row.  rp: A's row pointers, dslot: the diagonal's slot in each row (device).
+// launch_ilu_pack then writes the sweeps' layouts: Lf (by forward position),
+// Ub and uinv_t (planar, by backward position), their sptr filled beforehand.
+void launch_ilu_rows(const Sell& A, const int32_t* fperm, int32_t p0, int32_t p1, const int32_t* rp,
+                     const int32_t* dslot, double* W, double* uinv, int* bad, hipStream_t st);
+template <class T>
+void launch_ilu_pack(const Sell& A, const int32_t* rp, const int32_t* dslot, const double* W, const double* uinv,
+                     const int32_t* fperm, const int32_t* bperm, SellT<T>& Lf, SellT<T>& Ub, T* uinv_t,
+                     hipStream_t st);
 // A (3x3 blocks, CSR order) into its SELL-64 layout, for the whole slices of
 // rows [r0, r_end) (r0 a multiple of 64, r_end a multiple of 64 or the padded
 // end); rp on the device; the rows' columns and blocks staged from q0 = rp[r0].

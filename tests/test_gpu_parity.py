@@ -319,12 +319,14 @@ def test_cptr_against_cpr_on_the_peclet_sweep():
     assert max(its["cptr"]) - min(its["cptr"]) <= 1
 
 
-def test_device_ilu_zero_pivot_matches_host():
-    """On 7-point grids a device handle factors ILU(0) on the GPU; a singular
-    diagonal block is reported like the host factorisation does (same row)."""
-    c = J.small(3, 3, 2)
+@pytest.mark.parametrize("name,row", [("grid3x3x2", 2), ("prism2000x5", 0)])
+def test_device_ilu_zero_pivot_matches_host(name, row):
+    """A device handle factors ILU(0) on the GPU; a singular diagonal block is
+    reported like the host factorisation does (same row), on a grid and on an
+    unstructured mesh."""
+    c = J.small(3, 3, 2) if name == "grid3x3x2" else J.by_name(name)
     v = c.values.copy()
-    k = [q for q in range(c.row_ptr[2], c.row_ptr[3]) if c.col_idx[q] == 2][0]
+    k = [q for q in range(c.row_ptr[row], c.row_ptr[row + 1]) if c.col_idx[q] == row][0]
     v[k, 2, 2] = 0.0
     v[k, 0:2, 2] = 0.0
     v[k, 2, 0:2] = 0.0
@@ -337,8 +339,9 @@ def test_device_ilu_zero_pivot_matches_host():
     assert "ILU" in msgs[1] and msgs[0] == msgs[1], msgs
 
 
-def test_device_ilu_export_refused_on_grids():
-    c = J.by_name("grid7x5x3")
+@pytest.mark.parametrize("name", ["grid7x5x3", "prism2000x5"])
+def test_device_ilu_export_refused(name):
+    c = J.by_name(name)
     with L.Solver(c.row_ptr, c.col_idx, c.values) as s:
         with pytest.raises(L.CptrError) as e:
             s.export("ILU_VALS", 0, c.nnzb * 9)
