@@ -111,7 +111,8 @@ typedef struct {
   int32_t flexible;          /* 0: right GMRES (x += M^-1 V y), 1: FGMRES (x += Z y) */
   int32_t x0_is_zero;        /* 1: ignore x on entry and start from 0, default 1 */
   double rtol;               /* stop when ||b - A x||_2 <= rtol ||b||_2, default 1e-6 */
-  int32_t profile;           /* 1: time each kernel phase with HIP events (cptr_phase_times) */
+  int32_t profile;           /* 1: time each kernel phase with HIP events (cptr_phase_times);
+                                a value > 1 times only the phases k whose bit k + 1 is set */
 } cptr_solve_opts;
 
 typedef struct {

@@ -176,6 +176,7 @@ struct cptr_solver_s {
   double* hhost = nullptr;  // pinned copy
   // profiling
   bool profiling = false;
+  uint32_t profile_mask = 0;  // phases timed while profiling
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
@@ -674,9 +675,9 @@ int build_device(cptr_solver s, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------- profiling
-void ph_begin(cptr_solver s, hipStream_t st, hipEvent_t& ev) {
+void ph_begin(cptr_solver s, hipStream_t st, int phase, hipEvent_t& ev) {
   ev = nullptr;
-  if (!s->profiling) return;
+  if (!s->profiling || !(s->profile_mask & (1u << phase))) return;
   if (s->ev_used + 2 > s->ev_pool.size()) return;
   ev = s->ev_pool[s->ev_used++];
   (void)hipEventRecord(ev, st);
@@ -708,16 +709,16 @@ void enqueue_stage1(cptr_solver s, PrecDev<T>& d, const double* r, hipStream_t s
   const int L = (int)d.lev.size();
   auto& l0 = d.lev[0];
   hipEvent_t ev;
-  ph_begin(s, st, ev);
+  ph_begin(s, st, PH_RESTRICT, ev);
   launch_l0_restrict(s->host.nb, ne, r, s->W, s->eidx_h, s->hidx_h, l0.b, L > 1 ? l0.dinv : nullptr,
                      l0.x, st);
   ph_end(s, st, PH_RESTRICT, ev);
   if (L == 1) {
-    ph_begin(s, st, ev);
+    ph_begin(s, st, PH_VCC, ev);
     launch_coarse_solve(s->ncoarse, s->coarse_lu, s->coarse_piv, l0.b, l0.e, st);
     ph_end(s, st, PH_VCC, ev);
   } else {
-    ph_begin(s, st, ev);
+    ph_begin(s, st, PH_VC0, ev);
     // restrictions to a smoothed level also write its pre-smoothed iterate
     // x = D^-1 b, which its residual then reads
     auto restrict_to = [&](int l, const T* r) {
@@ -730,7 +731,7 @@ void enqueue_stage1(cptr_solver s, PrecDev<T>& d, const double* r, hipStream_t s
     launch_l0_resid(d.Ahat, ne, l0.x, l0.b, l0.r, st);
     restrict_to(0, l0.r);
     ph_end(s, st, PH_VC0, ev);
-    ph_begin(s, st, ev);
+    ph_begin(s, st, PH_VCC, ev);
     for (int l = 1; l + 1 < L; ++l) {
       auto& dl = d.lev[l];
       if (dl.sell)
@@ -749,7 +750,7 @@ void enqueue_stage1(cptr_solver s, PrecDev<T>& d, const double* r, hipStream_t s
         launch_csr_post(dl.A, dl.x, dl.b, dl.dinv, dl.e, st);
     }
     ph_end(s, st, PH_VCC, ev);
-    ph_begin(s, st, ev);
+    ph_begin(s, st, PH_VC0, ev);
     launch_csr_prolong(l0.P, d.lev[1].e, l0.b, l0.dinv, l0.x, st);
     launch_l0_post(d.Ahat, ne, l0.x, l0.b, l0.dinv, l0.e, st);
     ph_end(s, st, PH_VC0, ev);
@@ -764,15 +765,15 @@ void enqueue_stage2(cptr_solver s, PrecDev<T>& d, const double* r, const T* e0, 
   hipEvent_t ev;
   if (s->use_grid) {
     const int nx = s->grid[0], ny = s->grid[1], nz = s->grid[2];
-    ph_begin(s, st, ev);
+    ph_begin(s, st, PH_STAGE2, ev);
     launch_stage2_grid(nx, ny, nz, s->A, ne, s->eidx_h, e0, r, d.r2tile, d.e0tile, d.faces, s->tickets,
                        st);
     ph_end(s, st, PH_STAGE2, ev);
-    ph_begin(s, st, ev);
+    ph_begin(s, st, PH_ILU_F, ev);
     launch_ilu_fwd_grid(nx, ny, nz, d.Lg, d.r2tile, d.ytile, d.faces, s->tickets, s->hdev + 140,
                         kSweepSpinLimit, st);
     ph_end(s, st, PH_ILU_F, ev);
-    ph_begin(s, st, ev);
+    ph_begin(s, st, PH_ILU_B, ev);
     launch_ilu_bwd_grid(nx, ny, nz, d.Ug, d.ytile, e0 ? d.e0tile : nullptr, ne, s->eidx_h,
                         d.faces + grid_face_values(nx, ny, nz), z, s->tickets, s->hdev + 140,
                         kSweepSpinLimit, st);
@@ -782,7 +783,7 @@ void enqueue_stage2(cptr_solver s, PrecDev<T>& d, const double* r, const T* e0, 
   const T* rhs = d.r2;
   constexpr bool f64 = std::is_same<T, double>::value;
   if (s->sf_width > 0) {  // one-launch sweeps
-    ph_begin(s, st, ev);
+    ph_begin(s, st, PH_STAGE2, ev);
     if (e0 || !f64) {
       // the stage-two residual (or, without e0, r converted to T)
       launch_stage2_resid_sf(s->A, ne, s->eidx_h, e0, r, d.r2, d.y, d.x2, s->tickets, st);
@@ -791,11 +792,11 @@ void enqueue_stage2(cptr_solver s, PrecDev<T>& d, const double* r, const T* e0, 
       rhs = r;
     }
     ph_end(s, st, PH_STAGE2, ev);
-    ph_begin(s, st, ev);
+    ph_begin(s, st, PH_ILU_F, ev);
     launch_ilu_fwd_sf(d.Lf, s->sf_width, s->fperm, rhs, d.y, s->tickets, s->hdev + 140,
                       kSweepSpinLimit, st);
     ph_end(s, st, PH_ILU_F, ev);
-    ph_begin(s, st, ev);
+    ph_begin(s, st, PH_ILU_B, ev);
     launch_ilu_bwd_sf(d.Ub, s->sf_width, s->bperm, d.uinv, d.y, e0, ne, s->eidx_h, d.x2, z,
                       s->tickets, s->hdev + 140, kSweepSpinLimit, st);
     ph_end(s, st, PH_ILU_B, ev);
@@ -806,15 +807,15 @@ void enqueue_stage2(cptr_solver s, PrecDev<T>& d, const double* r, const T* e0, 
   }
   // per-level launches; the stage-two residual also converts r to T
   if (rhs == d.r2) {
-    ph_begin(s, st, ev);
+    ph_begin(s, st, PH_STAGE2, ev);
     launch_stage2_resid(s->A, ne, s->eidx_h, e0, r, d.r2, st);
     ph_end(s, st, PH_STAGE2, ev);
   }
-  ph_begin(s, st, ev);
+  ph_begin(s, st, PH_ILU_F, ev);
   for (size_t l = 0; l + 1 < s->flev_ptr.size(); ++l)
     launch_ilu_fwd_level(d.Lf, s->fperm, s->flev_ptr[l], s->flev_ptr[l + 1], rhs, d.y, st);
   ph_end(s, st, PH_ILU_F, ev);
-  ph_begin(s, st, ev);
+  ph_begin(s, st, PH_ILU_B, ev);
   for (size_t l = 0; l + 1 < s->blev_ptr.size(); ++l)
     launch_ilu_bwd_level(d.Ub, s->bperm, d.uinv, s->blev_ptr[l], s->blev_ptr[l + 1], d.y, e0, ne,
                          s->eidx_h, d.x2, z, st);
@@ -1189,6 +1190,7 @@ cptr_status cptr_gmres_solve(cptr_solver s, const double* b, double* x, const cp
       if (hipEventCreate(&e) != hipSuccess) e = nullptr;
   }
   s->profiling = o.profile != 0 && !s->ev_pool.empty() && s->ev_pool[0];
+  s->profile_mask = o.profile == 1 ? ~0u : (uint32_t)o.profile >> 1;
   s->ev_used = 0;
   s->ev_pending.clear();
   const int64_t N = s->N;
@@ -1206,7 +1208,7 @@ cptr_status cptr_gmres_solve(cptr_solver s, const double* b, double* x, const cp
     HIP_TRY(s, hipMemsetAsync(x, 0, sizeof(double) * N, st));
     HIP_TRY(s, hipMemcpyAsync(r, b, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
   } else {
-    ph_begin(s, st, ev);
+    ph_begin(s, st, PH_SPMV, ev);
     launch_bsr3_spmv(s->A, x, b, r, true, st);
     ph_end(s, st, PH_SPMV, ev);
   }
@@ -1232,11 +1234,11 @@ cptr_status cptr_gmres_solve(cptr_solver s, const double* b, double* x, const cp
       double* zj = o.flexible ? s->Z + (size_t)j * ld : s->wu;
       double* w = V + (size_t)(j + 1) * ld;
       enqueue_apply(s, vj, zj, st);
-      ph_begin(s, st, ev);
+      ph_begin(s, st, PH_SPMV, ev);
       launch_bsr3_spmv(s->A, zj, nullptr, w, false, st);
       ph_end(s, st, PH_SPMV, ev);
       // classical Gram-Schmidt, twice
-      ph_begin(s, st, ev);
+      ph_begin(s, st, PH_ARNOLDI, ev);
       const int nv = j + 1;
       launch_mdot(N, nv, V, ld, w, s->part, st);
       launch_reduce(nv, s->part, s->hdev, 0, st);
@@ -1288,7 +1290,7 @@ cptr_status cptr_gmres_solve(cptr_solver s, const double* b, double* x, const cp
       for (int q = i + 1; q < k; ++q) sum -= Hij(i, q) * yv[q];
       yv[i] = Hij(i, i) != 0.0 ? sum / Hij(i, i) : 0.0;
     }
-    ph_begin(s, st, ev);
+    ph_begin(s, st, PH_UPDATE, ev);
     if (o.flexible) {
       launch_update_host_coef(N, k, s->Z, ld, yv.data(), x, st);
       ph_end(s, st, PH_UPDATE, ev);
@@ -1297,12 +1299,12 @@ cptr_status cptr_gmres_solve(cptr_solver s, const double* b, double* x, const cp
       launch_update_host_coef(N, k, V, ld, yv.data(), s->wt, st);
       ph_end(s, st, PH_UPDATE, ev);
       enqueue_apply(s, s->wt, s->wu, st);
-      ph_begin(s, st, ev);
+      ph_begin(s, st, PH_UPDATE, ev);
       std::vector<double> one(1, 1.0);
       launch_update_host_coef(N, 1, s->wu, ld, one.data(), x, st);
       ph_end(s, st, PH_UPDATE, ev);
     }
-    ph_begin(s, st, ev);
+    ph_begin(s, st, PH_SPMV, ev);
     launch_bsr3_spmv(s->A, x, b, r, true, st);
     ph_end(s, st, PH_SPMV, ev);
     if ((rc = device_norm(s, r, beta, st))) return (cptr_status)rc;
