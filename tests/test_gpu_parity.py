@@ -178,6 +178,15 @@ def test_profiled_solve_reports_phases(solvers):
     assert ph["spmv"][1] >= info["iterations"]
     assert ph["ilu_fwd"][1] >= info["iterations"] and ph["ilu_fwd"][0] > 0
     assert ph["arnoldi"][1] == info["iterations"]
+    # a mask times only the phases whose bit (index + 1) is set, and the
+    # solve itself is unchanged
+    x2 = torch.zeros_like(b)
+    k = L.PHASES.index("ilu_bwd")
+    info2 = s.gmres_solve(b, x2, rtol=1e-8, profile=1 << (k + 1))
+    ph2 = s.phase_times(reset=True)
+    assert ph2["ilu_bwd"][1] == ph["ilu_bwd"][1] and ph2["ilu_bwd"][0] > 0
+    assert all(cnt == 0 for name, (_, cnt) in ph2.items() if name != "ilu_bwd")
+    assert info2["iterations"] == info["iterations"] and torch.equal(x, x2)
 
 
 @pytest.mark.parametrize("pe", [None, 0.1, 1000.0])
