@@ -155,6 +155,7 @@ struct cptr_solver_s {
   int grid[3] = {0, 0, 0};   // nx, ny, nz when A is a 7-point stencil in lexicographic order
   bool use_grid = false;     // tiled systolic sweeps on that grid
   bool device_ilu = false;   // ILU(0) factored on the device (every device handle; no host factors)
+  int32_t device_galerkin_levels = 0;  // coarse operators formed on the device
   int* tickets = nullptr;    // [2] workgroup ticket counters of the one-launch sweeps
   double* coarse_lu = nullptr;
   int32_t* coarse_piv = nullptr;
@@ -878,6 +879,120 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// ---------------------------------------------------------------- Galerkin
+// A CSR matrix on the device (int32 row pointers and columns, FP64 values),
+// allocated stream-ordered so that setups running beside solves never
+// synchronise the device.
+struct DevCsr {
+  int32_t n = 0;
+  int64_t nnz = 0;
+  int32_t* rp = nullptr;
+  int32_t* ci = nullptr;
+  double* v = nullptr;
+};
+
+class GalerkinOnDevice {
+ public:
+  GalerkinOnDevice() { ok_ = hipStreamCreateWithFlags(&st_, hipStreamNonBlocking) == hipSuccess; }
+  ~GalerkinOnDevice() {
+    for (void* p : mem_) (void)hipFreeAsync(p, st_);
+    if (st_) {
+      (void)hipStreamSynchronize(st_);
+      (void)hipStreamDestroy(st_);
+    }
+  }
+  // C = R (A P) in the host product's order; false if any step fails or a
+  // row has more products than the kernel takes
+  bool run(const Csr& R, const Csr& A, const Csr& P, Csr& C) {
+    if (!ok_) return false;
+    DevCsr a, p, r, ap, c;
+    std::vector<int32_t> crp;
+    if (!upload(A, a) || !upload(P, p) || !upload(R, r)) return false;
+    std::vector<int32_t> aprp;
+    if (!product(a, p, ap, aprp) || !product(r, ap, c, crp)) return false;
+    C.n = R.n;
+    C.m = P.m;
+    C.rp.assign(crp.begin(), crp.end());
+    C.ci.resize(c.nnz);
+    C.v.resize(c.nnz);
+    if (c.nnz > 0 &&
+        (hipMemcpyAsync(C.ci.data(), c.ci, sizeof(int32_t) * c.nnz, hipMemcpyDeviceToHost, st_) != hipSuccess ||
+         hipMemcpyAsync(C.v.data(), c.v, sizeof(double) * c.nnz, hipMemcpyDeviceToHost, st_) != hipSuccess))
+      return false;
+    return hipStreamSynchronize(st_) == hipSuccess;
+  }
+
+ private:
+  template <class T>
+  bool alloc(T*& p, int64_t count) {
+    void* q = nullptr;
+    if (hipMallocAsync(&q, sizeof(T) * (size_t)std::max<int64_t>(1, count), st_) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    mem_.push_back(q);
+    p = static_cast<T*>(q);
+    return true;
+  }
+  template <class T>
+  bool put(T*& p, const T* src, int64_t count) {
+    return alloc(p, count) &&
+           (count == 0 || hipMemcpyAsync(p, src, sizeof(T) * count, hipMemcpyHostToDevice, st_) == hipSuccess);
+  }
+  bool upload(const Csr& h, DevCsr& d) {
+    if (h.nnz() >= INT32_MAX) return false;
+    std::vector<int32_t> rp32(h.rp.begin(), h.rp.end());
+    d.n = h.n;
+    d.nnz = h.nnz();
+    // the staging vector dies here: copy synchronously with respect to the host
+    if (!put(d.rp, rp32.data(), (int64_t)rp32.size()) || hipStreamSynchronize(st_) != hipSuccess) return false;
+    return put(d.ci, h.ci.data(), d.nnz) && put(d.v, h.v.data(), d.nnz);
+  }
+  bool product(const DevCsr& x, const DevCsr& y, DevCsr& out, std::vector<int32_t>& rp_host) {
+    const int32_t n = x.n;
+    int32_t* bound = nullptr;
+    if (!alloc(bound, n)) return false;
+    launch_spgemm_bound(n, x.rp, x.ci, y.rp, bound, st_);
+    std::vector<int32_t> hb((size_t)n);
+    if (n > 0 && hipMemcpyAsync(hb.data(), bound, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st_) != hipSuccess)
+      return false;
+    if (hipStreamSynchronize(st_) != hipSuccess) return false;
+    std::vector<int64_t> off((size_t)n + 1, 0);
+    for (int32_t i = 0; i < n; ++i) {
+      if (hb[i] > spgemm_row_cap()) return false;
+      off[i + 1] = off[i] + hb[i];
+    }
+    int64_t* doff = nullptr;
+    int32_t *ocol = nullptr, *cnt = nullptr;
+    double* oval = nullptr;
+    if (!put(doff, off.data(), (int64_t)n + 1) || !alloc(ocol, off[n]) || !alloc(oval, off[n]) ||
+        !alloc(cnt, n))
+      return false;
+    launch_spgemm_rows(n, x.rp, x.ci, x.v, y.rp, y.ci, y.v, doff, ocol, oval, cnt, st_);
+    std::vector<int32_t> hc((size_t)n);
+    if (n > 0 && hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st_) != hipSuccess)
+      return false;
+    if (hipStreamSynchronize(st_) != hipSuccess || hipGetLastError() != hipSuccess) return false;
+    rp_host.assign((size_t)n + 1, 0);
+    int64_t total = 0;
+    for (int32_t i = 0; i < n; ++i) {
+      total += hc[i];
+      if (total >= INT32_MAX) return false;
+      rp_host[i + 1] = (int32_t)total;
+    }
+    out.n = n;
+    out.nnz = total;
+    if (!put(out.rp, rp_host.data(), (int64_t)n + 1) || !alloc(out.ci, total) || !alloc(out.v, total))
+      return false;
+    launch_spgemm_compact(n, doff, out.rp, ocol, oval, out.ci, out.v, st_);
+    return hipStreamSynchronize(st_) == hipSuccess && hipGetLastError() == hipSuccess;
+  }
+
+  hipStream_t st_ = nullptr;
+  bool ok_ = false;
+  std::vector<void*> mem_;
+};
+
 }  // namespace
 
 // ============================================================================
@@ -982,6 +1097,17 @@ int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_id
   // a device handle factors ILU(0) on the device
   const bool dev_ilu = !o.host_only;
   prm.skip_ilu = dev_ilu;
+  // a device handle forms the Galerkin products on the device (the host's
+  // summation order, so the hierarchy is the same); a level whose rows are
+  // too long for the kernel is formed on the host
+  int device_products = 0;
+  if (!o.host_only)
+    prm.galerkin = [&device_products](const Csr& R, const Csr& Al, const Csr& P, Csr& C) {
+      GalerkinOnDevice g;
+      const bool done = g.run(R, Al, P, C);
+      device_products += done;
+      return done;
+    };
   prm.theta = o.strong_threshold;
   prm.max_row_sum = o.max_row_sum;
   prm.max_levels = o.max_levels;
@@ -1012,6 +1138,7 @@ int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_id
   s->ilu_mode = o.ilu_sweep;
   s->threads = prm.threads;
   s->device_ilu = dev_ilu;
+  s->device_galerkin_levels = device_products;
   s->prec = o.precond_precision;
   *out = s.release();
   return CPTR_OK;
@@ -1388,6 +1515,10 @@ cptr_status cptr_export(cptr_solver s, int32_t what, int32_t level, void* buf, i
     case CPTR_EXPORT_ILU_NLEVELS: {
       int32_t nl[2] = {h.n_fwd_levels, h.n_bwd_levels};
       return put(nl, 8);
+    }
+    case CPTR_EXPORT_SETUP_SITES: {
+      int32_t v[2] = {s->device_galerkin_levels, (int32_t)h.lev.size() - 1};
+      return put(v, 8);
     }
     default:
       return (cptr_status)fail(s, CPTR_E_INVALID, "unknown export item");

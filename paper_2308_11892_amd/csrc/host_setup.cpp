@@ -920,7 +920,8 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
     Csr P = agg ? multipass_interp(A, S, cf, h.lev[l].func, threads)
                 : extended_i_interp(A, S, cf, h.lev[l].func, prm.pmax, threads);
     Csr R = transpose(P, threads);
-    Csr Ac = galerkin(R, A, P, threads);
+    Csr Ac;
+    if (!prm.galerkin || !prm.galerkin(R, A, P, Ac)) Ac = galerkin(R, A, P, threads);
     std::vector<int32_t> fc;
     fc.reserve(nc);
     for (int32_t i = 0; i < A.n; ++i)

@@ -69,7 +69,10 @@ struct SetupParams {
   bool quasi_impes = true;
   int threads = 1;
   int max_dense_coarse = 4096;  // largest coarsest level solved by dense LU
-  bool skip_ilu = false;        // ILU(0) is factored elsewhere (on the device, 7-point grids)
+  bool skip_ilu = false;        // ILU(0) is factored elsewhere (on the device)
+  // forms C = R A P elsewhere (on the device) in this file's summation order;
+  // false: formed here
+  std::function<bool(const Csr& R, const Csr& A, const Csr& P, Csr& C)> galerkin;
 };
 
 struct HostSetup {

@@ -8,6 +8,9 @@
 //   stage2 resid         r - A M1^-1 r with M1^-1 injecting into (p, T) (Eq. 3)
 //   ilu fwd / bwd        ILU(0) triangular sweeps, second stage (Sec. 3.1)
 //   mdot / maxpy         Arnoldi orthogonalisation of right-preconditioned GMRES
+//   setup                A's device layout, the reduced elliptic blocks (Sec. 5.2),
+//                        block ILU(0) (Sec. 3.1), the Galerkin products of the
+//                        AMG hierarchy (Sec. 3.1)
 //
 // Everything here is bandwidth-bound sparse or vector work: no MFMA.  Block
 // values are stored as lane-contiguous planes (see Sell in kernels.hpp) so a
@@ -15,6 +18,9 @@
 // Reductions are two-stage with a fixed order, so results are bit-identical
 // from run to run.
 #include "kernels.hpp"
+
+#include <algorithm>
+#include <climits>
 
 namespace cptr {
 
@@ -1608,6 +1614,145 @@ __global__ __launch_bounds__(kBlock) void k_grid_ilu_pack(int nb, int nx, int ny
 #pragma unroll
   for (int e = 0; e < 9; ++e) Ut[((size_t)br * 36 + 27 + e) * 64 + lane] = (T)uinv[(size_t)c * 9 + e];
 }
+
+// Sparse product C = X Y of scalar CSR matrices (int32 indices, FP64
+// values) with the summation order of the host's product: each entry of row
+// i of C is 0.0 plus the products x_ik y_kj added in the order of the stored
+// entries of row i of X and, within row k of Y, of Y's stored entries; rows
+// of C are sorted by column.  One 64-thread workgroup per row of X: the
+// row's products are expanded into LDS in that order, sorted by (column,
+// position) and each run of equal columns is summed from its first product
+// on by one lane.  bound[i] = the number of products of row i (at most
+// kGemmCap); the unique entries go to ocol/oval at off[i], their count to
+// cnt[i].
+constexpr int kGemmCap = 2048;
+
+__global__ __launch_bounds__(kBlock) void k_spgemm_bound(int n, const int32_t* __restrict__ xrp,
+                                                         const int32_t* __restrict__ xci,
+                                                         const int32_t* __restrict__ yrp,
+                                                         int32_t* __restrict__ bound) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int b = 0;
+  for (int q = xrp[i]; q < xrp[i + 1]; ++q) b += yrp[xci[q] + 1] - yrp[xci[q]];
+  bound[i] = b;
+}
+
+__global__ __launch_bounds__(64) void k_spgemm_rows(int n, const int32_t* __restrict__ xrp,
+                                                    const int32_t* __restrict__ xci,
+                                                    const double* __restrict__ xv,
+                                                    const int32_t* __restrict__ yrp,
+                                                    const int32_t* __restrict__ yci,
+                                                    const double* __restrict__ yv,
+                                                    const int64_t* __restrict__ off,
+                                                    int32_t* __restrict__ ocol, double* __restrict__ oval,
+                                                    int32_t* __restrict__ cnt) {
+#pragma clang fp contract(off)
+  __shared__ long long key[kGemmCap];  // column * kGemmCap + position
+  __shared__ double val[kGemmCap];
+  const int lane = threadIdx.x;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const int q0 = xrp[i], q1 = xrp[i + 1];
+    int m = 0;
+    for (int qb = q0; qb < q1; qb += 64) {
+      const int q = qb + lane;
+      int len = 0, k = 0;
+      double x = 0.0;
+      if (q < q1) {
+        k = xci[q];
+        x = xv[q];
+        len = yrp[k + 1] - yrp[k];
+      }
+      int incl = len;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += t;
+      }
+      const int start = m + incl - len;
+      for (int p = 0; p < len; ++p) {
+        const int e = yrp[k] + p;
+        key[start + p] = (long long)yci[e] * kGemmCap + (start + p);
+        val[start + p] = x * yv[e];
+      }
+      m += __shfl(incl, 63, 64);
+    }
+    int np = 1;
+    while (np < m) np <<= 1;
+    for (int t = m + lane; t < np; t += 64) key[t] = LLONG_MAX;
+    __syncthreads();
+    // bitonic sort of (key, val); keys are unique, so the order is total
+    for (int size = 2; size <= np; size <<= 1)
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int t = lane; t < np / 2; t += 64) {
+          const int a = 2 * t - (t & (stride - 1)), b = a + stride;
+          const bool up = (a & size) == 0;
+          const long long ka = key[a], kb = key[b];
+          if ((ka > kb) == up) {
+            key[a] = kb;
+            key[b] = ka;
+            const double va = val[a];
+            val[a] = val[b];
+            val[b] = va;
+          }
+        }
+        __syncthreads();
+      }
+    int runs = 0;
+    const int64_t o = off[i];
+    for (int t0 = 0; t0 < m; t0 += 64) {
+      const int t = t0 + lane;
+      long long c = -1;
+      bool first = false;
+      if (t < m) {
+        c = key[t] / kGemmCap;
+        first = t == 0 || key[t - 1] / kGemmCap != c;
+      }
+      const unsigned long long b = __ballot(first);
+      if (first) {
+        double sum = 0.0;
+        for (int u = t; u < m && key[u] / kGemmCap == c; ++u) sum = sum + val[u];
+        const int r = runs + __popcll(b & ((1ull << lane) - 1));
+        ocol[o + r] = (int32_t)c;
+        oval[o + r] = sum;
+      }
+      runs += __popcll(b);
+    }
+    if (lane == 0) cnt[i] = runs;
+    __syncthreads();
+  }
+}
+
+// rows of the product from their padded places (off) to CSR order (rp)
+__global__ __launch_bounds__(kBlock) void k_spgemm_compact(int n, const int64_t* __restrict__ off,
+                                                           const int32_t* __restrict__ rp,
+                                                           const int32_t* __restrict__ ocol,
+                                                           const double* __restrict__ oval,
+                                                           int32_t* __restrict__ ci, double* __restrict__ v) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int64_t o = off[i];
+  for (int q = rp[i]; q < rp[i + 1]; ++q) {
+    ci[q] = ocol[o + (q - rp[i])];
+    v[q] = oval[o + (q - rp[i])];
+  }
+}
+
+void launch_spgemm_bound(int n, const int32_t* xrp, const int32_t* xci, const int32_t* yrp, int32_t* bound,
+                         hipStream_t st) {
+  if (n > 0) k_spgemm_bound<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, xrp, xci, yrp, bound);
+}
+void launch_spgemm_rows(int n, const int32_t* xrp, const int32_t* xci, const double* xv, const int32_t* yrp,
+                        const int32_t* yci, const double* yv, const int64_t* off, int32_t* ocol, double* oval,
+                        int32_t* cnt, hipStream_t st) {
+  if (n > 0)
+    k_spgemm_rows<<<std::min(n, 8192), 64, 0, st>>>(n, xrp, xci, xv, yrp, yci, yv, off, ocol, oval, cnt);
+}
+void launch_spgemm_compact(int n, const int64_t* off, const int32_t* rp, const int32_t* ocol, const double* oval,
+                           int32_t* ci, double* v, hipStream_t st) {
+  if (n > 0) k_spgemm_compact<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, off, rp, ocol, oval, ci, v);
+}
+int spgemm_row_cap() { return kGemmCap; }
 
 // Block ILU(0) of any block-sparse A (Sec. 3.1) on W, a copy of A's SELL-64
 // values: one launch per forward dependency level, one thread per row, each

@@ -136,6 +136,20 @@ void launch_grid_ilu_diag(const Sell& A, const int32_t* fperm, int32_t p0, int32
 template <class T>
 void launch_grid_ilu_pack(const Sell& A, int nx, int ny, const double* uinv, T* Lt, T* Ut,
                           hipStream_t st);
+// Sparse product C = X Y of scalar CSR matrices in the host product's
+// summation order (each entry from 0.0, products in the order of X's and Y's
+// stored entries; rows sorted by column).  bound: products per row of X (at
+// most spgemm_row_cap()); off: exclusive prefix of bound (int64) into the
+// padded outputs ocol/oval; cnt: unique entries per row; then, with rp the
+// exclusive prefix of cnt, launch_spgemm_compact writes C's ci/v.
+void launch_spgemm_bound(int n, const int32_t* xrp, const int32_t* xci, const int32_t* yrp, int32_t* bound,
+                         hipStream_t st);
+void launch_spgemm_rows(int n, const int32_t* xrp, const int32_t* xci, const double* xv, const int32_t* yrp,
+                        const int32_t* yci, const double* yv, const int64_t* off, int32_t* ocol, double* oval,
+                        int32_t* cnt, hipStream_t st);
+void launch_spgemm_compact(int n, const int64_t* off, const int32_t* rp, const int32_t* ocol, const double* oval,
+                           int32_t* ci, double* v, hipStream_t st);
+int spgemm_row_cap();
 // Block ILU(0) of any block-sparse A on the device.  W: a copy of A's SELL-64
 // values, factored in place (L left of the diagonal, U on and right of it);
 // one launch_ilu_rows per forward dependency level (positions [p0, p1) of

@@ -375,3 +375,22 @@ def test_setup_from_device_arrays(name):
             s.apply(r, z)
             outs.append(host(z))
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("name,elliptic", [("grid20x20x5", (0, 1)), ("prism2000x5", (0, 1)),
+                                           ("grid30x20x6", (0,))])
+def test_device_galerkin_products_equal_host(name, elliptic):
+    """A device handle forms every coarse operator R A P on the GPU; they equal
+    the host's bit for bit (same splits, patterns and values on every level)."""
+    c = J.by_name(name)
+    with L.Solver(c.row_ptr, c.col_idx, c.values, elliptic=elliptic) as sd, \
+            L.Solver(c.row_ptr, c.col_idx, c.values, elliptic=elliptic, host_only=1) as sh:
+        rows_d, nnz_d = sd.hierarchy()
+        rows_h, nnz_h = sh.hierarchy()
+        assert np.array_equal(rows_d, rows_h) and np.array_equal(nnz_d, nnz_h)
+        sites = sd.export("SETUP_SITES", 0, 2, np.int32)
+        assert sites[1] == len(rows_d) - 1 and sites[0] == sites[1], sites
+        for l in range(1, len(rows_d)):
+            Ad, Ah = sd.level_matrix(l, "A"), sh.level_matrix(l, "A")
+            assert np.array_equal(Ad.indptr, Ah.indptr) and np.array_equal(Ad.indices, Ah.indices)
+            assert np.array_equal(Ad.data, Ah.data), f"level {l}"
