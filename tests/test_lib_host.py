@@ -164,6 +164,14 @@ def test_host_only_handle_refuses_device_calls():
     assert "host-only" in L.lib().cptr_last_error(s._h).decode()
 
 
+def test_host_only_handle_forms_products_on_the_host():
+    c = J.small(8, 6, 4)
+    s = host_solver(c)
+    rows, _ = s.hierarchy()
+    sites = s.export("SETUP_SITES", 0, 2, np.int32)
+    assert sites[0] == 0 and sites[1] == len(rows) - 1
+
+
 def test_coarsening_limit_reports_stall():
     c = J.small(6, 6, 4)
     # a two-level cap leaves a coarsest level far above the dense limit
