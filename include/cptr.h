@@ -137,8 +137,8 @@ void cptr_solve_opts_default(cptr_solve_opts *o);
  *   stream        hipStream_t (void*) receiving the uploads;
  *   out           receives the handle on success (NULL on failure).
  * The AMG hierarchy is built on the host, except that a device handle forms
- * the Galerkin products R A P on the device in the host's summation order (the
- * same coarse operators, bit for bit).  A device handle factors ILU(0) on
+ * the Galerkin products R A P and the extended+i interpolations on the device
+ * in the host's order and rounding (the same hierarchy, bit for bit).  A device handle factors ILU(0) on
  * the device (rows of one dependency level at a time, each in the host
  * factorisation's order and rounding, so the factors equal the host's); a
  * host-only handle factors it on the host.  A's device layout and the reduced
@@ -205,10 +205,12 @@ enum {
   CPTR_EXPORT_ILU_NLEVELS = 10, /* int32[2]: forward and backward dependency levels */
   CPTR_EXPORT_SWEEP = 11,      /* int32[4]: ILU sweep schedule in use (CPTR_ILU_SWEEP_*),
                                   then nx, ny, nz of the detected grid (0 if none) */
-  CPTR_EXPORT_SETUP_SITES = 12 /* int32[2]: coarse operators R A P formed on the device, and
-                                  in total (levels - 1); a device handle forms a level's
+  CPTR_EXPORT_SETUP_SITES = 12 /* int32[4]: coarse operators R A P formed on the device, and
+                                  in total (levels - 1); extended+i interpolations formed on
+                                  the device, and in total.  A device handle forms a level's
                                   product on the host only when a row of it has more than
-                                  2048 products */
+                                  2048 products, an interpolation only when a row's
+                                  interpolatory set has more than 64 points */
 };
 /* Copy one piece of the setup into host_buf (bytes = its capacity). */
 cptr_status cptr_export(cptr_solver s, int32_t what, int32_t level, void *host_buf, int64_t bytes);

@@ -156,6 +156,8 @@ struct cptr_solver_s {
   bool use_grid = false;     // tiled systolic sweeps on that grid
   bool device_ilu = false;   // ILU(0) factored on the device (every device handle; no host factors)
   int32_t device_galerkin_levels = 0;  // coarse operators formed on the device
+  int32_t device_interp_levels = 0;    // extended+i interpolations formed on the device
+  int32_t agg_levels_used = 0;         // levels with the aggressive (multipass) interpolation
   int* tickets = nullptr;    // [2] workgroup ticket counters of the one-launch sweeps
   double* coarse_lu = nullptr;
   int32_t* coarse_piv = nullptr;
@@ -891,10 +893,15 @@ struct DevCsr {
   double* v = nullptr;
 };
 
-class GalerkinOnDevice {
+// Steps of the AMG construction run on the device for a device handle: the
+// Galerkin product and extended+i interpolation, each giving the host
+// construction's result bit for bit.  A step returns false when it cannot
+// take the level (a row too long for the kernels, a HIP error); the host then
+// forms that piece itself.
+class DeviceSetupStep {
  public:
-  GalerkinOnDevice() { ok_ = hipStreamCreateWithFlags(&st_, hipStreamNonBlocking) == hipSuccess; }
-  ~GalerkinOnDevice() {
+  DeviceSetupStep() { ok_ = hipStreamCreateWithFlags(&st_, hipStreamNonBlocking) == hipSuccess; }
+  ~DeviceSetupStep() {
     for (void* p : mem_) (void)hipFreeAsync(p, st_);
     if (st_) {
       (void)hipStreamSynchronize(st_);
@@ -922,6 +929,60 @@ class GalerkinOnDevice {
     return hipStreamSynchronize(st_) == hipSuccess;
   }
 
+  // extended+i interpolation P of level A with strength pattern S
+  bool interp(const Csr& A, const Csr& S, const std::vector<int32_t>& cf, const std::vector<int32_t>& func,
+              int pmax, Csr& P) {
+    if (!ok_) return false;
+    const int32_t n = A.n;
+    std::vector<int32_t> cidx((size_t)n, -1);
+    int32_t nc = 0;
+    for (int32_t i = 0; i < n; ++i)
+      if (cf[i] == 1) cidx[i] = nc++;
+    const int outcap = pmax > 0 ? std::max(1, pmax) : interp_set_cap();
+    DevCsr a, sg;
+    int32_t *dcf = nullptr, *dfunc = nullptr, *dcidx = nullptr, *ocol = nullptr, *cnt = nullptr;
+    double* oval = nullptr;
+    int* over = nullptr;
+    if (!upload(A, a) || !upload_pattern(S, sg) || !put(dcf, cf.data(), n) || !put(dfunc, func.data(), n) ||
+        !put(dcidx, cidx.data(), n) || !alloc(ocol, (int64_t)n * outcap) || !alloc(oval, (int64_t)n * outcap) ||
+        !alloc(cnt, n) || !alloc(over, 1))
+      return false;
+    if (hipMemsetAsync(over, 0, sizeof(int), st_) != hipSuccess) return false;
+    launch_interp_exti(n, a.rp, a.ci, a.v, sg.rp, sg.ci, dcf, dfunc, dcidx, pmax, outcap, ocol, oval, cnt, over,
+                       st_);
+    std::vector<int32_t> hc((size_t)n);
+    int h_over = 0;
+    if ((n > 0 && hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st_) != hipSuccess) ||
+        hipMemcpyAsync(&h_over, over, sizeof(int), hipMemcpyDeviceToHost, st_) != hipSuccess ||
+        hipStreamSynchronize(st_) != hipSuccess || hipGetLastError() != hipSuccess || h_over != 0)
+      return false;
+    std::vector<int64_t> off((size_t)n + 1);
+    std::vector<int32_t> rp((size_t)n + 1, 0);
+    int64_t total = 0;
+    for (int32_t i = 0; i < n; ++i) {
+      off[i] = (int64_t)i * outcap;
+      total += hc[i];
+      rp[i + 1] = (int32_t)total;
+    }
+    int64_t* doff = nullptr;
+    int32_t *drp = nullptr, *pci = nullptr;
+    double* pv = nullptr;
+    if (!put(doff, off.data(), n) || !put(drp, rp.data(), (int64_t)n + 1) || !alloc(pci, total) ||
+        !alloc(pv, total))
+      return false;
+    launch_spgemm_compact(n, doff, drp, ocol, oval, pci, pv, st_);
+    P.n = n;
+    P.m = nc;
+    P.rp.assign(rp.begin(), rp.end());
+    P.ci.resize(total);
+    P.v.resize(total);
+    if (total > 0 &&
+        (hipMemcpyAsync(P.ci.data(), pci, sizeof(int32_t) * total, hipMemcpyDeviceToHost, st_) != hipSuccess ||
+         hipMemcpyAsync(P.v.data(), pv, sizeof(double) * total, hipMemcpyDeviceToHost, st_) != hipSuccess))
+      return false;
+    return hipStreamSynchronize(st_) == hipSuccess && hipGetLastError() == hipSuccess;
+  }
+
  private:
   template <class T>
   bool alloc(T*& p, int64_t count) {
@@ -938,6 +999,14 @@ class GalerkinOnDevice {
   bool put(T*& p, const T* src, int64_t count) {
     return alloc(p, count) &&
            (count == 0 || hipMemcpyAsync(p, src, sizeof(T) * count, hipMemcpyHostToDevice, st_) == hipSuccess);
+  }
+  bool upload_pattern(const Csr& h, DevCsr& d) {
+    if (h.nnz() >= INT32_MAX) return false;
+    std::vector<int32_t> rp32(h.rp.begin(), h.rp.end());
+    d.n = h.n;
+    d.nnz = h.nnz();
+    if (!put(d.rp, rp32.data(), (int64_t)rp32.size()) || hipStreamSynchronize(st_) != hipSuccess) return false;
+    return put(d.ci, h.ci.data(), d.nnz);
   }
   bool upload(const Csr& h, DevCsr& d) {
     if (h.nnz() >= INT32_MAX) return false;
@@ -1100,14 +1169,22 @@ int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_id
   // a device handle forms the Galerkin products on the device (the host's
   // summation order, so the hierarchy is the same); a level whose rows are
   // too long for the kernel is formed on the host
-  int device_products = 0;
-  if (!o.host_only)
+  int device_products = 0, device_interps = 0;
+  if (!o.host_only) {
     prm.galerkin = [&device_products](const Csr& R, const Csr& Al, const Csr& P, Csr& C) {
-      GalerkinOnDevice g;
+      DeviceSetupStep g;
       const bool done = g.run(R, Al, P, C);
       device_products += done;
       return done;
     };
+    prm.interp = [&device_interps](const Csr& Al, const Csr& S, const std::vector<int32_t>& cf,
+                                   const std::vector<int32_t>& func, int pmax, Csr& P) {
+      DeviceSetupStep g;
+      const bool done = g.interp(Al, S, cf, func, pmax, P);
+      device_interps += done;
+      return done;
+    };
+  }
   prm.theta = o.strong_threshold;
   prm.max_row_sum = o.max_row_sum;
   prm.max_levels = o.max_levels;
@@ -1139,6 +1216,8 @@ int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_id
   s->threads = prm.threads;
   s->device_ilu = dev_ilu;
   s->device_galerkin_levels = device_products;
+  s->device_interp_levels = device_interps;
+  s->agg_levels_used = std::min<int32_t>(prm.agg_levels, (int32_t)s->host.lev.size() - 1);
   s->prec = o.precond_precision;
   *out = s.release();
   return CPTR_OK;
@@ -1517,8 +1596,9 @@ cptr_status cptr_export(cptr_solver s, int32_t what, int32_t level, void* buf, i
       return put(nl, 8);
     }
     case CPTR_EXPORT_SETUP_SITES: {
-      int32_t v[2] = {s->device_galerkin_levels, (int32_t)h.lev.size() - 1};
-      return put(v, 8);
+      int32_t v[4] = {s->device_galerkin_levels, (int32_t)h.lev.size() - 1, s->device_interp_levels,
+                      std::max(0, (int32_t)h.lev.size() - 1 - s->agg_levels_used)};
+      return put(v, 16);
     }
     default:
       return (cptr_status)fail(s, CPTR_E_INVALID, "unknown export item");

@@ -917,8 +917,11 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
     int32_t nc = 0;
     for (auto x : cf) nc += x == 1;
     if (nc == 0 || nc == A.n) break;
-    Csr P = agg ? multipass_interp(A, S, cf, h.lev[l].func, threads)
-                : extended_i_interp(A, S, cf, h.lev[l].func, prm.pmax, threads);
+    Csr P;
+    if (agg)
+      P = multipass_interp(A, S, cf, h.lev[l].func, threads);
+    else if (!prm.interp || !prm.interp(A, S, cf, h.lev[l].func, prm.pmax, P))
+      P = extended_i_interp(A, S, cf, h.lev[l].func, prm.pmax, threads);
     Csr R = transpose(P, threads);
     Csr Ac;
     if (!prm.galerkin || !prm.galerkin(R, A, P, Ac)) Ac = galerkin(R, A, P, threads);

@@ -73,6 +73,11 @@ struct SetupParams {
   // forms C = R A P elsewhere (on the device) in this file's summation order;
   // false: formed here
   std::function<bool(const Csr& R, const Csr& A, const Csr& P, Csr& C)> galerkin;
+  // forms the extended+i interpolation elsewhere (on the device) exactly as
+  // extended_i_interp does; false: formed here
+  std::function<bool(const Csr& A, const Csr& S, const std::vector<int32_t>& cf,
+                     const std::vector<int32_t>& func, int pmax, Csr& P)>
+      interp;
 };
 
 struct HostSetup {

@@ -1615,6 +1615,185 @@ __global__ __launch_bounds__(kBlock) void k_grid_ilu_pack(int nb, int nx, int ny
   for (int e = 0; e < 9; ++e) Ut[((size_t)br * 36 + 27 + e) * 64 + lane] = (T)uinv[(size_t)c * 9 + e];
 }
 
+// Extended+i interpolation weights of one AMG level (De Sterck, Falgout,
+// Nolting, Yang 2008), one thread per row, in the host construction's order
+// and rounding: the interpolatory set of an F row is its strong C points and
+// the strong C points of its strong F points, in the order met; each same-type
+// off-diagonal a_im goes to its set point, through a strong F point m to the
+// set points (and i) in proportion to a_ml, or to the diagonal.  Rows keep
+// the pmax largest |w| (smaller column on ties), rescaled to the full row sum,
+// then are sorted by column.  The row's set and sums live in LDS (at most
+// kInterpCap points; more sets *overflow).  Output: row i's entries at
+// i * outcap of ocol/oval, their count in cnt[i].
+constexpr int kInterpCap = 64;
+
+__global__ __launch_bounds__(64) void k_interp_exti(int n, const int32_t* __restrict__ arp,
+                                                    const int32_t* __restrict__ aci,
+                                                    const double* __restrict__ av,
+                                                    const int32_t* __restrict__ srp,
+                                                    const int32_t* __restrict__ sci,
+                                                    const int32_t* __restrict__ cf,
+                                                    const int32_t* __restrict__ func,
+                                                    const int32_t* __restrict__ cidx, int pmax, int outcap,
+                                                    int32_t* __restrict__ ocol, double* __restrict__ oval,
+                                                    int32_t* __restrict__ cnt, int* __restrict__ overflow) {
+#pragma clang fp contract(off)
+  __shared__ int32_t s_set[64][kInterpCap];
+  __shared__ double s_acc[64][kInterpCap];
+  int32_t* set = s_set[threadIdx.x];
+  double* acc = s_acc[threadIdx.x];
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= n) return;
+  const size_t o = (size_t)i * outcap;
+  if (cf[i] == 1) {
+    ocol[o] = cidx[i];
+    oval[o] = 1.0;
+    cnt[i] = 1;
+    return;
+  }
+  int ns = 0;
+  bool full = false;
+  auto in_set = [&](int32_t c) -> int {
+    for (int q = 0; q < ns; ++q)
+      if (set[q] == c) return q;
+    return -1;
+  };
+  auto add = [&](int32_t c) {
+    if (in_set(c) >= 0) return;
+    if (ns == kInterpCap) {
+      full = true;
+      return;
+    }
+    set[ns++] = c;
+  };
+  for (int k = srp[i]; k < srp[i + 1]; ++k) {
+    const int32_t j = sci[k];
+    if (cf[j] == 1) {
+      add(j);
+    } else {
+      for (int q = srp[j]; q < srp[j + 1]; ++q)
+        if (cf[sci[q]] == 1) add(sci[q]);
+    }
+  }
+  if (full) {
+    atomicAdd(overflow, 1);
+    cnt[i] = 0;
+    return;
+  }
+  auto a_diag = [&](int32_t r) -> double {
+    for (int k = arp[r]; k < arp[r + 1]; ++k)
+      if (aci[k] == r) return av[k];
+    return 0.0;
+  };
+  auto strong = [&](int32_t m) -> bool {
+    for (int k = srp[i]; k < srp[i + 1]; ++k)
+      if (sci[k] == m) return true;
+    return false;
+  };
+  int nout = 0;
+  if (ns > 0) {
+    for (int q = 0; q < ns; ++q) acc[q] = 0.0;
+    double dg = a_diag(i);
+    const int32_t fi = func[i];
+    for (int k = arp[i]; k < arp[i + 1]; ++k) {
+      const int32_t m = aci[k];
+      if (m == i || func[m] != fi) continue;
+      const double aim = av[k];
+      const int pos = in_set(m);
+      if (pos >= 0) {
+        acc[pos] = acc[pos] + aim;
+        continue;
+      }
+      if (cf[m] != 1 && strong(m)) {
+        const double sm = a_diag(m) < 0.0 ? -1.0 : 1.0;
+        double den = 0.0;
+        for (int q = arp[m]; q < arp[m + 1]; ++q) {
+          const int32_t l = aci[q];
+          const double aml = av[q];
+          if (sm * aml < 0.0 && (l == i || in_set(l) >= 0)) den = den + aml;
+        }
+        if (den == 0.0) {
+          dg = dg + aim;
+          continue;
+        }
+        for (int q = arp[m]; q < arp[m + 1]; ++q) {
+          const int32_t l = aci[q];
+          const double aml = av[q];
+          if (!(sm * aml < 0.0)) continue;
+          const double share = aim * aml / den;
+          if (l == i) {
+            dg = dg + share;
+          } else {
+            const int p = in_set(l);
+            if (p >= 0) acc[p] = acc[p] + share;
+          }
+        }
+        continue;
+      }
+      dg = dg + aim;
+    }
+    if (dg != 0.0) {
+      // the row in set order: columns in set[], weights in acc[]
+      for (int q = 0; q < ns; ++q) {
+        set[q] = cidx[set[q]];
+        acc[q] = -acc[q] / dg;
+      }
+      nout = ns;
+      if (pmax > 0 && ns > pmax) {
+        double total = 0.0, kept = 0.0;
+        for (int q = 0; q < ns; ++q) total = total + acc[q];
+        // the pmax best by (|w| descending, column ascending), in that order,
+        // moved to the front
+        for (int r = 0; r < pmax; ++r) {
+          int best = r;
+          for (int q = r + 1; q < ns; ++q) {
+            const double fa = fabs(acc[q]), fb = fabs(acc[best]);
+            if (fa != fb ? fa > fb : set[q] < set[best]) best = q;
+          }
+          const int32_t tc = set[r];
+          set[r] = set[best];
+          set[best] = tc;
+          const double tw = acc[r];
+          acc[r] = acc[best];
+          acc[best] = tw;
+        }
+        for (int r = 0; r < pmax; ++r) kept = kept + acc[r];
+        nout = pmax;
+        if (kept != 0.0) {
+          const double scale = total / kept;
+          for (int r = 0; r < pmax; ++r) acc[r] = acc[r] * scale;
+        }
+      }
+      // by column (columns are distinct)
+      for (int a = 1; a < nout; ++a) {
+        const int32_t c = set[a];
+        const double w = acc[a];
+        int b = a;
+        for (; b > 0 && set[b - 1] > c; --b) {
+          set[b] = set[b - 1];
+          acc[b] = acc[b - 1];
+        }
+        set[b] = c;
+        acc[b] = w;
+      }
+      for (int q = 0; q < nout; ++q) {
+        ocol[o + q] = set[q];
+        oval[o + q] = acc[q];
+      }
+    }
+  }
+  cnt[i] = nout;
+}
+
+void launch_interp_exti(int n, const int32_t* arp, const int32_t* aci, const double* av, const int32_t* srp,
+                        const int32_t* sci, const int32_t* cf, const int32_t* func, const int32_t* cidx, int pmax,
+                        int outcap, int32_t* ocol, double* oval, int32_t* cnt, int* overflow, hipStream_t st) {
+  if (n > 0)
+    k_interp_exti<<<(n + 63) / 64, 64, 0, st>>>(n, arp, aci, av, srp, sci, cf, func, cidx, pmax, outcap, ocol, oval,
+                                               cnt, overflow);
+}
+int interp_set_cap() { return kInterpCap; }
+
 // Sparse product C = X Y of scalar CSR matrices (int32 indices, FP64
 // values) with the summation order of the host's product: each entry of row
 // i of C is 0.0 plus the products x_ik y_kj added in the order of the stored

@@ -136,6 +136,16 @@ void launch_grid_ilu_diag(const Sell& A, const int32_t* fperm, int32_t p0, int32
 template <class T>
 void launch_grid_ilu_pack(const Sell& A, int nx, int ny, const double* uinv, T* Lt, T* Ut,
                           hipStream_t st);
+// Extended+i interpolation of one AMG level in the host construction's order
+// and rounding (scalar CSR A and strength pattern S, int32; cf 1 = C, -1 =
+// F; func: unknown type per row; cidx: coarse index of each C point).  Row i
+// goes to ocol/oval at i * outcap (outcap >= pmax, or >= interp_set_cap()
+// without truncation), its length to cnt[i]; a row whose interpolatory set has
+// more than interp_set_cap() points adds 1 to *overflow.
+void launch_interp_exti(int n, const int32_t* arp, const int32_t* aci, const double* av, const int32_t* srp,
+                        const int32_t* sci, const int32_t* cf, const int32_t* func, const int32_t* cidx, int pmax,
+                        int outcap, int32_t* ocol, double* oval, int32_t* cnt, int* overflow, hipStream_t st);
+int interp_set_cap();
 // Sparse product C = X Y of scalar CSR matrices in the host product's
 // summation order (each entry from 0.0, products in the order of X's and Y's
 // stored entries; rows sorted by column).  bound: products per row of X (at
