@@ -1410,16 +1410,19 @@ cptr_status cptr_gmres_solve(cptr_solver s, const double* b, double* x, const cp
 
   double bnorm = 0.0;
   if ((rc = device_norm(s, b, bnorm, st))) return (cptr_status)rc;
+  // the residual the next cycle starts from: b itself when x0 = 0
+  const double* r0 = r;
+  double beta = 0.0;
   if (o.x0_is_zero || bnorm == 0.0) {
     HIP_TRY(s, hipMemsetAsync(x, 0, sizeof(double) * N, st));
-    HIP_TRY(s, hipMemcpyAsync(r, b, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    r0 = b;
+    beta = bnorm;
   } else {
     ph_begin(s, st, PH_SPMV, ev);
     launch_bsr3_spmv(s->A, x, b, r, true, st);
     ph_end(s, st, PH_SPMV, ev);
+    if ((rc = device_norm(s, r, beta, st))) return (cptr_status)rc;
   }
-  double beta = 0.0;
-  if ((rc = device_norm(s, r, beta, st))) return (cptr_status)rc;
   ph_harvest(s);
   const double bref = bnorm == 0.0 ? 1.0 : bnorm;
   const double target = o.rtol * bref;
@@ -1431,7 +1434,8 @@ cptr_status cptr_gmres_solve(cptr_solver s, const double* b, double* x, const cp
       break;
     }
     if (it >= o.max_iter) break;
-    launch_scale_host(N, r, beta, V, st);
+    launch_scale_host(N, r0, beta, V, st);
+    r0 = r;
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int jend = -1;
