@@ -137,8 +137,10 @@ void cptr_solve_opts_default(cptr_solve_opts *o);
  *   stream        hipStream_t (void*) receiving the uploads;
  *   out           receives the handle on success (NULL on failure).
  * The AMG hierarchy is built on the host, except that a device handle forms
- * the Galerkin products R A P and the extended+i interpolations on the device
- * in the host's order and rounding (the same hierarchy, bit for bit).  A device handle factors ILU(0) on
+ * the strength graphs, the extended+i interpolations and the Galerkin products
+ * R A P on the device in the host's order and rounding (the same hierarchy,
+ * bit for bit); the C/F splits and the aggressive level's multipass
+ * interpolation stay on the host.  A device handle factors ILU(0) on
  * the device (rows of one dependency level at a time, each in the host
  * factorisation's order and rounding, so the factors equal the host's); a
  * host-only handle factors it on the host.  A's device layout and the reduced
@@ -205,11 +207,11 @@ enum {
   CPTR_EXPORT_ILU_NLEVELS = 10, /* int32[2]: forward and backward dependency levels */
   CPTR_EXPORT_SWEEP = 11,      /* int32[4]: ILU sweep schedule in use (CPTR_ILU_SWEEP_*),
                                   then nx, ny, nz of the detected grid (0 if none) */
-  CPTR_EXPORT_SETUP_SITES = 12 /* int32[4]: coarse operators R A P formed on the device, and
-                                  in total (levels - 1); extended+i interpolations formed on
-                                  the device, and in total.  A device handle forms a level's
-                                  product on the host only when a row of it has more than
-                                  2048 products, an interpolation only when a row's
+  CPTR_EXPORT_SETUP_SITES = 12 /* int32[6]: strength graphs formed on the device and in total,
+                                  extended+i interpolations on the device and in total,
+                                  coarse operators R A P on the device and in total.  A device
+                                  handle forms a product on the host only when a row of it has
+                                  more than 2048 products, an interpolation only when a row's
                                   interpolatory set has more than 64 points */
 };
 /* Copy one piece of the setup into host_buf (bytes = its capacity). */

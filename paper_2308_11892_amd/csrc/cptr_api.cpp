@@ -131,6 +131,11 @@ struct PrecDev {
 
 }  // namespace
 
+// AMG construction steps a setup did on the device (levels)
+struct SetupSiteCounts {
+  int strength = 0, interp = 0, galerkin = 0;
+};
+
 struct cptr_solver_s {
   HostSetup host;
   bool device = false;
@@ -155,8 +160,7 @@ struct cptr_solver_s {
   int grid[3] = {0, 0, 0};   // nx, ny, nz when A is a 7-point stencil in lexicographic order
   bool use_grid = false;     // tiled systolic sweeps on that grid
   bool device_ilu = false;   // ILU(0) factored on the device (every device handle; no host factors)
-  int32_t device_galerkin_levels = 0;  // coarse operators formed on the device
-  int32_t device_interp_levels = 0;    // extended+i interpolations formed on the device
+  SetupSiteCounts device_steps;        // AMG construction steps done on the device
   int32_t agg_levels_used = 0;         // levels with the aggressive (multipass) interpolation
   int* tickets = nullptr;    // [2] workgroup ticket counters of the one-launch sweeps
   double* coarse_lu = nullptr;
@@ -893,69 +897,75 @@ struct DevCsr {
   double* v = nullptr;
 };
 
-// Steps of the AMG construction run on the device for a device handle: the
-// Galerkin product and extended+i interpolation, each giving the host
-// construction's result bit for bit.  A step returns false when it cannot
-// take the level (a row too long for the kernels, a HIP error); the host then
-// forms that piece itself.
-class DeviceSetupStep {
+// The steps of one AMG level's construction on the device for a device
+// handle: strength, extended+i interpolation and the Galerkin product, each
+// giving the host construction's result bit for bit.  The level's operator
+// goes to the device once.  A step returns false when it cannot take the
+// level (a row too long for the kernels, a HIP error); the host then forms
+// that piece itself.  Counts of the steps done here go to `done`.
+class DeviceLevelSteps : public LevelSteps {
  public:
-  DeviceSetupStep() { ok_ = hipStreamCreateWithFlags(&st_, hipStreamNonBlocking) == hipSuccess; }
-  ~DeviceSetupStep() {
+  DeviceLevelSteps(const Csr& A, SetupSiteCounts& done) : A_(A), done_(done) {
+    ok_ = hipStreamCreateWithFlags(&st_, hipStreamNonBlocking) == hipSuccess && upload(A, a_);
+  }
+  ~DeviceLevelSteps() override {
     for (void* p : mem_) (void)hipFreeAsync(p, st_);
     if (st_) {
       (void)hipStreamSynchronize(st_);
       (void)hipStreamDestroy(st_);
     }
   }
-  // C = R (A P) in the host product's order; false if any step fails or a
-  // row has more products than the kernel takes
-  bool run(const Csr& R, const Csr& A, const Csr& P, Csr& C) {
+
+  bool strength(const std::vector<int32_t>& func, double theta, double mrs, Csr& S) override {
     if (!ok_) return false;
-    DevCsr a, p, r, ap, c;
-    std::vector<int32_t> crp;
-    if (!upload(A, a) || !upload(P, p) || !upload(R, r)) return false;
-    std::vector<int32_t> aprp;
-    if (!product(a, p, ap, aprp) || !product(r, ap, c, crp)) return false;
-    C.n = R.n;
-    C.m = P.m;
-    C.rp.assign(crp.begin(), crp.end());
-    C.ci.resize(c.nnz);
-    C.v.resize(c.nnz);
-    if (c.nnz > 0 &&
-        (hipMemcpyAsync(C.ci.data(), c.ci, sizeof(int32_t) * c.nnz, hipMemcpyDeviceToHost, st_) != hipSuccess ||
-         hipMemcpyAsync(C.v.data(), c.v, sizeof(double) * c.nnz, hipMemcpyDeviceToHost, st_) != hipSuccess))
-      return false;
-    return hipStreamSynchronize(st_) == hipSuccess;
+    const int32_t n = A_.n;
+    int32_t *dfunc = nullptr, *ocol = nullptr, *cnt = nullptr;
+    if (!put(dfunc, func.data(), n) || !alloc(ocol, a_.nnz) || !alloc(cnt, n)) return fail();
+    launch_strength(n, a_.rp, a_.ci, a_.v, dfunc, theta, mrs, ocol, cnt, st_);
+    std::vector<int32_t> hc((size_t)n);
+    if (!get(hc.data(), cnt, n)) return fail();
+    std::vector<int32_t> rp((size_t)n + 1, 0);
+    for (int32_t i = 0; i < n; ++i) rp[i + 1] = rp[i] + hc[i];
+    DevCsr sd;
+    sd.n = n;
+    sd.nnz = rp[n];
+    if (!put(sd.rp, rp.data(), (int64_t)n + 1) || !alloc(sd.ci, sd.nnz)) return fail();
+    launch_compact_cols(n, a_.rp, sd.rp, ocol, sd.ci, st_);
+    S.n = S.m = n;
+    S.rp.assign(rp.begin(), rp.end());
+    S.ci.resize(sd.nnz);
+    S.v.clear();
+    if (!get(S.ci.data(), sd.ci, sd.nnz)) return fail();
+    s_ = sd;
+    have_s_ = true;
+    ++done_.strength;
+    return true;
   }
 
-  // extended+i interpolation P of level A with strength pattern S
-  bool interp(const Csr& A, const Csr& S, const std::vector<int32_t>& cf, const std::vector<int32_t>& func,
-              int pmax, Csr& P) {
+  bool interp(const Csr& S, const std::vector<int32_t>& cf, const std::vector<int32_t>& func, int pmax,
+              Csr& P) override {
     if (!ok_) return false;
-    const int32_t n = A.n;
+    const int32_t n = A_.n;
     std::vector<int32_t> cidx((size_t)n, -1);
     int32_t nc = 0;
     for (int32_t i = 0; i < n; ++i)
       if (cf[i] == 1) cidx[i] = nc++;
     const int outcap = pmax > 0 ? std::max(1, pmax) : interp_set_cap();
-    DevCsr a, sg;
+    if (!have_s_ && !upload_pattern(S, s_)) return fail();
+    have_s_ = true;
     int32_t *dcf = nullptr, *dfunc = nullptr, *dcidx = nullptr, *ocol = nullptr, *cnt = nullptr;
     double* oval = nullptr;
     int* over = nullptr;
-    if (!upload(A, a) || !upload_pattern(S, sg) || !put(dcf, cf.data(), n) || !put(dfunc, func.data(), n) ||
-        !put(dcidx, cidx.data(), n) || !alloc(ocol, (int64_t)n * outcap) || !alloc(oval, (int64_t)n * outcap) ||
-        !alloc(cnt, n) || !alloc(over, 1))
-      return false;
-    if (hipMemsetAsync(over, 0, sizeof(int), st_) != hipSuccess) return false;
-    launch_interp_exti(n, a.rp, a.ci, a.v, sg.rp, sg.ci, dcf, dfunc, dcidx, pmax, outcap, ocol, oval, cnt, over,
+    if (!put(dcf, cf.data(), n) || !put(dfunc, func.data(), n) || !put(dcidx, cidx.data(), n) ||
+        !alloc(ocol, (int64_t)n * outcap) || !alloc(oval, (int64_t)n * outcap) || !alloc(cnt, n) ||
+        !alloc(over, 1) || hipMemsetAsync(over, 0, sizeof(int), st_) != hipSuccess)
+      return fail();
+    launch_interp_exti(n, a_.rp, a_.ci, a_.v, s_.rp, s_.ci, dcf, dfunc, dcidx, pmax, outcap, ocol, oval, cnt, over,
                        st_);
     std::vector<int32_t> hc((size_t)n);
     int h_over = 0;
-    if ((n > 0 && hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st_) != hipSuccess) ||
-        hipMemcpyAsync(&h_over, over, sizeof(int), hipMemcpyDeviceToHost, st_) != hipSuccess ||
-        hipStreamSynchronize(st_) != hipSuccess || hipGetLastError() != hipSuccess || h_over != 0)
-      return false;
+    if (!get(hc.data(), cnt, n) || !get(&h_over, over, 1)) return fail();
+    if (h_over != 0) return false;
     std::vector<int64_t> off((size_t)n + 1);
     std::vector<int32_t> rp((size_t)n + 1, 0);
     int64_t total = 0;
@@ -969,21 +979,41 @@ class DeviceSetupStep {
     double* pv = nullptr;
     if (!put(doff, off.data(), n) || !put(drp, rp.data(), (int64_t)n + 1) || !alloc(pci, total) ||
         !alloc(pv, total))
-      return false;
+      return fail();
     launch_spgemm_compact(n, doff, drp, ocol, oval, pci, pv, st_);
     P.n = n;
     P.m = nc;
     P.rp.assign(rp.begin(), rp.end());
     P.ci.resize(total);
     P.v.resize(total);
-    if (total > 0 &&
-        (hipMemcpyAsync(P.ci.data(), pci, sizeof(int32_t) * total, hipMemcpyDeviceToHost, st_) != hipSuccess ||
-         hipMemcpyAsync(P.v.data(), pv, sizeof(double) * total, hipMemcpyDeviceToHost, st_) != hipSuccess))
-      return false;
-    return hipStreamSynchronize(st_) == hipSuccess && hipGetLastError() == hipSuccess;
+    if (!get(P.ci.data(), pci, total) || !get(P.v.data(), pv, total)) return fail();
+    ++done_.interp;
+    return true;
+  }
+
+  // C = R (A P) in the host product's order
+  bool galerkin(const Csr& R, const Csr& P, Csr& C) override {
+    if (!ok_) return false;
+    DevCsr p, r, ap, c;
+    std::vector<int32_t> crp, aprp;
+    if (!upload(P, p) || !upload(R, r)) return fail();
+    if (!product(a_, p, ap, aprp) || !product(r, ap, c, crp)) return false;
+    C.n = R.n;
+    C.m = P.m;
+    C.rp.assign(crp.begin(), crp.end());
+    C.ci.resize(c.nnz);
+    C.v.resize(c.nnz);
+    if (!get(C.ci.data(), c.ci, c.nnz) || !get(C.v.data(), c.v, c.nnz)) return fail();
+    ++done_.galerkin;
+    return true;
   }
 
  private:
+  bool fail() {
+    (void)hipGetLastError();
+    ok_ = false;
+    return false;
+  }
   template <class T>
   bool alloc(T*& p, int64_t count) {
     void* q = nullptr;
@@ -995,37 +1025,38 @@ class DeviceSetupStep {
     p = static_cast<T*>(q);
     return true;
   }
+  // host -> device; the source may die when this returns
   template <class T>
   bool put(T*& p, const T* src, int64_t count) {
     return alloc(p, count) &&
-           (count == 0 || hipMemcpyAsync(p, src, sizeof(T) * count, hipMemcpyHostToDevice, st_) == hipSuccess);
+           (count == 0 || (hipMemcpyAsync(p, src, sizeof(T) * count, hipMemcpyHostToDevice, st_) == hipSuccess &&
+                           hipStreamSynchronize(st_) == hipSuccess));
+  }
+  // device -> host, after the stream's earlier work
+  template <class T>
+  bool get(T* dst, const T* src, int64_t count) {
+    if (count > 0 && hipMemcpyAsync(dst, src, sizeof(T) * count, hipMemcpyDeviceToHost, st_) != hipSuccess)
+      return false;
+    return hipStreamSynchronize(st_) == hipSuccess && hipGetLastError() == hipSuccess;
   }
   bool upload_pattern(const Csr& h, DevCsr& d) {
     if (h.nnz() >= INT32_MAX) return false;
     std::vector<int32_t> rp32(h.rp.begin(), h.rp.end());
     d.n = h.n;
     d.nnz = h.nnz();
-    if (!put(d.rp, rp32.data(), (int64_t)rp32.size()) || hipStreamSynchronize(st_) != hipSuccess) return false;
-    return put(d.ci, h.ci.data(), d.nnz);
+    return put(d.rp, rp32.data(), (int64_t)rp32.size()) && put(d.ci, h.ci.data(), d.nnz);
   }
   bool upload(const Csr& h, DevCsr& d) {
-    if (h.nnz() >= INT32_MAX) return false;
-    std::vector<int32_t> rp32(h.rp.begin(), h.rp.end());
-    d.n = h.n;
-    d.nnz = h.nnz();
-    // the staging vector dies here: copy synchronously with respect to the host
-    if (!put(d.rp, rp32.data(), (int64_t)rp32.size()) || hipStreamSynchronize(st_) != hipSuccess) return false;
-    return put(d.ci, h.ci.data(), d.nnz) && put(d.v, h.v.data(), d.nnz);
+    if (h.v.size() != h.ci.size()) return false;
+    return upload_pattern(h, d) && put(d.v, h.v.data(), d.nnz);
   }
   bool product(const DevCsr& x, const DevCsr& y, DevCsr& out, std::vector<int32_t>& rp_host) {
     const int32_t n = x.n;
     int32_t* bound = nullptr;
-    if (!alloc(bound, n)) return false;
+    if (!alloc(bound, n)) return fail();
     launch_spgemm_bound(n, x.rp, x.ci, y.rp, bound, st_);
     std::vector<int32_t> hb((size_t)n);
-    if (n > 0 && hipMemcpyAsync(hb.data(), bound, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st_) != hipSuccess)
-      return false;
-    if (hipStreamSynchronize(st_) != hipSuccess) return false;
+    if (!get(hb.data(), bound, n)) return fail();
     std::vector<int64_t> off((size_t)n + 1, 0);
     for (int32_t i = 0; i < n; ++i) {
       if (hb[i] > spgemm_row_cap()) return false;
@@ -1036,12 +1067,10 @@ class DeviceSetupStep {
     double* oval = nullptr;
     if (!put(doff, off.data(), (int64_t)n + 1) || !alloc(ocol, off[n]) || !alloc(oval, off[n]) ||
         !alloc(cnt, n))
-      return false;
+      return fail();
     launch_spgemm_rows(n, x.rp, x.ci, x.v, y.rp, y.ci, y.v, doff, ocol, oval, cnt, st_);
     std::vector<int32_t> hc((size_t)n);
-    if (n > 0 && hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st_) != hipSuccess)
-      return false;
-    if (hipStreamSynchronize(st_) != hipSuccess || hipGetLastError() != hipSuccess) return false;
+    if (!get(hc.data(), cnt, n)) return fail();
     rp_host.assign((size_t)n + 1, 0);
     int64_t total = 0;
     for (int32_t i = 0; i < n; ++i) {
@@ -1052,13 +1081,17 @@ class DeviceSetupStep {
     out.n = n;
     out.nnz = total;
     if (!put(out.rp, rp_host.data(), (int64_t)n + 1) || !alloc(out.ci, total) || !alloc(out.v, total))
-      return false;
+      return fail();
     launch_spgemm_compact(n, doff, out.rp, ocol, oval, out.ci, out.v, st_);
-    return hipStreamSynchronize(st_) == hipSuccess && hipGetLastError() == hipSuccess;
+    return hipGetLastError() == hipSuccess || fail();
   }
 
+  const Csr& A_;
+  SetupSiteCounts& done_;
   hipStream_t st_ = nullptr;
   bool ok_ = false;
+  DevCsr a_, s_;
+  bool have_s_ = false;
   std::vector<void*> mem_;
 };
 
@@ -1169,22 +1202,11 @@ int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_id
   // a device handle forms the Galerkin products on the device (the host's
   // summation order, so the hierarchy is the same); a level whose rows are
   // too long for the kernel is formed on the host
-  int device_products = 0, device_interps = 0;
-  if (!o.host_only) {
-    prm.galerkin = [&device_products](const Csr& R, const Csr& Al, const Csr& P, Csr& C) {
-      DeviceSetupStep g;
-      const bool done = g.run(R, Al, P, C);
-      device_products += done;
-      return done;
+  SetupSiteCounts sites;
+  if (!o.host_only)
+    prm.level_steps = [&sites](const Csr& Al) -> std::unique_ptr<LevelSteps> {
+      return std::unique_ptr<LevelSteps>(new DeviceLevelSteps(Al, sites));
     };
-    prm.interp = [&device_interps](const Csr& Al, const Csr& S, const std::vector<int32_t>& cf,
-                                   const std::vector<int32_t>& func, int pmax, Csr& P) {
-      DeviceSetupStep g;
-      const bool done = g.interp(Al, S, cf, func, pmax, P);
-      device_interps += done;
-      return done;
-    };
-  }
   prm.theta = o.strong_threshold;
   prm.max_row_sum = o.max_row_sum;
   prm.max_levels = o.max_levels;
@@ -1215,8 +1237,7 @@ int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_id
   s->ilu_mode = o.ilu_sweep;
   s->threads = prm.threads;
   s->device_ilu = dev_ilu;
-  s->device_galerkin_levels = device_products;
-  s->device_interp_levels = device_interps;
+  s->device_steps = sites;
   s->agg_levels_used = std::min<int32_t>(prm.agg_levels, (int32_t)s->host.lev.size() - 1);
   s->prec = o.precond_precision;
   *out = s.release();
@@ -1600,9 +1621,10 @@ cptr_status cptr_export(cptr_solver s, int32_t what, int32_t level, void* buf, i
       return put(nl, 8);
     }
     case CPTR_EXPORT_SETUP_SITES: {
-      int32_t v[4] = {s->device_galerkin_levels, (int32_t)h.lev.size() - 1, s->device_interp_levels,
-                      std::max(0, (int32_t)h.lev.size() - 1 - s->agg_levels_used)};
-      return put(v, 16);
+      const int32_t built = (int32_t)h.lev.size() - 1;
+      int32_t v[6] = {s->device_steps.strength, built, s->device_steps.interp,
+                      std::max(0, built - s->agg_levels_used), s->device_steps.galerkin, built};
+      return put(v, 24);
     }
     default:
       return (cptr_status)fail(s, CPTR_E_INVALID, "unknown export item");

@@ -911,7 +911,10 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
     const size_t l = h.lev.size() - 1;
     const Csr& A = h.lev[l].A;
     if (A.n <= prm.max_coarse || (int)l + 1 >= prm.max_levels) break;
-    Csr S = strength_graph(A, h.lev[l].func, prm.theta, prm.max_row_sum, threads);
+    std::unique_ptr<LevelSteps> dev = prm.level_steps ? prm.level_steps(A) : nullptr;
+    Csr S;
+    if (!dev || !dev->strength(h.lev[l].func, prm.theta, prm.max_row_sum, S))
+      S = strength_graph(A, h.lev[l].func, prm.theta, prm.max_row_sum, threads);
     const bool agg = (int)l < prm.agg_levels;
     std::vector<int32_t> cf = agg ? aggressive_split(S, threads) : first_pass_split(S, threads);
     int32_t nc = 0;
@@ -920,11 +923,11 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
     Csr P;
     if (agg)
       P = multipass_interp(A, S, cf, h.lev[l].func, threads);
-    else if (!prm.interp || !prm.interp(A, S, cf, h.lev[l].func, prm.pmax, P))
+    else if (!dev || !dev->interp(S, cf, h.lev[l].func, prm.pmax, P))
       P = extended_i_interp(A, S, cf, h.lev[l].func, prm.pmax, threads);
     Csr R = transpose(P, threads);
     Csr Ac;
-    if (!prm.galerkin || !prm.galerkin(R, A, P, Ac)) Ac = galerkin(R, A, P, threads);
+    if (!dev || !dev->galerkin(R, P, Ac)) Ac = galerkin(R, A, P, threads);
     std::vector<int32_t> fc;
     fc.reserve(nc);
     for (int32_t i = 0; i < A.n; ++i)

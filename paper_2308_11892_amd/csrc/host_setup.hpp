@@ -59,6 +59,17 @@ struct AmgLevel {
   std::vector<double> dinv;    // inverse l1-Jacobi diagonal (empty on the coarsest)
 };
 
+// Steps of one level's construction done elsewhere (on the device) with the
+// results this file's functions give, bit for bit; a step that returns false
+// did not produce its result, which is then formed here.
+struct LevelSteps {
+  virtual ~LevelSteps() = default;
+  virtual bool strength(const std::vector<int32_t>& func, double theta, double mrs, Csr& S) = 0;
+  virtual bool interp(const Csr& S, const std::vector<int32_t>& cf, const std::vector<int32_t>& func, int pmax,
+                      Csr& P) = 0;
+  virtual bool galerkin(const Csr& R, const Csr& P, Csr& C) = 0;
+};
+
 struct SetupParams {
   double theta = 0.25;
   double max_row_sum = 0.9;
@@ -70,14 +81,9 @@ struct SetupParams {
   int threads = 1;
   int max_dense_coarse = 4096;  // largest coarsest level solved by dense LU
   bool skip_ilu = false;        // ILU(0) is factored elsewhere (on the device)
-  // forms C = R A P elsewhere (on the device) in this file's summation order;
-  // false: formed here
-  std::function<bool(const Csr& R, const Csr& A, const Csr& P, Csr& C)> galerkin;
-  // forms the extended+i interpolation elsewhere (on the device) exactly as
-  // extended_i_interp does; false: formed here
-  std::function<bool(const Csr& A, const Csr& S, const std::vector<int32_t>& cf,
-                     const std::vector<int32_t>& func, int pmax, Csr& P)>
-      interp;
+  // the steps of the level with operator A done elsewhere (null: all here):
+  // strength, extended+i interpolation and the Galerkin product
+  std::function<std::unique_ptr<LevelSteps>(const Csr& A)> level_steps;
 };
 
 struct HostSetup {

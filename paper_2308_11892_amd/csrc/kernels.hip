@@ -1615,6 +1615,69 @@ __global__ __launch_bounds__(kBlock) void k_grid_ilu_pack(int nb, int nx, int ny
   for (int e = 0; e < 9; ++e) Ut[((size_t)br * 36 + 27 + e) * 64 + lane] = (T)uinv[(size_t)c * 9 + e];
 }
 
+// Strength of connection of one AMG level, one thread per row, in the host
+// construction's order and rounding: j (j != i, of i's unknown type) is a
+// strong dependency of i when -sign(a_ii) a_ij >= theta * max over same-type
+// k != i of (-sign(a_ii) a_ik); none when that maximum is not positive or
+// the same-type row sum exceeds mrs |a_ii| (mrs < 1).  Row i's strong columns
+// go to ocol at arp[i] (A's own row offsets), their count to cnt[i].
+__global__ __launch_bounds__(kBlock) void k_strength(int n, const int32_t* __restrict__ arp,
+                                                     const int32_t* __restrict__ aci,
+                                                     const double* __restrict__ av,
+                                                     const int32_t* __restrict__ func, double theta, double mrs,
+                                                     int32_t* __restrict__ ocol, int32_t* __restrict__ cnt) {
+#pragma clang fp contract(off)
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int b = arp[i], e = arp[i + 1];
+  double aii = 0.0;
+  for (int k = b; k < e; ++k)
+    if (aci[k] == i) aii = av[k];
+  const double sg = aii < 0.0 ? -1.0 : 1.0;
+  double sum = 0.0, best = 0.0;
+  bool any = false;
+  const int32_t fi = func[i];
+  for (int k = b; k < e; ++k) {
+    const int32_t j = aci[k];
+    if (func[j] != fi) continue;
+    sum = sum + av[k];
+    if (j != i) {
+      const double t = -sg * av[k];
+      best = any ? (best < t ? t : best) : t;
+      any = true;
+    }
+  }
+  int c = 0;
+  if (any && best > 0.0 && !(mrs < 1.0 && fabs(sum) > mrs * fabs(aii))) {
+    const double cut = theta * best;
+    for (int k = b; k < e; ++k) {
+      const int32_t j = aci[k];
+      if (j != i && func[j] == fi && -sg * av[k] >= cut) ocol[b + c++] = j;
+    }
+  }
+  cnt[i] = c;
+}
+
+void launch_strength(int n, const int32_t* arp, const int32_t* aci, const double* av, const int32_t* func,
+                     double theta, double mrs, int32_t* ocol, int32_t* cnt, hipStream_t st) {
+  if (n > 0) k_strength<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, arp, aci, av, func, theta, mrs, ocol, cnt);
+}
+
+// the entries of each row from their padded places (off) to CSR order (rp),
+// columns only
+__global__ __launch_bounds__(kBlock) void k_compact_cols(int n, const int32_t* __restrict__ off,
+                                                         const int32_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ ocol, int32_t* __restrict__ ci) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  for (int q = rp[i]; q < rp[i + 1]; ++q) ci[q] = ocol[off[i] + (q - rp[i])];
+}
+
+void launch_compact_cols(int n, const int32_t* off, const int32_t* rp, const int32_t* ocol, int32_t* ci,
+                         hipStream_t st) {
+  if (n > 0) k_compact_cols<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, off, rp, ocol, ci);
+}
+
 // Extended+i interpolation weights of one AMG level (De Sterck, Falgout,
 // Nolting, Yang 2008), one thread per row, in the host construction's order
 // and rounding: the interpolatory set of an F row is its strong C points and

@@ -136,6 +136,14 @@ void launch_grid_ilu_diag(const Sell& A, const int32_t* fperm, int32_t p0, int32
 template <class T>
 void launch_grid_ilu_pack(const Sell& A, int nx, int ny, const double* uinv, T* Lt, T* Ut,
                           hipStream_t st);
+// Strength of connection of one AMG level in the host construction's order
+// and rounding (scalar CSR A, int32): row i's strong columns at ocol[arp[i]..],
+// their count in cnt[i]; launch_compact_cols moves them to CSR order (off:
+// padded row starts, rp: exclusive prefix of cnt).
+void launch_strength(int n, const int32_t* arp, const int32_t* aci, const double* av, const int32_t* func,
+                     double theta, double mrs, int32_t* ocol, int32_t* cnt, hipStream_t st);
+void launch_compact_cols(int n, const int32_t* off, const int32_t* rp, const int32_t* ocol, int32_t* ci,
+                         hipStream_t st);
 // Extended+i interpolation of one AMG level in the host construction's order
 // and rounding (scalar CSR A and strength pattern S, int32; cf 1 = C, -1 =
 // F; func: unknown type per row; cidx: coarse index of each C point).  Row i

@@ -380,18 +380,19 @@ def test_setup_from_device_arrays(name):
 @pytest.mark.parametrize("name,elliptic", [("grid20x20x5", (0, 1)), ("prism2000x5", (0, 1)),
                                            ("grid30x20x6", (0,))])
 def test_device_setup_steps_equal_host(name, elliptic):
-    """A device handle forms every coarse operator R A P and every extended+i
-    interpolation on the GPU; they equal the host's bit for bit (same splits,
-    patterns and values on every level)."""
+    """A device handle forms every strength graph, every extended+i
+    interpolation and every coarse operator R A P on the GPU; the hierarchy
+    equals the host's bit for bit (same splits, patterns and values on every
+    level)."""
     c = J.by_name(name)
     with L.Solver(c.row_ptr, c.col_idx, c.values, elliptic=elliptic) as sd, \
             L.Solver(c.row_ptr, c.col_idx, c.values, elliptic=elliptic, host_only=1) as sh:
         rows_d, nnz_d = sd.hierarchy()
         rows_h, nnz_h = sh.hierarchy()
         assert np.array_equal(rows_d, rows_h) and np.array_equal(nnz_d, nnz_h)
-        sites = sd.export("SETUP_SITES", 0, 4, np.int32)
-        assert sites[1] == len(rows_d) - 1 and sites[0] == sites[1], sites
-        assert sites[3] == len(rows_d) - 2 and sites[2] == sites[3], sites
+        sites = sd.export("SETUP_SITES", 0, 6, np.int32)
+        built = len(rows_d) - 1
+        assert list(sites) == [built, built, built - 1, built - 1, built, built], sites
         for l in range(len(rows_d)):
             for which in ("A", "P") if l + 1 < len(rows_d) else ("A",):
                 Md, Mh = sd.level_matrix(l, which), sh.level_matrix(l, which)
