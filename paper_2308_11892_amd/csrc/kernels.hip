@@ -2211,18 +2211,22 @@ void launch_grid_ilu_pack(const Sell& A, int nx, int ny, const double* uinv, T* 
                                                                   Lt, Ut);
 }
 
-// workgroup: the sweeping wave and the staging waves; ring slots: as many as
-// fit in LDS (18 KB forward, 24 KB backward per slot in FP64; the FP32 slots
-// are half that).  The forward sweep keeps five steps in flight from HBM; the
-// backward sweeping wave needs more than 256 VGPRs in FP64, which leaves room
-// for one wave per SIMD only (three stagers).
+// workgroup: the sweeping wave and the staging waves.  The forward sweep keeps
+// five steps in flight from HBM; the backward sweeping wave needs more than
+// 256 VGPRs in FP64, which leaves room for one wave per SIMD only (three
+// stagers).  Ring slots (18 KB forward, 24 KB backward per slot in FP64; the
+// FP32 slots are half that): measured on 250x250x50, rings of 6 forward and
+// 4 backward slots beat the 8 and 6 that fit in LDS (the sweeps took 0.347
+// and 0.510 ms against 0.356 and 0.537); with fewer slots the staging waves
+// wait more and compete less with the sweeping wave for LDS.
 constexpr int kGridStagersFwd = 5, kGridStagersBwd = 3;
+constexpr int kGridSlotsFwd = 6, kGridSlotsBwd = 4;
 
 template <class T>
 void launch_ilu_fwd_grid(int nx, int ny, int nz, const T* Lt, const T* r2t, T* ytile, T* faces,
                          int* tickets, double* err, long spin_limit, hipStream_t st) {
   const int nJ = (ny + kTJ - 1) / kTJ, nK = (nz + kTK - 1) / kTK;
-  k_ilu_grid<true, 2, kGridStagersFwd, 8, T><<<nJ * nK, 64 * (kGridStagersFwd + 1), 0, st>>>(
+  k_ilu_grid<true, 2, kGridStagersFwd, kGridSlotsFwd, T><<<nJ * nK, 64 * (kGridStagersFwd + 1), 0, st>>>(
       nx, ny, nz, nJ, nK, Lt, r2t, ytile, faces, nullptr, 0, 0, nullptr, tickets, err, spin_limit);
 }
 
@@ -2232,10 +2236,10 @@ void launch_ilu_bwd_grid(int nx, int ny, int nz, const T* Ut, T* ytile, const T*
                          long spin_limit, hipStream_t st) {
   const int nJ = (ny + kTJ - 1) / kTJ, nK = (nz + kTK - 1) / kTK;
   if (ne == 2)
-    k_ilu_grid<false, 2, kGridStagersBwd, 6, T><<<nJ * nK, 64 * (kGridStagersBwd + 1), 0, st>>>(
+    k_ilu_grid<false, 2, kGridStagersBwd, kGridSlotsBwd, T><<<nJ * nK, 64 * (kGridStagersBwd + 1), 0, st>>>(
         nx, ny, nz, nJ, nK, Ut, ytile, nullptr, faces, e0t, eidx[0], eidx[1], z, tickets, err, spin_limit);
   else
-    k_ilu_grid<false, 1, kGridStagersBwd, 6, T><<<nJ * nK, 64 * (kGridStagersBwd + 1), 0, st>>>(
+    k_ilu_grid<false, 1, kGridStagersBwd, kGridSlotsBwd, T><<<nJ * nK, 64 * (kGridStagersBwd + 1), 0, st>>>(
         nx, ny, nz, nJ, nK, Ut, ytile, nullptr, faces, e0t, eidx[0], 0, z, tickets, err, spin_limit);
 }
 
