@@ -399,13 +399,15 @@ int build_grid_factors_device(cptr_solver s, PrecDev<T>& d, hipStream_t st) {
       (rc = dalloc(s, uinv, (int64_t)nb * 9)) || (rc = dalloc(s, bad, 1)))
     return rc;
   if (s->measure) return CPTR_OK;
-  HIP_TRY(s, hipMemset(d.Lg, 0, sizeof(T) * (size_t)rows * 27 * 64));
-  HIP_TRY(s, hipMemset(d.Ug, 0, sizeof(T) * (size_t)rows * 36 * 64));
-  HIP_TRY(s, hipMemset(d.ytile, 0, sizeof(T) * (size_t)rows * 3 * 64));
-  HIP_TRY(s, hipMemset(d.r2tile, 0, sizeof(T) * (size_t)rows * 3 * 64));
-  HIP_TRY(s, hipMemset(d.e0tile, 0, sizeof(T) * (size_t)rows * 2 * 64));
-  const int none = INT32_MAX;
-  HIP_TRY(s, hipMemcpy(bad, &none, sizeof(int), hipMemcpyHostToDevice));
+  // every fill and copy of the build goes on `st`: a null-stream operation is
+  // not ordered with the kernels of a non-blocking stream
+  HIP_TRY(s, hipMemsetAsync(d.Lg, 0, sizeof(T) * (size_t)rows * 27 * 64, st));
+  HIP_TRY(s, hipMemsetAsync(d.Ug, 0, sizeof(T) * (size_t)rows * 36 * 64, st));
+  HIP_TRY(s, hipMemsetAsync(d.ytile, 0, sizeof(T) * (size_t)rows * 3 * 64, st));
+  HIP_TRY(s, hipMemsetAsync(d.r2tile, 0, sizeof(T) * (size_t)rows * 3 * 64, st));
+  HIP_TRY(s, hipMemsetAsync(d.e0tile, 0, sizeof(T) * (size_t)rows * 2 * 64, st));
+  const int none = INT32_MAX;  // lives until the synchronisation below
+  HIP_TRY(s, hipMemcpyAsync(bad, &none, sizeof(int), hipMemcpyHostToDevice, st));
   for (size_t l = 0; l + 1 < s->flev_ptr.size(); ++l)
     launch_grid_ilu_diag(s->A, s->fperm, s->flev_ptr[l], s->flev_ptr[l + 1], nx, nx * ny, uinv, bad, st);
   launch_grid_ilu_pack(s->A, nx, ny, uinv, d.Lg, d.Ug, st);
@@ -471,8 +473,8 @@ int build_ilu_factors_device(cptr_solver s, PrecDev<T>& d, const std::vector<int
       (rc = upload(s, ds_d, dslot.data(), (int64_t)nb, st)) || (rc = dalloc(s, bad, 1)))
     return rc;
   if (s->measure) return CPTR_OK;
-  const int none = INT32_MAX;
-  HIP_TRY(s, hipMemcpy(bad, &none, sizeof(int), hipMemcpyHostToDevice));
+  const int none = INT32_MAX;  // lives until the synchronisation below
+  HIP_TRY(s, hipMemcpyAsync(bad, &none, sizeof(int), hipMemcpyHostToDevice, st));
   HIP_TRY(s, hipMemcpyAsync(W, s->A.val, sizeof(double) * (size_t)s->A.nslots * kLanes * 9,
                             hipMemcpyDeviceToDevice, st));
   for (size_t l = 0; l + 1 < s->flev_ptr.size(); ++l)
@@ -654,7 +656,7 @@ int build_device(cptr_solver s, hipStream_t st) {
     order(h.fwd_level, h.n_fwd_levels, fp, s->flev_ptr);
     order(h.bwd_level, h.n_bwd_levels, bp, s->blev_ptr);
     if ((rc = dalloc(s, s->tickets, 2))) return rc;
-    if (!s->measure) HIP_TRY(s, hipMemset(s->tickets, 0, 2 * sizeof(int)));
+    if (!s->measure) HIP_TRY(s, hipMemsetAsync(s->tickets, 0, 2 * sizeof(int), st));
     const bool grid = detect_grid(h, s->grid);
     if (s->ilu_mode == CPTR_ILU_SWEEP_GRID && !grid)
       return fail(s, CPTR_E_INVALID, "ilu_sweep = GRID needs a 7-point stencil in lexicographic order");
@@ -671,7 +673,7 @@ int build_device(cptr_solver s, hipStream_t st) {
   if ((rc = dalloc(s, s->part, (int64_t)kRedBlocks * (kMaxRestart + 2)))) return rc;
   if ((rc = dalloc(s, s->hdev, 256))) return rc;
   if (s->measure) return CPTR_OK;
-  HIP_TRY(s, hipMemset(s->hdev, 0, 256 * sizeof(double)));
+  HIP_TRY(s, hipMemsetAsync(s->hdev, 0, 256 * sizeof(double), st));
   {
     void* hp = nullptr;
     HIP_TRY(s, hipHostMalloc(&hp, 256 * sizeof(double), hipHostMallocDefault));
@@ -1277,6 +1279,10 @@ int setup_device(cptr_solver s, DevArena* arena, int restart, bool flexible, hip
     rc = fail(s, CPTR_E_NOMEM, "host allocation failed while packing device layouts");
   }
   if (rc) {
+    // kernels of the failed build may still run on st: its memory goes back
+    // (to an arena other requests allocate from) only once they are done
+    (void)hipStreamSynchronize(st);
+    (void)hipGetLastError();
     release_device(s);
     return rc;
   }
