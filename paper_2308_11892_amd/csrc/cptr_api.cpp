@@ -263,10 +263,12 @@ template <class T>
 int upload(cptr_solver s, T*& p, const T* src, int64_t count, hipStream_t st) {
   int rc = dalloc(s, p, count);
   if (rc) return rc;
-  // blocking copy: the host staging vectors die right after the upload
-  (void)st;
-  if (count > 0 && !s->measure)
-    HIP_TRY(s, hipMemcpy(p, src, sizeof(T) * (size_t)count, hipMemcpyHostToDevice));
+  // on the build's stream, which the kernels reading p use too, and complete
+  // before returning: the host staging vectors die right after the upload
+  if (count > 0 && !s->measure) {
+    HIP_TRY(s, hipMemcpyAsync(p, src, sizeof(T) * (size_t)count, hipMemcpyHostToDevice, st));
+    HIP_TRY(s, hipStreamSynchronize(st));
+  }
   return CPTR_OK;
 }
 
