@@ -1210,6 +1210,25 @@ __device__ __forceinline__ void block_store(const double* acc, int nv, double* p
   (void)nv;
 }
 
+// Element i of basis columns jb .. jb+G-1, with columns past the first nv read
+// as column nv-1 (always present: nv >= 1).  The group's loads are issued
+// together, with no branch between them to wait at.  The callers give the
+// extra columns zero coefficients and drop their sums, so the results equal
+// those of a loop over the nv columns alone.  Kernels with MAXV <= 8 are
+// launched with nv == MAXV (one group, no extra column); larger ones read
+// groups of 8.
+template <int MAXV>
+constexpr int col_group() { return MAXV < 8 ? MAXV : 8; }
+template <int G>
+__device__ __forceinline__ void load_cols(const double* __restrict__ V, int64_t ldv, int nv, int jb, int64_t i,
+                                          double* v) {
+#pragma unroll
+  for (int q = 0; q < G; ++q) {
+    const int j = jb + q < nv ? jb + q : nv - 1;
+    v[q] = V[(size_t)j * ldv + i];
+  }
+}
+
 template <int MAXV>
 __global__ __launch_bounds__(kBlock) void k_mdot(int64_t n, int nv, const double* __restrict__ V, int64_t ldv,
                                                  const double* __restrict__ w, double* __restrict__ part) {
@@ -1220,8 +1239,13 @@ __global__ __launch_bounds__(kBlock) void k_mdot(int64_t n, int nv, const double
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
     const double wi = w[i];
 #pragma unroll
-    for (int j = 0; j < MAXV; ++j)
-      if (j < nv) acc[j] += V[(size_t)j * ldv + i] * wi;
+    for (int jb = 0; jb < MAXV; jb += col_group<MAXV>())
+      if (jb < nv) {
+        double v[col_group<MAXV>()];
+        load_cols<col_group<MAXV>()>(V, ldv, nv, jb, i, v);
+#pragma unroll
+        for (int q = 0; q < col_group<MAXV>(); ++q) acc[jb + q] += v[q] * wi;
+      }
   }
   block_store<MAXV>(acc, nv, part, nv);
 }
@@ -1241,12 +1265,22 @@ __global__ __launch_bounds__(kBlock) void k_maxpy_dot(int64_t n, int nv, const d
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
     double wi = w[i];
 #pragma unroll
-    for (int j = 0; j < MAXV; ++j)
-      if (j < nv) wi -= c[j] * V[(size_t)j * ldv + i];
+    for (int jb = 0; jb < MAXV; jb += col_group<MAXV>())
+      if (jb < nv) {
+        double v[col_group<MAXV>()];
+        load_cols<col_group<MAXV>()>(V, ldv, nv, jb, i, v);
+#pragma unroll
+        for (int q = 0; q < col_group<MAXV>(); ++q) wi -= c[jb + q] * v[q];
+      }
     w[i] = wi;
 #pragma unroll
-    for (int j = 0; j < MAXV; ++j)
-      if (j < nv) acc[j] += V[(size_t)j * ldv + i] * wi;
+    for (int jb = 0; jb < MAXV; jb += col_group<MAXV>())
+      if (jb < nv) {
+        double v[col_group<MAXV>()];
+        load_cols<col_group<MAXV>()>(V, ldv, nv, jb, i, v);
+#pragma unroll
+        for (int q = 0; q < col_group<MAXV>(); ++q) acc[jb + q] += v[q] * wi;
+      }
   }
   block_store<MAXV>(acc, nv, part, nv);
 }
@@ -1264,8 +1298,13 @@ __global__ __launch_bounds__(kBlock) void k_maxpy_norm(int64_t n, int nv, const 
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
     double wi = w[i];
 #pragma unroll
-    for (int j = 0; j < MAXV; ++j)
-      if (j < nv) wi -= c[j] * V[(size_t)j * ldv + i];
+    for (int jb = 0; jb < MAXV; jb += col_group<MAXV>())
+      if (jb < nv) {
+        double v[col_group<MAXV>()];
+        load_cols<col_group<MAXV>()>(V, ldv, nv, jb, i, v);
+#pragma unroll
+        for (int q = 0; q < col_group<MAXV>(); ++q) wi -= c[jb + q] * v[q];
+      }
     w[i] = wi;
     acc[0] += wi * wi;
   }
@@ -2278,7 +2317,14 @@ void launch_ilu_bwd_sf(const SellT<T>& U, int width, const int32_t* perm, const 
 
 #define MAXV_DISPATCH(KERNEL, nv, ...)                                                     \
   do {                                                                                     \
-    if ((nv) <= 8) KERNEL<8><<<kRedBlocks, kBlock, 0, st>>>(__VA_ARGS__);                  \
+    if ((nv) == 1) KERNEL<1><<<kRedBlocks, kBlock, 0, st>>>(__VA_ARGS__);                  \
+    else if ((nv) == 2) KERNEL<2><<<kRedBlocks, kBlock, 0, st>>>(__VA_ARGS__);             \
+    else if ((nv) == 3) KERNEL<3><<<kRedBlocks, kBlock, 0, st>>>(__VA_ARGS__);             \
+    else if ((nv) == 4) KERNEL<4><<<kRedBlocks, kBlock, 0, st>>>(__VA_ARGS__);             \
+    else if ((nv) == 5) KERNEL<5><<<kRedBlocks, kBlock, 0, st>>>(__VA_ARGS__);             \
+    else if ((nv) == 6) KERNEL<6><<<kRedBlocks, kBlock, 0, st>>>(__VA_ARGS__);             \
+    else if ((nv) == 7) KERNEL<7><<<kRedBlocks, kBlock, 0, st>>>(__VA_ARGS__);             \
+    else if ((nv) == 8) KERNEL<8><<<kRedBlocks, kBlock, 0, st>>>(__VA_ARGS__);             \
     else if ((nv) <= 16) KERNEL<16><<<kRedBlocks, kBlock, 0, st>>>(__VA_ARGS__);           \
     else if ((nv) <= 32) KERNEL<32><<<kRedBlocks, kBlock, 0, st>>>(__VA_ARGS__);           \
     else KERNEL<64><<<kRedBlocks, kBlock, 0, st>>>(__VA_ARGS__);                           \
