@@ -186,6 +186,7 @@ struct cptr_solver_s {
   uint32_t profile_mask = 0;  // phases timed while profiling
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
+  hipEvent_t ev_copy = nullptr;  // marks the Hessenberg column's copy to the host
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
   double phase_ms[kPhases] = {0};
   int64_t phase_cnt[kPhases] = {0};
@@ -714,16 +715,32 @@ void ph_harvest(cptr_solver s) {  // call after the stream is synchronised
 // ---------------------------------------------------------------- apply
 // e0 = V-cycle(R_QI r) on the elliptic block (first stage without
 // prolongation), in the preconditioner's type T
+// b0 = R_QI r and, with a smoothed level 0, its pre-smoothed iterate D^-1 b0
 template <class T>
-void enqueue_stage1(cptr_solver s, PrecDev<T>& d, const double* r, hipStream_t st) {
+void enqueue_restrict(cptr_solver s, PrecDev<T>& d, const double* r, hipStream_t st) {
+  auto& l0 = d.lev[0];
+  launch_l0_restrict(s->host.nb, s->ne, r, s->W, s->eidx_h, s->hidx_h, l0.b, d.lev.size() > 1 ? l0.dinv : nullptr,
+                     l0.x, st);
+}
+void enqueue_restrict(cptr_solver s, const double* r, hipStream_t st) {
+  if (s->prec == CPTR_PRECISION_FP32)
+    enqueue_restrict(s, s->p32, r, st);
+  else
+    enqueue_restrict(s, s->p64, r, st);
+}
+
+// `restricted`: the restriction of r is already queued on st
+template <class T>
+void enqueue_stage1(cptr_solver s, PrecDev<T>& d, const double* r, hipStream_t st, bool restricted) {
   const int ne = s->ne;
   const int L = (int)d.lev.size();
   auto& l0 = d.lev[0];
   hipEvent_t ev;
-  ph_begin(s, st, PH_RESTRICT, ev);
-  launch_l0_restrict(s->host.nb, ne, r, s->W, s->eidx_h, s->hidx_h, l0.b, L > 1 ? l0.dinv : nullptr,
-                     l0.x, st);
-  ph_end(s, st, PH_RESTRICT, ev);
+  if (!restricted) {
+    ph_begin(s, st, PH_RESTRICT, ev);
+    enqueue_restrict(s, d, r, st);
+    ph_end(s, st, PH_RESTRICT, ev);
+  }
   if (L == 1) {
     ph_begin(s, st, PH_VCC, ev);
     launch_coarse_solve(s->ncoarse, s->coarse_lu, s->coarse_piv, l0.b, l0.e, st);
@@ -834,16 +851,16 @@ void enqueue_stage2(cptr_solver s, PrecDev<T>& d, const double* r, const T* e0, 
 }
 
 template <class T>
-void enqueue_apply(cptr_solver s, PrecDev<T>& d, const double* r, double* z, hipStream_t st) {
-  enqueue_stage1(s, d, r, st);
+void enqueue_apply(cptr_solver s, PrecDev<T>& d, const double* r, double* z, hipStream_t st, bool restricted) {
+  enqueue_stage1(s, d, r, st, restricted);
   enqueue_stage2(s, d, r, (const T*)d.lev[0].e, z, st);
 }
 
-void enqueue_apply(cptr_solver s, const double* r, double* z, hipStream_t st) {
+void enqueue_apply(cptr_solver s, const double* r, double* z, hipStream_t st, bool restricted = false) {
   if (s->prec == CPTR_PRECISION_FP32)
-    enqueue_apply(s, s->p32, r, z, st);
+    enqueue_apply(s, s->p32, r, z, st, restricted);
   else
-    enqueue_apply(s, s->p64, r, z, st);
+    enqueue_apply(s, s->p64, r, z, st, restricted);
 }
 
 int ensure_solve_space(cptr_solver s, int m, bool flexible) {
@@ -1299,6 +1316,8 @@ void release_device(cptr_solver s) {
   for (auto& e : s->ev_pool)
     if (e) (void)hipEventDestroy(e);
   s->ev_pool.clear();
+  if (s->ev_copy) (void)hipEventDestroy(s->ev_copy);
+  s->ev_copy = nullptr;
   s->ev_used = 0;
   s->ev_pending.clear();
   reset_device_state(s);
@@ -1368,10 +1387,10 @@ cptr_status cptr_stage1(cptr_solver s, const double* r, double* x1, void* stream
   if (!r || !x1 || r == x1) return (cptr_status)fail(s, CPTR_E_INVALID, "r and x1 must be distinct non-NULL device pointers");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (s->prec == CPTR_PRECISION_FP32) {
-    enqueue_stage1(s, s->p32, r, st);
+    enqueue_stage1(s, s->p32, r, st, false);
     launch_prolong_e(s->host.nb, s->ne, s->eidx_h, s->p32.lev[0].e, x1, st);
   } else {
-    enqueue_stage1(s, s->p64, r, st);
+    enqueue_stage1(s, s->p64, r, st, false);
     launch_prolong_e(s->host.nb, s->ne, s->eidx_h, s->p64.lev[0].e, x1, st);
   }
   hipError_t e = hipGetLastError();
@@ -1428,6 +1447,13 @@ cptr_status cptr_gmres_solve(cptr_solver s, const double* b, double* x, const cp
   s->profile_mask = o.profile == 1 ? ~0u : (uint32_t)o.profile >> 1;
   s->ev_used = 0;
   s->ev_pending.clear();
+  if (!s->ev_copy && hipEventCreateWithFlags(&s->ev_copy, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    s->ev_copy = nullptr;
+  }
+  // queue the next step's restriction early unless its phase is being timed
+  const bool prefetch = s->ev_copy && !(s->profiling && (s->profile_mask & (1u << PH_RESTRICT)));
+  bool pre = false;  // the restriction of the next basis vector is queued
   const int64_t N = s->N;
   const int m = o.restart;
   const int64_t ld = s->ldv;
@@ -1464,6 +1490,7 @@ cptr_status cptr_gmres_solve(cptr_solver s, const double* b, double* x, const cp
     }
     if (it >= o.max_iter) break;
     launch_scale_host(N, r0, beta, V, st);
+    pre = false;
     r0 = r;
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
@@ -1472,7 +1499,8 @@ cptr_status cptr_gmres_solve(cptr_solver s, const double* b, double* x, const cp
       double* vj = V + (size_t)j * ld;
       double* zj = o.flexible ? s->Z + (size_t)j * ld : s->wu;
       double* w = V + (size_t)(j + 1) * ld;
-      enqueue_apply(s, vj, zj, st);
+      enqueue_apply(s, vj, zj, st, pre);
+      pre = false;
       ph_begin(s, st, PH_SPMV, ev);
       launch_bsr3_spmv(s->A, zj, nullptr, w, false, st);
       ph_end(s, st, PH_SPMV, ev);
@@ -1488,7 +1516,18 @@ cptr_status cptr_gmres_solve(cptr_solver s, const double* b, double* x, const cp
       launch_scale(N, w, s->hdev + 128, w, st);
       ph_end(s, st, PH_ARNOLDI, ev);
       HIP_TRY(s, hipMemcpyAsync(s->hhost, s->hdev, 144 * sizeof(double), hipMemcpyDeviceToHost, st));
-      HIP_TRY(s, hipStreamSynchronize(st));
+      if (prefetch && j + 1 < m) {
+        // the next step's restriction reads only v_{j+1}: it is queued before
+        // the host waits for the Hessenberg column, so the device has work
+        // while the host decides whether that step happens (if it does not,
+        // the restriction's level-0 output is scratch that nothing reads)
+        HIP_TRY(s, hipEventRecord(s->ev_copy, st));
+        enqueue_restrict(s, V + (size_t)(j + 1) * ld, st);
+        pre = true;
+        HIP_TRY(s, hipEventSynchronize(s->ev_copy));
+      } else {
+        HIP_TRY(s, hipStreamSynchronize(st));
+      }
       {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return (cptr_status)hip_fail(s, e, "kernel launch in cptr_gmres_solve");
