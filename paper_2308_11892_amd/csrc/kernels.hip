@@ -1227,6 +1227,9 @@ __device__ __forceinline__ void load_cols(const double* __restrict__ V, int64_t 
     const int j = jb + q < nv ? jb + q : nv - 1;
     v[q] = V[(size_t)j * ldv + i];
   }
+  // keep the scheduler from interleaving the group's loads with their uses
+  // (it otherwise issues some of them one at a time, each waited for)
+  __builtin_amdgcn_sched_barrier(0);
 }
 
 template <int MAXV>
@@ -1352,12 +1355,21 @@ struct Coef64 {
   double c[64];
 };
 
+// x += sum_j coef_j V_j (coefficients past nv are zero)
+template <int MAXV>
 __global__ __launch_bounds__(kBlock) void k_update(int64_t n, int nv, const double* __restrict__ V, int64_t ldv,
                                                    Coef64 coef, double* __restrict__ x) {
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
     double s = x[i];
-    for (int j = 0; j < nv; ++j) s += coef.c[j] * V[(size_t)j * ldv + i];
+#pragma unroll
+    for (int jb = 0; jb < MAXV; jb += col_group<MAXV>())
+      if (jb < nv) {
+        double v[col_group<MAXV>()];
+        load_cols<col_group<MAXV>()>(V, ldv, nv, jb, i, v);
+#pragma unroll
+        for (int q = 0; q < col_group<MAXV>(); ++q) s += coef.c[jb + q] * v[q];
+      }
     x[i] = s;
   }
 }
@@ -2332,14 +2344,17 @@ void launch_ilu_bwd_sf(const SellT<T>& U, int width, const int32_t* perm, const 
 
 void launch_mdot(int64_t n, int nv, const double* V, int64_t ldv, const double* w, double* part,
                  hipStream_t st) {
+  if (nv <= 0) return;  // callers pass 1 <= nv <= 64; the kernel reads column nv - 1
   MAXV_DISPATCH(k_mdot, nv, n, nv, V, ldv, w, part);
 }
 void launch_maxpy_dot(int64_t n, int nv, const double* V, int64_t ldv, const double* coef,
                       double* w, double* part, hipStream_t st) {
+  if (nv <= 0) return;  // callers pass 1 <= nv <= 64; the kernel reads column nv - 1
   MAXV_DISPATCH(k_maxpy_dot, nv, n, nv, V, ldv, coef, w, part);
 }
 void launch_maxpy_norm(int64_t n, int nv, const double* V, int64_t ldv, const double* coef,
                        double* w, double* part, hipStream_t st) {
+  if (nv <= 0) return;  // callers pass 1 <= nv <= 64; the kernel reads column nv - 1
   MAXV_DISPATCH(k_maxpy_norm, nv, n, nv, V, ldv, coef, w, part);
 }
 void launch_reduce(int ncols, const double* part, double* out, int add_to_out, hipStream_t st) {
@@ -2356,9 +2371,10 @@ void launch_norm2(int64_t n, const double* x, double* part, hipStream_t st) {
 }
 void launch_update_host_coef(int64_t n, int nv, const double* V, int64_t ldv, const double* coef,
                              double* x, hipStream_t st) {
+  if (nv <= 0 || n <= 0) return;  // nothing to add (the kernel reads column nv - 1)
   Coef64 c;
   for (int j = 0; j < 64; ++j) c.c[j] = j < nv ? coef[j] : 0.0;
-  k_update<<<kRedBlocks, kBlock, 0, st>>>(n, nv, V, ldv, c, x);
+  MAXV_DISPATCH(k_update, nv, n, nv, V, ldv, c, x);
 }
 
 // the preconditioner runs in FP64 or, in the mixed-precision mode, in FP32
