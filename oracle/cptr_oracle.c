@@ -731,6 +731,7 @@ struct or_amg {
   int *cf[OR_MAXLEV], *func[OR_MAXLEV];
   double *dinv[OR_MAXLEV];
   int nd;                     /* coarsest size */
+  int nsweeps;                /* l1-Jacobi sweeps before and after the coarse correction */
   double *lu;                 /* nd x nd, row-major, LU with partial pivoting */
   int *piv;
 };
@@ -742,6 +743,7 @@ void or_amg_opts_default(or_amg_opts *o) {
   o->max_coarse = 9;
   o->pmax = 4;
   o->agg_levels = 1;
+  o->num_sweeps = 1;
 }
 
 /* l1-Jacobi (Baker, Falgout, Kolev, Yang 2011) with one point per block:
@@ -835,7 +837,9 @@ int or_amg_setup(int n, const long *rp, const int *ci, const double *v,
     or_amg_opts_default(&o);
   if (n <= 0) return fail(OR_E_INVALID, "empty matrix");
   if (o.max_levels < 1 || o.max_levels > OR_MAXLEV) return fail(OR_E_INVALID, "max_levels");
+  if (o.num_sweeps < 1) return fail(OR_E_INVALID, "num_sweeps");
   or_amg *a = xcalloc(1, sizeof *a);
+  a->nsweeps = o.num_sweeps;
   a->A[0] = mat_from(n, n, rp, ci, v);
   a->func[0] = xmalloc(sizeof(int) * (size_t)n);
   memcpy(a->func[0], func, sizeof(int) * (size_t)n);
@@ -916,8 +920,10 @@ void or_amg_get_dinv(const or_amg *a, int l, double *d) {
   if (a->dinv[l]) memcpy(d, a->dinv[l], sizeof(double) * (size_t)a->A[l]->n);
 }
 
-/* One V-cycle from a zero initial guess (Sec. 3.1: one V-cycle, first-order
- * relaxation = one l1-Jacobi sweep before and after the coarse correction). */
+/* One V-cycle from a zero initial guess (Sec. 3.1: one V-cycle with
+ * "first-order relaxation", read as nsweeps l1-Jacobi sweeps before and after
+ * the coarse correction, one by default).  A sweep is x += D^-1 (b - A x); the
+ * first pre-sweep starts from x = 0, so it is x = D^-1 b. */
 static void vcycle_level(const or_amg *a, int l, const double *b, double *x) {
   const or_mat *A = a->A[l];
   int n = A->n;
@@ -929,6 +935,10 @@ static void vcycle_level(const or_amg *a, int l, const double *b, double *x) {
   double *r = xmalloc(sizeof(double) * (size_t)n);
   /* pre-smoothing from x = 0 */
   for (int i = 0; i < n; i++) x[i] = d[i] * b[i];
+  for (int s = 1; s < a->nsweeps; s++) {
+    mat_vec(A, x, r);
+    for (int i = 0; i < n; i++) x[i] += d[i] * (b[i] - r[i]);
+  }
   /* residual and restriction */
   mat_vec(A, x, r);
   for (int i = 0; i < n; i++) r[i] = b[i] - r[i];
@@ -941,8 +951,10 @@ static void vcycle_level(const or_amg *a, int l, const double *b, double *x) {
   mat_vec(a->P[l], xc, r);
   for (int i = 0; i < n; i++) x[i] += r[i];
   /* post-smoothing */
-  mat_vec(A, x, r);
-  for (int i = 0; i < n; i++) x[i] += d[i] * (b[i] - r[i]);
+  for (int s = 0; s < a->nsweeps; s++) {
+    mat_vec(A, x, r);
+    for (int i = 0; i < n; i++) x[i] += d[i] * (b[i] - r[i]);
+  }
   free(bc);
   free(xc);
   free(r);

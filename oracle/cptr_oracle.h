@@ -68,6 +68,7 @@ typedef struct {
   int max_coarse;      /* 9 */
   int pmax;            /* 4 */
   int agg_levels;      /* 1: levels coarsened aggressively (multipass interpolation) */
+  int num_sweeps;      /* 1: l1-Jacobi sweeps before and after the coarse correction */
 } or_amg_opts;
 void or_amg_opts_default(or_amg_opts *o);
 

@@ -331,16 +331,20 @@ def test_vcycle_symmetric_for_spd():
     assert np.linalg.eigvalsh(0.5 * (B + B.T)).min() > 0
 
 
-def test_two_grid_matrix_form():
+@pytest.mark.parametrize("sweeps", [1, 2, 3])
+def test_two_grid_matrix_form(sweeps):
+    """Two-grid cycle with `sweeps` l1-Jacobi sweeps on each side: its error
+    propagation is S^k (I - P Ac^-1 P^T A) S^k with S = I - D^-1 A."""
     A = lap3d(4, 4, 3, rng=np.random.default_rng(8))
     n = A.shape[0]
-    amg = O.Amg(A, np.zeros(n, dtype=np.int32), max_levels=2)
+    amg = O.Amg(A, np.zeros(n, dtype=np.int32), max_levels=2, num_sweeps=sweeps)
     P = amg.P(0).toarray()
     Ad = A.toarray()
     D = np.diag(amg.dinv(0))
     I = np.eye(n)
     Ac = P.T @ Ad @ P
-    E = (I - D @ Ad) @ (I - P @ np.linalg.solve(Ac, P.T @ Ad)) @ (I - D @ Ad)
+    S = np.linalg.matrix_power(I - D @ Ad, sweeps)
+    E = S @ (I - P @ np.linalg.solve(Ac, P.T @ Ad)) @ S
     Bref = (I - E) @ np.linalg.inv(Ad)
     B = np.column_stack([amg.vcycle(e) for e in np.eye(n)])
     assert np.abs(B - Bref).max() <= 1e-12 * np.abs(Bref).max()
