@@ -27,11 +27,17 @@
  *     completes.  Input and output must not alias.
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *     All device work is enqueued on it.
- *   - A handle owns all hierarchy, factor and workspace memory; it allocates
- *     in cptr_setup and frees in cptr_destroy.  cptr_apply never allocates;
- *     cptr_gmres_solve allocates only when its restart length exceeds every
- *     earlier call's.  A handle is not thread-safe; distinct handles are
- *     independent.
+ *   - A handle owns all hierarchy, factor and workspace memory, the Krylov
+ *     space of cptr_gmres_solve included (sized by cptr_setup_opts.max_restart
+ *     and flexible_space); it allocates in cptr_setup and frees in
+ *     cptr_destroy.  cptr_apply, cptr_stage1, cptr_ilu_solve, cptr_spmv and
+ *     cptr_gmres_solve never allocate device memory.  A handle is not
+ *     thread-safe; distinct handles are independent.
+ *   - The ILU(0) sweeps wait on each other's results with bounded waits.  A
+ *     wait that reaches its bound (never, for a valid schedule) sets a flag on
+ *     the handle; cptr_gmres_solve reports it as CPTR_E_HIP and clears it at
+ *     its start, and cptr_sweep_check reads and clears it after asynchronous
+ *     calls.
  */
 #ifndef CPTR_H
 #define CPTR_H
@@ -88,6 +94,15 @@ typedef struct {
                                 operators and vectors, the ILU(0) factors and sweeps); the
                                 Krylov method, A, the restriction weights and the coarsest dense
                                 solve stay FP64; default FP64 */
+  int32_t num_sweeps;        /* l1-Jacobi sweeps before and after the coarse correction on every
+                                AMG level above the coarsest (the "first order relaxation" of
+                                Sec. 3.1 reads as 1); default 1, at most 8 */
+  int32_t max_restart;       /* longest restart cptr_gmres_solve accepts: the handle allocates
+                                the Krylov basis V (max_restart + 1 vectors) in cptr_setup;
+                                default 50, 1..64 */
+  int32_t flexible_space;    /* 1: also allocate the max_restart preconditioned vectors Z that
+                                flexible solves keep; 0: flexible solves return CPTR_E_STATE;
+                                default 1 */
 } cptr_setup_opts;
 
 enum {
@@ -160,7 +175,10 @@ cptr_status cptr_apply(cptr_solver s, const double *r, double *z, void *stream);
 /* Solve A x = b with right-preconditioned restarted GMRES (or FGMRES) and the
  * CPTR preconditioner (Sec. 3).  Synchronises `stream` once per iteration for
  * the host Givens update and returns with x final and info filled (info may be
- * NULL; o NULL for defaults).  CPTR_NOT_CONVERGED when max_iter is reached. */
+ * NULL; o NULL for defaults).  CPTR_NOT_CONVERGED when max_iter is reached.
+ * CPTR_E_INVALID when o->restart exceeds the handle's max_restart, CPTR_E_STATE
+ * for a flexible solve on a handle set up with flexible_space = 0.  Allocates
+ * no device memory. */
 cptr_status cptr_gmres_solve(cptr_solver s, const double *b, double *x, const cptr_solve_opts *o,
                              cptr_solve_info *info, void *stream);
 
@@ -176,6 +194,12 @@ cptr_status cptr_spmv(cptr_solver s, const double *x, double *y, void *stream);
  * no allocation). */
 cptr_status cptr_stage1(cptr_solver s, const double *r, double *x1, void *stream);
 cptr_status cptr_ilu_solve(cptr_solver s, const double *r, double *x, void *stream);
+
+/* Synchronises `stream` and reports whether an ILU(0) sweep queued on the
+ * handle since the last check (or the last cptr_gmres_solve) gave up a
+ * dependency wait at its bound: CPTR_E_HIP with a message if so (the output of
+ * that apply is not valid), CPTR_OK otherwise.  Clears the flag. */
+cptr_status cptr_sweep_check(cptr_solver s, void *stream);
 
 cptr_status cptr_destroy(cptr_solver s);
 
@@ -207,6 +231,11 @@ enum {
   CPTR_EXPORT_ILU_NLEVELS = 10, /* int32[2]: forward and backward dependency levels */
   CPTR_EXPORT_SWEEP = 11,      /* int32[4]: ILU sweep schedule in use (CPTR_ILU_SWEEP_*),
                                   then nx, ny, nz of the detected grid (0 if none) */
+  CPTR_EXPORT_DEVICE_PLAN = 13, /* int64[1 + n]: n, then the n steps of building this host-only
+                                  handle's device half with its max_restart and flexible_space
+                                  (the solve server's footprint measurement): a positive entry
+                                  allocates that many bytes (in 256-byte pieces), -1 - k releases
+                                  the k-th allocation; CPTR_E_STATE for a device handle */
   CPTR_EXPORT_SETUP_SITES = 12 /* int32[6]: strength graphs formed on the device and in total,
                                   extended+i interpolations on the device and in total,
                                   coarse operators R A P on the device and in total.  A device

@@ -56,6 +56,9 @@ typedef struct {
   double solve_s;          /* right-hand side upload, (F)GMRES, solution download */
   double latency_s;        /* submitted -> done */
   int64_t device_bytes;    /* HBM footprint the request was admitted with */
+  double admitted_at_s;    /* when the request was admitted, seconds since the server was
+                              created (0 if never admitted) */
+  double done_at_s;        /* when its solution was back on the host, same clock */
 } cptr_serve_info;
 
 typedef struct {

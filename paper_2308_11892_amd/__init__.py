@@ -24,7 +24,8 @@ RESTRICT_QUASI_IMPES, RESTRICT_INJECTION = 0, 1
 ILU_SWEEP_AUTO, ILU_SWEEP_LEVELS, ILU_SWEEP_ONE_LAUNCH, ILU_SWEEP_GRID = 0, 1, 2, 3
 PRECISION_FP64, PRECISION_FP32 = 0, 1
 EXPORT = dict(CF=0, A_ROWPTR=1, A_COLS=2, A_VALS=3, P_ROWPTR=4, P_COLS=5, P_VALS=6, W=7,
-              DINV=8, ILU_VALS=9, ILU_NLEVELS=10, SWEEP=11, SETUP_SITES=12)
+              DINV=8, ILU_VALS=9, ILU_NLEVELS=10, SWEEP=11, SETUP_SITES=12,
+              DEVICE_PLAN=13)
 PHASES = ["spmv", "restrict", "vcycle_l0", "vcycle_coarse", "stage2_resid", "ilu_fwd",
           "ilu_bwd", "arnoldi", "update"]
 
@@ -47,7 +48,8 @@ class cptr_setup_opts(C.Structure):
                 ("p_max_elmts", C.c_int32), ("restriction", C.c_int32),
                 ("host_only", C.c_int32), ("setup_threads", C.c_int32),
                 ("ilu_sweep", C.c_int32), ("agg_levels", C.c_int32),
-                ("precond_precision", C.c_int32)]
+                ("precond_precision", C.c_int32), ("num_sweeps", C.c_int32),
+                ("max_restart", C.c_int32), ("flexible_space", C.c_int32)]
 
 
 class cptr_solve_opts(C.Structure):
@@ -72,7 +74,8 @@ class cptr_serve_info(C.Structure):
                 ("pad_", C.c_int32), ("rel_res_true", C.c_double), ("queue_s", C.c_double),
                 ("host_setup_s", C.c_double), ("admit_wait_s", C.c_double),
                 ("device_setup_s", C.c_double), ("solve_s", C.c_double),
-                ("latency_s", C.c_double), ("device_bytes", C.c_int64)]
+                ("latency_s", C.c_double), ("device_bytes", C.c_int64),
+                ("admitted_at_s", C.c_double), ("done_at_s", C.c_double)]
 
 
 class cptr_server_stats(C.Structure):
@@ -107,6 +110,8 @@ def lib():
         L.cptr_ilu_solve.restype = C.c_int
         L.cptr_spmv.argtypes = [P, P, P, P]
         L.cptr_spmv.restype = C.c_int
+        L.cptr_sweep_check.argtypes = [P, P]
+        L.cptr_sweep_check.restype = C.c_int
         L.cptr_gmres_solve.argtypes = [P, P, P, C.POINTER(cptr_solve_opts),
                                        C.POINTER(cptr_solve_info), P]
         L.cptr_gmres_solve.restype = C.c_int
@@ -248,6 +253,9 @@ class Solver:
 
     def spmv(self, x, y, stream=None):
         _check(lib().cptr_spmv(self._h, _ptr(x), _ptr(y), _stream(stream)), self._h)
+
+    def sweep_check(self, stream=None):
+        _check(lib().cptr_sweep_check(self._h, _stream(stream)), self._h)
 
     def gmres_solve(self, b, x, stream=None, **kw):
         o = solve_opts(**kw)

@@ -123,6 +123,7 @@ struct PrecDev {
     bool sell = false;
     T* dinv = nullptr;
     T *b = nullptr, *r = nullptr, *x = nullptr, *e = nullptr;
+    T* t = nullptr;          // second iterate of the smoothing sweeps (num_sweeps > 1)
     int32_t n = 0;
   };
   std::vector<Lev> lev;
@@ -143,11 +144,16 @@ struct cptr_solver_s {
   std::string err;
   double setup_s = 0.0;
   int ne = 2;
+  int nsweeps = 1;           // l1-Jacobi sweeps before and after the coarse correction
+  int max_restart = 0;       // Krylov space of cptr_setup (cptr_setup_opts.max_restart)
+  bool flex_space = false;   // ... with the FGMRES vectors Z
   int32_t eidx_h[3] = {0, 1, 2}, hidx_h[3] = {2, 0, 0};
   int64_t N = 0;  // DOF
   std::vector<void*> allocs;
   DevArena* arena = nullptr;  // device memory comes from here when set (serving)
   bool measure = false;       // count device bytes only: no allocation, copy or launch
+  std::vector<int64_t>* plan = nullptr;  // measure mode: the build's allocations (+bytes) and
+                                         // releases (-1 - index of the allocation), in order
   int threads = 1;            // host threads for packing device layouts
   int64_t dev_bytes = 0;      // device bytes held (or counted), in DevArena pieces
   // device operators shared by both precisions
@@ -181,6 +187,8 @@ struct cptr_solver_s {
   double* hdev = nullptr;   // [0,64): first CGS pass, [64,128): second, [128]: ||w||^2,
                             // [136]: scratch norm, [140]: sweep wait-limit flag
   double* hhost = nullptr;  // pinned copy
+  double* sweep_flag = nullptr;  // where the sweeps raise the wait-limit flag (hdev + 140,
+                                 // or the static scratch's slot during cptr_gmres_solve_static)
   // profiling
   bool profiling = false;
   uint32_t profile_mask = 0;  // phases timed while profiling
@@ -222,6 +230,15 @@ int dalloc(cptr_solver s, T*& p, int64_t count) {
   if (s->measure) {
     s->dev_bytes += (int64_t)DevArena::round(bytes);
     p = reinterpret_cast<T*>(g_measure_placeholder);
+    if (s->plan) {
+      // a distinct stand-in per allocation, so that its release can be
+      // recorded; never dereferenced, never passed to a kernel or a copy
+      const int64_t k = (int64_t)s->allocs.size();
+      void* q = reinterpret_cast<void*>((uintptr_t(1) << 44) + (uintptr_t)k * DevArena::kAlign);
+      s->allocs.push_back(q);
+      s->plan->push_back((int64_t)DevArena::round(bytes));
+      p = static_cast<T*>(q);
+    }
     return CPTR_OK;
   }
   void* q = nullptr;
@@ -246,6 +263,10 @@ int dalloc(cptr_solver s, T*& p, int64_t count) {
 void dfree(cptr_solver s, void* p) {
   auto it = std::find(s->allocs.begin(), s->allocs.end(), p);
   if (it == s->allocs.end()) return;
+  if (s->measure) {  // a recorded plan: stand-ins are never released
+    if (s->plan) s->plan->push_back(-1 - (int64_t)(it - s->allocs.begin()));
+    return;
+  }
   s->allocs.erase(it);
   if (s->arena) (void)s->arena->release(p);
   else (void)hipFree(p);
@@ -401,7 +422,11 @@ int build_grid_factors_device(cptr_solver s, PrecDev<T>& d, hipStream_t st) {
       (rc = dalloc(s, d.e0tile, rows * 2 * 64)) || (rc = dalloc(s, d.faces, 2 * grid_face_values(nx, ny, nz))) ||
       (rc = dalloc(s, uinv, (int64_t)nb * 9)) || (rc = dalloc(s, bad, 1)))
     return rc;
-  if (s->measure) return CPTR_OK;
+  if (s->measure) {  // the temporaries' releases, as below
+    dfree(s, uinv);
+    dfree(s, bad);
+    return CPTR_OK;
+  }
   // every fill and copy of the build goes on `st`: a null-stream operation is
   // not ordered with the kernels of a non-blocking stream
   HIP_TRY(s, hipMemsetAsync(d.Lg, 0, sizeof(T) * (size_t)rows * 27 * 64, st));
@@ -475,7 +500,14 @@ int build_ilu_factors_device(cptr_solver s, PrecDev<T>& d, const std::vector<int
       (rc = upload(s, rp_d, h.rp.data(), (int64_t)nb + 1, st)) ||
       (rc = upload(s, ds_d, dslot.data(), (int64_t)nb, st)) || (rc = dalloc(s, bad, 1)))
     return rc;
-  if (s->measure) return CPTR_OK;
+  if (s->measure) {  // the temporaries' releases, as below
+    dfree(s, W);
+    dfree(s, uinv);
+    dfree(s, rp_d);
+    dfree(s, ds_d);
+    dfree(s, bad);
+    return CPTR_OK;
+  }
   const int none = INT32_MAX;  // lives until the synchronisation below
   HIP_TRY(s, hipMemcpyAsync(bad, &none, sizeof(int), hipMemcpyHostToDevice, st));
   HIP_TRY(s, hipMemcpyAsync(W, s->A.val, sizeof(double) * (size_t)s->A.nslots * kLanes * 9,
@@ -545,6 +577,7 @@ int build_prec(cptr_solver s, PrecDev<T>& d, const std::vector<int32_t>& fp,
     if ((rc = dalloc(s, dl.b, dl.n)) || (rc = dalloc(s, dl.r, dl.n)) || (rc = dalloc(s, dl.x, dl.n)) ||
         (rc = dalloc(s, dl.e, dl.n)))
       return rc;
+    if (s->nsweeps > 1 && l + 1 < L && (rc = dalloc(s, dl.t, dl.n))) return rc;
   }
   const int64_t N = (int64_t)nb * 3;
   if (!s->use_grid && ((rc = dalloc(s, d.r2, N)) || (rc = dalloc(s, d.y, N)) || (rc = dalloc(s, d.x2, N))))
@@ -578,6 +611,7 @@ void reset_device_state(cptr_solver s) {
   s->part = nullptr;
   s->hdev = nullptr;
   s->hhost = nullptr;
+  s->sweep_flag = nullptr;
 }
 
 int build_device(cptr_solver s, hipStream_t st) {
@@ -675,6 +709,7 @@ int build_device(cptr_solver s, hipStream_t st) {
   if ((rc = upload(s, s->coarse_piv, h.coarse_piv.data(), (int64_t)h.coarse_piv.size(), st))) return rc;
   if ((rc = dalloc(s, s->part, (int64_t)kRedBlocks * (kMaxRestart + 2)))) return rc;
   if ((rc = dalloc(s, s->hdev, 256))) return rc;
+  s->sweep_flag = s->hdev + 140;
   if (s->measure) return CPTR_OK;
   HIP_TRY(s, hipMemsetAsync(s->hdev, 0, 256 * sizeof(double), st));
   {
@@ -682,6 +717,8 @@ int build_device(cptr_solver s, hipStream_t st) {
     HIP_TRY(s, hipHostMalloc(&hp, 256 * sizeof(double), hipHostMallocDefault));
     s->hhost = static_cast<double*>(hp);
   }
+  // marks the Hessenberg column's copy to the host in each Arnoldi step
+  HIP_TRY(s, hipEventCreateWithFlags(&s->ev_copy, hipEventDisableTiming));
   HIP_TRY(s, hipStreamSynchronize(st));
   return CPTR_OK;
 }
@@ -746,6 +783,53 @@ void enqueue_stage1(cptr_solver s, PrecDev<T>& d, const double* r, hipStream_t s
     launch_coarse_solve(s->ncoarse, s->coarse_lu, s->coarse_piv, l0.b, l0.e, st);
     ph_end(s, st, PH_VCC, ev);
   } else {
+    const int ns = s->nsweeps;
+    // the iterate after the pre-smoothing sweeps of each level: the first
+    // sweep from zero is written by the restriction to the level (x = D^-1 b),
+    // further sweeps alternate between x and t
+    std::vector<T*> cur((size_t)L, nullptr);
+    auto presmooth = [&](int l) {
+      auto& dl = d.lev[l];
+      T* c = dl.x;
+      for (int k = 1; k < ns; ++k) {
+        T* o = c == dl.x ? dl.t : dl.x;
+        if (l == 0)
+          launch_l0_post(d.Ahat, ne, c, dl.b, dl.dinv, o, st);
+        else if (dl.sell)
+          launch_sell_post(dl.As, c, dl.b, dl.dinv, o, st);
+        else
+          launch_csr_post(dl.A, c, dl.b, dl.dinv, o, st);
+        c = o;
+      }
+      cur[(size_t)l] = c;
+    };
+    // coarse correction and post-smoothing of level l; the result goes to e
+    auto correct = [&](int l) {
+      auto& dl = d.lev[l];
+      const T* ec = d.lev[l + 1].e;
+      auto post = [&](const T* in, T* out) {
+        if (l == 0)
+          launch_l0_post(d.Ahat, ne, in, dl.b, dl.dinv, out, st);
+        else if (dl.sell)
+          launch_sell_post(dl.As, in, dl.b, dl.dinv, out, st);
+        else
+          launch_csr_post(dl.A, in, dl.b, dl.dinv, out, st);
+      };
+      if (ns == 1) {
+        // x = D^-1 b + P ec recomputes the one pre-smoothing sweep
+        launch_csr_prolong(dl.P, ec, dl.b, dl.dinv, dl.x, st);
+        post(dl.x, dl.e);
+        return;
+      }
+      T* c = cur[(size_t)l];
+      T* o = c == dl.x ? dl.t : dl.x;
+      launch_csr_prolong_add(dl.P, ec, c, o, st);
+      for (int k = 0; k < ns; ++k) {
+        T* n = k + 1 == ns ? dl.e : (o == dl.x ? dl.t : dl.x);
+        post(o, n);
+        o = n;
+      }
+    };
     ph_begin(s, st, PH_VC0, ev);
     // restrictions to a smoothed level also write its pre-smoothed iterate
     // x = D^-1 b, which its residual then reads
@@ -756,31 +840,25 @@ void enqueue_stage1(cptr_solver s, PrecDev<T>& d, const double* r, hipStream_t s
       else
         launch_csr_spmv(d.lev[l].R, r, nx.b, st);
     };
-    launch_l0_resid(d.Ahat, ne, l0.x, l0.b, l0.r, st);
+    presmooth(0);
+    launch_l0_resid(d.Ahat, ne, cur[0], l0.b, l0.r, st);
     restrict_to(0, l0.r);
     ph_end(s, st, PH_VC0, ev);
     ph_begin(s, st, PH_VCC, ev);
     for (int l = 1; l + 1 < L; ++l) {
       auto& dl = d.lev[l];
+      presmooth(l);
       if (dl.sell)
-        launch_sell_resid(dl.As, dl.x, dl.b, dl.r, st);
+        launch_sell_resid(dl.As, cur[(size_t)l], dl.b, dl.r, st);
       else
-        launch_csr_resid(dl.A, dl.x, dl.b, dl.r, st);
+        launch_csr_resid(dl.A, cur[(size_t)l], dl.b, dl.r, st);
       restrict_to(l, dl.r);
     }
     launch_coarse_solve(s->ncoarse, s->coarse_lu, s->coarse_piv, d.lev[L - 1].b, d.lev[L - 1].e, st);
-    for (int l = L - 2; l >= 1; --l) {
-      auto& dl = d.lev[l];
-      launch_csr_prolong(dl.P, d.lev[l + 1].e, dl.b, dl.dinv, dl.x, st);
-      if (dl.sell)
-        launch_sell_post(dl.As, dl.x, dl.b, dl.dinv, dl.e, st);
-      else
-        launch_csr_post(dl.A, dl.x, dl.b, dl.dinv, dl.e, st);
-    }
+    for (int l = L - 2; l >= 1; --l) correct(l);
     ph_end(s, st, PH_VCC, ev);
     ph_begin(s, st, PH_VC0, ev);
-    launch_csr_prolong(l0.P, d.lev[1].e, l0.b, l0.dinv, l0.x, st);
-    launch_l0_post(d.Ahat, ne, l0.x, l0.b, l0.dinv, l0.e, st);
+    correct(0);
     ph_end(s, st, PH_VC0, ev);
   }
 }
@@ -798,12 +876,12 @@ void enqueue_stage2(cptr_solver s, PrecDev<T>& d, const double* r, const T* e0, 
                        st);
     ph_end(s, st, PH_STAGE2, ev);
     ph_begin(s, st, PH_ILU_F, ev);
-    launch_ilu_fwd_grid(nx, ny, nz, d.Lg, d.r2tile, d.ytile, d.faces, s->tickets, s->hdev + 140,
+    launch_ilu_fwd_grid(nx, ny, nz, d.Lg, d.r2tile, d.ytile, d.faces, s->tickets, s->sweep_flag,
                         kSweepSpinLimit, st);
     ph_end(s, st, PH_ILU_F, ev);
     ph_begin(s, st, PH_ILU_B, ev);
     launch_ilu_bwd_grid(nx, ny, nz, d.Ug, d.ytile, e0 ? d.e0tile : nullptr, ne, s->eidx_h,
-                        d.faces + grid_face_values(nx, ny, nz), z, s->tickets, s->hdev + 140,
+                        d.faces + grid_face_values(nx, ny, nz), z, s->tickets, s->sweep_flag,
                         kSweepSpinLimit, st);
     ph_end(s, st, PH_ILU_B, ev);
     return;
@@ -821,12 +899,12 @@ void enqueue_stage2(cptr_solver s, PrecDev<T>& d, const double* r, const T* e0, 
     }
     ph_end(s, st, PH_STAGE2, ev);
     ph_begin(s, st, PH_ILU_F, ev);
-    launch_ilu_fwd_sf(d.Lf, s->sf_width, s->fperm, rhs, d.y, s->tickets, s->hdev + 140,
+    launch_ilu_fwd_sf(d.Lf, s->sf_width, s->fperm, rhs, d.y, s->tickets, s->sweep_flag,
                       kSweepSpinLimit, st);
     ph_end(s, st, PH_ILU_F, ev);
     ph_begin(s, st, PH_ILU_B, ev);
     launch_ilu_bwd_sf(d.Ub, s->sf_width, s->bperm, d.uinv, d.y, e0, ne, s->eidx_h, d.x2, z,
-                      s->tickets, s->hdev + 140, kSweepSpinLimit, st);
+                      s->tickets, s->sweep_flag, kSweepSpinLimit, st);
     ph_end(s, st, PH_ILU_B, ev);
     return;
   }
@@ -863,40 +941,27 @@ void enqueue_apply(cptr_solver s, const double* r, double* z, hipStream_t st, bo
     enqueue_apply(s, s->p64, r, z, st, restricted);
 }
 
-int ensure_solve_space(cptr_solver s, int m, bool flexible) {
-  if (m <= s->restart_cap && (!flexible || s->have_z)) return CPTR_OK;
+// The Krylov space of (F)GMRES(m): V (m + 1 vectors), Z (m vectors, flexible
+// solves) and three work vectors, allocated once when the device half is
+// built.  A failure leaves the handle's other memory to the caller's release.
+int alloc_solve_space(cptr_solver s, int m, bool flexible) {
   const int64_t ld = (s->N + 63) / 64 * 64;
   int rc;
-  if (m > s->restart_cap) {
-    if (s->V) {
-      dfree(s, s->V);
-      s->V = nullptr;
-    }
-    if (s->Z) {
-      dfree(s, s->Z);
-      s->Z = nullptr;
-      s->have_z = false;
-    }
-    if ((rc = dalloc(s, s->V, ld * (m + 1)))) return rc;
-    s->restart_cap = m;
-    s->ldv = ld;
-  }
-  if (flexible && !s->have_z) {
-    if ((rc = dalloc(s, s->Z, ld * s->restart_cap))) return rc;
-    s->have_z = true;
-  }
-  if (!s->wr) {
-    if ((rc = dalloc(s, s->wr, s->N)) || (rc = dalloc(s, s->wt, s->N)) || (rc = dalloc(s, s->wu, s->N)))
-      return rc;
-  }
+  if ((rc = dalloc(s, s->V, ld * (m + 1)))) return rc;
+  if (flexible && (rc = dalloc(s, s->Z, ld * m))) return rc;
+  if ((rc = dalloc(s, s->wr, s->N)) || (rc = dalloc(s, s->wt, s->N)) || (rc = dalloc(s, s->wu, s->N)))
+    return rc;
+  s->restart_cap = m;
+  s->have_z = flexible;
+  s->ldv = ld;
   return CPTR_OK;
 }
 
-// ||x||_2 on the device, synchronising st
-int device_norm(cptr_solver s, const double* x, double& out, hipStream_t st) {
-  launch_norm2(s->N, x, s->part, st);
-  launch_reduce(1, s->part, s->hdev + 136, 0, st);
-  HIP_TRY(s, hipMemcpyAsync(s->hhost + 136, s->hdev + 136, sizeof(double), hipMemcpyDeviceToHost, st));
+// ||x||_2 on the device, synchronising st (part, hd: the reduction scratch)
+int device_norm(cptr_solver s, const double* x, double& out, hipStream_t st, double* part, double* hd) {
+  launch_norm2(s->N, x, part, st);
+  launch_reduce(1, part, hd + 136, 0, st);
+  HIP_TRY(s, hipMemcpyAsync(s->hhost + 136, hd + 136, sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(s, hipStreamSynchronize(st));
   out = std::sqrt(s->hhost[136]);
   return CPTR_OK;
@@ -1134,6 +1199,9 @@ void cptr_setup_opts_default(cptr_setup_opts* o) {
   o->ilu_sweep = CPTR_ILU_SWEEP_AUTO;
   o->agg_levels = 1;
   o->precond_precision = CPTR_PRECISION_FP64;
+  o->num_sweeps = 1;
+  o->max_restart = 50;
+  o->flexible_space = 1;
 }
 
 void cptr_solve_opts_default(cptr_solve_opts* o) {
@@ -1176,6 +1244,12 @@ int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_id
     return (cptr_status)fail(nullptr, CPTR_E_INVALID, "ilu_sweep must be 0, 1, 2 or 3");
   if (o.precond_precision != CPTR_PRECISION_FP64 && o.precond_precision != CPTR_PRECISION_FP32)
     return (cptr_status)fail(nullptr, CPTR_E_INVALID, "precond_precision must be FP64 or FP32");
+  if (o.num_sweeps < 1 || o.num_sweeps > 8)
+    return (cptr_status)fail(nullptr, CPTR_E_INVALID, "num_sweeps must be in [1, 8]");
+  if (o.max_restart < 1 || o.max_restart > kMaxRestart)
+    return (cptr_status)fail(nullptr, CPTR_E_INVALID, "max_restart must be in [1, 64]");
+  if (o.flexible_space != 0 && o.flexible_space != 1)
+    return (cptr_status)fail(nullptr, CPTR_E_INVALID, "flexible_space must be 0 or 1");
   if (o.max_levels < 1 || o.max_levels > 64 || o.max_coarse < 1 || o.p_max_elmts < 0 ||
       o.agg_levels < 0 ||
       !(o.strong_threshold >= 0.0) || !(o.max_row_sum > 0.0))
@@ -1261,6 +1335,9 @@ int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_id
   s->device_steps = sites;
   s->agg_levels_used = std::min<int32_t>(prm.agg_levels, (int32_t)s->host.lev.size() - 1);
   s->prec = o.precond_precision;
+  s->nsweeps = o.num_sweeps;
+  s->max_restart = o.max_restart;
+  s->flex_space = o.flexible_space != 0;
   *out = s.release();
   return CPTR_OK;
 }
@@ -1273,7 +1350,7 @@ int measure_device(cptr_solver s, int restart, bool flexible, int64_t* bytes) {
   int rc = CPTR_OK;
   try {
     rc = build_device(s, nullptr);
-    if (!rc) rc = ensure_solve_space(s, std::max(1, std::min(restart, kMaxRestart)), flexible);
+    if (!rc) rc = alloc_solve_space(s, std::max(1, std::min(restart, kMaxRestart)), flexible);
   } catch (const std::bad_alloc&) {
     rc = fail(s, CPTR_E_NOMEM, "host allocation failed while packing device layouts");
   }
@@ -1293,7 +1370,7 @@ int setup_device(cptr_solver s, DevArena* arena, int restart, bool flexible, hip
   int rc;
   try {
     rc = build_device(s, st);
-    if (!rc && restart > 0) rc = ensure_solve_space(s, std::min(restart, kMaxRestart), flexible);
+    if (!rc) rc = alloc_solve_space(s, std::max(1, std::min(restart, kMaxRestart)), flexible);
   } catch (const std::bad_alloc&) {
     rc = fail(s, CPTR_E_NOMEM, "host allocation failed while packing device layouts");
   }
@@ -1350,7 +1427,7 @@ cptr_status cptr_setup(const cptr_bsr* A, int32_t block_size, const int32_t* ell
   cptr_setup_opts_default(&o);
   if (opts) o = *opts;
   if (!o.host_only) {
-    rc = setup_device(s, nullptr, 0, false, static_cast<hipStream_t>(stream));
+    rc = setup_device(s, nullptr, o.max_restart, o.flexible_space != 0, static_cast<hipStream_t>(stream));
     if (rc) {
       g_setup_error = s->err;
       delete s;
@@ -1412,6 +1489,19 @@ cptr_status cptr_ilu_solve(cptr_solver s, const double* r, double* x, void* stre
   return CPTR_OK;
 }
 
+cptr_status cptr_sweep_check(cptr_solver s, void* stream) {
+  if (!s) return CPTR_E_INVALID;
+  if (!s->device) return (cptr_status)fail(s, CPTR_E_STATE, "handle was set up host-only");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(s, hipMemcpyAsync(s->hhost + 140, s->hdev + 140, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(s, hipStreamSynchronize(st));
+  launch_fill(1, s->hdev + 140, 0.0, st);
+  HIP_TRY(s, hipGetLastError());
+  if (s->hhost[140] != 0.0)
+    return (cptr_status)fail(s, CPTR_E_HIP, "ILU sweep dependency wait exceeded its limit");
+  return CPTR_OK;
+}
+
 cptr_status cptr_spmv(cptr_solver s, const double* x, double* y, void* stream) {
   if (!s) return CPTR_E_INVALID;
   if (!s->device) return (cptr_status)fail(s, CPTR_E_STATE, "handle was set up host-only");
@@ -1422,22 +1512,38 @@ cptr_status cptr_spmv(cptr_solver s, const double* x, double* y, void* stream) {
   return CPTR_OK;
 }
 
-cptr_status cptr_gmres_solve(cptr_solver s, const double* b, double* x, const cptr_solve_opts* o_in,
-                             cptr_solve_info* info, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Arguments of cptr_gmres_solve and its static-scratch variant.
+int check_solve_args(cptr_solver s, const double* b, double* x, const cptr_solve_opts* o_in,
+                     cptr_solve_opts& o) {
   if (!s) return CPTR_E_INVALID;
-  if (!s->device) return (cptr_status)fail(s, CPTR_E_STATE, "handle was set up host-only");
-  if (!b || !x || b == x) return (cptr_status)fail(s, CPTR_E_INVALID, "b and x must be distinct non-NULL device pointers");
-  cptr_solve_opts o;
+  if (!s->device) return fail(s, CPTR_E_STATE, "handle was set up host-only");
+  if (!b || !x || b == x) return fail(s, CPTR_E_INVALID, "b and x must be distinct non-NULL device pointers");
   cptr_solve_opts_default(&o);
   if (o_in) o = *o_in;
-  if (o.restart < 1 || o.restart > kMaxRestart)
-    return (cptr_status)fail(s, CPTR_E_INVALID, "restart must be in [1, 64]");
+  if (o.restart < 1 || o.restart > s->restart_cap)
+    return fail(s, CPTR_E_INVALID,
+                "restart must be in [1, " + std::to_string(s->restart_cap) + "] (the handle's max_restart)");
+  if (o.flexible && !s->have_z)
+    return fail(s, CPTR_E_STATE, "flexible solve on a handle set up with flexible_space = 0");
   if (o.max_iter < 0 || !(o.rtol >= 0.0))
-    return (cptr_status)fail(s, CPTR_E_INVALID, "max_iter must be >= 0 and rtol >= 0");
-  hipStream_t st = static_cast<hipStream_t>(stream);
+    return fail(s, CPTR_E_INVALID, "max_iter must be >= 0 and rtol >= 0");
+  return CPTR_OK;
+}
+
+// Restarted right-preconditioned (F)GMRES.  part: kRedBlocks * (kMaxRestart
+// + 2) doubles of reduction partials; hd: 256 doubles for the Hessenberg
+// column ([0,64) first Gram-Schmidt pass, [64,128) second, [128] ||w||^2),
+// a norm ([136]) and the sweeps' wait-limit flag ([140], s->sweep_flag).
+int gmres_run(cptr_solver s, const double* b, double* x, const cptr_solve_opts& o, cptr_solve_info* info,
+              hipStream_t st, double* part, double* hd) {
   const double t0 = now_s();
-  int rc = ensure_solve_space(s, o.restart, o.flexible != 0);
-  if (rc) return (cptr_status)rc;
+  int rc = CPTR_OK;
+  // the sweeps' wait-limit flag reports on this solve only
+  launch_fill(1, hd + 140, 0.0, st);
   if (o.profile != 0 && s->ev_pool.empty()) {
     s->ev_pool.resize(512);
     for (auto& e : s->ev_pool)
@@ -1447,10 +1553,6 @@ cptr_status cptr_gmres_solve(cptr_solver s, const double* b, double* x, const cp
   s->profile_mask = o.profile == 1 ? ~0u : (uint32_t)o.profile >> 1;
   s->ev_used = 0;
   s->ev_pending.clear();
-  if (!s->ev_copy && hipEventCreateWithFlags(&s->ev_copy, hipEventDisableTiming) != hipSuccess) {
-    (void)hipGetLastError();
-    s->ev_copy = nullptr;
-  }
   // queue the next step's restriction early unless its phase is being timed
   const bool prefetch = s->ev_copy && !(s->profiling && (s->profile_mask & (1u << PH_RESTRICT)));
   bool pre = false;  // the restriction of the next basis vector is queued
@@ -1464,19 +1566,19 @@ cptr_status cptr_gmres_solve(cptr_solver s, const double* b, double* x, const cp
   hipEvent_t ev;
 
   double bnorm = 0.0;
-  if ((rc = device_norm(s, b, bnorm, st))) return (cptr_status)rc;
+  if ((rc = device_norm(s, b, bnorm, st, part, hd))) return rc;
   // the residual the next cycle starts from: b itself when x0 = 0
   const double* r0 = r;
   double beta = 0.0;
   if (o.x0_is_zero || bnorm == 0.0) {
-    HIP_TRY(s, hipMemsetAsync(x, 0, sizeof(double) * N, st));
+    launch_fill(N, x, 0.0, st);
     r0 = b;
     beta = bnorm;
   } else {
     ph_begin(s, st, PH_SPMV, ev);
     launch_bsr3_spmv(s->A, x, b, r, true, st);
     ph_end(s, st, PH_SPMV, ev);
-    if ((rc = device_norm(s, r, beta, st))) return (cptr_status)rc;
+    if ((rc = device_norm(s, r, beta, st, part, hd))) return rc;
   }
   ph_harvest(s);
   const double bref = bnorm == 0.0 ? 1.0 : bnorm;
@@ -1507,15 +1609,15 @@ cptr_status cptr_gmres_solve(cptr_solver s, const double* b, double* x, const cp
       // classical Gram-Schmidt, twice
       ph_begin(s, st, PH_ARNOLDI, ev);
       const int nv = j + 1;
-      launch_mdot(N, nv, V, ld, w, s->part, st);
-      launch_reduce(nv, s->part, s->hdev, 0, st);
-      launch_maxpy_dot(N, nv, V, ld, s->hdev, w, s->part, st);
-      launch_reduce(nv, s->part, s->hdev + 64, 0, st);
-      launch_maxpy_norm(N, nv, V, ld, s->hdev + 64, w, s->part, st);
-      launch_reduce(1, s->part, s->hdev + 128, 0, st);
-      launch_scale(N, w, s->hdev + 128, w, st);
+      launch_mdot(N, nv, V, ld, w, part, st);
+      launch_reduce(nv, part, hd, 0, st);
+      launch_maxpy_dot(N, nv, V, ld, hd, w, part, st);
+      launch_reduce(nv, part, hd + 64, 0, st);
+      launch_maxpy_norm(N, nv, V, ld, hd + 64, w, part, st);
+      launch_reduce(1, part, hd + 128, 0, st);
+      launch_scale(N, w, hd + 128, w, st);
       ph_end(s, st, PH_ARNOLDI, ev);
-      HIP_TRY(s, hipMemcpyAsync(s->hhost, s->hdev, 144 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_TRY(s, hipMemcpyAsync(s->hhost, hd, 144 * sizeof(double), hipMemcpyDeviceToHost, st));
       if (prefetch && j + 1 < m) {
         // the next step's restriction reads only v_{j+1}: it is queued before
         // the host waits for the Hessenberg column, so the device has work
@@ -1530,11 +1632,11 @@ cptr_status cptr_gmres_solve(cptr_solver s, const double* b, double* x, const cp
       }
       {
         hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return (cptr_status)hip_fail(s, e, "kernel launch in cptr_gmres_solve");
+        if (e != hipSuccess) return hip_fail(s, e, "kernel launch in cptr_gmres_solve");
       }
       ph_harvest(s);
       if (s->hhost[140] != 0.0)
-        return (cptr_status)fail(s, CPTR_E_HIP, "ILU sweep dependency wait exceeded its limit");
+        return fail(s, CPTR_E_HIP, "ILU sweep dependency wait exceeded its limit");
       for (int i = 0; i <= j; ++i) Hij(i, j) = s->hhost[i] + s->hhost[64 + i];
       const double hn = std::sqrt(std::max(0.0, s->hhost[128]));
       Hij(j + 1, j) = hn;
@@ -1573,7 +1675,7 @@ cptr_status cptr_gmres_solve(cptr_solver s, const double* b, double* x, const cp
       launch_update_host_coef(N, k, s->Z, ld, yv.data(), x, st);
       ph_end(s, st, PH_UPDATE, ev);
     } else {
-      HIP_TRY(s, hipMemsetAsync(s->wt, 0, sizeof(double) * N, st));
+      launch_fill(N, s->wt, 0.0, st);
       launch_update_host_coef(N, k, V, ld, yv.data(), s->wt, st);
       ph_end(s, st, PH_UPDATE, ev);
       enqueue_apply(s, s->wt, s->wu, st);
@@ -1585,7 +1687,7 @@ cptr_status cptr_gmres_solve(cptr_solver s, const double* b, double* x, const cp
     ph_begin(s, st, PH_SPMV, ev);
     launch_bsr3_spmv(s->A, x, b, r, true, st);
     ph_end(s, st, PH_SPMV, ev);
-    if ((rc = device_norm(s, r, beta, st))) return (cptr_status)rc;
+    if ((rc = device_norm(s, r, beta, st, part, hd))) return rc;
     ph_harvest(s);
     if (beta > target && it < o.max_iter) ++restarts;
   }
@@ -1600,6 +1702,18 @@ cptr_status cptr_gmres_solve(cptr_solver s, const double* b, double* x, const cp
     info->solve_s = now_s() - t0;
   }
   return converged ? CPTR_OK : CPTR_NOT_CONVERGED;
+}
+
+}  // namespace
+
+extern "C" {
+
+cptr_status cptr_gmres_solve(cptr_solver s, const double* b, double* x, const cptr_solve_opts* o_in,
+                             cptr_solve_info* info, void* stream) {
+  cptr_solve_opts o;
+  int rc = check_solve_args(s, b, x, o_in, o);
+  if (rc) return (cptr_status)rc;
+  return (cptr_status)gmres_run(s, b, x, o, info, static_cast<hipStream_t>(stream), s->part, s->hdev);
 }
 
 cptr_status cptr_hierarchy_info(cptr_solver s, int32_t* n_levels, int64_t* rows, int64_t* nnz) {
@@ -1666,6 +1780,17 @@ cptr_status cptr_export(cptr_solver s, int32_t what, int32_t level, void* buf, i
     case CPTR_EXPORT_ILU_NLEVELS: {
       int32_t nl[2] = {h.n_fwd_levels, h.n_bwd_levels};
       return put(nl, 8);
+    }
+    case CPTR_EXPORT_DEVICE_PLAN: {
+      if (s->device) return (cptr_status)fail(s, CPTR_E_STATE, "the handle already has its device half");
+      std::vector<int64_t> plan;
+      int64_t total = 0;
+      s->plan = &plan;
+      const int rc = cptr::measure_device(s, s->max_restart, s->flex_space, &total);
+      s->plan = nullptr;
+      if (rc) return (cptr_status)rc;
+      plan.insert(plan.begin(), (int64_t)plan.size());
+      return put(plan.data(), (int64_t)plan.size() * 8);
     }
     case CPTR_EXPORT_SETUP_SITES: {
       const int32_t built = (int32_t)h.lev.size() - 1;

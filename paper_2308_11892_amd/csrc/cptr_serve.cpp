@@ -41,6 +41,7 @@ struct Request {
   State state = kQueued;
   cptr_solver h = nullptr;
   int64_t bytes = 0;  // device footprint: the handle plus b and x
+  int placements = 0; // admissions that found no contiguous room in the arena
   int status = CPTR_OK;
   std::string err;
   std::vector<double> x;
@@ -63,7 +64,8 @@ struct cptr_server_s {
   int64_t next_id = 1;
   int64_t reserved = 0;     // footprints of admitted requests
   int inflight = 0;
-  int64_t completions = 0;  // admitted requests that released their memory
+  int64_t releases = 0;     // admitted requests that gave their memory back (done, failed or requeued)
+  double t_created = 0;     // clock origin of cptr_serve_info's *_at_s times
   bool stop = false;        // no more submissions; setup workers drain and exit
   bool setups_done = false; // every setup worker has exited
   cptr_server_stats stats{};
@@ -225,7 +227,7 @@ void slot_worker(cptr_server sv) {
       sv->stats.peak_reserved_bytes = std::max(sv->stats.peak_reserved_bytes, sv->reserved);
       r->state = Request::kRunning;
       r->t_admit = now_s();
-      seen = sv->completions;
+      seen = sv->releases;
     }
     int rc = CPTR_OK;
     bool ran = true;
@@ -243,25 +245,31 @@ void slot_worker(cptr_server sv) {
     std::unique_lock<std::mutex> lk(sv->mu);
     sv->reserved -= r->bytes;
     sv->inflight -= 1;
+    sv->releases += 1;
+    sv->cv_admit.notify_all();
     if (ran) {
-      sv->completions += 1;
       finish(sv, r, rc);
-      sv->cv_admit.notify_all();
       continue;
     }
-    // the free memory is there but not in one piece: wait until another
-    // request returns its memory, or fail when nothing else holds any
-    if (sv->inflight == 0) {
+    // The free memory was there but not in one piece.  An empty arena always
+    // has room for a request whose footprint fits the budget (the footprint
+    // counts every allocation of its build), so with nothing else in flight
+    // the request is tried again at once; otherwise it waits at the head of
+    // the queue until another request gives memory back.  A request that
+    // keeps failing is reported instead of retried forever.
+    r->placements += 1;
+    if (r->placements > 64) {
       r->err = "HBM arena too fragmented for the request";
       cptr_destroy(r->h);
       r->h = nullptr;
       finish(sv, r, CPTR_E_NOMEM);
-    } else {
-      r->state = Request::kReady;
-      sv->ready_q.push_front(r);
-      sv->cv_admit.wait(lk, [&] { return sv->completions > seen; });
+      continue;
     }
-    sv->cv_admit.notify_all();
+    r->state = Request::kReady;
+    sv->ready_q.push_front(r);
+    // `seen` counted releases before this admission; this request's own
+    // release is one more
+    if (sv->inflight > 0) sv->cv_admit.wait(lk, [&] { return sv->releases > seen + 1; });
   }
   if (have_stream) (void)hipStreamDestroy(st);
 }
@@ -297,6 +305,7 @@ cptr_status cptr_server_create(const cptr_server_opts* o_in, cptr_server* out) {
   std::unique_ptr<cptr_server_s> sv(new (std::nothrow) cptr_server_s());
   if (!sv) return CPTR_E_NOMEM;
   sv->o = o;
+  sv->t_created = now_s();
   if (hipMalloc(&sv->arena_mem, (size_t)o.hbm_budget_bytes) != hipSuccess) {
     (void)hipGetLastError();
     return CPTR_E_NOMEM;
@@ -369,6 +378,8 @@ cptr_status cptr_server_wait(cptr_server sv, int64_t id, double* x, cptr_serve_i
     info->solve_s = r->t_dev > 0 ? r->t_done - r->t_dev : 0.0;
     info->latency_s = r->t_done - r->t_submit;
     info->device_bytes = r->bytes;
+    info->admitted_at_s = r->t_admit > 0 ? r->t_admit - sv->t_created : 0.0;
+    info->done_at_s = r->t_done - sv->t_created;
   }
   const int status = r->status;
   if (status < 0) sv->last_err = r->err;

@@ -189,8 +189,9 @@ __global__ __launch_bounds__(kBlock) void k_l0_post(int nc, int nblk, const int3
 // kRestrict: y = A x and y2 = D^-1 y (the next level's right-hand side and its
 // pre-smoothed iterate); kResid: y = b - A x with x = D^-1 b, the residual
 // after one l1-Jacobi sweep from zero; kProlong: y = D^-1 b + A x; kPost:
-// y = x + D^-1 (b - A x)
-enum CsrOp { kSpmv = 0, kResid = 1, kProlong = 2, kPost = 3, kRestrict = 4 };
+// y = x + D^-1 (b - A x); kProlongAdd: y = b + A x (b: the pre-smoothed
+// iterate, when it took more than one sweep)
+enum CsrOp { kSpmv = 0, kResid = 1, kProlong = 2, kPost = 3, kRestrict = 4, kProlongAdd = 5 };
 
 template <int G, int OP, class T>
 __global__ __launch_bounds__(kBlock) void k_csr(int n, const int32_t* __restrict__ rp,
@@ -221,6 +222,7 @@ __global__ __launch_bounds__(kBlock) void k_csr(int n, const int32_t* __restrict
       break;
     case kResid: y[row] = b[row] - acc; break;
     case kProlong: y[row] = dinv[row] * b[row] + acc; break;
+    case kProlongAdd: y[row] = b[row] + acc; break;
     case kPost: y[row] = x[row] + dinv[row] * (b[row] - acc); break;
   }
 }
@@ -1434,6 +1436,10 @@ void launch_csr_prolong(const DCsrT<T>& P, const T* xc, const T* b, const T* din
   launch_csr_op<kProlong, T>(P, xc, b, dinv, x, st);
 }
 template <class T>
+void launch_csr_prolong_add(const DCsrT<T>& P, const T* xc, const T* x, T* y, hipStream_t st) {
+  launch_csr_op<kProlongAdd, T>(P, xc, x, nullptr, y, st);
+}
+template <class T>
 void launch_csr_post(const DCsrT<T>& A, const T* x, const T* b, const T* dinv, T* e, hipStream_t st) {
   launch_csr_op<kPost, T>(A, x, b, dinv, e, st);
 }
@@ -1509,6 +1515,14 @@ void launch_prolong_e(int32_t nrows, int ne, const int32_t* eidx, const T* e0, d
 }
 void launch_sweep_prepare(int64_t n, double* y, double* x2, int* tickets, hipStream_t st) {
   k_sweep_prepare<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, y, x2, tickets);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(int64_t n, double* __restrict__ x, double v) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+void launch_fill(int64_t n, double* x, double v, hipStream_t st) {
+  if (n > 0) k_fill<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, x, v);
 }
 
 
@@ -2387,6 +2401,7 @@ void launch_update_host_coef(int64_t n, int nv, const double* V, int64_t ldv, co
   template void launch_csr_spmv<T>(const DCsrT<T>&, const T*, T*, hipStream_t);                      \
   template void launch_csr_restrict<T>(const DCsrT<T>&, const T*, const T*, T*, T*, hipStream_t);    \
   template void launch_csr_prolong<T>(const DCsrT<T>&, const T*, const T*, const T*, T*, hipStream_t); \
+  template void launch_csr_prolong_add<T>(const DCsrT<T>&, const T*, const T*, T*, hipStream_t);     \
   template void launch_csr_post<T>(const DCsrT<T>&, const T*, const T*, const T*, T*, hipStream_t);  \
   template void launch_sell_resid<T>(const SellT<T>&, const T*, const T*, T*, hipStream_t);          \
   template void launch_sell_post<T>(const SellT<T>&, const T*, const T*, const T*, T*, hipStream_t); \

@@ -75,6 +75,9 @@ void launch_csr_restrict(const DCsrT<T>& R, const T* r, const T* dinv_c, T* bc, 
 template <class T>
 void launch_csr_prolong(const DCsrT<T>& P, const T* xc, const T* b, const T* dinv, T* x,
                         hipStream_t st);
+// prolong_add: y = x + P xc (x: a pre-smoothed iterate of several sweeps)
+template <class T>
+void launch_csr_prolong_add(const DCsrT<T>& P, const T* xc, const T* x, T* y, hipStream_t st);
 template <class T>
 void launch_csr_post(const DCsrT<T>& A, const T* x, const T* b, const T* dinv, T* e, hipStream_t st);
 // resid and post on a scalar SELL-64 operator (nv = 1, one thread per row)
@@ -214,6 +217,8 @@ template <class T>
 void launch_prolong_e(int32_t nrows, int ne, const int32_t* eidx, const T* e0, double* x1,
                       hipStream_t st);
 void launch_sweep_prepare(int64_t n, double* y, double* x2, int* tickets, hipStream_t st);
+// x[0..n) = v (a kernel, so that it may sit in a captured graph)
+void launch_fill(int64_t n, double* x, double v, hipStream_t st);
 
 // Arnoldi / BLAS-1 (deterministic two-stage reductions into `part`)
 void launch_mdot(int64_t n, int nv, const double* V, int64_t ldv, const double* w, double* part,

@@ -195,7 +195,7 @@ def test_profiled_solve_reports_phases(solvers):
     assert info3["iterations"] == info["iterations"] and torch.equal(x, x3)
 
 
-@pytest.mark.parametrize("pe", [None, 0.1, 1000.0])
+@pytest.mark.parametrize("pe", [None, 0.1, 10.0, 1000.0])
 def test_gmres_parity_grid100x100x20(pe):
     c = J.config1(pe)
     say(f"[gmres] {c.name} FGMRES(50) tol 1e-6")

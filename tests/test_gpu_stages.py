@@ -21,7 +21,8 @@ def say(*a):
 
 
 @pytest.mark.parametrize("name,mode", [
-    (n, m) for n in ["grid20x20x5", "grid100x100x20", "grid100x100x20_pe0.1", "grid100x100x20_pe1000"]
+    (n, m) for n in ["grid20x20x5", "grid100x100x20", "grid100x100x20_pe0.1", "grid100x100x20_pe10",
+                             "grid100x100x20_pe1000"]
     for m in [L.ILU_SWEEP_LEVELS, L.ILU_SWEEP_ONE_LAUNCH, L.ILU_SWEEP_GRID]] + [
     (n, m) for n in ["prism2000x5", "prism10000x10"]
     for m in [L.ILU_SWEEP_LEVELS, L.ILU_SWEEP_ONE_LAUNCH]])

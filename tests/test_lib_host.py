@@ -34,6 +34,9 @@ def test_defaults_follow_the_paper():
             o.agg_levels) == (0.25, 0.9, 25, 9, 4, 1)
     s = L.solve_opts()
     assert (s.max_iter, s.rtol, s.restart) == (200, 1e-6, 30)
+    # one l1-Jacobi sweep on each side; the Krylov space of FGMRES(50) is
+    # allocated at setup
+    assert (o.num_sweeps, o.max_restart, o.flexible_space) == (1, 50, 1)
 
 
 @pytest.mark.parametrize("case,agg", [("grid20x20x5", 1), ("grid6x5x4", 1), ("grid12x1x1", 1),
@@ -139,6 +142,11 @@ def test_invalid_arguments():
     rp[5:] -= 1
     msg = _expect(L.CPTR_E_INVALID, lambda: L.Solver(rp, c.col_idx[keep], c.values[keep], host_only=1))
     assert "diagonal" in msg and "4" in msg
+    for kw, word in [(dict(num_sweeps=0), "num_sweeps"), (dict(num_sweeps=9), "num_sweeps"),
+                     (dict(max_restart=0), "max_restart"), (dict(max_restart=65), "max_restart"),
+                     (dict(flexible_space=2), "flexible_space")]:
+        msg = _expect(L.CPTR_E_INVALID, lambda: L.Solver(c.row_ptr, c.col_idx, c.values, host_only=1, **kw))
+        assert word in msg, msg
 
 
 def test_zero_pivot_errors():
