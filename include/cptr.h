@@ -182,6 +182,26 @@ cptr_status cptr_apply(cptr_solver s, const double *r, double *z, void *stream);
 cptr_status cptr_gmres_solve(cptr_solver s, const double *b, double *x, const cptr_solve_opts *o,
                              cptr_solve_info *info, void *stream);
 
+/* cptr_gmres_solve for callers that cannot allocate device memory or must
+ * not touch the handle's own workspace beyond the Krylov space (serving loops
+ * running many resident handles, harnesses that forbid allocation).  Same
+ * arguments, result and errors as cptr_gmres_solve, bit for bit; the
+ * reduction partials of the Gram-Schmidt passes and norms and the
+ * Hessenberg/flag slots live in a static device array of the library
+ * (kept by each GPU the library runs on until the process ends; 1024 * 66 +
+ * 256 doubles, about 530 KiB) instead of the handle's.  The first call on a
+ * device looks up that device's address of the array; no call allocates or
+ * frees device memory.
+ *   - Every call on one GPU shares that GPU's array: calls that overlap in
+ *     time on one GPU (other threads, other streams) race and must not be
+ *     made.  The array keeps the last call's contents; each call clears what
+ *     must start at zero (the sweeps' wait-limit flag).
+ *   - CPTR_E_INVALID when o->restart needs more partials than the array holds
+ *     (restart + 2 columns of 1024; every restart the handle accepts fits) or
+ *     when o->profile != 0 (this variant does not time phases). */
+cptr_status cptr_gmres_solve_static(cptr_solver s, const double *b, double *x, const cptr_solve_opts *o,
+                                    cptr_solve_info *info, void *stream);
+
 /* y = A x with the block SpMV kernel of the solve (Eq. 3 uses A in the
  * stage-two residual and GMRES applies it once per iteration). */
 cptr_status cptr_spmv(cptr_solver s, const double *x, double *y, void *stream);

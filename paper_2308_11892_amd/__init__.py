@@ -115,6 +115,9 @@ def lib():
         L.cptr_gmres_solve.argtypes = [P, P, P, C.POINTER(cptr_solve_opts),
                                        C.POINTER(cptr_solve_info), P]
         L.cptr_gmres_solve.restype = C.c_int
+        L.cptr_gmres_solve_static.argtypes = [P, P, P, C.POINTER(cptr_solve_opts),
+                                              C.POINTER(cptr_solve_info), P]
+        L.cptr_gmres_solve_static.restype = C.c_int
         L.cptr_destroy.argtypes = [P]
         L.cptr_destroy.restype = C.c_int
         L.cptr_last_error.argtypes = [P]
@@ -257,11 +260,12 @@ class Solver:
     def sweep_check(self, stream=None):
         _check(lib().cptr_sweep_check(self._h, _stream(stream)), self._h)
 
-    def gmres_solve(self, b, x, stream=None, **kw):
+    def gmres_solve(self, b, x, stream=None, static_scratch=False, **kw):
+        """cptr_gmres_solve, or cptr_gmres_solve_static with static_scratch."""
         o = solve_opts(**kw)
         info = cptr_solve_info()
-        code = _check(lib().cptr_gmres_solve(self._h, _ptr(b), _ptr(x), C.byref(o), C.byref(info),
-                                             _stream(stream)), self._h)
+        fn = lib().cptr_gmres_solve_static if static_scratch else lib().cptr_gmres_solve
+        code = _check(fn(self._h, _ptr(b), _ptr(x), C.byref(o), C.byref(info), _stream(stream)), self._h)
         return dict(status=code, converged=bool(info.converged), iterations=info.iterations,
                     restarts=info.restarts, rel_res_est=info.rel_res_est,
                     rel_res_true=info.rel_res_true, setup_s=info.setup_s, solve_s=info.solve_s)

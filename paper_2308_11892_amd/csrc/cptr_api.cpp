@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <type_traits>
@@ -1704,6 +1705,40 @@ int gmres_run(cptr_solver s, const double* b, double* x, const cptr_solve_opts& 
   return converged ? CPTR_OK : CPTR_NOT_CONVERGED;
 }
 
+// Scratch of cptr_gmres_solve_static: the reduction partials and the
+// Hessenberg / norm / flag slots, in one static device array per GPU instead
+// of the handle's own.  Every call on a GPU shares that GPU's copy.
+constexpr int64_t kStaticPartDoubles = (int64_t)kRedBlocks * (kMaxRestart + 2);
+constexpr int64_t kStaticScratchDoubles = kStaticPartDoubles + 256;
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};  // device address of `scratch`, per device
+
+// The current device's address of `scratch`, looked up once per device (with
+// that device current) on the first call there.  The host-side name of the
+// array is not a device address and is never passed to a kernel or a copy.
+int static_scratch(cptr_solver s, double*& out) {
+  out = nullptr;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(s, e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(s, CPTR_E_HIP, "device ordinal out of range for the static scratch");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(s, CPTR_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  out = g_scratch_ptr[dev];
+  return CPTR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1714,6 +1749,25 @@ cptr_status cptr_gmres_solve(cptr_solver s, const double* b, double* x, const cp
   int rc = check_solve_args(s, b, x, o_in, o);
   if (rc) return (cptr_status)rc;
   return (cptr_status)gmres_run(s, b, x, o, info, static_cast<hipStream_t>(stream), s->part, s->hdev);
+}
+
+cptr_status cptr_gmres_solve_static(cptr_solver s, const double* b, double* x, const cptr_solve_opts* o_in,
+                                    cptr_solve_info* info, void* stream) {
+  cptr_solve_opts o;
+  int rc = check_solve_args(s, b, x, o_in, o);
+  if (rc) return (cptr_status)rc;
+  if ((int64_t)kRedBlocks * (o.restart + 2) > kStaticPartDoubles)
+    return (cptr_status)fail(s, CPTR_E_INVALID, "restart " + std::to_string(o.restart) +
+                                                    " needs more reduction scratch than the static array holds");
+  if (o.profile != 0)
+    return (cptr_status)fail(s, CPTR_E_INVALID, "cptr_gmres_solve_static does not profile (profile must be 0)");
+  double* sc = nullptr;
+  if ((rc = static_scratch(s, sc))) return (cptr_status)rc;
+  double* hd = sc + kStaticPartDoubles;
+  s->sweep_flag = hd + 140;
+  rc = gmres_run(s, b, x, o, info, static_cast<hipStream_t>(stream), sc, hd);
+  s->sweep_flag = s->hdev + 140;
+  return (cptr_status)rc;
 }
 
 cptr_status cptr_hierarchy_info(cptr_solver s, int32_t* n_levels, int64_t* rows, int64_t* nnz) {
