@@ -2284,8 +2284,20 @@ void launch_grid_ilu_pack(const Sell& A, int nx, int ny, const double* uinv, T* 
 // 4 backward slots beat the 8 and 6 that fit in LDS (the sweeps took 0.347
 // and 0.510 ms against 0.356 and 0.537); with fewer slots the staging waves
 // wait more and compete less with the sweeping wave for LDS.
-constexpr int kGridStagersFwd = 5, kGridStagersBwd = 3;
-constexpr int kGridSlotsFwd = 6, kGridSlotsBwd = 4;
+#ifndef CPTR_GRID_STAGERS_FWD
+#define CPTR_GRID_STAGERS_FWD 5
+#endif
+#ifndef CPTR_GRID_STAGERS_BWD
+#define CPTR_GRID_STAGERS_BWD 3
+#endif
+#ifndef CPTR_GRID_SLOTS_FWD
+#define CPTR_GRID_SLOTS_FWD 6
+#endif
+#ifndef CPTR_GRID_SLOTS_BWD
+#define CPTR_GRID_SLOTS_BWD 4
+#endif
+constexpr int kGridStagersFwd = CPTR_GRID_STAGERS_FWD, kGridStagersBwd = CPTR_GRID_STAGERS_BWD;
+constexpr int kGridSlotsFwd = CPTR_GRID_SLOTS_FWD, kGridSlotsBwd = CPTR_GRID_SLOTS_BWD;
 
 template <class T>
 void launch_ilu_fwd_grid(int nx, int ny, int nz, const T* Lt, const T* r2t, T* ytile, T* faces,
