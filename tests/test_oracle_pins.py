@@ -369,15 +369,18 @@ def _vcycle_factor(m, agg=0):
 @pytest.mark.parametrize("agg,bound", [(0, 0.5), (1, 0.75)])
 def test_amg_decoupled_two_equation_poisson_h_independent(agg, bound):
     """Stationary V-cycle iteration on two decoupled 3D Poisson problems
-    (functions interleaved): the asymptotic convergence factor stays bounded
-    and does not grow with refinement (h-independence).  Aggressive coarsening
-    of the first level trades convergence for a much smaller second level
-    (measured 0.41 without, 0.68 with)."""
-    f16, L16 = _vcycle_factor(16, agg)
-    f24, L24 = _vcycle_factor(24, agg)
-    assert f16 < bound and f24 < bound, (f16, f24)
-    assert f24 < f16 + 0.08
-    assert L24 >= L16
+    (functions interleaved) at 16^3, 32^3 and 64^3 (up to 524k unknowns): the
+    asymptotic convergence factor stays bounded and does not grow with
+    refinement (h-independence).  Aggressive coarsening of the first level
+    trades convergence for a much smaller second level (measured 0.41, 0.42,
+    0.43 without and 0.68, 0.68, 0.69 with)."""
+    f = {}
+    nl = {}
+    for m in (16, 32, 64):
+        f[m], nl[m] = _vcycle_factor(m, agg)
+    assert all(v < bound for v in f.values()), f
+    assert f[64] < f[16] + 0.05 and f[32] < f[16] + 0.05, f
+    assert nl[16] <= nl[32] <= nl[64]
 
 
 # ----------------------------------------------------------------- aggressive level
