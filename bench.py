@@ -85,23 +85,67 @@ def pmc_traffic(kernel):
     return table["bytes_per_launch"].get(kernel)
 
 
-def run_cpu_baseline(c, restart):
-    """The oracle on the same system (single thread): its FGMRES solve is the
-    bounded sample, about 10 s of CPU work; setup is timed separately."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _copy_bandwidth_gbs(mib=1024, reps=5):
+    """Attainable host memory bandwidth: the median of `reps` single-thread
+    numpy copies of `mib` MiB (read + write bytes per second)."""
+    import numpy as np
+    a = np.ones(mib * (1 << 20) // 8)
+    b = np.empty_like(a)
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        np.copyto(b, a)
+        ts.append(time.perf_counter() - t0)
+    return 2 * a.nbytes / float(np.median(ts)) / 1e9
+
+
+def run_cpu_baseline(c, restart, reps=5):
+    """The oracle as it stands (plain sequential C, one thread) on the same
+    system: the median of `reps` FGMRES solves after one untimed warm-up is
+    the value; its SpMV, one preconditioner application and the ILU(0)
+    solve are timed beside (median of 5 each).  Setup is timed once, apart."""
+    import numpy as np
     import oracle as O
     t0 = time.perf_counter()
     h = O.Cptr(c.row_ptr, c.col_idx, c.values)
     t_setup = time.perf_counter() - t0
-    t0 = time.perf_counter()
     xo, info = h.gmres(c.b, restart=restart, flexible=True, rtol=c.tol)
-    t_solve = time.perf_counter() - t0
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        xo, info = h.gmres(c.b, restart=restart, flexible=True, rtol=c.tol)
+        ts.append(time.perf_counter() - t0)
+    t_solve = float(np.median(ts))
+    r = np.random.default_rng(5).standard_normal(c.n_dof)
+    kern = {}
+    for name, fn in (("spmv", h.spmv), ("apply", h.apply), ("ilu_fwd_bwd", h.ilu_solve),
+                     ("stage1", h.stage1)):
+        kt = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            fn(r)
+            kt.append(time.perf_counter() - t0)
+        kern[name] = round(float(np.median(kt)) * 1e3, 3)
     v = c.n_dof * info["iterations"] / t_solve
     return dict(value=v, unit="DOF-iter/s", cores=1, kind="oracle",
-                sample=(f"one oracle FGMRES({restart}) solve to {c.tol:g} of the same "
-                        f"{c.name} system ({c.n_dof} DOF), single thread: "
-                        f"{info['iterations']} iterations in {t_solve:.2f} s; oracle setup "
-                        f"{t_setup:.2f} s not in value"),
-                iterations=info["iterations"], solve_s=t_solve, setup_s=t_setup, x=xo)
+                sample=(f"median of {reps} oracle FGMRES({restart}) solves to {c.tol:g} of the same "
+                        f"{c.name} system ({c.n_dof} DOF) after one warm-up, one thread: "
+                        f"{info['iterations']} iterations in {t_solve:.2f} s (runs "
+                        + ", ".join(f"{t:.2f}" for t in ts) + f" s); oracle setup {t_setup:.2f} s not in value"),
+                threads=1, cpu_model=_cpu_model(), host_cpus=os.cpu_count(),
+                copy_bandwidth_gbs=round(_copy_bandwidth_gbs(), 1),
+                kernel_ms=kern, setup_s=round(t_setup, 2), solve_s_runs=[round(t, 3) for t in ts],
+                iterations=info["iterations"], x=xo)
 
 
 def _make_request(spec):
@@ -110,31 +154,33 @@ def _make_request(spec):
     return J.serving_case(grid, tol, seed)
 
 
-def run_serving(args):
-    """Serving: requests arrive as a Poisson stream; each is one FGMRES(50)
-    solve of its own seeded Jacobian.  The Jacobians are generated before the
-    stream starts (the simulator's side); the timed part is submission to
-    completion through the solve server.  Prints one JSON line with solves/s
-    and the p50/p99 latency."""
+def generate_requests(n, rate):
+    """The serving stream's Jacobians, generated in forked worker processes
+    (call before this process touches the GPU)."""
     import multiprocessing as mp
+    from synth import jacobian as J
+    stream = J.serving_stream(n, rate=rate)
+    log(f"serving: generating {len(stream)} requests")
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        cases = pool.map(_make_request, stream, chunksize=1)
+    return stream, cases
+
+
+def serve_stream(stream, cases, rate, slots, setup_workers, setup_threads, verbose=True):
+    """Submit the requests at their Poisson arrival times to a solve server
+    (mixed-precision FGMRES(50)) and wait for all of them.  Returns the
+    serving summary: solves/s over the makespan, p50/p99 latency, the median
+    latency split, and whether the offered rate was sustained."""
     import threading
 
     import numpy as np
+    import paper_2308_11892_amd as L
     from synth import jacobian as J
 
-    stream = J.serving_stream(args.serve, rate=args.rate)
-    log(f"serving: generating {len(stream)} requests")
-    # worker processes are forked before this process touches the GPU
-    with mp.get_context("fork").Pool(min(8, os.cpu_count() or 1)) as pool:
-        cases = pool.map(_make_request, stream, chunksize=1)
-    import torch
-    import paper_2308_11892_amd as L
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
     cells = [c.n_cells for c in cases]
-    log(f"serving: {sum(cells)} cells in total; starting the server")
-    sv = L.Server(max_inflight=args.slots, setup_workers=args.setup_workers,
-                  setup_threads=args.setup_threads, hbm_budget_bytes=64 << 30)
+    log(f"serving: {len(cases)} requests, {sum(cells)} cells in total; starting the server")
+    sv = L.Server(max_inflight=slots, setup_workers=setup_workers,
+                  setup_threads=setup_threads, hbm_budget_bytes=64 << 30)
     ids = [None] * len(stream)
     t0 = time.perf_counter()
 
@@ -157,33 +203,86 @@ def run_serving(args):
         rr = float("nan") if x is None else float(
             np.linalg.norm(c.b - J.bsr_matvec_plain(c.row_ptr, c.col_idx, c.values, x)) / np.linalg.norm(c.b))
         res.append((info, rr, stream[r][2]))
-        log(f"request {r} {c.name} tol {stream[r][2]:g}: status {info['status']} {info['iterations']} it "
-            f"rel res {rr:.2e} latency {info['latency_s'] * 1e3:.0f} ms (queue {info['queue_s'] * 1e3:.0f}, "
-            f"host setup {info['host_setup_s'] * 1e3:.0f}, admit {info['admit_wait_s'] * 1e3:.0f}, "
-            f"device setup {info['device_setup_s'] * 1e3:.0f}, solve {info['solve_s'] * 1e3:.0f})")
+        if verbose:
+            log(f"request {r} {c.name} tol {stream[r][2]:g}: status {info['status']} {info['iterations']} it "
+                f"rel res {rr:.2e} latency {info['latency_s'] * 1e3:.0f} ms (queue {info['queue_s'] * 1e3:.0f}, "
+                f"host setup {info['host_setup_s'] * 1e3:.0f}, admit {info['admit_wait_s'] * 1e3:.0f}, "
+                f"device setup {info['device_setup_s'] * 1e3:.0f}, solve {info['solve_s'] * 1e3:.0f})")
     t_end = time.perf_counter()
     st = sv.stats()
     sv.close()
     ok = [i for i, rr, tol in res if i["status"] >= 0 and rr <= tol]
     lat = np.array([i["latency_s"] for i, _, _ in res])
     med = lambda k: float(np.median([i[k] for i, _, _ in res]))
-    out = {
-        "metric": "CPTR-FGMRES serving: solves/s and p50/p99 solve latency",
-        "value": len(ok) / (t_end - t0), "unit": "solves/s", "n_gpus": 1,
+    span = stream[-1][0] - stream[0][0]
+    sps = len(ok) / (t_end - t0)
+    return {
         "requests": len(res), "converged_within_tol": len(ok),
+        "offered_rate_per_s": rate, "arrival_span_s": round(span, 3),
+        "solves_per_s": sps, "makespan_s": t_end - t0,
+        "sustained": bool(sps >= 0.9 * len(res) / max(span, 1e-9) and len(ok) == len(res)),
         "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
         "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
         "median_ms": {k: med(k) * 1e3 for k in ("queue_s", "host_setup_s", "admit_wait_s",
                                                   "device_setup_s", "solve_s")},
-        "makespan_s": t_end - t0, "peak_inflight": st["peak_inflight"],
-        "peak_reserved_gib": st["peak_reserved_bytes"] / 2**30, "hbm_budget_gib": st["hbm_budget_bytes"] / 2**30,
-        "higher_is_better": True, "dtype": "f32 preconditioner, f64 Krylov", "data": "synthetic",
-        "config": {"workload": f"serving: {len(res)} Poisson arrivals at {args.rate:g}/s, grids "
-                               "40x40x10/80x80x20/160x160x20/200x200x40, tol 1e-4 or 1e-6, FGMRES(50)",
-                   "slots": args.slots, "setup_workers": args.setup_workers,
-                   "setup_threads": args.setup_threads},
+        "peak_inflight": st["peak_inflight"], "peak_reserved_gib": st["peak_reserved_bytes"] / 2**30,
+        "hbm_budget_gib": st["hbm_budget_bytes"] / 2**30,
+        "dtype": "f32 preconditioner, f64 Krylov",
+        "workload": f"{len(res)} Poisson arrivals at {rate:g}/s, grids 40x40x10/80x80x20/160x160x20/"
+                    "200x200x40 (100x100x20 generator, own seeds), tol 1e-4 or 1e-6, FGMRES(50)",
+        "slots": slots, "setup_workers": setup_workers, "setup_threads": setup_threads,
     }
+
+
+def run_serving(args):
+    """Serving alone (--serve N): one JSON line with solves/s and p50/p99."""
+    import torch
+    stream, cases = generate_requests(args.serve, args.rate)
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    out = serve_stream(stream, cases, args.rate, args.slots, args.setup_workers, args.setup_threads)
+    out.update({"metric": "CPTR-FGMRES serving: solves/s and p50/p99 solve latency",
+                "value": out["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+                "data": "synthetic"})
     print(json.dumps(out), flush=True)
+
+
+def run_unstructured(restart):
+    """The 1M-cell Voronoi-prism mesh in RCM order (no grid structure: the
+    one-launch level-scheduled sweeps): FP64 FGMRES(50) to 1e-6, iterations,
+    time to tolerance (median of 3 solves), setup, and the phase times of one
+    profiled solve."""
+    import numpy as np
+    import torch
+    import paper_2308_11892_amd as L
+    from synth import jacobian as J
+    log("unstructured: generating prism50000x20")
+    c = J.by_name("prism50000x20")
+    b = torch.tensor(c.b, device="cuda:0")
+    kw = dict(restart=restart, flexible=True, rtol=c.tol)
+    out = {"workload": f"{c.name}: 50k-point Voronoi prisms x 20 layers in RCM order, "
+                       f"{c.n_cells} cells, {c.n_dof} DOF, {c.nnzb} blocks, FGMRES({restart}), rtol {c.tol:g}"}
+    for prec, key in ((L.PRECISION_FP64, "fp64"), (L.PRECISION_FP32, "fp32_preconditioner")):
+        with L.Solver(c.row_ptr, c.col_idx, c.values, precond_precision=prec) as s:
+            x = torch.zeros_like(b)
+            info = s.gmres_solve(b, x, **kw)
+            ts = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                info = s.gmres_solve(b, x, **kw)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            s.phase_times(reset=True)
+            s.gmres_solve(b, torch.zeros_like(b), profile=True, **kw)
+            ph = {k: round(ms / cnt, 4) for k, (ms, cnt) in s.phase_times(reset=True).items() if cnt}
+            out[key] = {"iterations": info["iterations"], "converged": info["converged"],
+                        "true_rel_res": info["rel_res_true"], "time_to_tol_ms": float(np.median(ts)) * 1e3,
+                        "dof_iter_per_s": c.n_dof * info["iterations"] / float(np.median(ts)),
+                        "setup_s": info["setup_s"], "phase_avg_ms": ph,
+                        "sweep": ["auto", "levels", "one_launch", "grid"][int(s.export("SWEEP", 0, 4, np.int32)[0])]}
+            log(f"unstructured {key}: {info['iterations']} it, {np.median(ts) * 1e3:.1f} ms; "
+                f"ILU {ph.get('ilu_fwd', 0):.3f} + {ph.get('ilu_bwd', 0):.3f} ms per application")
+    return out
 
 
 def run_cpr_comparison():
@@ -215,6 +314,15 @@ def run_cpr_comparison():
                       "config": {"workload": "grid100x100x20 Peclet sweep"}, "rows": rows}), flush=True)
 
 
+def build_info():
+    """Source revision and kernel source hash recorded by the build (the GPU
+    box has no git metadata)."""
+    try:
+        return json.load(open(os.path.join(ROOT, "paper_2308_11892_amd", "build_info.json")))
+    except (OSError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -238,6 +346,10 @@ def main():
     ap.add_argument("--setup-workers", type=int, default=16, help="serving: concurrent host setups")
     ap.add_argument("--setup-threads", type=int, default=0,
                     help="serving: threads per host setup (0: sized per request, 1 to 4)")
+    ap.add_argument("--serve-requests", type=int, default=40,
+                    help="requests of the serving sub-object of the default run (0: none)")
+    ap.add_argument("--no-unstructured", action="store_true",
+                    help="leave out the unstructured (1M-cell prism mesh) sub-object")
     ap.add_argument("--compare-cpr", action="store_true",
                     help="instead of the solve benchmark, compare CPTR with CPR (elliptic set {p}) "
                          "on the 100x100x20 Peclet sweep at time steps of 1 and 30 days")
@@ -255,6 +367,9 @@ def main():
         return
 
     import numpy as np
+    # the serving requests are generated in forked workers before this
+    # process touches the GPU
+    serve_reqs = generate_requests(args.serve_requests, args.rate) if args.serve_requests > 0 else None
     import torch
     import paper_2308_11892_amd as L
     from synth import jacobian as J
@@ -353,6 +468,9 @@ def main():
                    "ilu_sweep": ["auto", "levels", "one_launch", "grid"][int(sweep_mode[0])]},
         "iterations": its,
         "time_to_tol_s": dt / args.steps,
+        "seed": int(c.meta["seed"]),
+        "build": build_info(),
+        "gpu": torch.cuda.get_device_name(0) + " " + getattr(torch.cuda.get_device_properties(0), "gcnArchName", ""),
         "setup_s": setup_s,
         "roofline": roof,
         "phases": phases,
@@ -397,12 +515,20 @@ def main():
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on {c.name}")
         cb = run_cpu_baseline(c, args.restart)
-        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        out["cpu_baseline"] = {k: v for k, v in cb.items() if k != "x"}
         xo = cb["x"]
         out["rel_diff_vs_oracle_solution"] = float(np.linalg.norm(x64 - xo) / np.linalg.norm(xo))
         if x32h is not None:
             out["mixed_precision"]["rel_diff_vs_oracle_solution"] = float(
                 np.linalg.norm(x32h - xo) / np.linalg.norm(xo))
+    if not args.no_unstructured:
+        out["unstructured"] = run_unstructured(args.restart)
+    if serve_reqs is not None:
+        out["serving"] = serve_stream(*serve_reqs, args.rate, args.slots, args.setup_workers, args.setup_threads,
+                                      verbose=False)
+        sv = out["serving"]
+        log(f"serving: {sv['solves_per_s']:.1f} solves/s over {sv['makespan_s']:.2f} s, p50 "
+            f"{sv['p50_latency_ms']:.0f} ms, p99 {sv['p99_latency_ms']:.0f} ms, sustained {sv['sustained']}")
     print(json.dumps(out), flush=True)
 
 

@@ -256,6 +256,11 @@ enum {
                                   (the solve server's footprint measurement): a positive entry
                                   allocates that many bytes (in 256-byte pieces), -1 - k releases
                                   the k-th allocation; CPTR_E_STATE for a device handle */
+  CPTR_EXPORT_SETUP_TIMES = 14, /* double[10]: wall seconds of the setup steps: validation,
+                                  quasi-IMPES weights and level-0 operator, strength graphs,
+                                  C/F splits, interpolations (with R = P^T), Galerkin products,
+                                  l1 diagonals and coarsest LU, host ILU(0) and sweep levels,
+                                  then the device half and the whole cptr_setup */
   CPTR_EXPORT_SETUP_SITES = 12 /* int32[6]: strength graphs formed on the device and in total,
                                   extended+i interpolations on the device and in total,
                                   coarse operators R A P on the device and in total.  A device

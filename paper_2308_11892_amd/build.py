@@ -29,6 +29,25 @@ def _run(cmd):
     return r
 
 
+def _write_build_info():
+    """Revision of the sources the library was built from (read by the
+    benchmark on machines without the git metadata)."""
+    import hashlib
+    import json
+    info = {"kernels_hip_sha256": hashlib.sha256(open(os.path.join(CSRC, "kernels.hip"), "rb").read()).hexdigest()}
+    try:
+        sha = subprocess.run(["git", "rev-parse", "HEAD"], cwd=ROOT, capture_output=True, text=True)
+        dirty = subprocess.run(["git", "status", "--porcelain", "--untracked-files=no"], cwd=ROOT,
+                               capture_output=True, text=True)
+        if sha.returncode == 0:
+            info["git_sha"] = sha.stdout.strip()
+            info["git_dirty"] = bool(dirty.stdout.strip())
+    except OSError:
+        pass
+    with open(os.path.join(HERE, "build_info.json"), "w") as f:
+        json.dump(info, f)
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = []
@@ -45,6 +64,7 @@ def build(verbose: bool = False) -> str:
     tmp = OUT + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"])
     os.replace(tmp, OUT)
+    _write_build_info()
     if verbose:
         print("built", OUT)
     return OUT

@@ -144,6 +144,7 @@ struct cptr_solver_s {
   int ilu_mode = CPTR_ILU_SWEEP_AUTO;
   std::string err;
   double setup_s = 0.0;
+  double device_build_s = 0.0;  // wall time of the device half
   int ne = 2;
   int nsweeps = 1;           // l1-Jacobi sweeps before and after the coarse correction
   int max_restart = 0;       // Krylov space of cptr_setup (cptr_setup_opts.max_restart)
@@ -1369,6 +1370,7 @@ int setup_device(cptr_solver s, DevArena* arena, int restart, bool flexible, hip
   if (he != hipSuccess || dev_count == 0) return fail(s, CPTR_E_HIP, "no HIP device available");
   s->arena = arena;
   int rc;
+  const double t_dev = now_s();
   try {
     rc = build_device(s, st);
     if (!rc) rc = alloc_solve_space(s, std::max(1, std::min(restart, kMaxRestart)), flexible);
@@ -1384,6 +1386,7 @@ int setup_device(cptr_solver s, DevArena* arena, int restart, bool flexible, hip
     return rc;
   }
   s->device = true;
+  s->device_build_s = now_s() - t_dev;
   return CPTR_OK;
 }
 
@@ -1845,6 +1848,13 @@ cptr_status cptr_export(cptr_solver s, int32_t what, int32_t level, void* buf, i
       if (rc) return (cptr_status)rc;
       plan.insert(plan.begin(), (int64_t)plan.size());
       return put(plan.data(), (int64_t)plan.size() * 8);
+    }
+    case CPTR_EXPORT_SETUP_TIMES: {
+      double t[10];
+      for (int k = 0; k < 8; ++k) t[k] = h.step_s[k];
+      t[8] = s->device_build_s;
+      t[9] = s->setup_s;
+      return put(t, sizeof t);
     }
     case CPTR_EXPORT_SETUP_SITES: {
       const int32_t built = (int32_t)h.lev.size() - 1;

@@ -10,6 +10,7 @@
 // Compiled with FP contraction off so that the reduced elliptic matrix and the
 // strength tests on it are bit-reproducible.
 #include <algorithm>
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -810,6 +811,14 @@ static inline void mm3(const double* a, const double* b, double* c) {
 int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const double* v,
                      const int32_t* elliptic, int ne, const SetupParams& prm, HostSetup& h,
                      std::string& err) {
+  using clock = std::chrono::steady_clock;
+  auto tick = clock::now();
+  // adds the time since the last mark to step k
+  auto mark = [&](int k) {
+    const auto now = clock::now();
+    h.step_s[k] += std::chrono::duration<double>(now - tick).count();
+    tick = now;
+  };
   const int threads = std::max(1, prm.threads);
   h.nb = nb;
   h.ne = ne;
@@ -831,6 +840,7 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
       for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
         if (ci[k] == i) h.diag[i] = k;
   });
+  mark(kStepValidate);
 
   // ---- quasi-IMPES weights W_i = A_ii[E,H] A_ii[H,H]^-1 (Sec. 5.2) ----
   const int nh = h.nh;
@@ -907,6 +917,7 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
     L0.func.resize(A0.n);
     for (int32_t r = 0; r < A0.n; ++r) L0.func[r] = r % ne;
   }
+  mark(kStepReduce);
   for (;;) {
     const size_t l = h.lev.size() - 1;
     const Csr& A = h.lev[l].A;
@@ -915,8 +926,10 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
     Csr S;
     if (!dev || !dev->strength(h.lev[l].func, prm.theta, prm.max_row_sum, S))
       S = strength_graph(A, h.lev[l].func, prm.theta, prm.max_row_sum, threads);
+    mark(kStepStrength);
     const bool agg = (int)l < prm.agg_levels;
     std::vector<int32_t> cf = agg ? aggressive_split(S, threads) : first_pass_split(S, threads);
+    mark(kStepSplit);
     int32_t nc = 0;
     for (auto x : cf) nc += x == 1;
     if (nc == 0 || nc == A.n) break;
@@ -926,8 +939,10 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
     else if (!dev || !dev->interp(S, cf, h.lev[l].func, prm.pmax, P))
       P = extended_i_interp(A, S, cf, h.lev[l].func, prm.pmax, threads);
     Csr R = transpose(P, threads);
+    mark(kStepInterp);
     Csr Ac;
     if (!dev || !dev->galerkin(R, P, Ac)) Ac = galerkin(R, A, P, threads);
+    mark(kStepGalerkin);
     std::vector<int32_t> fc;
     fc.reserve(nc);
     for (int32_t i = 0; i < A.n; ++i)
@@ -956,6 +971,7 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
     int st = dense_lu(Ac.n, h.coarse_lu, h.coarse_piv, err);
     if (st != CPTR_OK) return st;
   }
+  mark(kStepSmoother);
 
   // ---- block ILU(0) on A's pattern, matrix ordering (Sec. 3.1) ----
   if (!prm.skip_ilu) {
@@ -1004,6 +1020,7 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
   }
   h.n_fwd_levels = nf;
   h.n_bwd_levels = nbk;
+  mark(kStepIlu);
   return CPTR_OK;
 }
 

@@ -103,6 +103,18 @@ struct HostSetup {
   std::vector<double> uinv;    // [nb][3][3] inverse of each U_ii (both empty with skip_ilu)
   std::vector<int32_t> fwd_level, bwd_level;  // dependency level of each row
   int32_t n_fwd_levels = 0, n_bwd_levels = 0;
+  // wall seconds of the setup steps (kSetupStep*), summed over levels
+  double step_s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+};
+enum SetupStep {
+  kStepValidate = 0,   // validation, diagonal search
+  kStepReduce = 1,     // quasi-IMPES weights and the level-0 operator
+  kStepStrength = 2,   // strength graphs
+  kStepSplit = 3,      // C/F splits (first passes, aggressive second pass)
+  kStepInterp = 4,     // interpolation and its transpose
+  kStepGalerkin = 5,   // R A P
+  kStepSmoother = 6,   // l1 diagonals, coarsest dense LU
+  kStepIlu = 7         // host ILU(0) (host-only handles) and the sweeps' dependency levels
 };
 
 // Returns a cptr_status value; on failure `err` holds the message.
