@@ -387,6 +387,7 @@ def main():
     s = L.Solver(c.row_ptr, c.col_idx, c.values)
     rows, nnz = s.hierarchy()
     sweep_mode = s.export("SWEEP", 0, 4, np.int32)
+    setup_steps = {k: round(float(v), 4) for k, v in zip(L.SETUP_STEPS, s.export("SETUP_TIMES", 0, 10))}
     grid_sweeps = int(sweep_mode[0]) == L.ILU_SWEEP_GRID
     b = torch.tensor(c.b, device=dev)
     x = torch.zeros_like(b)
@@ -476,6 +477,7 @@ def main():
         "build": build_info(),
         "gpu": torch.cuda.get_device_name(0) + " " + getattr(torch.cuda.get_device_properties(0), "gcnArchName", ""),
         "setup_s": setup_s,
+        "setup_steps_s": setup_steps,
         "roofline": roof,
         "phases": phases,
     }
