@@ -103,6 +103,11 @@ typedef struct {
   int32_t flexible_space;    /* 1: also allocate the max_restart preconditioned vectors Z that
                                 flexible solves keep; 0: flexible solves return CPTR_E_STATE;
                                 default 1 */
+  int32_t hmis_block;        /* HMIS coarsening (Sec. 3.1) over blocks of this many consecutive
+                                rows of a level, each block standing for one subdomain: the
+                                Ruge-Stueben first pass inside every block, then PMIS on the
+                                points it leaves undecided across blocks; 1 = PMIS; default
+                                0 = one block (the first pass over the whole level) */
 } cptr_setup_opts;
 
 enum {

@@ -55,6 +55,8 @@ def lib():
         L.or_strength2.restype = P
         L.or_strength2.argtypes = [C.c_int, lp, ip, ip]
         L.or_aggressive_split.argtypes = [C.c_int, lp, ip, ip]
+        L.or_hmis_split.argtypes = [C.c_int, lp, ip, C.c_int, ip]
+        L.or_aggressive_hmis.argtypes = [C.c_int, lp, ip, C.c_int, ip]
         L.or_multipass.restype = P
         L.or_multipass.argtypes = [C.c_int, lp, ip, dp, lp, ip, ip, ip]
         L.or_amg_setup.argtypes = [C.c_int, lp, ip, dp, ip, P, C.POINTER(P)]
@@ -88,11 +90,12 @@ def lib():
 class AmgOpts(C.Structure):
     _fields_ = [("theta", C.c_double), ("max_row_sum", C.c_double),
                 ("max_levels", C.c_int), ("max_coarse", C.c_int), ("pmax", C.c_int),
-                ("agg_levels", C.c_int), ("num_sweeps", C.c_int)]
+                ("agg_levels", C.c_int), ("num_sweeps", C.c_int), ("hmis_block", C.c_int)]
 
     def __init__(self, theta=0.25, max_row_sum=0.9, max_levels=25, max_coarse=9, pmax=4,
-                 agg_levels=1, num_sweeps=1):
-        super().__init__(theta, max_row_sum, max_levels, max_coarse, pmax, agg_levels, num_sweeps)
+                 agg_levels=1, num_sweeps=1, hmis_block=0):
+        super().__init__(theta, max_row_sum, max_levels, max_coarse, pmax, agg_levels, num_sweeps,
+                         hmis_block)
 
 
 class GmresOpts(C.Structure):
@@ -202,6 +205,21 @@ def aggressive_split(S):
     n, rp, ci, _ = _csr_parts(S)
     cf = np.zeros(n, dtype=np.int32)
     lib().or_aggressive_split(n, _l(rp), _i(ci), _i(cf))
+    return cf
+
+
+def hmis_split(S, block):
+    """HMIS split over blocks of `block` consecutive points (0: one block)."""
+    n, rp, ci, _ = _csr_parts(S)
+    cf = np.zeros(n, dtype=np.int32)
+    lib().or_hmis_split(n, _l(rp), _i(ci), int(block), _i(cf))
+    return cf
+
+
+def aggressive_hmis(S, block):
+    n, rp, ci, _ = _csr_parts(S)
+    cf = np.zeros(n, dtype=np.int32)
+    lib().or_aggressive_hmis(n, _l(rp), _i(ci), int(block), _i(cf))
     return cf
 
 

@@ -363,6 +363,125 @@ void or_rs_first_pass(int n, const long *srp, const int *sci, int *cf) {
 }
 
 /* ------------------------------------------------------------------ */
+/* HMIS coarsening (De Sterck, Yang, Heys 2006), Sec. 3.1              */
+/* ------------------------------------------------------------------ */
+/* SplitMix64 (Steele, Lea, Flood 2014): the generator's output for the
+ * counter value x, i.e. its mixing function applied to x + golden gamma. */
+static unsigned long long splitmix64(unsigned long long x) {
+  unsigned long long z = x + 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+/* PMIS priority of point i: (count, splitmix64(i), i), larger first. */
+static int key_above(long ci, int i, long cj, int j) {
+  if (ci != cj) return ci > cj;
+  unsigned long long hi = splitmix64((unsigned long long)i), hj = splitmix64((unsigned long long)j);
+  if (hi != hj) return hi > hj;
+  return i > j;
+}
+
+/* HMIS over fixed blocks of `block` consecutive points (block <= 0 or >= n:
+ * one block).  HMIS runs the Ruge-Stueben first pass inside every
+ * processor's subdomain and hands the C points it finds to PMIS as its first
+ * independent set; here a subdomain is a block.
+ *  1. Each block: or_rs_first_pass on the strong links with both ends in the
+ *     block.  Its C points are C.
+ *  2. A point that is not C and depends strongly on a C point is F.
+ *  3. PMIS on the remaining points U.  cnt_i = how many points of U depend
+ *     strongly on i.  A point with cnt_i = 0 is F.  Then, in rounds: every
+ *     point of U whose key (cnt_i, splitmix64(i), i) exceeds the key of each
+ *     of its strong neighbours still in U (links in either direction) becomes
+ *     C, and then every point of U that depends strongly on one of these new C
+ *     points becomes F; until U is empty.
+ * With one block, the C points of step 1 are those of the first pass, step 2
+ * gives the F points that pass made while picking, and every point left over
+ * has cnt = 0, so the split equals or_rs_first_pass.  With blocks of one
+ * point, step 1 finds nothing and the split is PMIS.  cf: 1 = C, -1 = F. */
+void or_hmis_split(int n, const long *srp, const int *sci, int block, int *cf) {
+  if (block <= 0 || block > n) block = n > 0 ? n : 1;
+  /* step 1 */
+  long *brp = xmalloc(sizeof(long) * ((size_t)block + 1));
+  int *bci = xmalloc(sizeof(int) * (size_t)(srp[n] > 0 ? srp[n] : 1));
+  int *bcf = xmalloc(sizeof(int) * (size_t)block);
+  for (int lo = 0; lo < n; lo += block) {
+    const int hi = lo + block < n ? lo + block : n;
+    long nz = 0;
+    brp[0] = 0;
+    for (int i = lo; i < hi; i++) {
+      for (long a = srp[i]; a < srp[i + 1]; a++)
+        if (sci[a] >= lo && sci[a] < hi) bci[nz++] = sci[a] - lo;
+      brp[i - lo + 1] = nz;
+    }
+    or_rs_first_pass(hi - lo, brp, bci, bcf);
+    for (int i = lo; i < hi; i++) cf[i] = bcf[i - lo] == 1 ? 1 : 0;
+  }
+  free(bcf);
+  free(bci);
+  free(brp);
+  /* step 2 */
+  for (int i = 0; i < n; i++) {
+    if (cf[i] != 0) continue;
+    for (long a = srp[i]; a < srp[i + 1]; a++)
+      if (cf[sci[a]] == 1) {
+        cf[i] = -2; /* F, marked after the scan so the scan sees only C */
+        break;
+      }
+  }
+  for (int i = 0; i < n; i++)
+    if (cf[i] == -2) cf[i] = -1;
+  /* step 3 */
+  or_mat *s = mat_from(n, n, srp, sci, NULL);
+  or_mat *st = mat_transpose(s);
+  long *cnt = xcalloc((size_t)(n ? n : 1), sizeof(long));
+  for (int i = 0; i < n; i++) {
+    if (cf[i] != 0) continue;
+    for (long a = st->rp[i]; a < st->rp[i + 1]; a++) cnt[i] += cf[st->ci[a]] == 0;
+  }
+  for (int i = 0; i < n; i++)
+    if (cf[i] == 0 && cnt[i] == 0) cf[i] = -3; /* F, applied together below */
+  for (int i = 0; i < n; i++)
+    if (cf[i] == -3) cf[i] = -1;
+  int *isnew = xcalloc((size_t)(n ? n : 1), sizeof(int));
+  for (;;) {
+    int left = 0;
+    for (int i = 0; i < n; i++) {
+      isnew[i] = 0;
+      if (cf[i] != 0) continue;
+      left = 1;
+      int top = 1;
+      for (int dir = 0; dir < 2 && top; dir++) {
+        const or_mat *g = dir ? st : s;
+        for (long a = g->rp[i]; a < g->rp[i + 1]; a++) {
+          int j = g->ci[a];
+          if (cf[j] == 0 && key_above(cnt[j], j, cnt[i], i)) {
+            top = 0;
+            break;
+          }
+        }
+      }
+      isnew[i] = top;
+    }
+    if (!left) break;
+    for (int i = 0; i < n; i++)
+      if (isnew[i]) cf[i] = 1;
+    for (int i = 0; i < n; i++) {
+      if (cf[i] != 0) continue;
+      for (long a = s->rp[i]; a < s->rp[i + 1]; a++)
+        if (isnew[s->ci[a]]) {
+          cf[i] = -1;
+          break;
+        }
+    }
+  }
+  free(isnew);
+  free(cnt);
+  or_mat_free(s);
+  or_mat_free(st);
+}
+
+/* ------------------------------------------------------------------ */
 /* Extended+i interpolation (De Sterck, Falgout, Nolting, Yang 2008)    */
 /* ------------------------------------------------------------------ */
 /* For an F point i with strong C neighbours C_i and strong F neighbours F_i,
@@ -570,15 +689,16 @@ or_mat *or_strength2(int n, const long *srp, const int *sci, const int *cf) {
   return s2;
 }
 
-/* Aggressive C/F split: a first pass on S gives C1; a second first pass over
- * the C1 points with the distance-two strength S2 gives C2, the final C
+/* Aggressive C/F split: an HMIS split of S (blocks of `block` points) gives
+ * C1; a second HMIS split over the C1 points, numbered in order, with the
+ * distance-two strength S2 and the same block length gives C2, the final C
  * points.  Everything else is F.  cf: 1 = C, -1 = F. */
-void or_aggressive_split(int n, const long *srp, const int *sci, int *cf) {
+void or_aggressive_hmis(int n, const long *srp, const int *sci, int block, int *cf) {
   int *cf1 = xmalloc(sizeof(int) * (size_t)(n ? n : 1));
-  or_rs_first_pass(n, srp, sci, cf1);
+  or_hmis_split(n, srp, sci, block, cf1);
   or_mat *s2 = or_strength2(n, srp, sci, cf1);
   int *cf2 = xmalloc(sizeof(int) * (size_t)(s2->n ? s2->n : 1));
-  or_rs_first_pass(s2->n, s2->rp, s2->ci, cf2);
+  or_hmis_split(s2->n, s2->rp, s2->ci, block, cf2);
   for (int i = 0, c = 0; i < n; i++) {
     if (cf1[i] == 1)
       cf[i] = cf2[c++] == 1 ? 1 : -1;
@@ -588,6 +708,11 @@ void or_aggressive_split(int n, const long *srp, const int *sci, int *cf) {
   or_mat_free(s2);
   free(cf2);
   free(cf1);
+}
+
+/* the aggressive split with one block: first passes over the whole level */
+void or_aggressive_split(int n, const long *srp, const int *sci, int *cf) {
+  or_aggressive_hmis(n, srp, sci, 0, cf);
 }
 
 /* Multipass interpolation (Stueben, "A review of algebraic multigrid", 2001)
@@ -744,6 +869,7 @@ void or_amg_opts_default(or_amg_opts *o) {
   o->pmax = 4;
   o->agg_levels = 1;
   o->num_sweeps = 1;
+  o->hmis_block = 0;
 }
 
 /* l1-Jacobi (Baker, Falgout, Kolev, Yang 2011) with one point per block:
@@ -826,7 +952,8 @@ void or_amg_free(or_amg *a) {
 /* Coarsen while the level has more than max_coarse rows and fewer than
  * max_levels levels exist; stop early when a split gives no C point or only
  * C points.  The first agg_levels levels use the aggressive split with
- * multipass interpolation, the others the first pass with extended+i.  A_{l+1} = R_l A_l P_l with R_l = P_l^T (Galerkin), coarse
+ * multipass interpolation, the others the HMIS split with extended+i; both
+ * split over blocks of hmis_block points.  A_{l+1} = R_l A_l P_l with R_l = P_l^T (Galerkin), coarse
  * function labels inherited from the C points. */
 int or_amg_setup(int n, const long *rp, const int *ci, const double *v,
                  const int *func, const or_amg_opts *o_in, or_amg **out) {
@@ -838,6 +965,7 @@ int or_amg_setup(int n, const long *rp, const int *ci, const double *v,
   if (n <= 0) return fail(OR_E_INVALID, "empty matrix");
   if (o.max_levels < 1 || o.max_levels > OR_MAXLEV) return fail(OR_E_INVALID, "max_levels");
   if (o.num_sweeps < 1) return fail(OR_E_INVALID, "num_sweeps");
+  if (o.hmis_block < 0) return fail(OR_E_INVALID, "hmis_block");
   or_amg *a = xcalloc(1, sizeof *a);
   a->nsweeps = o.num_sweeps;
   a->A[0] = mat_from(n, n, rp, ci, v);
@@ -851,9 +979,9 @@ int or_amg_setup(int n, const long *rp, const int *ci, const double *v,
     int *cf = xmalloc(sizeof(int) * (size_t)A->n);
     const int agg = l < o.agg_levels;
     if (agg)
-      or_aggressive_split(A->n, s->rp, s->ci, cf);
+      or_aggressive_hmis(A->n, s->rp, s->ci, o.hmis_block, cf);
     else
-      or_rs_first_pass(A->n, s->rp, s->ci, cf);
+      or_hmis_split(A->n, s->rp, s->ci, o.hmis_block, cf);
     int nc = 0;
     for (int i = 0; i < A->n; i++) nc += cf[i] == 1;
     if (nc == 0 || nc == A->n) {

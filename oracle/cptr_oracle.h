@@ -55,7 +55,11 @@ or_mat *or_extpi(int n, const long *rp, const int *ci, const double *v,
                  int pmax);
 /* distance-two strength among the C points of cf (rows = C points in order) */
 or_mat *or_strength2(int n, const long *srp, const int *sci, const int *cf);
-/* aggressive split: first pass, then a first pass over C with or_strength2 */
+/* HMIS split over blocks of `block` consecutive points (<= 0: one block) */
+void or_hmis_split(int n, const long *srp, const int *sci, int block, int *cf);
+/* aggressive split: HMIS, then HMIS over the C points with or_strength2 */
+void or_aggressive_hmis(int n, const long *srp, const int *sci, int block, int *cf);
+/* the same with one block (first passes over the whole level) */
 void or_aggressive_split(int n, const long *srp, const int *sci, int *cf);
 /* multipass interpolation for a split (no truncation) */
 or_mat *or_multipass(int n, const long *rp, const int *ci, const double *v,
@@ -69,6 +73,7 @@ typedef struct {
   int pmax;            /* 4 */
   int agg_levels;      /* 1: levels coarsened aggressively (multipass interpolation) */
   int num_sweeps;      /* 1: l1-Jacobi sweeps before and after the coarse correction */
+  int hmis_block;      /* 0: points per HMIS block (0: one block per level) */
 } or_amg_opts;
 void or_amg_opts_default(or_amg_opts *o);
 

@@ -1204,6 +1204,7 @@ void cptr_setup_opts_default(cptr_setup_opts* o) {
   o->num_sweeps = 1;
   o->max_restart = 50;
   o->flexible_space = 1;
+  o->hmis_block = 0;
 }
 
 void cptr_solve_opts_default(cptr_solve_opts* o) {
@@ -1253,7 +1254,7 @@ int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_id
   if (o.flexible_space != 0 && o.flexible_space != 1)
     return (cptr_status)fail(nullptr, CPTR_E_INVALID, "flexible_space must be 0 or 1");
   if (o.max_levels < 1 || o.max_levels > 64 || o.max_coarse < 1 || o.p_max_elmts < 0 ||
-      o.agg_levels < 0 ||
+      o.agg_levels < 0 || o.hmis_block < 0 ||
       !(o.strong_threshold >= 0.0) || !(o.max_row_sum > 0.0))
     return (cptr_status)fail(nullptr, CPTR_E_INVALID, "setup options out of range");
   if (A->n_block_rows <= 0 || A->nnz_blocks <= 0 || A->nnz_blocks >= INT32_MAX)
@@ -1310,6 +1311,7 @@ int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_id
   prm.max_coarse = o.max_coarse;
   prm.pmax = o.p_max_elmts;
   prm.agg_levels = o.agg_levels;
+  prm.hmis_block = o.hmis_block;
   prm.quasi_impes = o.restriction == CPTR_RESTRICT_QUASI_IMPES;
   unsigned hw = std::thread::hardware_concurrency();
   prm.threads = o.setup_threads > 0 ? o.setup_threads : (int)std::min<unsigned>(16, hw ? hw : 1);

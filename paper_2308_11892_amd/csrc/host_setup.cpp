@@ -316,6 +316,119 @@ std::vector<int32_t> first_pass_split(const Csr& S, int threads) {
 }
 
 // ---------------------------------------------------------------------------
+// HMIS (De Sterck, Yang, Heys 2006) over blocks of `block` consecutive points,
+// a block standing for one processor's subdomain:
+//  1. the first pass above inside every block, on the strong links with both
+//     ends in the block; its C points are C;
+//  2. a point that is not C and depends strongly on a C point is F;
+//  3. PMIS on the rest, U: cnt_i = number of points of U depending strongly on
+//     i; cnt_i = 0 makes i F; then in rounds every point of U whose priority
+//     (cnt_i, splitmix64(i), i) beats that of each strong neighbour still in
+//     U (links either way) is C, and the points of U depending on one of those
+//     are F.
+// One block (block <= 0 or >= n) is the first pass itself: its picks make
+// exactly the F points of step 2 and every leftover has cnt = 0.
+namespace {
+// SplitMix64 (Steele, Lea, Flood 2014): the output for counter value x.
+inline uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+inline bool beats(int64_t ca, int32_t a, int64_t cb, int32_t b) {
+  if (ca != cb) return ca > cb;
+  const uint64_t ha = splitmix64((uint64_t)a), hb = splitmix64((uint64_t)b);
+  if (ha != hb) return ha > hb;
+  return a > b;
+}
+}  // namespace
+
+std::vector<int32_t> hmis_split(const Csr& S, int32_t block, int threads) {
+  const int32_t n = S.n;
+  if (block <= 0 || block >= n) return first_pass_split(S, threads);
+  const int nthreads = std::max(1, threads);
+  const int64_t nblocks = ((int64_t)n + block - 1) / block;
+  std::vector<int32_t> cf(n, 0);
+  // step 1: the blocks are independent
+  parallel_for(nthreads, nblocks, [&](int64_t b0, int64_t b1, int) {
+    Csr sub;
+    for (int64_t b = b0; b < b1; ++b) {
+      const int32_t lo = (int32_t)(b * block), hi = (int32_t)std::min<int64_t>(n, (b + 1) * (int64_t)block);
+      sub.n = sub.m = hi - lo;
+      sub.rp.assign(sub.n + 1, 0);
+      sub.ci.clear();
+      for (int32_t i = lo; i < hi; ++i) {
+        for (int64_t a = S.rp[i]; a < S.rp[i + 1]; ++a)
+          if (S.ci[a] >= lo && S.ci[a] < hi) sub.ci.push_back(S.ci[a] - lo);
+        sub.rp[i - lo + 1] = (int64_t)sub.ci.size();
+      }
+      const std::vector<int32_t> bcf = first_pass_split(sub, 1);
+      for (int32_t i = lo; i < hi; ++i) cf[i] = bcf[i - lo] == 1 ? 1 : 0;
+    }
+  });
+  // step 2: marks first, then applied, so every scan sees the C points only
+  std::vector<uint8_t> dep_c(n, 0);
+  parallel_for(nthreads, n, [&](int64_t lo, int64_t hi, int) {
+    for (int64_t i = lo; i < hi; ++i) {
+      if (cf[i] == 1) continue;
+      for (int64_t a = S.rp[i]; a < S.rp[i + 1]; ++a)
+        if (cf[S.ci[a]] == 1) {
+          dep_c[i] = 1;
+          break;
+        }
+    }
+  });
+  for (int32_t i = 0; i < n; ++i)
+    if (dep_c[i]) cf[i] = -1;
+  // step 3
+  std::vector<int32_t> und;
+  for (int32_t i = 0; i < n; ++i)
+    if (cf[i] == 0) und.push_back(i);
+  if (und.empty()) return cf;
+  const Csr St = transpose(S, nthreads);
+  std::vector<int64_t> cnt(n, 0);
+  for (int32_t i : und)
+    for (int64_t a = St.rp[i]; a < St.rp[i + 1]; ++a) cnt[i] += cf[St.ci[a]] == 0;
+  std::vector<int32_t> rest;
+  for (int32_t i : und)
+    if (cnt[i] == 0)
+      cf[i] = -1;
+    else
+      rest.push_back(i);
+  std::vector<int32_t> fresh;
+  std::vector<uint8_t> is_new(n, 0);
+  while (!rest.empty()) {
+    fresh.clear();
+    for (int32_t i : rest) {
+      bool top = true;
+      for (int64_t a = S.rp[i]; a < S.rp[i + 1] && top; ++a)
+        if (cf[S.ci[a]] == 0 && beats(cnt[S.ci[a]], S.ci[a], cnt[i], i)) top = false;
+      for (int64_t a = St.rp[i]; a < St.rp[i + 1] && top; ++a)
+        if (cf[St.ci[a]] == 0 && beats(cnt[St.ci[a]], St.ci[a], cnt[i], i)) top = false;
+      if (top) fresh.push_back(i);
+    }
+    for (int32_t i : fresh) {
+      cf[i] = 1;
+      is_new[i] = 1;
+    }
+    std::vector<int32_t> next;
+    for (int32_t i : rest) {
+      if (cf[i] != 0) continue;
+      bool dep = false;
+      for (int64_t a = S.rp[i]; a < S.rp[i + 1] && !dep; ++a) dep = is_new[S.ci[a]] != 0;
+      if (dep)
+        cf[i] = -1;
+      else
+        next.push_back(i);
+    }
+    for (int32_t i : fresh) is_new[i] = 0;
+    rest.swap(next);
+  }
+  return cf;
+}
+
+// ---------------------------------------------------------------------------
 // Aggressive coarsening (the "aggregate level" of Sec. 3.1).  Among the C
 // points of a first pass, C point j is a distance-two strong dependency of C
 // point i when i depends strongly on j directly or through one intermediate
@@ -363,10 +476,10 @@ Csr distance_two_strength(const Csr& S, const std::vector<int32_t>& cf, int thre
   return S2;
 }
 
-std::vector<int32_t> aggressive_split(const Csr& S, int threads) {
-  std::vector<int32_t> cf1 = first_pass_split(S, threads);
+std::vector<int32_t> aggressive_split(const Csr& S, int32_t block, int threads) {
+  std::vector<int32_t> cf1 = hmis_split(S, block, threads);
   const Csr S2 = distance_two_strength(S, cf1, threads);
-  const std::vector<int32_t> cf2 = first_pass_split(S2, threads);
+  const std::vector<int32_t> cf2 = hmis_split(S2, block, threads);
   std::vector<int32_t> cf(S.n, -1);
   for (int32_t i = 0, c = 0; i < S.n; ++i)
     if (cf1[i] == 1) cf[i] = cf2[c++] == 1 ? 1 : -1;
@@ -928,7 +1041,8 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
       S = strength_graph(A, h.lev[l].func, prm.theta, prm.max_row_sum, threads);
     mark(kStepStrength);
     const bool agg = (int)l < prm.agg_levels;
-    std::vector<int32_t> cf = agg ? aggressive_split(S, threads) : first_pass_split(S, threads);
+    std::vector<int32_t> cf = agg ? aggressive_split(S, prm.hmis_block, threads)
+                                  : hmis_split(S, prm.hmis_block, threads);
     mark(kStepSplit);
     int32_t nc = 0;
     for (auto x : cf) nc += x == 1;

@@ -80,6 +80,7 @@ struct SetupParams {
   bool quasi_impes = true;
   int threads = 1;
   int max_dense_coarse = 4096;  // largest coarsest level solved by dense LU
+  int32_t hmis_block = 0;       // points per HMIS block, 0 = one block per level
   bool skip_ilu = false;        // ILU(0) is factored elsewhere (on the device)
   // the steps of the level with operator A done elsewhere (null: all here):
   // strength, extended+i interpolation and the Galerkin product
@@ -131,7 +132,9 @@ std::vector<int32_t> first_pass_split(const Csr& S, int threads = 1);
 Csr extended_i_interp(const Csr& A, const Csr& S, const std::vector<int32_t>& cf,
                       const std::vector<int32_t>& func, int pmax, int threads);
 Csr distance_two_strength(const Csr& S, const std::vector<int32_t>& cf, int threads);
-std::vector<int32_t> aggressive_split(const Csr& S, int threads);
+std::vector<int32_t> aggressive_split(const Csr& S, int32_t block, int threads);
+// HMIS split over blocks of `block` consecutive points (<= 0: one block)
+std::vector<int32_t> hmis_split(const Csr& S, int32_t block, int threads);
 Csr multipass_interp(const Csr& A, const Csr& S, const std::vector<int32_t>& cf,
                      const std::vector<int32_t>& func, int threads);
 

@@ -37,6 +37,8 @@ def test_defaults_follow_the_paper():
     # one l1-Jacobi sweep on each side; the Krylov space of FGMRES(50) is
     # allocated at setup
     assert (o.num_sweeps, o.max_restart, o.flexible_space) == (1, 50, 1)
+    # one HMIS block per level: the first pass over the whole level
+    assert o.hmis_block == 0
 
 
 @pytest.mark.parametrize("case,agg", [("grid20x20x5", 1), ("grid6x5x4", 1), ("grid12x1x1", 1),
@@ -144,9 +146,30 @@ def test_invalid_arguments():
     assert "diagonal" in msg and "4" in msg
     for kw, word in [(dict(num_sweeps=0), "num_sweeps"), (dict(num_sweeps=9), "num_sweeps"),
                      (dict(max_restart=0), "max_restart"), (dict(max_restart=65), "max_restart"),
-                     (dict(flexible_space=2), "flexible_space")]:
+                     (dict(flexible_space=2), "flexible_space"), (dict(hmis_block=-1), "range")]:
         msg = _expect(L.CPTR_E_INVALID, lambda: L.Solver(c.row_ptr, c.col_idx, c.values, host_only=1, **kw))
         assert word in msg, msg
+
+
+@pytest.mark.parametrize("case,agg,block", [("grid100x100x20_pe0.1", 1, 4096), ("grid100x100x20_pe0.1", 0, 4096),
+                                            ("grid20x20x5", 1, 1), ("prism2000x5", 1, 512),
+                                            ("prism2000x5", 0, 64), ("grid40x40x10", 1, 1000)])
+def test_host_hmis_split_matches_oracle(case, agg, block):
+    """HMIS over row blocks: the library's host split (blocks in parallel,
+    then the PMIS rounds) equals the oracle's on every level, and so do the
+    interpolation and the coarse operators built on it."""
+    c = J.by_name(case)
+    h = O.Cptr(c.row_ptr, c.col_idx, c.values, agg_levels=agg, hmis_block=block)
+    s = host_solver(c, agg_levels=agg, hmis_block=block)
+    rows, _ = s.hierarchy()
+    a = h.amg
+    assert len(rows) == a.nlevels
+    for l in range(a.nlevels - 1):
+        assert np.array_equal(s.cf(l), a.cf(l)), f"C/F split differs at level {l}"
+        Pl, Po = s.level_matrix(l, "P"), a.P(l)
+        assert np.array_equal(Pl.indices, Po.indices) and np.array_equal(Pl.data, Po.data), l
+    Al, Ao = s.level_matrix(a.nlevels - 1, "A"), a.A(a.nlevels - 1)
+    assert np.array_equal(Al.data, Ao.data)
 
 
 def test_zero_pivot_errors():
