@@ -266,12 +266,18 @@ enum {
                                   C/F splits, interpolations (with R = P^T), Galerkin products,
                                   l1 diagonals and coarsest LU, host ILU(0) and sweep levels,
                                   then the device half and the whole cptr_setup */
-  CPTR_EXPORT_SETUP_SITES = 12 /* int32[6]: strength graphs formed on the device and in total,
+  CPTR_EXPORT_SETUP_SITES = 12 /* int32[10]: strength graphs formed on the device and in total,
                                   extended+i interpolations on the device and in total,
-                                  coarse operators R A P on the device and in total.  A device
-                                  handle forms a product on the host only when a row of it has
-                                  more than 2048 products, an interpolation only when a row's
-                                  interpolatory set has more than 64 points */
+                                  coarse operators R A P on the device and in total, multipass
+                                  interpolations (aggressive levels) on the device and in total,
+                                  distance-two strength graphs (aggressive levels) on the device
+                                  and in total.
+                                  A device handle forms a product on the host only when a row of
+                                  it has more than 2048 products, an extended+i interpolation
+                                  only when a row's interpolatory set has more than 64 points, a
+                                  multipass interpolation only when a row has more than 64
+                                  interpolating points or 2048 products, a distance-two graph
+                                  only when a row has more than 2048 candidates */
 };
 /* Copy one piece of the setup into host_buf (bytes = its capacity). */
 cptr_status cptr_export(cptr_solver s, int32_t what, int32_t level, void *host_buf, int64_t bytes);

@@ -135,7 +135,7 @@ struct PrecDev {
 
 // AMG construction steps a setup did on the device (levels)
 struct SetupSiteCounts {
-  int strength = 0, interp = 0, galerkin = 0;
+  int strength = 0, interp = 0, galerkin = 0, multipass = 0, strength2 = 0;
 };
 
 struct cptr_solver_s {
@@ -1079,6 +1079,129 @@ class DeviceLevelSteps : public LevelSteps {
     return true;
   }
 
+  // Distance-two strength of an aggressive level: candidates counted, rows
+  // counted, then written at their CSR places.
+  bool strength2(const Csr& S, const std::vector<int32_t>& cf, Csr& S2) override {
+    if (!ok_) return false;
+    const int32_t n = A_.n;
+    if (!have_s_ && !upload_pattern(S, s_)) return fail();
+    have_s_ = true;
+    std::vector<int32_t> cidx((size_t)n, -1), cpts;
+    for (int32_t i = 0; i < n; ++i)
+      if (cf[i] == 1) {
+        cidx[i] = (int32_t)cpts.size();
+        cpts.push_back(i);
+      }
+    const int32_t nc = (int32_t)cpts.size();
+    int32_t *dcpts = nullptr, *dcidx = nullptr, *bound = nullptr, *cnt = nullptr;
+    if (!put(dcpts, cpts.data(), nc) || !put(dcidx, cidx.data(), n) || !alloc(bound, nc) || !alloc(cnt, nc))
+      return fail();
+    launch_s2_bound(nc, dcpts, s_.rp, s_.ci, bound, st_);
+    std::vector<int32_t> h((size_t)nc);
+    if (!get(h.data(), bound, nc)) return fail();
+    for (int32_t r = 0; r < nc; ++r)
+      if (h[r] > s2_row_cap()) return false;
+    launch_s2_rows(nc, dcpts, s_.rp, s_.ci, dcidx, nullptr, nullptr, cnt, st_);
+    if (!get(h.data(), cnt, nc)) return fail();
+    std::vector<int32_t> rp((size_t)nc + 1, 0);
+    for (int32_t r = 0; r < nc; ++r) {
+      if ((int64_t)rp[r] + h[r] >= INT32_MAX) return false;
+      rp[r + 1] = rp[r] + h[r];
+    }
+    int32_t *drp = nullptr, *dci = nullptr;
+    if (!put(drp, rp.data(), (int64_t)nc + 1) || !alloc(dci, rp[nc])) return fail();
+    launch_s2_rows(nc, dcpts, s_.rp, s_.ci, dcidx, drp, dci, nullptr, st_);
+    S2.n = S2.m = nc;
+    S2.rp.assign(rp.begin(), rp.end());
+    S2.ci.resize(rp[nc]);
+    S2.v.clear();
+    if (!get(S2.ci.data(), dci, rp[nc])) return fail();
+    ++done_.strength2;
+    return true;
+  }
+
+  // Multipass interpolation of an aggressive level, pass by pass: the rows of
+  // a pass are those without interpolation next to a point with one; their
+  // coefficients and products come from the kernels, the row pointers of each
+  // next P from here.
+  bool multipass(const Csr& S, const std::vector<int32_t>& cf, const std::vector<int32_t>& func,
+                 Csr& P) override {
+    if (!ok_) return false;
+    const int32_t n = A_.n;
+    if (!have_s_ && !upload_pattern(S, s_)) return fail();
+    have_s_ = true;
+    std::vector<int32_t> pass((size_t)n), lens((size_t)n, 0), prp((size_t)n + 1, 0), pci;
+    int32_t nc = 0;
+    for (int32_t i = 0; i < n; ++i) {
+      pass[i] = cf[i] == 1 ? 0 : -1;
+      if (cf[i] == 1) {
+        lens[i] = 1;
+        pci.push_back(nc++);
+      }
+      prp[i + 1] = prp[i] + lens[i];
+    }
+    const std::vector<double> pv(pci.size(), 1.0);
+    int32_t *dpass = nullptr, *dfunc = nullptr, *drp = nullptr, *dci = nullptr, *rowpos = nullptr;
+    double* dv = nullptr;
+    int8_t* flag = nullptr;
+    if (!put(dpass, pass.data(), n) || !put(dfunc, func.data(), n) || !put(drp, prp.data(), (int64_t)n + 1) ||
+        !put(dci, pci.data(), nc) || !put(dv, pv.data(), nc) || !alloc(flag, n) || !alloc(rowpos, n))
+      return fail();
+    launch_fill_i32(n, rowpos, -1, st_);
+    std::vector<int8_t> hflag((size_t)n);
+    std::vector<int32_t> now;
+    for (int pass_no = 1;; ++pass_no) {
+      launch_mp_mark(n, s_.rp, s_.ci, dpass, flag, st_);
+      if (!get(hflag.data(), flag, n)) return fail();
+      now.clear();
+      for (int32_t i = 0; i < n; ++i)
+        if (hflag[i]) now.push_back(i);
+      if (now.empty()) break;
+      const int32_t m = (int32_t)now.size();
+      int32_t *dnow = nullptr, *bound = nullptr, *cnt = nullptr, *ocol = nullptr;
+      int64_t* doff = nullptr;
+      double* oval = nullptr;
+      if (!put(dnow, now.data(), m) || !alloc(bound, m)) return fail();
+      launch_mp_bound(m, dnow, a_.rp, a_.ci, a_.v, s_.rp, s_.ci, dpass, dfunc, drp, bound, st_);
+      std::vector<int32_t> hb((size_t)m);
+      if (!get(hb.data(), bound, m)) return fail();
+      std::vector<int64_t> off((size_t)m + 1, 0);
+      for (int32_t r = 0; r < m; ++r) {
+        if (hb[r] < 0 || hb[r] > spgemm_row_cap()) return false;
+        off[r + 1] = off[r] + hb[r];
+      }
+      if (!put(doff, off.data(), (int64_t)m + 1) || !alloc(ocol, off[m]) || !alloc(oval, off[m]) || !alloc(cnt, m))
+        return fail();
+      launch_mp_rows(m, dnow, a_.rp, a_.ci, a_.v, s_.rp, s_.ci, dpass, dfunc, drp, dci, dv, doff, ocol, oval, cnt,
+                     st_);
+      std::vector<int32_t> hc((size_t)m);
+      if (!get(hc.data(), cnt, m)) return fail();
+      for (int32_t r = 0; r < m; ++r) lens[now[r]] = hc[r];
+      int64_t total = 0;
+      for (int32_t i = 0; i < n; ++i) {
+        prp[i] = (int32_t)total;
+        total += lens[i];
+        if (total >= INT32_MAX) return false;
+      }
+      prp[n] = (int32_t)total;
+      int32_t *nrp = nullptr, *nci = nullptr;
+      double* nv = nullptr;
+      if (!put(nrp, prp.data(), (int64_t)n + 1) || !alloc(nci, total) || !alloc(nv, total)) return fail();
+      launch_mp_merge(n, pass_no, rowpos, dnow, m, doff, ocol, oval, drp, dci, dv, nrp, nci, nv, dpass, st_);
+      drp = nrp;
+      dci = nci;
+      dv = nv;
+    }
+    P.n = n;
+    P.m = nc;
+    P.rp.assign(prp.begin(), prp.end());
+    P.ci.resize(prp[n]);
+    P.v.resize(prp[n]);
+    if (!get(P.ci.data(), dci, prp[n]) || !get(P.v.data(), dv, prp[n])) return fail();
+    ++done_.multipass;
+    return true;
+  }
+
   // C = R (A P) in the host product's order
   bool galerkin(const Csr& R, const Csr& P, Csr& C) override {
     if (!ok_) return false;
@@ -1860,9 +1983,11 @@ cptr_status cptr_export(cptr_solver s, int32_t what, int32_t level, void* buf, i
     }
     case CPTR_EXPORT_SETUP_SITES: {
       const int32_t built = (int32_t)h.lev.size() - 1;
-      int32_t v[6] = {s->device_steps.strength, built, s->device_steps.interp,
-                      std::max(0, built - s->agg_levels_used), s->device_steps.galerkin, built};
-      return put(v, 24);
+      const int32_t agg = std::min(built, s->agg_levels_used);
+      int32_t v[10] = {s->device_steps.strength, built, s->device_steps.interp,
+                       std::max(0, built - s->agg_levels_used), s->device_steps.galerkin, built,
+                       s->device_steps.multipass, agg, s->device_steps.strength2, agg};
+      return put(v, 40);
     }
     default:
       return (cptr_status)fail(s, CPTR_E_INVALID, "unknown export item");

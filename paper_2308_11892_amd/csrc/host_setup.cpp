@@ -1041,16 +1041,26 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
       S = strength_graph(A, h.lev[l].func, prm.theta, prm.max_row_sum, threads);
     mark(kStepStrength);
     const bool agg = (int)l < prm.agg_levels;
-    std::vector<int32_t> cf = agg ? aggressive_split(S, prm.hmis_block, threads)
-                                  : hmis_split(S, prm.hmis_block, threads);
+    std::vector<int32_t> cf;
+    if (agg) {  // aggressive_split, with the distance-two graph formed where dev says
+      std::vector<int32_t> cf1 = hmis_split(S, prm.hmis_block, threads);
+      Csr S2;
+      if (!dev || !dev->strength2(S, cf1, S2)) S2 = distance_two_strength(S, cf1, threads);
+      const std::vector<int32_t> cf2 = hmis_split(S2, prm.hmis_block, threads);
+      cf.assign(S.n, -1);
+      for (int32_t i = 0, c = 0; i < S.n; ++i)
+        if (cf1[i] == 1) cf[i] = cf2[c++] == 1 ? 1 : -1;
+    } else {
+      cf = hmis_split(S, prm.hmis_block, threads);
+    }
     mark(kStepSplit);
     int32_t nc = 0;
     for (auto x : cf) nc += x == 1;
     if (nc == 0 || nc == A.n) break;
     Csr P;
-    if (agg)
-      P = multipass_interp(A, S, cf, h.lev[l].func, threads);
-    else if (!dev || !dev->interp(S, cf, h.lev[l].func, prm.pmax, P))
+    if (agg) {
+      if (!dev || !dev->multipass(S, cf, h.lev[l].func, P)) P = multipass_interp(A, S, cf, h.lev[l].func, threads);
+    } else if (!dev || !dev->interp(S, cf, h.lev[l].func, prm.pmax, P))
       P = extended_i_interp(A, S, cf, h.lev[l].func, prm.pmax, threads);
     Csr R = transpose(P, threads);
     mark(kStepInterp);

@@ -68,6 +68,17 @@ struct LevelSteps {
   virtual bool interp(const Csr& S, const std::vector<int32_t>& cf, const std::vector<int32_t>& func, int pmax,
                       Csr& P) = 0;
   virtual bool galerkin(const Csr& R, const Csr& P, Csr& C) = 0;
+  // distance-two strength among the C points of cf (aggressive level)
+  virtual bool strength2(const Csr& S, const std::vector<int32_t>& cf, Csr& S2) {
+    (void)S, (void)cf, (void)S2;
+    return false;
+  }
+  // multipass interpolation of an aggressive level
+  virtual bool multipass(const Csr& S, const std::vector<int32_t>& cf, const std::vector<int32_t>& func,
+                         Csr& P) {
+    (void)S, (void)cf, (void)func, (void)P;
+    return false;
+  }
 };
 
 struct SetupParams {
@@ -83,7 +94,7 @@ struct SetupParams {
   int32_t hmis_block = 0;       // points per HMIS block, 0 = one block per level
   bool skip_ilu = false;        // ILU(0) is factored elsewhere (on the device)
   // the steps of the level with operator A done elsewhere (null: all here):
-  // strength, extended+i interpolation and the Galerkin product
+  // strength, extended+i or multipass interpolation and the Galerkin product
   std::function<std::unique_ptr<LevelSteps>(const Csr& A)> level_steps;
 };
 

@@ -2061,6 +2061,354 @@ void launch_spgemm_compact(int n, const int64_t* off, const int32_t* rp, const i
 }
 int spgemm_row_cap() { return kGemmCap; }
 
+// --------------------------------------------------------------------------
+// Multipass interpolation (Stueben 2001) of the aggressive level, one pass at
+// a time, each row in the host construction's order and rounding.  In row i,
+// "negative" means of sign opposite to a_ii, N_i are the same-type
+// off-diagonal entries and P_i the strong dependencies of i that already have
+// a row of P (pass[q] != -1): alpha = negative sum over N_i / negative sum
+// over P_i, d = a_ii + the non-negative rest of N_i, and c_q = -alpha a_iq / d
+// for q in P_i in A's column order; row i of P is the sum of c_q times row q
+// (entries from 0.0, terms in the order of q and of row q's entries), sorted
+// by column.  A row with d = 0 or a zero negative sum over P_i is empty.
+constexpr int kMpCap = 64;  // interpolating points per row
+
+__global__ __launch_bounds__(kBlock) void k_mp_mark(int n, const int32_t* __restrict__ srp,
+                                                    const int32_t* __restrict__ sci,
+                                                    const int32_t* __restrict__ pass, int8_t* __restrict__ flag) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int8_t f = 0;
+  if (pass[i] == -1)
+    for (int a = srp[i]; a < srp[i + 1]; ++a)
+      if (pass[sci[a]] != -1) {
+        f = 1;
+        break;
+      }
+  flag[i] = f;
+}
+
+// the interpolating points of row i and their coefficients, in A's column
+// order; visit(q, c) for each; returns their count (0 for an empty row)
+template <class Visit>
+__device__ int mp_coefs(int i, const int32_t* __restrict__ arp, const int32_t* __restrict__ aci,
+                        const double* __restrict__ av, const int32_t* __restrict__ srp,
+                        const int32_t* __restrict__ sci, const int32_t* __restrict__ pass,
+                        const int32_t* __restrict__ func, Visit visit) {
+#pragma clang fp contract(off)
+  const int b = arp[i], e = arp[i + 1], s0 = srp[i], s1 = srp[i + 1];
+  double aii = 0.0;
+  for (int k = b; k < e; ++k)
+    if (aci[k] == i) aii = av[k];
+  const int32_t fi = func[i];
+  // is column q in P_i?  walks row i of S (sorted) alongside A's sorted row
+  auto in_p = [&](int& sa, int32_t q) {
+    while (sa < s1 && sci[sa] < q) ++sa;
+    return sa < s1 && sci[sa] == q && pass[q] != -1;
+  };
+  double negn = 0.0, posn = 0.0, negp = 0.0;
+  int sa = s0;
+  for (int k = b; k < e; ++k) {
+    const int32_t j = aci[k];
+    if (j == i || func[j] != fi) continue;
+    const bool opp = aii < 0.0 ? av[k] > 0.0 : av[k] < 0.0;
+    if (opp)
+      negn = negn + av[k];
+    else
+      posn = posn + av[k];
+    if (opp && in_p(sa, j)) negp = negp + av[k];
+  }
+  const double d = aii + posn;
+  if (d == 0.0 || negp == 0.0) return 0;
+  const double alpha = negn / negp;
+  int cnt = 0;
+  sa = s0;
+  for (int k = b; k < e; ++k) {
+    const int32_t q = aci[k];
+    if (q == i || func[q] != fi || !in_p(sa, q)) continue;
+    visit(cnt++, q, -alpha * av[k] / d);
+  }
+  return cnt;
+}
+
+__global__ __launch_bounds__(kBlock) void k_mp_bound(int m, const int32_t* __restrict__ now,
+                                                     const int32_t* __restrict__ arp,
+                                                     const int32_t* __restrict__ aci,
+                                                     const double* __restrict__ av,
+                                                     const int32_t* __restrict__ srp,
+                                                     const int32_t* __restrict__ sci,
+                                                     const int32_t* __restrict__ pass,
+                                                     const int32_t* __restrict__ func,
+                                                     const int32_t* __restrict__ prp, int32_t* __restrict__ bound) {
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  if (r >= m) return;
+  int b = 0;
+  const int cnt = mp_coefs(now[r], arp, aci, av, srp, sci, pass, func,
+                           [&](int, int32_t q, double) { b += prp[q + 1] - prp[q]; });
+  bound[r] = cnt > kMpCap ? -1 : b;
+}
+
+// one 64-lane workgroup per row of the pass: the interpolating points and
+// coefficients into LDS (lane 0, in order), the products c_q p_qj expanded in
+// that order, sorted by (column, position), each run summed from its first
+// product on
+__global__ __launch_bounds__(64) void k_mp_rows(int m, const int32_t* __restrict__ now,
+                                                const int32_t* __restrict__ arp, const int32_t* __restrict__ aci,
+                                                const double* __restrict__ av, const int32_t* __restrict__ srp,
+                                                const int32_t* __restrict__ sci, const int32_t* __restrict__ pass,
+                                                const int32_t* __restrict__ func, const int32_t* __restrict__ prp,
+                                                const int32_t* __restrict__ pci, const double* __restrict__ pv,
+                                                const int64_t* __restrict__ off, int32_t* __restrict__ ocol,
+                                                double* __restrict__ oval, int32_t* __restrict__ cnt) {
+#pragma clang fp contract(off)
+  __shared__ long long key[kGemmCap];  // column * kGemmCap + position
+  __shared__ double val[kGemmCap];
+  __shared__ int32_t qs[kMpCap];
+  __shared__ double cs[kMpCap];
+  __shared__ int nq;
+  const int lane = threadIdx.x;
+  for (int r = blockIdx.x; r < m; r += gridDim.x) {
+    if (lane == 0)
+      nq = mp_coefs(now[r], arp, aci, av, srp, sci, pass, func, [&](int t, int32_t q, double c) {
+        if (t < kMpCap) {
+          qs[t] = q;
+          cs[t] = c;
+        }
+      });
+    __syncthreads();
+    const int nqr = min(nq, kMpCap);  // the bound kernel rejected longer sets
+    int len = 0, q = 0;
+    double c = 0.0;
+    if (lane < nqr) {
+      q = qs[lane];
+      c = cs[lane];
+      len = prp[q + 1] - prp[q];
+    }
+    int incl = len;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int t = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += t;
+    }
+    const int start = incl - len;
+    const int np_total = __shfl(incl, 63, 64);
+    const int total = min(np_total, kGemmCap);  // the bound kernel rejected larger rows
+    for (int p = 0; p < len && start + p < total; ++p) {
+      const int e = prp[q] + p;
+      key[start + p] = (long long)pci[e] * kGemmCap + (start + p);
+      val[start + p] = c * pv[e];
+    }
+    int np = 1;
+    while (np < total) np <<= 1;
+    for (int t = total + lane; t < np; t += 64) key[t] = LLONG_MAX;
+    __syncthreads();
+    for (int size = 2; size <= np; size <<= 1)
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int t = lane; t < np / 2; t += 64) {
+          const int a = 2 * t - (t & (stride - 1)), b = a + stride;
+          const bool up = (a & size) == 0;
+          const long long ka = key[a], kb = key[b];
+          if ((ka > kb) == up) {
+            key[a] = kb;
+            key[b] = ka;
+            const double va = val[a];
+            val[a] = val[b];
+            val[b] = va;
+          }
+        }
+        __syncthreads();
+      }
+    int runs = 0;
+    const int64_t o = off[r];
+    for (int t0 = 0; t0 < total; t0 += 64) {
+      const int t = t0 + lane;
+      long long col = -1;
+      bool first = false;
+      if (t < total) {
+        col = key[t] / kGemmCap;
+        first = t == 0 || key[t - 1] / kGemmCap != col;
+      }
+      const unsigned long long bal = __ballot(first);
+      if (first) {
+        double sum = 0.0;
+        for (int u = t; u < total && key[u] / kGemmCap == col; ++u) sum = sum + val[u];
+        const int w = runs + __popcll(bal & ((1ull << lane) - 1));
+        ocol[o + w] = (int32_t)col;
+        oval[o + w] = sum;
+      }
+      runs += __popcll(bal);
+    }
+    if (lane == 0) cnt[r] = runs;
+    __syncthreads();
+  }
+}
+
+// next P: the pass's rows from their padded places, every other row copied;
+// the pass's points get pass number pass_no and their rowpos is reset
+__global__ __launch_bounds__(kBlock) void k_mp_merge(int n, int pass_no, int32_t* __restrict__ rowpos,
+                                                     const int64_t* __restrict__ off,
+                                                     const int32_t* __restrict__ ocol,
+                                                     const double* __restrict__ oval,
+                                                     const int32_t* __restrict__ prp,
+                                                     const int32_t* __restrict__ pci,
+                                                     const double* __restrict__ pv,
+                                                     const int32_t* __restrict__ nrp, int32_t* __restrict__ nci,
+                                                     double* __restrict__ nv, int32_t* __restrict__ pass) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int r = rowpos[i];
+  const int o = nrp[i], len = nrp[i + 1] - nrp[i];
+  if (r >= 0) {
+    for (int t = 0; t < len; ++t) {
+      nci[o + t] = ocol[off[r] + t];
+      nv[o + t] = oval[off[r] + t];
+    }
+    pass[i] = pass_no;
+    rowpos[i] = -1;
+  } else {
+    for (int t = 0; t < len; ++t) {
+      nci[o + t] = pci[prp[i] + t];
+      nv[o + t] = pv[prp[i] + t];
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_mp_scatter(int m, const int32_t* __restrict__ now,
+                                                       int32_t* __restrict__ rowpos) {
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  if (r < m) rowpos[now[r]] = r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_i32(int64_t n, int32_t* __restrict__ x, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+void launch_mp_mark(int n, const int32_t* srp, const int32_t* sci, const int32_t* pass, int8_t* flag,
+                    hipStream_t st) {
+  if (n > 0) k_mp_mark<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, srp, sci, pass, flag);
+}
+void launch_mp_bound(int m, const int32_t* now, const int32_t* arp, const int32_t* aci, const double* av,
+                     const int32_t* srp, const int32_t* sci, const int32_t* pass, const int32_t* func,
+                     const int32_t* prp, int32_t* bound, hipStream_t st) {
+  if (m > 0) k_mp_bound<<<nblocks(m, kBlock), kBlock, 0, st>>>(m, now, arp, aci, av, srp, sci, pass, func, prp, bound);
+}
+void launch_mp_rows(int m, const int32_t* now, const int32_t* arp, const int32_t* aci, const double* av,
+                    const int32_t* srp, const int32_t* sci, const int32_t* pass, const int32_t* func,
+                    const int32_t* prp, const int32_t* pci, const double* pv, const int64_t* off, int32_t* ocol,
+                    double* oval, int32_t* cnt, hipStream_t st) {
+  if (m > 0)
+    k_mp_rows<<<std::min(m, 8192), 64, 0, st>>>(m, now, arp, aci, av, srp, sci, pass, func, prp, pci, pv, off, ocol,
+                                                oval, cnt);
+}
+void launch_mp_merge(int n, int pass_no, int32_t* rowpos, const int32_t* now, int m, const int64_t* off,
+                     const int32_t* ocol, const double* oval, const int32_t* prp, const int32_t* pci,
+                     const double* pv, const int32_t* nrp, int32_t* nci, double* nv, int32_t* pass,
+                     hipStream_t st) {
+  if (m > 0) k_mp_scatter<<<nblocks(m, kBlock), kBlock, 0, st>>>(m, now, rowpos);
+  if (n > 0)
+    k_mp_merge<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, pass_no, rowpos, off, ocol, oval, prp, pci, pv, nrp, nci,
+                                                      nv, pass);
+}
+void launch_fill_i32(int64_t n, int32_t* x, int32_t v, hipStream_t st) {
+  if (n > 0) k_fill_i32<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, x, v);
+}
+int mp_point_cap() { return kMpCap; }
+
+// --------------------------------------------------------------------------
+// Distance-two strength among the C points of a first pass (the aggressive
+// level): row r is C point i = cpts[r]; its columns are the coarse indices of
+// the C points j != i reached from i by one strong link (j in S_i) or two
+// (j in S_k, k in S_i), sorted, each once.  One 64-lane workgroup per row:
+// the candidates go to LDS, are sorted and the first of each run is kept.
+// bound[r] = 1 + |S_k| summed over k in S_i (at most s2_row_cap()); a first
+// launch with rp == nullptr counts the columns into cnt, a second writes them
+// at rp[r].
+constexpr int kS2Cap = 2048;
+
+__global__ __launch_bounds__(kBlock) void k_s2_bound(int nc, const int32_t* __restrict__ cpts,
+                                                     const int32_t* __restrict__ srp,
+                                                     const int32_t* __restrict__ sci, int32_t* __restrict__ bound) {
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  if (r >= nc) return;
+  const int i = cpts[r];
+  int b = 0;
+  for (int a = srp[i]; a < srp[i + 1]; ++a) b += 1 + srp[sci[a] + 1] - srp[sci[a]];
+  bound[r] = b;
+}
+
+__global__ __launch_bounds__(64) void k_s2_rows(int nc, const int32_t* __restrict__ cpts,
+                                                const int32_t* __restrict__ srp, const int32_t* __restrict__ sci,
+                                                const int32_t* __restrict__ cidx, const int32_t* __restrict__ rp,
+                                                int32_t* __restrict__ ci, int32_t* __restrict__ cnt) {
+  __shared__ int32_t key[kS2Cap];
+  const int lane = threadIdx.x;
+  for (int r = blockIdx.x; r < nc; r += gridDim.x) {
+    const int i = cpts[r], a0 = srp[i], a1 = srp[i + 1];
+    int m = 0;  // candidates so far
+    for (int ab = a0; ab < a1; ab += 64) {
+      const int a = ab + lane;
+      int k = 0, len = 0;
+      if (a < a1) {
+        k = sci[a];
+        len = 1 + srp[k + 1] - srp[k];
+      }
+      int incl = len;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += t;
+      }
+      const int start = m + incl - len;
+      for (int p = 0; p < len && start + p < kS2Cap; ++p) {
+        const int j = p == 0 ? k : sci[srp[k] + p - 1];
+        const int c = j == i ? -1 : cidx[j];  // -1: not a C point, or i itself
+        key[start + p] = c < 0 ? INT_MAX : c;
+      }
+      m += __shfl(incl, 63, 64);
+    }
+    m = min(m, kS2Cap);  // the host rejects rows with more candidates
+    int np = 1;
+    while (np < m) np <<= 1;
+    for (int t = m + lane; t < np; t += 64) key[t] = INT_MAX;
+    __syncthreads();
+    for (int size = 2; size <= np; size <<= 1)
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int t = lane; t < np / 2; t += 64) {
+          const int a = 2 * t - (t & (stride - 1)), b = a + stride;
+          const bool up = (a & size) == 0;
+          const int ka = key[a], kb = key[b];
+          if ((ka > kb) == up) {
+            key[a] = kb;
+            key[b] = ka;
+          }
+        }
+        __syncthreads();
+      }
+    int runs = 0;
+    for (int t0 = 0; t0 < m; t0 += 64) {
+      const int t = t0 + lane;
+      const int c = t < m ? key[t] : INT_MAX;
+      const bool first = c != INT_MAX && (t == 0 || key[t - 1] != c);
+      const unsigned long long bal = __ballot(first);
+      if (first && rp) ci[rp[r] + runs + __popcll(bal & ((1ull << lane) - 1))] = c;
+      runs += __popcll(bal);
+    }
+    if (lane == 0 && !rp) cnt[r] = runs;
+    __syncthreads();
+  }
+}
+
+void launch_s2_bound(int nc, const int32_t* cpts, const int32_t* srp, const int32_t* sci, int32_t* bound,
+                     hipStream_t st) {
+  if (nc > 0) k_s2_bound<<<nblocks(nc, kBlock), kBlock, 0, st>>>(nc, cpts, srp, sci, bound);
+}
+void launch_s2_rows(int nc, const int32_t* cpts, const int32_t* srp, const int32_t* sci, const int32_t* cidx,
+                    const int32_t* rp, int32_t* ci, int32_t* cnt, hipStream_t st) {
+  if (nc > 0) k_s2_rows<<<std::min(nc, 8192), 64, 0, st>>>(nc, cpts, srp, sci, cidx, rp, ci, cnt);
+}
+int s2_row_cap() { return kS2Cap; }
+
 // Block ILU(0) of any block-sparse A (Sec. 3.1) on W, a copy of A's SELL-64
 // values: one launch per forward dependency level, one thread per row, each
 // row in the host factorisation's order: for its lower blocks in column

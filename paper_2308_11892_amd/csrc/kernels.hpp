@@ -171,6 +171,45 @@ void launch_spgemm_rows(int n, const int32_t* xrp, const int32_t* xci, const dou
 void launch_spgemm_compact(int n, const int64_t* off, const int32_t* rp, const int32_t* ocol, const double* oval,
                            int32_t* ci, double* v, hipStream_t st);
 int spgemm_row_cap();
+// Multipass interpolation (Stueben 2001) of an aggressive AMG level, one pass
+// at a time, rows in the host construction's order and rounding (scalar CSR
+// A and strength pattern S, int32; func: unknown type per row).  pass[i]: 0
+// for C points, the pass that gave row i of P, -1 while it has none; P is CSR
+// over all rows.  launch_mp_mark: flag[i] = 1 when i has no row and a strong
+// dependency of i has one.  For the pass's rows now[0..m): launch_mp_bound
+// gives bound[r], the products of row now[r] (or -1 when it has more than
+// mp_point_cap() interpolating points); with off the exclusive prefix of
+// bound (every bound at most spgemm_row_cap()), launch_mp_rows writes row r
+// sorted by column at off[r] of ocol/oval and its length to cnt[r].
+// launch_mp_merge forms the next P (nrp: its row pointers) from P and the new
+// rows, sets the pass's points to pass number pass_no and leaves rowpos (n
+// entries, -1 outside a call) at -1.
+void launch_mp_mark(int n, const int32_t* srp, const int32_t* sci, const int32_t* pass, int8_t* flag,
+                    hipStream_t st);
+void launch_mp_bound(int m, const int32_t* now, const int32_t* arp, const int32_t* aci, const double* av,
+                     const int32_t* srp, const int32_t* sci, const int32_t* pass, const int32_t* func,
+                     const int32_t* prp, int32_t* bound, hipStream_t st);
+void launch_mp_rows(int m, const int32_t* now, const int32_t* arp, const int32_t* aci, const double* av,
+                    const int32_t* srp, const int32_t* sci, const int32_t* pass, const int32_t* func,
+                    const int32_t* prp, const int32_t* pci, const double* pv, const int64_t* off, int32_t* ocol,
+                    double* oval, int32_t* cnt, hipStream_t st);
+void launch_mp_merge(int n, int pass_no, int32_t* rowpos, const int32_t* now, int m, const int64_t* off,
+                     const int32_t* ocol, const double* oval, const int32_t* prp, const int32_t* pci,
+                     const double* pv, const int32_t* nrp, int32_t* nci, double* nv, int32_t* pass,
+                     hipStream_t st);
+void launch_fill_i32(int64_t n, int32_t* x, int32_t v, hipStream_t st);
+int mp_point_cap();
+// Distance-two strength among the C points of a first pass (aggressive
+// level), as the host forms it: row r is C point cpts[r], its columns the
+// coarse indices (cidx, -1 for F points) of the other C points one or two
+// strong links away, sorted, each once.  bound[r]: candidates of row r (must
+// be at most s2_row_cap()); launch_s2_rows with rp == nullptr writes the
+// column counts to cnt, with rp (exclusive prefix of cnt) the columns to ci.
+void launch_s2_bound(int nc, const int32_t* cpts, const int32_t* srp, const int32_t* sci, int32_t* bound,
+                     hipStream_t st);
+void launch_s2_rows(int nc, const int32_t* cpts, const int32_t* srp, const int32_t* sci, const int32_t* cidx,
+                    const int32_t* rp, int32_t* ci, int32_t* cnt, hipStream_t st);
+int s2_row_cap();
 // Block ILU(0) of any block-sparse A on the device.  W: a copy of A's SELL-64
 // values, factored in place (L left of the diagonal, U on and right of it);
 // one launch_ilu_rows per forward dependency level (positions [p0, p1) of

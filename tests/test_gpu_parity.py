@@ -383,22 +383,25 @@ def test_setup_from_device_arrays(name):
     assert np.array_equal(outs[0], outs[1])
 
 
-@pytest.mark.parametrize("name,elliptic", [("grid20x20x5", (0, 1)), ("prism2000x5", (0, 1)),
-                                           ("grid30x20x6", (0,))])
-def test_device_setup_steps_equal_host(name, elliptic):
-    """A device handle forms every strength graph, every extended+i
-    interpolation and every coarse operator R A P on the GPU; the hierarchy
-    equals the host's bit for bit (same splits, patterns and values on every
-    level)."""
+@pytest.mark.parametrize("name,elliptic,agg", [("grid20x20x5", (0, 1), 1), ("prism2000x5", (0, 1), 1),
+                                               ("grid30x20x6", (0,), 1), ("grid100x100x20", (0, 1), 1),
+                                               ("prism2000x5", (0, 1), 2), ("grid20x20x5", (0, 1), 0)])
+def test_device_setup_steps_equal_host(name, elliptic, agg):
+    """A device handle forms every strength graph, every interpolation
+    (extended+i, and multipass on the aggressive levels) and every coarse
+    operator R A P on the GPU; the hierarchy equals the host's bit for bit
+    (same splits, patterns and values on every level)."""
     c = J.by_name(name)
-    with L.Solver(c.row_ptr, c.col_idx, c.values, elliptic=elliptic) as sd, \
-            L.Solver(c.row_ptr, c.col_idx, c.values, elliptic=elliptic, host_only=1) as sh:
+    say(f"[device setup] {name} elliptic={elliptic} agg_levels={agg}")
+    with L.Solver(c.row_ptr, c.col_idx, c.values, elliptic=elliptic, agg_levels=agg) as sd, \
+            L.Solver(c.row_ptr, c.col_idx, c.values, elliptic=elliptic, host_only=1, agg_levels=agg) as sh:
         rows_d, nnz_d = sd.hierarchy()
         rows_h, nnz_h = sh.hierarchy()
         assert np.array_equal(rows_d, rows_h) and np.array_equal(nnz_d, nnz_h)
-        sites = sd.export("SETUP_SITES", 0, 6, np.int32)
+        sites = sd.export("SETUP_SITES", 0, 10, np.int32)
         built = len(rows_d) - 1
-        assert list(sites) == [built, built, built - 1, built - 1, built, built], sites
+        na = min(agg, built)
+        assert list(sites) == [built, built, built - na, built - na, built, built, na, na, na, na], sites
         for l in range(len(rows_d)):
             for which in ("A", "P") if l + 1 < len(rows_d) else ("A",):
                 Md, Mh = sd.level_matrix(l, which), sh.level_matrix(l, which)

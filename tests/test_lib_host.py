@@ -199,8 +199,9 @@ def test_host_only_handle_forms_products_on_the_host():
     c = J.small(8, 6, 4)
     s = host_solver(c)
     rows, _ = s.hierarchy()
-    sites = s.export("SETUP_SITES", 0, 6, np.int32)
-    assert list(sites) == [0, len(rows) - 1, 0, len(rows) - 2, 0, len(rows) - 1]  # one aggressive level
+    sites = s.export("SETUP_SITES", 0, 10, np.int32)
+    # one aggressive level
+    assert list(sites) == [0, len(rows) - 1, 0, len(rows) - 2, 0, len(rows) - 1, 0, 1, 0, 1]
 
 
 def test_coarsening_limit_reports_stall():
