@@ -136,6 +136,9 @@ struct PrecDev {
 // AMG construction steps a setup did on the device (levels)
 struct SetupSiteCounts {
   int strength = 0, interp = 0, galerkin = 0, multipass = 0, strength2 = 0;
+  int split = 0;              // first passes begun on the device
+  int64_t split_points = 0;   // points those decided on the device
+  int64_t first_points = 0;   // points of all first passes of a one-block split
 };
 
 struct cptr_solver_s {
@@ -1079,6 +1082,46 @@ class DeviceLevelSteps : public LevelSteps {
     return true;
   }
 
+  // The first pass over the components of at most kSmallComponent points:
+  // components and measures from the union-find kernels, the components
+  // picked here by size, their passes on the device (one thread each).
+  static constexpr int32_t kSmallComponent = 64;
+  bool first_pass_small(const Csr& G, bool second, std::vector<int32_t>& cf) override {
+    if (!ok_) return false;
+    if (second && !have_s2_) return false;
+    if (!second && !have_s_) {
+      if (!upload_pattern(G, s_)) return fail();
+      have_s_ = true;
+    }
+    const DevCsr& g = second ? s2_ : s_;
+    const int32_t n = G.n;
+    int32_t *parent = nullptr, *lam = nullptr, *root = nullptr, *size = nullptr, *dcf = nullptr;
+    if (!alloc(parent, n) || !alloc(lam, n) || !alloc(root, n) || !alloc(size, n) || !alloc(dcf, n)) return fail();
+    launch_fp_components(n, g.rp, g.ci, parent, lam, root, size, dcf, st_);
+    std::vector<int32_t> hs((size_t)n);
+    if (!get(hs.data(), size, n)) return fail();
+    std::vector<int32_t> cursor((size_t)n, -1), coff(1, 0);
+    for (int32_t r = 0; r < n; ++r)
+      if (hs[r] >= 2 && hs[r] <= kSmallComponent) {
+        cursor[r] = coff.back();
+        coff.push_back(coff.back() + hs[r]);
+      }
+    const int32_t ncomp = (int32_t)coff.size() - 1;
+    if (ncomp > 0) {
+      int32_t *dcur = nullptr, *dcoff = nullptr, *members = nullptr;
+      if (!put(dcur, cursor.data(), n) || !put(dcoff, coff.data(), (int64_t)ncomp + 1) ||
+          !alloc(members, coff.back()))
+        return fail();
+      launch_fp_small(n, root, dcur, members, ncomp, dcoff, g.rp, g.ci, lam, dcf, st_);
+    }
+    cf.resize(n);
+    if (!get(cf.data(), dcf, n)) return fail();
+    ++done_.split;
+    done_.split_points += coff.back();
+    done_.first_points += n;
+    return true;
+  }
+
   // Distance-two strength of an aggressive level: candidates counted, rows
   // counted, then written at their CSR places.
   bool strength2(const Csr& S, const std::vector<int32_t>& cf, Csr& S2) override {
@@ -1116,6 +1159,11 @@ class DeviceLevelSteps : public LevelSteps {
     S2.ci.resize(rp[nc]);
     S2.v.clear();
     if (!get(S2.ci.data(), dci, rp[nc])) return fail();
+    s2_.n = nc;
+    s2_.nnz = rp[nc];
+    s2_.rp = drp;
+    s2_.ci = dci;
+    have_s2_ = true;
     ++done_.strength2;
     return true;
   }
@@ -1301,8 +1349,8 @@ class DeviceLevelSteps : public LevelSteps {
   SetupSiteCounts& done_;
   hipStream_t st_ = nullptr;
   bool ok_ = false;
-  DevCsr a_, s_;
-  bool have_s_ = false;
+  DevCsr a_, s_, s2_;
+  bool have_s_ = false, have_s2_ = false;
   std::vector<void*> mem_;
 };
 
@@ -1984,10 +2032,12 @@ cptr_status cptr_export(cptr_solver s, int32_t what, int32_t level, void* buf, i
     case CPTR_EXPORT_SETUP_SITES: {
       const int32_t built = (int32_t)h.lev.size() - 1;
       const int32_t agg = std::min(built, s->agg_levels_used);
-      int32_t v[10] = {s->device_steps.strength, built, s->device_steps.interp,
-                       std::max(0, built - s->agg_levels_used), s->device_steps.galerkin, built,
-                       s->device_steps.multipass, agg, s->device_steps.strength2, agg};
-      return put(v, 40);
+      const SetupSiteCounts& d = s->device_steps;
+      const int32_t permille =
+          d.first_points > 0 ? (int32_t)(1000 * d.split_points / d.first_points) : 0;
+      int32_t v[13] = {d.strength, built, d.interp, std::max(0, built - s->agg_levels_used), d.galerkin, built,
+                       d.multipass, agg, d.strength2, agg, d.split, h.first_passes, permille};
+      return put(v, 52);
     }
     default:
       return (cptr_status)fail(s, CPTR_E_INVALID, "unknown export item");

@@ -272,17 +272,13 @@ struct BucketQueue {
 };
 }  // namespace
 
-std::vector<int32_t> first_pass_split(const Csr& S, int threads) {
+// The pass over the undecided points (cf 0) of S, given their measures; every
+// decided point must have no strong link to an undecided one.
+static void first_pass_run(const Csr& S, const Csr& St, std::vector<int32_t>& cf, std::vector<int64_t>& lam) {
   const int32_t n = S.n;
-  Csr St = transpose(S, threads);
-  std::vector<int32_t> cf(n, 0);
-  std::vector<int64_t> lam(n);
   BucketQueue queue(n);
-  for (int32_t i = 0; i < n; ++i) {
-    lam[i] = St.rp[i + 1] - St.rp[i];
-    if (lam[i] == 0 && S.rp[i + 1] == S.rp[i]) cf[i] = -1;
+  for (int32_t i = 0; i < n; ++i)
     if (cf[i] == 0) queue.set(i, lam[i]);
-  }
   auto refresh = [&](int32_t m) { queue.set(m, cf[m] == 0 ? lam[m] : -1); };
   for (;;) {
     const int32_t c = queue.pick();
@@ -312,6 +308,33 @@ std::vector<int32_t> first_pass_split(const Csr& S, int threads) {
   }
   for (auto& x : cf)
     if (x == 0) x = -1;
+}
+
+std::vector<int32_t> first_pass_split(const Csr& S, int threads) {
+  const int32_t n = S.n;
+  const Csr St = transpose(S, threads);
+  std::vector<int32_t> cf(n, 0);
+  std::vector<int64_t> lam(n);
+  for (int32_t i = 0; i < n; ++i) {
+    lam[i] = St.rp[i + 1] - St.rp[i];
+    if (lam[i] == 0 && S.rp[i + 1] == S.rp[i]) cf[i] = -1;
+  }
+  first_pass_run(S, St, cf, lam);
+  return cf;
+}
+
+// The pass leaves the weakly connected components of S independent (it reads
+// and changes only a pick's strong neighbours, and a component's picks come
+// in the order a pass over it alone takes them), so components already
+// passed elsewhere (cf +-1, as are points without links) are final; the rest
+// (cf 0) is passed here.
+std::vector<int32_t> first_pass_finish(const Csr& S, std::vector<int32_t> cf, int threads) {
+  const int32_t n = S.n;
+  if (std::find(cf.begin(), cf.end(), 0) == cf.end()) return cf;
+  const Csr St = transpose(S, threads);
+  std::vector<int64_t> lam(n);
+  for (int32_t i = 0; i < n; ++i) lam[i] = St.rp[i + 1] - St.rp[i];
+  first_pass_run(S, St, cf, lam);
   return cf;
 }
 
@@ -1041,17 +1064,28 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
       S = strength_graph(A, h.lev[l].func, prm.theta, prm.max_row_sum, threads);
     mark(kStepStrength);
     const bool agg = (int)l < prm.agg_levels;
+    // a first pass (one HMIS block) starts with dev's passes over the small
+    // components of the graph, when dev holds the graph (which: 0 = S, 1 =
+    // the distance-two graph it formed, -1 = neither)
+    auto split = [&](const Csr& G, int which) {
+      if (prm.hmis_block <= 0 || prm.hmis_block >= G.n) ++h.first_passes;
+      std::vector<int32_t> part;
+      if (prm.hmis_block <= 0 && dev && which >= 0 && dev->first_pass_small(G, which == 1, part))
+        return first_pass_finish(G, std::move(part), threads);
+      return hmis_split(G, prm.hmis_block, threads);
+    };
     std::vector<int32_t> cf;
     if (agg) {  // aggressive_split, with the distance-two graph formed where dev says
-      std::vector<int32_t> cf1 = hmis_split(S, prm.hmis_block, threads);
+      std::vector<int32_t> cf1 = split(S, 0);
       Csr S2;
-      if (!dev || !dev->strength2(S, cf1, S2)) S2 = distance_two_strength(S, cf1, threads);
-      const std::vector<int32_t> cf2 = hmis_split(S2, prm.hmis_block, threads);
+      const bool s2_dev = dev && dev->strength2(S, cf1, S2);
+      if (!s2_dev) S2 = distance_two_strength(S, cf1, threads);
+      const std::vector<int32_t> cf2 = split(S2, s2_dev ? 1 : -1);
       cf.assign(S.n, -1);
       for (int32_t i = 0, c = 0; i < S.n; ++i)
         if (cf1[i] == 1) cf[i] = cf2[c++] == 1 ? 1 : -1;
     } else {
-      cf = hmis_split(S, prm.hmis_block, threads);
+      cf = split(S, 0);
     }
     mark(kStepSplit);
     int32_t nc = 0;

@@ -68,6 +68,13 @@ struct LevelSteps {
   virtual bool interp(const Csr& S, const std::vector<int32_t>& cf, const std::vector<int32_t>& func, int pmax,
                       Csr& P) = 0;
   virtual bool galerkin(const Csr& R, const Csr& P, Csr& C) = 0;
+  // the first pass over the small weakly connected components of the level's
+  // strength graph S (second: of the distance-two graph strength2 formed):
+  // cf = 1 / -1 for their points and for points without links, 0 for the rest
+  virtual bool first_pass_small(const Csr& G, bool second, std::vector<int32_t>& cf) {
+    (void)G, (void)second, (void)cf;
+    return false;
+  }
   // distance-two strength among the C points of cf (aggressive level)
   virtual bool strength2(const Csr& S, const std::vector<int32_t>& cf, Csr& S2) {
     (void)S, (void)cf, (void)S2;
@@ -115,6 +122,7 @@ struct HostSetup {
   std::vector<double> uinv;    // [nb][3][3] inverse of each U_ii (both empty with skip_ilu)
   std::vector<int32_t> fwd_level, bwd_level;  // dependency level of each row
   int32_t n_fwd_levels = 0, n_bwd_levels = 0;
+  int first_passes = 0;         // one-block splits run (first passes over a whole graph)
   // wall seconds of the setup steps (kSetupStep*), summed over levels
   double step_s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
@@ -140,6 +148,8 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
 Csr strength_graph(const Csr& A, const std::vector<int32_t>& func, double theta, double mrs,
                    int threads);
 std::vector<int32_t> first_pass_split(const Csr& S, int threads = 1);
+// the first pass over the points with cf 0, the others being final
+std::vector<int32_t> first_pass_finish(const Csr& S, std::vector<int32_t> cf, int threads);
 Csr extended_i_interp(const Csr& A, const Csr& S, const std::vector<int32_t>& cf,
                       const std::vector<int32_t>& func, int pmax, int threads);
 Csr distance_two_strength(const Csr& S, const std::vector<int32_t>& cf, int threads);

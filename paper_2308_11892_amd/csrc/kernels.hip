@@ -2409,6 +2409,147 @@ void launch_s2_rows(int nc, const int32_t* cpts, const int32_t* srp, const int32
 }
 int s2_row_cap() { return kS2Cap; }
 
+// --------------------------------------------------------------------------
+// Ruge-Stueben first pass over the small weakly connected components of a
+// strength graph.  The pass reads and changes only the strong neighbours of a
+// pick, so components never interact, and the picks inside one component are
+// those of a pass over it alone, in the same order.  Components come from a
+// lock-free union-find (a root is hooked under a smaller root by
+// compare-and-swap, a failed swap retries from the value it found; paths are
+// halved on the way up), so every root is its component's smallest point.
+
+// parent[i] = i, lam[i] = 0, size[i] = 0
+__global__ __launch_bounds__(kBlock) void k_fp_init(int n, int32_t* __restrict__ parent, int32_t* __restrict__ lam,
+                                                    int32_t* __restrict__ size) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  parent[i] = i;
+  lam[i] = 0;
+  size[i] = 0;
+}
+
+__device__ __forceinline__ int32_t uf_load(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// the root of x, halving the path: each visited point is pointed at its
+// grandparent (still an ancestor, so concurrent hooks stay valid)
+__device__ int32_t uf_root(int32_t* parent, int32_t x) {
+  int32_t p = uf_load(&parent[x]);
+  while (p != x) {
+    const int32_t g = uf_load(&parent[p]);
+    if (g == p) return p;
+    __hip_atomic_store(&parent[x], g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    x = g;
+    p = uf_load(&parent[x]);
+  }
+  return x;
+}
+
+// every strong link i -> j: lam[j] += 1 (the points depending on j) and the
+// union of i's and j's sets
+__global__ __launch_bounds__(kBlock) void k_fp_links(int n, const int32_t* __restrict__ srp,
+                                                     const int32_t* __restrict__ sci, int32_t* parent,
+                                                     int32_t* __restrict__ lam) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  for (int a = srp[i]; a < srp[i + 1]; ++a) {
+    const int32_t j = sci[a];
+    atomicAdd(&lam[j], 1);
+    int32_t ri = uf_root(parent, i), rj = uf_root(parent, j);
+    while (ri != rj) {
+      if (ri < rj) {  // hook rj under ri
+        const int32_t seen = atomicCAS(&parent[rj], rj, ri);
+        if (seen == rj) break;
+        rj = uf_root(parent, seen);
+      } else {
+        const int32_t seen = atomicCAS(&parent[ri], ri, rj);
+        if (seen == ri) break;
+        ri = uf_root(parent, seen);
+      }
+    }
+  }
+}
+
+// root[i] and the component sizes; isolated points (no link either way) are
+// F, the rest undecided
+__global__ __launch_bounds__(kBlock) void k_fp_roots(int n, const int32_t* __restrict__ srp, int32_t* parent,
+                                                     const int32_t* __restrict__ lam, int32_t* __restrict__ root,
+                                                     int32_t* __restrict__ size, int32_t* __restrict__ cf) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int32_t r = uf_root(parent, i);
+  root[i] = r;
+  atomicAdd(&size[r], 1);
+  cf[i] = (srp[i + 1] == srp[i] && lam[i] == 0) ? -1 : 0;
+}
+
+// members of the components picked by the host: cursor[r] starts at the
+// component's offset (-1 for components not taken)
+__global__ __launch_bounds__(kBlock) void k_fp_members(int n, const int32_t* __restrict__ root,
+                                                       int32_t* __restrict__ cursor, int32_t* __restrict__ members) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int32_t r = root[i];
+  if (cursor[r] >= 0) members[atomicAdd(&cursor[r], 1)] = i;
+}
+
+// one thread per small component: the first pass over its members (picks by
+// scanning them: the largest measure >= 1, the smallest index on ties), with
+// the points depending on a pick found by scanning the members' rows
+__global__ __launch_bounds__(kBlock) void k_fp_small(int ncomp, const int32_t* __restrict__ coff,
+                                                     const int32_t* __restrict__ members,
+                                                     const int32_t* __restrict__ srp,
+                                                     const int32_t* __restrict__ sci, int32_t* __restrict__ lam,
+                                                     int32_t* __restrict__ cf) {
+  const int q = blockIdx.x * kBlock + threadIdx.x;
+  if (q >= ncomp) return;
+  const int32_t* mem = members + coff[q];
+  const int m = coff[q + 1] - coff[q];
+  for (;;) {
+    int32_t best = -1, bl = 0;
+    for (int t = 0; t < m; ++t) {
+      const int32_t i = mem[t];
+      if (cf[i] != 0) continue;
+      const int32_t l = lam[i];
+      if (l >= 1 && (best < 0 || l > bl || (l == bl && i < best))) {
+        best = i;
+        bl = l;
+      }
+    }
+    if (best < 0) break;
+    cf[best] = 1;
+    for (int t = 0; t < m; ++t) {  // the undecided points depending on best become F
+      const int32_t f = mem[t];
+      if (cf[f] != 0) continue;
+      bool dep = false;
+      for (int a = srp[f]; a < srp[f + 1] && !dep; ++a) dep = sci[a] == best;
+      if (!dep) continue;
+      cf[f] = -1;
+      for (int a = srp[f]; a < srp[f + 1]; ++a)
+        if (cf[sci[a]] == 0) ++lam[sci[a]];
+    }
+    for (int a = srp[best]; a < srp[best + 1]; ++a)
+      if (cf[sci[a]] == 0) --lam[sci[a]];
+  }
+  for (int t = 0; t < m; ++t)
+    if (cf[mem[t]] == 0) cf[mem[t]] = -1;
+}
+
+void launch_fp_components(int n, const int32_t* srp, const int32_t* sci, int32_t* parent, int32_t* lam,
+                          int32_t* root, int32_t* size, int32_t* cf, hipStream_t st) {
+  if (n <= 0) return;
+  k_fp_init<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, parent, lam, size);
+  k_fp_links<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, srp, sci, parent, lam);
+  k_fp_roots<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, srp, parent, lam, root, size, cf);
+}
+void launch_fp_small(int n, const int32_t* root, int32_t* cursor, int32_t* members, int ncomp, const int32_t* coff,
+                     const int32_t* srp, const int32_t* sci, int32_t* lam, int32_t* cf, hipStream_t st) {
+  if (n <= 0 || ncomp <= 0) return;
+  k_fp_members<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, root, cursor, members);
+  k_fp_small<<<nblocks(ncomp, kBlock), kBlock, 0, st>>>(ncomp, coff, members, srp, sci, lam, cf);
+}
+
 // Block ILU(0) of any block-sparse A (Sec. 3.1) on W, a copy of A's SELL-64
 // values: one launch per forward dependency level, one thread per row, each
 // row in the host factorisation's order: for its lower blocks in column

@@ -210,6 +210,19 @@ void launch_s2_bound(int nc, const int32_t* cpts, const int32_t* srp, const int3
 void launch_s2_rows(int nc, const int32_t* cpts, const int32_t* srp, const int32_t* sci, const int32_t* cidx,
                     const int32_t* rp, int32_t* ci, int32_t* cnt, hipStream_t st);
 int s2_row_cap();
+// Ruge-Stueben first pass over the small weakly connected components of a
+// strength pattern S (n points, int32 CSR).  launch_fp_components: lam[i] =
+// the number of points depending strongly on i, root[i] = the smallest point
+// of i's component, size[r] = the size of the component with root r, cf[i] =
+// -1 for points without any strong link, else 0.  With cursor[r] = the
+// offset of root r's component in `members` (-1 for components not taken)
+// and coff the offsets of the ncomp components taken (ascending roots),
+// launch_fp_small lists their members and runs the pass over each (one thread
+// per component: cf 1 = C, -1 = F), leaving the other points untouched.
+void launch_fp_components(int n, const int32_t* srp, const int32_t* sci, int32_t* parent, int32_t* lam,
+                          int32_t* root, int32_t* size, int32_t* cf, hipStream_t st);
+void launch_fp_small(int n, const int32_t* root, int32_t* cursor, int32_t* members, int ncomp, const int32_t* coff,
+                     const int32_t* srp, const int32_t* sci, int32_t* lam, int32_t* cf, hipStream_t st);
 // Block ILU(0) of any block-sparse A on the device.  W: a copy of A's SELL-64
 // values, factored in place (L left of the diagonal, U on and right of it);
 // one launch_ilu_rows per forward dependency level (positions [p0, p1) of

@@ -398,10 +398,13 @@ def test_device_setup_steps_equal_host(name, elliptic, agg):
         rows_d, nnz_d = sd.hierarchy()
         rows_h, nnz_h = sh.hierarchy()
         assert np.array_equal(rows_d, rows_h) and np.array_equal(nnz_d, nnz_h)
-        sites = sd.export("SETUP_SITES", 0, 10, np.int32)
+        sites = sd.export("SETUP_SITES", 0, 13, np.int32)
         built = len(rows_d) - 1
         na = min(agg, built)
-        assert list(sites) == [built, built, built - na, built - na, built, built, na, na, na, na], sites
+        assert list(sites[:10]) == [built, built, built - na, built - na, built, built, na, na, na, na], sites
+        # every first pass starts on the device (its small components there)
+        assert sites[10] == sites[11] >= built + na, sites
+        say(f"  first-pass points decided on the device: {sites[12] / 10:.1f} %")
         for l in range(len(rows_d)):
             for which in ("A", "P") if l + 1 < len(rows_d) else ("A",):
                 Md, Mh = sd.level_matrix(l, which), sh.level_matrix(l, which)
