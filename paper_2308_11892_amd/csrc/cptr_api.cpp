@@ -1214,14 +1214,16 @@ class DeviceLevelSteps : public LevelSteps {
       std::vector<int32_t> hb((size_t)m);
       if (!get(hb.data(), bound, m)) return fail();
       std::vector<int64_t> off((size_t)m + 1, 0);
+      int32_t maxb = 0;
       for (int32_t r = 0; r < m; ++r) {
         if (hb[r] < 0 || hb[r] > spgemm_row_cap()) return false;
         off[r + 1] = off[r] + hb[r];
+        maxb = std::max(maxb, hb[r]);
       }
       if (!put(doff, off.data(), (int64_t)m + 1) || !alloc(ocol, off[m]) || !alloc(oval, off[m]) || !alloc(cnt, m))
         return fail();
       launch_mp_rows(m, dnow, a_.rp, a_.ci, a_.v, s_.rp, s_.ci, dpass, dfunc, drp, dci, dv, doff, ocol, oval, cnt,
-                     st_);
+                     maxb, st_);
       std::vector<int32_t> hc((size_t)m);
       if (!get(hc.data(), cnt, m)) return fail();
       for (int32_t r = 0; r < m; ++r) lens[now[r]] = hc[r];
@@ -1317,9 +1319,11 @@ class DeviceLevelSteps : public LevelSteps {
     std::vector<int32_t> hb((size_t)n);
     if (!get(hb.data(), bound, n)) return fail();
     std::vector<int64_t> off((size_t)n + 1, 0);
+    int32_t maxb = 0;
     for (int32_t i = 0; i < n; ++i) {
       if (hb[i] > spgemm_row_cap()) return false;
       off[i + 1] = off[i] + hb[i];
+      maxb = std::max(maxb, hb[i]);
     }
     int64_t* doff = nullptr;
     int32_t *ocol = nullptr, *cnt = nullptr;
@@ -1327,7 +1331,7 @@ class DeviceLevelSteps : public LevelSteps {
     if (!put(doff, off.data(), (int64_t)n + 1) || !alloc(ocol, off[n]) || !alloc(oval, off[n]) ||
         !alloc(cnt, n))
       return fail();
-    launch_spgemm_rows(n, x.rp, x.ci, x.v, y.rp, y.ci, y.v, doff, ocol, oval, cnt, st_);
+    launch_spgemm_rows(n, x.rp, x.ci, x.v, y.rp, y.ci, y.v, doff, ocol, oval, cnt, maxb, st_);
     std::vector<int32_t> hc((size_t)n);
     if (!get(hc.data(), cnt, n)) return fail();
     rp_host.assign((size_t)n + 1, 0);

@@ -1766,10 +1766,20 @@ __global__ __launch_bounds__(64) void k_interp_exti(int n, const int32_t* __rest
                                                     int32_t* __restrict__ ocol, double* __restrict__ oval,
                                                     int32_t* __restrict__ cnt, int* __restrict__ overflow) {
 #pragma clang fp contract(off)
-  __shared__ int32_t s_set[64][kInterpCap];
-  __shared__ double s_acc[64][kInterpCap];
-  int32_t* set = s_set[threadIdx.x];
-  double* acc = s_acc[threadIdx.x];
+  // each thread's set and sums run down a column, so that the 64 threads
+  // reading their q-th entries hit 64 consecutive words (no bank conflicts)
+  __shared__ int32_t s_set[kInterpCap][64];
+  __shared__ double s_acc[kInterpCap][64];
+  struct Col {
+    int32_t* p;
+    __device__ int32_t& operator[](int q) const { return p[q * 64]; }
+  };
+  struct ColD {
+    double* p;
+    __device__ double& operator[](int q) const { return p[q * 64]; }
+  };
+  const Col set{&s_set[0][threadIdx.x]};
+  const ColD acc{&s_acc[0][threadIdx.x]};
   const int i = blockIdx.x * 64 + threadIdx.x;
   if (i >= n) return;
   const size_t o = (size_t)i * outcap;
@@ -1953,10 +1963,13 @@ __global__ __launch_bounds__(64) void k_spgemm_rows(int n, const int32_t* __rest
                                                     const double* __restrict__ yv,
                                                     const int64_t* __restrict__ off,
                                                     int32_t* __restrict__ ocol, double* __restrict__ oval,
-                                                    int32_t* __restrict__ cnt) {
+                                                    int32_t* __restrict__ cnt, int cap) {
 #pragma clang fp contract(off)
-  __shared__ long long key[kGemmCap];  // column * kGemmCap + position
-  __shared__ double val[kGemmCap];
+  // cap (a power of two, at least every row's product count) keys and values
+  // in dynamic LDS, so short rows leave room for many workgroups per CU
+  extern __shared__ double gemm_lds[];
+  long long* key = reinterpret_cast<long long*>(gemm_lds);  // column * kGemmCap + position
+  double* val = gemm_lds + cap;
   const int lane = threadIdx.x;
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
     const int q0 = xrp[i], q1 = xrp[i + 1];
@@ -2049,11 +2062,18 @@ void launch_spgemm_bound(int n, const int32_t* xrp, const int32_t* xci, const in
                          hipStream_t st) {
   if (n > 0) k_spgemm_bound<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, xrp, xci, yrp, bound);
 }
+static int lds_cap(int max_count) {
+  int cap = 64;
+  while (cap < max_count) cap <<= 1;
+  return std::min(cap, kGemmCap);
+}
 void launch_spgemm_rows(int n, const int32_t* xrp, const int32_t* xci, const double* xv, const int32_t* yrp,
                         const int32_t* yci, const double* yv, const int64_t* off, int32_t* ocol, double* oval,
-                        int32_t* cnt, hipStream_t st) {
+                        int32_t* cnt, int max_bound, hipStream_t st) {
+  const int cap = lds_cap(max_bound);
   if (n > 0)
-    k_spgemm_rows<<<std::min(n, 8192), 64, 0, st>>>(n, xrp, xci, xv, yrp, yci, yv, off, ocol, oval, cnt);
+    k_spgemm_rows<<<std::min(n, 16384), 64, (size_t)cap * 16, st>>>(n, xrp, xci, xv, yrp, yci, yv, off, ocol, oval,
+                                                                     cnt, cap);
 }
 void launch_spgemm_compact(int n, const int64_t* off, const int32_t* rp, const int32_t* ocol, const double* oval,
                            int32_t* ci, double* v, hipStream_t st) {
@@ -2159,10 +2179,11 @@ __global__ __launch_bounds__(64) void k_mp_rows(int m, const int32_t* __restrict
                                                 const int32_t* __restrict__ func, const int32_t* __restrict__ prp,
                                                 const int32_t* __restrict__ pci, const double* __restrict__ pv,
                                                 const int64_t* __restrict__ off, int32_t* __restrict__ ocol,
-                                                double* __restrict__ oval, int32_t* __restrict__ cnt) {
+                                                double* __restrict__ oval, int32_t* __restrict__ cnt, int cap) {
 #pragma clang fp contract(off)
-  __shared__ long long key[kGemmCap];  // column * kGemmCap + position
-  __shared__ double val[kGemmCap];
+  extern __shared__ double mp_lds[];  // cap keys and values (cap: see k_spgemm_rows)
+  long long* key = reinterpret_cast<long long*>(mp_lds);  // column * kGemmCap + position
+  double* val = mp_lds + cap;
   __shared__ int32_t qs[kMpCap];
   __shared__ double cs[kMpCap];
   __shared__ int nq;
@@ -2192,7 +2213,7 @@ __global__ __launch_bounds__(64) void k_mp_rows(int m, const int32_t* __restrict
     }
     const int start = incl - len;
     const int np_total = __shfl(incl, 63, 64);
-    const int total = min(np_total, kGemmCap);  // the bound kernel rejected larger rows
+    const int total = min(np_total, cap);  // the host sized cap to the largest bound
     for (int p = 0; p < len && start + p < total; ++p) {
       const int e = prp[q] + p;
       key[start + p] = (long long)pci[e] * kGemmCap + (start + p);
@@ -2296,10 +2317,11 @@ void launch_mp_bound(int m, const int32_t* now, const int32_t* arp, const int32_
 void launch_mp_rows(int m, const int32_t* now, const int32_t* arp, const int32_t* aci, const double* av,
                     const int32_t* srp, const int32_t* sci, const int32_t* pass, const int32_t* func,
                     const int32_t* prp, const int32_t* pci, const double* pv, const int64_t* off, int32_t* ocol,
-                    double* oval, int32_t* cnt, hipStream_t st) {
+                    double* oval, int32_t* cnt, int max_bound, hipStream_t st) {
+  const int cap = lds_cap(max_bound);
   if (m > 0)
-    k_mp_rows<<<std::min(m, 8192), 64, 0, st>>>(m, now, arp, aci, av, srp, sci, pass, func, prp, pci, pv, off, ocol,
-                                                oval, cnt);
+    k_mp_rows<<<std::min(m, 16384), 64, (size_t)cap * 16, st>>>(m, now, arp, aci, av, srp, sci, pass, func, prp, pci,
+                                                                 pv, off, ocol, oval, cnt, cap);
 }
 void launch_mp_merge(int n, int pass_no, int32_t* rowpos, const int32_t* now, int m, const int64_t* off,
                      const int32_t* ocol, const double* oval, const int32_t* prp, const int32_t* pci,

@@ -167,7 +167,7 @@ void launch_spgemm_bound(int n, const int32_t* xrp, const int32_t* xci, const in
                          hipStream_t st);
 void launch_spgemm_rows(int n, const int32_t* xrp, const int32_t* xci, const double* xv, const int32_t* yrp,
                         const int32_t* yci, const double* yv, const int64_t* off, int32_t* ocol, double* oval,
-                        int32_t* cnt, hipStream_t st);
+                        int32_t* cnt, int max_bound, hipStream_t st);
 void launch_spgemm_compact(int n, const int64_t* off, const int32_t* rp, const int32_t* ocol, const double* oval,
                            int32_t* ci, double* v, hipStream_t st);
 int spgemm_row_cap();
@@ -192,7 +192,7 @@ void launch_mp_bound(int m, const int32_t* now, const int32_t* arp, const int32_
 void launch_mp_rows(int m, const int32_t* now, const int32_t* arp, const int32_t* aci, const double* av,
                     const int32_t* srp, const int32_t* sci, const int32_t* pass, const int32_t* func,
                     const int32_t* prp, const int32_t* pci, const double* pv, const int64_t* off, int32_t* ocol,
-                    double* oval, int32_t* cnt, hipStream_t st);
+                    double* oval, int32_t* cnt, int max_bound, hipStream_t st);
 void launch_mp_merge(int n, int pass_no, int32_t* rowpos, const int32_t* now, int m, const int64_t* off,
                      const int32_t* ocol, const double* oval, const int32_t* prp, const int32_t* pci,
                      const double* pv, const int32_t* nrp, int32_t* nci, double* nv, int32_t* pass,
