@@ -1051,7 +1051,10 @@ class DeviceLevelSteps : public LevelSteps {
         !alloc(ocol, (int64_t)n * outcap) || !alloc(oval, (int64_t)n * outcap) || !alloc(cnt, n) ||
         !alloc(over, 1) || hipMemsetAsync(over, 0, sizeof(int), st_) != hipSuccess)
       return fail();
+    // a workgroup per row once rows average 16 entries (the coarse levels)
+    const bool long_rows = a_.nnz >= 16 * (int64_t)n;
     launch_interp_exti(n, a_.rp, a_.ci, a_.v, s_.rp, s_.ci, dcf, dfunc, dcidx, pmax, outcap, ocol, oval, cnt, over,
+                       long_rows,
                        st_);
     std::vector<int32_t> hc((size_t)n);
     int h_over = 0;

@@ -1923,10 +1923,237 @@ __global__ __launch_bounds__(64) void k_interp_exti(int n, const int32_t* __rest
   cnt[i] = nout;
 }
 
+// The same rows with one 64-lane workgroup per row, for levels whose rows are
+// long: every step of k_interp_exti in the same order (the lanes compute the
+// same uniform values), but a lookup in the interpolatory set or in row i of
+// S is one ballot over the lanes, which hold one entry each, and rows of A
+// are read 64 entries at a time and walked with shuffles.
+__global__ __launch_bounds__(64) void k_interp_exti_wave(int n, const int32_t* __restrict__ arp,
+                                                         const int32_t* __restrict__ aci,
+                                                         const double* __restrict__ av,
+                                                         const int32_t* __restrict__ srp,
+                                                         const int32_t* __restrict__ sci,
+                                                         const int32_t* __restrict__ cf,
+                                                         const int32_t* __restrict__ func,
+                                                         const int32_t* __restrict__ cidx, int pmax, int outcap,
+                                                         int32_t* __restrict__ ocol, double* __restrict__ oval,
+                                                         int32_t* __restrict__ cnt, int* __restrict__ overflow) {
+#pragma clang fp contract(off)
+  __shared__ int32_t s_set[kInterpCap];
+  __shared__ double s_acc[kInterpCap];
+  const int lane = threadIdx.x;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const size_t o = (size_t)i * outcap;
+    if (cf[i] == 1) {
+      if (lane == 0) {
+        ocol[o] = cidx[i];
+        oval[o] = 1.0;
+        cnt[i] = 1;
+      }
+      continue;
+    }
+    // the set: lane q holds entry q (q < ns), in insertion order
+    int32_t my_set = -1;
+    int ns = 0;
+    bool full = false;
+    auto find = [&](int32_t c) -> int {
+      const unsigned long long b = __ballot(lane < ns && my_set == c);
+      return b ? __ffsll(b) - 1 : -1;
+    };
+    auto add = [&](int32_t c) {
+      if (find(c) >= 0) return;
+      if (ns == kInterpCap) {
+        full = true;
+        return;
+      }
+      if (lane == ns) my_set = c;
+      ++ns;
+    };
+    const int s0 = srp[i], s1 = srp[i + 1];
+    for (int k = s0; k < s1; ++k) {
+      const int32_t j = sci[k];
+      if (cf[j] == 1) {
+        add(j);
+      } else {
+        for (int qb = srp[j]; qb < srp[j + 1]; qb += 64) {
+          const int len = min(64, srp[j + 1] - qb);
+          int32_t c = -1;
+          bool isc = false;
+          if (lane < len) {
+            c = sci[qb + lane];
+            isc = cf[c] == 1;
+          }
+          const unsigned long long cm = __ballot(isc);
+          for (int t = 0; t < len; ++t)
+            if ((cm >> t) & 1ull) add(__shfl(c, t, 64));
+        }
+      }
+    }
+    if (full) {
+      if (lane == 0) {
+        atomicAdd(overflow, 1);
+        cnt[i] = 0;
+      }
+      continue;
+    }
+    if (ns == 0) {
+      if (lane == 0) cnt[i] = 0;
+      continue;
+    }
+    const int slen = s1 - s0;
+    const int32_t my_s = lane < slen ? sci[s0 + lane] : -1;
+    auto strong = [&](int32_t m) -> bool {
+      if (slen <= 64) return __ballot(my_s == m) != 0;
+      bool hit = false;
+      for (int kb = s0; kb < s1; kb += 64) {
+        const int32_t v = kb + lane < s1 ? sci[kb + lane] : -1;
+        hit = hit || __ballot(v == m) != 0;
+      }
+      return hit;
+    };
+    auto a_diag = [&](int32_t r) -> double {
+      for (int kb = arp[r]; kb < arp[r + 1]; kb += 64) {
+        const bool hit = kb + lane < arp[r + 1] && aci[kb + lane] == r;
+        const unsigned long long b = __ballot(hit);
+        if (b) return av[kb + __ffsll(b) - 1];
+      }
+      return 0.0;
+    };
+    double my_acc = 0.0;
+    double dg = a_diag(i);
+    const int32_t fi = func[i];
+    for (int kb = arp[i]; kb < arp[i + 1]; kb += 64) {
+      const int len = min(64, arp[i + 1] - kb);
+      int32_t mm = -1, fm = -1, cm = 0;
+      double va = 0.0;
+      if (lane < len) {
+        mm = aci[kb + lane];
+        va = av[kb + lane];
+        fm = func[mm];
+        cm = cf[mm];
+      }
+      for (int t = 0; t < len; ++t) {
+        const int32_t m = __shfl(mm, t, 64);
+        const double aim = __shfl(va, t, 64);
+        if (m == i || __shfl(fm, t, 64) != fi) continue;
+        const int pos = find(m);
+        if (pos >= 0) {
+          if (lane == pos) my_acc = my_acc + aim;
+          continue;
+        }
+        if (__shfl(cm, t, 64) != 1 && strong(m)) {
+          const double sm = a_diag(m) < 0.0 ? -1.0 : 1.0;
+          double den = 0.0;
+          for (int qb = arp[m]; qb < arp[m + 1]; qb += 64) {
+            const int ln = min(64, arp[m + 1] - qb);
+            int32_t lq = -1;
+            double aq = 0.0;
+            if (lane < ln) {
+              lq = aci[qb + lane];
+              aq = av[qb + lane];
+            }
+            for (int u = 0; u < ln; ++u) {
+              const int32_t l = __shfl(lq, u, 64);
+              const double aml = __shfl(aq, u, 64);
+              if (sm * aml < 0.0 && (l == i || find(l) >= 0)) den = den + aml;
+            }
+          }
+          if (den == 0.0) {
+            dg = dg + aim;
+            continue;
+          }
+          for (int qb = arp[m]; qb < arp[m + 1]; qb += 64) {
+            const int ln = min(64, arp[m + 1] - qb);
+            int32_t lq = -1;
+            double aq = 0.0;
+            if (lane < ln) {
+              lq = aci[qb + lane];
+              aq = av[qb + lane];
+            }
+            for (int u = 0; u < ln; ++u) {
+              const int32_t l = __shfl(lq, u, 64);
+              const double aml = __shfl(aq, u, 64);
+              if (!(sm * aml < 0.0)) continue;
+              const double share = aim * aml / den;
+              if (l == i) {
+                dg = dg + share;
+              } else {
+                const int p = find(l);
+                if (p >= 0 && lane == p) my_acc = my_acc + share;
+              }
+            }
+          }
+          continue;
+        }
+        dg = dg + aim;
+      }
+    }
+    if (dg == 0.0) {
+      if (lane == 0) cnt[i] = 0;
+      continue;
+    }
+    if (lane < ns) {
+      s_set[lane] = cidx[my_set];
+      s_acc[lane] = -my_acc / dg;
+    }
+    __syncthreads();
+    if (lane == 0) {  // truncation and order exactly as in k_interp_exti
+      int32_t* set = s_set;
+      double* acc = s_acc;
+      int nout = ns;
+      if (pmax > 0 && ns > pmax) {
+        double total = 0.0, kept = 0.0;
+        for (int q = 0; q < ns; ++q) total = total + acc[q];
+        for (int r = 0; r < pmax; ++r) {
+          int best = r;
+          for (int q = r + 1; q < ns; ++q) {
+            const double fa = fabs(acc[q]), fb = fabs(acc[best]);
+            if (fa != fb ? fa > fb : set[q] < set[best]) best = q;
+          }
+          const int32_t tc = set[r];
+          set[r] = set[best];
+          set[best] = tc;
+          const double tw = acc[r];
+          acc[r] = acc[best];
+          acc[best] = tw;
+        }
+        for (int r = 0; r < pmax; ++r) kept = kept + acc[r];
+        nout = pmax;
+        if (kept != 0.0) {
+          const double scale = total / kept;
+          for (int r = 0; r < pmax; ++r) acc[r] = acc[r] * scale;
+        }
+      }
+      for (int a = 1; a < nout; ++a) {
+        const int32_t c = set[a];
+        const double w = acc[a];
+        int b = a;
+        for (; b > 0 && set[b - 1] > c; --b) {
+          set[b] = set[b - 1];
+          acc[b] = acc[b - 1];
+        }
+        set[b] = c;
+        acc[b] = w;
+      }
+      for (int q = 0; q < nout; ++q) {
+        ocol[o + q] = set[q];
+        oval[o + q] = acc[q];
+      }
+      cnt[i] = nout;
+    }
+    __syncthreads();
+  }
+}
+
 void launch_interp_exti(int n, const int32_t* arp, const int32_t* aci, const double* av, const int32_t* srp,
                         const int32_t* sci, const int32_t* cf, const int32_t* func, const int32_t* cidx, int pmax,
-                        int outcap, int32_t* ocol, double* oval, int32_t* cnt, int* overflow, hipStream_t st) {
-  if (n > 0)
+                        int outcap, int32_t* ocol, double* oval, int32_t* cnt, int* overflow, bool long_rows,
+                        hipStream_t st) {
+  if (n <= 0) return;
+  if (long_rows)
+    k_interp_exti_wave<<<std::min(n, 16384), 64, 0, st>>>(n, arp, aci, av, srp, sci, cf, func, cidx, pmax, outcap,
+                                                          ocol, oval, cnt, overflow);
+  else
     k_interp_exti<<<(n + 63) / 64, 64, 0, st>>>(n, arp, aci, av, srp, sci, cf, func, cidx, pmax, outcap, ocol, oval,
                                                cnt, overflow);
 }

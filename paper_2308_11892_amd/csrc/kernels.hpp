@@ -152,10 +152,13 @@ void launch_compact_cols(int n, const int32_t* off, const int32_t* rp, const int
 // F; func: unknown type per row; cidx: coarse index of each C point).  Row i
 // goes to ocol/oval at i * outcap (outcap >= pmax, or >= interp_set_cap()
 // without truncation), its length to cnt[i]; a row whose interpolatory set has
-// more than interp_set_cap() points adds 1 to *overflow.
+// more than interp_set_cap() points adds 1 to *overflow.  long_rows: one
+// workgroup per row instead of one thread (same results; faster when rows
+// are long).
 void launch_interp_exti(int n, const int32_t* arp, const int32_t* aci, const double* av, const int32_t* srp,
                         const int32_t* sci, const int32_t* cf, const int32_t* func, const int32_t* cidx, int pmax,
-                        int outcap, int32_t* ocol, double* oval, int32_t* cnt, int* overflow, hipStream_t st);
+                        int outcap, int32_t* ocol, double* oval, int32_t* cnt, int* overflow, bool long_rows,
+                        hipStream_t st);
 int interp_set_cap();
 // Sparse product C = X Y of scalar CSR matrices in the host product's
 // summation order (each entry from 0.0, products in the order of X's and Y's
