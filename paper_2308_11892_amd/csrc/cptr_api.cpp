@@ -1193,64 +1193,51 @@ class DeviceLevelSteps : public LevelSteps {
     }
     const std::vector<double> pv(pci.size(), 1.0);
     int32_t *dpass = nullptr, *dfunc = nullptr, *drp = nullptr, *dci = nullptr, *rowpos = nullptr;
+    int32_t *flag = nullptr, *pos = nullptr, *dlens = nullptr;
     double* dv = nullptr;
-    int8_t* flag = nullptr;
     if (!put(dpass, pass.data(), n) || !put(dfunc, func.data(), n) || !put(drp, prp.data(), (int64_t)n + 1) ||
-        !put(dci, pci.data(), nc) || !put(dv, pv.data(), nc) || !alloc(flag, n) || !alloc(rowpos, n))
+        !put(dci, pci.data(), nc) || !put(dv, pv.data(), nc) || !put(dlens, lens.data(), n) || !alloc(flag, n) ||
+        !alloc(pos, (int64_t)n + 1) || !alloc(rowpos, n))
       return fail();
     launch_fill_i32(n, rowpos, -1, st_);
-    std::vector<int8_t> hflag((size_t)n);
-    std::vector<int32_t> now;
+    int64_t nnz = nc;
     for (int pass_no = 1;; ++pass_no) {
       launch_mp_mark(n, s_.rp, s_.ci, dpass, flag, st_);
-      if (!get(hflag.data(), flag, n)) return fail();
-      now.clear();
-      for (int32_t i = 0; i < n; ++i)
-        if (hflag[i]) now.push_back(i);
-      if (now.empty()) break;
-      const int32_t m = (int32_t)now.size();
-      int32_t *dnow = nullptr, *bound = nullptr, *cnt = nullptr, *ocol = nullptr;
+      const int64_t m = scan<int32_t>(flag, n, pos, nullptr);
+      if (m < 0) return fail();
+      if (m == 0) break;
+      int32_t *dnow = nullptr, *bound = nullptr, *cnt = nullptr, *ocol = nullptr, *nrp = nullptr, *nci = nullptr;
       int64_t* doff = nullptr;
-      double* oval = nullptr;
-      if (!put(dnow, now.data(), m) || !alloc(bound, m)) return fail();
-      launch_mp_bound(m, dnow, a_.rp, a_.ci, a_.v, s_.rp, s_.ci, dpass, dfunc, drp, bound, st_);
-      std::vector<int32_t> hb((size_t)m);
-      if (!get(hb.data(), bound, m)) return fail();
-      std::vector<int64_t> off((size_t)m + 1, 0);
-      int32_t maxb = 0;
-      for (int32_t r = 0; r < m; ++r) {
-        if (hb[r] < 0 || hb[r] > spgemm_row_cap()) return false;
-        off[r + 1] = off[r] + hb[r];
-        maxb = std::max(maxb, hb[r]);
-      }
-      if (!put(doff, off.data(), (int64_t)m + 1) || !alloc(ocol, off[m]) || !alloc(oval, off[m]) || !alloc(cnt, m))
+      double *oval = nullptr, *nv = nullptr;
+      if (!alloc(dnow, m) || !alloc(bound, m) || !alloc(doff, m + 1) || !alloc(cnt, m) || !alloc(nrp, (int64_t)n + 1))
         return fail();
-      launch_mp_rows(m, dnow, a_.rp, a_.ci, a_.v, s_.rp, s_.ci, dpass, dfunc, drp, dci, dv, doff, ocol, oval, cnt,
-                     maxb, st_);
-      std::vector<int32_t> hc((size_t)m);
-      if (!get(hc.data(), cnt, m)) return fail();
-      for (int32_t r = 0; r < m; ++r) lens[now[r]] = hc[r];
-      int64_t total = 0;
-      for (int32_t i = 0; i < n; ++i) {
-        prp[i] = (int32_t)total;
-        total += lens[i];
-        if (total >= INT32_MAX) return false;
-      }
-      prp[n] = (int32_t)total;
-      int32_t *nrp = nullptr, *nci = nullptr;
-      double* nv = nullptr;
-      if (!put(nrp, prp.data(), (int64_t)n + 1) || !alloc(nci, total) || !alloc(nv, total)) return fail();
-      launch_mp_merge(n, pass_no, rowpos, dnow, m, doff, ocol, oval, drp, dci, dv, nrp, nci, nv, dpass, st_);
+      launch_select(n, flag, pos, dnow, st_);
+      launch_mp_bound((int)m, dnow, a_.rp, a_.ci, a_.v, s_.rp, s_.ci, dpass, dfunc, drp, bound, st_);
+      int32_t maxb = 0;
+      const int64_t nprod = scan<int64_t>(bound, m, doff, &maxb);
+      if (nprod < 0) return fail();
+      if (maxb > spgemm_row_cap()) return false;
+      if (!alloc(ocol, nprod) || !alloc(oval, nprod)) return fail();
+      launch_mp_rows((int)m, dnow, a_.rp, a_.ci, a_.v, s_.rp, s_.ci, dpass, dfunc, drp, dci, dv, doff, ocol, oval,
+                     cnt, maxb, st_);
+      launch_mp_setlen((int)m, dnow, cnt, dlens, st_);
+      const int64_t total = scan<int32_t>(dlens, n, nrp, nullptr);
+      if (total < 0) return fail();
+      if (total >= INT32_MAX) return false;
+      if (!alloc(nci, total) || !alloc(nv, total)) return fail();
+      launch_mp_merge(n, pass_no, rowpos, dnow, (int)m, doff, ocol, oval, drp, dci, dv, nrp, nci, nv, dpass, st_);
       drp = nrp;
       dci = nci;
       dv = nv;
+      nnz = total;
     }
     P.n = n;
     P.m = nc;
+    if (!get(prp.data(), drp, (int64_t)n + 1)) return fail();
     P.rp.assign(prp.begin(), prp.end());
-    P.ci.resize(prp[n]);
-    P.v.resize(prp[n]);
-    if (!get(P.ci.data(), dci, prp[n]) || !get(P.v.data(), dv, prp[n])) return fail();
+    P.ci.resize(nnz);
+    P.v.resize(nnz);
+    if (!get(P.ci.data(), dci, nnz) || !get(P.v.data(), dv, nnz)) return fail();
     ++done_.multipass;
     return true;
   }
@@ -1259,9 +1246,9 @@ class DeviceLevelSteps : public LevelSteps {
   bool galerkin(const Csr& R, const Csr& P, Csr& C) override {
     if (!ok_) return false;
     DevCsr p, r, ap, c;
-    std::vector<int32_t> crp, aprp;
+    std::vector<int32_t> crp;
     if (!upload(P, p) || !upload(R, r)) return fail();
-    if (!product(a_, p, ap, aprp) || !product(r, ap, c, crp)) return false;
+    if (!product(a_, p, ap, nullptr) || !product(r, ap, c, &crp)) return false;
     C.n = R.n;
     C.m = P.m;
     C.rp.assign(crp.begin(), crp.end());
@@ -1314,41 +1301,49 @@ class DeviceLevelSteps : public LevelSteps {
     if (h.v.size() != h.ci.size()) return false;
     return upload_pattern(h, d) && put(d.v, h.v.data(), d.nnz);
   }
-  bool product(const DevCsr& x, const DevCsr& y, DevCsr& out, std::vector<int32_t>& rp_host) {
-    const int32_t n = x.n;
-    int32_t* bound = nullptr;
-    if (!alloc(bound, n)) return fail();
-    launch_spgemm_bound(n, x.rp, x.ci, y.rp, bound, st_);
-    std::vector<int32_t> hb((size_t)n);
-    if (!get(hb.data(), bound, n)) return fail();
-    std::vector<int64_t> off((size_t)n + 1, 0);
-    int32_t maxb = 0;
-    for (int32_t i = 0; i < n; ++i) {
-      if (hb[i] > spgemm_row_cap()) return false;
-      off[i + 1] = off[i] + hb[i];
-      maxb = std::max(maxb, hb[i]);
-    }
-    int64_t* doff = nullptr;
-    int32_t *ocol = nullptr, *cnt = nullptr;
-    double* oval = nullptr;
-    if (!put(doff, off.data(), (int64_t)n + 1) || !alloc(ocol, off[n]) || !alloc(oval, off[n]) ||
-        !alloc(cnt, n))
-      return fail();
-    launch_spgemm_rows(n, x.rp, x.ci, x.v, y.rp, y.ci, y.v, doff, ocol, oval, cnt, maxb, st_);
-    std::vector<int32_t> hc((size_t)n);
-    if (!get(hc.data(), cnt, n)) return fail();
-    rp_host.assign((size_t)n + 1, 0);
+  // exclusive prefix sums of n device counts into out (n + 1 entries, the
+  // total last); returns the total (and the largest count in *maxc), -1 on a
+  // HIP error
+  template <class O>
+  int64_t scan(const int32_t* in, int64_t n, O* out, int32_t* maxc) {
+    const int64_t ntmp = scan_tmp_size(n);
+    int64_t* tmp = nullptr;
+    int32_t* dmax = nullptr;
+    if (!alloc(tmp, ntmp) || !alloc(dmax, 1)) return -1;
+    launch_fill_i32(1, dmax, 0, st_);
+    launch_scan<O>(n, in, out, tmp, dmax, st_);
     int64_t total = 0;
-    for (int32_t i = 0; i < n; ++i) {
-      total += hc[i];
-      if (total >= INT32_MAX) return false;
-      rp_host[i + 1] = (int32_t)total;
-    }
+    int32_t mx = 0;
+    if (!get(&total, tmp + ntmp - 1, 1) || !get(&mx, dmax, 1)) return -1;
+    if (maxc) *maxc = mx;
+    return total;
+  }
+  // out = x y; row pointers prefixed on the device, copied to *rp_host if asked
+  bool product(const DevCsr& x, const DevCsr& y, DevCsr& out, std::vector<int32_t>* rp_host) {
+    const int32_t n = x.n;
+    int32_t *bound = nullptr, *ocol = nullptr, *cnt = nullptr;
+    int64_t* doff = nullptr;
+    double* oval = nullptr;
+    if (!alloc(bound, n) || !alloc(doff, (int64_t)n + 1) || !alloc(cnt, n) || !alloc(out.rp, (int64_t)n + 1))
+      return fail();
+    launch_spgemm_bound(n, x.rp, x.ci, y.rp, bound, st_);
+    int32_t maxb = 0;
+    const int64_t nprod = scan<int64_t>(bound, n, doff, &maxb);
+    if (nprod < 0) return fail();
+    if (maxb > spgemm_row_cap()) return false;
+    if (!alloc(ocol, nprod) || !alloc(oval, nprod)) return fail();
+    launch_spgemm_rows(n, x.rp, x.ci, x.v, y.rp, y.ci, y.v, doff, ocol, oval, cnt, maxb, st_);
+    const int64_t total = scan<int32_t>(cnt, n, out.rp, nullptr);
+    if (total < 0) return fail();
+    if (total >= INT32_MAX) return false;
     out.n = n;
     out.nnz = total;
-    if (!put(out.rp, rp_host.data(), (int64_t)n + 1) || !alloc(out.ci, total) || !alloc(out.v, total))
-      return fail();
+    if (!alloc(out.ci, total) || !alloc(out.v, total)) return fail();
     launch_spgemm_compact(n, doff, out.rp, ocol, oval, out.ci, out.v, st_);
+    if (rp_host) {
+      rp_host->resize((size_t)n + 1);
+      if (!get(rp_host->data(), out.rp, (int64_t)n + 1)) return fail();
+    }
     return hipGetLastError() == hipSuccess || fail();
   }
 

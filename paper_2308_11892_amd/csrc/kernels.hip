@@ -2322,10 +2322,10 @@ constexpr int kMpCap = 64;  // interpolating points per row
 
 __global__ __launch_bounds__(kBlock) void k_mp_mark(int n, const int32_t* __restrict__ srp,
                                                     const int32_t* __restrict__ sci,
-                                                    const int32_t* __restrict__ pass, int8_t* __restrict__ flag) {
+                                                    const int32_t* __restrict__ pass, int32_t* __restrict__ flag) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  int8_t f = 0;
+  int32_t f = 0;
   if (pass[i] == -1)
     for (int a = srp[i]; a < srp[i + 1]; ++a)
       if (pass[sci[a]] != -1) {
@@ -2392,7 +2392,7 @@ __global__ __launch_bounds__(kBlock) void k_mp_bound(int m, const int32_t* __res
   int b = 0;
   const int cnt = mp_coefs(now[r], arp, aci, av, srp, sci, pass, func,
                            [&](int, int32_t q, double) { b += prp[q + 1] - prp[q]; });
-  bound[r] = cnt > kMpCap ? -1 : b;
+  bound[r] = cnt > kMpCap ? kGemmCap + 1 : b;  // beyond any row cap: the host takes the level
 }
 
 // one 64-lane workgroup per row of the pass: the interpolating points and
@@ -2527,14 +2527,33 @@ __global__ __launch_bounds__(kBlock) void k_mp_scatter(int m, const int32_t* __r
   if (r < m) rowpos[now[r]] = r;
 }
 
+// now[pos[i]] = i for the flagged points (pos: exclusive prefix of flag)
+__global__ __launch_bounds__(kBlock) void k_select(int n, const int32_t* __restrict__ flag,
+                                                   const int32_t* __restrict__ pos, int32_t* __restrict__ now) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n && flag[i]) now[pos[i]] = i;
+}
+
+__global__ __launch_bounds__(kBlock) void k_mp_setlen(int m, const int32_t* __restrict__ now,
+                                                      const int32_t* __restrict__ cnt, int32_t* __restrict__ len) {
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  if (r < m) len[now[r]] = cnt[r];
+}
+
 __global__ __launch_bounds__(kBlock) void k_fill_i32(int64_t n, int32_t* __restrict__ x, int32_t v) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < n) x[i] = v;
 }
 
-void launch_mp_mark(int n, const int32_t* srp, const int32_t* sci, const int32_t* pass, int8_t* flag,
+void launch_mp_mark(int n, const int32_t* srp, const int32_t* sci, const int32_t* pass, int32_t* flag,
                     hipStream_t st) {
   if (n > 0) k_mp_mark<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, srp, sci, pass, flag);
+}
+void launch_select(int n, const int32_t* flag, const int32_t* pos, int32_t* now, hipStream_t st) {
+  if (n > 0) k_select<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, flag, pos, now);
+}
+void launch_mp_setlen(int m, const int32_t* now, const int32_t* cnt, int32_t* len, hipStream_t st) {
+  if (m > 0) k_mp_setlen<<<nblocks(m, kBlock), kBlock, 0, st>>>(m, now, cnt, len);
 }
 void launch_mp_bound(int m, const int32_t* now, const int32_t* arp, const int32_t* aci, const double* av,
                      const int32_t* srp, const int32_t* sci, const int32_t* pass, const int32_t* func,
@@ -2657,6 +2676,97 @@ void launch_s2_rows(int nc, const int32_t* cpts, const int32_t* srp, const int32
   if (nc > 0) k_s2_rows<<<std::min(nc, 8192), 64, 0, st>>>(nc, cpts, srp, sci, cidx, rp, ci, cnt);
 }
 int s2_row_cap() { return kS2Cap; }
+
+// --------------------------------------------------------------------------
+// Exclusive prefix sums of int32 counts on the device (setup row pointers):
+// each 256-thread workgroup sums 16 consecutive counts per thread and scans
+// the thread sums in LDS; one workgroup then scans the workgroup totals in
+// chunks with a running carry; a last pass adds each workgroup's offset.
+// out[0..n) are the offsets, out[n] the total; also the largest count.
+constexpr int kScanPer = 16;
+constexpr int kScanChunk = kBlock * kScanPer;
+
+template <class O>
+__global__ __launch_bounds__(kBlock) void k_scan_local(int64_t n, const int32_t* __restrict__ in,
+                                                       O* __restrict__ out, int64_t* __restrict__ bsum,
+                                                       int* __restrict__ maxv) {
+  __shared__ int64_t part[kBlock];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPer;
+  int32_t v[kScanPer];
+  int64_t sum = 0;
+  int mx = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    v[k] = base + k < n ? in[base + k] : 0;
+    sum += v[k];
+    mx = max(mx, v[k]);
+  }
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (int d = 1; d < kBlock; d <<= 1) {  // inclusive Hillis-Steele scan of the thread sums
+    const int64_t t = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
+    __syncthreads();
+    part[threadIdx.x] += t;
+    __syncthreads();
+  }
+  int64_t run = part[threadIdx.x] - sum;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    if (base + k < n) out[base + k] = (O)run;
+    run += v[k];
+  }
+  if (threadIdx.x == kBlock - 1) bsum[blockIdx.x] = part[kBlock - 1];
+  if (maxv) {
+    for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_down(mx, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(maxv, mx);
+  }
+}
+
+// exclusive scan of the nb workgroup totals, in place, one workgroup; the
+// grand total to *total
+__global__ __launch_bounds__(kBlock) void k_scan_sums(int64_t nb, int64_t* __restrict__ bsum,
+                                                      int64_t* __restrict__ total) {
+  __shared__ int64_t part[kBlock];
+  int64_t carry = 0;
+  for (int64_t c0 = 0; c0 < nb; c0 += kBlock) {
+    const int64_t i = c0 + threadIdx.x;
+    const int64_t x = i < nb ? bsum[i] : 0;
+    part[threadIdx.x] = x;
+    __syncthreads();
+    for (int d = 1; d < kBlock; d <<= 1) {
+      const int64_t t = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
+      __syncthreads();
+      part[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < nb) bsum[i] = carry + part[threadIdx.x] - x;
+    carry += part[kBlock - 1];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+template <class O>
+__global__ __launch_bounds__(kBlock) void k_scan_add(int64_t n, O* __restrict__ out,
+                                                     const int64_t* __restrict__ bsum,
+                                                     const int64_t* __restrict__ total) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) out[i] = (O)(out[i] + bsum[i / kScanChunk]);
+  if (i == 0) out[n] = (O)*total;
+}
+
+int64_t scan_tmp_size(int64_t n) { return std::max<int64_t>(1, (n + kScanChunk - 1) / kScanChunk) + 1; }
+
+template <class O>
+void launch_scan(int64_t n, const int32_t* in, O* out, int64_t* tmp, int* maxv, hipStream_t st) {
+  const int64_t nb = std::max<int64_t>(1, (n + kScanChunk - 1) / kScanChunk);
+  int64_t* total = tmp + nb;
+  k_scan_local<O><<<(unsigned)nb, kBlock, 0, st>>>(n, in, out, tmp, maxv);
+  k_scan_sums<<<1, kBlock, 0, st>>>(nb, tmp, total);
+  k_scan_add<O><<<(unsigned)std::max<int64_t>(1, (n + kBlock - 1) / kBlock), kBlock, 0, st>>>(n, out, tmp, total);
+}
+template void launch_scan<int64_t>(int64_t, const int32_t*, int64_t*, int64_t*, int*, hipStream_t);
+template void launch_scan<int32_t>(int64_t, const int32_t*, int32_t*, int64_t*, int*, hipStream_t);
 
 // --------------------------------------------------------------------------
 // Ruge-Stueben first pass over the small weakly connected components of a

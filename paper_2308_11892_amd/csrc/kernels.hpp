@@ -180,15 +180,19 @@ int spgemm_row_cap();
 // for C points, the pass that gave row i of P, -1 while it has none; P is CSR
 // over all rows.  launch_mp_mark: flag[i] = 1 when i has no row and a strong
 // dependency of i has one.  For the pass's rows now[0..m): launch_mp_bound
-// gives bound[r], the products of row now[r] (or -1 when it has more than
-// mp_point_cap() interpolating points); with off the exclusive prefix of
+// gives bound[r], the products of row now[r] (or spgemm_row_cap() + 1 when it
+// has more than mp_point_cap() interpolating points); with off the exclusive prefix of
 // bound (every bound at most spgemm_row_cap()), launch_mp_rows writes row r
 // sorted by column at off[r] of ocol/oval and its length to cnt[r].
 // launch_mp_merge forms the next P (nrp: its row pointers) from P and the new
 // rows, sets the pass's points to pass number pass_no and leaves rowpos (n
 // entries, -1 outside a call) at -1.
-void launch_mp_mark(int n, const int32_t* srp, const int32_t* sci, const int32_t* pass, int8_t* flag,
+void launch_mp_mark(int n, const int32_t* srp, const int32_t* sci, const int32_t* pass, int32_t* flag,
                     hipStream_t st);
+// now[pos[i]] = i where flag[i] != 0 (pos: exclusive prefix of flag)
+void launch_select(int n, const int32_t* flag, const int32_t* pos, int32_t* now, hipStream_t st);
+// len[now[r]] = cnt[r]
+void launch_mp_setlen(int m, const int32_t* now, const int32_t* cnt, int32_t* len, hipStream_t st);
 void launch_mp_bound(int m, const int32_t* now, const int32_t* arp, const int32_t* aci, const double* av,
                      const int32_t* srp, const int32_t* sci, const int32_t* pass, const int32_t* func,
                      const int32_t* prp, int32_t* bound, hipStream_t st);
@@ -213,6 +217,13 @@ void launch_s2_bound(int nc, const int32_t* cpts, const int32_t* srp, const int3
 void launch_s2_rows(int nc, const int32_t* cpts, const int32_t* srp, const int32_t* sci, const int32_t* cidx,
                     const int32_t* rp, int32_t* ci, int32_t* cnt, hipStream_t st);
 int s2_row_cap();
+// Exclusive prefix sums of n int32 counts: out[0..n) the offsets, out[n] the
+// total (O = int64_t, or int32_t when the total fits); *maxv (if not null,
+// set beforehand) is raised to the largest count.  tmp: scan_tmp_size(n)
+// int64 of scratch.
+template <class O>
+void launch_scan(int64_t n, const int32_t* in, O* out, int64_t* tmp, int* maxv, hipStream_t st);
+int64_t scan_tmp_size(int64_t n);
 // Ruge-Stueben first pass over the small weakly connected components of a
 // strength pattern S (n points, int32 CSR).  launch_fp_components: lam[i] =
 // the number of points depending strongly on i, root[i] = the smallest point
