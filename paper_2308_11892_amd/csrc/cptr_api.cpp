@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -384,33 +385,39 @@ int upload_level_op(cptr_solver s, Lev& dl, const Csr& h, hipStream_t st) {
 // Is A's block pattern exactly the 7-point stencil of an nx*ny*nz grid in
 // lexicographic order (x fastest)?  Requires nx, ny, nz >= 2.  (rp, ci:
 // a validated pattern with sorted rows.)
-bool detect_grid(int32_t nb, const int32_t* rp, const int32_t* ci, int dims[3]) {
+bool detect_grid(int32_t nb, const int32_t* rp, const int32_t* ci, int dims[3], int threads = 1) {
   if (rp[1] - rp[0] != 4) return false;  // corner cell: itself, +x, +y, +z
   const int32_t nx = ci[rp[0] + 1] == 1 ? ci[rp[0] + 2] : 0;
   const int32_t nxy = ci[rp[0] + 3];
   if (ci[rp[0]] != 0 || ci[rp[0] + 1] != 1 || nx < 2 || nxy % nx != 0 || nxy / nx < 2) return false;
   if (nb % nxy != 0 || nb / nxy < 2) return false;
   const int32_t ny = nxy / nx, nz = nb / nxy;
-  for (int32_t c = 0; c < nb; ++c) {
-    const int32_t x = c % nx, yy = (c / nx) % ny, zz = c / nxy;
-    int32_t want[7], m = 0;
-    if (zz > 0) want[m++] = c - nxy;
-    if (yy > 0) want[m++] = c - nx;
-    if (x > 0) want[m++] = c - 1;
-    want[m++] = c;
-    if (x < nx - 1) want[m++] = c + 1;
-    if (yy < ny - 1) want[m++] = c + nx;
-    if (zz < nz - 1) want[m++] = c + nxy;
-    if (rp[c + 1] - rp[c] != m) return false;
-    for (int q = 0; q < m; ++q)
-      if (ci[rp[c] + q] != want[q]) return false;
-  }
+  std::atomic<bool> ok{true};
+  parallel_ranges(nb, threads, [&](int64_t lo, int64_t hi) {
+    for (int64_t c = lo; c < hi && ok.load(std::memory_order_relaxed); ++c) {
+      const int32_t x = (int32_t)(c % nx), yy = (int32_t)((c / nx) % ny), zz = (int32_t)(c / nxy);
+      int32_t want[7], m = 0;
+      if (zz > 0) want[m++] = (int32_t)c - nxy;
+      if (yy > 0) want[m++] = (int32_t)c - nx;
+      if (x > 0) want[m++] = (int32_t)c - 1;
+      want[m++] = (int32_t)c;
+      if (x < nx - 1) want[m++] = (int32_t)c + 1;
+      if (yy < ny - 1) want[m++] = (int32_t)c + nx;
+      if (zz < nz - 1) want[m++] = (int32_t)c + nxy;
+      bool same = rp[c + 1] - rp[c] == m;
+      for (int q = 0; q < m && same; ++q) same = ci[rp[c] + q] == want[q];
+      if (!same) ok.store(false, std::memory_order_relaxed);
+    }
+  });
+  if (!ok.load()) return false;
   dims[0] = nx;
   dims[1] = ny;
   dims[2] = nz;
   return true;
 }
-bool detect_grid(const HostSetup& h, int dims[3]) { return detect_grid(h.nb, h.rp.data(), h.ci.data(), dims); }
+bool detect_grid(const HostSetup& h, int dims[3], int threads) {
+  return detect_grid(h.nb, h.rp.data(), h.ci.data(), dims, threads);
+}
 
 // The grid factors computed on the device from A (see launch_grid_ilu_diag):
 // U_cc^-1 level by level into a temporary FP64 array, then the tile layouts.
@@ -634,12 +641,18 @@ int build_device(cptr_solver s, hipStream_t st) {
     d.nslices = (nb + kLanes - 1) / kLanes;
     d.nv = 9;
     std::vector<int32_t> sptr((size_t)d.nslices + 1, 0);
+    parallel_ranges(d.nslices, s->threads, [&](int64_t s0, int64_t s1) {
+      for (int64_t sl = s0; sl < s1; ++sl) {
+        const int32_t r0 = (int32_t)sl * kLanes, r1 = std::min(nb, r0 + kLanes);
+        int32_t w = 0;
+        for (int32_t r = r0; r < r1; ++r) w = std::max(w, h.rp[r + 1] - h.rp[r]);
+        sptr[sl + 1] = w;
+      }
+    });
     int64_t max_slice_blocks = 0;
     for (int32_t sl = 0; sl < d.nslices; ++sl) {
       const int32_t r0 = sl * kLanes, r1 = std::min(nb, r0 + kLanes);
-      int32_t w = 0;
-      for (int32_t r = r0; r < r1; ++r) w = std::max(w, h.rp[r + 1] - h.rp[r]);
-      sptr[sl + 1] = sptr[sl] + w;
+      sptr[sl + 1] += sptr[sl];
       max_slice_blocks = std::max<int64_t>(max_slice_blocks, h.rp[r1] - h.rp[r0]);
     }
     d.nslots = sptr[d.nslices];
@@ -678,28 +691,53 @@ int build_device(cptr_solver s, hipStream_t st) {
   }
   // W padded to 2 per cell
   {
-    std::vector<double> w2((size_t)nb * 2, 0.0);
-    for (int32_t i = 0; i < nb; ++i)
-      for (int t = 0; t < ne * h.nh; ++t) w2[(size_t)i * 2 + t] = h.W[(size_t)i * ne * h.nh + t];
+    std::vector<double> w2((size_t)nb * 2);
+    parallel_ranges(nb, s->threads, [&](int64_t lo, int64_t hi) {
+      for (int64_t i = lo; i < hi; ++i)
+        for (int t = 0; t < 2; ++t) w2[(size_t)i * 2 + t] = t < ne * h.nh ? h.W[(size_t)i * ne * h.nh + t] : 0.0;
+    });
     if ((rc = upload(s, s->W, w2.data(), (int64_t)w2.size(), st))) return rc;
   }
-  // ILU sweeps: positions sorted by level (stable in row order)
+  // ILU sweeps: positions sorted by level (stable in row order): a counting
+  // sort whose threads each count, then place, one contiguous range of rows
   std::vector<int32_t> fp, bp;
   {
     auto order = [&](const std::vector<int32_t>& lvl, int32_t nl, std::vector<int32_t>& perm,
                      std::vector<int32_t>& ptr) {
+      const int t = (int)std::max<int64_t>(1, std::min<int64_t>(s->threads, nb / 65536));
+      std::vector<int64_t> cnt((size_t)t * nl, 0);  // [thread][level]
+      auto range = [&](int k) { return std::make_pair((int64_t)nb * k / t, (int64_t)nb * (k + 1) / t); };
+      auto each = [&](auto&& f) {
+        std::vector<std::thread> th;
+        for (int k = 1; k < t; ++k) th.emplace_back(f, k);
+        f(0);
+        for (auto& x : th) x.join();
+      };
+      each([&](int k) {
+        for (int64_t i = range(k).first; i < range(k).second; ++i) ++cnt[(size_t)k * nl + lvl[i]];
+      });
       ptr.assign(nl + 1, 0);
-      for (int32_t i = 0; i < nb; ++i) ++ptr[lvl[i] + 1];
-      for (int32_t l = 0; l < nl; ++l) ptr[l + 1] += ptr[l];
-      std::vector<int32_t> fillp(ptr.begin(), ptr.end() - 1);
+      int64_t run = 0;
+      for (int32_t l = 0; l < nl; ++l) {
+        ptr[l] = (int32_t)run;
+        for (int k = 0; k < t; ++k) {
+          const int64_t c = cnt[(size_t)k * nl + l];
+          cnt[(size_t)k * nl + l] = run;
+          run += c;
+        }
+      }
+      ptr[nl] = (int32_t)run;
       perm.resize(nb);
-      for (int32_t i = 0; i < nb; ++i) perm[fillp[lvl[i]]++] = i;
+      each([&](int k) {
+        for (int64_t i = range(k).first; i < range(k).second; ++i)
+          perm[cnt[(size_t)k * nl + lvl[i]]++] = (int32_t)i;
+      });
     };
     order(h.fwd_level, h.n_fwd_levels, fp, s->flev_ptr);
     order(h.bwd_level, h.n_bwd_levels, bp, s->blev_ptr);
     if ((rc = dalloc(s, s->tickets, 2))) return rc;
     if (!s->measure) HIP_TRY(s, hipMemsetAsync(s->tickets, 0, 2 * sizeof(int), st));
-    const bool grid = detect_grid(h, s->grid);
+    const bool grid = detect_grid(h, s->grid, s->threads);
     if (s->ilu_mode == CPTR_ILU_SWEEP_GRID && !grid)
       return fail(s, CPTR_E_INVALID, "ilu_sweep = GRID needs a 7-point stencil in lexicographic order");
     s->use_grid = grid && (s->ilu_mode == CPTR_ILU_SWEEP_AUTO || s->ilu_mode == CPTR_ILU_SWEEP_GRID);
