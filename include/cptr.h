@@ -266,7 +266,7 @@ enum {
                                   C/F splits, interpolations (with R = P^T), Galerkin products,
                                   l1 diagonals and coarsest LU, host ILU(0) and sweep levels,
                                   then the device half and the whole cptr_setup */
-  CPTR_EXPORT_SETUP_SITES = 12 /* int32[13]: strength graphs formed on the device and in total,
+  CPTR_EXPORT_SETUP_SITES = 12 /* int32[15]: strength graphs formed on the device and in total,
                                   extended+i interpolations on the device and in total,
                                   coarse operators R A P on the device and in total, multipass
                                   interpolations (aggressive levels) on the device and in total,
@@ -276,7 +276,8 @@ enum {
                                   host) and first passes in total (with hmis_block = 0: one per
                                   level split, two on an aggressive level), and the share, in
                                   thousandths, of the device passes' points that the device
-                                  decided.
+                                  decided; then the splits over several HMIS blocks formed on
+                                  the device (hmis_block from 1 to 4096) and in total.
                                   A device handle forms a product on the host only when a row of
                                   it has more than 2048 products, an extended+i interpolation
                                   only when a row's interpolatory set has more than 64 points, a

@@ -138,6 +138,7 @@ struct PrecDev {
 struct SetupSiteCounts {
   int strength = 0, interp = 0, galerkin = 0, multipass = 0, strength2 = 0;
   int split = 0;              // first passes begun on the device
+  int hmis = 0;               // splits over several HMIS blocks on the device
   int64_t split_points = 0;   // points those decided on the device
   int64_t first_points = 0;   // points of all first passes of a one-block split
 };
@@ -1163,6 +1164,48 @@ class DeviceLevelSteps : public LevelSteps {
     return true;
   }
 
+  // HMIS over blocks on the device: the graph's transpose, the blocks' first
+  // passes, the cover by their C points, then PMIS rounds until no point is
+  // undecided (one count back per round).
+  bool hmis(const Csr& G, bool second, int32_t block, std::vector<int32_t>& cf) override {
+    if (!ok_ || block < 1 || block > hmis_block_cap()) return false;
+    if (second && !have_s2_) return false;
+    if (!second && !have_s_) {
+      if (!upload_pattern(G, s_)) return fail();
+      have_s_ = true;
+    }
+    const DevCsr& g = second ? s2_ : s_;
+    const int32_t n = G.n;
+    int32_t *deg = nullptr, *trp = nullptr, *cursor = nullptr, *tci = nullptr, *cf1 = nullptr, *dcf = nullptr;
+    int32_t *cnt = nullptr, *isnew = nullptr;
+    int* left = nullptr;
+    if (!alloc(deg, n) || !alloc(trp, (int64_t)n + 1) || !alloc(cursor, (int64_t)n + 1) || !alloc(cf1, n) ||
+        !alloc(dcf, n) || !alloc(cnt, n) || !alloc(isnew, n) || !alloc(left, 1))
+      return fail();
+    launch_fill_i32(n, deg, 0, st_);
+    launch_transpose_pattern(n, g.rp, g.ci, deg, nullptr, nullptr, 0, st_);
+    const int64_t nt = scan<int32_t>(deg, n, trp, nullptr);
+    if (nt < 0) return fail();
+    if (!alloc(tci, nt) ||
+        hipMemcpyAsync(cursor, trp, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToDevice, st_) != hipSuccess)
+      return fail();
+    launch_transpose_pattern(n, g.rp, g.ci, nullptr, cursor, tci, 1, st_);
+    launch_hmis_blocks(n, block, g.rp, g.ci, trp, tci, cf1, dcf, st_);
+    launch_pmis_start(n, g.rp, g.ci, dcf, cnt, st_);
+    // every round with a point left decides at least the best of them
+    for (int64_t round = 0;; ++round) {
+      launch_pmis_round(n, g.rp, g.ci, trp, tci, cnt, dcf, isnew, left, st_);
+      int h_left = 0;
+      if (!get(&h_left, left, 1)) return fail();
+      if (h_left == 0) break;
+      if (round > n) return false;
+    }
+    cf.resize(n);
+    if (!get(cf.data(), dcf, n)) return fail();
+    ++done_.hmis;
+    return true;
+  }
+
   // Distance-two strength of an aggressive level: candidates counted, rows
   // counted, then written at their CSR places.
   bool strength2(const Csr& S, const std::vector<int32_t>& cf, Csr& S2) override {
@@ -2075,9 +2118,10 @@ cptr_status cptr_export(cptr_solver s, int32_t what, int32_t level, void* buf, i
       const SetupSiteCounts& d = s->device_steps;
       const int32_t permille =
           d.first_points > 0 ? (int32_t)(1000 * d.split_points / d.first_points) : 0;
-      int32_t v[13] = {d.strength, built, d.interp, std::max(0, built - s->agg_levels_used), d.galerkin, built,
-                       d.multipass, agg, d.strength2, agg, d.split, h.first_passes, permille};
-      return put(v, 52);
+      int32_t v[15] = {d.strength, built, d.interp, std::max(0, built - s->agg_levels_used), d.galerkin, built,
+                       d.multipass, agg, d.strength2, agg, d.split, h.first_passes, permille, d.hmis,
+                       h.hmis_splits};
+      return put(v, 60);
     }
     default:
       return (cptr_status)fail(s, CPTR_E_INVALID, "unknown export item");

@@ -1065,13 +1065,21 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
     mark(kStepStrength);
     const bool agg = (int)l < prm.agg_levels;
     // a first pass (one HMIS block) starts with dev's passes over the small
-    // components of the graph, when dev holds the graph (which: 0 = S, 1 =
-    // the distance-two graph it formed, -1 = neither)
+    // components of the graph, and a split over several blocks runs on dev,
+    // when dev holds the graph (which: 0 = S, 1 = the distance-two graph it
+    // formed, -1 = neither)
     auto split = [&](const Csr& G, int which) {
-      if (prm.hmis_block <= 0 || prm.hmis_block >= G.n) ++h.first_passes;
+      const bool one_block = prm.hmis_block <= 0 || prm.hmis_block >= G.n;
+      if (one_block)
+        ++h.first_passes;
+      else
+        ++h.hmis_splits;
       std::vector<int32_t> part;
-      if (prm.hmis_block <= 0 && dev && which >= 0 && dev->first_pass_small(G, which == 1, part))
-        return first_pass_finish(G, std::move(part), threads);
+      if (dev && which >= 0) {
+        if (one_block && dev->first_pass_small(G, which == 1, part))
+          return first_pass_finish(G, std::move(part), threads);
+        if (!one_block && dev->hmis(G, which == 1, prm.hmis_block, part)) return part;
+      }
       return hmis_split(G, prm.hmis_block, threads);
     };
     std::vector<int32_t> cf;

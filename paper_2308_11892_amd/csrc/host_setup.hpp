@@ -75,6 +75,12 @@ struct LevelSteps {
     (void)G, (void)second, (void)cf;
     return false;
   }
+  // the HMIS split over blocks of `block` points of G (as first_pass_small's
+  // G and second), the whole split
+  virtual bool hmis(const Csr& G, bool second, int32_t block, std::vector<int32_t>& cf) {
+    (void)G, (void)second, (void)block, (void)cf;
+    return false;
+  }
   // distance-two strength among the C points of cf (aggressive level)
   virtual bool strength2(const Csr& S, const std::vector<int32_t>& cf, Csr& S2) {
     (void)S, (void)cf, (void)S2;
@@ -123,6 +129,7 @@ struct HostSetup {
   std::vector<int32_t> fwd_level, bwd_level;  // dependency level of each row
   int32_t n_fwd_levels = 0, n_bwd_levels = 0;
   int first_passes = 0;         // one-block splits run (first passes over a whole graph)
+  int hmis_splits = 0;          // splits over several HMIS blocks
   // wall seconds of the setup steps (kSetupStep*), summed over levels
   double step_s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };

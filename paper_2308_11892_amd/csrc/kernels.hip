@@ -2678,6 +2678,221 @@ void launch_s2_rows(int nc, const int32_t* cpts, const int32_t* srp, const int32
 int s2_row_cap() { return kS2Cap; }
 
 // --------------------------------------------------------------------------
+// HMIS over blocks of consecutive points (the hmis_block reading): the first
+// pass inside every block on its in-block links, then the points depending
+// on a C point are F, then PMIS with the priority (count, SplitMix64(i), i).
+
+// the transpose's columns: dependents of each point, in any order within a row
+__global__ __launch_bounds__(kBlock) void k_tr_count(int n, const int32_t* __restrict__ srp,
+                                                     const int32_t* __restrict__ sci, int32_t* __restrict__ deg) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  for (int a = srp[i]; a < srp[i + 1]; ++a) atomicAdd(&deg[sci[a]], 1);
+}
+__global__ __launch_bounds__(kBlock) void k_tr_fill(int n, const int32_t* __restrict__ srp,
+                                                    const int32_t* __restrict__ sci, int32_t* __restrict__ cursor,
+                                                    int32_t* __restrict__ tci) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  for (int a = srp[i]; a < srp[i + 1]; ++a) tci[atomicAdd(&cursor[sci[a]], 1)] = i;
+}
+
+// one 64-lane workgroup per block: measures and states of the block's points
+// in LDS (dynamic, 8 bytes a point); each pick is the largest measure >= 1,
+// smallest index, found by a scan and a wave reduction; the points of the
+// block depending on it (its row of the transpose) become F and raise their
+// undecided in-block dependencies, then its own undecided in-block
+// dependencies drop.  cf1[i] = 1 for the block's C points, else 0.
+__global__ __launch_bounds__(64) void k_hmis_block(int n, int block, const int32_t* __restrict__ srp,
+                                                   const int32_t* __restrict__ sci,
+                                                   const int32_t* __restrict__ trp,
+                                                   const int32_t* __restrict__ tci, int32_t* __restrict__ cf1) {
+  extern __shared__ int32_t hmis_lds[];
+  int32_t* lam = hmis_lds;
+  int32_t* st = hmis_lds + block;  // 0 undecided, 1 C, -1 F (a count while starting)
+  const int lane = threadIdx.x;
+  const int lo = blockIdx.x * block, hi = min(n, lo + block), m = hi - lo;
+  for (int t = lane; t < m; t += 64) {
+    lam[t] = 0;
+    st[t] = 0;
+  }
+  __syncthreads();
+  for (int t = lane; t < m; t += 64) {
+    const int i = lo + t;
+    int out = 0;
+    for (int a = srp[i]; a < srp[i + 1]; ++a) {
+      const int j = sci[a];
+      if (j >= lo && j < hi) {
+        atomicAdd(&lam[j - lo], 1);
+        ++out;
+      }
+    }
+    st[t] = out;
+  }
+  __syncthreads();
+  for (int t = lane; t < m; t += 64) st[t] = (st[t] == 0 && lam[t] == 0) ? -1 : 0;
+  __syncthreads();
+  for (;;) {
+    int bl = 0, bt = -1;
+    for (int t = lane; t < m; t += 64)
+      if (st[t] == 0 && lam[t] >= 1 && lam[t] > bl) {
+        bl = lam[t];
+        bt = t;
+      }
+    for (int off = 32; off > 0; off >>= 1) {
+      const int ol = __shfl_xor(bl, off, 64), ot = __shfl_xor(bt, off, 64);
+      if (ot >= 0 && (bt < 0 || ol > bl || (ol == bl && ot < bt))) {
+        bl = ol;
+        bt = ot;
+      }
+    }
+    if (bt < 0) break;
+    const int c = lo + bt;
+    if (lane == 0) st[bt] = 1;
+    __syncthreads();
+    for (int k = trp[c] + lane; k < trp[c + 1]; k += 64) {
+      const int f = tci[k];
+      if (f < lo || f >= hi || st[f - lo] != 0) continue;
+      st[f - lo] = -1;
+      for (int a = srp[f]; a < srp[f + 1]; ++a) {
+        const int q = sci[a];
+        if (q >= lo && q < hi && st[q - lo] == 0) atomicAdd(&lam[q - lo], 1);
+      }
+    }
+    __syncthreads();
+    for (int a = srp[c] + lane; a < srp[c + 1]; a += 64) {
+      const int q = sci[a];
+      if (q >= lo && q < hi && st[q - lo] == 0) atomicSub(&lam[q - lo], 1);
+    }
+    __syncthreads();
+  }
+  for (int t = lane; t < m; t += 64) cf1[lo + t] = st[t] == 1 ? 1 : 0;
+}
+
+// step 2: C stays C, a point depending strongly on a C point is F, the rest
+// undecided (0)
+__global__ __launch_bounds__(kBlock) void k_hmis_cover(int n, const int32_t* __restrict__ srp,
+                                                       const int32_t* __restrict__ sci,
+                                                       const int32_t* __restrict__ cf1, int32_t* __restrict__ cf) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int v = cf1[i] == 1 ? 1 : 0;
+  if (v == 0)
+    for (int a = srp[i]; a < srp[i + 1]; ++a)
+      if (cf1[sci[a]] == 1) {
+        v = -1;
+        break;
+      }
+  cf[i] = v;
+}
+
+// PMIS counts: cnt[i] += 1 for every undecided j depending on i
+__global__ __launch_bounds__(kBlock) void k_pmis_count(int n, const int32_t* __restrict__ srp,
+                                                       const int32_t* __restrict__ sci,
+                                                       const int32_t* __restrict__ cf, int32_t* __restrict__ cnt) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n || cf[j] != 0) return;
+  for (int a = srp[j]; a < srp[j + 1]; ++a) atomicAdd(&cnt[sci[a]], 1);
+}
+
+// undecided points nobody undecided depends on are F
+__global__ __launch_bounds__(kBlock) void k_pmis_drop(int n, const int32_t* __restrict__ cnt,
+                                                      int32_t* __restrict__ cf) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n && cf[i] == 0 && cnt[i] == 0) cf[i] = -1;
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014): the output for counter value x
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ bool pmis_beats(int32_t ca, int a, int32_t cb, int b) {
+  if (ca != cb) return ca > cb;
+  const uint64_t ha = splitmix64((uint64_t)a), hb = splitmix64((uint64_t)b);
+  if (ha != hb) return ha > hb;
+  return a > b;
+}
+
+// one round: isnew[i] = 1 for the undecided points whose priority beats every
+// undecided strong neighbour's (links either way); *left counts the
+// undecided points
+__global__ __launch_bounds__(kBlock) void k_pmis_pick(int n, const int32_t* __restrict__ srp,
+                                                      const int32_t* __restrict__ sci,
+                                                      const int32_t* __restrict__ trp,
+                                                      const int32_t* __restrict__ tci,
+                                                      const int32_t* __restrict__ cnt,
+                                                      const int32_t* __restrict__ cf, int32_t* __restrict__ isnew,
+                                                      int* __restrict__ left) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  int top = 0;
+  if (cf[i] == 0) {
+    atomicAdd(left, 1);
+    top = 1;
+    for (int a = srp[i]; a < srp[i + 1] && top; ++a) {
+      const int j = sci[a];
+      if (cf[j] == 0 && pmis_beats(cnt[j], j, cnt[i], i)) top = 0;
+    }
+    for (int a = trp[i]; a < trp[i + 1] && top; ++a) {
+      const int j = tci[a];
+      if (cf[j] == 0 && pmis_beats(cnt[j], j, cnt[i], i)) top = 0;
+    }
+  }
+  isnew[i] = top;
+}
+
+// the round's C points, then the undecided points depending on one are F
+__global__ __launch_bounds__(kBlock) void k_pmis_c(int n, const int32_t* __restrict__ isnew,
+                                                   int32_t* __restrict__ cf) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n && isnew[i]) cf[i] = 1;
+}
+__global__ __launch_bounds__(kBlock) void k_pmis_f(int n, const int32_t* __restrict__ srp,
+                                                   const int32_t* __restrict__ sci,
+                                                   const int32_t* __restrict__ isnew, int32_t* __restrict__ cf) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n || cf[i] != 0) return;
+  for (int a = srp[i]; a < srp[i + 1]; ++a)
+    if (isnew[sci[a]]) {
+      cf[i] = -1;
+      return;
+    }
+}
+
+void launch_transpose_pattern(int n, const int32_t* srp, const int32_t* sci, int32_t* deg, int32_t* cursor,
+                              int32_t* tci, int phase, hipStream_t st) {
+  if (n <= 0) return;
+  if (phase == 0)
+    k_tr_count<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, srp, sci, deg);
+  else
+    k_tr_fill<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, srp, sci, cursor, tci);
+}
+void launch_hmis_blocks(int n, int block, const int32_t* srp, const int32_t* sci, const int32_t* trp,
+                        const int32_t* tci, int32_t* cf1, int32_t* cf, hipStream_t st) {
+  if (n <= 0) return;
+  k_hmis_block<<<nblocks(n, block), 64, (size_t)block * 8, st>>>(n, block, srp, sci, trp, tci, cf1);
+  k_hmis_cover<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, srp, sci, cf1, cf);
+}
+void launch_pmis_start(int n, const int32_t* srp, const int32_t* sci, int32_t* cf, int32_t* cnt, hipStream_t st) {
+  if (n <= 0) return;
+  k_fill_i32<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, cnt, 0);
+  k_pmis_count<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, srp, sci, cf, cnt);
+  k_pmis_drop<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, cnt, cf);
+}
+void launch_pmis_round(int n, const int32_t* srp, const int32_t* sci, const int32_t* trp, const int32_t* tci,
+                       const int32_t* cnt, int32_t* cf, int32_t* isnew, int* left, hipStream_t st) {
+  if (n <= 0) return;
+  k_fill_i32<<<1, kBlock, 0, st>>>(1, left, 0);
+  k_pmis_pick<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, srp, sci, trp, tci, cnt, cf, isnew, left);
+  k_pmis_c<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, isnew, cf);
+  k_pmis_f<<<nblocks(n, kBlock), kBlock, 0, st>>>(n, srp, sci, isnew, cf);
+}
+int hmis_block_cap() { return 4096; }
+
+// --------------------------------------------------------------------------
 // Exclusive prefix sums of int32 counts on the device (setup row pointers):
 // each 256-thread workgroup sums 16 consecutive counts per thread and scans
 // the thread sums in LDS; one workgroup then scans the workgroup totals in

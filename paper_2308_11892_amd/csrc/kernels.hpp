@@ -217,6 +217,24 @@ void launch_s2_bound(int nc, const int32_t* cpts, const int32_t* srp, const int3
 void launch_s2_rows(int nc, const int32_t* cpts, const int32_t* srp, const int32_t* sci, const int32_t* cidx,
                     const int32_t* rp, int32_t* ci, int32_t* cnt, hipStream_t st);
 int s2_row_cap();
+// HMIS over blocks of `block` (at most hmis_block_cap()) consecutive points
+// of a strength pattern S (n points, int32 CSR), as the host's hmis_split.
+// launch_transpose_pattern: phase 0 adds each point's dependents to deg
+// (zeroed beforehand); phase 1, with cursor = the exclusive prefix of deg
+// (trp), writes them to tci (any order within a row).  launch_hmis_blocks:
+// the first pass inside every block (cf1: 1 for its C points, else 0), then
+// cf = 1 (C), -1 (depends strongly on a C point) or 0.  launch_pmis_start:
+// the undecided points' counts (cnt) and the ones without undecided
+// dependents made F; launch_pmis_round: one round of picks (isnew) and their
+// F points; *left = the undecided points at the round's start (0: done).
+void launch_transpose_pattern(int n, const int32_t* srp, const int32_t* sci, int32_t* deg, int32_t* cursor,
+                              int32_t* tci, int phase, hipStream_t st);
+void launch_hmis_blocks(int n, int block, const int32_t* srp, const int32_t* sci, const int32_t* trp,
+                        const int32_t* tci, int32_t* cf1, int32_t* cf, hipStream_t st);
+void launch_pmis_start(int n, const int32_t* srp, const int32_t* sci, int32_t* cf, int32_t* cnt, hipStream_t st);
+void launch_pmis_round(int n, const int32_t* srp, const int32_t* sci, const int32_t* trp, const int32_t* tci,
+                       const int32_t* cnt, int32_t* cf, int32_t* isnew, int* left, hipStream_t st);
+int hmis_block_cap();
 // Exclusive prefix sums of n int32 counts: out[0..n) the offsets, out[n] the
 // total (O = int64_t, or int32_t when the total fits); *maxv (if not null,
 // set beforehand) is raised to the largest count.  tmp: scan_tmp_size(n)

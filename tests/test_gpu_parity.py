@@ -398,13 +398,38 @@ def test_device_setup_steps_equal_host(name, elliptic, agg):
         rows_d, nnz_d = sd.hierarchy()
         rows_h, nnz_h = sh.hierarchy()
         assert np.array_equal(rows_d, rows_h) and np.array_equal(nnz_d, nnz_h)
-        sites = sd.export("SETUP_SITES", 0, 13, np.int32)
+        sites = sd.export("SETUP_SITES", 0, 15, np.int32)
         built = len(rows_d) - 1
         na = min(agg, built)
         assert list(sites[:10]) == [built, built, built - na, built - na, built, built, na, na, na, na], sites
         # every first pass starts on the device (its small components there)
         assert sites[10] == sites[11] >= built + na, sites
+        assert list(sites[13:]) == [0, 0], sites
         say(f"  first-pass points decided on the device: {sites[12] / 10:.1f} %")
+        for l in range(len(rows_d)):
+            for which in ("A", "P") if l + 1 < len(rows_d) else ("A",):
+                Md, Mh = sd.level_matrix(l, which), sh.level_matrix(l, which)
+                assert np.array_equal(Md.indptr, Mh.indptr) and np.array_equal(Md.indices, Mh.indices)
+                assert np.array_equal(Md.data, Mh.data), f"level {l} {which}"
+
+
+@pytest.mark.parametrize("name,block,agg", [("grid100x100x20", 4096, 1), ("grid100x100x20", 1, 1),
+                                            ("prism2000x5", 512, 1), ("prism2000x5", 64, 0),
+                                            ("grid20x20x5", 1000, 1)])
+def test_device_hmis_blocks_equal_host(name, block, agg):
+    """hmis_block > 0: every split over several blocks (the blocks' first
+    passes, the cover by their C points and the PMIS rounds) runs on the GPU
+    and gives the host's split, so the whole hierarchy matches bit for bit."""
+    c = J.by_name(name)
+    say(f"[device hmis] {name} hmis_block={block} agg_levels={agg}")
+    kw = dict(hmis_block=block, agg_levels=agg)
+    with L.Solver(c.row_ptr, c.col_idx, c.values, **kw) as sd, \
+            L.Solver(c.row_ptr, c.col_idx, c.values, host_only=1, **kw) as sh:
+        rows_d, nnz_d = sd.hierarchy()
+        rows_h, nnz_h = sh.hierarchy()
+        assert np.array_equal(rows_d, rows_h) and np.array_equal(nnz_d, nnz_h)
+        sites = sd.export("SETUP_SITES", 0, 15, np.int32)
+        assert sites[14] > 0 and sites[13] == sites[14], sites
         for l in range(len(rows_d)):
             for which in ("A", "P") if l + 1 < len(rows_d) else ("A",):
                 Md, Mh = sd.level_matrix(l, which), sh.level_matrix(l, which)

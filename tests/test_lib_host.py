@@ -199,10 +199,11 @@ def test_host_only_handle_forms_products_on_the_host():
     c = J.small(8, 6, 4)
     s = host_solver(c)
     rows, _ = s.hierarchy()
-    sites = s.export("SETUP_SITES", 0, 13, np.int32)
+    sites = s.export("SETUP_SITES", 0, 15, np.int32)
     # one aggressive level
     L_ = len(rows) - 1
     assert list(sites[:11]) == [0, L_, 0, L_ - 1, 0, L_, 0, 1, 0, 1, 0] and sites[11] >= L_ + 1 and sites[12] == 0
+    assert list(sites[13:]) == [0, 0]  # one HMIS block: no blocked split
 
 
 def test_coarsening_limit_reports_stall():
