@@ -327,6 +327,30 @@ def build_info():
         return None
 
 
+def run_setup_only(args):
+    """N setups of the workload on the GPU (device handle, FP64), one JSON line
+    with each one's wall time and CPTR_EXPORT_SETUP_TIMES steps."""
+    import numpy as np
+    import torch
+    import paper_2308_11892_amd as L
+    from synth import jacobian as J
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.init()
+    c = J.by_name(args.workload)
+    runs = []
+    for k in range(args.setup_only):
+        t0 = time.perf_counter()
+        with L.Solver(c.row_ptr, c.col_idx, c.values) as s:
+            steps = s.export("SETUP_TIMES", 0, 10)
+            sites = s.export("SETUP_SITES", 0, 15, np.int32)
+        wall = time.perf_counter() - t0
+        runs.append({"wall_s": round(wall, 4), **{k2: round(float(v), 4) for k2, v in zip(L.SETUP_STEPS, steps)}})
+        log(f"setup {k}: {wall:.3f} s")
+    print(json.dumps({"workload": args.workload, "setups": runs,
+                      "first_pass_share_on_device": int(sites[12]) / 1000.0,
+                      "device_sites": [int(v) for v in sites[:12]]}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -354,6 +378,9 @@ def main():
                     help="requests of the serving sub-object of the default run (0: none)")
     ap.add_argument("--no-unstructured", action="store_true",
                     help="leave out the unstructured (1M-cell prism mesh) sub-object")
+    ap.add_argument("--setup-only", type=int, default=0, metavar="N",
+                    help="instead of the solve benchmark, run N setups of the workload (the first "
+                         "a warm-up) and print their step times; for a kernel trace of the setup")
     ap.add_argument("--compare-cpr", action="store_true",
                     help="instead of the solve benchmark, compare CPTR with CPR (elliptic set {p}) "
                          "on the 100x100x20 Peclet sweep at time steps of 1 and 30 days")
@@ -368,6 +395,9 @@ def main():
         return
     if args.compare_cpr:
         run_cpr_comparison()
+        return
+    if args.setup_only:
+        run_setup_only(args)
         return
 
     import numpy as np
