@@ -1593,19 +1593,6 @@ __device__ __forceinline__ bool inv3_dev(const double* m, double* out) {
     for (int c = 0; c < 3; ++c) out[r * 3 + c] = a[r][c + 3];
   return true;
 }
-// block (9 values) of A's row r at column c, or zeros when absent
-__device__ __forceinline__ void sell_block(const int32_t* __restrict__ sptr, const int32_t* __restrict__ col,
-                                           const double* __restrict__ val, int r, int c, double* out) {
-  const int s = r >> 6, lane = r & 63;
-#pragma unroll
-  for (int e = 0; e < 9; ++e) out[e] = 0.0;
-  for (int k = sptr[s]; k < sptr[s + 1]; ++k)
-    if (col[(size_t)k * 64 + lane] == c) {
-#pragma unroll
-      for (int e = 0; e < 9; ++e) out[e] = val[((size_t)k * 9 + e) * 64 + lane];
-      return;
-    }
-}
 
 __global__ __launch_bounds__(kBlock) void k_grid_ilu_diag(int p0, int p1, const int32_t* __restrict__ perm,
                                                           const int32_t* __restrict__ sptr,
@@ -1615,19 +1602,41 @@ __global__ __launch_bounds__(kBlock) void k_grid_ilu_diag(int p0, int p1, const 
   const int p = p0 + blockIdx.x * kBlock + threadIdx.x;
   if (p >= p1) return;
   const int c = perm[p];
+  const int ny = nxy / nx;
+  // A's pattern is the 7-point stencil in sorted column order, so a row's
+  // slot of each neighbour follows from which of its neighbours exist: the
+  // blocks are read directly instead of searching the row's columns
+  auto slot = [&](int r, int d) -> size_t {  // slot in row r of column r + d
+    const int xr = r % nx, yr = (r / nx) % ny, zr = r / nxy;
+    int k = 0;
+    if (d > -nxy) k += zr > 0;
+    if (d > -nx) k += yr > 0;
+    if (d > -1) k += xr > 0;
+    if (d > 0) k += 1;
+    if (d > 1) k += xr < nx - 1;
+    if (d > nx) k += yr < ny - 1;
+    return (size_t)sptr[r >> 6] + k;
+  };
+  auto block_at = [&](int r, size_t q, double* out) {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) out[e] = val[(q * 9 + e) * 64 + (r & 63)];
+  };
   double D[9];
-  sell_block(sptr, col, val, c, c, D);
-  const int lower[3] = {c - nxy, c - nx, c - 1};  // increasing column order
+  block_at(c, slot(c, 0), D);
+  const int x = c % nx, y = (c / nx) % ny, z = c / nxy;
+  const int dl[3] = {nxy, nx, 1};  // lower neighbours in increasing column order
+  const bool has[3] = {z > 0, y > 0, x > 0};
   for (int q = 0; q < 3; ++q) {
-    const int k = lower[q];
+    if (!has[q]) continue;
+    const int k = c - dl[q];
     double Ack[9], Akc[9], Lq[9], prod[9];
-    sell_block(sptr, col, val, c, k, Ack);
+    block_at(c, slot(c, -dl[q]), Ack);
     bool present = false;
 #pragma unroll
     for (int e = 0; e < 9; ++e) present |= Ack[e] != 0.0;
-    if (k < 0 || !present) continue;
+    if (!present) continue;
     mm3_dev(Ack, uinv + (size_t)k * 9, Lq);
-    sell_block(sptr, col, val, k, c, Akc);
+    block_at(k, slot(k, dl[q]), Akc);
     mm3_dev(Lq, Akc, prod);
 #pragma unroll
     for (int e = 0; e < 9; ++e) D[e] -= prod[e];
@@ -3046,13 +3055,19 @@ __global__ __launch_bounds__(kBlock) void k_fp_links(int n, const int32_t* __res
 }
 
 // root[i] and the component sizes; isolated points (no link either way) are
-// F, the rest undecided
-__global__ __launch_bounds__(kBlock) void k_fp_roots(int n, const int32_t* __restrict__ srp, int32_t* parent,
+// F, the rest undecided.  The forest no longer changes: plain (cached)
+// loads walk up to the root.
+__global__ __launch_bounds__(kBlock) void k_fp_roots(int n, const int32_t* __restrict__ srp,
+                                                     const int32_t* __restrict__ parent,
                                                      const int32_t* __restrict__ lam, int32_t* __restrict__ root,
                                                      int32_t* __restrict__ size, int32_t* __restrict__ cf) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  const int32_t r = uf_root(parent, i);
+  int32_t r = i, p = parent[i];
+  while (p != r) {
+    r = p;
+    p = parent[r];
+  }
   root[i] = r;
   atomicAdd(&size[r], 1);
   cf[i] = (srp[i + 1] == srp[i] && lam[i] == 0) ? -1 : 0;

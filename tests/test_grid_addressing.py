@@ -178,3 +178,66 @@ def test_backward_sweep_reads_no_e0_without_first_stage():
     assert copies and all("e0t)" in ln or "&& e0t" in ln for ln in copies), copies
     update = src[src.index("struct GridCell"):src.index("// The kernel: one workgroup per tile.")]
     assert "has_e0 = e0t != nullptr" in update and "has_e0 ? (double)r[3]" in update
+
+
+def grid_pattern(nx, ny, nz):
+    """The 7-point stencil in lexicographic order with sorted rows (what the
+    library's grid check accepts), as CSR."""
+    n = nx * ny * nz
+    rp, ci = [0], []
+    for c in range(n):
+        x, y, z = c % nx, (c // nx) % ny, c // (nx * ny)
+        cols = []
+        if z > 0:
+            cols.append(c - nx * ny)
+        if y > 0:
+            cols.append(c - nx)
+        if x > 0:
+            cols.append(c - 1)
+        cols.append(c)
+        if x < nx - 1:
+            cols.append(c + 1)
+        if y < ny - 1:
+            cols.append(c + nx)
+        if z < nz - 1:
+            cols.append(c + nx * ny)
+        ci += cols
+        rp.append(len(ci))
+    return np.array(rp), np.array(ci)
+
+
+def diag_slot(nx, ny, r, d):
+    """k_grid_ilu_diag's slot of column r + d within row r (mirrors its
+    `slot` lambda)."""
+    nxy = nx * ny
+    xr, yr, zr = r % nx, (r // nx) % ny, r // nxy
+    k = 0
+    k += d > -nxy and zr > 0
+    k += d > -nx and yr > 0
+    k += d > -1 and xr > 0
+    k += d > 0
+    k += d > 1 and xr < nx - 1
+    k += d > nx and yr < ny - 1
+    return int(k)
+
+
+@pytest.mark.parametrize("shape", [(2, 2, 2), (3, 2, 2), (7, 5, 3), (20, 20, 5), (16, 16, 8)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_grid_ilu_diag_slots_are_the_searched_ones(shape):
+    """The factorisation kernel reads a neighbour's block at a slot computed
+    from the cell's coordinates: for every cell and every neighbour it reads
+    (its own diagonal, the lower blocks A_ck, and A_kc in each lower
+    neighbour's row), that slot holds exactly that column, inside the row."""
+    nx, ny, nz = shape
+    rp, ci = grid_pattern(nx, ny, nz)
+    nxy = nx * ny
+    for c in range(nx * ny * nz):
+        x, y, z = c % nx, (c // nx) % ny, c // nxy
+        reads = [(c, 0)]
+        for d, has in ((nxy, z > 0), (nx, y > 0), (1, x > 0)):
+            if has:
+                reads += [(c, -d), (c - d, d)]
+        for r, d in reads:
+            k = diag_slot(nx, ny, r, d)
+            assert 0 <= k < rp[r + 1] - rp[r]
+            assert ci[rp[r] + k] == r + d
