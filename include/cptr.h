@@ -108,6 +108,11 @@ typedef struct {
                                 Ruge-Stueben first pass inside every block, then PMIS on the
                                 points it leaves undecided across blocks; 1 = PMIS; default
                                 0 = one block (the first pass over the whole level) */
+  int32_t max_dense_coarse;  /* largest coarsest level solved exactly (dense LU, Sec. 3.1's
+                                coarse solve); a coarsest level above it (the coarsening
+                                stopped early: a split with no C point, or max_levels) gets
+                                num_sweeps l1-Jacobi sweeps before and after a zero coarse
+                                correction instead; default 4096, 0..4096 */
 } cptr_setup_opts;
 
 enum {

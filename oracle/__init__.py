@@ -90,12 +90,13 @@ def lib():
 class AmgOpts(C.Structure):
     _fields_ = [("theta", C.c_double), ("max_row_sum", C.c_double),
                 ("max_levels", C.c_int), ("max_coarse", C.c_int), ("pmax", C.c_int),
-                ("agg_levels", C.c_int), ("num_sweeps", C.c_int), ("hmis_block", C.c_int)]
+                ("agg_levels", C.c_int), ("num_sweeps", C.c_int), ("hmis_block", C.c_int),
+                ("max_dense", C.c_int)]
 
     def __init__(self, theta=0.25, max_row_sum=0.9, max_levels=25, max_coarse=9, pmax=4,
-                 agg_levels=1, num_sweeps=1, hmis_block=0):
+                 agg_levels=1, num_sweeps=1, hmis_block=0, max_dense=4096):
         super().__init__(theta, max_row_sum, max_levels, max_coarse, pmax, agg_levels, num_sweeps,
-                         hmis_block)
+                         hmis_block, max_dense)
 
 
 class GmresOpts(C.Structure):

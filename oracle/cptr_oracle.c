@@ -851,7 +851,9 @@ or_mat *or_multipass(int n, const long *rp, const int *ci, const double *v,
 /* ------------------------------------------------------------------ */
 #define OR_MAXLEV 64
 struct or_amg {
-  int nlev;                   /* levels 0..nlev-1; the last is solved directly */
+  int nlev;                   /* levels 0..nlev-1; the last is solved directly,
+                                 or relaxed when larger than max_dense */
+  int relax_coarsest;         /* 1: the coarsest level gets 2 * nsweeps sweeps, no LU */
   or_mat *A[OR_MAXLEV], *P[OR_MAXLEV], *R[OR_MAXLEV];
   int *cf[OR_MAXLEV], *func[OR_MAXLEV];
   double *dinv[OR_MAXLEV];
@@ -870,6 +872,7 @@ void or_amg_opts_default(or_amg_opts *o) {
   o->agg_levels = 1;
   o->num_sweeps = 1;
   o->hmis_block = 0;
+  o->max_dense = 4096;
 }
 
 /* l1-Jacobi (Baker, Falgout, Kolev, Yang 2011) with one point per block:
@@ -966,6 +969,7 @@ int or_amg_setup(int n, const long *rp, const int *ci, const double *v,
   if (o.max_levels < 1 || o.max_levels > OR_MAXLEV) return fail(OR_E_INVALID, "max_levels");
   if (o.num_sweeps < 1) return fail(OR_E_INVALID, "num_sweeps");
   if (o.hmis_block < 0) return fail(OR_E_INVALID, "hmis_block");
+  if (o.max_dense < 0) return fail(OR_E_INVALID, "max_dense");
   or_amg *a = xcalloc(1, sizeof *a);
   a->nsweeps = o.num_sweeps;
   a->A[0] = mat_from(n, n, rp, ci, v);
@@ -1006,7 +1010,10 @@ int or_amg_setup(int n, const long *rp, const int *ci, const double *v,
     l++;
   }
   a->nlev = l + 1;
-  for (int k = 0; k < a->nlev - 1; k++) {
+  or_mat *Ac = a->A[a->nlev - 1];
+  a->nd = Ac->n;
+  a->relax_coarsest = Ac->n > o.max_dense;
+  for (int k = 0; k < a->nlev - 1 + a->relax_coarsest; k++) {
     a->dinv[k] = xmalloc(sizeof(double) * (size_t)a->A[k]->n);
     int st = l1_diag(a->A[k], a->dinv[k]);
     if (st != OR_OK) {
@@ -1014,10 +1021,12 @@ int or_amg_setup(int n, const long *rp, const int *ci, const double *v,
       return st;
     }
   }
-  /* coarsest: dense LU */
-  or_mat *Ac = a->A[a->nlev - 1];
-  a->nd = Ac->n;
   a->cf[a->nlev - 1] = xcalloc((size_t)Ac->n, sizeof(int));
+  if (a->relax_coarsest) {
+    *out = a;
+    return OR_OK;
+  }
+  /* coarsest: dense LU */
   a->lu = xcalloc((size_t)Ac->n * Ac->n, sizeof(double));
   a->piv = xmalloc(sizeof(int) * (size_t)Ac->n);
   for (int i = 0; i < Ac->n; i++)
@@ -1052,10 +1061,14 @@ void or_amg_get_dinv(const or_amg *a, int l, double *d) {
  * "first-order relaxation", read as nsweeps l1-Jacobi sweeps before and after
  * the coarse correction, one by default).  A sweep is x += D^-1 (b - A x); the
  * first pre-sweep starts from x = 0, so it is x = D^-1 b. */
+/* A coarsest level larger than max_dense (coarsening stopped early) is not
+ * solved: it is smoothed like the other levels with no coarse correction,
+ * nsweeps sweeps before and nsweeps after. */
 static void vcycle_level(const or_amg *a, int l, const double *b, double *x) {
   const or_mat *A = a->A[l];
   int n = A->n;
-  if (l == a->nlev - 1) {
+  const int coarsest = l == a->nlev - 1;
+  if (coarsest && !a->relax_coarsest) {
     dense_lu_solve(n, a->lu, a->piv, b, x);
     return;
   }
@@ -1067,24 +1080,26 @@ static void vcycle_level(const or_amg *a, int l, const double *b, double *x) {
     mat_vec(A, x, r);
     for (int i = 0; i < n; i++) x[i] += d[i] * (b[i] - r[i]);
   }
-  /* residual and restriction */
-  mat_vec(A, x, r);
-  for (int i = 0; i < n; i++) r[i] = b[i] - r[i];
-  int nc = a->A[l + 1]->n;
-  double *bc = xmalloc(sizeof(double) * (size_t)nc);
-  double *xc = xmalloc(sizeof(double) * (size_t)nc);
-  mat_vec(a->R[l], r, bc);
-  vcycle_level(a, l + 1, bc, xc);
-  /* prolongation and correction */
-  mat_vec(a->P[l], xc, r);
-  for (int i = 0; i < n; i++) x[i] += r[i];
+  if (!coarsest) {
+    /* residual and restriction */
+    mat_vec(A, x, r);
+    for (int i = 0; i < n; i++) r[i] = b[i] - r[i];
+    int nc = a->A[l + 1]->n;
+    double *bc = xmalloc(sizeof(double) * (size_t)nc);
+    double *xc = xmalloc(sizeof(double) * (size_t)nc);
+    mat_vec(a->R[l], r, bc);
+    vcycle_level(a, l + 1, bc, xc);
+    /* prolongation and correction */
+    mat_vec(a->P[l], xc, r);
+    for (int i = 0; i < n; i++) x[i] += r[i];
+    free(bc);
+    free(xc);
+  }
   /* post-smoothing */
   for (int s = 0; s < a->nsweeps; s++) {
     mat_vec(A, x, r);
     for (int i = 0; i < n; i++) x[i] += d[i] * (b[i] - r[i]);
   }
-  free(bc);
-  free(xc);
   free(r);
 }
 void or_amg_vcycle(const or_amg *a, const double *b, double *x) { vcycle_level(a, 0, b, x); }

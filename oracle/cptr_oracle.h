@@ -74,6 +74,8 @@ typedef struct {
   int agg_levels;      /* 1: levels coarsened aggressively (multipass interpolation) */
   int num_sweeps;      /* 1: l1-Jacobi sweeps before and after the coarse correction */
   int hmis_block;      /* 0: points per HMIS block (0: one block per level) */
+  int max_dense;       /* 4096: largest coarsest level solved by dense LU; a larger
+                          one (coarsening stopped early) is smoothed instead */
 } or_amg_opts;
 void or_amg_opts_default(or_amg_opts *o);
 

@@ -52,7 +52,7 @@ class cptr_setup_opts(C.Structure):
                 ("ilu_sweep", C.c_int32), ("agg_levels", C.c_int32),
                 ("precond_precision", C.c_int32), ("num_sweeps", C.c_int32),
                 ("max_restart", C.c_int32), ("flexible_space", C.c_int32),
-                ("hmis_block", C.c_int32)]
+                ("hmis_block", C.c_int32), ("max_dense_coarse", C.c_int32)]
 
 
 class cptr_solve_opts(C.Structure):

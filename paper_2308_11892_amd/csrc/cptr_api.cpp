@@ -581,16 +581,18 @@ int build_prec(cptr_solver s, PrecDev<T>& d, const std::vector<int32_t>& fp,
     const AmgLevel& hl = h.lev[l];
     auto& dl = d.lev[l];
     dl.n = hl.A.n;
-    if (l > 0 && l + 1 < L && (rc = upload_level_op(s, dl, hl.A, st))) return rc;
+    // smoothed: every level but a coarsest one solved by dense LU
+    const bool smoothed = l + 1 < L || h.coarse_relax;
+    if (l > 0 && smoothed && (rc = upload_level_op(s, dl, hl.A, st))) return rc;
     if (l + 1 < L) {
       if ((rc = upload_csr(s, dl.P, hl.P, st))) return rc;
       if ((rc = upload_csr(s, dl.R, hl.R, st))) return rc;
-      if ((rc = upload_as(s, dl.dinv, hl.dinv.data(), (int64_t)hl.dinv.size(), st))) return rc;
     }
+    if (smoothed && (rc = upload_as(s, dl.dinv, hl.dinv.data(), (int64_t)hl.dinv.size(), st))) return rc;
     if ((rc = dalloc(s, dl.b, dl.n)) || (rc = dalloc(s, dl.r, dl.n)) || (rc = dalloc(s, dl.x, dl.n)) ||
         (rc = dalloc(s, dl.e, dl.n)))
       return rc;
-    if (s->nsweeps > 1 && l + 1 < L && (rc = dalloc(s, dl.t, dl.n))) return rc;
+    if (s->nsweeps > 1 && smoothed && (rc = dalloc(s, dl.t, dl.n))) return rc;
   }
   const int64_t N = (int64_t)nb * 3;
   if (!s->use_grid && ((rc = dalloc(s, d.r2, N)) || (rc = dalloc(s, d.y, N)) || (rc = dalloc(s, d.x2, N))))
@@ -800,8 +802,9 @@ void ph_harvest(cptr_solver s) {  // call after the stream is synchronised
 template <class T>
 void enqueue_restrict(cptr_solver s, PrecDev<T>& d, const double* r, hipStream_t st) {
   auto& l0 = d.lev[0];
-  launch_l0_restrict(s->host.nb, s->ne, r, s->W, s->eidx_h, s->hidx_h, l0.b, d.lev.size() > 1 ? l0.dinv : nullptr,
-                     l0.x, st);
+  const bool smoothed = d.lev.size() > 1 || s->host.coarse_relax;
+  launch_l0_restrict(s->host.nb, s->ne, r, s->W, s->eidx_h, s->hidx_h, l0.b, smoothed ? l0.dinv : nullptr, l0.x,
+                     st);
 }
 void enqueue_restrict(cptr_solver s, const double* r, hipStream_t st) {
   if (s->prec == CPTR_PRECISION_FP32)
@@ -822,7 +825,8 @@ void enqueue_stage1(cptr_solver s, PrecDev<T>& d, const double* r, hipStream_t s
     enqueue_restrict(s, d, r, st);
     ph_end(s, st, PH_RESTRICT, ev);
   }
-  if (L == 1) {
+  const bool relax = s->host.coarse_relax;
+  if (L == 1 && !relax) {
     ph_begin(s, st, PH_VCC, ev);
     launch_coarse_solve(s->ncoarse, s->coarse_lu, s->coarse_piv, l0.b, l0.e, st);
     ph_end(s, st, PH_VCC, ev);
@@ -847,18 +851,33 @@ void enqueue_stage1(cptr_solver s, PrecDev<T>& d, const double* r, hipStream_t s
       }
       cur[(size_t)l] = c;
     };
+    // one sweep out = in + D^-1 (b - A in) on level l
+    auto post_l = [&](int l, const T* in, T* out) {
+      auto& dl = d.lev[l];
+      if (l == 0)
+        launch_l0_post(d.Ahat, ne, in, dl.b, dl.dinv, out, st);
+      else if (dl.sell)
+        launch_sell_post(dl.As, in, dl.b, dl.dinv, out, st);
+      else
+        launch_csr_post(dl.A, in, dl.b, dl.dinv, out, st);
+    };
+    // a coarsest level above the dense limit: its pre-smoothing sweeps, no
+    // coarse correction, its post-smoothing sweeps; the result goes to e
+    auto relax_coarsest = [&](int l) {
+      auto& dl = d.lev[l];
+      presmooth(l);
+      T* c = cur[(size_t)l];
+      for (int k = 0; k < ns; ++k) {
+        T* n = k + 1 == ns ? dl.e : (c == dl.x ? dl.t : dl.x);
+        post_l(l, c, n);
+        c = n;
+      }
+    };
     // coarse correction and post-smoothing of level l; the result goes to e
     auto correct = [&](int l) {
       auto& dl = d.lev[l];
       const T* ec = d.lev[l + 1].e;
-      auto post = [&](const T* in, T* out) {
-        if (l == 0)
-          launch_l0_post(d.Ahat, ne, in, dl.b, dl.dinv, out, st);
-        else if (dl.sell)
-          launch_sell_post(dl.As, in, dl.b, dl.dinv, out, st);
-        else
-          launch_csr_post(dl.A, in, dl.b, dl.dinv, out, st);
-      };
+      auto post = [&](const T* in, T* out) { post_l(l, in, out); };
       if (ns == 1) {
         // x = D^-1 b + P ec recomputes the one pre-smoothing sweep
         launch_csr_prolong(dl.P, ec, dl.b, dl.dinv, dl.x, st);
@@ -874,12 +893,18 @@ void enqueue_stage1(cptr_solver s, PrecDev<T>& d, const double* r, hipStream_t s
         o = n;
       }
     };
+    if (L == 1) {  // level 0 is a coarsest level above the dense limit
+      ph_begin(s, st, PH_VC0, ev);
+      relax_coarsest(0);
+      ph_end(s, st, PH_VC0, ev);
+      return;
+    }
     ph_begin(s, st, PH_VC0, ev);
     // restrictions to a smoothed level also write its pre-smoothed iterate
     // x = D^-1 b, which its residual then reads
     auto restrict_to = [&](int l, const T* r) {
       auto& nx = d.lev[l + 1];
-      if (l + 2 < L)
+      if (l + 2 < L || relax)
         launch_csr_restrict(d.lev[l].R, r, nx.dinv, nx.b, nx.x, st);
       else
         launch_csr_spmv(d.lev[l].R, r, nx.b, st);
@@ -898,7 +923,10 @@ void enqueue_stage1(cptr_solver s, PrecDev<T>& d, const double* r, hipStream_t s
         launch_csr_resid(dl.A, cur[(size_t)l], dl.b, dl.r, st);
       restrict_to(l, dl.r);
     }
-    launch_coarse_solve(s->ncoarse, s->coarse_lu, s->coarse_piv, d.lev[L - 1].b, d.lev[L - 1].e, st);
+    if (relax)
+      relax_coarsest(L - 1);
+    else
+      launch_coarse_solve(s->ncoarse, s->coarse_lu, s->coarse_piv, d.lev[L - 1].b, d.lev[L - 1].e, st);
     for (int l = L - 2; l >= 1; --l) correct(l);
     ph_end(s, st, PH_VCC, ev);
     ph_begin(s, st, PH_VC0, ev);
@@ -1459,6 +1487,7 @@ void cptr_setup_opts_default(cptr_setup_opts* o) {
   o->max_restart = 50;
   o->flexible_space = 1;
   o->hmis_block = 0;
+  o->max_dense_coarse = 4096;
 }
 
 void cptr_solve_opts_default(cptr_solve_opts* o) {
@@ -1508,7 +1537,7 @@ int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_id
   if (o.flexible_space != 0 && o.flexible_space != 1)
     return (cptr_status)fail(nullptr, CPTR_E_INVALID, "flexible_space must be 0 or 1");
   if (o.max_levels < 1 || o.max_levels > 64 || o.max_coarse < 1 || o.p_max_elmts < 0 ||
-      o.agg_levels < 0 || o.hmis_block < 0 ||
+      o.agg_levels < 0 || o.hmis_block < 0 || o.max_dense_coarse < 0 || o.max_dense_coarse > 4096 ||
       !(o.strong_threshold >= 0.0) || !(o.max_row_sum > 0.0))
     return (cptr_status)fail(nullptr, CPTR_E_INVALID, "setup options out of range");
   if (A->n_block_rows <= 0 || A->nnz_blocks <= 0 || A->nnz_blocks >= INT32_MAX)
@@ -1566,6 +1595,7 @@ int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_id
   prm.pmax = o.p_max_elmts;
   prm.agg_levels = o.agg_levels;
   prm.hmis_block = o.hmis_block;
+  prm.max_dense_coarse = o.max_dense_coarse;
   prm.quasi_impes = o.restriction == CPTR_RESTRICT_QUASI_IMPES;
   unsigned hw = std::thread::hardware_concurrency();
   prm.threads = o.setup_threads > 0 ? o.setup_threads : (int)std::min<unsigned>(16, hw ? hw : 1);
@@ -2075,7 +2105,7 @@ cptr_status cptr_export(cptr_solver s, int32_t what, int32_t level, void* buf, i
     case CPTR_EXPORT_W:
       return put(h.W.data(), (int64_t)h.W.size() * 8);
     case CPTR_EXPORT_DINV:
-      if (!has_p) break;
+      if (!has_p && !(h.coarse_relax && level + 1 == (int)h.lev.size())) break;
       return put(h.lev[level].dinv.data(), (int64_t)h.lev[level].dinv.size() * 8);
     case CPTR_EXPORT_ILU_VALS:
       if (s->device_ilu)

@@ -1121,16 +1121,15 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
     next.func = std::move(fc);
     h.lev.push_back(std::move(next));
   }
-  for (size_t l = 0; l + 1 < h.lev.size(); ++l) {
+  // a coarsest level above the dense limit (the coarsening stopped early) is
+  // smoothed like the others, with no coarse correction
+  h.coarse_relax = h.lev.back().A.n > prm.max_dense_coarse;
+  for (size_t l = 0; l + 1 < h.lev.size() + (h.coarse_relax ? 1 : 0); ++l) {
     int st = l1_inverse_diag(h.lev[l].A, h.lev[l].dinv, threads, err);
     if (st != CPTR_OK) return st;
   }
-  {
+  if (!h.coarse_relax) {
     const Csr& Ac = h.lev.back().A;
-    if (Ac.n > prm.max_dense_coarse)
-      return err = "AMG coarsening stalled at " + std::to_string(Ac.n) +
-                   " rows, above the dense coarse-solve limit",
-             CPTR_E_SINGULAR_COARSE;
     h.coarse_lu.assign((size_t)Ac.n * Ac.n, 0.0);
     for (int32_t i = 0; i < Ac.n; ++i)
       for (int64_t k = Ac.rp[i]; k < Ac.rp[i + 1]; ++k) h.coarse_lu[(size_t)i * Ac.n + Ac.ci[k]] += Ac.v[k];

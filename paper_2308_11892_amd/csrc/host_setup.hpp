@@ -103,7 +103,7 @@ struct SetupParams {
   int agg_levels = 1;           // levels coarsened aggressively (multipass interpolation)
   bool quasi_impes = true;
   int threads = 1;
-  int max_dense_coarse = 4096;  // largest coarsest level solved by dense LU
+  int max_dense_coarse = 4096;  // largest coarsest level solved by dense LU (a larger one is smoothed)
   int32_t hmis_block = 0;       // points per HMIS block, 0 = one block per level
   bool skip_ilu = false;        // ILU(0) is factored elsewhere (on the device)
   // the steps of the level with operator A done elsewhere (null: all here):
@@ -122,6 +122,7 @@ struct HostSetup {
   std::vector<int32_t> diag;   // position of the diagonal block of each row
   std::vector<double> W;       // [nb][ne][nh]
   std::vector<AmgLevel> lev;   // lev.back() is the coarsest level
+  bool coarse_relax = false;      // coarsest level above the dense limit: smoothed, no LU
   std::vector<double> coarse_lu;  // dense LU of the coarsest matrix, row-major
   std::vector<int32_t> coarse_piv;
   std::vector<double> ilu;     // [nnzb][3][3]: L blocks left of the diagonal, U on/right

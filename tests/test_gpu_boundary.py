@@ -1,7 +1,9 @@
 """GPU checks of the boundary's options: more l1-Jacobi sweeps per level
 (cptr_setup_opts.num_sweeps) against the oracle's V-cycle with the same
-count, the Krylov space allocated at setup (max_restart, flexible_space) and
-the sweeps' wait-limit report (cptr_sweep_check).
+count, a coarsest level above the dense limit smoothed instead of factored
+(max_dense_coarse, and a coarsening that stops at level 0), the Krylov space
+allocated at setup (max_restart, flexible_space) and the sweeps' wait-limit
+report (cptr_sweep_check).
 
 Bars as in the parity tests: one application within 1e-10 relative of the
 oracle, GMRES iterations within +-1 and the true residual at the tolerance.
@@ -59,6 +61,66 @@ def test_num_sweeps_parity(name, sweeps):
     _, oinfo = ref.gmres(c.b, restart=30, rtol=c.tol)
     say(f"  gpu {info['iterations']} it, oracle {oinfo['iterations']} it")
     assert info["converged"] and abs(info["iterations"] - oinfo["iterations"]) <= 1
+
+
+@pytest.mark.parametrize("name,sweeps,maxd,levels", [("grid20x20x5", 1, 0, 25), ("grid20x20x5", 2, 0, 25),
+                                                     ("prism2000x5", 1, 100, 3), ("grid33x17x2", 2, 0, 25),
+                                                     ("grid20x20x5", 1, 100, 1)])
+def test_relaxed_coarsest_parity(name, sweeps, maxd, levels):
+    """max_dense_coarse below the coarsest level's size: that level gets
+    num_sweeps sweeps before and after a zero coarse correction; the first
+    stage, one application and the GMRES iterations match the oracle's
+    V-cycle with the same limit."""
+    c = J.by_name(name)
+    say(f"[relaxed coarsest] {name} num_sweeps={sweeps} max_dense={maxd} max_levels={levels}")
+    ref = O.Cptr(c.row_ptr, c.col_idx, c.values, num_sweeps=sweeps, max_dense=maxd, max_levels=levels)
+    r = np.random.default_rng(33).standard_normal(c.n_dof)
+    x1o, zo = ref.stage1(r), ref.apply(r)
+    with L.Solver(c.row_ptr, c.col_idx, c.values, num_sweeps=sweeps, max_dense_coarse=maxd,
+                  max_levels=levels) as s:
+        rows, _ = s.hierarchy()
+        assert rows[-1] > maxd
+        rd = dev(r)
+        x1 = torch.empty_like(rd)
+        z = torch.empty_like(rd)
+        s.stage1(rd, x1)
+        s.apply(rd, z)
+        e1 = np.linalg.norm(host(x1) - x1o) / np.linalg.norm(x1o)
+        ez = np.linalg.norm(host(z) - zo) / np.linalg.norm(zo)
+        assert e1 <= 1e-10 and ez <= 1e-10, (e1, ez)
+        b = dev(c.b)
+        x = torch.zeros_like(b)
+        info = s.gmres_solve(b, x, restart=30, rtol=c.tol)
+    _, oinfo = ref.gmres(c.b, restart=30, rtol=c.tol)
+    say(f"  gpu {info['iterations']} it, oracle {oinfo['iterations']} it")
+    assert info["converged"] and abs(info["iterations"] - oinfo["iterations"]) <= 1
+
+
+@pytest.mark.parametrize("prec", [L.PRECISION_FP64, L.PRECISION_FP32])
+def test_stalled_coarsening_solves(prec):
+    """250x250x2: no strong link on level 0, so the hierarchy is level 0
+    alone, 250,000 rows, smoothed rather than factored.  One application
+    matches the oracle (1e-10 in FP64, 1e-3 with the FP32 preconditioner) and
+    FGMRES converges in the oracle's iterations (+-1; +2 in FP32)."""
+    c = J.by_name("grid250x250x2")
+    say(f"[stalled coarsening] grid250x250x2 precision={prec}")
+    ref = O.Cptr(c.row_ptr, c.col_idx, c.values)
+    r = np.random.default_rng(34).standard_normal(c.n_dof)
+    zo = ref.apply(r)
+    with L.Solver(c.row_ptr, c.col_idx, c.values, precond_precision=prec) as s:
+        rows, _ = s.hierarchy()
+        assert list(rows) == [2 * c.n_cells]
+        z = torch.empty(c.n_dof, dtype=torch.float64, device=DEV)
+        s.apply(dev(r), z)
+        ez = np.linalg.norm(host(z) - zo) / np.linalg.norm(zo)
+        assert ez <= (1e-10 if prec == L.PRECISION_FP64 else 1e-3), ez
+        b = dev(c.b)
+        x = torch.zeros_like(b)
+        info = s.gmres_solve(b, x, restart=50, flexible=True, rtol=c.tol)
+    _, oinfo = ref.gmres(c.b, restart=50, flexible=True, rtol=c.tol)
+    say(f"  gpu {info['iterations']} it, oracle {oinfo['iterations']} it")
+    slack = 1 if prec == L.PRECISION_FP64 else 2
+    assert info["converged"] and abs(info["iterations"] - oinfo["iterations"]) <= slack
 
 
 def test_num_sweeps_fp32():

@@ -37,8 +37,9 @@ def test_defaults_follow_the_paper():
     # one l1-Jacobi sweep on each side; the Krylov space of FGMRES(50) is
     # allocated at setup
     assert (o.num_sweeps, o.max_restart, o.flexible_space) == (1, 50, 1)
-    # one HMIS block per level: the first pass over the whole level
-    assert o.hmis_block == 0
+    # one HMIS block per level: the first pass over the whole level; coarsest
+    # levels up to 4096 rows solved exactly
+    assert o.hmis_block == 0 and o.max_dense_coarse == 4096
 
 
 @pytest.mark.parametrize("case,agg", [("grid20x20x5", 1), ("grid6x5x4", 1), ("grid12x1x1", 1),
@@ -146,7 +147,8 @@ def test_invalid_arguments():
     assert "diagonal" in msg and "4" in msg
     for kw, word in [(dict(num_sweeps=0), "num_sweeps"), (dict(num_sweeps=9), "num_sweeps"),
                      (dict(max_restart=0), "max_restart"), (dict(max_restart=65), "max_restart"),
-                     (dict(flexible_space=2), "flexible_space"), (dict(hmis_block=-1), "range")]:
+                     (dict(flexible_space=2), "flexible_space"), (dict(hmis_block=-1), "range"),
+                     (dict(max_dense_coarse=-1), "range"), (dict(max_dense_coarse=4097), "range")]:
         msg = _expect(L.CPTR_E_INVALID, lambda: L.Solver(c.row_ptr, c.col_idx, c.values, host_only=1, **kw))
         assert word in msg, msg
 
@@ -213,6 +215,39 @@ def test_coarsening_limit_reports_stall():
     s = L.Solver(c.row_ptr, c.col_idx, c.values, host_only=1, max_levels=1)
     rows, _ = s.hierarchy()
     assert len(rows) == 1 and rows[0] == 2 * c.n_cells
+
+
+@pytest.mark.parametrize("case,maxd,levels", [("grid20x20x5", 0, 25), ("grid20x20x5", 50, 2),
+                                               ("prism2000x5", 100, 3), ("grid12x1x1", 0, 1)])
+def test_relaxed_coarsest_matches_oracle(case, maxd, levels):
+    """A coarsest level above max_dense_coarse is smoothed, not factored: the
+    library forms its l1 diagonal (and no LU) exactly as the oracle does with
+    the same limit, on top of the same hierarchy."""
+    c = J.by_name(case)
+    h = O.Cptr(c.row_ptr, c.col_idx, c.values, max_dense=maxd, max_levels=levels)
+    s = host_solver(c, max_dense_coarse=maxd, max_levels=levels)
+    rows, _ = s.hierarchy()
+    a = h.amg
+    assert len(rows) == a.nlevels and rows[-1] > maxd
+    last = a.nlevels - 1
+    for l in range(a.nlevels):
+        Al, Ao = s.level_matrix(l, "A"), a.A(l)
+        assert np.array_equal(Al.indices, Ao.indices) and np.array_equal(Al.data, Ao.data)
+    dv = s.export("DINV", last, int(rows[last]))
+    assert np.array_equal(dv, a.dinv(last))
+
+
+def test_stalled_coarsening_is_relaxed():
+    """On the 250x250x2 grid no row of level 0 passes the row-sum test, so the
+    strength graph is empty, the first split has no C point and level 0 is the
+    coarsest with 250,000 rows: it is smoothed (the setup used to refuse it
+    with CPTR_E_SINGULAR_COARSE)."""
+    c = J.by_name("grid250x250x2")
+    s = host_solver(c)
+    rows, _ = s.hierarchy()
+    assert list(rows) == [2 * c.n_cells]
+    dv = s.export("DINV", 0, int(rows[0]))
+    assert np.all(np.isfinite(dv)) and np.all(dv != 0.0)
 
 
 def test_fp32_preconditioner_options():

@@ -495,6 +495,55 @@ def test_two_grid_matrix_form(sweeps):
     assert np.abs(B - Bref).max() <= 1e-12 * np.abs(Bref).max()
 
 
+@pytest.mark.parametrize("sweeps", [1, 2])
+def test_relaxed_one_level_is_jacobi_from_zero(sweeps):
+    """A single level above the dense limit (max_dense = 0) is smoothed, not
+    solved: 2 * sweeps l1-Jacobi sweeps from zero, x = sum_{k < 2s} (I - D A)^k D b
+    with D the l1 inverse diagonal computed here from its definition."""
+    A = lap3d(4, 3, 3, rng=np.random.default_rng(5))
+    n = A.shape[0]
+    amg = O.Amg(A, np.zeros(n, dtype=np.int32), max_levels=1, num_sweeps=sweeps, max_dense=0)
+    Ad = A.toarray()
+    d = np.diag(Ad)
+    l1 = d + np.sign(d) * (np.abs(Ad).sum(axis=1) - np.abs(d))
+    D = np.diag(1.0 / l1)
+    I = np.eye(n)
+    G = I - D @ Ad
+    Bref = sum(np.linalg.matrix_power(G, k) for k in range(2 * sweeps)) @ D
+    B = np.column_stack([amg.vcycle(e) for e in np.eye(n)])
+    assert np.abs(B - Bref).max() <= 1e-12 * np.abs(Bref).max()
+    assert np.allclose(amg.dinv(0), 1.0 / l1, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("sweeps", [1, 2])
+def test_two_grid_with_relaxed_coarse_level(sweeps):
+    """Two levels with the coarse one above the dense limit: the coarse
+    'solve' is its own 2 * sweeps Jacobi sweeps, Bc = (I - Gc^(2s)) Ac^-1, and
+    the cycle's error propagation is S^s (I - P Bc P^T A) S^s."""
+    A = lap3d(4, 4, 3, rng=np.random.default_rng(8))
+    n = A.shape[0]
+    amg = O.Amg(A, np.zeros(n, dtype=np.int32), max_levels=2, num_sweeps=sweeps, max_dense=0)
+    P = amg.P(0).toarray()
+    Ad = A.toarray()
+    I = np.eye(n)
+    D = np.diag(amg.dinv(0))
+    Ac = P.T @ Ad @ P
+    dc = np.diag(Ac)
+    Dc = np.diag(1.0 / (dc + np.sign(dc) * (np.abs(Ac).sum(axis=1) - np.abs(dc))))
+    Ic = np.eye(Ac.shape[0])
+    Bc = (Ic - np.linalg.matrix_power(Ic - Dc @ Ac, 2 * sweeps)) @ np.linalg.inv(Ac)
+    S = np.linalg.matrix_power(I - D @ Ad, sweeps)
+    E = S @ (I - P @ Bc @ P.T @ Ad) @ S
+    Bref = (I - E) @ np.linalg.inv(Ad)
+    B = np.column_stack([amg.vcycle(e) for e in np.eye(n)])
+    assert np.abs(B - Bref).max() <= 1e-12 * np.abs(Bref).max()
+    # below the limit the same hierarchy solves its coarse level exactly
+    exact = O.Amg(A, np.zeros(n, dtype=np.int32), max_levels=2, num_sweeps=sweeps)
+    Ee = S @ (I - P @ np.linalg.solve(Ac, P.T @ Ad)) @ S
+    Be = np.column_stack([exact.vcycle(e) for e in np.eye(n)])
+    assert np.abs(Be - (I - Ee) @ np.linalg.inv(Ad)).max() <= 1e-12 * np.abs(Bref).max()
+
+
 def _vcycle_factor(m, agg=0, block=0):
     rng = np.random.default_rng(10)
     A0 = lap3d(m, m, m)
