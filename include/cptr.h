@@ -55,7 +55,7 @@ typedef enum {
   CPTR_E_INVALID = -1,         /* bad argument; message names field and row */
   CPTR_E_NOMEM = -2,           /* host or device allocation failed */
   CPTR_E_ZERO_PIVOT = -3,      /* zero ILU(0) pivot, singular hyperbolic block or zero smoother diagonal */
-  CPTR_E_SINGULAR_COARSE = -4, /* coarsest AMG matrix singular or too large */
+  CPTR_E_SINGULAR_COARSE = -4, /* coarsest AMG matrix (solved by dense LU) singular */
   CPTR_E_HIP = -5,             /* a HIP runtime call failed */
   CPTR_E_STATE = -6            /* call not valid for this handle (e.g. host-only setup) */
 } cptr_status;
