@@ -378,6 +378,8 @@ def main():
                     help="requests of the serving sub-object of the default run (0: none)")
     ap.add_argument("--no-unstructured", action="store_true",
                     help="leave out the unstructured (1M-cell prism mesh) sub-object")
+    ap.add_argument("--warm-setups", type=int, default=3, metavar="N",
+                    help="after the FP64 solves, N more setups of the workload (setup_warm_s)")
     ap.add_argument("--setup-only", type=int, default=0, metavar="N",
                     help="instead of the solve benchmark, run N setups of the workload (the first "
                          "a warm-up) and print their step times; for a kernel trace of the setup")
@@ -513,6 +515,19 @@ def main():
     }
     x64 = x.cpu().numpy()
     s.close()
+    if args.warm_setups > 0:
+        # setups after the first in the process (no one-time initialisation):
+        # what each linear solve of a simulation pays
+        log(f"{args.warm_setups} more setups")
+        runs = []
+        for k in range(args.warm_setups):
+            t0 = time.perf_counter()
+            with L.Solver(c.row_ptr, c.col_idx, c.values) as sw:
+                total = float(sw.export("SETUP_TIMES", 0, 10)[L.SETUP_STEPS.index("total")])
+            runs.append({"library_s": round(total, 4), "wall_s": round(time.perf_counter() - t0, 4)})
+        out["setup_warm_s"] = {"median": float(np.median([r["library_s"] for r in runs])), "runs": runs,
+                               "note": "setup_s is the first setup in the process (one-time initialisation "
+                                       "included); these are the following ones"}
     x32h = None
     if args.precision == "both":
         log("mixed precision: FP32 preconditioner, FP64 FGMRES; setup")

@@ -34,6 +34,140 @@ namespace {
 
 thread_local std::string g_setup_error;
 
+// ---------------------------------------------------------------------------
+// Large copies between pageable host memory and the device.  Copies from or
+// to pageable memory run well below the link's rate (the runtime stages them
+// itself; ~4 GB/s device to host, ~22 GB/s host to device here), so large ones
+// go through pinned buffers in chunks: the DMA of one chunk overlaps the host
+// copy of the next (or the previous) one, and the host copies are split over
+// threads.  The pinned buffers live as long as the process and are shared by
+// the setups in flight on a device, one pair each (a pair's events belong to
+// the device it was made on).
+namespace staged {
+
+constexpr size_t kChunk = size_t(16) << 20;  // bytes per chunk and buffer
+constexpr size_t kDirect = size_t(2) << 20;  // smaller copies go direct
+
+struct Pair {
+  int device = -1;
+  char* buf[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+std::mutex g_mu;
+std::vector<Pair> g_free;  // idle pairs
+
+// a pair for the current device (false: copy directly)
+bool take(Pair& p) {
+  if (hipGetDevice(&p.device) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  {
+    std::lock_guard<std::mutex> g(g_mu);
+    for (size_t k = 0; k < g_free.size(); ++k)
+      if (g_free[k].device == p.device) {
+        p = g_free[k];
+        g_free.erase(g_free.begin() + (ptrdiff_t)k);
+        return true;
+      }
+  }
+  for (int b = 0; b < 2; ++b) {
+    void* q = nullptr;
+    if (hipHostMalloc(&q, kChunk, hipHostMallocDefault) != hipSuccess ||
+        (p.buf[b] = static_cast<char*>(q), hipEventCreateWithFlags(&p.ev[b], hipEventDisableTiming)) != hipSuccess) {
+      (void)hipGetLastError();
+      for (int c = 0; c <= b; ++c) {
+        if (p.buf[c]) (void)hipHostFree(p.buf[c]);
+        if (p.ev[c]) (void)hipEventDestroy(p.ev[c]);
+      }
+      return false;
+    }
+  }
+  return true;
+}
+
+void give(const Pair& p) {
+  std::lock_guard<std::mutex> g(g_mu);
+  g_free.push_back(p);
+}
+
+// dst[0, n) = src[0, n) on the host, split over threads in pieces of >= 1 MB
+void host_copy(char* dst, const char* src, size_t n, int threads) {
+  const int64_t pieces = std::max<int64_t>(1, std::min<int64_t>(threads, (int64_t)(n >> 20)));
+  if (pieces == 1) {
+    std::memcpy(dst, src, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int64_t k = 1; k < pieces; ++k)
+    th.emplace_back([=] {
+      const size_t lo = n * k / pieces, hi = n * (k + 1) / pieces;
+      std::memcpy(dst + lo, src + lo, hi - lo);
+    });
+  std::memcpy(dst, src, n / pieces);
+  for (auto& t : th) t.join();
+}
+
+// device -> pageable host, after the stream's earlier work; complete on return
+hipError_t to_host(void* dst, const void* src, size_t n, hipStream_t st, int threads) {
+  hipError_t e;
+  Pair p;
+  if (n < kDirect || !take(p)) {
+    if ((e = hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    return hipStreamSynchronize(st);
+  }
+  char* d = static_cast<char*>(dst);
+  const char* q = static_cast<const char*>(src);
+  const size_t nc = (n + kChunk - 1) / kChunk;
+  auto len = [&](size_t i) { return std::min(kChunk, n - i * kChunk); };
+  e = hipSuccess;
+  for (size_t i = 0; i <= nc && e == hipSuccess; ++i) {
+    // chunk i's DMA goes out before the host copies chunk i - 1 (buffer
+    // (i - 1) & 1); chunk i + 1 reuses buffer (i + 1) & 1 only after that copy
+    if (i < nc) {
+      e = hipMemcpyAsync(p.buf[i & 1], q + i * kChunk, len(i), hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipEventRecord(p.ev[i & 1], st);
+    }
+    if (i > 0 && e == hipSuccess) {
+      e = hipEventSynchronize(p.ev[(i - 1) & 1]);
+      if (e == hipSuccess) host_copy(d + (i - 1) * kChunk, p.buf[(i - 1) & 1], len(i - 1), threads);
+    }
+  }
+  if (e != hipSuccess) (void)hipStreamSynchronize(st);  // no DMA left into the pair
+  give(p);
+  return e;
+}
+
+// pageable host -> device on the stream; the source may die on return (the
+// copies into pinned memory are done, and the DMAs complete before return)
+hipError_t to_device(void* dst, const void* src, size_t n, hipStream_t st, int threads) {
+  hipError_t e;
+  Pair p;
+  if (n < kDirect || !take(p)) {
+    if ((e = hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
+    return hipStreamSynchronize(st);
+  }
+  char* d = static_cast<char*>(dst);
+  const char* q = static_cast<const char*>(src);
+  const size_t nc = (n + kChunk - 1) / kChunk;
+  e = hipSuccess;
+  for (size_t i = 0; i < nc && e == hipSuccess; ++i) {
+    const size_t m = std::min(kChunk, n - i * kChunk);
+    // buffer i & 1 is free once chunk i - 2's DMA is done
+    if (i >= 2) e = hipEventSynchronize(p.ev[i & 1]);
+    if (e != hipSuccess) break;
+    host_copy(p.buf[i & 1], q + i * kChunk, m, threads);
+    e = hipMemcpyAsync(d + i * kChunk, p.buf[i & 1], m, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipEventRecord(p.ev[i & 1], st);
+  }
+  const hipError_t s2 = hipStreamSynchronize(st);
+  give(p);
+  return e != hipSuccess ? e : s2;
+}
+
+}  // namespace staged
+
 constexpr int kMaxRestart = 64;
 // Rounds a wave of the one-launch sweeps polls before it gives up and raises
 // the wait-limit flag (seconds of waiting; never reached when the schedule is
@@ -294,10 +428,7 @@ int upload(cptr_solver s, T*& p, const T* src, int64_t count, hipStream_t st) {
   if (rc) return rc;
   // on the build's stream, which the kernels reading p use too, and complete
   // before returning: the host staging vectors die right after the upload
-  if (count > 0 && !s->measure) {
-    HIP_TRY(s, hipMemcpyAsync(p, src, sizeof(T) * (size_t)count, hipMemcpyHostToDevice, st));
-    HIP_TRY(s, hipStreamSynchronize(st));
-  }
+  if (count > 0 && !s->measure) HIP_TRY(s, staged::to_device(p, src, sizeof(T) * (size_t)count, st, s->threads));
   return CPTR_OK;
 }
 
@@ -677,10 +808,10 @@ int build_device(cptr_solver s, hipStream_t st) {
         while (s1 < d.nslices && h.rp[std::min<int64_t>(nb, (int64_t)(s1 + 1) * kLanes)] - q0 <= cap) ++s1;
         const int32_t q1 = h.rp[std::min<int64_t>(nb, (int64_t)s1 * kLanes)];
         if (q1 > q0) {
-          HIP_TRY(s, hipMemcpyAsync(ci_st, h.ci.data() + q0, sizeof(int32_t) * (size_t)(q1 - q0),
-                                    hipMemcpyHostToDevice, st));
-          HIP_TRY(s, hipMemcpyAsync(v_st, h.av + (size_t)q0 * 9, sizeof(double) * 9 * (size_t)(q1 - q0),
-                                    hipMemcpyHostToDevice, st));
+          HIP_TRY(s, staged::to_device(ci_st, h.ci.data() + q0, sizeof(int32_t) * (size_t)(q1 - q0), st,
+                                       s->threads));
+          HIP_TRY(s, staged::to_device(v_st, h.av + (size_t)q0 * 9, sizeof(double) * 9 * (size_t)(q1 - q0), st,
+                                       s->threads));
         }
         launch_bsr_to_sell(nb, s0 * kLanes, s1 * kLanes, rp_d, q0, ci_st, v_st, d, st);
         HIP_TRY(s, hipGetLastError());
@@ -1063,7 +1194,8 @@ struct DevCsr {
 // that piece itself.  Counts of the steps done here go to `done`.
 class DeviceLevelSteps : public LevelSteps {
  public:
-  DeviceLevelSteps(const Csr& A, SetupSiteCounts& done) : A_(A), done_(done) {
+  DeviceLevelSteps(const Csr& A, SetupSiteCounts& done, int threads)
+      : A_(A), done_(done), threads_(std::max(1, threads)) {
     ok_ = hipStreamCreateWithFlags(&st_, hipStreamNonBlocking) == hipSuccess && upload(A, a_);
   }
   ~DeviceLevelSteps() override {
@@ -1389,14 +1521,12 @@ class DeviceLevelSteps : public LevelSteps {
   template <class T>
   bool put(T*& p, const T* src, int64_t count) {
     return alloc(p, count) &&
-           (count == 0 || (hipMemcpyAsync(p, src, sizeof(T) * count, hipMemcpyHostToDevice, st_) == hipSuccess &&
-                           hipStreamSynchronize(st_) == hipSuccess));
+           (count == 0 || staged::to_device(p, src, sizeof(T) * count, st_, threads_) == hipSuccess);
   }
   // device -> host, after the stream's earlier work
   template <class T>
   bool get(T* dst, const T* src, int64_t count) {
-    if (count > 0 && hipMemcpyAsync(dst, src, sizeof(T) * count, hipMemcpyDeviceToHost, st_) != hipSuccess)
-      return false;
+    if (count > 0 && staged::to_host(dst, src, sizeof(T) * count, st_, threads_) != hipSuccess) return false;
     return hipStreamSynchronize(st_) == hipSuccess && hipGetLastError() == hipSuccess;
   }
   bool upload_pattern(const Csr& h, DevCsr& d) {
@@ -1458,6 +1588,7 @@ class DeviceLevelSteps : public LevelSteps {
 
   const Csr& A_;
   SetupSiteCounts& done_;
+  int threads_ = 1;  // host threads for the staged copies
   hipStream_t st_ = nullptr;
   bool ok_ = false;
   DevCsr a_, s_, s2_;
@@ -1585,8 +1716,8 @@ int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_id
   // too long for the kernel is formed on the host
   SetupSiteCounts sites;
   if (!o.host_only)
-    prm.level_steps = [&sites](const Csr& Al) -> std::unique_ptr<LevelSteps> {
-      return std::unique_ptr<LevelSteps>(new DeviceLevelSteps(Al, sites));
+    prm.level_steps = [&sites, &prm](const Csr& Al) -> std::unique_ptr<LevelSteps> {
+      return std::unique_ptr<LevelSteps>(new DeviceLevelSteps(Al, sites, prm.threads));
     };
   prm.theta = o.strong_threshold;
   prm.max_row_sum = o.max_row_sum;
