@@ -270,7 +270,11 @@ enum {
                                   quasi-IMPES weights and level-0 operator, strength graphs,
                                   C/F splits, interpolations (with R = P^T), Galerkin products,
                                   l1 diagonals and coarsest LU, host ILU(0) and sweep levels,
-                                  then the device half and the whole cptr_setup */
+                                  then the device half and the whole cptr_setup.  In
+                                  cptr_setup the device half's first part (A's layout, the
+                                  ILU(0) factors and the sweeps' levels) runs on a second
+                                  thread beside the AMG steps, so the steps may add up to
+                                  more than the whole */
   CPTR_EXPORT_SETUP_SITES = 12 /* int32[15]: strength graphs formed on the device and in total,
                                   extended+i interpolations on the device and in total,
                                   coarse operators R A P on the device and in total, multipass

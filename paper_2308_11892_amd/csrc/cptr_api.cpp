@@ -283,7 +283,8 @@ struct cptr_solver_s {
   int ilu_mode = CPTR_ILU_SWEEP_AUTO;
   std::string err;
   double setup_s = 0.0;
-  double device_build_s = 0.0;  // wall time of the device half
+  double device_build_s = 0.0;  // wall time of the device half (both parts)
+  bool dev_a_done = false;      // the device half's first part was built during setup_host
   int ne = 2;
   int nsweeps = 1;           // l1-Jacobi sweeps before and after the coarse correction
   int max_restart = 0;       // Krylov space of cptr_setup (cptr_setup_opts.max_restart)
@@ -676,11 +677,11 @@ int build_ilu_factors_device(cptr_solver s, PrecDev<T>& d, const std::vector<int
 }
 
 // The preconditioner's own operators in its value type T.
+// The preconditioner's operators that need only A: Ahat and the ILU factors.
 template <class T>
-int build_prec(cptr_solver s, PrecDev<T>& d, const std::vector<int32_t>& fp,
-               const std::vector<int32_t>& bp, hipStream_t st) {
+int build_prec_ilu(cptr_solver s, PrecDev<T>& d, const std::vector<int32_t>& fp,
+                   const std::vector<int32_t>& bp, hipStream_t st) {
   const HostSetup& h = s->host;
-  const int32_t nb = h.nb;
   const int ne = h.ne;
   int rc;
   // Ahat (ne x ne blocks) in A's SELL-64 slots, formed on the device from A
@@ -705,7 +706,16 @@ int build_prec(cptr_solver s, PrecDev<T>& d, const std::vector<int32_t>& fp,
   } else {
     if ((rc = build_ilu_factors_device(s, d, fp, bp, st))) return rc;
   }
-  // AMG hierarchy (the coarsest LU stays FP64 and is shared)
+  return CPTR_OK;
+}
+
+// The rest: the AMG hierarchy (the coarsest LU stays FP64 and is shared) and
+// the sweeps' work vectors.
+template <class T>
+int build_prec_amg(cptr_solver s, PrecDev<T>& d, hipStream_t st) {
+  const HostSetup& h = s->host;
+  const int32_t nb = h.nb;
+  int rc;
   const int L = (int)h.lev.size();
   d.lev.resize(L);
   for (int l = 0; l < L; ++l) {
@@ -749,6 +759,8 @@ void reset_device_state(cptr_solver s) {
   s->ncoarse = 0;
   s->p64 = PrecDev<double>();
   s->p32 = PrecDev<float>();
+  s->dev_a_done = false;
+  s->device_build_s = 0.0;
   s->restart_cap = 0;
   s->have_z = false;
   s->V = s->Z = nullptr;
@@ -760,7 +772,9 @@ void reset_device_state(cptr_solver s) {
   s->sweep_flag = nullptr;
 }
 
-int build_device(cptr_solver s, hipStream_t st) {
+// The device half's first part, which needs only A and the host steps that
+// depend on A alone (diagonals, weights, dependency levels).
+int build_device_a(cptr_solver s, hipStream_t st) {
   const HostSetup& h = s->host;
   const int32_t nb = h.nb;
   const int ne = h.ne;
@@ -879,7 +893,17 @@ int build_device(cptr_solver s, hipStream_t st) {
     if ((rc = upload(s, s->fperm, fp.data(), nb, st))) return rc;
     if ((rc = upload(s, s->bperm, bp.data(), nb, st))) return rc;
   }
-  rc = s->prec == CPTR_PRECISION_FP32 ? build_prec(s, s->p32, fp, bp, st) : build_prec(s, s->p64, fp, bp, st);
+  rc = s->prec == CPTR_PRECISION_FP32 ? build_prec_ilu(s, s->p32, fp, bp, st)
+                                      : build_prec_ilu(s, s->p64, fp, bp, st);
+  if (rc) return rc;
+  if (!s->measure) HIP_TRY(s, hipStreamSynchronize(st));
+  return CPTR_OK;
+}
+
+// The rest of the device half: the AMG hierarchy and the solve's buffers.
+int build_device_b(cptr_solver s, hipStream_t st) {
+  const HostSetup& h = s->host;
+  int rc = s->prec == CPTR_PRECISION_FP32 ? build_prec_amg(s, s->p32, st) : build_prec_amg(s, s->p64, st);
   if (rc) return rc;
   s->ncoarse = h.lev.back().A.n;
   if ((rc = upload(s, s->coarse_lu, h.coarse_lu.data(), (int64_t)h.coarse_lu.size(), st))) return rc;
@@ -898,6 +922,11 @@ int build_device(cptr_solver s, hipStream_t st) {
   HIP_TRY(s, hipEventCreateWithFlags(&s->ev_copy, hipEventDisableTiming));
   HIP_TRY(s, hipStreamSynchronize(st));
   return CPTR_OK;
+}
+
+int build_device(cptr_solver s, hipStream_t st) {
+  int rc = build_device_a(s, st);
+  return rc ? rc : build_device_b(s, st);
 }
 
 // ---------------------------------------------------------------- profiling
@@ -1638,7 +1667,7 @@ const char* cptr_last_error(cptr_solver s) { return s ? s->err.c_str() : g_setup
 namespace cptr {
 
 int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_idx, int32_t n_elliptic,
-               const cptr_setup_opts* opts, cptr_solver* out) {
+               const cptr_setup_opts* opts, cptr_solver* out, const hipStream_t* early_stream) {
   g_setup_error.clear();
   if (!out) return (cptr_status)fail(nullptr, CPTR_E_INVALID, "out is NULL");
   *out = nullptr;
@@ -1730,33 +1759,83 @@ int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_id
   prm.quasi_impes = o.restriction == CPTR_RESTRICT_QUASI_IMPES;
   unsigned hw = std::thread::hardware_concurrency();
   prm.threads = o.setup_threads > 0 ? o.setup_threads : (int)std::min<unsigned>(16, hw ? hw : 1);
+  s->ne = n_elliptic;
+  s->N = (int64_t)nb * 3;
+  s->ilu_mode = o.ilu_sweep;
+  s->threads = prm.threads;
+  s->device_ilu = dev_ilu;
+  s->prec = o.precond_precision;
+  s->nsweeps = o.num_sweeps;
+  s->max_restart = o.max_restart;
+  s->flex_space = o.flexible_space != 0;
+  // the device half's first part on a second thread, overlapping the AMG
+  // levels (it needs A, its diagonals and weights, which are final once the
+  // weights are formed, and the sweeps' dependency levels, computed there)
+  std::thread early;
+  int early_rc = CPTR_OK;
+  int early_dev = -1;
+  double early_s = 0.0;
+  bool early_ran = false;
+  if (early_stream && !o.host_only && hipGetDevice(&early_dev) == hipSuccess) {
+    const hipStream_t est = *early_stream;
+    cptr_solver hs = s.get();
+    prm.ilu_levels_elsewhere = true;
+    prm.after_weights = [&early, &early_rc, &early_s, &early_ran, early_dev, est, hs](HostSetup& h) {
+      early_ran = true;
+      for (int e = 0; e < 3; ++e) {
+        hs->eidx_h[e] = h.eidx[e];
+        hs->hidx_h[e] = h.hidx[e];
+      }
+      early = std::thread([&early_rc, &early_s, early_dev, est, hs, &h] {
+        const double t = now_s();
+        if (hipSetDevice(early_dev) != hipSuccess) {
+          early_rc = hip_fail(hs, hipGetLastError(), "hipSetDevice for the device half");
+          return;
+        }
+        try {
+          ilu_dependency_levels(h);
+          early_rc = build_device_a(hs, est);
+        } catch (const std::bad_alloc&) {
+          early_rc = fail(hs, CPTR_E_NOMEM, "host allocation failed while packing device layouts");
+        }
+        early_s = now_s() - t;
+      });
+    };
+  } else {
+    (void)hipGetLastError();
+  }
+  bool no_mem = false;
   try {
     rc = build_host_setup(nb, prp, pci, pv, elliptic_idx, n_elliptic, prm, s->host, err);
   } catch (const std::bad_alloc&) {
-    return (cptr_status)fail(nullptr, CPTR_E_NOMEM, "host allocation failed during setup");
+    no_mem = true;
   }
-  if (rc) return (cptr_status)fail(nullptr, rc, err);
+  if (early.joinable()) early.join();
+  if (no_mem || rc || early_rc) {
+    const std::string msg = no_mem ? "host allocation failed during setup" : rc ? err : s->err;
+    const int code = no_mem ? CPTR_E_NOMEM : rc ? rc : early_rc;
+    // kernels of the first part may still run on its stream: its memory goes
+    // back only once they are done
+    if (early_ran) {
+      (void)hipStreamSynchronize(*early_stream);
+      release_device(s.get());
+    }
+    return (cptr_status)fail(nullptr, code, msg);
+  }
+  s->dev_a_done = early_ran;
+  s->device_build_s = early_s;
   if (A->on_device) {
     // the host copy of A's values dies with this call: the handle keeps it
     // until the device half has been built
     s->host.av_owned = std::move(v);
     s->host.av = s->host.av_owned.data();
   }
-  s->ne = n_elliptic;
   for (int e = 0; e < 3; ++e) {
     s->eidx_h[e] = s->host.eidx[e];
     s->hidx_h[e] = s->host.hidx[e];
   }
-  s->N = (int64_t)nb * 3;
-  s->ilu_mode = o.ilu_sweep;
-  s->threads = prm.threads;
-  s->device_ilu = dev_ilu;
   s->device_steps = sites;
   s->agg_levels_used = std::min<int32_t>(prm.agg_levels, (int32_t)s->host.lev.size() - 1);
-  s->prec = o.precond_precision;
-  s->nsweeps = o.num_sweeps;
-  s->max_restart = o.max_restart;
-  s->flex_space = o.flexible_space != 0;
   *out = s.release();
   return CPTR_OK;
 }
@@ -1789,7 +1868,7 @@ int setup_device(cptr_solver s, DevArena* arena, int restart, bool flexible, hip
   int rc;
   const double t_dev = now_s();
   try {
-    rc = build_device(s, st);
+    rc = s->dev_a_done ? build_device_b(s, st) : build_device(s, st);
     if (!rc) rc = alloc_solve_space(s, std::max(1, std::min(restart, kMaxRestart)), flexible);
   } catch (const std::bad_alloc&) {
     rc = fail(s, CPTR_E_NOMEM, "host allocation failed while packing device layouts");
@@ -1803,7 +1882,7 @@ int setup_device(cptr_solver s, DevArena* arena, int restart, bool flexible, hip
     return rc;
   }
   s->device = true;
-  s->device_build_s = now_s() - t_dev;
+  s->device_build_s += now_s() - t_dev;
   return CPTR_OK;
 }
 
@@ -1842,13 +1921,14 @@ cptr_status cptr_setup(const cptr_bsr* A, int32_t block_size, const int32_t* ell
   const double t0 = now_s();
   if (out) *out = nullptr;
   cptr_solver s = nullptr;
-  int rc = setup_host(A, block_size, elliptic_idx, n_elliptic, opts, &s);
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  int rc = setup_host(A, block_size, elliptic_idx, n_elliptic, opts, &s, &st);
   if (rc) return (cptr_status)rc;
   cptr_setup_opts o;
   cptr_setup_opts_default(&o);
   if (opts) o = *opts;
   if (!o.host_only) {
-    rc = setup_device(s, nullptr, o.max_restart, o.flexible_space != 0, static_cast<hipStream_t>(stream));
+    rc = setup_device(s, nullptr, o.max_restart, o.flexible_space != 0, st);
     if (rc) {
       g_setup_error = s->err;
       delete s;

@@ -1016,6 +1016,7 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
       return err = "singular hyperbolic diagonal block in row " + std::to_string(bad),
              CPTR_E_ZERO_PIVOT;
   }
+  if (prm.after_weights) prm.after_weights(h);
   // ---- system AMG on Ahat, unknowns interleaved per cell (Sec. 3.1, 3.2) ----
   // Level 0 is Ahat as a scalar matrix, formed here from the reduced elliptic
   // blocks Ahat_ij = A_ij[E,E] - W_i A_ij[H,E]: each product rounded before
@@ -1167,7 +1168,15 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
                CPTR_E_ZERO_PIVOT;
     }
   }
-  // ---- dependency levels of the two triangular sweeps ----
+  if (!prm.ilu_levels_elsewhere) ilu_dependency_levels(h);
+  mark(kStepIlu);
+  return CPTR_OK;
+}
+
+void ilu_dependency_levels(HostSetup& h) {
+  const int32_t nb = h.nb;
+  const int32_t* rp = h.rp.data();
+  const int32_t* ci = h.ci.data();
   h.fwd_level.assign(nb, 0);
   h.bwd_level.assign(nb, 0);
   int32_t nf = 0, nbk = 0;
@@ -1185,8 +1194,6 @@ int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const dou
   }
   h.n_fwd_levels = nf;
   h.n_bwd_levels = nbk;
-  mark(kStepIlu);
-  return CPTR_OK;
 }
 
 }  // namespace cptr

@@ -94,6 +94,8 @@ struct LevelSteps {
   }
 };
 
+struct HostSetup;
+
 struct SetupParams {
   double theta = 0.25;
   double max_row_sum = 0.9;
@@ -109,6 +111,12 @@ struct SetupParams {
   // the steps of the level with operator A done elsewhere (null: all here):
   // strength, extended+i or multipass interpolation and the Galerkin product
   std::function<std::unique_ptr<LevelSteps>(const Csr& A)> level_steps;
+  // called once the quasi-IMPES weights are formed, before the AMG levels:
+  // from then on A's arrays, diag and W do not change (null: nothing)
+  std::function<void(HostSetup& h)> after_weights;
+  // the sweeps' dependency levels (ilu_dependency_levels) are computed by
+  // whoever after_weights started, not at the end of the setup
+  bool ilu_levels_elsewhere = false;
 };
 
 struct HostSetup {
@@ -151,6 +159,9 @@ int validate_bsr(int32_t nb, int64_t nnzb, const int32_t* rp, const int32_t* ci,
 int build_host_setup(int32_t nb, const int32_t* rp, const int32_t* ci, const double* v,
                      const int32_t* elliptic, int ne, const SetupParams& prm, HostSetup& out,
                      std::string& err);
+// The dependency levels of the sweeps' rows (h.fwd_level, h.bwd_level and
+// their counts) from A's pattern and diagonals.
+void ilu_dependency_levels(HostSetup& h);
 
 // Building blocks, exported for the library's own host tests.
 Csr strength_graph(const Csr& A, const std::vector<int32_t>& func, double theta, double mrs,

@@ -17,9 +17,13 @@ namespace cptr {
 
 // Host half.  On success *out is a handle with no device state.  The handle
 // reads A's values in place until drop_input is called: the caller keeps them
-// alive until then (setup_device reads them).
+// alive until then (setup_device reads them).  With early_stream set (and a
+// device handle), the part of the device half that needs only A (its layout,
+// the weights, the ILU(0) factors and sweep orders) is built on that stream by
+// a second thread while this one builds the AMG hierarchy; the handle then has
+// that part when this returns, and setup_device adds the rest.
 int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_idx, int32_t n_elliptic,
-               const cptr_setup_opts* opts, cptr_solver* out);
+               const cptr_setup_opts* opts, cptr_solver* out, const hipStream_t* early_stream = nullptr);
 // Device bytes setup_device(s, arena, restart, flexible) allocates, counted in
 // DevArena pieces.
 int measure_device(cptr_solver s, int restart, bool flexible, int64_t* bytes);
