@@ -822,6 +822,12 @@ struct GridCell {
   double* z;
   bool has_e0;
   int ea, eb;
+  // backward: z goes out in pairs of cells (c, c + 1), c even, as three
+  // 16-byte stores (half the lanes storing per step, half the cache lines
+  // touched); the odd cell's values wait here for their partner.  Single
+  // cells at a pencil's ends, and every cell when z is not 16-byte aligned.
+  bool pairs;
+  double h0, h1, h2;
 
   __device__ __forceinline__ void init(int nx, int ny, int nz, int nJ, int t, int lane, T* faces,
                                        T* ytile, const T* e0t, int ea_, int eb_, double* z_) {
@@ -829,6 +835,8 @@ struct GridCell {
     const size_t trow = (size_t)t * g.nsteps;
     yo = FWD ? ytile + (trow + g.nsteps - 1) * 3 * 64 + lane : nullptr;
     z = z_;
+    pairs = ((uintptr_t)z_ & 15) == 0;
+    h0 = h1 = h2 = 0.0;
     has_e0 = e0t != nullptr;
     ea = ea_;
     eb = eb_;
@@ -859,9 +867,24 @@ struct GridCell {
       // z = P_E e0 + x2 in FP64
       const double ex = has_e0 ? (double)r[3] : 0.0;
       const double ey = (NE == 2 && has_e0) ? (double)r[3 + NE - 1] : 0.0;
-      z[3 * c] = (double)o0 + (ea == 0 ? ex : 0.0) + (NE == 2 && eb == 0 ? ey : 0.0);
-      z[3 * c + 1] = (double)o1 + (ea == 1 ? ex : 0.0) + (NE == 2 && eb == 1 ? ey : 0.0);
-      z[3 * c + 2] = (double)o2 + (ea == 2 ? ex : 0.0) + (NE == 2 && eb == 2 ? ey : 0.0);
+      const double z0 = (double)o0 + (ea == 0 ? ex : 0.0) + (NE == 2 && eb == 0 ? ey : 0.0);
+      const double z1 = (double)o1 + (ea == 1 ? ex : 0.0) + (NE == 2 && eb == 1 ? ey : 0.0);
+      const double z2 = (double)o2 + (ea == 2 ? ex : 0.0) + (NE == 2 && eb == 2 ? ey : 0.0);
+      const int i = g.cell_i(s);  // the sweep visits i = nx - 1 down to 0
+      if (pairs && (c & 1) == 0 && i + 1 < g.nx) {
+        double2* q = reinterpret_cast<double2*>(z + 3 * c);  // 48 c bytes: 16-byte aligned
+        q[0] = make_double2(z0, z1);
+        q[1] = make_double2(z2, h0);
+        q[2] = make_double2(h1, h2);
+      } else if (pairs && (c & 1) == 1 && i > 0) {
+        h0 = z0;
+        h1 = z1;
+        h2 = z2;
+      } else {
+        z[3 * c] = z0;
+        z[3 * c + 1] = z1;
+        z[3 * c + 2] = z2;
+      }
       prev = {o0, o1, o2};
     }
     last = prev;

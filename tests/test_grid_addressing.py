@@ -123,8 +123,27 @@ def test_sweep_addresses_in_bounds_and_consistent(shape, fwd):
         assert np.array_equal(brow[cell[act]], (t * ns + (ns - 1 - s))[act])
         yidx = ((t * ns + ns - 1) * 3 * 64 + lane - s * 3 * 64)[act]
         assert yidx.min() >= 0 and yidx.max() + 128 < rows * 3 * 64
-    else:  # z[3c .. 3c+2]
-        assert cell[act].max() * 3 + 2 < 3 * nc
+    else:
+        # z goes out in pairs of cells (c, c + 1) with c even, stored when
+        # the sweep (i = nx - 1 down to 0) reaches c; the odd cell c + 1 was
+        # the same lane's previous step, held until then.  Single cells at a
+        # pencil's ends.
+        i_of = cell % nx
+        even = act & (cell % 2 == 0)
+        pair = even & (i_of + 1 < nx)
+        held = act & (cell % 2 == 1) & (i_of > 0)
+        single = act & ~pair & ~held
+        # a pair's partner is the lane's previous step, a held cell
+        prev = np.full(cell.shape, -1)
+        prev[:, 1:, :] = cell[:, :-1, :]
+        assert np.array_equal(prev[pair], cell[pair] + 1)
+        prev_held = np.zeros(cell.shape, dtype=bool)
+        prev_held[:, 1:, :] = held[:, :-1, :]
+        assert prev_held[pair].all()
+        written = np.concatenate([cell[pair], cell[pair] + 1, cell[single]])
+        # every cell's z written exactly once, in bounds
+        assert np.array_equal(np.sort(written), np.arange(nc))
+        assert (cell[pair] + 1).max(initial=0) < nc
     # staging: the matrix, right-hand side and e0 rows of steps 0 .. nst + 1
     H, R = CONFIGS[fwd]
     nst = (ns + 1) & ~1
