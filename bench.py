@@ -227,8 +227,8 @@ def serve_stream(stream, cases, rate, slots, setup_workers, setup_threads, verbo
         "sustained": bool(sps >= 0.9 * rate and len(ok) == len(res)),
         "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
         "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
-        "median_ms": {k: med(k) * 1e3 for k in ("queue_s", "host_setup_s", "admit_wait_s",
-                                                  "device_setup_s", "solve_s")},
+        "median_ms": {k[:-2]: med(k) * 1e3 for k in ("queue_s", "host_setup_s", "admit_wait_s",
+                                                       "device_setup_s", "solve_s")},
         "peak_inflight": st["peak_inflight"], "peak_reserved_gib": st["peak_reserved_bytes"] / 2**30,
         "hbm_budget_gib": st["hbm_budget_bytes"] / 2**30,
         "dtype": "f32 preconditioner, f64 Krylov",
