@@ -31,10 +31,12 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def phase_bytes(c, rows, nnz, ne, grid):
+def phase_bytes(c, rows, nnz, ne, grid, tail=0):
     """Algorithmic bytes per launch of each timed phase: the values a phase must
     read and write once (FP64 values, int32 indices where an index array is
-    part of the format).  On a detected grid the ILU sweeps carry no indices."""
+    part of the format).  On a detected grid the ILU sweeps carry no indices.
+    With a dense bottom of the V-cycle at level `tail`, the levels from there
+    down are one read of its n x n operator (and its vectors)."""
     nc, nnzb, N = c.n_cells, c.nnzb, c.n_dof
     n0 = ne * nc
     out = {}
@@ -56,8 +58,10 @@ def phase_bytes(c, rows, nnz, ne, grid):
         out["ilu_fwd"] = 76 * nl + 4 * nc + 16 * N
         out["ilu_bwd"] = 76 * nl + 72 * nc + 4 * nc + 24 * N + 8 * n0
     coarse = 0
-    for l in range(1, len(rows)):
+    for l in range(1, tail if tail > 0 else len(rows)):
         coarse += 2 * 12 * nnz[l] + 8 * 6 * rows[l]
+    if tail > 0:
+        coarse += 8 * rows[tail] * rows[tail] + 16 * rows[tail]
     out["vcycle_coarse"] = coarse
     return out
 
@@ -438,7 +442,8 @@ def main():
         info = s.gmres_solve(b, x, **kw)
         setup_s = info["setup_s"]
         log(f"warmup {w}: {info['iterations']} it, {info['solve_s']:.3f} s, rel res {info['rel_res_true']:.2e}")
-    pbytes = phase_bytes(c, list(rows), list(nnz), 2, grid_sweeps)
+    tail = int(s.export("DENSE_TAIL", 0, 2, np.int32)[0])
+    pbytes = phase_bytes(c, list(rows), list(nnz), 2, grid_sweeps, tail)
 
     def phase_table():
         table = {}
@@ -502,6 +507,7 @@ def main():
                                f"FGMRES({args.restart}) + CPTR, rtol {c.tol:g}",
                    "cells": c.n_cells, "dof": c.n_dof, "nnz_blocks": c.nnzb,
                    "amg_levels": len(rows), "amg_rows": [int(r) for r in rows],
+                   "amg_dense_tail_level": tail,
                    "ilu_sweep": ["auto", "levels", "one_launch", "grid"][int(sweep_mode[0])]},
         "iterations": its,
         "time_to_tol_s": dt / args.steps,

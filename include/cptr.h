@@ -113,6 +113,14 @@ typedef struct {
                                 stopped early: a split with no C point, or max_levels) gets
                                 num_sweeps l1-Jacobi sweeps before and after a zero coarse
                                 correction instead; default 4096, 0..4096 */
+  int32_t dense_tail;        /* the V-cycle below the largest AMG level l >= 1 of at most this
+                                many rows (with a smoothed level and the dense coarsest solve
+                                under it) is applied as one dense n_l x n_l operator, formed at
+                                setup by running that part of the cycle on the n_l unit vectors:
+                                the same linear map (the cycle starts from zero iterates, Sec.
+                                3.1), evaluated in one matrix-vector product instead of about
+                                four launches per level; n_l^2 values of device memory in the
+                                preconditioner's type; default 2048, 0 = off, at most 4096 */
 } cptr_setup_opts;
 
 enum {
@@ -292,7 +300,10 @@ enum {
                                   only when a row's interpolatory set has more than 64 points, a
                                   multipass interpolation only when a row has more than 64
                                   interpolating points or 2048 products, a distance-two graph
-                                  only when a row has more than 2048 candidates */
+                                  only when a row has more than 2048 candidates */,
+  CPTR_EXPORT_DENSE_TAIL = 15  /* int32[2]: the AMG level whose V-cycle below runs as one dense
+                                  operator (dense_tail; 0 = none) and its rows; CPTR_E_STATE for
+                                  a host-only handle */
 };
 /* Copy one piece of the setup into host_buf (bytes = its capacity). */
 cptr_status cptr_export(cptr_solver s, int32_t what, int32_t level, void *host_buf, int64_t bytes);

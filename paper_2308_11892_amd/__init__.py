@@ -25,7 +25,7 @@ ILU_SWEEP_AUTO, ILU_SWEEP_LEVELS, ILU_SWEEP_ONE_LAUNCH, ILU_SWEEP_GRID = 0, 1, 2
 PRECISION_FP64, PRECISION_FP32 = 0, 1
 EXPORT = dict(CF=0, A_ROWPTR=1, A_COLS=2, A_VALS=3, P_ROWPTR=4, P_COLS=5, P_VALS=6, W=7,
               DINV=8, ILU_VALS=9, ILU_NLEVELS=10, SWEEP=11, SETUP_SITES=12,
-              DEVICE_PLAN=13, SETUP_TIMES=14)
+              DEVICE_PLAN=13, SETUP_TIMES=14, DENSE_TAIL=15)
 SETUP_STEPS = ["validate", "reduce", "strength", "split", "interp", "galerkin", "smoother", "ilu_levels",
                "device", "total"]
 PHASES = ["spmv", "restrict", "vcycle_l0", "vcycle_coarse", "stage2_resid", "ilu_fwd",
@@ -52,7 +52,8 @@ class cptr_setup_opts(C.Structure):
                 ("ilu_sweep", C.c_int32), ("agg_levels", C.c_int32),
                 ("precond_precision", C.c_int32), ("num_sweeps", C.c_int32),
                 ("max_restart", C.c_int32), ("flexible_space", C.c_int32),
-                ("hmis_block", C.c_int32), ("max_dense_coarse", C.c_int32)]
+                ("hmis_block", C.c_int32), ("max_dense_coarse", C.c_int32),
+                ("dense_tail", C.c_int32)]
 
 
 class cptr_solve_opts(C.Structure):

@@ -264,6 +264,10 @@ struct PrecDev {
   };
   std::vector<Lev> lev;
   T *r2 = nullptr, *y = nullptr, *x2 = nullptr;  // apply workspace
+  // the V-cycle below level `tail` (0: none) as one dense operator, row-major
+  // n_tail x n_tail (kernels.hip, "the bottom of the V-cycle")
+  int tail = 0;
+  T* tailB = nullptr;
 };
 
 }  // namespace
@@ -287,6 +291,7 @@ struct cptr_solver_s {
   bool dev_a_done = false;      // the device half's first part was built during setup_host
   int ne = 2;
   int nsweeps = 1;           // l1-Jacobi sweeps before and after the coarse correction
+  int dense_tail = 0;        // largest level whose cycle below runs as one dense operator
   int max_restart = 0;       // Krylov space of cptr_setup (cptr_setup_opts.max_restart)
   bool flex_space = false;   // ... with the FGMRES vectors Z
   int32_t eidx_h[3] = {0, 1, 2}, hidx_h[3] = {2, 0, 0};
@@ -738,6 +743,80 @@ int build_prec_amg(cptr_solver s, PrecDev<T>& d, hipStream_t st) {
   const int64_t N = (int64_t)nb * 3;
   if (!s->use_grid && ((rc = dalloc(s, d.r2, N)) || (rc = dalloc(s, d.y, N)) || (rc = dalloc(s, d.x2, N))))
     return rc;
+  // the dense bottom: the largest level l >= 1 of at most dense_tail rows
+  // with a smoothed level and the coarsest LU below it (level 0 keeps its
+  // block operator, a smoothed coarsest level its sweeps)
+  d.tail = 0;
+  if (!h.coarse_relax)
+    for (int l = 1; l + 2 <= L; ++l)
+      if (h.lev[l].A.n <= s->dense_tail) {
+        d.tail = l;
+        break;
+      }
+  return CPTR_OK;
+}
+
+// B = the V-cycle from level d.tail down as a dense operator: the cycle's
+// passes over that level and the coarser ones (the same sweeps, residuals,
+// restrictions, coarsest LU solve and prolongations as an apply, over the
+// level operators of type T, in FP64) run once on the n_t unit vectors at
+// once; B is then rounded to T.
+template <class T>
+int build_tail(cptr_solver s, PrecDev<T>& d, hipStream_t st) {
+  const int t = d.tail;
+  if (t <= 0) return CPTR_OK;
+  const int L = (int)d.lev.size();
+  const int w = d.lev[t].n;
+  const int ns = s->nsweeps;
+  int rc;
+  if ((rc = dalloc(s, d.tailB, (int64_t)w * w))) return rc;
+  // per level: right-hand sides b, iterate x, and y (a residual, or the next
+  // sweep's iterate); the coarsest solves in place in b
+  std::vector<double*> b((size_t)L, nullptr), x((size_t)L, nullptr), y((size_t)L, nullptr);
+  for (int l = t; l < L; ++l) {
+    const int64_t m = (int64_t)d.lev[l].n * w;
+    if ((rc = dalloc(s, b[l], m))) return rc;
+    if (l + 1 < L && ((rc = dalloc(s, x[l], m)) || (rc = dalloc(s, y[l], m)))) return rc;
+  }
+  auto release = [&] {
+    for (int l = t; l < L; ++l) {
+      dfree(s, b[l]);
+      if (l + 1 < L) {
+        dfree(s, x[l]);
+        dfree(s, y[l]);
+      }
+    }
+  };
+  if (s->measure) {
+    release();
+    return CPTR_OK;
+  }
+  launch_blk_identity(w, b[t], st);
+  for (int l = t; l + 1 < L; ++l) {
+    auto& dl = d.lev[l];
+    launch_blk_csr<T>(kBlkScale, dl.n, w, nullptr, dl.dinv, nullptr, b[l], x[l], st);
+    for (int k = 1; k < ns; ++k) {
+      launch_blk_csr<T>(kBlkJacobi, dl.n, w, &dl.A, dl.dinv, x[l], b[l], y[l], st);
+      std::swap(x[l], y[l]);
+    }
+    launch_blk_csr<T>(kBlkResid, dl.n, w, &dl.A, nullptr, x[l], b[l], y[l], st);
+    launch_blk_csr<T>(kBlkProduct, d.lev[l + 1].n, w, &dl.R, nullptr, y[l], nullptr, b[l + 1], st);
+  }
+  launch_blk_lu(s->ncoarse, w, s->coarse_lu, s->coarse_piv, b[L - 1], st);
+  x[L - 1] = b[L - 1];
+  for (int l = L - 2; l >= t; --l) {
+    auto& dl = d.lev[l];
+    launch_blk_csr<T>(kBlkAdd, dl.n, w, &dl.P, nullptr, x[l + 1], nullptr, x[l], st);
+    for (int k = 0; k < ns; ++k) {
+      launch_blk_csr<T>(kBlkJacobi, dl.n, w, &dl.A, dl.dinv, x[l], b[l], y[l], st);
+      std::swap(x[l], y[l]);
+    }
+  }
+  launch_blk_to<T>((int64_t)w * w, x[t], d.tailB, st);
+  HIP_TRY(s, hipGetLastError());
+  // the temporaries go back once the kernels reading them are done
+  HIP_TRY(s, hipStreamSynchronize(st));
+  release();
   return CPTR_OK;
 }
 
@@ -908,6 +987,8 @@ int build_device_b(cptr_solver s, hipStream_t st) {
   s->ncoarse = h.lev.back().A.n;
   if ((rc = upload(s, s->coarse_lu, h.coarse_lu.data(), (int64_t)h.coarse_lu.size(), st))) return rc;
   if ((rc = upload(s, s->coarse_piv, h.coarse_piv.data(), (int64_t)h.coarse_piv.size(), st))) return rc;
+  rc = s->prec == CPTR_PRECISION_FP32 ? build_tail(s, s->p32, st) : build_tail(s, s->p64, st);
+  if (rc) return rc;
   if ((rc = dalloc(s, s->part, (int64_t)kRedBlocks * (kMaxRestart + 2)))) return rc;
   if ((rc = dalloc(s, s->hdev, 256))) return rc;
   s->sweep_flag = s->hdev + 140;
@@ -1074,7 +1155,10 @@ void enqueue_stage1(cptr_solver s, PrecDev<T>& d, const double* r, hipStream_t s
     restrict_to(0, l0.r);
     ph_end(s, st, PH_VC0, ev);
     ph_begin(s, st, PH_VCC, ev);
-    for (int l = 1; l + 1 < L; ++l) {
+    // levels 1 .. top - 1 run pass by pass; below them one operator: the
+    // dense bottom B (e_top = B b_top), or the coarsest solve or sweeps
+    const int top = d.tail > 0 ? d.tail : L - 1;
+    for (int l = 1; l < top; ++l) {
       auto& dl = d.lev[l];
       presmooth(l);
       if (dl.sell)
@@ -1083,11 +1167,13 @@ void enqueue_stage1(cptr_solver s, PrecDev<T>& d, const double* r, hipStream_t s
         launch_csr_resid(dl.A, cur[(size_t)l], dl.b, dl.r, st);
       restrict_to(l, dl.r);
     }
-    if (relax)
+    if (d.tail > 0)
+      launch_dense_gemv(d.lev[top].n, d.tailB, d.lev[top].b, d.lev[top].e, st);
+    else if (relax)
       relax_coarsest(L - 1);
     else
       launch_coarse_solve(s->ncoarse, s->coarse_lu, s->coarse_piv, d.lev[L - 1].b, d.lev[L - 1].e, st);
-    for (int l = L - 2; l >= 1; --l) correct(l);
+    for (int l = top - 1; l >= 1; --l) correct(l);
     ph_end(s, st, PH_VCC, ev);
     ph_begin(s, st, PH_VC0, ev);
     correct(0);
@@ -1648,6 +1734,7 @@ void cptr_setup_opts_default(cptr_setup_opts* o) {
   o->flexible_space = 1;
   o->hmis_block = 0;
   o->max_dense_coarse = 4096;
+  o->dense_tail = 2048;
 }
 
 void cptr_solve_opts_default(cptr_solve_opts* o) {
@@ -1698,6 +1785,7 @@ int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_id
     return (cptr_status)fail(nullptr, CPTR_E_INVALID, "flexible_space must be 0 or 1");
   if (o.max_levels < 1 || o.max_levels > 64 || o.max_coarse < 1 || o.p_max_elmts < 0 ||
       o.agg_levels < 0 || o.hmis_block < 0 || o.max_dense_coarse < 0 || o.max_dense_coarse > 4096 ||
+      o.dense_tail < 0 || o.dense_tail > 4096 ||
       !(o.strong_threshold >= 0.0) || !(o.max_row_sum > 0.0))
     return (cptr_status)fail(nullptr, CPTR_E_INVALID, "setup options out of range");
   if (A->n_block_rows <= 0 || A->nnz_blocks <= 0 || A->nnz_blocks >= INT32_MAX)
@@ -1766,6 +1854,7 @@ int setup_host(const cptr_bsr* A, int32_t block_size, const int32_t* elliptic_id
   s->device_ilu = dev_ilu;
   s->prec = o.precond_precision;
   s->nsweeps = o.num_sweeps;
+  s->dense_tail = o.dense_tail;
   s->max_restart = o.max_restart;
   s->flex_space = o.flexible_space != 0;
   // the device half's first part on a second thread, overlapping the AMG
@@ -2330,6 +2419,12 @@ cptr_status cptr_export(cptr_solver s, int32_t what, int32_t level, void* buf, i
       int32_t v[4] = {mode, s->use_grid ? s->grid[0] : 0, s->use_grid ? s->grid[1] : 0,
                       s->use_grid ? s->grid[2] : 0};
       return put(v, 16);
+    }
+    case CPTR_EXPORT_DENSE_TAIL: {
+      if (!s->device) return (cptr_status)fail(s, CPTR_E_STATE, "a host-only handle has no device V-cycle");
+      const int t = s->prec == CPTR_PRECISION_FP32 ? s->p32.tail : s->p64.tail;
+      int32_t v[2] = {t, t > 0 ? (int32_t)h.lev[t].A.n : 0};
+      return put(v, 8);
     }
     case CPTR_EXPORT_ILU_NLEVELS: {
       int32_t nl[2] = {h.n_fwd_levels, h.n_bwd_levels};

@@ -300,6 +300,112 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(int n, const double* __
 }
 
 // --------------------------------------------------------------------------
+// The bottom of the V-cycle as one dense operator.  The cycle of Sec. 3.1
+// starts every level's iterate from zero, so the part below a small level t
+// (its smoothing, the coarser levels and the coarsest solve) is a fixed linear
+// map e_t = B_t b_t.  Setup forms B_t by running exactly that part of the
+// cycle on the n_t unit vectors at once: every level's vectors become
+// row-major blocks of n_l x w FP64 values (w = n_t columns), every operator
+// pass a pass over all columns.  Each apply then replaces the ~4 launches per
+// level below t by one dense matrix-vector product.
+
+// one sparse row (blockIdx.y) times the block z, the threads over columns:
+//   scale:   y = dinv x                   (the first sweep from zero)
+//   resid:   y = x - A z                  (x: right-hand sides)
+//   jacobi:  y = z + dinv (x - A z)       (one l1-Jacobi sweep from iterate z)
+//   product: y = S z                      (restriction)
+//   add:     y += S z                     (prolongation into the iterate)
+template <int OP, class T>
+__global__ __launch_bounds__(kBlock) void k_blk_csr(int w, const int32_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ ci, const T* __restrict__ v,
+                                                    const T* __restrict__ dinv, const double* __restrict__ z,
+                                                    const double* __restrict__ x, double* __restrict__ y) {
+  const int row = blockIdx.y;
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= w) return;
+  const size_t o = (size_t)row * w + c;
+  if (OP == kBlkScale) {
+    y[o] = (double)dinv[row] * x[o];
+    return;
+  }
+  double acc = 0.0;
+  for (int k = rp[row]; k < rp[row + 1]; ++k) acc += (double)v[k] * z[(size_t)ci[k] * w + c];
+  switch (OP) {
+    case kBlkResid: y[o] = x[o] - acc; break;
+    case kBlkJacobi: y[o] = z[o] + (double)dinv[row] * (x[o] - acc); break;
+    case kBlkProduct: y[o] = acc; break;
+    case kBlkAdd: y[o] += acc; break;
+  }
+}
+
+// the coarsest dense LU solve (the same steps as k_coarse_solve) on every
+// column of the n x w block x, one thread per column
+__global__ __launch_bounds__(kBlock) void k_blk_lu(int n, int w, const double* __restrict__ lu,
+                                                   const int32_t* __restrict__ piv, double* __restrict__ x) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= w) return;
+  double* xc = x + c;
+  for (int k = 0; k < n; ++k) {
+    const int p = piv[k];
+    if (p != k) {
+      const double t = xc[(size_t)k * w];
+      xc[(size_t)k * w] = xc[(size_t)p * w];
+      xc[(size_t)p * w] = t;
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    const double xi = xc[(size_t)i * w];
+    for (int j = i + 1; j < n; ++j) xc[(size_t)j * w] -= lu[(size_t)j * n + i] * xi;
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    xc[(size_t)i * w] /= lu[(size_t)i * n + i];
+    const double xi = xc[(size_t)i * w];
+    for (int j = 0; j < i; ++j) xc[(size_t)j * w] -= lu[(size_t)j * n + i] * xi;
+  }
+}
+
+// the n x n identity block; the finished B in the preconditioner's type
+__global__ __launch_bounds__(kBlock) void k_blk_identity(int n, double* __restrict__ x) {
+  const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (q < (int64_t)n * n) x[q] = q / n == q % n ? 1.0 : 0.0;
+}
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_blk_to(int64_t m, const double* __restrict__ x, T* __restrict__ y) {
+  const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (q < m) y[q] = (T)x[q];
+}
+
+// e = B b, B row-major n x n: one workgroup per row, each thread PER columns
+// (n <= PER * kBlock) whose loads all go out before the first product; the
+// index is clamped and the surplus products dropped, so no load waits on a
+// branch.  Accumulates in T like the other operators of the preconditioner.
+template <int PER, class T>
+__global__ __launch_bounds__(kBlock) void k_dense_gemv(int n, const T* __restrict__ B, const T* __restrict__ b,
+                                                       T* __restrict__ e) {
+  const T* r = B + (size_t)blockIdx.x * n;
+  T bv[PER], rv[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int c = min((int)threadIdx.x + q * kBlock, n - 1);
+    rv[q] = r[c];
+    bv[q] = b[c];
+  }
+  T acc = 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q)
+    if ((int)threadIdx.x + q * kBlock < n) acc += rv[q] * bv[q];
+  acc = group_sum<64, T>(acc);
+  __shared__ T part[kBlock / 64];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T sum = 0;
+    for (int w = 0; w < kBlock / 64; ++w) sum += part[w];
+    e[blockIdx.x] = sum;
+  }
+}
+
+// --------------------------------------------------------------------------
 // stage-two residual r2 = r - A x1 with x1[E] = e0, x1[H] = 0: only the
 // elliptic columns of each block are read
 // (A and the arithmetic in FP64, e0 and r2 in the preconditioner's type T;
@@ -1487,6 +1593,42 @@ template <class T>
 void launch_coarse_solve(int n, const double* lu, const int32_t* piv, const T* b, T* x,
                          hipStream_t st) {
   k_coarse_solve<T><<<1, kBlock, sizeof(double) * (size_t)n, st>>>(n, lu, piv, b, x);
+}
+
+template <class T>
+void launch_blk_csr(int op, int nrows, int w, const DCsrT<T>* S, const T* dinv, const double* z,
+                    const double* x, double* y, hipStream_t st) {
+  if (nrows <= 0 || w <= 0) return;
+  const dim3 g(nblocks(w, kBlock), nrows);
+  const int32_t* rp = S ? S->rp : nullptr;
+  const int32_t* ci = S ? S->ci : nullptr;
+  const T* v = S ? S->v : nullptr;
+  switch (op) {
+    case kBlkScale: k_blk_csr<kBlkScale, T><<<g, kBlock, 0, st>>>(w, rp, ci, v, dinv, z, x, y); break;
+    case kBlkResid: k_blk_csr<kBlkResid, T><<<g, kBlock, 0, st>>>(w, rp, ci, v, dinv, z, x, y); break;
+    case kBlkJacobi: k_blk_csr<kBlkJacobi, T><<<g, kBlock, 0, st>>>(w, rp, ci, v, dinv, z, x, y); break;
+    case kBlkProduct: k_blk_csr<kBlkProduct, T><<<g, kBlock, 0, st>>>(w, rp, ci, v, dinv, z, x, y); break;
+    case kBlkAdd: k_blk_csr<kBlkAdd, T><<<g, kBlock, 0, st>>>(w, rp, ci, v, dinv, z, x, y); break;
+  }
+}
+void launch_blk_lu(int n, int w, const double* lu, const int32_t* piv, double* x, hipStream_t st) {
+  if (n > 0 && w > 0) k_blk_lu<<<nblocks(w, kBlock), kBlock, 0, st>>>(n, w, lu, piv, x);
+}
+void launch_blk_identity(int n, double* x, hipStream_t st) {
+  if (n > 0) k_blk_identity<<<nblocks((int64_t)n * n, kBlock), kBlock, 0, st>>>(n, x);
+}
+template <class T>
+void launch_blk_to(int64_t m, const double* x, T* y, hipStream_t st) {
+  if (m > 0) k_blk_to<T><<<nblocks(m, kBlock), kBlock, 0, st>>>(m, x, y);
+}
+template <class T>
+void launch_dense_gemv(int n, const T* B, const T* b, T* e, hipStream_t st) {
+  if (n <= 0) return;
+  if (n <= kBlock) k_dense_gemv<1, T><<<n, kBlock, 0, st>>>(n, B, b, e);
+  else if (n <= 2 * kBlock) k_dense_gemv<2, T><<<n, kBlock, 0, st>>>(n, B, b, e);
+  else if (n <= 4 * kBlock) k_dense_gemv<4, T><<<n, kBlock, 0, st>>>(n, B, b, e);
+  else if (n <= 8 * kBlock) k_dense_gemv<8, T><<<n, kBlock, 0, st>>>(n, B, b, e);
+  else k_dense_gemv<16, T><<<n, kBlock, 0, st>>>(n, B, b, e);  // n <= 4096 (dense_tail)
 }
 
 template <class T>
@@ -3523,6 +3665,10 @@ void launch_update_host_coef(int64_t n, int nv, const double* V, int64_t ldv, co
   template void launch_sell_resid<T>(const SellT<T>&, const T*, const T*, T*, hipStream_t);          \
   template void launch_sell_post<T>(const SellT<T>&, const T*, const T*, const T*, T*, hipStream_t); \
   template void launch_coarse_solve<T>(int, const double*, const int32_t*, const T*, T*, hipStream_t); \
+  template void launch_blk_csr<T>(int, int, int, const DCsrT<T>*, const T*, const double*,            \
+                                  const double*, double*, hipStream_t);                              \
+  template void launch_blk_to<T>(int64_t, const double*, T*, hipStream_t);                           \
+  template void launch_dense_gemv<T>(int, const T*, const T*, T*, hipStream_t);                      \
   template void launch_stage2_resid<T>(const Sell&, int, const int32_t*, const T*, const double*, T*, \
                                        hipStream_t);                                                 \
   template void launch_ilu_fwd_level<T>(const SellT<T>&, const int32_t*, int32_t, int32_t, const T*, \

@@ -88,6 +88,24 @@ void launch_sell_post(const SellT<T>& A, const T* x, const T* b, const T* dinv, 
 template <class T>
 void launch_coarse_solve(int n, const double* lu, const int32_t* piv, const T* b, T* x,
                          hipStream_t st);
+// The V-cycle below a small level as one dense operator B (kernels.hip): the
+// setup passes over row-major n_l x w FP64 blocks, the operators (S: A_l, R_l
+// or P_l; null for kBlkScale) in the preconditioner's type T:
+//   kBlkScale   y = dinv x             kBlkResid  y = x - S z
+//   kBlkJacobi  y = z + dinv (x - S z) kBlkProduct y = S z      kBlkAdd y += S z
+enum BlkOp { kBlkScale = 0, kBlkResid = 1, kBlkJacobi = 2, kBlkProduct = 3, kBlkAdd = 4 };
+template <class T>
+void launch_blk_csr(int op, int nrows, int w, const DCsrT<T>* S, const T* dinv, const double* z,
+                    const double* x, double* y, hipStream_t st);
+// the coarsest LU solve on every column of the n x w block x; the n x n identity
+void launch_blk_lu(int n, int w, const double* lu, const int32_t* piv, double* x, hipStream_t st);
+void launch_blk_identity(int n, double* x, hipStream_t st);
+// y = x rounded to T (m values)
+template <class T>
+void launch_blk_to(int64_t m, const double* x, T* y, hipStream_t st);
+// e = B b with B row-major n x n in T
+template <class T>
+void launch_dense_gemv(int n, const T* B, const T* b, T* e, hipStream_t st);
 template <class T>
 void launch_stage2_resid(const Sell& A, int ne, const int32_t* eidx, const T* e0, const double* r,
                          T* r2, hipStream_t st);

@@ -40,6 +40,9 @@ def test_defaults_follow_the_paper():
     # one HMIS block per level: the first pass over the whole level; coarsest
     # levels up to 4096 rows solved exactly
     assert o.hmis_block == 0 and o.max_dense_coarse == 4096
+    # the V-cycle below the largest level of at most 2048 rows runs as one
+    # dense operator
+    assert o.dense_tail == 2048
 
 
 @pytest.mark.parametrize("case,agg", [("grid20x20x5", 1), ("grid6x5x4", 1), ("grid12x1x1", 1),
@@ -148,7 +151,8 @@ def test_invalid_arguments():
     for kw, word in [(dict(num_sweeps=0), "num_sweeps"), (dict(num_sweeps=9), "num_sweeps"),
                      (dict(max_restart=0), "max_restart"), (dict(max_restart=65), "max_restart"),
                      (dict(flexible_space=2), "flexible_space"), (dict(hmis_block=-1), "range"),
-                     (dict(max_dense_coarse=-1), "range"), (dict(max_dense_coarse=4097), "range")]:
+                     (dict(max_dense_coarse=-1), "range"), (dict(max_dense_coarse=4097), "range"),
+                     (dict(dense_tail=-1), "range"), (dict(dense_tail=4097), "range")]:
         msg = _expect(L.CPTR_E_INVALID, lambda: L.Solver(c.row_ptr, c.col_idx, c.values, host_only=1, **kw))
         assert word in msg, msg
 
