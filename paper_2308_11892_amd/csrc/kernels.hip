@@ -193,6 +193,8 @@ __global__ __launch_bounds__(kBlock) void k_l0_post(int nc, int nblk, const int3
 // iterate, when it took more than one sweep)
 enum CsrOp { kSpmv = 0, kResid = 1, kProlong = 2, kPost = 3, kRestrict = 4, kProlongAdd = 5 };
 
+// entries per lane and chunk of the scalar CSR kernels
+constexpr int kCsrE = 4;
 template <int G, int OP, class T>
 __global__ __launch_bounds__(kBlock) void k_csr(int n, const int32_t* __restrict__ rp,
                                                 const int32_t* __restrict__ ci,
@@ -205,12 +207,24 @@ __global__ __launch_bounds__(kBlock) void k_csr(int n, const int32_t* __restrict
   const int row = (int)(t / G), sub = (int)(t % G);
   const bool live = row < n;
   T acc = 0;
-  if (live) {
-#pragma unroll 4
-    for (int k = rp[row] + sub; k < rp[row + 1]; k += G) {
-      const int c = ci[k];
-      acc += v[k] * x[c];
+  // the row in chunks of kCsrE entries per lane whose loads all go out
+  // before the chunk's first product (indices clamped to the row's last
+  // entry, surplus products dropped); the sum runs in entry order
+  const int k1 = live ? rp[row + 1] : 0;
+  for (int kb = (live ? rp[row] : 0) + sub; kb < k1; kb += kCsrE * G) {
+    int cc[kCsrE];
+    T vv[kCsrE], xx[kCsrE];
+#pragma unroll
+    for (int q = 0; q < kCsrE; ++q) {
+      const int k = min(kb + q * G, k1 - 1);
+      cc[q] = ci[k];
+      vv[q] = v[k];
     }
+#pragma unroll
+    for (int q = 0; q < kCsrE; ++q) xx[q] = x[cc[q]];
+#pragma unroll
+    for (int q = 0; q < kCsrE; ++q)
+      if (kb + q * G < k1) acc += vv[q] * xx[q];
   }
   acc = group_sum<G, T>(acc);
   if (!live || sub != 0) return;
@@ -239,7 +253,25 @@ __global__ __launch_bounds__(kBlock) void k_sell_scalar(int n, int nblk, const i
   if (row >= n) return;
   const int s = row >> 6, lane = row & 63;
   T acc = 0;
-  for (int k = sptr[s]; k < sptr[s + 1]; ++k) acc += val[(size_t)k * 64 + lane] * x[col[(size_t)k * 64 + lane]];
+  // slots in chunks whose loads all go out before the first product (slot
+  // clamped to the slice's last, surplus products dropped); entry order kept
+  constexpr int CH = 8;
+  const int k1 = sptr[s + 1];
+  for (int kb = sptr[s]; kb < k1; kb += CH) {
+    int cc[CH];
+    T vv[CH], xx[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const size_t k = (size_t)min(kb + q, k1 - 1);
+      cc[q] = col[k * 64 + lane];
+      vv[q] = val[k * 64 + lane];
+    }
+#pragma unroll
+    for (int q = 0; q < CH; ++q) xx[q] = x[cc[q]];
+#pragma unroll
+    for (int q = 0; q < CH; ++q)
+      if (kb + q < k1) acc += vv[q] * xx[q];
+  }
   if (OP == kResid)
     y[row] = b[row] - acc;
   else
