@@ -367,6 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_blk_csr(int w, const int32_t* __rest
     case kBlkJacobi: y[o] = z[o] + (double)dinv[row] * (x[o] - acc); break;
     case kBlkProduct: y[o] = acc; break;
     case kBlkAdd: y[o] += acc; break;
+    default: break;
   }
 }
 
@@ -1241,6 +1242,56 @@ __global__ __launch_bounds__(64 * (H + 1)) void k_ilu_grid(int nx, int ny, int n
   }
 }
 
+// A P_E e0 on one SELL-64 row: only the elliptic columns ea (and eb) of each
+// block are read, slots in chunks of CH whose loads all go out before the
+// chunk's first product (slot clamped to the slice's last, surplus products
+// dropped; entry order kept).  A is read once per product: non-temporal loads.
+// HOLD keeps all of a chunk's loads in flight at the cost of occupancy (the
+// compiler otherwise trades them for more waves); which is faster was
+// measured per kernel and type.
+template <int NE, int CH, bool HOLD, class T>
+__device__ __forceinline__ void stage2_row_sum(int k0, int k1, int lane, const int32_t* __restrict__ col,
+                                               const double* __restrict__ val, int ea, int eb,
+                                               const T* __restrict__ e0, double& a0, double& a1,
+                                               double& a2) {
+  for (int kb = k0; kb < k1; kb += CH) {
+    int cc[CH];
+    double m[CH][6];
+    T uu[CH][2];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const size_t kq = (size_t)min(kb + q, k1 - 1);
+      cc[q] = __builtin_nontemporal_load(col + kq * 64 + lane);
+      const double* v = val + kq * 9 * 64 + lane;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        m[q][a] = __builtin_nontemporal_load(v + (a * 3 + ea) * 64);
+        if (NE == 2) m[q][3 + a] = __builtin_nontemporal_load(v + (a * 3 + eb) * 64);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      uu[q][0] = e0[(size_t)cc[q] * NE];
+      if (NE == 2) uu[q][1] = e0[(size_t)cc[q] * NE + 1];
+    }
+    if (HOLD) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < CH; ++q)
+      if (kb + q < k1) {
+        const double u = uu[q][0];
+        a0 += m[q][0] * u;
+        a1 += m[q][1] * u;
+        a2 += m[q][2] * u;
+        if (NE == 2) {
+          const double w = uu[q][1];
+          a0 += m[q][3] * w;
+          a1 += m[q][4] * w;
+          a2 += m[q][5] * w;
+        }
+      }
+  }
+}
+
 // stage-two residual for the grid sweeps: r2 and e0 are also written in the
 // tile layouts (r2 forward, e0 backward), the face buffers of both sweeps
 // (nfaces values) get the sentinel, and both ticket counters := 0
@@ -1269,21 +1320,7 @@ __global__ __launch_bounds__(kBlock) void k_stage2_grid(int nx, int ny, int nz, 
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   if (e0) {
     const int s = row >> 6, lane = row & 63;
-#pragma unroll 4
-    for (int kq = sptr[s]; kq < sptr[s + 1]; ++kq) {
-      const int c = __builtin_nontemporal_load(col + (size_t)kq * 64 + lane);
-      const double* v = val + (size_t)kq * 9 * 64 + lane;
-      const double u = e0[(size_t)c * NE];
-      a0 += __builtin_nontemporal_load(v + (0 * 3 + ea) * 64) * u;
-      a1 += __builtin_nontemporal_load(v + (1 * 3 + ea) * 64) * u;
-      a2 += __builtin_nontemporal_load(v + (2 * 3 + ea) * 64) * u;
-      if (NE == 2) {
-        const double w = e0[(size_t)c * NE + 1];
-        a0 += __builtin_nontemporal_load(v + (0 * 3 + eb) * 64) * w;
-        a1 += __builtin_nontemporal_load(v + (1 * 3 + eb) * 64) * w;
-        a2 += __builtin_nontemporal_load(v + (2 * 3 + eb) * 64) * w;
-      }
-    }
+    stage2_row_sum<NE, 8, sizeof(T) == 8>(sptr[s], sptr[s + 1], lane, col, val, ea, eb, e0, a0, a1, a2);
   }
   const int i = row % nx, jg = (row / nx) % ny, kg = row / (nx * ny);
   const int nJ = (ny + kTJ - 1) / kTJ;
@@ -1326,20 +1363,7 @@ __global__ __launch_bounds__(kBlock) void k_stage2_resid_sf(int nrows, int nblk,
   const int s = row >> 6, lane = row & 63;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   // without e0 (M2^-1 alone) this only converts r to T
-  for (int k = sptr[s]; e0 && k < sptr[s + 1]; ++k) {
-    const int c = col[(size_t)k * 64 + lane];
-    const double* v = val + (size_t)k * 9 * 64 + lane;
-    const double u = e0[(size_t)c * NE];
-    a0 += v[(0 * 3 + ea) * 64] * u;
-    a1 += v[(1 * 3 + ea) * 64] * u;
-    a2 += v[(2 * 3 + ea) * 64] * u;
-    if (NE == 2) {
-      const double w = e0[(size_t)c * NE + 1];
-      a0 += v[(0 * 3 + eb) * 64] * w;
-      a1 += v[(1 * 3 + eb) * 64] * w;
-      a2 += v[(2 * 3 + eb) * 64] * w;
-    }
-  }
+  if (e0) stage2_row_sum<NE, 4, true>(sptr[s], sptr[s + 1], lane, col, val, ea, eb, e0, a0, a1, a2);
   const double* ri = r + 3 * (size_t)row;
   T* o = r2 + 3 * (size_t)row;
   o[0] = (T)(ri[0] - a0);
