@@ -1063,13 +1063,13 @@ typedef __attribute__((address_space(1))) void glb_void;
 // right-hand sides are read once per sweep, and streaming them past the L2
 // keeps the face hand-offs' lines there (sweeps 4 % faster).
 template <class T, int N>
-__device__ __forceinline__ void wave_copy_to_lds(const T* src, T* dst, int lane) {
+__device__ __forceinline__ void wave_copy_to_lds(const T* src, T* dst, int lane, bool on = true) {
   constexpr int PL = 16 / (int)sizeof(T);  // values per lane and instruction
   constexpr int PI = 64 * PL;              // values per instruction
   constexpr int kNonTemporal = 2;          // the nt bit of the load's cache policy
 #pragma unroll
   for (int q = 0; q < (N + PI - 1) / PI; ++q) {
-    if (N % PI == 0 || q * PI + PL * lane < N)
+    if (on && (N % PI == 0 || q * PI + PL * lane < N))
       __builtin_amdgcn_global_load_lds((glb_void*)(src + q * PI + PL * lane), (lds_void*)(dst + q * PI),
                                        16, 0, kNonTemporal);
   }
@@ -1130,10 +1130,29 @@ __global__ __launch_bounds__(64 * (H + 1)) void k_ilu_grid(int nx, int ny, int n
       lds_acquire();
       T* slot = ring + (s % R) * SLOT;
       const size_t row = trow + min(s, nsteps - 1);
-      wave_copy_to_lds<T, NV * 64>(M + row * NV * 64, slot, lane);
-      wave_copy_to_lds<T, 3 * 64>(rhs + row * 3 * 64, slot + OR, lane);
+      // a load lane moves the values of PL consecutive cell lanes of one row
+      // of the tile (the same lanes in every instruction): in FP64 it is
+      // skipped when none of them is active at step s (padding pencils, the
+      // skew's ramps), whose slot values the sweeping wave never uses (1 %
+      // faster; in FP32, four cells per load lane, the test costs more than
+      // it saves)
+      bool on = true;
+      if constexpr (sizeof(T) == 8) {
+        constexpr int PL = 16 / (int)sizeof(T);
+        const int c0 = PL * (lane % (64 / PL));
+        const int kk = c0 / kTJ, k = (t / nJ) * kTK + kk;
+        on = false;
+#pragma unroll
+        for (int u = 0; u < PL; ++u) {
+          const int jj = (c0 + u) % kTJ, j = (t % nJ) * kTJ + jj;
+          const int lag = FWD ? jj + kk : (kTJ - 1 - jj) + (kTK - 1 - kk);
+          on = on || (j < ny && k < nz && s >= lag && s < lag + nx);
+        }
+      }
+      wave_copy_to_lds<T, NV * 64>(M + row * NV * 64, slot, lane, on);
+      wave_copy_to_lds<T, 3 * 64>(rhs + row * 3 * 64, slot + OR, lane, on);
       // without e0 (M2^-1 alone) the slot's e0 part is left as it is: unused
-      if (!FWD && e0t) wave_copy_to_lds<T, NE0 * 64>(e0t + row * NE0 * 64, slot + OE, lane);
+      if (!FWD && e0t) wave_copy_to_lds<T, NE0 * 64>(e0t + row * NE0 * 64, slot + OE, lane, on);
       // values of the neighbouring tiles, once published.  All face values a
       // step needs from one neighbour come from one step of that tile, so
       // while they are missing a single lane waits on one of them and the

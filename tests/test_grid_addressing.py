@@ -154,6 +154,21 @@ def test_sweep_addresses_in_bounds_and_consistent(shape, fwd):
     NR = 3 + (0 if fwd else 2)
     slot = (NV + NR + 6) * 64
     assert ((np.arange(nst + 2) % R).max() + 1) * slot <= R * slot
+    # FP64 staging skips a load lane (two consecutive cell lanes of one tile
+    # row, the same in every instruction) when neither cell is active at that
+    # step: every cell the sweeping wave computes must still be staged
+    m = np.arange(32)
+    tt = np.arange(ntiles)[:, None, None]
+    ss = np.arange(nst + 2)[None, :, None]
+    on = np.zeros((ntiles, nst + 2, 32), dtype=bool)
+    for u in (0, 1):
+        c = 2 * m + u
+        cjj, ckk = c % TJ, c // TJ
+        cj, ck = (tt % nJ) * TJ + cjj, (tt // nJ) * TK + ckk
+        lag = cjj + ckk if fwd else (TJ - 1 - cjj) + (TK - 1 - ckk)
+        on |= (cj < ny) & (ck < nz) & (ss >= lag) & (ss < lag + nx)
+    n = min(act.shape[1], nst + 2)
+    assert not (act[:, :n, :] & ~np.repeat(on[:, :n, :], 2, axis=2)).any()
     # faces: published at (t, s), polled at (tJ, s + 15) / (tK, s + 3)
     nfaces = ntiles * ns * FACE
     def jface(tile, step, q, kk):
