@@ -1134,8 +1134,8 @@ __global__ __launch_bounds__(64 * (H + 1)) void k_ilu_grid(int nx, int ny, int n
       // of the tile (the same lanes in every instruction): in FP64 it is
       // skipped when none of them is active at step s (padding pencils, the
       // skew's ramps), whose slot values the sweeping wave never uses (1 %
-      // faster; in FP32, four cells per load lane, the test costs more than
-      // it saves)
+      // faster; in FP32, four cells per load lane, the masked copies made
+      // the sweeps slower, also with the test reduced to two comparisons)
       bool on = true;
       if constexpr (sizeof(T) == 8) {
         constexpr int PL = 16 / (int)sizeof(T);
